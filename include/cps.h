@@ -1,0 +1,147 @@
+/*
+ * cps.h -- C-ABI of the MI355X (gfx950) compact immersed-interface Poisson solver.
+ *
+ * The library solves the 3D Dirichlet Poisson problem of Hosseinverdi & Fasel (arXiv
+ * 1901.08269), Eq. (poisson):
+ *     Laplacian u = f  in the fluid region (level set phi > 0),
+ *     u = g            on the box walls and on the interface Gamma (phi = 0),
+ *     u = 0            inside the bodies (phi <= 0),
+ * on a tensor-product nonuniform grid (Sec. 2), with the fourth-order compact 27-point
+ * scheme (Sec. 2.1, Eqs. A27/As_qs/q), modified at irregular points next to Gamma
+ * (Secs. 2.2-2.3, Eqs. A27_mod/bc/cor and their multiple-intersection forms), and solves
+ * the resulting system B u = q + b (Sec. 3, Eq. Bu=q, split B = A-bar + C of Eq. Bdec)
+ * by right-preconditioned BiCGSTAB (Sec. 3.2, Alg. 1) whose preconditioner is the
+ * second-order 7-point operator K with Shortley-Weller rows at Gamma (Sec. 3.3, Eqs.
+ * A7/A7_mod), solved approximately by a fixed number of inner iterations.
+ *
+ * Conventions shared by every entry point
+ *   - Grid: nx, ny, nz points per direction INCLUDING both wall planes; coordinates
+ *     x[nx], y[ny], z[nz] strictly increasing.  Unknowns are the interior nodes with
+ *     phi > 0: (nx-2)(ny-2)(nz-2) minus the solid nodes (Sec. 3, first paragraph).
+ *   - Node arrays have nx*ny*nz float64 entries, node (i,j,k) at index i + nx*(j + ny*k),
+ *     0-based, x fastest.
+ *   - Pointers are host pointers unless cps_options.device_ptrs = 1, in which case every
+ *     array argument of every call on that solver is a device pointer (e.g. a torch
+ *     tensor's data_ptr()).  The caller owns all input and output buffers; the library
+ *     copies what it needs and never keeps a caller pointer after a call returns.
+ *   - Work is ordered on cps_options.stream (NULL = the null stream); every call
+ *     synchronises that stream before it returns.  A solver object is not thread-safe.
+ *   - Return value: 0 on success or a negative CPS_E* code; cps_strerror names it.
+ */
+#ifndef CPS_H
+#define CPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPS_OK 0
+#define CPS_EINVAL (-1)      /* bad sizes, non-increasing coordinates, NaN/Inf input, bad option */
+#define CPS_EGEOM (-2)       /* a body touches a wall node (phi <= 0 on the boundary) */
+#define CPS_ENOMEM (-3)      /* device or host allocation failed */
+#define CPS_EDEVICE (-4)     /* a HIP runtime call failed or no device is present */
+#define CPS_EBREAKDOWN (-5)  /* BiCGSTAB broke down more often than max_restarts allows */
+#define CPS_ENOCONV (-6)     /* max_iters reached; u holds the last iterate, stats are filled */
+#define CPS_ENAN (-7)        /* the iteration produced NaN/Inf */
+
+#define CPS_FP64 0           /* plain mode: every sweep in FP64 */
+#define CPS_MIXED 1          /* FP32 inner BiCGSTAB inside an FP64 iterative-refinement loop */
+
+typedef struct cps_solver cps_solver; /* opaque; owns all of its device memory */
+
+typedef struct cps_options {
+    int32_t struct_size;   /* = sizeof(cps_options) */
+    int32_t precision;     /* CPS_FP64 or CPS_MIXED */
+    int32_t inner_iters;   /* preconditioner inner iterations per apply; paper: 8 (Sec. 4) */
+    int32_t max_iters;     /* cap on BiCGSTAB iterations (summed over refinement steps) */
+    int32_t max_refine;    /* CPS_MIXED: cap on refinement steps */
+    int32_t max_restarts;  /* restarts after breakdown or a failed true-residual check */
+    int32_t device_ptrs;   /* 1: array arguments are device pointers */
+    int32_t kernel_timing; /* 1: time every preconditioner sweep with HIP events (stats) */
+    double inner_tol;      /* CPS_MIXED: residual reduction asked of each FP32 inner solve */
+    double lam_lo, lam_hi; /* Chebyshev interval for the spectrum of diag(K)^-1 K */
+    void *stream;          /* hipStream_t the library launches on; NULL = null stream */
+} cps_options;
+
+typedef struct cps_stats {
+    int32_t struct_size;    /* = sizeof(cps_stats) */
+    int32_t iters;          /* BiCGSTAB iterations (all precisions) */
+    int32_t iters_fp32;     /* of which FP32 inner iterations (CPS_MIXED) */
+    int32_t refine_steps;
+    int32_t restarts;
+    int32_t status;         /* return code of the solve */
+    int64_t n_unknowns, n_irregular, n_solid, nnz_irregular, fallback_lines;
+    double rel_residual;        /* ||b - B u||_2 / ||b||_2 over unknowns, FP64, paper row scaling */
+    double rel_residual_jacobi; /* ||D^-1 (b - B u)||_2 / ||D^-1 b||_2, D = diag(B) */
+    double min_ibi_frac;        /* min over IBIs of |x_fluid - x_IBI| / segment length */
+    double setup_ms, solve_ms;
+    double sweep_ms;            /* kernel_timing: summed duration of preconditioner sweeps */
+    int64_t sweep_launches;     /* kernel_timing: number of sweeps timed */
+    int64_t sweep_points;       /* interior points one sweep processes */
+    int32_t sweep_bytes_per_point; /* algorithmic bytes one sweep moves per point */
+    int32_t pad;
+} cps_stats;
+
+/* Fill `o` with the defaults: CPS_FP64, 8 inner iterations (Sec. 4), max_iters 20000,
+ * max_refine 40, max_restarts 5, host pointers, inner_tol 1e-4, the default Chebyshev
+ * interval, null stream, no kernel timing. */
+void cps_default_options(cps_options *o);
+
+/* Build the discrete problem (Secs. 2-3): classify nodes from the sign of phi (Sec. 2,
+ * Fig. grid_point_types), locate the interface intersections (IBIs) on grid segments where
+ * phi changes sign (degree-5 interpolation of nodal phi; g at an IBI from the same
+ * interpolation of nodal g), build the modified rows of B at irregular nodes and the
+ * Shortley-Weller rows of K, and assemble the right-hand side q + b (Eqs. q, bc, cor).
+ * phi, g, f: nx*ny*nz float64 node arrays.  g must be a smooth field whose values at wall
+ * nodes and at the IBIs are the Dirichlet data; f is read at fluid and wall nodes.
+ * opt may be NULL (defaults).  On success *out receives a new solver. */
+int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double *x, const double *y,
+              const double *z, const double *phi, const double *g, const double *f, const cps_options *opt);
+
+/* Replace f and g (same grid and geometry) and rebuild the right-hand side. */
+int cps_set_rhs(cps_solver *s, const double *f, const double *g);
+
+/* Solve B u = q + b (Alg. 1) until ||r||/||b|| <= tol and ||D^-1 r||/||D^-1 b|| <= tol in
+ * FP64.  u: nx*ny*nz float64; if warm_start is nonzero its unknown entries are the initial
+ * guess (NaN/Inf there -> the guess is discarded and 0 used), else the guess is 0.  On
+ * return u holds the solution at unknowns, g at wall nodes and 0 at solid nodes.  st may
+ * be NULL.  Returns CPS_OK, CPS_ENOCONV, CPS_EBREAKDOWN or CPS_ENAN (u then holds the
+ * last finite iterate). */
+int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stats *st);
+
+/* r = b - B u at unknown nodes (0 elsewhere), FP64, using the unknown entries of u.
+ * r may be NULL.  rel[0] = ||r||_2/||b||_2, rel[1] = ||D^-1 r||_2/||D^-1 b||_2 (rel may be NULL). */
+int cps_residual(cps_solver *s, const double *u, double *r, double *rel);
+
+/* y = B x (Eq. Bu=q, B = A-bar + C of Eq. Bdec) at unknown nodes, 0 elsewhere.
+ * precision CPS_FP64 applies the FP64 operator, CPS_MIXED the FP32 operator (x rounded to
+ * FP32 first, y widened back).  Entries of x at non-unknown nodes are ignored. */
+int cps_apply(cps_solver *s, const double *x, double *y, int32_t precision);
+
+/* phi = M rho: the preconditioner of Alg. 1 (lines 4 and 8), i.e. inner_iters
+ * Chebyshev-Jacobi steps on K phi = rho (Sec. 3.3) from phi = 0; FP64 or FP32 as above. */
+int cps_precond(cps_solver *s, const double *rho, double *phi, int32_t precision);
+
+/* Copy out the right-hand side q + b (node array, 0 at non-unknowns) and the node types
+ * (int8 node array: 0 wall, 1 regular fluid, 2 irregular fluid, 3 solid).  Either may be NULL. */
+int cps_get_rhs(cps_solver *s, double *rhs, int8_t *types);
+
+/* Sizes: out[0] unknowns, [1] irregular rows, [2] solid nodes, [3] stored nonzeros of the
+ * irregular rows, [4] fallback lines, [5] nx*ny*nz. */
+int cps_get_info(cps_solver *s, int64_t out[6]);
+
+/* Export the irregular rows (Eqs. A27_mod, bc, cor): node[n_irr] (int64 node index, rows in
+ * increasing node order), ptr[n_irr+1], col[nnz] (int64 node index of an unknown), val[nnz]
+ * (FP64 coefficient of B), krow[7*n_irr] (K row: diag, -x, +x, -y, +y, -z, +z).  Host
+ * pointers always; any may be NULL. */
+int cps_get_irregular(cps_solver *s, int64_t *node, int64_t *ptr, int64_t *col, double *val, double *krow);
+
+void cps_destroy(cps_solver *s);
+const char *cps_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPS_H */
