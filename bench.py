@@ -1,0 +1,182 @@
+#!/usr/bin/env python
+"""Benchmark of the hot path on one MI355X.
+
+Workload: unit cube, 256^3 interior points, tanh wall stretching (factor 1.5), 8 seeded
+non-overlapping spheres, manufactured u = sin(2 pi x) cos(pi y) exp(z), f = (1 - 5 pi^2) u,
+g = u.  Inputs are synthetic, generated once and resident in HBM before timing.
+
+One step = the whole hot path on that input: setup (1D coefficients, classification, IBIs,
+modified rows, right-hand side), the warm start (when a trained network is available),
+and the FP32-inner / FP64-refinement BiCGSTAB solve to ||r||/||b|| <= 1e-10 (and the same
+bound on the Jacobi-weighted residual).  The plain FP64 solve of the same problem is timed
+once beside it for the speedup; the CPU oracle is timed on a bounded sample.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=1)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1901_08269_amd as cps
+    from paper_1901_08269_amd import metrics
+    from paper_1901_08269_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}), flush=True)
+        sys.exit(3)
+    t_gen = time.time()
+    w = W.spheres8(args.N)
+    dev = {k: torch.as_tensor(getattr(w, k), dtype=torch.float64).cuda().contiguous()
+           for k in ("x", "y", "z", "phi", "g", "f")}
+    torch.cuda.synchronize()
+    print(f"# inputs generated in {time.time() - t_gen:.1f}s", file=sys.stderr, flush=True)
+
+    learned = None
+    try:
+        from paper_1901_08269_amd import learned as _learned
+        learned = _learned.load_default(args.N) if hasattr(_learned, "load_default") else None
+    except Exception as exc:  # the warm start is optional; the plain solve judges
+        print(f"# no warm start: {exc}", file=sys.stderr, flush=True)
+
+    def step(precision, timing):
+        S = cps.Solver(dev["x"], dev["y"], dev["z"], dev["phi"], dev["g"], dev["f"], precision=precision,
+                       kernel_timing=timing)
+        u0 = learned.predict(S, w) if (learned is not None and precision == "mixed") else None
+        u, st = S.solve(args.tol, u0=u0)
+        S.close()
+        return u, st
+
+    for _ in range(args.warmup):
+        step("mixed", False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for q in range(args.steps):
+        u, st = step("mixed", True)
+        stats.append(st)
+        print(f"# step {q}: {st['iters']} iters, {st['refine_steps']} refinements, "
+              f"rel res {st['rel_residual']:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    last = stats[-1]
+    t_mask = None
+    err = None
+    if w.u_exact is not None:
+        ue = torch.as_tensor(w.u_exact).cuda()
+        _, types = cps.Solver(dev["x"], dev["y"], dev["z"], dev["phi"], dev["g"], dev["f"]).rhs_and_types()
+        t_mask = (types == 1) | (types == 2)
+        err = float(torch.max(torch.abs(u - ue)[t_mask]))
+
+    fp64 = None
+    if not args.no_fp64:
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        u64, st64 = step("fp64", False)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        diff = float(torch.max(torch.abs(u - u64)[t_mask]) / torch.max(torch.abs(u64)[t_mask])) if t_mask is not None else None
+        fp64 = {"step_s": tb - ta, "solve_s": st64["solve_ms"] / 1e3, "iters": st64["iters"],
+                "rel_residual": st64["rel_residual"], "mixed_vs_fp64_rel_maxdiff": diff}
+
+    # roofline of the dominant kernel: the FP32 Chebyshev sweep of the preconditioner
+    sweeps = sum(s["sweep_launches"] for s in stats)
+    sweep_ms = sum(s["sweep_ms"] for s in stats)
+    pts = last["sweep_points"]
+    bpp = last["sweep_bytes_per_point"]
+    avg_ms = sweep_ms / max(sweeps, 1)
+    achieved = bpp * pts / (avg_ms * 1e-3) / 1e9 if sweeps else None
+    roofline = {"kernel": "k_cheb<float> (preconditioner sweep)", "bound": "hbm",
+                "achieved": achieved, "peak": metrics.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / metrics.MI355X_HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "avg_launch_us": avg_ms * 1e3, "launches": sweeps, "bytes_per_launch": bpp * pts}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args, fp64["iters"] if fp64 else last["iters"])
+
+    solve_s = sum(s["solve_ms"] for s in stats) / len(stats) / 1e3
+    setup_s = sum(s["setup_ms"] for s in stats) / len(stats) / 1e3
+    n_unk = last["n_unknowns"]
+    out = {
+        "metric": "solve s to 1e-10 rel residual at 256^3 (mixed+learned vs FP64); stencil GB/s",
+        "value": ms_step / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 inner / f64 outer",
+        "data": "synthetic",
+        "config": {"workload": f"spheres8_{args.N}: {args.N}^3 interior, tanh 1.5, 8 spheres seed 0, "
+                               f"u = sin(2pi x) cos(pi y) exp(z), tol {args.tol:g}",
+                   "precision": "mixed", "warm_start": "learned" if learned is not None else "zero",
+                   "inner_iters": 8},
+        "solve_s": solve_s,
+        "setup_s": setup_s,
+        "iters": last["iters"],
+        "iters_fp32": last["iters_fp32"],
+        "refine_steps": last["refine_steps"],
+        "rel_residual": last["rel_residual"],
+        "rel_residual_jacobi": last["rel_residual_jacobi"],
+        "max_error_vs_exact": err,
+        "n_unknowns": n_unk,
+        "n_irregular": last["n_irregular"],
+        "unknown_iters_per_s": n_unk * last["iters"] / solve_s,
+        "fp64": fp64,
+        "speedup_vs_fp64_solve": (fp64["solve_s"] / solve_s) if fp64 else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, args, iters_full):
+    """The CPU oracle, timed on the same workload: its setup plus `cpu_iters` FP64 BiCGSTAB
+    iterations, scaled to the GPU FP64 solve's iteration count (seconds per solve)."""
+    import oracle
+    t0 = time.perf_counter()
+    P = oracle.Problem.from_workload(w)
+    t1 = time.perf_counter()
+    _, st = P.solve(args.tol, max_iters=args.cpu_iters, check=False)
+    t2 = time.perf_counter()
+    per_iter = (t2 - t1) / max(st["iters"], 1)
+    return {"value": (t1 - t0) + per_iter * iters_full, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle setup + {st['iters']} FP64 BiCGSTAB iteration(s) on the same {args.N}^3 workload "
+                      f"({t2 - t0:.1f}s of CPU work), scaled to {iters_full} iterations",
+            "setup_s": t1 - t0, "iter_s": per_iter}
+
+
+if __name__ == "__main__":
+    main()

@@ -141,6 +141,51 @@ int cps_get_irregular(cps_solver *s, int64_t *node, int64_t *ptr, int64_t *col, 
 void cps_destroy(cps_solver *s);
 const char *cps_strerror(int code);
 
+/* ---------------------------------------------------------------------------------------
+ * Learned warm start: a 4-level 3D convolutional encoder-decoder on the grid coarsened 4x
+ * per direction (inputs: cell means of f, phi, g; output: the cell means of u), trained
+ * on solutions of this solver.  It only supplies the initial guess of cps_solve; the
+ * BiCGSTAB solve always runs to the requested tolerance from it.
+ * Network arrays are always DEVICE pointers (FP32): inputs [batch][in_ch][nc^3], targets,
+ * masks and predictions [batch][nc^3], index (x + nc (y + nc z)) inside a sample.
+ * Parameters: FP32, flat, per 3x3x3 layer W[co][ci][kz][ky][kx] then b[co] in the order
+ * E0a E0b E1a E1b E2a E2b E3a E3b D2a D2b D1a D1b D0a D0b, then the 1x1x1 head (c0
+ * weights, 1 bias).  Host pointers for cps_model_set_params / get_params.
+ * ------------------------------------------------------------------------------------- */
+typedef struct cps_model cps_model;   /* opaque; owns weights, Adam state and activations */
+
+typedef struct cps_model_spec {
+    int32_t struct_size;  /* = sizeof(cps_model_spec) */
+    int32_t nc;           /* coarse points per direction (multiple of 8) */
+    int32_t batch;        /* largest batch the model is sized for */
+    int32_t in_ch;        /* input channels (3: f, phi, g) */
+    int32_t channels[4];  /* per level, multiples of 16 in [16, 64]; channels[0] = 16 */
+    uint64_t seed;        /* initialisation seed */
+} cps_model_spec;
+
+int64_t cps_model_param_count(const cps_model_spec *spec);
+/* stream: hipStream_t for all work of this model (NULL = null stream) */
+int cps_model_create(cps_model **m, const cps_model_spec *spec, void *stream);
+int cps_model_set_params(cps_model *m, const float *params, int64_t n);          /* resets Adam */
+int cps_model_get_params(cps_model *m, float *params, float *grads, int64_t n);  /* grads: last step */
+/* pred = network(inputs) */
+int cps_model_forward(cps_model *m, const float *inputs, int32_t batch, float *pred);
+/* forward + masked mean-squared error + backward (+ one Adam step with learning rate lr
+ * when update != 0).  mask may be NULL (all ones).  *loss_out = loss before the update. */
+int cps_model_train_step(cps_model *m, const float *inputs, const float *target, const float *mask, int32_t batch,
+                         float lr, int32_t update, double *loss_out);
+/* Network input of one problem: cell means over 4^3 blocks of interior nodes of f, phi, g
+ * (scaled: sigma = RMS over nodes of sqrt(g^2 + (f / 3 pi^2)^2)); with u non-NULL also the
+ * cell means of u / sigma as target.  The solver grid must have 4 nc interior points per
+ * direction.  u, inputs, target: device pointers; sigma: host (may be NULL). */
+int cps_model_restrict(cps_model *m, cps_solver *s, const double *u, float *inputs, float *target, double *sigma);
+/* u0 (device, nx*ny*nz FP64) = sigma * trilinear prolongation of the network's prediction
+ * for the solver's problem; pass it to cps_solve as the warm start. */
+int cps_model_predict(cps_model *m, cps_solver *s, double *u0);
+int cps_model_save(cps_model *m, const char *path);   /* raw binary with a header */
+int cps_model_load(cps_model *m, const char *path);
+void cps_model_destroy(cps_model *m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,75 @@
+// cps_kernels.h -- launchers of the solver's HIP kernels (host-callable).
+#pragma once
+#include <algorithm>
+
+#include "cps_device.h"
+
+namespace cps {
+
+enum { MODE_PLAIN = 0, MODE_V = 1, MODE_T = 2, MODE_RES = 3 };
+enum { FIRST_P = 0, FIRST_S = 1 };
+
+struct Launch {
+    Geom g;
+    hipStream_t stream;
+    const uint32_t *skip;
+    double *partials;   // >= 2 doubles per block of the largest launch
+    unsigned *ticket;   // one counter, 0 between launches
+};
+
+// sweeps.hip
+template <typename T, typename TO>
+void launch_apply(int mode, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, TO *y, const T *w,
+                  const double *bvec, DevState *st);
+template <typename T>
+void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
+                 double c1, double c2, const DevState *st);
+template <typename T>
+void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
+                  double c2, const DevState *st);
+template <typename T, typename TX_>
+void launch_update(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, TX_ *xs, const T *ph, const T *sh, const T *s,
+                   const T *t, const T *r0, T *r, DevState *st);
+template <typename T>
+void launch_restart(const Launch &L, const Irr<T> &ir, const T *r, T *r0, T *p, T *v, DevState *st);
+void launch_add_correction(hipStream_t s, size_t n, double *u, const float *d);
+template <typename T>
+void launch_fill(hipStream_t s, size_t n, T *a, T val);
+template <typename TI, typename TO>
+void launch_masked_copy(hipStream_t s, size_t n, const int8_t *type, const TI *src, TO *dst);
+void launch_output(hipStream_t s, size_t n, const int8_t *type, const double *x, const double *gv, double *u);
+void launch_check_finite(hipStream_t s, size_t n, const int8_t *type, const double *x, int *flag);
+
+// setup.hip
+struct SetupOut {
+    int n_irr;
+    long long n_solid, n_unknown, nnz, fallback;
+    double min_hb;
+};
+
+// 1D tables (FP64) from coordinates; t holds the three coordinate arrays
+void launch_coef(hipStream_t s, int n, const double *t, double *coef);
+// classify nodes; flags: bit0 invalid input (NaN/Inf), bit1 body touches a wall
+void launch_classify(hipStream_t s, int nx, int ny, int nz, const double *phi, const double *g, const double *f,
+                     int8_t *type, int *flags);
+void launch_mark_irregular(hipStream_t s, int nx, int ny, int nz, int8_t *type);
+// ordered compaction of the irregular nodes; returns the count through *count (device int)
+void launch_compact(hipStream_t s, size_t n, const int8_t *type, int8_t want, int *blockcnt, int *list, int *count,
+                    int nblocks);
+int compact_blocks(size_t n);
+void launch_skipbits(hipStream_t s, const Geom &g, const int8_t *type, uint32_t *skip);
+// build irregular rows in a fixed-stride scratch (cap entries per row)
+void launch_build_rows(hipStream_t s, int nx, int ny, int nz, const double *x, const double *y, const double *z,
+                       const double *coef, const double *phi, const double *g, const double *f, const int8_t *type,
+                       int nirr, const int *nodes, int cap, int *ell_col, double *ell_val, int *len, double *rhs_row,
+                       double *k7, double *bdiag, double *minhb, int *fallback, int *bad);
+void launch_scan(hipStream_t s, const int *in, int *out, int n);   // exclusive scan, out[n] = total
+void launch_pack_rows(hipStream_t s, int nirr, int cap, const int *ell_col, const double *ell_val, const int *len,
+                      const int *ptr, int *col, double *val64, float *val32);
+void launch_rhs_regular(hipStream_t s, int nx, int ny, int nz, const double *coef, const double *f, const double *g,
+                        const int8_t *type, double *rhs);
+void launch_scatter_rows(hipStream_t s, int nirr, const int *nodes, const double *rhs_row, double *rhs);
+void launch_to_float(hipStream_t s, size_t n, const double *a, float *b);
+void launch_min_reduce(hipStream_t s, int n, const double *a, const int *fb, double *out_min, long long *out_sum);
+
+}  // namespace cps

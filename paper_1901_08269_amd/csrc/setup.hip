@@ -1,0 +1,712 @@
+// setup.hip -- construction of the discrete problem on the GPU, all in FP64:
+// 1D compact and second-order coefficients (Eqs. app_xxx, 2ndorder_coef), node
+// classification (Sec. 2, Fig. grid_point_types), the ordered list of irregular nodes, the
+// modified rows of B at those nodes (Secs. 2.2-2.3), their Shortley-Weller K rows (Sec. 3.3)
+// and the right-hand side q + b (Eqs. q, bc, cor).
+//
+// Readings of the paper used here:
+//  * An IBI exists on a grid segment whose end nodes have level sets of opposite sign
+//    (phi > 0 fluid, phi <= 0 solid).  Its position is the root, inside the segment, of the
+//    degree-5 polynomial interpolating nodal phi at six nodes around the segment (the window
+//    is shifted to stay inside the grid); g at the IBI is that interpolation of nodal g.
+//  * A modified line window (three nodes along one direction, Eq. lhsrhs_xxyyzz_mod) keeps
+//    the row's L weights at its fluid nodes (they form Q-bar) and replaces its R part by a
+//    one-sided operator per fluid run whose weights reproduce sum_p L[p] u''(x_p) exactly for
+//    all polynomials of degree < |P| -- the Taylor systems of Eqs. mat1-mat4 written as
+//    moment conditions.  |P| = 6 (run + extra nodes marching away from the interface + IBI)
+//    for a window with one run, 5 per side of an F-S-F window (Sec. 2.3), 3 for S-F-S.  A
+//    march that meets a wall node keeps it (known value) and stops; one that meets a solid
+//    node ends at that IBI.  Every shortened set is counted as a fallback.
+#include <math.h>
+
+#include "cps_device.h"
+#include "cps_kernels.h"
+
+namespace cps {
+
+// ---------------------------------------------------------------------------------------
+// 1D coefficient tables
+// ---------------------------------------------------------------------------------------
+__global__ void k_coef(int n, const double *__restrict__ t, double *__restrict__ coef)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double *o = coef + 8 * (size_t)i;
+    for (int q = 0; q < 8; ++q) o[q] = 0.0;
+    if (i == 0 || i == n - 1) return;
+    double hf = t[i + 1] - t[i], hb = t[i] - t[i - 1];
+    // Eq. (app_xxx): denominator (hf + hb)(hf^2 + 3 hf hb + hb^2)
+    double den = hf * hf * hf + 4.0 * hf * hf * hb + 4.0 * hf * hb * hb + hb * hb * hb;
+    o[0] = hf * (hb * hb + hb * hf - hf * hf) / den;        // a
+    o[1] = hb * (hf * hf + hb * hf - hb * hb) / den;        // c
+    o[2] = 12.0 * hf / den;                                 // ar
+    o[3] = -12.0 / (hf * hf + 3.0 * hf * hb + hb * hb);     // br
+    o[4] = 12.0 * hb / den;                                 // cr
+    // Eq. (2ndorder_coef)
+    o[5] = 2.0 / (hb * (hf + hb));
+    o[6] = -2.0 / (hb * hf);
+    o[7] = 2.0 / (hf * (hf + hb));
+}
+
+void launch_coef(hipStream_t s, int n, const double *t, double *coef)
+{
+    k_coef<<<(n + 255) / 256, 256, 0, s>>>(n, t, coef);
+}
+
+// ---------------------------------------------------------------------------------------
+// classification
+// ---------------------------------------------------------------------------------------
+__global__ void k_classify(int nx, int ny, int nz, const double *__restrict__ phi, const double *__restrict__ g,
+                           const double *__restrict__ f, int8_t *__restrict__ type, int *flags)
+{
+    size_t n = (size_t)nx * ny * nz;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        int i = (int)(e % nx);
+        int j = (int)((e / nx) % ny);
+        int k = (int)(e / ((size_t)nx * ny));
+        double p = phi[e];
+        if (!isfinite(p) || !isfinite(g[e]) || !isfinite(f[e])) atomicOr(flags, 1);
+        bool wall = i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1;
+        if (wall) {
+            if (!(p > 0.0)) atomicOr(flags, 2);
+            type[e] = 0;
+        } else {
+            type[e] = (p > 0.0) ? 1 : 3;
+        }
+    }
+}
+
+void launch_classify(hipStream_t s, int nx, int ny, int nz, const double *phi, const double *g, const double *f,
+                     int8_t *type, int *flags)
+{
+    size_t n = (size_t)nx * ny * nz;
+    k_classify<<<(unsigned)std::min<size_t>((n + 255) / 256, 65536), 256, 0, s>>>(nx, ny, nz, phi, g, f, type, flags);
+}
+
+// a fluid node with a solid node among its 26 neighbours is irregular
+__global__ void k_mark_irregular(int nx, int ny, int nz, int8_t *__restrict__ type)
+{
+    size_t n = (size_t)nx * ny * nz;
+    size_t plane = (size_t)nx * ny;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        if (type[e] != 1) continue;
+        bool irr = false;
+        for (int dz = -1; dz <= 1 && !irr; ++dz)
+            for (int dy = -1; dy <= 1 && !irr; ++dy)
+                for (int dx = -1; dx <= 1 && !irr; ++dx)
+                    irr = type[e + dx + (ptrdiff_t)dy * nx + (ptrdiff_t)dz * (ptrdiff_t)plane] == 3;
+        if (irr) type[e] = 2;
+    }
+}
+
+void launch_mark_irregular(hipStream_t s, int nx, int ny, int nz, int8_t *type)
+{
+    size_t n = (size_t)nx * ny * nz;
+    k_mark_irregular<<<(unsigned)std::min<size_t>((n + 255) / 256, 65536), 256, 0, s>>>(nx, ny, nz, type);
+}
+
+// ---------------------------------------------------------------------------------------
+// ordered stream compaction (counts per block -> scan -> scatter)
+// ---------------------------------------------------------------------------------------
+constexpr int CMP_THREADS = 256, CMP_PER_THREAD = 16, CMP_CHUNK = CMP_THREADS * CMP_PER_THREAD;
+
+int compact_blocks(size_t n) { return (int)((n + CMP_CHUNK - 1) / CMP_CHUNK); }
+
+__global__ void k_count(size_t n, const int8_t *__restrict__ type, int8_t want, int *blockcnt)
+{
+    __shared__ int sh[CMP_THREADS];
+    size_t base = (size_t)blockIdx.x * CMP_CHUNK + (size_t)threadIdx.x * CMP_PER_THREAD;
+    int c = 0;
+    for (int q = 0; q < CMP_PER_THREAD; ++q)
+        if (base + q < n && type[base + q] == want) ++c;
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = CMP_THREADS / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blockcnt[blockIdx.x] = sh[0];
+}
+
+__global__ void k_scatter(size_t n, const int8_t *__restrict__ type, int8_t want, const int *__restrict__ offs,
+                          int *__restrict__ list)
+{
+    __shared__ int sh[CMP_THREADS];
+    size_t base = (size_t)blockIdx.x * CMP_CHUNK + (size_t)threadIdx.x * CMP_PER_THREAD;
+    int c = 0;
+    for (int q = 0; q < CMP_PER_THREAD; ++q)
+        if (base + q < n && type[base + q] == want) ++c;
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    // inclusive scan (Hillis-Steele) over the block
+    for (int o = 1; o < CMP_THREADS; o <<= 1) {
+        int v = ((int)threadIdx.x >= o) ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int pos = offs[blockIdx.x] + sh[threadIdx.x] - c;
+    for (int q = 0; q < CMP_PER_THREAD; ++q)
+        if (base + q < n && type[base + q] == want) list[pos++] = (int)(base + q);
+}
+
+// exclusive scan of n ints by one block; out[n] = total
+__global__ void k_scan(const int *__restrict__ in, int *__restrict__ out, int n)
+{
+    __shared__ int sh[1024];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        int idx = base + threadIdx.x;
+        int v = idx < n ? in[idx] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            int a = ((int)threadIdx.x >= o) ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (idx < n) out[idx] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sh[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+void launch_scan(hipStream_t s, const int *in, int *out, int n) { k_scan<<<1, 1024, 0, s>>>(in, out, n); }
+
+void launch_compact(hipStream_t s, size_t n, const int8_t *type, int8_t want, int *blockcnt, int *list, int *count,
+                    int nblocks)
+{
+    // blockcnt holds 2*nblocks+1 ints: counts, then the exclusive offsets (+ total)
+    k_count<<<nblocks, CMP_THREADS, 0, s>>>(n, type, want, blockcnt);
+    k_scan<<<1, 1024, 0, s>>>(blockcnt, blockcnt + nblocks, nblocks);
+    k_scatter<<<nblocks, CMP_THREADS, 0, s>>>(n, type, want, blockcnt + nblocks, list);
+    hipMemcpyAsync(count, blockcnt + 2 * nblocks, sizeof(int), hipMemcpyDeviceToDevice, s);
+}
+
+// skip bits: solid or irregular interior nodes
+__global__ void k_skipbits(Geom g, const int8_t *__restrict__ type, uint32_t *__restrict__ skip)
+{
+    size_t nw = (size_t)g.W * g.ny * g.nz;
+    for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (size_t)gridDim.x * blockDim.x) {
+        size_t line = w / g.W;
+        int i0 = (int)(w % g.W) * 32;
+        uint32_t bits = 0;
+        for (int q = 0; q < 32; ++q) {
+            int i = i0 + q;
+            if (i >= g.nx) break;
+            int8_t t = type[line * g.nx + i];
+            if (t == 2 || t == 3) bits |= 1u << q;
+        }
+        skip[w] = bits;
+    }
+}
+
+void launch_skipbits(hipStream_t s, const Geom &g, const int8_t *type, uint32_t *skip)
+{
+    size_t nw = (size_t)g.W * g.ny * g.nz;
+    k_skipbits<<<(unsigned)std::min<size_t>((nw + 255) / 256, 65536), 256, 0, s>>>(g, type, skip);
+}
+
+// ---------------------------------------------------------------------------------------
+// irregular rows
+// ---------------------------------------------------------------------------------------
+struct Ctx {
+    int n[3];
+    size_t stride[3];
+    const double *t[3];
+    const double *coef[3];
+    const double *phi, *g, *f;
+    const int8_t *type;
+};
+
+constexpr int NSLOT = 27 + 3 * 2 * 4 * 9;   // 3x3x3 box + extra points 2..5 cells out along a line
+
+// slot of a node at offset o from the row node, or -1
+__device__ __forceinline__ int slot_of(const int o[3])
+{
+    int far = -1;
+    for (int d = 0; d < 3; ++d)
+        if (o[d] < -1 || o[d] > 1) {
+            if (far >= 0) return -1;
+            far = d;
+        }
+    if (far < 0) return (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1);
+    int m = o[far] < 0 ? -o[far] : o[far];
+    if (m > 5) return -1;
+    int d1 = (far + 1) % 3, d2 = (far + 2) % 3;
+    return 27 + (((far * 2 + (o[far] > 0)) * 4 + (m - 2)) * 9 + (o[d1] + 1) * 3 + (o[d2] + 1));
+}
+
+// Interpolating polynomial of degree m-1 through (ts, vs) in Newton form (in place).
+__device__ void newton_coeffs(int m, const double *ts, double *c)
+{
+    for (int lvl = 1; lvl < m; ++lvl)
+        for (int q = m - 1; q >= lvl; --q) c[q] = (c[q] - c[q - 1]) / (ts[q] - ts[q - lvl]);
+}
+
+__device__ double newton_eval(int m, const double *ts, const double *c, double t, double *deriv)
+{
+    double p = c[m - 1], dp = 0.0;
+    for (int q = m - 2; q >= 0; --q) {
+        dp = dp * (t - ts[q]) + p;
+        p = p * (t - ts[q]) + c[q];
+    }
+    if (deriv) *deriv = dp;
+    return p;
+}
+
+// IBI on the segment between node index `ifl` (fluid) and `isol` (solid) of the grid line
+// along d through node `line0` (index 0 along d); returns its coordinate, g there, and the
+// fraction of the segment between the fluid node and the IBI.
+__device__ double ibi_on_segment(const Ctx &C, int d, size_t line0, int ifl, int isol, double *gval, double *frac)
+{
+    int n = C.n[d];
+    int m = n < 6 ? n : 6;
+    int lo = min(ifl, isol) - 2;
+    lo = max(0, min(lo, n - m));
+    double ts[6], cp[6], cg[6];
+    for (int q = 0; q < m; ++q) {
+        size_t node = line0 + (size_t)(lo + q) * C.stride[d];
+        ts[q] = C.t[d][lo + q];
+        cp[q] = C.phi[node];
+        cg[q] = C.g[node];
+    }
+    newton_coeffs(m, ts, cp);
+    newton_coeffs(m, ts, cg);
+    double tf = C.t[d][ifl], tsol = C.t[d][isol];
+    double root;
+    if (C.phi[line0 + (size_t)isol * C.stride[d]] == 0.0) {
+        root = tsol;
+    } else {
+        // safeguarded Newton: keep the bracket [fluid side (> 0), solid side (<= 0)]
+        double a = tf, b = tsol;
+        root = 0.5 * (a + b);
+        for (int it = 0; it < 200; ++it) {
+            double dv, v = newton_eval(m, ts, cp, root, &dv);
+            if (v > 0.0) a = root; else b = root;
+            double nxt = (dv != 0.0) ? root - v / dv : 0.5 * (a + b);
+            bool inside = (a < b) ? (nxt > a && nxt < b) : (nxt < a && nxt > b);
+            if (!inside) nxt = a + 0.5 * (b - a);
+            if (nxt == root || nxt == a || nxt == b) { root = nxt; break; }
+            root = nxt;
+        }
+    }
+    *gval = newton_eval(m, ts, cg, root, nullptr);
+    *frac = fabs(root - tf) / fabs(tsol - tf);
+    return root;
+}
+
+// Solve the m x m system A w = rhs (row-major, destroyed) by elimination with row pivoting.
+__device__ bool small_solve(int m, double *A, double *rhs, double *w)
+{
+    for (int c = 0; c < m; ++c) {
+        int pr = c;
+        double best = fabs(A[c * m + c]);
+        for (int r = c + 1; r < m; ++r)
+            if (fabs(A[r * m + c]) > best) { best = fabs(A[r * m + c]); pr = r; }
+        if (best == 0.0) return false;
+        if (pr != c) {
+            for (int q = 0; q < m; ++q) { double tmp = A[c * m + q]; A[c * m + q] = A[pr * m + q]; A[pr * m + q] = tmp; }
+            double tmp = rhs[c]; rhs[c] = rhs[pr]; rhs[pr] = tmp;
+        }
+        for (int r = c + 1; r < m; ++r) {
+            double l = A[r * m + c] / A[c * m + c];
+            for (int q = c; q < m; ++q) A[r * m + q] -= l * A[c * m + q];
+            rhs[r] -= l * rhs[c];
+        }
+    }
+    for (int r = m - 1; r >= 0; --r) {
+        double acc = rhs[r];
+        for (int q = r + 1; q < m; ++q) acc -= A[r * m + q] * w[q];
+        w[r] = acc / A[r * m + r];
+    }
+    return true;
+}
+
+struct RowAcc {
+    double val[NSLOT];
+    uint32_t used[(NSLOT + 31) / 32];
+    double rhs;
+};
+
+// coefficient c on the node at offset o (from the row node): unknown -> slot; wall -> RHS
+__device__ __forceinline__ void put(const Ctx &C, RowAcc &R, size_t rownode, const int o[3], double c)
+{
+    size_t node = rownode + (ptrdiff_t)o[0] * (ptrdiff_t)C.stride[0] + (ptrdiff_t)o[1] * (ptrdiff_t)C.stride[1] +
+                  (ptrdiff_t)o[2] * (ptrdiff_t)C.stride[2];
+    int8_t ty = C.type[node];
+    if (ty == 0) {
+        R.rhs -= c * C.g[node];
+        return;
+    }
+    int sl = slot_of(o);
+    if (sl < 0) return;  // unreachable for marches of at most 5 cells
+    R.val[sl] += c;
+    R.used[sl >> 5] |= 1u << (sl & 31);
+}
+
+struct Pt {
+    double t;
+    int off;       // offset along d from the window centre (grid node), or IBI marker
+    bool ibi;
+    double gval;
+};
+
+// one fluid run [plo, phi_] (positions -1..1 along d of the window centred at `wc` = row
+// offset) of a window meeting the body
+__device__ void run_operator(const Ctx &C, RowAcc &R, size_t rownode, const int rowidx[3], int d, const int wc[3],
+                             int plo, int phi_, const bool sol[3], int nruns, const double Ld[3], double W, int &fb,
+                             double &minhb, int *bad)
+{
+    const int n = C.n[d];
+    int cidx = rowidx[d];   // window centre index along d (same as the row's)
+    int base[3] = {rowidx[0] + wc[0], rowidx[1] + wc[1], rowidx[2] + wc[2]};
+    base[d] = 0;
+    size_t line0 = (size_t)base[0] * C.stride[0] + (size_t)base[1] * C.stride[1] + (size_t)base[2] * C.stride[2];
+    bool sl = plo > -1 && sol[plo - 1 + 1];
+    bool sr = phi_ < 1 && sol[phi_ + 1 + 1];
+    Pt P[8];
+    int np = 0;
+    bool shortened = false;
+    double gv, fr;
+    if (sl && sr) {
+        double tl = ibi_on_segment(C, d, line0, cidx + plo, cidx + plo - 1, &gv, &fr);
+        minhb = fmin(minhb, fr);
+        P[np++] = {tl, 0, true, gv};
+        for (int p = plo; p <= phi_; ++p) P[np++] = {C.t[d][cidx + p], p, false, 0.0};
+        double th = ibi_on_segment(C, d, line0, cidx + phi_, cidx + phi_ + 1, &gv, &fr);
+        minhb = fmin(minhb, fr);
+        P[np++] = {th, 0, true, gv};
+        shortened = true;
+    } else {
+        const int want = (nruns == 2) ? 5 : 6;
+        for (int p = plo; p <= phi_; ++p) P[np++] = {C.t[d][cidx + p], p, false, 0.0};
+        int near = sr ? phi_ : plo;                 // run node next to the interface
+        int step = sr ? -1 : 1;                     // march away from the interface
+        double tb = ibi_on_segment(C, d, line0, cidx + near, cidx + near - step, &gv, &fr);
+        minhb = fmin(minhb, fr);
+        P[np++] = {tb, 0, true, gv};
+        int pos = sr ? plo : phi_;
+        while (np < want) {
+            int nxt = pos + step;
+            int gi = cidx + nxt;
+            if (gi < 0 || gi >= n) { shortened = true; break; }
+            size_t node = line0 + (size_t)gi * C.stride[d];
+            int8_t ty = C.type[node];
+            if (ty == 3) {
+                double te = ibi_on_segment(C, d, line0, cidx + pos, gi, &gv, &fr);
+                minhb = fmin(minhb, fr);
+                P[np++] = {te, 0, true, gv};
+                shortened = true;
+                break;
+            }
+            P[np++] = {C.t[d][gi], nxt, false, 0.0};
+            pos = nxt;
+            if (ty == 0) break;   // a wall node: known value, nothing beyond it
+        }
+        if (np < want) shortened = true;
+    }
+    if (shortened) ++fb;
+    // moment conditions in scaled coordinates
+    double tref = C.t[d][cidx + ((sl && sr) ? plo : (sr ? phi_ : plo))];
+    double href = 0.0;
+    for (int q = 0; q < np; ++q) href = fmax(href, fabs(P[q].t - tref));
+    double A[64], rhs[8], w[8];
+    for (int m = 0; m < np; ++m) {
+        double s = 0.0;
+        if (m >= 2)
+            for (int p = plo; p <= phi_; ++p) {
+                double xi = (C.t[d][cidx + p] - tref) / href;
+                double pw = 1.0;
+                for (int q = 0; q < m - 2; ++q) pw *= xi;
+                s += Ld[p + 1] * (double)(m * (m - 1)) * pw;
+            }
+        rhs[m] = s / (href * href);
+        for (int q = 0; q < np; ++q) {
+            double xi = (P[q].t - tref) / href;
+            double pw = 1.0;
+            for (int e = 0; e < m; ++e) pw *= xi;
+            A[m * np + q] = pw;
+        }
+    }
+    if (!small_solve(np, A, rhs, w)) {
+        atomicOr(bad, 1);   // singular one-sided system: reported to the host
+        return;
+    }
+    for (int q = 0; q < np; ++q) {
+        double c = W * w[q];
+        if (P[q].ibi) {
+            R.rhs -= c * P[q].gval;
+        } else {
+            int o[3] = {wc[0], wc[1], wc[2]};
+            o[d] = P[q].off;
+            put(C, R, rownode, o, c);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64) k_build_rows(Ctx C, int nirr, const int *__restrict__ nodes, int cap,
+                                                   int *__restrict__ ell_col, double *__restrict__ ell_val,
+                                                   int *__restrict__ len, double *__restrict__ rhs_row,
+                                                   double *__restrict__ k7, double *__restrict__ bdiag,
+                                                   double *__restrict__ minhb_row, int *__restrict__ fb_row,
+                                                   int *__restrict__ bad)
+{
+    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nirr) return;
+    const size_t rownode = (size_t)nodes[row];
+    const int nx = C.n[0], ny = C.n[1];
+    const int idx[3] = {(int)(rownode % nx), (int)((rownode / nx) % ny), (int)(rownode / ((size_t)nx * ny))};
+    double L[3][3], Rr[3][3];
+    for (int d = 0; d < 3; ++d) {
+        const double *c = C.coef[d] + 8 * idx[d];
+        L[d][0] = c[0]; L[d][1] = 1.0; L[d][2] = c[1];
+        Rr[d][0] = c[2]; Rr[d][1] = c[3]; Rr[d][2] = c[4];
+    }
+    RowAcc R;
+    for (int q = 0; q < NSLOT; ++q) R.val[q] = 0.0;
+    for (int q = 0; q < (NSLOT + 31) / 32; ++q) R.used[q] = 0u;
+    R.rhs = 0.0;
+    int fb = 0;
+    double minhb = 1.0;
+    // Q-bar: the row's L_x L_y L_z weights on f at every non-solid node of the 3x3x3 box
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                size_t node = rownode + dx + (ptrdiff_t)dy * nx + (ptrdiff_t)dz * (ptrdiff_t)C.stride[2];
+                if (C.type[node] != 3) R.rhs += L[0][dx + 1] * L[1][dy + 1] * L[2][dz + 1] * C.f[node];
+            }
+    // 27 windows
+    for (int d = 0; d < 3; ++d) {
+        const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        for (int s1 = -1; s1 <= 1; ++s1)
+            for (int s2 = -1; s2 <= 1; ++s2) {
+                const double W = L[d1][s1 + 1] * L[d2][s2 + 1];
+                int wc[3] = {0, 0, 0};
+                wc[d1] = s1;
+                wc[d2] = s2;
+                bool sol[3];
+                int nsol = 0;
+                for (int p = -1; p <= 1; ++p) {
+                    int o[3] = {wc[0], wc[1], wc[2]};
+                    o[d] = p;
+                    size_t node = rownode + (ptrdiff_t)o[0] + (ptrdiff_t)o[1] * nx + (ptrdiff_t)o[2] * (ptrdiff_t)C.stride[2];
+                    sol[p + 1] = C.type[node] == 3;
+                    nsol += sol[p + 1];
+                }
+                if (nsol == 3) continue;   // window inside the body: dropped
+                if (nsol == 0) {
+                    for (int p = -1; p <= 1; ++p) {
+                        int o[3] = {wc[0], wc[1], wc[2]};
+                        o[d] = p;
+                        put(C, R, rownode, o, W * Rr[d][p + 1]);
+                    }
+                    continue;
+                }
+                int lo[2], hi[2], nr = 0;
+                for (int p = -1; p <= 1;) {
+                    if (sol[p + 1]) { ++p; continue; }
+                    int a = p;
+                    while (p < 1 && !sol[p + 2]) ++p;
+                    lo[nr] = a;
+                    hi[nr] = p;
+                    ++nr;
+                    ++p;
+                }
+                for (int q = 0; q < nr; ++q)
+                    run_operator(C, R, rownode, idx, d, wc, lo[q], hi[q], sol, nr, L[d], W, fb, minhb, bad);
+            }
+    }
+    // Shortley-Weller K row (Eqs. 2ndorder_coef_mod, A7_mod)
+    double kr[7];
+    kr[0] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        int b0[3] = {idx[0], idx[1], idx[2]};
+        b0[d] = 0;
+        size_t line0 = (size_t)b0[0] * C.stride[0] + (size_t)b0[1] * C.stride[1] + (size_t)b0[2] * C.stride[2];
+        size_t nm = rownode - C.stride[d], npl = rownode + C.stride[d];
+        double hb = C.t[d][idx[d]] - C.t[d][idx[d] - 1], hf = C.t[d][idx[d] + 1] - C.t[d][idx[d]];
+        double gv, fr;
+        if (C.type[nm] == 3) hb = C.t[d][idx[d]] - ibi_on_segment(C, d, line0, idx[d], idx[d] - 1, &gv, &fr);
+        if (C.type[npl] == 3) hf = ibi_on_segment(C, d, line0, idx[d], idx[d] + 1, &gv, &fr) - C.t[d][idx[d]];
+        kr[0] += -2.0 / (hb * hf);
+        int8_t tm = C.type[nm], tp = C.type[npl];
+        kr[1 + 2 * d] = (tm == 1 || tm == 2) ? 2.0 / (hb * (hf + hb)) : 0.0;
+        kr[2 + 2 * d] = (tp == 1 || tp == 2) ? 2.0 / (hf * (hf + hb)) : 0.0;
+    }
+    for (int q = 0; q < 7; ++q) k7[7 * (size_t)row + q] = kr[q];
+    // emit the row in slot order
+    int cnt = 0;
+    for (int sl = 0; sl < NSLOT; ++sl) {
+        if (!((R.used[sl >> 5] >> (sl & 31)) & 1u)) continue;
+        int o[3];
+        if (sl < 27) {
+            o[0] = sl % 3 - 1; o[1] = (sl / 3) % 3 - 1; o[2] = sl / 9 - 1;
+        } else {
+            int q = sl - 27;
+            int t2 = q % 3 - 1; q /= 3;
+            int t1 = q % 3 - 1; q /= 3;
+            int m = q % 4 + 2; q /= 4;
+            int pos = q % 2; int far = q / 2;
+            o[far] = pos ? m : -m;
+            o[(far + 1) % 3] = t1;
+            o[(far + 2) % 3] = t2;
+        }
+        size_t node = rownode + (ptrdiff_t)o[0] + (ptrdiff_t)o[1] * nx + (ptrdiff_t)o[2] * (ptrdiff_t)C.stride[2];
+        if (cnt < cap) {
+            ell_col[(size_t)row * cap + cnt] = (int)node;
+            ell_val[(size_t)row * cap + cnt] = R.val[sl];
+        }
+        ++cnt;
+    }
+    len[row] = min(cnt, cap);
+    rhs_row[row] = R.rhs;
+    bdiag[row] = R.val[13];
+    minhb_row[row] = minhb;
+    fb_row[row] = fb;
+    if (cnt > cap) atomicOr(bad, 2);
+}
+
+void launch_build_rows(hipStream_t s, int nx, int ny, int nz, const double *x, const double *y, const double *z,
+                       const double *coef, const double *phi, const double *g, const double *f, const int8_t *type,
+                       int nirr, const int *nodes, int cap, int *ell_col, double *ell_val, int *len, double *rhs_row,
+                       double *k7, double *bdiag, double *minhb, int *fallback, int *bad)
+{
+    if (nirr == 0) return;
+    Ctx C;
+    C.n[0] = nx; C.n[1] = ny; C.n[2] = nz;
+    C.stride[0] = 1; C.stride[1] = nx; C.stride[2] = (size_t)nx * ny;
+    C.t[0] = x; C.t[1] = y; C.t[2] = z;
+    int nmax = std::max(nx, std::max(ny, nz));
+    for (int d = 0; d < 3; ++d) C.coef[d] = coef + (size_t)d * 8 * nmax;
+    C.phi = phi; C.g = g; C.f = f; C.type = type;
+    k_build_rows<<<(nirr + 63) / 64, 64, 0, s>>>(C, nirr, nodes, cap, ell_col, ell_val, len, rhs_row, k7, bdiag, minhb,
+                                                 fallback, bad);
+}
+
+__global__ void k_pack_rows(int nirr, int cap, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
+                            const int *__restrict__ len, const int *__restrict__ ptr, int *__restrict__ col,
+                            double *__restrict__ val64, float *__restrict__ val32)
+{
+    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nirr) return;
+    int n = min(len[row], cap), o = ptr[row];
+    for (int q = 0; q < n; ++q) {
+        col[o + q] = ell_col[(size_t)row * cap + q];
+        double v = ell_val[(size_t)row * cap + q];
+        val64[o + q] = v;
+        val32[o + q] = (float)v;
+    }
+}
+
+void launch_pack_rows(hipStream_t s, int nirr, int cap, const int *ell_col, const double *ell_val, const int *len,
+                      const int *ptr, int *col, double *val64, float *val32)
+{
+    if (nirr == 0) return;
+    k_pack_rows<<<(nirr + 255) / 256, 256, 0, s>>>(nirr, cap, ell_col, ell_val, len, ptr, col, val64, val32);
+}
+
+// ---------------------------------------------------------------------------------------
+// right-hand side at regular rows: Q f (Eq. q) minus the known wall-node terms of Eq. A27
+// ---------------------------------------------------------------------------------------
+__global__ void k_rhs_regular(int nx, int ny, int nz, const double *__restrict__ coef, int nmax,
+                              const double *__restrict__ f, const double *__restrict__ g,
+                              const int8_t *__restrict__ type, double *__restrict__ rhs)
+{
+    size_t n = (size_t)nx * ny * nz;
+    size_t plane = (size_t)nx * ny;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        if (type[e] != 1) continue;
+        int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / plane);
+        const double *cx = coef + 8 * i, *cy = coef + 8 * (size_t)nmax + 8 * j, *cz = coef + 16 * (size_t)nmax + 8 * k;
+        double Lx[3] = {cx[0], 1.0, cx[1]}, Rx[3] = {cx[2], cx[3], cx[4]};
+        double Ly[3] = {cy[0], 1.0, cy[1]}, Ry[3] = {cy[2], cy[3], cy[4]};
+        double Lz[3] = {cz[0], 1.0, cz[1]}, Rz[3] = {cz[2], cz[3], cz[4]};
+        double acc = 0.0;
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q)
+                for (int p = 0; p < 3; ++p) {
+                    size_t nb = e + (p - 1) + (ptrdiff_t)(q - 1) * nx + (ptrdiff_t)(r - 1) * (ptrdiff_t)plane;
+                    acc += Lx[p] * Ly[q] * Lz[r] * f[nb];
+                    if (type[nb] == 0) {
+                        double a = Rx[p] * Ly[q] * Lz[r] + Lx[p] * Ry[q] * Lz[r] + Lx[p] * Ly[q] * Rz[r];
+                        acc -= a * g[nb];
+                    }
+                }
+        rhs[e] = acc;
+    }
+}
+
+void launch_rhs_regular(hipStream_t s, int nx, int ny, int nz, const double *coef, const double *f, const double *g,
+                        const int8_t *type, double *rhs)
+{
+    size_t n = (size_t)nx * ny * nz;
+    int nmax = std::max(nx, std::max(ny, nz));
+    k_rhs_regular<<<(unsigned)std::min<size_t>((n + 255) / 256, 65536), 256, 0, s>>>(nx, ny, nz, coef, nmax, f, g, type,
+                                                                                      rhs);
+}
+
+__global__ void k_scatter_rows(int nirr, const int *__restrict__ nodes, const double *__restrict__ rhs_row,
+                               double *__restrict__ rhs)
+{
+    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row < nirr) rhs[nodes[row]] = rhs_row[row];
+}
+
+void launch_scatter_rows(hipStream_t s, int nirr, const int *nodes, const double *rhs_row, double *rhs)
+{
+    if (nirr == 0) return;
+    k_scatter_rows<<<(nirr + 255) / 256, 256, 0, s>>>(nirr, nodes, rhs_row, rhs);
+}
+
+__global__ void k_to_float(size_t n, const double *__restrict__ a, float *__restrict__ b)
+{
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        b[e] = (float)a[e];
+}
+
+void launch_to_float(hipStream_t s, size_t n, const double *a, float *b)
+{
+    if (n == 0) return;
+    k_to_float<<<(unsigned)std::min<size_t>((n + 255) / 256, 65536), 256, 0, s>>>(n, a, b);
+}
+
+// min of a[] and sum of fb[] by one block
+__global__ void k_min_reduce(int n, const double *__restrict__ a, const int *__restrict__ fb, double *out_min,
+                             long long *out_sum)
+{
+    __shared__ double smin[256];
+    __shared__ long long ssum[256];
+    double mn = 1.0;
+    long long sm = 0;
+    for (int q = threadIdx.x; q < n; q += 256) {
+        mn = fmin(mn, a[q]);
+        sm += fb[q];
+    }
+    smin[threadIdx.x] = mn;
+    ssum[threadIdx.x] = sm;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+            ssum[threadIdx.x] += ssum[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out_min = smin[0];
+        *out_sum = ssum[0];
+    }
+}
+
+void launch_min_reduce(hipStream_t s, int n, const double *a, const int *fb, double *out_min, long long *out_sum)
+{
+    k_min_reduce<<<1, 256, 0, s>>>(n, a, fb, out_min, out_sum);
+}
+
+}  // namespace cps

@@ -1,0 +1,861 @@
+// solver.hip -- host side of the C-ABI declared in include/cps.h: device memory, the setup
+// sequence, the BiCGSTAB driver (Alg. 1) in FP64, and the FP32-inner / FP64-refinement
+// driver.  Every arithmetic step runs in the kernels of setup.hip and sweeps.hip; the host
+// only launches, polls one small device-state record per iteration and checks the final
+// FP64 residual.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cps.h"
+#include "cps_device.h"
+#include "cps_kernels.h"
+
+using namespace cps;
+
+namespace {
+
+constexpr double DEFAULT_LAM_LO = 0.03;   // Chebyshev interval of diag(K)^-1 K
+constexpr double DEFAULT_LAM_HI = 2.0;    // Gershgorin bound: diag-dominant K rows
+constexpr int ELL_CAP = 243;               // 27 box nodes + 216 extra-point positions
+constexpr int MAX_INNER = 64;
+
+template <typename T>
+struct Vecs {
+    T *r = nullptr, *r0 = nullptr, *p = nullptr, *ph = nullptr, *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr;
+    T *x = nullptr, *c[3] = {nullptr, nullptr, nullptr};
+    bool ready = false;
+};
+
+}  // namespace
+
+struct cps_solver {
+    cps_options opt;
+    hipStream_t stream = nullptr;
+    Geom g{};
+    int nx = 0, ny = 0, nz = 0, nmax = 0;
+    size_t nn = 0;
+    // device data
+    double *xyz = nullptr;        // x | y | z
+    double *coef64 = nullptr;     // 3 * 8 * nmax
+    float *coef32 = nullptr;
+    double *phi = nullptr, *gf = nullptr, *f = nullptr;
+    int8_t *type = nullptr;
+    uint32_t *skip = nullptr;
+    int nirr = 0;
+    int *irr_node = nullptr, *irr_ptr = nullptr, *irr_col = nullptr;
+    double *irr_val64 = nullptr, *irr_k64 = nullptr, *irr_bd64 = nullptr;
+    float *irr_val32 = nullptr, *irr_k32 = nullptr, *irr_bd32 = nullptr;
+    double *rhs = nullptr;
+    double *partials = nullptr;
+    unsigned *ticket = nullptr;
+    DevState *st = nullptr;
+    int *dflag = nullptr;
+    DevState *hst = nullptr;      // pinned, 2 slots
+    double *hscalar = nullptr;    // pinned staging
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> tev;  // sweep timing events
+    size_t tev_used = 0;
+    Vecs<double> v64;
+    Vecs<float> v32;
+    double *tmp64 = nullptr;      // user-facing staging (residual, apply, precond)
+    double *x64 = nullptr;        // FP64 solution in mixed mode
+    float *tmp32a = nullptr, *tmp32b = nullptr;
+    // host-side facts
+    long long n_unknown = 0, n_solid = 0, nnz = 0, fallback = 0;
+    double min_hb = 1.0;
+    double bn2 = 0.0, bs2 = 0.0;  // ||b||^2, ||D^-1 b||^2
+    double setup_ms = 0.0;
+    std::vector<void *> allocs;
+
+    Launch launch() const { return Launch{g, stream, skip, partials, ticket}; }
+    Coef<double> cf64() const
+    {
+        Coef<double> c;
+        for (int d = 0; d < 3; ++d) c.c[d] = coef64 + (size_t)d * 8 * nmax;
+        return c;
+    }
+    Coef<float> cf32() const
+    {
+        Coef<float> c;
+        for (int d = 0; d < 3; ++d) c.c[d] = coef32 + (size_t)d * 8 * nmax;
+        return c;
+    }
+    Irr<double> ir64() const { return Irr<double>{nirr, irr_node, irr_ptr, irr_col, irr_val64, irr_k64, irr_bd64}; }
+    Irr<float> ir32() const { return Irr<float>{nirr, irr_node, irr_ptr, irr_col, irr_val32, irr_k32, irr_bd32}; }
+};
+
+namespace {
+
+struct HipFail {
+    hipError_t e;
+};
+
+inline void ck(hipError_t e)
+{
+    if (e != hipSuccess) throw HipFail{e};
+}
+
+template <typename T>
+T *dalloc(cps_solver *s, size_t n)
+{
+    void *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) throw std::bad_alloc();
+    s->allocs.push_back(p);
+    return (T *)p;
+}
+
+void dfree(cps_solver *s, void *p)
+{
+    if (!p) return;
+    auto it = std::find(s->allocs.begin(), s->allocs.end(), p);
+    if (it != s->allocs.end()) s->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+// copy a caller array (host or device per opt.device_ptrs) to device memory
+void to_device(cps_solver *s, void *dst, const void *src, size_t bytes)
+{
+    ck(hipMemcpyAsync(dst, src, bytes, s->opt.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+}
+
+void from_device(cps_solver *s, void *dst, const void *src, size_t bytes)
+{
+    ck(hipMemcpyAsync(dst, src, bytes, s->opt.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+}
+
+void sync(cps_solver *s) { ck(hipStreamSynchronize(s->stream)); }
+
+DevState read_state(cps_solver *s)
+{
+    ck(hipMemcpyAsync(&s->hst[0], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+    sync(s);
+    return s->hst[0];
+}
+
+void set_stop2(cps_solver *s, double v)
+{
+    // staged through pinned memory; the copy is ordered with the kernels on the stream
+    s->hscalar[0] = v;
+    ck(hipMemcpyAsync(&s->st->stop2, s->hscalar, sizeof(double), hipMemcpyHostToDevice, s->stream));
+}
+
+Geom make_geom(int nx, int ny, int nz)
+{
+    Geom g{};
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.W = (nx + 31) / 32;
+    g.tiles_x = (nx - 2 + TX - 1) / TX;
+    g.tiles_y = (ny - 2 + TY - 1) / TY;
+    int per_plane = g.tiles_x * g.tiles_y;
+    int nzi = nz - 2;
+    int want = std::max(1, (2048 + per_plane - 1) / per_plane);
+    int TZ = std::max(std::min(8, nzi), (nzi + want - 1) / want);
+    g.TZ = TZ;
+    g.zchunks = (nzi + TZ - 1) / TZ;
+    g.ntiles = per_plane * g.zchunks;
+    g.nblk_tiles = (g.ntiles + NXCD - 1) / NXCD * NXCD;
+    return g;
+}
+
+// Chebyshev step coefficients for [lo, hi] (Saad, Alg. 12.1): c1[0] = 0, c2[0] = 1/theta
+void cheb_coefficients(int m, double lo, double hi, double *c1, double *c2)
+{
+    double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double rp = 1.0 / sigma;
+    c1[0] = 0.0;
+    c2[0] = 1.0 / theta;
+    for (int k = 1; k < m; ++k) {
+        double r = 1.0 / (2.0 * sigma - rp);
+        c1[k] = r * rp;
+        c2[k] = 2.0 * r / delta;
+        rp = r;
+    }
+}
+
+template <typename T>
+void alloc_vecs(cps_solver *s, Vecs<T> &V)
+{
+    if (V.ready) return;
+    T **all[] = {&V.r, &V.r0, &V.p, &V.ph, &V.v, &V.s, &V.sh, &V.t, &V.x, &V.c[0], &V.c[1], &V.c[2]};
+    for (T **p : all) {
+        *p = dalloc<T>(s, s->nn);
+        launch_fill<T>(s->stream, s->nn, *p, T(0));
+    }
+    V.ready = true;
+}
+
+hipEvent_t timing_event(cps_solver *s)
+{
+    if (s->tev_used == s->tev.size()) {
+        hipEvent_t e;
+        ck(hipEventCreate(&e));
+        s->tev.push_back(e);
+    }
+    return s->tev[s->tev_used++];
+}
+
+// p^ = M p: inner_iters Chebyshev steps; the first is fused with the vector update `kind`
+template <typename T>
+void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T *v, T *dst, const double *c1,
+                   const double *c2, const DevState *st)
+{
+    const Launch L = s->launch();
+    Coef<T> cf;
+    Irr<T> ir;
+    if constexpr (sizeof(T) == 8) { cf = s->cf64(); ir = s->ir64(); } else { cf = s->cf32(); ir = s->ir32(); }
+    const int m = s->opt.inner_iters;
+    T *x1 = (m == 1) ? dst : V.c[0];
+    launch_first<T>(kind, L, cf, ir, r, ps, v, x1, c2[0], st);
+    for (int k = 1; k < m; ++k) {
+        const T *xc = V.c[(k - 1) % 3];
+        const T *xm1 = (k == 1) ? nullptr : V.c[(k - 2) % 3];
+        T *xn = (k == m - 1) ? dst : V.c[k % 3];
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (s->opt.kernel_timing) {
+            e0 = timing_event(s);
+            e1 = timing_event(s);
+            ck(hipEventRecord(e0, s->stream));
+        }
+        launch_cheb<T>(L, cf, ir, xc, xm1, ps, xn, c1[k], c2[k], st);
+        if (s->opt.kernel_timing) ck(hipEventRecord(e1, s->stream));
+    }
+}
+
+// one BiCGSTAB iteration (Alg. 1, lines 4-14) entirely on the device
+template <typename T, typename TXS>
+void enqueue_iteration(cps_solver *s, Vecs<T> &V, TXS *xsol, const double *c1, const double *c2)
+{
+    const Launch L = s->launch();
+    Coef<T> cf;
+    Irr<T> ir;
+    if constexpr (sizeof(T) == 8) { cf = s->cf64(); ir = s->ir64(); } else { cf = s->cf32(); ir = s->ir32(); }
+    precond_apply<T>(s, V, FIRST_P, V.r, V.p, V.v, V.ph, c1, c2, s->st);        // p update; K p^ = p
+    launch_apply<T, T>(MODE_V, L, cf, ir, V.ph, V.v, V.r0, nullptr, s->st);    // v = B p^; alpha
+    precond_apply<T>(s, V, FIRST_S, V.r, V.s, V.v, V.sh, c1, c2, s->st);       // s = r - alpha v; K s^ = s
+    launch_apply<T, T>(MODE_T, L, cf, ir, V.sh, V.t, V.s, nullptr, s->st);     // t = B s^; omega
+    launch_update<T, TXS>(L, cf, ir, xsol, V.ph, V.sh, V.s, V.t, V.r0, V.r, s->st);  // x, r, beta
+}
+
+// run iterations until the device reports done or `budget` iterations were enqueued;
+// the host polls the state of iteration n-1 while iteration n is queued.
+template <typename T, typename TXS>
+DevState run_iterations(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget, const double *c1, const double *c2)
+{
+    for (int n = 0; n < budget; ++n) {
+        enqueue_iteration<T, TXS>(s, V, xsol, c1, c2);
+        ck(hipMemcpyAsync(&s->hst[n & 1], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+        ck(hipEventRecord(s->ev[n & 1], s->stream));
+        if (n >= 1) {
+            ck(hipEventSynchronize(s->ev[(n - 1) & 1]));
+            if (s->hst[(n - 1) & 1].done) break;
+        }
+    }
+    return read_state(s);
+}
+
+void free_solver(cps_solver *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (void *p : s->allocs) (void)hipFree(p);
+    s->allocs.clear();
+    if (s->hst) (void)hipHostFree(s->hst);
+    if (s->hscalar) (void)hipHostFree(s->hscalar);
+    for (auto &e : s->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto e : s->tev) (void)hipEventDestroy(e);
+    delete s;
+}
+
+int fill_stats(cps_solver *s, cps_stats *st, const DevState &ds, int iters, int iters32, int refine, int restarts,
+               int status, double solve_ms)
+{
+    if (!st) return status;
+    if (st->struct_size != (int32_t)sizeof(cps_stats) && st->struct_size != 0) return CPS_EINVAL;
+    std::memset(st, 0, sizeof(*st));
+    st->struct_size = sizeof(cps_stats);
+    st->iters = iters;
+    st->iters_fp32 = iters32;
+    st->refine_steps = refine;
+    st->restarts = restarts;
+    st->status = status;
+    st->n_unknowns = s->n_unknown;
+    st->n_irregular = s->nirr;
+    st->n_solid = s->n_solid;
+    st->nnz_irregular = s->nnz;
+    st->fallback_lines = s->fallback;
+    st->rel_residual = std::sqrt(ds.res2 / (s->bn2 > 0 ? s->bn2 : 1.0));
+    st->rel_residual_jacobi = std::sqrt(ds.res2s / (s->bs2 > 0 ? s->bs2 : 1.0));
+    st->min_ibi_frac = s->min_hb;
+    st->setup_ms = s->setup_ms;
+    st->solve_ms = solve_ms;
+    st->sweep_points = (int64_t)(s->nx - 2) * (s->ny - 2) * (s->nz - 2);
+    if (s->opt.kernel_timing && s->tev_used >= 2) {
+        double tot = 0.0;
+        for (size_t q = 0; q + 1 < s->tev_used; q += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, s->tev[q], s->tev[q + 1]) == hipSuccess) tot += ms;
+        }
+        st->sweep_ms = tot;
+        st->sweep_launches = (int64_t)(s->tev_used / 2);
+    }
+    st->sweep_bytes_per_point = (s->opt.precision == CPS_MIXED) ? 16 : 32;
+    return status;
+}
+
+int rhs_build(cps_solver *s)
+{
+    // irregular rows (FP64): ELL scratch -> CSR; K rows; diagonal; RHS; then regular RHS
+    const hipStream_t st = s->stream;
+    int n = s->nirr;
+    int *ell_col = dalloc<int>(s, (size_t)n * ELL_CAP);
+    double *ell_val = dalloc<double>(s, (size_t)n * ELL_CAP);
+    int *len = dalloc<int>(s, n + 1);
+    double *rhs_row = dalloc<double>(s, n);
+    double *minhb = dalloc<double>(s, n);
+    int *fb = dalloc<int>(s, n);
+    if (!s->irr_k64) {
+        s->irr_k64 = dalloc<double>(s, (size_t)7 * n);
+        s->irr_bd64 = dalloc<double>(s, n);
+        s->irr_ptr = dalloc<int>(s, n + 1);
+    }
+    ck(hipMemsetAsync(s->dflag, 0, sizeof(int), st));
+    launch_build_rows(st, s->nx, s->ny, s->nz, s->xyz, s->xyz + s->nx, s->xyz + s->nx + s->ny, s->coef64, s->phi, s->gf,
+                      s->f, s->type, n, s->irr_node, ELL_CAP, ell_col, ell_val, len, rhs_row, s->irr_k64, s->irr_bd64,
+                      minhb, fb, s->dflag);
+    launch_scan(st, len, s->irr_ptr, n);
+    int total = 0, bad = 0;
+    ck(hipMemcpyAsync(s->hscalar, s->irr_ptr + n, sizeof(int), hipMemcpyDeviceToHost, st));
+    ck(hipMemcpyAsync(s->hscalar + 1, s->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    sync(s);
+    std::memcpy(&total, s->hscalar, sizeof(int));
+    std::memcpy(&bad, s->hscalar + 1, sizeof(int));
+    if (bad) {
+        for (void *p : {(void *)ell_col, (void *)ell_val, (void *)len, (void *)rhs_row, (void *)minhb, (void *)fb})
+            dfree(s, p);
+        return CPS_EGEOM;   // a singular one-sided system
+    }
+    if (!s->irr_col || s->nnz != total) {
+        dfree(s, s->irr_col);
+        dfree(s, s->irr_val64);
+        dfree(s, s->irr_val32);
+        s->irr_col = dalloc<int>(s, total);
+        s->irr_val64 = dalloc<double>(s, total);
+        s->irr_val32 = dalloc<float>(s, total);
+    }
+    s->nnz = total;
+    launch_pack_rows(st, n, ELL_CAP, ell_col, ell_val, len, s->irr_ptr, s->irr_col, s->irr_val64, s->irr_val32);
+    if (!s->irr_k32) {
+        s->irr_k32 = dalloc<float>(s, (size_t)7 * n);
+        s->irr_bd32 = dalloc<float>(s, n);
+    }
+    launch_to_float(st, (size_t)7 * n, s->irr_k64, s->irr_k32);
+    launch_to_float(st, (size_t)n, s->irr_bd64, s->irr_bd32);
+    launch_fill<double>(st, s->nn, s->rhs, 0.0);
+    launch_rhs_regular(st, s->nx, s->ny, s->nz, s->coef64, s->f, s->gf, s->type, s->rhs);
+    launch_scatter_rows(st, n, s->irr_node, rhs_row, s->rhs);
+    long long *dsum = dalloc<long long>(s, 1);
+    double *dmin = dalloc<double>(s, 1);
+    if (n > 0) {
+        launch_min_reduce(st, n, minhb, fb, dmin, dsum);
+        ck(hipMemcpyAsync(s->hscalar, dmin, sizeof(double), hipMemcpyDeviceToHost, st));
+        ck(hipMemcpyAsync(s->hscalar + 1, dsum, sizeof(long long), hipMemcpyDeviceToHost, st));
+        sync(s);
+        s->min_hb = s->hscalar[0];
+        long long fbs;
+        std::memcpy(&fbs, s->hscalar + 1, sizeof(long long));
+        s->fallback = fbs;
+    }
+    // ||b||^2 and ||D^-1 b||^2: the residual kernel applied to x = 0
+    double *zero = dalloc<double>(s, s->nn);
+    double *outb = dalloc<double>(s, s->nn);
+    launch_fill<double>(st, s->nn, zero, 0.0);
+    launch_apply<double, double>(MODE_RES, s->launch(), s->cf64(), s->ir64(), zero, outb, nullptr, s->rhs, s->st);
+    DevState ds = read_state(s);
+    s->bn2 = ds.res2;
+    s->bs2 = ds.res2s;
+    for (void *p : {(void *)ell_col, (void *)ell_val, (void *)len, (void *)rhs_row, (void *)minhb, (void *)fb,
+                    (void *)dsum, (void *)dmin, (void *)zero, (void *)outb})
+        dfree(s, p);
+    return CPS_OK;
+}
+
+int count_type(cps_solver *s, int8_t want, int *list, long long *count)
+{
+    int nb = compact_blocks(s->nn);
+    int *bc = dalloc<int>(s, 2 * (size_t)nb + 1);
+    int *dcount = dalloc<int>(s, 1);
+    int *lst = list ? list : dalloc<int>(s, s->nn);
+    launch_compact(s->stream, s->nn, s->type, want, bc, lst, dcount, nb);
+    ck(hipMemcpyAsync(s->hscalar, dcount, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    sync(s);
+    int c;
+    std::memcpy(&c, s->hscalar, sizeof(int));
+    *count = c;
+    dfree(s, bc);
+    dfree(s, dcount);
+    if (!list) dfree(s, lst);
+    return CPS_OK;
+}
+
+template <typename T>
+void precond_standalone(cps_solver *s, const double *rho_dev, double *out_dev)
+{
+    Vecs<T> V;
+    T *all[6];
+    for (auto &p : all) {
+        p = dalloc<T>(s, s->nn);
+        launch_fill<T>(s->stream, s->nn, p, T(0));
+    }
+    V.c[0] = all[0]; V.c[1] = all[1]; V.c[2] = all[2];
+    T *rin = all[3], *ps = all[4], *dst = all[5];
+    launch_masked_copy<double, T>(s->stream, s->nn, s->type, rho_dev, rin);
+    // state: alpha = 0 so that the fused first step computes x1 from rho itself
+    DevState zero{};
+    ck(hipMemcpyAsync(s->st, &zero, sizeof(DevState), hipMemcpyHostToDevice, s->stream));
+    sync(s);
+    double c1[MAX_INNER], c2[MAX_INNER];
+    cheb_coefficients(s->opt.inner_iters, s->opt.lam_lo, s->opt.lam_hi, c1, c2);
+    precond_apply<T>(s, V, FIRST_S, rin, ps, rin, dst, c1, c2, s->st);
+    launch_masked_copy<T, double>(s->stream, s->nn, s->type, dst, out_dev);
+    sync(s);
+    for (auto p : all) dfree(s, p);
+}
+
+}  // namespace
+
+// accessor used by the network's restriction (net.hip)
+int cps_internal_fields(cps_solver *s, const double **phi, const double **g, const double **f, int *nx, int *ny, int *nz,
+                        void **stream)
+{
+    *phi = s->phi;
+    *g = s->gf;
+    *f = s->f;
+    *nx = s->nx;
+    *ny = s->ny;
+    *nz = s->nz;
+    *stream = (void *)s->stream;
+    return 0;
+}
+
+// =========================================================================================
+// C-ABI
+// =========================================================================================
+extern "C" {
+
+void cps_default_options(cps_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(cps_options);
+    o->precision = CPS_FP64;
+    o->inner_iters = 8;
+    o->max_iters = 20000;
+    o->max_refine = 40;
+    o->max_restarts = 5;
+    o->device_ptrs = 0;
+    o->kernel_timing = 0;
+    o->inner_tol = 1e-4;
+    o->lam_lo = DEFAULT_LAM_LO;
+    o->lam_hi = DEFAULT_LAM_HI;
+    o->stream = nullptr;
+}
+
+const char *cps_strerror(int code)
+{
+    switch (code) {
+    case CPS_OK: return "ok";
+    case CPS_EINVAL: return "invalid argument (sizes, coordinates, NaN/Inf input or options)";
+    case CPS_EGEOM: return "invalid geometry (a body touches the wall, or a singular modified line)";
+    case CPS_ENOMEM: return "out of memory";
+    case CPS_EDEVICE: return "HIP runtime error or no GPU";
+    case CPS_EBREAKDOWN: return "BiCGSTAB breakdown beyond max_restarts";
+    case CPS_ENOCONV: return "not converged within max_iters";
+    case CPS_ENAN: return "NaN/Inf in the iteration";
+    default: return "unknown error";
+    }
+}
+
+int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double *x, const double *y, const double *z,
+              const double *phi, const double *g, const double *f, const cps_options *opt)
+{
+    if (!out || !x || !y || !z || !phi || !g || !f) return CPS_EINVAL;
+    *out = nullptr;
+    cps_options o;
+    cps_default_options(&o);
+    if (opt) {
+        if (opt->struct_size != (int32_t)sizeof(cps_options)) return CPS_EINVAL;
+        o = *opt;
+    }
+    if (nx < 3 || ny < 3 || nz < 3) return CPS_EINVAL;
+    if ((double)nx * ny * nz >= 2147483647.0) return CPS_EINVAL;
+    if (o.precision != CPS_FP64 && o.precision != CPS_MIXED) return CPS_EINVAL;
+    if (o.inner_iters < 1 || o.inner_iters > MAX_INNER || o.max_iters < 1 || o.max_refine < 1 || o.max_restarts < 0)
+        return CPS_EINVAL;
+    if (!(o.lam_hi > o.lam_lo) || !(o.lam_lo > 0.0) || !(o.inner_tol > 0.0 && o.inner_tol < 1.0)) return CPS_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return CPS_EDEVICE;
+    auto t0 = std::chrono::steady_clock::now();
+    cps_solver *s = new (std::nothrow) cps_solver();
+    if (!s) return CPS_ENOMEM;
+    s->opt = o;
+    s->stream = (hipStream_t)o.stream;
+    s->nx = nx; s->ny = ny; s->nz = nz;
+    s->nn = (size_t)nx * ny * nz;
+    s->nmax = std::max(nx, std::max(ny, nz));
+    s->g = make_geom(nx, ny, nz);
+    int rc = CPS_OK;
+    try {
+        ck(hipHostMalloc((void **)&s->hst, 2 * sizeof(DevState), hipHostMallocDefault));
+        ck(hipHostMalloc((void **)&s->hscalar, 8 * sizeof(double), hipHostMallocDefault));
+        for (auto &e : s->ev) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        // coordinates: validated on the host (they are small)
+        std::vector<double> hx(nx + ny + nz);
+        const double *srcs[3] = {x, y, z};
+        int ns[3] = {nx, ny, nz};
+        size_t off = 0;
+        s->xyz = dalloc<double>(s, nx + ny + nz);
+        for (int d = 0; d < 3; ++d) {
+            if (o.device_ptrs) ck(hipMemcpy(hx.data() + off, srcs[d], ns[d] * sizeof(double), hipMemcpyDeviceToHost));
+            else std::memcpy(hx.data() + off, srcs[d], ns[d] * sizeof(double));
+            for (int q = 0; q < ns[d]; ++q)
+                if (!std::isfinite(hx[off + q]) || (q > 0 && !(hx[off + q] > hx[off + q - 1]))) throw CPS_EINVAL;
+            off += ns[d];
+        }
+        ck(hipMemcpyAsync(s->xyz, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        s->phi = dalloc<double>(s, s->nn);
+        s->gf = dalloc<double>(s, s->nn);
+        s->f = dalloc<double>(s, s->nn);
+        to_device(s, s->phi, phi, s->nn * sizeof(double));
+        to_device(s, s->gf, g, s->nn * sizeof(double));
+        to_device(s, s->f, f, s->nn * sizeof(double));
+        // 1D tables
+        s->coef64 = dalloc<double>(s, (size_t)3 * 8 * s->nmax);
+        s->coef32 = dalloc<float>(s, (size_t)3 * 8 * s->nmax);
+        launch_fill<double>(s->stream, (size_t)3 * 8 * s->nmax, s->coef64, 0.0);
+        launch_coef(s->stream, nx, s->xyz, s->coef64);
+        launch_coef(s->stream, ny, s->xyz + nx, s->coef64 + (size_t)8 * s->nmax);
+        launch_coef(s->stream, nz, s->xyz + nx + ny, s->coef64 + (size_t)16 * s->nmax);
+        launch_to_float(s->stream, (size_t)3 * 8 * s->nmax, s->coef64, s->coef32);
+        // classification
+        s->type = dalloc<int8_t>(s, s->nn);
+        s->dflag = dalloc<int>(s, 1);
+        ck(hipMemsetAsync(s->dflag, 0, sizeof(int), s->stream));
+        launch_classify(s->stream, nx, ny, nz, s->phi, s->gf, s->f, s->type, s->dflag);
+        ck(hipMemcpyAsync(s->hscalar, s->dflag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        sync(s);
+        int flags;
+        std::memcpy(&flags, s->hscalar, sizeof(int));
+        if (flags & 1) throw CPS_EINVAL;
+        if (flags & 2) throw CPS_EGEOM;
+        launch_mark_irregular(s->stream, nx, ny, nz, s->type);
+        long long cnt;
+        s->irr_node = dalloc<int>(s, s->nn);   // trimmed below
+        count_type(s, 2, s->irr_node, &cnt);
+        s->nirr = (int)cnt;
+        count_type(s, 3, nullptr, &s->n_solid);
+        long long nreg;
+        count_type(s, 1, nullptr, &nreg);
+        s->n_unknown = nreg + s->nirr;
+        {
+            int *trimmed = dalloc<int>(s, s->nirr);
+            if (s->nirr) ck(hipMemcpyAsync(trimmed, s->irr_node, s->nirr * sizeof(int), hipMemcpyDeviceToDevice, s->stream));
+            sync(s);
+            dfree(s, s->irr_node);
+            s->irr_node = trimmed;
+        }
+        s->skip = dalloc<uint32_t>(s, (size_t)s->g.W * ny * nz);
+        launch_skipbits(s->stream, s->g, s->type, s->skip);
+        // reduction scratch: enough for the largest launch
+        size_t maxblk = (size_t)s->g.nblk_tiles + (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
+        s->partials = dalloc<double>(s, 2 * maxblk);
+        s->ticket = dalloc<unsigned>(s, 1);
+        launch_fill<unsigned>(s->stream, 1, s->ticket, 0u);
+        s->st = dalloc<DevState>(s, 1);
+        ck(hipMemsetAsync(s->st, 0, sizeof(DevState), s->stream));
+        s->rhs = dalloc<double>(s, s->nn);
+        rc = rhs_build(s);
+        sync(s);
+    } catch (int code) {
+        rc = code;
+    } catch (HipFail &) {
+        rc = CPS_EDEVICE;
+    } catch (std::bad_alloc &) {
+        rc = CPS_ENOMEM;
+    }
+    if (rc != CPS_OK) {
+        free_solver(s);
+        return rc;
+    }
+    s->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = s;
+    return CPS_OK;
+}
+
+int cps_set_rhs(cps_solver *s, const double *f, const double *g)
+{
+    if (!s || !f || !g) return CPS_EINVAL;
+    try {
+        to_device(s, s->f, f, s->nn * sizeof(double));
+        to_device(s, s->gf, g, s->nn * sizeof(double));
+        ck(hipMemsetAsync(s->dflag, 0, sizeof(int), s->stream));
+        // re-check finiteness with the classification kernel on a scratch type array
+        int8_t *tt = dalloc<int8_t>(s, s->nn);
+        launch_classify(s->stream, s->nx, s->ny, s->nz, s->phi, s->gf, s->f, tt, s->dflag);
+        ck(hipMemcpyAsync(s->hscalar, s->dflag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        sync(s);
+        dfree(s, tt);
+        int flags;
+        std::memcpy(&flags, s->hscalar, sizeof(int));
+        if (flags & 1) return CPS_EINVAL;
+        int rc = rhs_build(s);
+        sync(s);
+        return rc;
+    } catch (HipFail &) {
+        return CPS_EDEVICE;
+    } catch (std::bad_alloc &) {
+        return CPS_ENOMEM;
+    }
+}
+
+int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stats *stats)
+{
+    if (!s || !u || !(tol > 0.0)) return CPS_EINVAL;
+    if (stats && stats->struct_size != (int32_t)sizeof(cps_stats) && stats->struct_size != 0) return CPS_EINVAL;
+    auto t0 = std::chrono::steady_clock::now();
+    int status = CPS_ENOCONV;
+    int iters = 0, iters32 = 0, refine = 0, restarts = 0;
+    DevState ds{};
+    try {
+        s->tev_used = 0;
+        const int m = s->opt.inner_iters;
+        double c1[MAX_INNER], c2[MAX_INNER];
+        cheb_coefficients(m, s->opt.lam_lo, s->opt.lam_hi, c1, c2);
+        const Launch L = s->launch();
+        const double tol2 = tol * tol;
+        // FP64 solution vector (unknown entries only); the FP64 Krylov set only in FP64 mode
+        if (s->opt.precision == CPS_FP64) alloc_vecs<double>(s, s->v64);
+        if (!s->x64) s->x64 = dalloc<double>(s, s->nn);
+        double *x64 = (s->opt.precision == CPS_FP64) ? s->v64.x : s->x64;
+        if (warm_start) {
+            if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
+            to_device(s, s->tmp64, u, s->nn * sizeof(double));
+            launch_masked_copy<double, double>(s->stream, s->nn, s->type, s->tmp64, x64);
+            ck(hipMemsetAsync(s->dflag, 0, sizeof(int), s->stream));
+            launch_check_finite(s->stream, s->nn, s->type, x64, s->dflag);
+            ck(hipMemcpyAsync(s->hscalar, s->dflag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+            sync(s);
+            int bad;
+            std::memcpy(&bad, s->hscalar, sizeof(int));
+            if (bad) launch_fill<double>(s->stream, s->nn, x64, 0.0);   // reject a NaN/Inf warm start
+        } else {
+            launch_fill<double>(s->stream, s->nn, x64, 0.0);
+        }
+        auto converged = [&](const DevState &d) { return d.res2 <= tol2 * s->bn2 && d.res2s <= tol2 * s->bs2; };
+        // Target for the recursive Jacobi-weighted norm: tol^2 ||D^-1 b||^2, tightened in
+        // proportion when the paper-scaled norm is the one still above its target.
+        auto jacobi_target = [&](const DevState &d) {
+            double t2 = tol2 * s->bs2;
+            if (d.res2 > tol2 * s->bn2 && d.res2 > 0.0) t2 = std::min(t2, d.res2s * (tol2 * s->bn2 / d.res2));
+            return t2;
+        };
+        if (s->opt.precision == CPS_FP64) {
+            Vecs<double> &V = s->v64;
+            for (int pass = 0;; ++pass) {
+                launch_apply<double, double>(MODE_RES, L, s->cf64(), s->ir64(), x64, V.r, nullptr, s->rhs, s->st);
+                ds = read_state(s);
+                if (!(ds.res2 == ds.res2) || !(ds.res2s == ds.res2s)) { status = CPS_ENAN; break; }
+                if (converged(ds)) { status = CPS_OK; break; }
+                if (iters >= s->opt.max_iters) { status = CPS_ENOCONV; break; }
+                if (pass > 0 && ++restarts > s->opt.max_restarts) { status = CPS_EBREAKDOWN; break; }
+                set_stop2(s, jacobi_target(ds));
+                launch_restart<double>(L, s->ir64(), V.r, V.r0, V.p, V.v, s->st);
+                DevState d0 = read_state(s);
+                DevState d1 = d0.done ? d0 : run_iterations<double, double>(s, V, x64, s->opt.max_iters - iters, c1, c2);
+                iters += d1.iters - d0.iters;
+                if (d1.done == 3) { status = CPS_ENAN; break; }
+            }
+        } else {
+            alloc_vecs<float>(s, s->v32);
+            Vecs<float> &V = s->v32;
+            for (refine = 0;; ++refine) {
+                launch_apply<double, float>(MODE_RES, L, s->cf64(), s->ir64(), x64, V.r, nullptr, s->rhs, s->st);
+                ds = read_state(s);
+                if (!(ds.res2 == ds.res2) || !(ds.res2s == ds.res2s)) { status = CPS_ENAN; break; }
+                if (converged(ds)) { status = CPS_OK; break; }
+                if (iters >= s->opt.max_iters || refine >= s->opt.max_refine) { status = CPS_ENOCONV; break; }
+                if (restarts > s->opt.max_restarts) { status = CPS_EBREAKDOWN; break; }
+                // each FP32 solve reduces the residual by inner_tol, the last one just enough
+                double target2 = std::max(s->opt.inner_tol * s->opt.inner_tol * ds.res2s, 0.25 * jacobi_target(ds));
+                set_stop2(s, target2);
+                launch_fill<float>(s->stream, s->nn, V.x, 0.0f);
+                launch_restart<float>(L, s->ir32(), V.r, V.r0, V.p, V.v, s->st);
+                DevState d0 = read_state(s);
+                DevState d1 = d0.done ? d0 : run_iterations<float, float>(s, V, V.x, s->opt.max_iters - iters, c1, c2);
+                iters += d1.iters - d0.iters;
+                iters32 += d1.iters - d0.iters;
+                if (d1.done == 3) { ++restarts; continue; }   // discard a non-finite correction
+                if (d1.done == 2) ++restarts;
+                launch_add_correction(s->stream, s->nn, x64, V.x);
+            }
+        }
+        // output: unknowns, g on the walls, 0 in the bodies
+        if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
+        launch_output(s->stream, s->nn, s->type, x64, s->gf, s->tmp64);
+        from_device(s, u, s->tmp64, s->nn * sizeof(double));
+        sync(s);
+    } catch (HipFail &) {
+        return CPS_EDEVICE;
+    } catch (std::bad_alloc &) {
+        return CPS_ENOMEM;
+    }
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(s, stats, ds, iters, iters32, refine, restarts, status, ms);
+    return status;
+}
+
+int cps_residual(cps_solver *s, const double *u, double *r, double *rel)
+{
+    if (!s || !u) return CPS_EINVAL;
+    try {
+        if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
+        double *xin = dalloc<double>(s, s->nn);
+        double *rout = dalloc<double>(s, s->nn);
+        to_device(s, s->tmp64, u, s->nn * sizeof(double));
+        launch_masked_copy<double, double>(s->stream, s->nn, s->type, s->tmp64, xin);
+        launch_fill<double>(s->stream, s->nn, rout, 0.0);
+        launch_apply<double, double>(MODE_RES, s->launch(), s->cf64(), s->ir64(), xin, rout, nullptr, s->rhs, s->st);
+        if (r) from_device(s, r, rout, s->nn * sizeof(double));
+        DevState ds = read_state(s);
+        if (rel) {
+            rel[0] = std::sqrt(ds.res2 / (s->bn2 > 0 ? s->bn2 : 1.0));
+            rel[1] = std::sqrt(ds.res2s / (s->bs2 > 0 ? s->bs2 : 1.0));
+        }
+        dfree(s, xin);
+        dfree(s, rout);
+    } catch (HipFail &) {
+        return CPS_EDEVICE;
+    } catch (std::bad_alloc &) {
+        return CPS_ENOMEM;
+    }
+    return CPS_OK;
+}
+
+int cps_apply(cps_solver *s, const double *x, double *y, int32_t precision)
+{
+    if (!s || !x || !y || (precision != CPS_FP64 && precision != CPS_MIXED)) return CPS_EINVAL;
+    try {
+        if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
+        to_device(s, s->tmp64, x, s->nn * sizeof(double));
+        if (precision == CPS_FP64) {
+            double *xin = dalloc<double>(s, s->nn), *yo = dalloc<double>(s, s->nn);
+            launch_masked_copy<double, double>(s->stream, s->nn, s->type, s->tmp64, xin);
+            launch_fill<double>(s->stream, s->nn, yo, 0.0);
+            launch_apply<double, double>(MODE_PLAIN, s->launch(), s->cf64(), s->ir64(), xin, yo, nullptr, nullptr, nullptr);
+            from_device(s, y, yo, s->nn * sizeof(double));
+            sync(s);
+            dfree(s, xin);
+            dfree(s, yo);
+        } else {
+            float *xin = dalloc<float>(s, s->nn), *yo = dalloc<float>(s, s->nn);
+            launch_masked_copy<double, float>(s->stream, s->nn, s->type, s->tmp64, xin);
+            launch_fill<float>(s->stream, s->nn, yo, 0.0f);
+            launch_apply<float, float>(MODE_PLAIN, s->launch(), s->cf32(), s->ir32(), xin, yo, nullptr, nullptr, nullptr);
+            launch_masked_copy<float, double>(s->stream, s->nn, s->type, yo, s->tmp64);
+            from_device(s, y, s->tmp64, s->nn * sizeof(double));
+            sync(s);
+            dfree(s, xin);
+            dfree(s, yo);
+        }
+    } catch (HipFail &) {
+        return CPS_EDEVICE;
+    } catch (std::bad_alloc &) {
+        return CPS_ENOMEM;
+    }
+    return CPS_OK;
+}
+
+int cps_precond(cps_solver *s, const double *rho, double *phi, int32_t precision)
+{
+    if (!s || !rho || !phi || (precision != CPS_FP64 && precision != CPS_MIXED)) return CPS_EINVAL;
+    try {
+        if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
+        double *out = dalloc<double>(s, s->nn);
+        to_device(s, s->tmp64, rho, s->nn * sizeof(double));
+        bool timing = s->opt.kernel_timing;
+        s->opt.kernel_timing = 0;
+        if (precision == CPS_FP64) precond_standalone<double>(s, s->tmp64, out);
+        else precond_standalone<float>(s, s->tmp64, out);
+        s->opt.kernel_timing = timing;
+        from_device(s, phi, out, s->nn * sizeof(double));
+        sync(s);
+        dfree(s, out);
+    } catch (HipFail &) {
+        return CPS_EDEVICE;
+    } catch (std::bad_alloc &) {
+        return CPS_ENOMEM;
+    }
+    return CPS_OK;
+}
+
+int cps_get_rhs(cps_solver *s, double *rhs, int8_t *types)
+{
+    if (!s) return CPS_EINVAL;
+    try {
+        if (rhs) from_device(s, rhs, s->rhs, s->nn * sizeof(double));
+        if (types) from_device(s, types, s->type, s->nn);
+        sync(s);
+    } catch (HipFail &) {
+        return CPS_EDEVICE;
+    }
+    return CPS_OK;
+}
+
+int cps_get_info(cps_solver *s, int64_t out[6])
+{
+    if (!s || !out) return CPS_EINVAL;
+    out[0] = s->n_unknown;
+    out[1] = s->nirr;
+    out[2] = s->n_solid;
+    out[3] = s->nnz;
+    out[4] = s->fallback;
+    out[5] = (int64_t)s->nn;
+    return CPS_OK;
+}
+
+int cps_get_irregular(cps_solver *s, int64_t *node, int64_t *ptr, int64_t *col, double *val, double *krow)
+{
+    if (!s) return CPS_EINVAL;
+    try {
+        const int n = s->nirr;
+        std::vector<int> tmp;
+        auto widen = [&](const int *src, size_t cnt, int64_t *dst) {
+            tmp.resize(cnt);
+            if (cnt) ck(hipMemcpy(tmp.data(), src, cnt * sizeof(int), hipMemcpyDeviceToHost));
+            for (size_t q = 0; q < cnt; ++q) dst[q] = tmp[q];
+        };
+        sync(s);
+        if (node) widen(s->irr_node, n, node);
+        if (ptr) widen(s->irr_ptr, (size_t)n + 1, ptr);
+        if (col) widen(s->irr_col, (size_t)s->nnz, col);
+        if (val && s->nnz) ck(hipMemcpy(val, s->irr_val64, s->nnz * sizeof(double), hipMemcpyDeviceToHost));
+        if (krow && n) ck(hipMemcpy(krow, s->irr_k64, (size_t)7 * n * sizeof(double), hipMemcpyDeviceToHost));
+    } catch (HipFail &) {
+        return CPS_EDEVICE;
+    }
+    return CPS_OK;
+}
+
+void cps_destroy(cps_solver *s) { free_solver(s); }
+
+}  // extern "C"

