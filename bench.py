@@ -30,6 +30,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--parity-tol", type=float, default=1e-12,
+                    help="tolerance of the extra solves compared against the stored oracle samples")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
@@ -107,6 +109,34 @@ def main():
         fp64 = {"step_s": tb - ta, "solve_s": st64["solve_ms"] / 1e3, "iters": st64["iters"],
                 "rel_residual": st64["rel_residual"], "mixed_vs_fp64_rel_maxdiff": diff}
 
+    # parity: both precisions at a tighter tolerance against the stored FP64 oracle samples
+    parity = None
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_spheres8_{args.N}.txt")
+    if not args.no_fp64 and args.parity_tol > 0:
+        parity = {"tol": args.parity_tol}
+        samples = None
+        if os.path.exists(gold):
+            data = np.loadtxt(gold, comments="#")
+            umax = [float(l.split()[-1]) for l in open(gold) if l.startswith("# max_abs_u_fluid")][0]
+            samples = (torch.as_tensor(data[:, 0].astype(np.int64)).cuda(), torch.as_tensor(data[:, 1]).cuda(), umax)
+        for prec in ("mixed", "fp64"):
+            saved = args.tol
+            args.tol = args.parity_tol
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            up, stp = step(prec, False)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            args.tol = saved
+            ent = {"step_s": tb - ta, "solve_s": stp["solve_ms"] / 1e3, "iters": stp["iters"],
+                   "rel_residual": stp["rel_residual"], "rel_residual_jacobi": stp["rel_residual_jacobi"]}
+            if samples is not None:
+                got = up.reshape(-1)[samples[0]]
+                ent["vs_oracle_rel_maxdiff"] = float(torch.max(torch.abs(got - samples[1])) / samples[2])
+                ent["oracle_samples"] = int(samples[0].numel())
+            parity[prec] = ent
+        parity["speedup_mixed_vs_fp64_solve"] = parity["fp64"]["solve_s"] / parity["mixed"]["solve_s"]
+
     # roofline of the dominant kernel: the FP32 Chebyshev sweep of the preconditioner
     sweeps = sum(s["sweep_launches"] for s in stats)
     sweep_ms = sum(s["sweep_ms"] for s in stats)
@@ -156,6 +186,7 @@ def main():
         "unknown_iters_per_s": n_unk * last["iters"] / solve_s,
         "fp64": fp64,
         "speedup_vs_fp64_solve": (fp64["solve_s"] / solve_s) if fp64 else None,
+        "parity": parity,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -24,12 +24,20 @@ constexpr int NT = TX * TY;   // threads per block
 constexpr int IRR_LANES = 16; // lanes per irregular row in the B pass
 constexpr int NXCD = 8;       // MI355X: 8 XCDs, blocks dispatched round-robin over them
 
+// A tiling of the interior into (64 x ty) columns that march over z-chunks of TZ planes.
+struct Tiling {
+    int ty;                    // tile rows in y
+    int tiles_x, tiles_y, zchunks, TZ;
+    int ntiles;                // tiles_x * tiles_y * zchunks
+    int nblk;                  // ntiles rounded up to a multiple of NXCD
+};
+
 struct Geom {
     int nx, ny, nz;
     int W;                     // skip-bit words per x-line
-    int tiles_x, tiles_y, zchunks, TZ;
-    int ntiles;                // tiles_x * tiles_y * zchunks
-    int nblk_tiles;            // ntiles rounded up to a multiple of NXCD
+    Tiling t4;                 // 64 x 4 tiles: Chebyshev sweeps
+    Tiling t8;                 // 64 x 8 tiles (two rows per thread): the B apply
+    int nflat;                 // blocks of the flat (vectorised) pointwise kernels
 };
 
 template <typename T>
@@ -60,17 +68,17 @@ struct DevState {
     int iters;                 // completed iterations
 };
 
-__device__ __forceinline__ bool tile_of_block(const Geom &g, int b, int &bx, int &by, int &bz)
+__device__ __forceinline__ bool tile_of_block(const Tiling &t, int b, int &bx, int &by, int &bz)
 {
     // Give each XCD a contiguous range of tiles so that the halos of neighbouring tiles
     // are served from the same L2.
-    int per = g.nblk_tiles / NXCD;
-    int t = (b % NXCD) * per + b / NXCD;
-    if (t >= g.ntiles) return false;
-    bx = t % g.tiles_x;
-    t /= g.tiles_x;
-    by = t % g.tiles_y;
-    bz = t / g.tiles_y;
+    int per = t.nblk / NXCD;
+    int q = (b % NXCD) * per + b / NXCD;
+    if (q >= t.ntiles) return false;
+    bx = q % t.tiles_x;
+    q /= t.tiles_x;
+    by = q % t.tiles_y;
+    bz = q / t.tiles_y;
     return true;
 }
 
@@ -107,32 +115,26 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[NT / 64]
     }
 }
 
-// Writes this block's partial sums; returns true in every thread of the block that
-// finishes last.  That block then reads all partials (fixed order) and resets the ticket.
+// Writes this block's NV partial sums to partials[blockIdx.x * NV + q].  They are summed,
+// in a fixed order, by a one-block finalize kernel launched next on the same stream: the
+// kernel boundary makes every block's writes visible without device-scope fences.
 template <int NV>
-__device__ __forceinline__ bool publish_partials(double (&v)[NV], double *partials, unsigned *ticket, int nblocks)
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *partials)
 {
-    __shared__ double sh[NV > 0 ? NV : 1][NT / 64];
-    __shared__ bool last;
+    __shared__ double sh[NV][NT / 64];
     block_sum<NV>(v, sh);
     int tid = threadIdx.x + threadIdx.y * blockDim.x;
     if (tid == 0) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) partials[(size_t)blockIdx.x * NV + q] = v[q];
-        __threadfence();
-        unsigned t = atomicAdd(ticket, 1u);
-        last = (t == (unsigned)nblocks - 1);
     }
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
 }
 
-// In the last block: totals of the NV partial columns in fixed order; valid in thread 0.
+// Fixed-order totals of the NV partial columns over nblocks blocks; valid in thread 0.
 template <int NV>
-__device__ __forceinline__ void total_partials(double (&tot)[NV], const double *partials, unsigned *ticket, int nblocks)
+__device__ __forceinline__ void total_partials(double (&tot)[NV], const double *partials, int nblocks)
 {
-    __shared__ double sh[NV > 0 ? NV : 1][NT / 64];
+    __shared__ double sh[NV][NT / 64];
     int tid = threadIdx.x + threadIdx.y * blockDim.x;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -141,7 +143,6 @@ __device__ __forceinline__ void total_partials(double (&tot)[NV], const double *
         tot[q] = s;
     }
     block_sum<NV>(tot, sh);
-    if (tid == 0) *ticket = 0u;
 }
 
 }  // namespace cps

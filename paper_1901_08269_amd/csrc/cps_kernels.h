@@ -8,6 +8,7 @@ namespace cps {
 
 enum { MODE_PLAIN = 0, MODE_V = 1, MODE_T = 2, MODE_RES = 3 };
 enum { FIRST_P = 0, FIRST_S = 1 };
+enum { FIN_V = 0, FIN_T = 1, FIN_UPDATE = 2, FIN_RES = 3, FIN_RESTART = 4 };
 
 struct Launch {
     Geom g;

@@ -33,7 +33,13 @@ __global__ void k_coef(int n, const double *__restrict__ t, double *__restrict__
     if (i >= n) return;
     double *o = coef + 8 * (size_t)i;
     for (int q = 0; q < 8; ++q) o[q] = 0.0;
-    if (i == 0 || i == n - 1) return;
+    if (i == 0 || i == n - 1) {
+        // wall indices: never used by a row; nonzero diagonals keep flat pointwise
+        // kernels finite on the (zero) wall entries
+        o[3] = -1.0;
+        o[6] = -1.0;
+        return;
+    }
     double hf = t[i + 1] - t[i], hb = t[i] - t[i - 1];
     // Eq. (app_xxx): denominator (hf + hb)(hf^2 + 3 hf hb + hb^2)
     double den = hf * hf * hf + 4.0 * hf * hf * hb + 4.0 * hf * hb * hb + hb * hb * hb;

@@ -149,21 +149,31 @@ void set_stop2(cps_solver *s, double v)
     ck(hipMemcpyAsync(&s->st->stop2, s->hscalar, sizeof(double), hipMemcpyHostToDevice, s->stream));
 }
 
+Tiling make_tiling(int nx, int ny, int nz, int ty, int target_blocks, int min_tz)
+{
+    Tiling t{};
+    t.ty = ty;
+    t.tiles_x = (nx - 2 + TX - 1) / TX;
+    t.tiles_y = (ny - 2 + ty - 1) / ty;
+    int per_plane = t.tiles_x * t.tiles_y;
+    int nzi = nz - 2;
+    int want = std::max(1, (target_blocks + per_plane - 1) / per_plane);
+    t.TZ = std::max(std::min(min_tz, nzi), (nzi + want - 1) / want);
+    t.zchunks = (nzi + t.TZ - 1) / t.TZ;
+    t.ntiles = per_plane * t.zchunks;
+    t.nblk = (t.ntiles + NXCD - 1) / NXCD * NXCD;
+    return t;
+}
+
 Geom make_geom(int nx, int ny, int nz)
 {
     Geom g{};
     g.nx = nx; g.ny = ny; g.nz = nz;
     g.W = (nx + 31) / 32;
-    g.tiles_x = (nx - 2 + TX - 1) / TX;
-    g.tiles_y = (ny - 2 + TY - 1) / TY;
-    int per_plane = g.tiles_x * g.tiles_y;
-    int nzi = nz - 2;
-    int want = std::max(1, (2048 + per_plane - 1) / per_plane);
-    int TZ = std::max(std::min(8, nzi), (nzi + want - 1) / want);
-    g.TZ = TZ;
-    g.zchunks = (nzi + TZ - 1) / TZ;
-    g.ntiles = per_plane * g.zchunks;
-    g.nblk_tiles = (g.ntiles + NXCD - 1) / NXCD * NXCD;
+    g.t4 = make_tiling(nx, ny, nz, 4, 2048, 8);
+    g.t8 = make_tiling(nx, ny, nz, 8, 1024, 8);
+    size_t nn = (size_t)nx * ny * nz;
+    g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, 8192);
     return g;
 }
 
@@ -577,7 +587,8 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->skip = dalloc<uint32_t>(s, (size_t)s->g.W * ny * nz);
         launch_skipbits(s->stream, s->g, s->type, s->skip);
         // reduction scratch: enough for the largest launch
-        size_t maxblk = (size_t)s->g.nblk_tiles + (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
+        size_t maxblk = (size_t)std::max({s->g.t4.nblk, s->g.t8.nblk, s->g.nflat}) +
+                        (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
         s->partials = dalloc<double>(s, 2 * maxblk);
         s->ticket = dalloc<unsigned>(s, 1);
         launch_fill<unsigned>(s->stream, 1, s->ticket, 0u);

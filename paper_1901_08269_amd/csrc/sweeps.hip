@@ -3,9 +3,10 @@
 // sweeps of the preconditioner K, and the BiCGSTAB vector updates with their dot products
 // reduced in the same launch (Alg. 1 with the split of Eq. Bdec).
 //
-// Launch shape of every kernel here: blocks [0, nblk_tiles) are (64 x 4) tiles of the
-// interior that march over a z-chunk of TZ planes (XCD-aware tile order); blocks beyond
-// that process the irregular rows.  Kernels that reduce write one partial per block; the
+// Launch shape: the stencil kernels use 64 x 4 (Chebyshev) or 64 x 8 (B apply) column
+// tiles of the interior that march over z-chunks (XCD-aware tile order); the pointwise
+// kernels stride over all nodes with 16-byte vectors; blocks beyond those process the
+// irregular rows.  Kernels that reduce write one partial per block; the
 // last block to finish sums them in a fixed order (deterministic) and updates the
 // device-resident BiCGSTAB scalars, so the host never waits inside an iteration.
 #include "cps_device.h"
@@ -13,19 +14,45 @@
 
 namespace cps {
 
+
 // ---------------------------------------------------------------------------------------
 // B apply: v = B x (Eqs. A27 / As_qs at regular rows, A27_mod + C at irregular rows)
 // ---------------------------------------------------------------------------------------
 // Regular rows use sum factorisation of the tensor form
 //   A = R_x (x) L_y (x) L_z + L_x (x) R_y (x) L_z + L_x (x) L_y (x) R_z
-// with L = (a, 1, c) and R = (ar, br, cr) taken at the row's own index per direction:
-// per z-plane the block stages x in LDS, filters along x (L_x u, R_x u), then along y,
-// and keeps the three y-filtered planes it needs in registers while it marches in z.
+// with L = (a, 1, c) and R = (ar, br, cr) taken at the row's own index per direction.
+// A block owns a 64 x 8 column tile (two rows per thread) and marches in z: each plane of x
+// (with a one-node halo) is staged in a double-buffered LDS tile while the next plane is
+// already being fetched into registers; every thread filters its 3 x 3 neighbourhood along
+// x, then y, from LDS and keeps the two y-filtered planes it still needs in registers.
+// One barrier per plane.
 //
 // MODE_PLAIN  y = B x
 // MODE_V      v = B x;  partials (w, v), (v, v);  last block: alpha = rho / (r0, v)
 // MODE_T      t = B x;  partials (t, w), (t, t);  last block: omega = (t, s) / (t, t)
 // MODE_RES    y = b - B x; partials (y, y), (y/d, y/d); last block stores the norms
+template <typename T, typename TO, int MODE>
+__device__ __forceinline__ void emit(size_t e, T v, double bd, TO *__restrict__ y, const T *__restrict__ w,
+                                     const double *__restrict__ bvec, double (&acc)[2])
+{
+    if (MODE == MODE_RES) {
+        double r = bvec[e] - (double)v;
+        y[e] = (TO)r;
+        double rd = r / bd;
+        acc[0] += r * r;
+        acc[1] += rd * rd;
+    } else {
+        y[e] = (TO)v;
+        if (MODE == MODE_V) {
+            acc[0] += (double)w[e] * (double)v;
+            acc[1] += (double)v * (double)v;
+        } else if (MODE == MODE_T) {
+            acc[0] += (double)v * (double)w[e];
+            acc[1] += (double)v * (double)v;
+        }
+    }
+}
+
 template <typename T, typename TO, int MODE>
 __global__ void __launch_bounds__(NT) k_apply(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
                                               const T *__restrict__ x, TO *__restrict__ y, const T *__restrict__ w,
@@ -33,132 +60,160 @@ __global__ void __launch_bounds__(NT) k_apply(Geom g, Coef<T> cf, Irr<T> ir, con
                                               unsigned *ticket, int nblocks)
 {
     constexpr int NV = (MODE == MODE_PLAIN) ? 0 : 2;
+    constexpr int AY = 2 * TY;                       // tile rows (two per thread)
+    constexpr int LW = TX + 2, LH = AY + 2;          // staged plane with a one-node halo
+    constexpr int NLD = (LW * LH + NT - 1) / NT;     // staging loads per thread and plane
     if (MODE != MODE_PLAIN && MODE != MODE_RES && st->done) return;
-    __shared__ T su[TY + 2][TX + 2];
-    __shared__ T sL[TY + 2][TX];
-    __shared__ T sR[TY + 2][TX];
+    __shared__ T su[2][LH][LW];
     double acc[2] = {0.0, 0.0};
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ty * TX;
     const int nx = g.nx, ny = g.ny;
     const size_t plane = (size_t)nx * ny;
     const int b = blockIdx.x;
-    if (b < g.nblk_tiles) {
+    const Tiling &tl = g.t8;
+    if (b < tl.nblk) {
         int bx, by, bz;
-        if (tile_of_block(g, b, bx, by, bz)) {
-            const int x0 = 1 + bx * TX, y0 = 1 + by * TY;
-            const int i = x0 + tx, j = y0 + ty;
-            const int k0 = 1 + bz * g.TZ;
-            const int k1 = min(k0 + g.TZ, g.nz - 1);      // output planes [k0, k1)
-            const bool own = (i <= nx - 2) && (j <= ny - 2);
-            // x-filtered rows are shared through LDS by every row of the tile, so the x
-            // coefficients depend on i alone (and the y ones on j alone)
-            const T *cx = cf.c[0] + 8 * (i <= nx - 2 ? i : 1);
-            const T *cy = cf.c[1] + 8 * (j <= ny - 2 ? j : 1);
+        if (tile_of_block(tl, b, bx, by, bz)) {
+            const int x0 = 1 + bx * TX, y0 = 1 + by * AY;
+            const int i = x0 + tx, ja = y0 + ty, jb = ja + TY;
+            const int k0 = 1 + bz * tl.TZ;
+            const int k1 = min(k0 + tl.TZ, g.nz - 1);      // output planes [k0, k1)
+            const bool iok = i <= nx - 2, aok = iok && ja <= ny - 2, bok = iok && jb <= ny - 2;
+            // x-filtered values are computed per thread, so coefficients only need to be
+            // valid where they are used; out-of-range columns/rows read index 1
+            const T *cx = cf.c[0] + 8 * (iok ? i : 1);
+            const T *ca = cf.c[1] + 8 * (ja <= ny - 2 ? ja : 1);
+            const T *cb = cf.c[1] + 8 * (jb <= ny - 2 ? jb : 1);
             const T ax = cx[0], ccx = cx[1], arx = cx[2], brx = cx[3], crx = cx[4];
-            const T ay = cy[0], ccy = cy[1], ary = cy[2], bry = cy[3], cry = cy[4];
-            T LL0 = 0, LR0 = 0, LL1 = 0, LR1 = 0;   // y-filtered planes k-1 and k
+            const T aya = ca[0], cya = ca[1], arya = ca[2], brya = ca[3], crya = ca[4];
+            const T ayb = cb[0], cyb = cb[1], aryb = cb[2], bryb = cb[3], cryb = cb[4];
+            // staging slots of this thread
+            int soff[NLD], srow[NLD], scol[NLD];
+            bool sok[NLD], sin[NLD];
+#pragma unroll
+            for (int q = 0; q < NLD; ++q) {
+                int idx = tid + q * NT;
+                sin[q] = idx < LW * LH;
+                int r = sin[q] ? idx / LW : 0, c = sin[q] ? idx - r * LW : 0;
+                srow[q] = r;
+                scol[q] = c;
+                int gi = x0 - 1 + c, gj = y0 - 1 + r;
+                sok[q] = sin[q] && gi < nx && gj < ny;
+                soff[q] = sok[q] ? gi + nx * gj : 0;
+            }
+            T pre[NLD];
+#pragma unroll
+            for (int q = 0; q < NLD; ++q) pre[q] = sok[q] ? x[(size_t)soff[q] + (size_t)(k0 - 1) * plane] : T(0);
+            T LLa0 = 0, LRa0 = 0, LLa1 = 0, LRa1 = 0, LLb0 = 0, LRb0 = 0, LLb1 = 0, LRb1 = 0;
+            int buf = 0;
             for (int kk = k0 - 1; kk <= k1; ++kk) {
-                const T *xp = x + (size_t)kk * plane;
-                for (int q = tid; q < (TY + 2) * (TX + 2); q += NT) {
-                    int r = q / (TX + 2), c = q - r * (TX + 2);
-                    int gi = x0 - 1 + c, gj = y0 - 1 + r;
-                    su[r][c] = (gi < nx && gj < ny) ? xp[gi + (size_t)nx * gj] : T(0);
+#pragma unroll
+                for (int q = 0; q < NLD; ++q)
+                    if (sin[q]) su[buf][srow[q]][scol[q]] = pre[q];
+                if (kk + 1 <= k1) {
+#pragma unroll
+                    for (int q = 0; q < NLD; ++q)
+                        pre[q] = sok[q] ? x[(size_t)soff[q] + (size_t)(kk + 1) * plane] : T(0);
                 }
                 __syncthreads();
-                for (int r = ty; r < TY + 2; r += TY) {
-                    T um = su[r][tx], u0 = su[r][tx + 1], up = su[r][tx + 2];
-                    sL[r][tx] = ax * um + u0 + ccx * up;
-                    sR[r][tx] = arx * um + brx * u0 + crx * up;
+                // x filters of the three rows around row a (LDS rows ty..ty+2) and row b
+                T ul[6], ur[6];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    T um = su[buf][ty + r][tx], u0 = su[buf][ty + r][tx + 1], up = su[buf][ty + r][tx + 2];
+                    ul[r] = ax * um + u0 + ccx * up;
+                    ur[r] = arx * um + brx * u0 + crx * up;
+                    T vm = su[buf][ty + TY + r][tx], v0 = su[buf][ty + TY + r][tx + 1], vp = su[buf][ty + TY + r][tx + 2];
+                    ul[3 + r] = ax * vm + v0 + ccx * vp;
+                    ur[3 + r] = arx * vm + brx * v0 + crx * vp;
                 }
-                __syncthreads();
-                T l_m = sL[ty][tx], l_0 = sL[ty + 1][tx], l_p = sL[ty + 2][tx];
-                T r_m = sR[ty][tx], r_0 = sR[ty + 1][tx], r_p = sR[ty + 2][tx];
-                T LL2 = ay * l_m + l_0 + ccy * l_p;                 // L_y L_x u
-                T LR2 = (ay * r_m + r_0 + ccy * r_p)                // L_y R_x u
-                        + (ary * l_m + bry * l_0 + cry * l_p);      // + R_y L_x u
+                T LLa2 = aya * ul[0] + ul[1] + cya * ul[2];
+                T LRa2 = (aya * ur[0] + ur[1] + cya * ur[2]) + (arya * ul[0] + brya * ul[1] + crya * ul[2]);
+                T LLb2 = ayb * ul[3] + ul[4] + cyb * ul[5];
+                T LRb2 = (ayb * ur[3] + ur[4] + cyb * ur[5]) + (aryb * ul[3] + bryb * ul[4] + cryb * ul[5]);
                 if (kk >= k0 + 1) {
                     const int k = kk - 1;
                     const T *cz = cf.c[2] + 8 * k;
                     const T az = cz[0], ccz = cz[1], arz = cz[2], brz = cz[3], crz = cz[4];
-                    if (own && !skip_bit(skip, g, i, j, k)) {
-                        T v = az * LR0 + LR1 + ccz * LR2 + arz * LL0 + brz * LL1 + crz * LL2;
-                        size_t e = (size_t)i + (size_t)nx * j + (size_t)k * plane;
-                        if (MODE == MODE_RES) {
-                            double r = bvec[e] - (double)v;
-                            y[e] = (TO)r;
-                            double rd = r / (double)(brx + bry + brz);
-                            acc[0] += r * r;
-                            acc[1] += rd * rd;
-                        } else {
-                            y[e] = (TO)v;
-                            if (MODE == MODE_V) {
-                                acc[0] += (double)w[e] * (double)v;
-                                acc[1] += (double)v * (double)v;
-                            } else if (MODE == MODE_T) {
-                                acc[0] += (double)v * (double)w[e];
-                                acc[1] += (double)v * (double)v;
-                            }
-                        }
+                    if (aok && !skip_bit(skip, g, i, ja, k)) {
+                        T v = az * LRa0 + LRa1 + ccz * LRa2 + arz * LLa0 + brz * LLa1 + crz * LLa2;
+                        emit<T, TO, MODE>((size_t)i + (size_t)nx * ja + (size_t)k * plane, v,
+                                          (double)(brx + brya + brz), y, w, bvec, acc);
+                    }
+                    if (bok && !skip_bit(skip, g, i, jb, k)) {
+                        T v = az * LRb0 + LRb1 + ccz * LRb2 + arz * LLb0 + brz * LLb1 + crz * LLb2;
+                        emit<T, TO, MODE>((size_t)i + (size_t)nx * jb + (size_t)k * plane, v,
+                                          (double)(brx + bryb + brz), y, w, bvec, acc);
                     }
                 }
-                LL0 = LL1; LR0 = LR1;
-                LL1 = LL2; LR1 = LR2;
+                LLa0 = LLa1; LRa0 = LRa1; LLa1 = LLa2; LRa1 = LRa2;
+                LLb0 = LLb1; LRb0 = LRb1; LLb1 = LLb2; LRb1 = LRb2;
+                buf ^= 1;
             }
         }
     } else {
         // irregular rows: IRR_LANES lanes per row gather the full row of B
         const int rows_per_block = NT / IRR_LANES;
-        const int row = (b - g.nblk_tiles) * rows_per_block + tid / IRR_LANES;
+        const int row = (b - tl.nblk) * rows_per_block + tid / IRR_LANES;
         const int lane = tid % IRR_LANES;
-        double s = 0.0;
+        double sacc = 0.0;
         if (row < ir.n) {
             for (int e = ir.ptr[row] + lane; e < ir.ptr[row + 1]; e += IRR_LANES)
-                s += (double)ir.val[e] * (double)x[ir.col[e]];
+                sacc += (double)ir.val[e] * (double)x[ir.col[e]];
         }
-        for (int o = IRR_LANES / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, IRR_LANES);
-        if (row < ir.n && lane == 0) {
-            const int e = ir.node[row];
-            if (MODE == MODE_RES) {
-                double r = bvec[e] - s;
-                y[e] = (TO)r;
-                double rd = r / (double)ir.bdiag[row];
-                acc[0] += r * r;
-                acc[1] += rd * rd;
-            } else {
-                T v = (T)s;
-                y[e] = (TO)v;
-                if (MODE == MODE_V) {
-                    acc[0] += (double)w[e] * (double)v;
-                    acc[1] += (double)v * (double)v;
-                } else if (MODE == MODE_T) {
-                    acc[0] += (double)v * (double)w[e];
-                    acc[1] += (double)v * (double)v;
-                }
-            }
-        }
+        for (int o = IRR_LANES / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, IRR_LANES);
+        if (row < ir.n && lane == 0)
+            emit<T, TO, MODE>((size_t)ir.node[row], (T)sacc, (double)ir.bdiag[row], y, w, bvec, acc);
     }
-    if constexpr (NV > 0) {
-        if (publish_partials<2>(acc, partials, ticket, nblocks)) {
-            double tot[2];
-            total_partials<2>(tot, partials, ticket, nblocks);
-            if (tid == 0) {
-                if (MODE == MODE_V) {
-                    // alpha = (r0, r_i) / (r0, v), Alg. 1; breakdown when (r0, v) vanishes
-                    double sig = tot[0];
-                    if (!(sig == sig) || !(tot[1] == tot[1])) st->done = 3;
-                    else if (sig == 0.0 || fabs(sig) <= 1e-30 * sqrt(st->r0n2 * tot[1])) st->done = 2;
-                    else st->alpha = st->rho / sig;
-                } else if (MODE == MODE_T) {
-                    // omega = (t, s) / (t, t)
-                    double tt = tot[1];
-                    if (!(tt == tt) || !(tot[0] == tot[0])) st->done = 3;
-                    else st->omega = tt > 0.0 ? tot[0] / tt : 0.0;
-                } else if (MODE == MODE_RES) {
-                    st->res2 = tot[0];
-                    st->res2s = tot[1];
-                }
-            }
+    if constexpr (NV > 0) write_partials<2>(acc, partials);
+}
+
+// One block: fixed-order totals of a reducing kernel's partials and the scalar updates of
+// Alg. 1 that depend on them.
+//   FIN_V       alpha = rho / (r0, v)        (breakdown when (r0, v) vanishes)
+//   FIN_T       omega = (t, s) / (t, t)
+//   FIN_UPDATE  rho_new = (r0, r); convergence on ||D^-1 r||; beta = (alpha/omega)(rho_new/rho)
+//   FIN_RES     true residual norms ||r||^2, ||D^-1 r||^2
+//   FIN_RESTART rho = r0n2 = (r, r); alpha = beta = 0, omega = 1
+template <int KIND>
+__global__ void __launch_bounds__(NT) k_finalize(const double *partials, int nblocks, DevState *st)
+{
+    constexpr int NV = (KIND == FIN_RESTART) ? 1 : 2;
+    if ((KIND == FIN_V || KIND == FIN_T || KIND == FIN_UPDATE) && st->done) return;
+    double tot[NV];
+    total_partials<NV>(tot, partials, nblocks);
+    if (threadIdx.x + threadIdx.y * blockDim.x != 0) return;
+    if (KIND == FIN_V) {
+        double sig = tot[0];
+        if (!(sig == sig) || !(tot[NV - 1] == tot[NV - 1])) st->done = 3;
+        else if (sig == 0.0 || fabs(sig) <= 1e-30 * sqrt(st->r0n2 * tot[NV - 1])) st->done = 2;
+        else st->alpha = st->rho / sig;
+    } else if (KIND == FIN_T) {
+        double tt = tot[NV - 1];
+        if (!(tt == tt) || !(tot[0] == tot[0])) st->done = 3;
+        else st->omega = tt > 0.0 ? tot[0] / tt : 0.0;
+    } else if (KIND == FIN_UPDATE) {
+        double rho_new = tot[0];
+        st->iters += 1;
+        st->rn2s = tot[NV - 1];
+        if (!(rho_new == rho_new) || !(tot[NV - 1] == tot[NV - 1])) st->done = 3;
+        else if (tot[NV - 1] <= st->stop2) st->done = 1;
+        else if (st->omega == 0.0 || st->rho == 0.0) st->done = 2;
+        else {
+            st->beta = (st->alpha / st->omega) * (rho_new / st->rho);   // line 13
+            st->rho = rho_new;
         }
+    } else if (KIND == FIN_RES) {
+        st->res2 = tot[0];
+        st->res2s = tot[NV - 1];
+    } else {
+        st->rho = tot[0];
+        st->r0n2 = tot[0];
+        st->alpha = 0.0;
+        st->beta = 0.0;
+        st->omega = 1.0;
+        st->rn2s = st->res2s;
+        st->done = (tot[0] == tot[0]) ? ((st->res2s <= st->stop2) ? 1 : 0) : 3;
     }
 }
 
@@ -167,9 +222,10 @@ __global__ void __launch_bounds__(NT) k_apply(Geom g, Coef<T> cf, Irr<T> ir, con
 // ---------------------------------------------------------------------------------------
 // x_{m+1} = x_m + c1 (x_m - x_{m-1}) + c2 (rho - K x_m) / diag(K)
 // (Chebyshev acceleration of Jacobi for -K, Saad Alg. 12.1), x_{m-1} = 0 when PREV0.
-// Regular rows: K from the second-order 1D tables; the z neighbours stay in registers
-// while the column marches in z; x and y neighbours come from L1.  Irregular rows use
-// their stored Shortley-Weller row (one thread per row, same launch).
+// Regular rows: K from the second-order 1D tables.  Each thread marches its column in z
+// with the three z-neighbours in registers and every operand of the next plane already in
+// flight while the current plane is computed; x and y neighbours come through L1.
+// Irregular rows use their stored Shortley-Weller row (one thread per row, same launch).
 template <typename T, bool PREV0>
 __global__ void __launch_bounds__(NT) k_cheb(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
                                              const T *__restrict__ xc, const T *__restrict__ xm1,
@@ -181,34 +237,44 @@ __global__ void __launch_bounds__(NT) k_cheb(Geom g, Coef<T> cf, Irr<T> ir, cons
     const int nx = g.nx, ny = g.ny;
     const size_t plane = (size_t)nx * ny;
     const int b = blockIdx.x;
-    if (b < g.nblk_tiles) {
+    const Tiling &tl = g.t4;
+    if (b < tl.nblk) {
         int bx, by, bz;
-        if (!tile_of_block(g, b, bx, by, bz)) return;
+        if (!tile_of_block(tl, b, bx, by, bz)) return;
         const int i = 1 + bx * TX + tx, j = 1 + by * TY + ty;
         if (i > nx - 2 || j > ny - 2) return;
-        const int k0 = 1 + bz * g.TZ;
-        const int k1 = min(k0 + g.TZ, g.nz - 1);
+        const int k0 = 1 + bz * tl.TZ;
+        const int k1 = min(k0 + tl.TZ, g.nz - 1);
         const T *cx = cf.c[0] + 8 * i;
         const T *cy = cf.c[1] + 8 * j;
         const T kax = cx[5], kbx = cx[6], kcx = cx[7];
         const T kay = cy[5], kby = cy[6], kcy = cy[7];
         size_t e = (size_t)i + (size_t)nx * j + (size_t)k0 * plane;
-        T zm = xc[e - plane], z0 = xc[e];
+        T zm = xc[e - plane], z0 = xc[e], zp = xc[e + plane];
+        T wm = xc[e - 1], wp = xc[e + 1], sm = xc[e - nx], sp = xc[e + nx];
+        T rh = rho[e], pv = PREV0 ? T(0) : xm1[e];
         for (int k = k0; k < k1; ++k, e += plane) {
-            T zp = xc[e + plane];
-            if (!skip_bit(skip, g, i, j, k)) {
-                const T *cz = cf.c[2] + 8 * k;
-                T kd = kbx + kby + cz[6];
-                T kx = kd * z0 + kax * xc[e - 1] + kcx * xc[e + 1] + kay * xc[e - nx] + kcy * xc[e + nx] +
-                       cz[5] * zm + cz[7] * zp;
-                T prev = PREV0 ? T(0) : xm1[e];
-                xn[e] = z0 + c1 * (z0 - prev) + c2 * (rho[e] - kx) / kd;
+            T zpp = 0, wmn = 0, wpn = 0, smn = 0, spn = 0, rhn = 0, pvn = 0;
+            if (k + 1 < k1) {
+                const size_t en = e + plane;
+                zpp = xc[en + plane];
+                wmn = xc[en - 1];
+                wpn = xc[en + 1];
+                smn = xc[en - nx];
+                spn = xc[en + nx];
+                rhn = rho[en];
+                if (!PREV0) pvn = xm1[en];
             }
-            zm = z0;
-            z0 = zp;
+            const T *cz = cf.c[2] + 8 * k;
+            T kd = kbx + kby + cz[6];
+            T kx = kd * z0 + kax * wm + kcx * wp + kay * sm + kcy * sp + cz[5] * zm + cz[7] * zp;
+            T val = z0 + c1 * (z0 - pv) + c2 * (rh - kx) / kd;
+            if (!skip_bit(skip, g, i, j, k)) xn[e] = val;
+            zm = z0; z0 = zp; zp = zpp;
+            wm = wmn; wp = wpn; sm = smn; sp = spn; rh = rhn; pv = pvn;
         }
     } else {
-        const int row = (b - g.nblk_tiles) * NT + tid;
+        const int row = (b - tl.nblk) * NT + tid;
         if (row >= ir.n) return;
         const int e = ir.node[row];
         const T *k7 = ir.k7 + 7 * row;
@@ -221,39 +287,112 @@ __global__ void __launch_bounds__(NT) k_cheb(Geom g, Coef<T> cf, Irr<T> ir, cons
 }
 
 // ---------------------------------------------------------------------------------------
-// pointwise updates of Alg. 1 fused with the first Chebyshev step (x_1 = c2 rho / diag K)
+// flat, vectorised pointwise kernels: blocks [0, nflat) stride over all nodes in groups of
+// 16 bytes per thread; wall and solid entries are 0 in every vector and stay 0
 // ---------------------------------------------------------------------------------------
-// FIRST_P:  p = r + beta (p - omega v)   (line 14; p = r after a (re)start: beta = 0)
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    typedef float4 type;
+    static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+    typedef double2 type;
+    static constexpr int n = 2;
+};
+
+template <typename T>
+__device__ __forceinline__ void load16(const T *p, T (&v)[Vec16<T>::n])
+{
+    typename Vec16<T>::type q = *reinterpret_cast<const typename Vec16<T>::type *>(p);
+    const T *a = reinterpret_cast<const T *>(&q);
+#pragma unroll
+    for (int u = 0; u < Vec16<T>::n; ++u) v[u] = a[u];
+}
+
+template <typename T>
+__device__ __forceinline__ void store16(T *p, const T (&v)[Vec16<T>::n])
+{
+    typename Vec16<T>::type q;
+    T *a = reinterpret_cast<T *>(&q);
+#pragma unroll
+    for (int u = 0; u < Vec16<T>::n; ++u) a[u] = v[u];
+    *reinterpret_cast<typename Vec16<T>::type *>(p) = q;
+}
+
+// node coordinates of `base` and its successors
+struct NodeIt {
+    int i, j, k;
+    __device__ NodeIt(size_t base, int nx, int ny)
+    {
+        i = (int)(base % nx);
+        size_t r = base / nx;
+        j = (int)(r % ny);
+        k = (int)(r / ny);
+    }
+    __device__ void next(int nx, int ny)
+    {
+        if (++i == nx) {
+            i = 0;
+            if (++j == ny) { j = 0; ++k; }
+        }
+    }
+};
+
+// FIRST_P:  p = r + beta (p - omega v)   (Alg. 1 line 14; p = r after a (re)start: beta = 0)
 // FIRST_S:  s = r - alpha v              (line 7)
-// then x1 = c2 * (p or s) / diag(K) into `x1`.
+// then x1 = c2 * (p or s) / diag(K), the first Chebyshev step from x0 = 0.  Irregular rows
+// (their K diagonal is the Shortley-Weller one) are done by the trailing blocks.
 template <typename T, int KIND>
 __global__ void __launch_bounds__(NT) k_first(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
                                               const T *__restrict__ r, T *__restrict__ ps, const T *__restrict__ v,
                                               T *__restrict__ x1, T c2, const DevState *st)
 {
     if (st->done) return;
+    constexpr int VN = Vec16<T>::n;
     const T alpha = (T)st->alpha, beta = (T)st->beta, omega = (T)st->omega;
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ty * TX;
+    const int tid = threadIdx.x + threadIdx.y * TX;
     const int nx = g.nx, ny = g.ny;
-    const size_t plane = (size_t)nx * ny;
+    const size_t nn = (size_t)nx * ny * g.nz;
     const int b = blockIdx.x;
-    if (b < g.nblk_tiles) {
-        int bx, by, bz;
-        if (!tile_of_block(g, b, bx, by, bz)) return;
-        const int i = 1 + bx * TX + tx, j = 1 + by * TY + ty;
-        if (i > nx - 2 || j > ny - 2) return;
-        const int k0 = 1 + bz * g.TZ;
-        const int k1 = min(k0 + g.TZ, g.nz - 1);
-        const T kbxy = cf.c[0][8 * i + 6] + cf.c[1][8 * j + 6];
-        size_t e = (size_t)i + (size_t)nx * j + (size_t)k0 * plane;
-        for (int k = k0; k < k1; ++k, e += plane) {
-            if (skip_bit(skip, g, i, j, k)) continue;
-            T val = (KIND == FIRST_P) ? r[e] + beta * (ps[e] - omega * v[e]) : r[e] - alpha * v[e];
-            ps[e] = val;
-            x1[e] = c2 * val / (kbxy + cf.c[2][8 * k + 6]);
+    if (b < g.nflat) {
+        const size_t ngroups = nn / VN;
+        for (size_t q = (size_t)b * NT + tid; q < ngroups; q += (size_t)g.nflat * NT) {
+            const size_t base = q * VN;
+            T rv[VN], pv[VN], vv[VN], out[VN], xo[VN];
+            load16(r + base, rv);
+            load16(v + base, vv);
+            if (KIND == FIRST_P) load16(ps + base, pv);
+            NodeIt it(base, nx, ny);
+            bool any_skip = false;
+#pragma unroll
+            for (int u = 0; u < VN; ++u) {
+                out[u] = (KIND == FIRST_P) ? rv[u] + beta * (pv[u] - omega * vv[u]) : rv[u] - alpha * vv[u];
+                T kd = cf.c[0][8 * it.i + 6] + cf.c[1][8 * it.j + 6] + cf.c[2][8 * it.k + 6];
+                xo[u] = c2 * out[u] / kd;
+                any_skip |= skip_bit(skip, g, it.i, it.j, it.k);
+                it.next(nx, ny);
+            }
+            if (!any_skip) {
+                store16(ps + base, out);
+                store16(x1 + base, xo);
+            } else {
+                NodeIt it2(base, nx, ny);
+#pragma unroll
+                for (int u = 0; u < VN; ++u) {
+                    if (!skip_bit(skip, g, it2.i, it2.j, it2.k)) {
+                        ps[base + u] = out[u];
+                        x1[base + u] = xo[u];
+                    }
+                    it2.next(nx, ny);
+                }
+            }
         }
+        // tail nodes (nn not a multiple of VN) are wall nodes: nothing to do
     } else {
-        const int row = (b - g.nblk_tiles) * NT + tid;
+        const int row = (b - g.nflat) * NT + tid;
         if (row >= ir.n) return;
         const int e = ir.node[row];
         T val = (KIND == FIRST_P) ? r[e] + beta * (ps[e] - omega * v[e]) : r[e] - alpha * v[e];
@@ -262,133 +401,89 @@ __global__ void __launch_bounds__(NT) k_first(Geom g, Coef<T> cf, Irr<T> ir, con
     }
 }
 
-// ---------------------------------------------------------------------------------------
-// lines 11-13 of Alg. 1: x += alpha p^ + omega s^, r = s - omega t, (r0, r), ||D^-1 r||^2
-// ---------------------------------------------------------------------------------------
-template <typename T, typename TX_>
+// Alg. 1 lines 11-13: x += alpha p^ + omega s^, r = s - omega t, partials of (r0, r) and of
+// ||D^-1 r||^2 (D = diag B; regular rows here, irregular rows by the trailing blocks);
+// the last block forms beta and tests convergence.
+template <typename T>
 __global__ void __launch_bounds__(NT) k_update(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
-                                               TX_ *__restrict__ xs, const T *__restrict__ ph,
-                                               const T *__restrict__ sh, const T *__restrict__ s,
-                                               const T *__restrict__ t, const T *__restrict__ r0, T *__restrict__ r,
-                                               DevState *st, double *partials, unsigned *ticket, int nblocks)
+                                               T *__restrict__ xs, const T *__restrict__ ph, const T *__restrict__ sh,
+                                               const T *__restrict__ s, const T *__restrict__ t,
+                                               const T *__restrict__ r0, T *__restrict__ r, DevState *st,
+                                               double *partials, unsigned *ticket, int nblocks)
 {
     if (st->done) return;
+    constexpr int VN = Vec16<T>::n;
     const double alpha = st->alpha, omega = st->omega;
     const T alphaT = (T)alpha, omegaT = (T)omega;
     double acc[2] = {0.0, 0.0};
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ty * TX;
+    const int tid = threadIdx.x + threadIdx.y * TX;
     const int nx = g.nx, ny = g.ny;
-    const size_t plane = (size_t)nx * ny;
+    const size_t nn = (size_t)nx * ny * g.nz;
     const int b = blockIdx.x;
-    if (b < g.nblk_tiles) {
-        int bx, by, bz;
-        if (tile_of_block(g, b, bx, by, bz)) {
-            const int i = 1 + bx * TX + tx, j = 1 + by * TY + ty;
-            if (i <= nx - 2 && j <= ny - 2) {
-                const int k0 = 1 + bz * g.TZ;
-                const int k1 = min(k0 + g.TZ, g.nz - 1);
-                const T bxy = cf.c[0][8 * i + 3] + cf.c[1][8 * j + 3];
-                size_t e = (size_t)i + (size_t)nx * j + (size_t)k0 * plane;
-                for (int k = k0; k < k1; ++k, e += plane) {
-                    if (skip_bit(skip, g, i, j, k)) continue;
-                    xs[e] = (TX_)((double)xs[e] + (double)(alphaT * ph[e] + omegaT * sh[e]));
-                    T rv = s[e] - omegaT * t[e];
-                    r[e] = rv;
-                    double rd = (double)rv / (double)(bxy + cf.c[2][8 * k + 3]);
-                    acc[0] += (double)r0[e] * (double)rv;
+    if (b < g.nflat) {
+        const size_t ngroups = nn / VN;
+        for (size_t q = (size_t)b * NT + tid; q < ngroups; q += (size_t)g.nflat * NT) {
+            const size_t base = q * VN;
+            T xv[VN], pv[VN], shv[VN], sv[VN], tv[VN], r0v[VN], rv[VN];
+            load16(xs + base, xv);
+            load16(ph + base, pv);
+            load16(sh + base, shv);
+            load16(s + base, sv);
+            load16(t + base, tv);
+            load16(r0 + base, r0v);
+            NodeIt it(base, nx, ny);
+#pragma unroll
+            for (int u = 0; u < VN; ++u) {
+                xv[u] = xv[u] + (alphaT * pv[u] + omegaT * shv[u]);
+                rv[u] = sv[u] - omegaT * tv[u];
+                acc[0] += (double)r0v[u] * (double)rv[u];
+                if (!skip_bit(skip, g, it.i, it.j, it.k)) {
+                    double d = (double)cf.c[0][8 * it.i + 3] + (double)cf.c[1][8 * it.j + 3] + (double)cf.c[2][8 * it.k + 3];
+                    double rd = (double)rv[u] / d;
                     acc[1] += rd * rd;
                 }
+                it.next(nx, ny);
             }
+            store16(xs + base, xv);
+            store16(r + base, rv);
         }
     } else {
-        const int row = (b - g.nblk_tiles) * NT + tid;
+        const int row = (b - g.nflat) * NT + tid;
         if (row < ir.n) {
             const int e = ir.node[row];
-            xs[e] = (TX_)((double)xs[e] + (double)(alphaT * ph[e] + omegaT * sh[e]));
             T rv = s[e] - omegaT * t[e];
-            r[e] = rv;
             double rd = (double)rv / (double)ir.bdiag[row];
-            acc[0] += (double)r0[e] * (double)rv;
             acc[1] += rd * rd;
         }
     }
-    if (publish_partials<2>(acc, partials, ticket, nblocks)) {
-        double tot[2];
-        total_partials<2>(tot, partials, ticket, nblocks);
-        if (tid == 0) {
-            double rho_new = tot[0];
-            st->iters += 1;
-            st->rn2s = tot[1];
-            if (!(rho_new == rho_new) || !(tot[1] == tot[1])) {
-                st->done = 3;
-            } else if (tot[1] <= st->stop2) {
-                st->done = 1;
-            } else if (omega == 0.0 || st->rho == 0.0) {
-                st->done = 2;
-            } else {
-                st->beta = (alpha / omega) * (rho_new / st->rho);   // line 13
-                st->rho = rho_new;
-            }
-        }
-    }
+    write_partials<2>(acc, partials);
 }
 
-// ---------------------------------------------------------------------------------------
-// (re)start: r0 = r, p = v = 0, rho = (r, r), recursive norm from the true residual norms
-// ---------------------------------------------------------------------------------------
+// (re)start: r0 = r, p = v = 0, rho = (r, r); the recursive norm starts from the true one
 template <typename T>
-__global__ void __launch_bounds__(NT) k_restart(Geom g, Irr<T> ir, const uint32_t *__restrict__ skip,
-                                                const T *__restrict__ r, T *__restrict__ r0, T *__restrict__ p,
+__global__ void __launch_bounds__(NT) k_restart(Geom g, const T *__restrict__ r, T *__restrict__ r0, T *__restrict__ p,
                                                 T *__restrict__ v, DevState *st, double *partials, unsigned *ticket,
                                                 int nblocks)
 {
+    constexpr int VN = Vec16<T>::n;
     double acc[1] = {0.0};
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ty * TX;
-    const int nx = g.nx, ny = g.ny;
-    const size_t plane = (size_t)nx * ny;
-    const int b = blockIdx.x;
-    if (b < g.nblk_tiles) {
-        int bx, by, bz;
-        if (tile_of_block(g, b, bx, by, bz)) {
-            const int i = 1 + bx * TX + tx, j = 1 + by * TY + ty;
-            if (i <= nx - 2 && j <= ny - 2) {
-                const int k0 = 1 + bz * g.TZ;
-                const int k1 = min(k0 + g.TZ, g.nz - 1);
-                size_t e = (size_t)i + (size_t)nx * j + (size_t)k0 * plane;
-                for (int k = k0; k < k1; ++k, e += plane) {
-                    if (skip_bit(skip, g, i, j, k)) continue;
-                    T rv = r[e];
-                    r0[e] = rv;
-                    p[e] = T(0);
-                    v[e] = T(0);
-                    acc[0] += (double)rv * (double)rv;
-                }
-            }
+    const int tid = threadIdx.x + threadIdx.y * TX;
+    const size_t nn = (size_t)g.nx * g.ny * g.nz;
+    const size_t ngroups = nn / VN;
+    for (size_t q = (size_t)blockIdx.x * NT + tid; q < ngroups; q += (size_t)gridDim.x * NT) {
+        const size_t base = q * VN;
+        T rv[VN], z[VN];
+        load16(r + base, rv);
+#pragma unroll
+        for (int u = 0; u < VN; ++u) {
+            z[u] = T(0);
+            acc[0] += (double)rv[u] * (double)rv[u];
         }
-    } else {
-        const int row = (b - g.nblk_tiles) * NT + tid;
-        if (row < ir.n) {
-            const int e = ir.node[row];
-            T rv = r[e];
-            r0[e] = rv;
-            p[e] = T(0);
-            v[e] = T(0);
-            acc[0] += (double)rv * (double)rv;
-        }
+        store16(r0 + base, rv);
+        store16(p + base, z);
+        store16(v + base, z);
     }
-    if (publish_partials<1>(acc, partials, ticket, nblocks)) {
-        double tot[1];
-        total_partials<1>(tot, partials, ticket, nblocks);
-        if (tid == 0) {
-            st->rho = tot[0];
-            st->r0n2 = tot[0];
-            st->alpha = 0.0;
-            st->beta = 0.0;
-            st->omega = 1.0;
-            st->rn2s = st->res2s;
-            st->done = (tot[0] == tot[0]) ? ((st->res2s <= st->stop2) ? 1 : 0) : 3;
-        }
-    }
+    write_partials<1>(acc, partials);
 }
 
 // u64 += d32 (refinement step) on unknown rows; d is exactly 0 elsewhere
@@ -442,12 +537,20 @@ __global__ void k_check_finite(size_t n, const int8_t *__restrict__ type, const 
 // ---------------------------------------------------------------------------------------
 static inline dim3 tile_block() { return dim3(TX, TY, 1); }
 
+static inline int rows_blocks(int n) { return (n + NT - 1) / NT; }
+
+template <int KIND>
+static void finalize(const Launch &L, int nb, DevState *st)
+{
+    k_finalize<KIND><<<1, tile_block(), 0, L.stream>>>(L.partials, nb, st);
+}
+
 template <typename T, typename TO>
 void launch_apply(int mode, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, TO *y, const T *w,
                   const double *bvec, DevState *st)
 {
     int irr_blocks = (ir.n + (NT / IRR_LANES) - 1) / (NT / IRR_LANES);
-    int nb = L.g.nblk_tiles + irr_blocks;
+    int nb = L.g.t8.nblk + irr_blocks;
     dim3 grid(nb), blk = tile_block();
     switch (mode) {
     case MODE_PLAIN:
@@ -455,23 +558,24 @@ void launch_apply(int mode, const Launch &L, const Coef<T> &cf, const Irr<T> &ir
         break;
     case MODE_V:
         k_apply<T, TO, MODE_V><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, y, w, bvec, st, L.partials, L.ticket, nb);
+        finalize<FIN_V>(L, nb, st);
         break;
     case MODE_T:
         k_apply<T, TO, MODE_T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, y, w, bvec, st, L.partials, L.ticket, nb);
+        finalize<FIN_T>(L, nb, st);
         break;
     case MODE_RES:
         k_apply<T, TO, MODE_RES><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, y, w, bvec, st, L.partials, L.ticket, nb);
+        finalize<FIN_RES>(L, nb, st);
         break;
     }
 }
-
-static inline int rows_blocks(int n) { return (n + NT - 1) / NT; }
 
 template <typename T>
 void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
                  double c1, double c2, const DevState *st)
 {
-    dim3 grid(L.g.nblk_tiles + rows_blocks(ir.n)), blk = tile_block();
+    dim3 grid(L.g.t4.nblk + rows_blocks(ir.n)), blk = tile_block();
     if (xm1 == nullptr)
         k_cheb<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st);
     else
@@ -482,7 +586,7 @@ template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st)
 {
-    dim3 grid(L.g.nblk_tiles + rows_blocks(ir.n)), blk = tile_block();
+    dim3 grid(L.g.nflat + rows_blocks(ir.n)), blk = tile_block();
     if (kind == FIRST_P)
         k_first<T, FIRST_P><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, r, ps, v, x1, (T)c2, st);
     else
@@ -493,16 +597,19 @@ template <typename T, typename TX_>
 void launch_update(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, TX_ *xs, const T *ph, const T *sh, const T *s,
                    const T *t, const T *r0, T *r, DevState *st)
 {
-    int nb = L.g.nblk_tiles + rows_blocks(ir.n);
-    k_update<T, TX_><<<dim3(nb), tile_block(), 0, L.stream>>>(L.g, cf, ir, L.skip, xs, ph, sh, s, t, r0, r, st,
-                                                              L.partials, L.ticket, nb);
+    static_assert(sizeof(T) == sizeof(TX_), "solution and Krylov vectors share a precision");
+    int nb = L.g.nflat + rows_blocks(ir.n);
+    k_update<T><<<dim3(nb), tile_block(), 0, L.stream>>>(L.g, cf, ir, L.skip, (T *)xs, ph, sh, s, t, r0, r, st,
+                                                         L.partials, L.ticket, nb);
+    finalize<FIN_UPDATE>(L, nb, st);
 }
 
 template <typename T>
 void launch_restart(const Launch &L, const Irr<T> &ir, const T *r, T *r0, T *p, T *v, DevState *st)
 {
-    int nb = L.g.nblk_tiles + rows_blocks(ir.n);
-    k_restart<T><<<dim3(nb), tile_block(), 0, L.stream>>>(L.g, ir, L.skip, r, r0, p, v, st, L.partials, L.ticket, nb);
+    int nb = L.g.nflat;
+    k_restart<T><<<dim3(nb), tile_block(), 0, L.stream>>>(L.g, r, r0, p, v, st, L.partials, L.ticket, nb);
+    finalize<FIN_RESTART>(L, nb, st);
 }
 
 static inline dim3 flat_grid(size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) / 256, 65536)); }

@@ -154,34 +154,79 @@ class Model:
 # ----------------------------------------------------------------------------------------
 # problem families (seeded; the bench problem's seeds are never used for training)
 # ----------------------------------------------------------------------------------------
+def _torch_mesh(x):
+    import torch
+    t = torch.as_tensor(x, dtype=torch.float64, device="cuda")
+    return t.view(-1, 1, 1), t.view(1, -1, 1), t.view(1, 1, -1)   # Z, Y, X (same 1D grid)
+
+
 def smooth_family(seed, x, terms=4):
     """u = sum_t c_t sin(pi k1 x + a) cos(pi k2 y + b) exp(gamma z), k <= 2, gamma in [-1, 1];
-    f = Laplacian(u) = sum_t (gamma^2 - pi^2 (k1^2 + k2^2)) u_t; g = u."""
+    f = Laplacian(u) = sum_t (gamma^2 - pi^2 (k1^2 + k2^2)) u_t; g = u.  Evaluated on the GPU."""
+    import torch
     rng = np.random.Generator(np.random.PCG64(seed))
-    Z, Y, X = W.mesh(x, x, x)
-    u = np.zeros((len(x),) * 3)
-    f = np.zeros_like(u)
+    Z, Y, X = _torch_mesh(x)
+    n = len(x)
+    u = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    f = torch.zeros_like(u)
     for _ in range(terms):
         k1, k2 = rng.integers(1, 3, size=2)
         a, b = rng.uniform(0, 2 * math.pi, 2)
         gam = rng.uniform(-1, 1)
         c = rng.standard_normal()
-        ut = c * np.sin(math.pi * k1 * X + a) * np.cos(math.pi * k2 * Y + b) * np.exp(gam * Z)
+        ut = c * torch.sin(math.pi * int(k1) * X + a) * torch.cos(math.pi * int(k2) * Y + b) * torch.exp(gam * Z)
         u += ut
         f += (gam * gam - math.pi ** 2 * (k1 * k1 + k2 * k2)) * ut
     return u, f
 
 
+def spheres_level(bodies, x):
+    """Union (min) of sphere level sets on the GPU."""
+    import torch
+    Z, Y, X = _torch_mesh(x)
+    n = len(x)
+    phi = torch.full((n, n, n), float("inf"), dtype=torch.float64, device="cuda")
+    for b in bodies:
+        d = torch.sqrt((X - b.c[0]) ** 2 + (Y - b.c[1]) ** 2 + (Z - b.c[2]) ** 2) - b.r
+        phi = torch.minimum(phi, d)
+    return phi
+
+
+def fourier_gpu(seed, K, x):
+    """The seeded random Fourier source of workloads.fourier_field, evaluated on the GPU."""
+    import torch
+    ks, amp, ph = W.fourier_modes(seed, K)
+    t = torch.as_tensor(x, dtype=torch.float64, device="cuda")
+    ks_t = torch.as_tensor(ks, device="cuda")
+    ph_t = torch.as_tensor(ph, device="cuda")
+    A = torch.as_tensor(amp, device="cuda")
+    Xm = torch.cos(math.pi * ks_t[:, 0:1] * t[None, :] + ph_t[:, 0:1])
+    Ym = torch.cos(math.pi * ks_t[:, 1:2] * t[None, :] + ph_t[:, 1:2])
+    Zm = torch.cos(math.pi * ks_t[:, 2:3] * t[None, :] + ph_t[:, 2:3]) * A[:, None]
+    n = len(x)
+    out = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+    for k in range(n):
+        out[k] = (Ym * Zm[:, k:k + 1]).T @ Xm
+    return out
+
+
+_STAR_PHI = {}
+
+
 def make_problem(family, N, seed):
-    """(x, y, z, phi, g, f) of one training/test instance."""
+    """(x, y, z, phi, g, f) of one training/test instance; phi, g, f are GPU tensors."""
+    import torch
     if family == "star":
-        w = W.star_fourier(N, seed=seed)
-        return w.x, w.y, w.z, w.phi, w.g, w.f
+        x = W.tanh_grid(N + 2, 2.0)
+        if N not in _STAR_PHI:
+            _STAR_PHI[N] = torch.as_tensor(W.union_level([W.Star()], x, x, x), device="cuda")
+        f = fourier_gpu(seed, 8, x)
+        return x, x, x, _STAR_PHI[N], torch.zeros_like(f), f
     if family == "spheres8":
         x = W.tanh_grid(N + 2, 1.5)
         hc = float(np.max(np.diff(x)))
         bodies = W.sample_bodies(seed, 8, 0, (0.06, 0.14), None, gap=6 * hc)
-        phi = W.union_level(bodies, x, x, x)
+        phi = spheres_level(bodies, x)
         u, f = smooth_family(seed + 7919, x)
         return x, x, x, phi, u, f
     raise KeyError(family)
