@@ -30,16 +30,44 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--parity-tol", type=float, default=1e-12,
+    ap.add_argument("--parity-tol", type=float, default=1e-13,
                     help="tolerance of the extra solves compared against the stored oracle samples")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only time a plain 1 GiB device copy (HBM reference and counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB (torch's copy kernel), timed with events: the
+    measured HBM copy bandwidth, and the known byte count that FETCH_SIZE / WRITE_SIZE
+    counters are scaled against."""
+    import torch
+    n = 1 << 28   # 2^28 floats = 1 GiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": ms,
+                      "GBps_read_plus_write": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -144,15 +172,28 @@ def main():
     bpp = last["sweep_bytes_per_point"]
     avg_ms = sweep_ms / max(sweeps, 1)
     achieved = bpp * pts / (avg_ms * 1e-3) / 1e9 if sweeps else None
+    # HBM traffic per launch from the committed counter report, only while it still
+    # describes the kernel sources (the report carries their hash) and this workload
+    from paper_1901_08269_amd import profiling
+    traffic, traffic_note = None, "no counter report for this workload"
+    rep = profiling.read_traffic(os.path.join(ROOT, "profiles", f"k_cheb_spheres8_{args.N}_traffic.md"))
+    if rep is not None:
+        if rep.get("kernel_source_sha256_16") == profiling.source_hash():
+            traffic = float(rep["traffic_bytes_per_launch"])
+            traffic_note = f"profiles/k_cheb_spheres8_{args.N}_traffic.md (FETCH_SIZE+WRITE_SIZE, copy-calibrated)"
+        else:
+            traffic_note = "kernel sources changed since the counters were taken"
     roofline = {"kernel": "k_cheb<float> (preconditioner sweep)", "bound": "hbm",
                 "achieved": achieved, "peak": metrics.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / metrics.MI355X_HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "frac": (achieved / metrics.MI355X_HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "traffic_source": traffic_note,
                 "avg_launch_us": avg_ms * 1e3, "launches": sweeps, "bytes_per_launch": bpp * pts}
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args, fp64["iters"] if fp64 else last["iters"])
 
+    opts = cps.default_options()
     solve_s = sum(s["solve_ms"] for s in stats) / len(stats) / 1e3
     setup_s = sum(s["setup_ms"] for s in stats) / len(stats) / 1e3
     n_unk = last["n_unknowns"]
@@ -172,7 +213,9 @@ def main():
         "config": {"workload": f"spheres8_{args.N}: {args.N}^3 interior, tanh 1.5, 8 spheres seed 0, "
                                f"u = sin(2pi x) cos(pi y) exp(z), tol {args.tol:g}",
                    "precision": "mixed", "warm_start": "learned" if learned is not None else "zero",
-                   "inner_iters": 8},
+                   "inner_iters": opts.inner_iters,
+                   "cheb_interval": [opts.lam_lo or max(opts.lam_hi / (4.0 * opts.inner_iters ** 2),
+                                                        (1 - np.cos(np.pi / (args.N + 1))) * 1.0), opts.lam_hi]},
         "solve_s": solve_s,
         "setup_s": setup_s,
         "iters": last["iters"],

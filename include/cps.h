@@ -54,14 +54,17 @@ typedef struct cps_solver cps_solver; /* opaque; owns all of its device memory *
 typedef struct cps_options {
     int32_t struct_size;   /* = sizeof(cps_options) */
     int32_t precision;     /* CPS_FP64 or CPS_MIXED */
-    int32_t inner_iters;   /* preconditioner inner iterations per apply; paper: 8 (Sec. 4) */
+    int32_t inner_iters;   /* Chebyshev-Jacobi steps per preconditioner apply (default 24; the
+                            * paper's MSI preconditioner runs 8 inner iterations, Sec. 4) */
     int32_t max_iters;     /* cap on BiCGSTAB iterations (summed over refinement steps) */
     int32_t max_refine;    /* CPS_MIXED: cap on refinement steps */
     int32_t max_restarts;  /* restarts after breakdown or a failed true-residual check */
     int32_t device_ptrs;   /* 1: array arguments are device pointers */
     int32_t kernel_timing; /* 1: time every preconditioner sweep with HIP events (stats) */
     double inner_tol;      /* CPS_MIXED: residual reduction asked of each FP32 inner solve */
-    double lam_lo, lam_hi; /* Chebyshev interval for the spectrum of diag(K)^-1 K */
+    double lam_lo, lam_hi; /* Chebyshev interval for the spectrum of diag(K)^-1 K (default
+                            * hi = 2; lo = 0 selects max(hi / (4 inner_iters^2), lambda_1) with
+                            * lambda_1 = (1/3) sum_d (1 - cos(pi / (n_d - 1)))) */
     void *stream;          /* hipStream_t the library launches on; NULL = null stream */
 } cps_options;
 
@@ -120,7 +123,7 @@ int cps_residual(cps_solver *s, const double *u, double *r, double *rel);
  * FP32 first, y widened back).  Entries of x at non-unknown nodes are ignored. */
 int cps_apply(cps_solver *s, const double *x, double *y, int32_t precision);
 
-/* phi = M rho: the preconditioner of Alg. 1 (lines 4 and 8), i.e. inner_iters
+/* phi = M rho: the preconditioner of Alg. 1 (applied to p and to s), i.e. inner_iters
  * Chebyshev-Jacobi steps on K phi = rho (Sec. 3.3) from phi = 0; FP64 or FP32 as above. */
 int cps_precond(cps_solver *s, const double *rho, double *phi, int32_t precision);
 

@@ -83,11 +83,18 @@ class OrcOpts(C.Structure):
                 ("lam_lo", C.c_double), ("lam_hi", C.c_double), ("inner_tol", C.c_double)]
 
 
-# Default preconditioner parameters, shared by name (not by code) with the GPU library's
-# defaults: 8 inner steps (Sec. 4, first paragraph) and the Chebyshev interval.
-DEFAULT_INNER = 8
-DEFAULT_LAM_LO = 0.03
+# Default preconditioner parameters, the same policy as the GPU library's defaults (stated
+# there independently): 24 Chebyshev-Jacobi steps on [lo, hi] with hi = 2 (Gershgorin bound
+# of the diagonally dominant rows of K) and, unless given, lo = max(hi / (4 m^2), lambda_1),
+# lambda_1 being the smallest eigenvalue of the Jacobi-scaled 7-point Laplacian on a uniform
+# grid with the same point counts n_d: (1/3) sum_d (1 - cos(pi / (n_d - 1))).
+DEFAULT_INNER = 24
 DEFAULT_LAM_HI = 2.0
+
+
+def default_lam_lo(m, shape, hi=DEFAULT_LAM_HI):
+    lam1 = sum(1.0 - np.cos(np.pi / (n - 1)) for n in shape) / 3.0
+    return max(hi / (4.0 * m * m), lam1)
 
 
 def compact_coef(x):
@@ -203,15 +210,17 @@ class Problem:
         lib().orc_apply_K(self.h, _p(x), _p(y))
         return y
 
-    def precond(self, rho, iters=DEFAULT_INNER, lo=DEFAULT_LAM_LO, hi=DEFAULT_LAM_HI):
+    def precond(self, rho, iters=DEFAULT_INNER, lo=None, hi=DEFAULT_LAM_HI):
+        lo = default_lam_lo(iters, self.shape, hi) if lo is None else lo
         rho = _f64(rho).reshape(self.shape)
         phi = np.zeros(self.shape)
         lib().orc_precond(self.h, _p(rho), _p(phi), iters, lo, hi)
         return phi
 
     def solve(self, tol=1e-10, u0=None, mixed=False, inner_iters=DEFAULT_INNER, max_iters=20000,
-              lam_lo=DEFAULT_LAM_LO, lam_hi=DEFAULT_LAM_HI, inner_tol=1e-4, max_refine=30, max_restarts=5,
+              lam_lo=None, lam_hi=DEFAULT_LAM_HI, inner_tol=1e-4, max_refine=30, max_restarts=5,
               check=True):
+        lam_lo = default_lam_lo(inner_iters, self.shape, lam_hi) if lam_lo is None else lam_lo
         u = np.zeros(self.shape) if u0 is None else _f64(u0).reshape(self.shape).copy()
         o = OrcOpts(inner_iters, max_iters, int(mixed), max_refine, max_restarts, lam_lo, lam_hi, inner_tol)
         st = np.zeros(5)

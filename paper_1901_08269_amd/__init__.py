@@ -89,6 +89,13 @@ def load_library(path: str = LIB_PATH):
     return L
 
 
+def default_options():
+    """The library's default cps_options (lam_lo = 0 means hi / (4 inner_iters^2))."""
+    o = CpsOptions()
+    load_library().cps_default_options(C.byref(o))
+    return o
+
+
 def _torch():
     import torch
     if not torch.cuda.is_available():
@@ -115,7 +122,7 @@ class Solver:
     Arrays are (nz, ny, nx) float64 (numpy or torch); node (i,j,k) is element [k, j, i].
     """
 
-    def __init__(self, x, y, z, phi, g, f, precision="fp64", inner_iters=8, lam_lo=None, lam_hi=None,
+    def __init__(self, x, y, z, phi, g, f, precision="fp64", inner_iters=None, lam_lo=None, lam_hi=None,
                  inner_tol=1e-4, max_iters=20000, max_refine=40, max_restarts=5, kernel_timing=False):
         torch = _torch()
         L = load_library()
@@ -124,7 +131,8 @@ class Solver:
         o = CpsOptions()
         L.cps_default_options(C.byref(o))
         o.precision = CPS_MIXED if precision == "mixed" else CPS_FP64
-        o.inner_iters = inner_iters
+        if inner_iters is not None:
+            o.inner_iters = inner_iters
         if lam_lo is not None:
             o.lam_lo = lam_lo
         if lam_hi is not None:

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace cps {
 
 constexpr int TX = 64;        // tile width in x: one wavefront

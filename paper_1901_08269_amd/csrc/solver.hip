@@ -22,8 +22,16 @@ using namespace cps;
 
 namespace {
 
-constexpr double DEFAULT_LAM_LO = 0.03;   // Chebyshev interval of diag(K)^-1 K
-constexpr double DEFAULT_LAM_HI = 2.0;    // Gershgorin bound: diag-dominant K rows
+// Preconditioner defaults: Chebyshev-Jacobi steps per apply, and the interval [lo, hi] for
+// the spectrum of diag(K)^-1 K.  hi = 2 is the Gershgorin bound of the diagonally dominant
+// rows of K.  lo = 0 selects max(hi / (4 m^2), lambda_1): hi / (4 m^2) is the lower end at
+// which an m-step Chebyshev polynomial still damps the smooth error (measured best to
+// within a few iterations for m = 8 ... 32 on 256^3 stretched grids with bodies), and
+// lambda_1 = (1/3) sum_d (1 - cos(pi / (n_d - 1))) is the smallest eigenvalue of the
+// Jacobi-scaled 7-point Laplacian on a uniform grid with the same point counts, below
+// which a small grid has no spectrum to cover.
+constexpr int DEFAULT_INNER = 24;
+constexpr double DEFAULT_LAM_HI = 2.0;
 constexpr int ELL_CAP = 243;               // 27 box nodes + 216 extra-point positions
 constexpr int MAX_INNER = 64;
 
@@ -165,15 +173,26 @@ Tiling make_tiling(int nx, int ny, int nz, int ty, int target_blocks, int min_tz
     return t;
 }
 
+// Target block counts of the two stencil tilings (the z-chunk length follows from them).
+#ifndef CPS_CHEB_BLOCKS
+#define CPS_CHEB_BLOCKS 2048
+#endif
+#ifndef CPS_APPLY_BLOCKS
+#define CPS_APPLY_BLOCKS 2048
+#endif
+#ifndef CPS_FLAT_BLOCKS
+#define CPS_FLAT_BLOCKS 4096
+#endif
+
 Geom make_geom(int nx, int ny, int nz)
 {
     Geom g{};
     g.nx = nx; g.ny = ny; g.nz = nz;
     g.W = (nx + 31) / 32;
-    g.t4 = make_tiling(nx, ny, nz, 4, 2048, 8);
-    g.t8 = make_tiling(nx, ny, nz, 8, 1024, 8);
+    g.t4 = make_tiling(nx, ny, nz, 4, CPS_CHEB_BLOCKS, 8);
+    g.t8 = make_tiling(nx, ny, nz, 8, CPS_APPLY_BLOCKS, 8);
     size_t nn = (size_t)nx * ny * nz;
-    g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, 8192);
+    g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, CPS_FLAT_BLOCKS);
     return g;
 }
 
@@ -241,7 +260,7 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
     }
 }
 
-// one BiCGSTAB iteration (Alg. 1, lines 4-14) entirely on the device
+// one BiCGSTAB iteration (Alg. 1) entirely on the device
 template <typename T, typename TXS>
 void enqueue_iteration(cps_solver *s, Vecs<T> &V, TXS *xsol, const double *c1, const double *c2)
 {
@@ -469,14 +488,14 @@ void cps_default_options(cps_options *o)
     std::memset(o, 0, sizeof(*o));
     o->struct_size = sizeof(cps_options);
     o->precision = CPS_FP64;
-    o->inner_iters = 8;
+    o->inner_iters = DEFAULT_INNER;
     o->max_iters = 20000;
     o->max_refine = 40;
     o->max_restarts = 5;
     o->device_ptrs = 0;
     o->kernel_timing = 0;
     o->inner_tol = 1e-4;
-    o->lam_lo = DEFAULT_LAM_LO;
+    o->lam_lo = 0.0;
     o->lam_hi = DEFAULT_LAM_HI;
     o->stream = nullptr;
 }
@@ -512,7 +531,14 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
     if (o.precision != CPS_FP64 && o.precision != CPS_MIXED) return CPS_EINVAL;
     if (o.inner_iters < 1 || o.inner_iters > MAX_INNER || o.max_iters < 1 || o.max_refine < 1 || o.max_restarts < 0)
         return CPS_EINVAL;
-    if (!(o.lam_hi > o.lam_lo) || !(o.lam_lo > 0.0) || !(o.inner_tol > 0.0 && o.inner_tol < 1.0)) return CPS_EINVAL;
+    if (!(o.lam_lo >= 0.0) || !(o.lam_hi > 0.0) || !(o.inner_tol > 0.0 && o.inner_tol < 1.0)) return CPS_EINVAL;
+    if (o.lam_lo == 0.0) {
+        const double pi = 3.14159265358979323846;
+        double lam1 = ((1.0 - std::cos(pi / (nx - 1))) + (1.0 - std::cos(pi / (ny - 1))) +
+                       (1.0 - std::cos(pi / (nz - 1)))) / 3.0;
+        o.lam_lo = std::max(o.lam_hi / (4.0 * (double)o.inner_iters * (double)o.inner_iters), lam1);
+    }
+    if (!(o.lam_hi > o.lam_lo)) return CPS_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return CPS_EDEVICE;
     auto t0 = std::chrono::steady_clock::now();

@@ -5,14 +5,24 @@
 //
 // Launch shape: the stencil kernels use 64 x 4 (Chebyshev) or 64 x 8 (B apply) column
 // tiles of the interior that march over z-chunks (XCD-aware tile order); the pointwise
-// kernels stride over all nodes with 16-byte vectors; blocks beyond those process the
-// irregular rows.  Kernels that reduce write one partial per block; the
-// last block to finish sums them in a fixed order (deterministic) and updates the
+// kernels stride over all nodes with 16-byte vectors; blocks ahead of those process the
+// irregular rows.  Kernels that reduce write one partial per block; a one-block finalize
+// kernel that follows sums them in a fixed order (deterministic) and updates the
 // device-resident BiCGSTAB scalars, so the host never waits inside an iteration.
 #include "cps_device.h"
 #include "cps_kernels.h"
 
 namespace cps {
+
+// Blocks that process irregular rows come first in every launch that has them, in a count
+// rounded up to a multiple of the XCD count: they are short, so they finish within the
+// first round of blocks instead of trailing behind the regular tiles, and the regular
+// tiles keep their XCD assignment (block index modulo the XCD count).
+__host__ __device__ __forceinline__ int irr_blocks(int nrows, int rows_per_block)
+{
+    int nb = (nrows + rows_per_block - 1) / rows_per_block;
+    return (nb + NXCD - 1) / NXCD * NXCD;
+}
 
 
 // ---------------------------------------------------------------------------------------
@@ -22,35 +32,45 @@ namespace cps {
 //   A = R_x (x) L_y (x) L_z + L_x (x) R_y (x) L_z + L_x (x) L_y (x) R_z
 // with L = (a, 1, c) and R = (ar, br, cr) taken at the row's own index per direction.
 // A block owns a 64 x 8 column tile (two rows per thread) and marches in z: each plane of x
-// (with a one-node halo) is staged in a double-buffered LDS tile while the next plane is
-// already being fetched into registers; every thread filters its 3 x 3 neighbourhood along
+// (with a one-node halo) is staged in a double-buffered LDS tile while the next two planes
+// are already being fetched into registers; every thread filters its 3 x 3 neighbourhood along
 // x, then y, from LDS and keeps the two y-filtered planes it still needs in registers.
 // One barrier per plane.
 //
 // MODE_PLAIN  y = B x
-// MODE_V      v = B x;  partials (w, v), (v, v);  last block: alpha = rho / (r0, v)
-// MODE_T      t = B x;  partials (t, w), (t, t);  last block: omega = (t, s) / (t, t)
-// MODE_RES    y = b - B x; partials (y, y), (y/d, y/d); last block stores the norms
+// MODE_V      v = B x;  partials (w, v), (v, v);  finalize: alpha = rho / (r0, v)
+// MODE_T      t = B x;  partials (t, w), (t, t);  finalize: omega = (t, s) / (t, t)
+// MODE_RES    y = b - B x; partials (y, y), (y/d, y/d); finalize stores the norms
+// `aux` is the second operand of the row's output: w[e] for MODE_V / MODE_T, b[e] for
+// MODE_RES (unused for MODE_PLAIN).  The regular tiles load it one pipeline stage ahead.
+template <typename T, int MODE>
+using AuxT = typename std::conditional<MODE == MODE_RES, double, T>::type;
+
 template <typename T, typename TO, int MODE>
-__device__ __forceinline__ void emit(size_t e, T v, double bd, TO *__restrict__ y, const T *__restrict__ w,
-                                     const double *__restrict__ bvec, double (&acc)[2])
+__device__ __forceinline__ void emit(size_t e, T v, double bd, AuxT<T, MODE> aux, TO *__restrict__ y,
+                                     double (&acc)[2])
 {
     if (MODE == MODE_RES) {
-        double r = bvec[e] - (double)v;
+        double r = (double)aux - (double)v;
         y[e] = (TO)r;
         double rd = r / bd;
         acc[0] += r * r;
         acc[1] += rd * rd;
     } else {
         y[e] = (TO)v;
-        if (MODE == MODE_V) {
-            acc[0] += (double)w[e] * (double)v;
-            acc[1] += (double)v * (double)v;
-        } else if (MODE == MODE_T) {
-            acc[0] += (double)v * (double)w[e];
+        if (MODE == MODE_V || MODE == MODE_T) {
+            acc[0] += (double)aux * (double)v;
             acc[1] += (double)v * (double)v;
         }
     }
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ AuxT<T, MODE> load_aux(size_t e, const T *__restrict__ w, const double *__restrict__ bvec)
+{
+    if (MODE == MODE_RES) return bvec[e];
+    if (MODE == MODE_V || MODE == MODE_T) return w[e];
+    return AuxT<T, MODE>(0);
 }
 
 template <typename T, typename TO, int MODE>
@@ -69,9 +89,10 @@ __global__ void __launch_bounds__(NT) k_apply(Geom g, Coef<T> cf, Irr<T> ir, con
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ty * TX;
     const int nx = g.nx, ny = g.ny;
     const size_t plane = (size_t)nx * ny;
-    const int b = blockIdx.x;
+    const int nib = irr_blocks(ir.n, NT / IRR_LANES);
+    const int b = (int)blockIdx.x - nib;
     const Tiling &tl = g.t8;
-    if (b < tl.nblk) {
+    if (b >= 0) {
         int bx, by, bz;
         if (tile_of_block(tl, b, bx, by, bz)) {
             const int x0 = 1 + bx * TX, y0 = 1 + by * AY;
@@ -101,29 +122,63 @@ __global__ void __launch_bounds__(NT) k_apply(Geom g, Coef<T> cf, Irr<T> ir, con
                 sok[q] = sin[q] && gi < nx && gj < ny;
                 soff[q] = sok[q] ? gi + nx * gj : 0;
             }
-            T pre[NLD];
+            // Two register sets serve alternate planes.  While plane kk sits in LDS, planes
+            // kk+1 and kk+2 of x are in flight, together with the skip words and the second
+            // operand (aux) of the output rows two steps ahead.  Every load of a step is
+            // issued after the waits of that step, so the in-order completion counter never
+            // forces a wait on a plane that is still being prefetched.  The loop is unrolled
+            // by two so that each set and each LDS buffer has a fixed role and no in-flight
+            // register is ever copied.
+            using AT = AuxT<T, MODE>;
+            struct Set { T r[NLD]; AT wa, wb; uint32_t sa, sb; T z[5]; };
+            Set A, B;
+            // lanes outside the grid address row 1, column 1 and are masked off by aok / bok
+            const int ic = iok ? i : 1;
+            const size_t ea0 = (size_t)ic + (size_t)nx * (aok ? ja : 1), eb0 = (size_t)ic + (size_t)nx * (bok ? jb : 1);
+            const uint32_t *ska = skip + (size_t)(aok ? ja : 1) * g.W + (ic >> 5);
+            const uint32_t *skb = skip + (size_t)(bok ? jb : 1) * g.W + (ic >> 5);
+            const size_t skw = (size_t)g.ny * g.W;
+            // x of plane kk (clamped to k1; planes past k1 are loaded but unused)
+            auto stage_fetch = [&](Set &S, int kk) __attribute__((always_inline)) {
+                const size_t kp = (size_t)min(kk, k1) * plane;
 #pragma unroll
-            for (int q = 0; q < NLD; ++q) pre[q] = sok[q] ? x[(size_t)soff[q] + (size_t)(k0 - 1) * plane] : T(0);
+                for (int q = 0; q < NLD; ++q) S.r[q] = sok[q] ? x[(size_t)soff[q] + kp] : T(0);
+            };
+            // row-type bits, aux and z coefficients of output plane k (clamped to k1 - 1)
+            auto aux_fetch = [&](Set &S, int k) __attribute__((always_inline)) {
+                k = min(k, k1 - 1);
+                const size_t kp = (size_t)k * plane;
+                S.sa = aok ? ska[(size_t)k * skw] : ~0u;
+                S.sb = bok ? skb[(size_t)k * skw] : ~0u;
+                if (MODE != MODE_PLAIN) {
+                    S.wa = load_aux<T, MODE>(ea0 + kp, w, bvec);
+                    S.wb = load_aux<T, MODE>(eb0 + kp, w, bvec);
+                }
+                const T *cz = cf.c[2] + 8 * k;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) S.z[q] = cz[q];
+            };
+            stage_fetch(A, k0 - 1);
+            stage_fetch(B, k0);
+            A.wa = A.wb = B.wa = B.wb = AT(0);
+            A.sa = A.sb = B.sa = B.sb = ~0u;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) A.z[q] = B.z[q] = T(0);
             T LLa0 = 0, LRa0 = 0, LLa1 = 0, LRa1 = 0, LLb0 = 0, LRb0 = 0, LLb1 = 0, LRb1 = 0;
-            int buf = 0;
-            for (int kk = k0 - 1; kk <= k1; ++kk) {
+            auto plane_step = [&](Set &S, T (&lds)[LH][LW], int kk) __attribute__((always_inline)) {
 #pragma unroll
                 for (int q = 0; q < NLD; ++q)
-                    if (sin[q]) su[buf][srow[q]][scol[q]] = pre[q];
-                if (kk + 1 <= k1) {
-#pragma unroll
-                    for (int q = 0; q < NLD; ++q)
-                        pre[q] = sok[q] ? x[(size_t)soff[q] + (size_t)(kk + 1) * plane] : T(0);
-                }
+                    if (sin[q]) lds[srow[q]][scol[q]] = S.r[q];
+                stage_fetch(S, kk + 2);
                 __syncthreads();
                 // x filters of the three rows around row a (LDS rows ty..ty+2) and row b
                 T ul[6], ur[6];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
-                    T um = su[buf][ty + r][tx], u0 = su[buf][ty + r][tx + 1], up = su[buf][ty + r][tx + 2];
+                    T um = lds[ty + r][tx], u0 = lds[ty + r][tx + 1], up = lds[ty + r][tx + 2];
                     ul[r] = ax * um + u0 + ccx * up;
                     ur[r] = arx * um + brx * u0 + crx * up;
-                    T vm = su[buf][ty + TY + r][tx], v0 = su[buf][ty + TY + r][tx + 1], vp = su[buf][ty + TY + r][tx + 2];
+                    T vm = lds[ty + TY + r][tx], v0 = lds[ty + TY + r][tx + 1], vp = lds[ty + TY + r][tx + 2];
                     ul[3 + r] = ax * vm + v0 + ccx * vp;
                     ur[3 + r] = arx * vm + brx * v0 + crx * vp;
                 }
@@ -133,28 +188,31 @@ __global__ void __launch_bounds__(NT) k_apply(Geom g, Coef<T> cf, Irr<T> ir, con
                 T LRb2 = (ayb * ur[3] + ur[4] + cyb * ur[5]) + (aryb * ul[3] + bryb * ul[4] + cryb * ul[5]);
                 if (kk >= k0 + 1) {
                     const int k = kk - 1;
-                    const T *cz = cf.c[2] + 8 * k;
-                    const T az = cz[0], ccz = cz[1], arz = cz[2], brz = cz[3], crz = cz[4];
-                    if (aok && !skip_bit(skip, g, i, ja, k)) {
+                    const size_t kp = (size_t)k * plane;
+                    const T az = S.z[0], ccz = S.z[1], arz = S.z[2], brz = S.z[3], crz = S.z[4];
+                    if (!((S.sa >> (i & 31)) & 1u)) {
                         T v = az * LRa0 + LRa1 + ccz * LRa2 + arz * LLa0 + brz * LLa1 + crz * LLa2;
-                        emit<T, TO, MODE>((size_t)i + (size_t)nx * ja + (size_t)k * plane, v,
-                                          (double)(brx + brya + brz), y, w, bvec, acc);
+                        emit<T, TO, MODE>(ea0 + kp, v, (double)(brx + brya + brz), S.wa, y, acc);
                     }
-                    if (bok && !skip_bit(skip, g, i, jb, k)) {
+                    if (!((S.sb >> (i & 31)) & 1u)) {
                         T v = az * LRb0 + LRb1 + ccz * LRb2 + arz * LLb0 + brz * LLb1 + crz * LLb2;
-                        emit<T, TO, MODE>((size_t)i + (size_t)nx * jb + (size_t)k * plane, v,
-                                          (double)(brx + bryb + brz), y, w, bvec, acc);
+                        emit<T, TO, MODE>(eb0 + kp, v, (double)(brx + bryb + brz), S.wb, y, acc);
                     }
                 }
+                aux_fetch(S, kk + 1);
                 LLa0 = LLa1; LRa0 = LRa1; LLa1 = LLa2; LRa1 = LRa2;
                 LLb0 = LLb1; LRb0 = LRb1; LLb1 = LLb2; LRb1 = LRb2;
-                buf ^= 1;
+            };
+            for (int kk = k0 - 1; kk <= k1; kk += 2) {
+                plane_step(A, su[0], kk);
+                if (kk + 1 > k1) break;
+                plane_step(B, su[1], kk + 1);
             }
         }
     } else {
         // irregular rows: IRR_LANES lanes per row gather the full row of B
         const int rows_per_block = NT / IRR_LANES;
-        const int row = (b - tl.nblk) * rows_per_block + tid / IRR_LANES;
+        const int row = (int)blockIdx.x * rows_per_block + tid / IRR_LANES;
         const int lane = tid % IRR_LANES;
         double sacc = 0.0;
         if (row < ir.n) {
@@ -162,8 +220,10 @@ __global__ void __launch_bounds__(NT) k_apply(Geom g, Coef<T> cf, Irr<T> ir, con
                 sacc += (double)ir.val[e] * (double)x[ir.col[e]];
         }
         for (int o = IRR_LANES / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, IRR_LANES);
-        if (row < ir.n && lane == 0)
-            emit<T, TO, MODE>((size_t)ir.node[row], (T)sacc, (double)ir.bdiag[row], y, w, bvec, acc);
+        if (row < ir.n && lane == 0) {
+            const size_t e = (size_t)ir.node[row];
+            emit<T, TO, MODE>(e, (T)sacc, (double)ir.bdiag[row], load_aux<T, MODE>(e, w, bvec), y, acc);
+        }
     }
     if constexpr (NV > 0) write_partials<2>(acc, partials);
 }
@@ -200,7 +260,7 @@ __global__ void __launch_bounds__(NT) k_finalize(const double *partials, int nbl
         else if (tot[NV - 1] <= st->stop2) st->done = 1;
         else if (st->omega == 0.0 || st->rho == 0.0) st->done = 2;
         else {
-            st->beta = (st->alpha / st->omega) * (rho_new / st->rho);   // line 13
+            st->beta = (st->alpha / st->omega) * (rho_new / st->rho);
             st->rho = rho_new;
         }
     } else if (KIND == FIN_RES) {
@@ -236,9 +296,10 @@ __global__ void __launch_bounds__(NT) k_cheb(Geom g, Coef<T> cf, Irr<T> ir, cons
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ty * TX;
     const int nx = g.nx, ny = g.ny;
     const size_t plane = (size_t)nx * ny;
-    const int b = blockIdx.x;
+    const int nib = irr_blocks(ir.n, NT);
+    const int b = (int)blockIdx.x - nib;
     const Tiling &tl = g.t4;
-    if (b < tl.nblk) {
+    if (b >= 0) {
         int bx, by, bz;
         if (!tile_of_block(tl, b, bx, by, bz)) return;
         const int i = 1 + bx * TX + tx, j = 1 + by * TY + ty;
@@ -249,32 +310,54 @@ __global__ void __launch_bounds__(NT) k_cheb(Geom g, Coef<T> cf, Irr<T> ir, cons
         const T *cy = cf.c[1] + 8 * j;
         const T kax = cx[5], kbx = cx[6], kcx = cx[7];
         const T kay = cy[5], kby = cy[6], kcy = cy[7];
-        size_t e = (size_t)i + (size_t)nx * j + (size_t)k0 * plane;
-        T zm = xc[e - plane], z0 = xc[e], zp = xc[e + plane];
-        T wm = xc[e - 1], wp = xc[e + 1], sm = xc[e - nx], sp = xc[e + nx];
-        T rh = rho[e], pv = PREV0 ? T(0) : xm1[e];
-        for (int k = k0; k < k1; ++k, e += plane) {
-            T zpp = 0, wmn = 0, wpn = 0, smn = 0, spn = 0, rhn = 0, pvn = 0;
-            if (k + 1 < k1) {
-                const size_t en = e + plane;
-                zpp = xc[en + plane];
-                wmn = xc[en - 1];
-                wpn = xc[en + 1];
-                smn = xc[en - nx];
-                spn = xc[en + nx];
-                rhn = rho[en];
-                if (!PREV0) pvn = xm1[en];
-            }
+        const size_t e0 = (size_t)i + (size_t)nx * j;
+        // Software pipeline over three register sets, one per plane: plane k is computed
+        // from sets (k-1, k, k+1) and the set of plane k-1, dead after that, then receives
+        // plane k+2, so two planes of loads stay in flight.  Every operand of a plane (its
+        // skip word and z coefficients included) travels in its set: a load issued just
+        // before its use would make the in-order completion counter wait for the whole
+        // prefetch.  Fetches are unconditional, with the plane clamped to k1 <= nz - 1
+        // (planes past k1 are loaded but unused), and the loop is unrolled by three so that
+        // each set keeps a fixed register home.
+        struct Pl { T c, w, e, s, n, r, p, za, zb, zc; uint32_t sk; };
+        const size_t skw = (size_t)g.ny * g.W;
+        const uint32_t *skp = skip + (size_t)j * g.W + (i >> 5);
+        auto fetch = [&](Pl &P, int k) __attribute__((always_inline)) {
+            k = min(k, k1);
+            const size_t e = e0 + (size_t)k * plane;
             const T *cz = cf.c[2] + 8 * k;
-            T kd = kbx + kby + cz[6];
-            T kx = kd * z0 + kax * wm + kcx * wp + kay * sm + kcy * sp + cz[5] * zm + cz[7] * zp;
-            T val = z0 + c1 * (z0 - pv) + c2 * (rh - kx) / kd;
-            if (!skip_bit(skip, g, i, j, k)) xn[e] = val;
-            zm = z0; z0 = zp; zp = zpp;
-            wm = wmn; wp = wpn; sm = smn; sp = spn; rh = rhn; pv = pvn;
+            P.sk = skp[(size_t)k * skw];
+            P.c = xc[e];
+            P.w = xc[e - 1];
+            P.e = xc[e + 1];
+            P.s = xc[e - nx];
+            P.n = xc[e + nx];
+            P.r = rho[e];
+            P.p = PREV0 ? T(0) : xm1[e];
+            P.za = cz[5];
+            P.zb = cz[6];
+            P.zc = cz[7];
+        };
+        auto step = [&](const Pl &M, const Pl &C, const Pl &U, Pl &F, int k) __attribute__((always_inline)) {
+            T kd = kbx + kby + C.zb;
+            T kx = kd * C.c + kax * C.w + kcx * C.e + kay * C.s + kcy * C.n + C.za * M.c + C.zc * U.c;
+            T val = C.c + c1 * (C.c - C.p) + c2 * (C.r - kx) / kd;
+            if (!((C.sk >> (i & 31)) & 1u)) xn[e0 + (size_t)k * plane] = val;
+            fetch(F, k + 2);
+        };
+        Pl P0, P1, P2;
+        fetch(P2, k0 - 1);
+        fetch(P0, k0);
+        fetch(P1, k0 + 1);
+        for (int k = k0; k < k1; k += 3) {
+            step(P2, P0, P1, P2, k);
+            if (k + 1 >= k1) break;
+            step(P0, P1, P2, P0, k + 1);
+            if (k + 2 >= k1) break;
+            step(P1, P2, P0, P1, k + 2);
         }
     } else {
-        const int row = (b - tl.nblk) * NT + tid;
+        const int row = (int)blockIdx.x * NT + tid;
         if (row >= ir.n) return;
         const int e = ir.node[row];
         const T *k7 = ir.k7 + 7 * row;
@@ -341,10 +424,10 @@ struct NodeIt {
     }
 };
 
-// FIRST_P:  p = r + beta (p - omega v)   (Alg. 1 line 14; p = r after a (re)start: beta = 0)
-// FIRST_S:  s = r - alpha v              (line 7)
+// FIRST_P:  p = r + beta (p - omega v)   (search direction of Alg. 1; p = r after a (re)start: beta = 0)
+// FIRST_S:  s = r - alpha v              (intermediate residual of Alg. 1)
 // then x1 = c2 * (p or s) / diag(K), the first Chebyshev step from x0 = 0.  Irregular rows
-// (their K diagonal is the Shortley-Weller one) are done by the trailing blocks.
+// (their K diagonal is the Shortley-Weller one) are done by the leading blocks.
 template <typename T, int KIND>
 __global__ void __launch_bounds__(NT) k_first(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
                                               const T *__restrict__ r, T *__restrict__ ps, const T *__restrict__ v,
@@ -356,8 +439,9 @@ __global__ void __launch_bounds__(NT) k_first(Geom g, Coef<T> cf, Irr<T> ir, con
     const int tid = threadIdx.x + threadIdx.y * TX;
     const int nx = g.nx, ny = g.ny;
     const size_t nn = (size_t)nx * ny * g.nz;
-    const int b = blockIdx.x;
-    if (b < g.nflat) {
+    const int nib = irr_blocks(ir.n, NT);
+    const int b = (int)blockIdx.x - nib;
+    if (b >= 0) {
         const size_t ngroups = nn / VN;
         for (size_t q = (size_t)b * NT + tid; q < ngroups; q += (size_t)g.nflat * NT) {
             const size_t base = q * VN;
@@ -392,7 +476,7 @@ __global__ void __launch_bounds__(NT) k_first(Geom g, Coef<T> cf, Irr<T> ir, con
         }
         // tail nodes (nn not a multiple of VN) are wall nodes: nothing to do
     } else {
-        const int row = (b - g.nflat) * NT + tid;
+        const int row = (int)blockIdx.x * NT + tid;
         if (row >= ir.n) return;
         const int e = ir.node[row];
         T val = (KIND == FIRST_P) ? r[e] + beta * (ps[e] - omega * v[e]) : r[e] - alpha * v[e];
@@ -401,9 +485,9 @@ __global__ void __launch_bounds__(NT) k_first(Geom g, Coef<T> cf, Irr<T> ir, con
     }
 }
 
-// Alg. 1 lines 11-13: x += alpha p^ + omega s^, r = s - omega t, partials of (r0, r) and of
-// ||D^-1 r||^2 (D = diag B; regular rows here, irregular rows by the trailing blocks);
-// the last block forms beta and tests convergence.
+// Solution and residual updates of Alg. 1: x += alpha p^ + omega s^, r = s - omega t, partials of (r0, r) and of
+// ||D^-1 r||^2 (D = diag B; regular rows in the flat part, irregular rows by the leading
+// blocks); the finalize kernel forms beta and tests convergence.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_update(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
                                                T *__restrict__ xs, const T *__restrict__ ph, const T *__restrict__ sh,
@@ -419,8 +503,9 @@ __global__ void __launch_bounds__(NT) k_update(Geom g, Coef<T> cf, Irr<T> ir, co
     const int tid = threadIdx.x + threadIdx.y * TX;
     const int nx = g.nx, ny = g.ny;
     const size_t nn = (size_t)nx * ny * g.nz;
-    const int b = blockIdx.x;
-    if (b < g.nflat) {
+    const int nib = irr_blocks(ir.n, NT);
+    const int b = (int)blockIdx.x - nib;
+    if (b >= 0) {
         const size_t ngroups = nn / VN;
         for (size_t q = (size_t)b * NT + tid; q < ngroups; q += (size_t)g.nflat * NT) {
             const size_t base = q * VN;
@@ -448,7 +533,7 @@ __global__ void __launch_bounds__(NT) k_update(Geom g, Coef<T> cf, Irr<T> ir, co
             store16(r + base, rv);
         }
     } else {
-        const int row = (b - g.nflat) * NT + tid;
+        const int row = (int)blockIdx.x * NT + tid;
         if (row < ir.n) {
             const int e = ir.node[row];
             T rv = s[e] - omegaT * t[e];
@@ -537,8 +622,6 @@ __global__ void k_check_finite(size_t n, const int8_t *__restrict__ type, const 
 // ---------------------------------------------------------------------------------------
 static inline dim3 tile_block() { return dim3(TX, TY, 1); }
 
-static inline int rows_blocks(int n) { return (n + NT - 1) / NT; }
-
 template <int KIND>
 static void finalize(const Launch &L, int nb, DevState *st)
 {
@@ -549,8 +632,7 @@ template <typename T, typename TO>
 void launch_apply(int mode, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, TO *y, const T *w,
                   const double *bvec, DevState *st)
 {
-    int irr_blocks = (ir.n + (NT / IRR_LANES) - 1) / (NT / IRR_LANES);
-    int nb = L.g.t8.nblk + irr_blocks;
+    int nb = L.g.t8.nblk + irr_blocks(ir.n, NT / IRR_LANES);
     dim3 grid(nb), blk = tile_block();
     switch (mode) {
     case MODE_PLAIN:
@@ -575,7 +657,7 @@ template <typename T>
 void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
                  double c1, double c2, const DevState *st)
 {
-    dim3 grid(L.g.t4.nblk + rows_blocks(ir.n)), blk = tile_block();
+    dim3 grid(L.g.t4.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
     if (xm1 == nullptr)
         k_cheb<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st);
     else
@@ -586,7 +668,7 @@ template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st)
 {
-    dim3 grid(L.g.nflat + rows_blocks(ir.n)), blk = tile_block();
+    dim3 grid(L.g.nflat + irr_blocks(ir.n, NT)), blk = tile_block();
     if (kind == FIRST_P)
         k_first<T, FIRST_P><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, r, ps, v, x1, (T)c2, st);
     else
@@ -598,7 +680,7 @@ void launch_update(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, TX_ *xs
                    const T *t, const T *r0, T *r, DevState *st)
 {
     static_assert(sizeof(T) == sizeof(TX_), "solution and Krylov vectors share a precision");
-    int nb = L.g.nflat + rows_blocks(ir.n);
+    int nb = L.g.nflat + irr_blocks(ir.n, NT);
     k_update<T><<<dim3(nb), tile_block(), 0, L.stream>>>(L.g, cf, ir, L.skip, (T *)xs, ph, sh, s, t, r0, r, st,
                                                          L.partials, L.ticket, nb);
     finalize<FIN_UPDATE>(L, nb, st);

@@ -165,9 +165,10 @@ def test_apply_fp64_and_fp32(name):
 def test_precond_fp64_and_fp32(name):
     P, S, _ = _both(name)
     rho = _random_field(P, 12)
-    for m in (1, 8):
-        S2 = cps.Solver(*_case(name)[:6], inner_iters=m)
-        ref = P.precond(rho, iters=m)
+    # default interval policy on both sides (lo = hi / (4 m^2)), and one explicit interval
+    for m, lo in ((1, None), (8, 0.03), (24, None)):
+        S2 = cps.Solver(*_case(name)[:6], inner_iters=m, lam_lo=lo)
+        ref = P.precond(rho, iters=m, lo=lo)
         scale = np.max(np.abs(ref))
         got = _np(S2.precond(rho, "fp64"))
         assert np.max(np.abs(got - ref)) <= 1e-11 * scale, m
@@ -180,10 +181,14 @@ def test_solve_fp64_matches_oracle(name):
     P, S, ue = _both(name)
     t = P.types()
     fl = (t == 1) | (t == 2)
-    u_ref, st_ref = P.solve(1e-13)
-    u, st = S.solve(1e-12)
+    # The near-coincident case is ill-conditioned: at ||r||/||b|| = 1e-13 its solution is
+    # fixed only to ~5e-10 (oracle solves at 1e-13 and 1e-15 differ by that much), so both
+    # sides converge further there before the 1e-10 comparison.
+    tol = 1e-14 if name == "near_coincident" else 1e-12
+    u_ref, st_ref = P.solve(tol / 10)
+    u, st = S.solve(tol)
     u = _np(u)
-    assert st["rel_residual"] <= 1e-12 and st["rel_residual_jacobi"] <= 1e-12
+    assert st["rel_residual"] <= tol and st["rel_residual_jacobi"] <= tol
     rel = np.max(np.abs(u - u_ref)[fl]) / np.max(np.abs(u_ref[fl]))
     assert rel <= 1e-10, rel
     assert np.all(u[t == 3] == 0.0)                 # exactly zero inside bodies
@@ -296,9 +301,10 @@ def test_sphere_exp_128_fp64_vs_oracle_samples():
 
 
 def test_spheres8_256_mixed_vs_oracle_samples():
-    """256^3, 8 spheres, mixed precision.  At tol 1e-10 the residual bound holds but the
-    iteration error (~1e-7) exceeds 1e-9 at this size; at tol 1e-12 the solution matches
-    the FP64 oracle (solved to 1e-13) to <= 1e-9 relative max-norm on the stored samples."""
+    """256^3, 8 spheres.  At tol 1e-10 the residual bound holds but the iteration error
+    (~1e-7) exceeds 1e-9 at this size: a residual of 1e-12 still leaves ~1e-9 of it.  At
+    tol 1e-13 both the mixed and the plain FP64 solution match the FP64 oracle (solved to
+    1e-13, Jacobi-weighted residual 6e-14) to <= 1e-9 relative max-norm on the samples."""
     nodes, vals, umax = _samples("oracle_spheres8_256.txt")
     w = W.spheres8(256)
     print("[case] spheres8 256 mixed", flush=True)
@@ -306,9 +312,17 @@ def test_spheres8_256_mixed_vs_oracle_samples():
     u, st = S.solve(1e-10)
     assert st["rel_residual"] <= 1e-10 and st["rel_residual_jacobi"] <= 1e-10
     assert st["fallback_lines"] == 0
-    u, st = S.solve(1e-12)
-    assert st["rel_residual"] <= 1e-12 and st["rel_residual_jacobi"] <= 1e-12
+    u, st = S.solve(1e-13)
+    assert st["rel_residual"] <= 1e-13 and st["rel_residual_jacobi"] <= 1e-13
     got = _np(u).ravel()[nodes]
     rel = np.max(np.abs(got - vals)) / umax
-    print(f"max rel. difference vs oracle samples: {rel:.2e}")
+    print(f"mixed: max rel. difference vs oracle samples: {rel:.2e}")
+    assert rel <= 1e-9
+    S.close()
+    print("[case] spheres8 256 fp64", flush=True)
+    S = cps.Solver.from_workload(w, precision="fp64")
+    u, st = S.solve(1e-13)
+    assert st["rel_residual"] <= 1e-13 and st["rel_residual_jacobi"] <= 1e-13
+    rel = np.max(np.abs(_np(u).ravel()[nodes] - vals)) / umax
+    print(f"fp64: max rel. difference vs oracle samples: {rel:.2e}")
     assert rel <= 1e-9
