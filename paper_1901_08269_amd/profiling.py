@@ -1,0 +1,143 @@
+"""Summaries of rocprofv3 result databases as short markdown.
+
+Two reports:
+
+``stats``    per-kernel call counts and durations from a ``--kernel-trace --stats`` run.
+``traffic``  HBM bytes per launch of one kernel from two ``--pmc`` runs (``FETCH_SIZE`` and
+             ``WRITE_SIZE``, each in its own pass), each counter scaled by what the same counter
+             reads for a plain device copy of known size (the calibration runs).  The report
+             ends with machine-readable ``key: value`` lines, including a hash of the kernel
+             sources, so a reader can tell whether the counters still describe the code.
+
+Usage::
+
+    python -m paper_1901_08269_amd.profiling stats DB --title T --cmd C [--top 20]
+    python -m paper_1901_08269_amd.profiling traffic --fetch DB --write DB \\
+        --copy-fetch DB --copy-write DB --copy-bytes B --kernel NAME --units U --unit-bytes UB \\
+        --title T --cmd C
+"""
+import argparse
+import hashlib
+import os
+import re
+import sqlite3
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# the sources that define the sweep kernels; a traffic report is stale once they change
+KERNEL_SOURCES = ("csrc/sweeps.hip", "csrc/cps_device.h", "csrc/cps_kernels.h")
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def source_hash(files=KERNEL_SOURCES):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(n):
+    n = re.sub(r"\(cps::Geom.*", "", n)
+    n = re.sub(r"\(.*", "", n)
+    return n.replace("void ", "")
+
+
+def kernel_stats(db):
+    con = sqlite3.connect(db)
+    rows = list(con.execute("select name,total_calls,total_duration,average,percentage from top_kernels"))
+    con.close()
+    return rows
+
+
+def pmc_per_kernel(db):
+    """{short kernel name: (dispatches, mean counter value, mean duration ns)}"""
+    con = sqlite3.connect(db)
+    acc = {}
+    for name, val, dur in con.execute("select name,counter_value,duration from pmc_events"):
+        n = short_name(name)
+        c, v, d = acc.get(n, (0, 0.0, 0.0))
+        acc[n] = (c + 1, v + val, d + dur)
+    con.close()
+    return {k: (c, v / c, d / c) for k, (c, v, d) in acc.items()}
+
+
+def stats_report(db, title, cmd, top=20):
+    out = [f"# {title}", "", "Command (run from the repository root on an MI355X):", "", "```", cmd, "```", "",
+           "Kernel statistics from `rocprofv3 --kernel-trace --stats` (durations in microseconds):", "",
+           "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for n, c, t, a, p in kernel_stats(db)[:top]:
+        out.append(f"| `{short_name(n)}` | {c} | {t:.1f} | {a:.2f} | {p:.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def traffic_report(a):
+    cf = pmc_per_kernel(a.copy_fetch)[COPY_KERNEL]
+    cw = pmc_per_kernel(a.copy_write)[COPY_KERNEL]
+    kib = a.copy_bytes / 1024.0
+    sf, sw = kib / cf[1], kib / cw[1]
+    f = pmc_per_kernel(a.fetch)[a.kernel]
+    w = pmc_per_kernel(a.write)[a.kernel]
+    rd, wr = f[1] * sf * 1024.0, w[1] * sw * 1024.0
+    alg = a.units * a.unit_bytes
+    out = [f"# {a.title}", "", "Commands (run from the repository root on an MI355X, each counter in its own pass):",
+           "", "```", a.cmd, "```", "",
+           f"Calibration: a device copy of {a.copy_bytes} bytes (`{COPY_KERNEL}`) reads "
+           f"FETCH_SIZE = {cf[1]:.1f} KiB and WRITE_SIZE = {cw[1]:.1f} KiB per dispatch, so the counters are "
+           f"scaled by {sf:.4f} (fetch) and {sw:.4f} (write).", "",
+           "| quantity | value |", "|---|---:|",
+           f"| kernel | `{a.kernel}` |",
+           f"| dispatches (fetch pass / write pass) | {f[0]} / {w[0]} |",
+           f"| FETCH_SIZE per dispatch, raw KiB | {f[1]:.1f} |",
+           f"| WRITE_SIZE per dispatch, raw KiB | {w[1]:.1f} |",
+           f"| HBM read per launch, bytes (scaled) | {rd:.4g} |",
+           f"| HBM write per launch, bytes (scaled) | {wr:.4g} |",
+           f"| HBM traffic per launch, bytes | {rd + wr:.4g} |",
+           f"| algorithmic bytes per launch ({a.units} units x {a.unit_bytes} B) | {alg:.4g} |",
+           f"| traffic / algorithmic | {(rd + wr) / alg:.3f} |",
+           f"| mean duration under counters, us | {f[2] / 1e3:.1f} |", "",
+           "Machine-readable:", "", "```",
+           f"kernel: {a.kernel}",
+           f"traffic_bytes_per_launch: {rd + wr:.6g}",
+           f"read_bytes_per_launch: {rd:.6g}",
+           f"write_bytes_per_launch: {wr:.6g}",
+           f"algorithmic_bytes_per_launch: {alg:.6g}",
+           f"kernel_source_sha256_16: {source_hash()}",
+           "```", ""]
+    return "\n".join(out)
+
+
+def read_traffic(path):
+    """The machine-readable lines of a traffic report, or None if absent."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        m = re.match(r"^([a-z_0-9]+): (.+)$", line.strip())
+        if m:
+            kv[m.group(1)] = m.group(2)
+    return kv or None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("--title", required=True)
+    s.add_argument("--cmd", required=True)
+    s.add_argument("--top", type=int, default=20)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "title", "cmd"):
+        t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--units", type=int, required=True)
+    t.add_argument("--unit-bytes", type=float, required=True)
+    a = ap.parse_args(argv)
+    if a.mode == "stats":
+        print(stats_report(a.db, a.title, a.cmd, a.top), end="")
+    else:
+        print(traffic_report(a), end="")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,53 @@
+"""Host-side checks of the rocprofv3 summary tool: the counter scaling of the traffic report
+and the parsing that the benchmark relies on, on small synthetic result databases."""
+import argparse
+import sqlite3
+
+from paper_1901_08269_amd import profiling
+
+
+def _pmc_db(path, rows):
+    con = sqlite3.connect(path)
+    con.execute("create table pmc_events (name text, counter_value real, duration real)")
+    con.executemany("insert into pmc_events values (?,?,?)", rows)
+    con.commit()
+    con.close()
+    return str(path)
+
+
+def test_traffic_report_scales_by_copy_calibration(tmp_path):
+    copy_bytes = 1 << 20                       # 1024 KiB copied
+    cf = _pmc_db(tmp_path / "cf.db", [(profiling.COPY_KERNEL, 512.0, 10.0)] * 3)     # counter reads half
+    cw = _pmc_db(tmp_path / "cw.db", [(profiling.COPY_KERNEL, 1024.0, 10.0)] * 3)    # counter exact
+    k = "void cps::k_cheb<float, false>(cps::Geom, int)"
+    f = _pmc_db(tmp_path / "f.db", [(k, 100.0, 2000.0), (k, 300.0, 4000.0), ("other", 9.0, 1.0)])
+    w = _pmc_db(tmp_path / "w.db", [(k, 50.0, 2000.0)] * 2)
+    a = argparse.Namespace(fetch=f, write=w, copy_fetch=cf, copy_write=cw, copy_bytes=copy_bytes,
+                           kernel="cps::k_cheb<float, false>", units=1000, unit_bytes=16.0,
+                           title="t", cmd="c")
+    rep = profiling.traffic_report(a)
+    p = tmp_path / "rep.md"
+    p.write_text(rep)
+    kv = profiling.read_traffic(str(p))
+    # fetch: mean 200 KiB x 2 = 400 KiB; write: 50 KiB x 1
+    assert abs(float(kv["read_bytes_per_launch"]) - 400 * 1024) < 1
+    assert abs(float(kv["write_bytes_per_launch"]) - 50 * 1024) < 1
+    assert abs(float(kv["traffic_bytes_per_launch"]) - 450 * 1024) < 1
+    assert float(kv["algorithmic_bytes_per_launch"]) == 16000.0
+    assert kv["kernel_source_sha256_16"] == profiling.source_hash()
+    assert len(profiling.source_hash()) == 16
+
+
+def test_read_traffic_missing(tmp_path):
+    assert profiling.read_traffic(str(tmp_path / "none.md")) is None
+
+
+def test_stats_report(tmp_path):
+    db = tmp_path / "s.db"
+    con = sqlite3.connect(db)
+    con.execute("create table top_kernels (name text, total_calls int, total_duration real, average real, percentage real)")
+    con.execute("insert into top_kernels values ('void cps::k_update<float>(cps::Geom, int)', 4, 400.0, 100.0, 55.0)")
+    con.commit()
+    con.close()
+    rep = profiling.stats_report(str(db), "T", "cmd")
+    assert "| `cps::k_update<float>` | 4 | 400.0 | 100.00 | 55.0 |" in rep
