@@ -110,7 +110,7 @@ def main():
     t0 = time.perf_counter()
     stats = []
     for q in range(args.steps):
-        u, st = step("mixed", True)
+        u, st = step("mixed", 8)
         stats.append(st)
         print(f"# step {q}: {st['iters']} iters, {st['refine_steps']} refinements, "
               f"rel res {st['rel_residual']:.2e}", file=sys.stderr, flush=True)
@@ -165,7 +165,7 @@ def main():
             parity[prec] = ent
         parity["speedup_mixed_vs_fp64_solve"] = parity["fp64"]["solve_s"] / parity["mixed"]["solve_s"]
 
-    # roofline of the dominant kernel: the FP32 Chebyshev sweep of the preconditioner
+    # roofline of the dominant kernel: the fused FP32 Chebyshev sweep of the preconditioner
     sweeps = sum(s["sweep_launches"] for s in stats)
     sweep_ms = sum(s["sweep_ms"] for s in stats)
     pts = last["sweep_points"]
@@ -176,14 +176,14 @@ def main():
     # describes the kernel sources (the report carries their hash) and this workload
     from paper_1901_08269_amd import profiling
     traffic, traffic_note = None, "no counter report for this workload"
-    rep = profiling.read_traffic(os.path.join(ROOT, "profiles", f"k_cheb_spheres8_{args.N}_traffic.md"))
+    rep = profiling.read_traffic(os.path.join(ROOT, "profiles", f"k_cheb4_spheres8_{args.N}_traffic.md"))
     if rep is not None:
         if rep.get("kernel_source_sha256_16") == profiling.source_hash():
             traffic = float(rep["traffic_bytes_per_launch"])
-            traffic_note = f"profiles/k_cheb_spheres8_{args.N}_traffic.md (FETCH_SIZE+WRITE_SIZE, copy-calibrated)"
+            traffic_note = f"profiles/k_cheb4_spheres8_{args.N}_traffic.md (FETCH_SIZE+WRITE_SIZE, copy-calibrated)"
         else:
             traffic_note = "kernel sources changed since the counters were taken"
-    roofline = {"kernel": "k_cheb<float> (preconditioner sweep)", "bound": "hbm",
+    roofline = {"kernel": "k_cheb4<float> (preconditioner sweep)", "bound": "hbm",
                 "achieved": achieved, "peak": metrics.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / metrics.MI355X_HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                 "traffic_source": traffic_note,

@@ -141,7 +141,7 @@ class Solver:
         o.max_iters = max_iters
         o.max_refine = max_refine
         o.max_restarts = max_restarts
-        o.kernel_timing = int(kernel_timing)
+        o.kernel_timing = int(kernel_timing)   # True: every sweep; n: every n-th
         o.device_ptrs = 1
         self.stream = torch.cuda.current_stream()
         o.stream = C.c_void_p(self.stream.cuda_stream)

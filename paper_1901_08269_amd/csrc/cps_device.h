@@ -26,8 +26,9 @@ constexpr int NT = TX * TY;   // threads per block
 constexpr int IRR_LANES = 16; // lanes per irregular row in the B pass
 constexpr int NXCD = 8;       // MI355X: 8 XCDs, blocks dispatched round-robin over them
 
-// A tiling of the interior into (64 x ty) columns that march over z-chunks of TZ planes.
+// A tiling of the interior into (tw x ty) columns that march over z-chunks of TZ planes.
 struct Tiling {
+    int tw;                    // tile width in x (nodes)
     int ty;                    // tile rows in y
     int tiles_x, tiles_y, zchunks, TZ;
     int ntiles;                // tiles_x * tiles_y * zchunks
@@ -37,8 +38,10 @@ struct Tiling {
 struct Geom {
     int nx, ny, nz;
     int W;                     // skip-bit words per x-line
-    Tiling t4;                 // 64 x 4 tiles: Chebyshev sweeps
+    Tiling t4;                 // 64 x 4 tiles: single-node-per-lane sweeps
     Tiling t8;                 // 64 x 8 tiles (two rows per thread): the B apply
+    Tiling tr;                 // 256 x 4 tiles: one x-row segment of 256 nodes per wavefront,
+                               // four nodes per lane (vectorised Chebyshev sweeps)
     int nflat;                 // blocks of the flat (vectorised) pointwise kernels
 };
 
@@ -56,7 +59,17 @@ struct Irr {
     const T *val;              // B entries
     const T *k7;               // K row: diag, -x, +x, -y, +y, -z, +z
     const T *bdiag;            // diagonal entry of B
+    const uint32_t *bits;      // irregular-node bits, laid out like the skip words
+    const int *wstart;         // per bit word: rows of the nodes before the word's first node
 };
+
+// Row of irregular node (i, j, k) from its bit word: the rows are in node order, so the row
+// is the word's start count plus the irregular nodes below i in that word.
+template <typename T>
+__device__ __forceinline__ int irr_row_of(const Irr<T> &ir, size_t word, int i)
+{
+    return ir.wstart[word] + __popc(ir.bits[word] & ((1u << (i & 31)) - 1u));
+}
 
 // Device-resident BiCGSTAB scalars (Alg. 1); all FP64 whatever the vector precision.
 struct DevState {

@@ -26,6 +26,9 @@ template <typename T>
 void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
                  double c1, double c2, const DevState *st);
 template <typename T>
+void launch_cheb2(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xk, const T *xkm1, const T *rho,
+                  T *x1, T *x2, double c1a, double c2a, double c1b, double c2b, const DevState *st);
+template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st);
 template <typename T, typename TX_>
@@ -59,6 +62,8 @@ void launch_compact(hipStream_t s, size_t n, const int8_t *type, int8_t want, in
                     int nblocks);
 int compact_blocks(size_t n);
 void launch_skipbits(hipStream_t s, const Geom &g, const int8_t *type, uint32_t *skip);
+void launch_irr_words(hipStream_t s, const Geom &g, const int8_t *type, const int *nodes, int nirr, uint32_t *bits,
+                      int *wstart);
 // build irregular rows in a fixed-stride scratch (cap entries per row)
 void launch_build_rows(hipStream_t s, int nx, int ny, int nz, const double *x, const double *y, const double *z,
                        const double *coef, const double *phi, const double *g, const double *f, const int8_t *type,

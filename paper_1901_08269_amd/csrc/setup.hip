@@ -218,6 +218,40 @@ void launch_skipbits(hipStream_t s, const Geom &g, const int8_t *type, uint32_t 
     k_skipbits<<<(unsigned)std::min<size_t>((nw + 255) / 256, 65536), 256, 0, s>>>(g, type, skip);
 }
 
+// irregular-node bits per word, and the number of irregular rows (nodes in ascending
+// order) before the word's first node: a binary search in the row list
+__global__ void k_irr_words(Geom g, const int8_t *__restrict__ type, const int *__restrict__ nodes, int nirr,
+                            uint32_t *__restrict__ bits, int *__restrict__ wstart)
+{
+    size_t nw = (size_t)g.W * g.ny * g.nz;
+    for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (size_t)gridDim.x * blockDim.x) {
+        size_t line = w / g.W;
+        int i0 = (int)(w % g.W) * 32;
+        uint32_t b = 0;
+        for (int q = 0; q < 32; ++q) {
+            int i = i0 + q;
+            if (i >= g.nx) break;
+            if (type[line * g.nx + i] == 2) b |= 1u << q;
+        }
+        bits[w] = b;
+        const long long first = (long long)line * g.nx + i0;
+        int lo = 0, hi = nirr;           // first row whose node is >= first
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if ((long long)nodes[mid] < first) lo = mid + 1;
+            else hi = mid;
+        }
+        wstart[w] = lo;
+    }
+}
+
+void launch_irr_words(hipStream_t s, const Geom &g, const int8_t *type, const int *nodes, int nirr, uint32_t *bits,
+                      int *wstart)
+{
+    size_t nw = (size_t)g.W * g.ny * g.nz;
+    k_irr_words<<<(unsigned)std::min<size_t>((nw + 255) / 256, 65536), 256, 0, s>>>(g, type, nodes, nirr, bits, wstart);
+}
+
 // ---------------------------------------------------------------------------------------
 // irregular rows
 // ---------------------------------------------------------------------------------------

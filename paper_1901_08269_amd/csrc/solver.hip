@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -38,7 +39,7 @@ constexpr int MAX_INNER = 64;
 template <typename T>
 struct Vecs {
     T *r = nullptr, *r0 = nullptr, *p = nullptr, *ph = nullptr, *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr;
-    T *x = nullptr, *c[3] = {nullptr, nullptr, nullptr};
+    T *x = nullptr, *c[4] = {nullptr, nullptr, nullptr, nullptr};
     bool ready = false;
 };
 
@@ -57,6 +58,8 @@ struct cps_solver {
     double *phi = nullptr, *gf = nullptr, *f = nullptr;
     int8_t *type = nullptr;
     uint32_t *skip = nullptr;
+    uint32_t *irr_bits = nullptr;  // irregular-node bits (skip-word layout)
+    int *irr_wstart = nullptr;     // irregular rows before each bit word
     int nirr = 0;
     int *irr_node = nullptr, *irr_ptr = nullptr, *irr_col = nullptr;
     double *irr_val64 = nullptr, *irr_k64 = nullptr, *irr_bd64 = nullptr;
@@ -71,6 +74,7 @@ struct cps_solver {
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> tev;  // sweep timing events
     size_t tev_used = 0;
+    int64_t sweep_count = 0;      // sweeps enqueued since the solve started (timing sample)
     Vecs<double> v64;
     Vecs<float> v32;
     double *tmp64 = nullptr;      // user-facing staging (residual, apply, precond)
@@ -81,7 +85,11 @@ struct cps_solver {
     double min_hb = 1.0;
     double bn2 = 0.0, bs2 = 0.0;  // ||b||^2, ||D^-1 b||^2
     double setup_ms = 0.0;
-    std::vector<void *> allocs;
+    struct Alloc {
+        void *p;
+        size_t bytes;
+    };
+    std::vector<Alloc> allocs;    // device blocks owned by this solver
 
     Launch launch() const { return Launch{g, stream, skip, partials, ticket}; }
     Coef<double> cf64() const
@@ -96,8 +104,14 @@ struct cps_solver {
         for (int d = 0; d < 3; ++d) c.c[d] = coef32 + (size_t)d * 8 * nmax;
         return c;
     }
-    Irr<double> ir64() const { return Irr<double>{nirr, irr_node, irr_ptr, irr_col, irr_val64, irr_k64, irr_bd64}; }
-    Irr<float> ir32() const { return Irr<float>{nirr, irr_node, irr_ptr, irr_col, irr_val32, irr_k32, irr_bd32}; }
+    Irr<double> ir64() const
+    {
+        return Irr<double>{nirr, irr_node, irr_ptr, irr_col, irr_val64, irr_k64, irr_bd64, irr_bits, irr_wstart};
+    }
+    Irr<float> ir32() const
+    {
+        return Irr<float>{nirr, irr_node, irr_ptr, irr_col, irr_val32, irr_k32, irr_bd32, irr_bits, irr_wstart};
+    }
 };
 
 namespace {
@@ -111,23 +125,115 @@ inline void ck(hipError_t e)
     if (e != hipSuccess) throw HipFail{e};
 }
 
+// Pinned host blocks for the small device-to-host state copies.  Freeing pinned memory is
+// slow (it synchronises and unpins), so blocks go back to a process-wide free list.
+constexpr size_t PINNED_BLOCK = 4096;
+std::mutex pinned_mu;
+std::vector<void *> pinned_free;
+
+void *pinned_get()
+{
+    {
+        std::lock_guard<std::mutex> lk(pinned_mu);
+        if (!pinned_free.empty()) {
+            void *p = pinned_free.back();
+            pinned_free.pop_back();
+            return p;
+        }
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, PINNED_BLOCK, hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
+    return p;
+}
+
+void pinned_put(void *p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(pinned_mu);
+    pinned_free.push_back(p);
+}
+
+// Device memory cache.  Returning memory to the HIP runtime costs about a quarter of a
+// millisecond per block, so blocks released by a solver (at destroy, or setup temporaries)
+// stay in a per-device list and serve later allocations of up to the same size; only a
+// miss allocates.  Blocks enter the list idle (the owning stream is synchronised first), so
+// any stream may reuse them.  An allocation that fails releases the device's cached blocks
+// and retries once.  The cache lives until the process ends.
+struct CachedBlock {
+    void *p;
+    size_t bytes;
+    int dev;
+};
+std::mutex cache_mu;
+std::vector<CachedBlock> cache_blocks;
+
+size_t cache_round(size_t bytes)
+{
+    const size_t g = bytes >= ((size_t)1 << 20) ? ((size_t)2 << 20) : 256;
+    return (bytes + g - 1) / g * g;
+}
+
+void *cache_alloc(size_t bytes)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) throw std::bad_alloc();
+    bytes = cache_round(bytes);
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        int best = -1;
+        for (int q = 0; q < (int)cache_blocks.size(); ++q) {
+            const CachedBlock &c = cache_blocks[q];
+            if (c.dev == dev && c.bytes >= bytes && c.bytes <= 2 * bytes &&
+                (best < 0 || c.bytes < cache_blocks[best].bytes))
+                best = q;
+        }
+        if (best >= 0) {
+            void *p = cache_blocks[best].p;
+            cache_blocks.erase(cache_blocks.begin() + best);
+            return p;
+        }
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) == hipSuccess) return p;
+    (void)hipGetLastError();
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        for (int q = (int)cache_blocks.size() - 1; q >= 0; --q)
+            if (cache_blocks[q].dev == dev) {
+                (void)hipFree(cache_blocks[q].p);
+                cache_blocks.erase(cache_blocks.begin() + q);
+            }
+    }
+    if (hipMalloc(&p, bytes) == hipSuccess) return p;
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+}
+
+void cache_release(void *p, size_t bytes)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(cache_mu);
+    cache_blocks.push_back(CachedBlock{p, cache_round(bytes), dev});
+}
+
 template <typename T>
 T *dalloc(cps_solver *s, size_t n)
 {
-    void *p = nullptr;
     if (n == 0) n = 1;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
-    if (e != hipSuccess) throw std::bad_alloc();
-    s->allocs.push_back(p);
+    void *p = cache_alloc(n * sizeof(T));
+    s->allocs.push_back({p, n * sizeof(T)});
     return (T *)p;
 }
 
 void dfree(cps_solver *s, void *p)
 {
     if (!p) return;
-    auto it = std::find(s->allocs.begin(), s->allocs.end(), p);
-    if (it != s->allocs.end()) s->allocs.erase(it);
-    (void)hipFree(p);
+    auto it = std::find_if(s->allocs.begin(), s->allocs.end(), [&](const cps_solver::Alloc &a) { return a.p == p; });
+    if (it == s->allocs.end()) return;
+    (void)hipStreamSynchronize(s->stream);
+    cache_release(it->p, it->bytes);
+    s->allocs.erase(it);
 }
 
 // copy a caller array (host or device per opt.device_ptrs) to device memory
@@ -157,11 +263,12 @@ void set_stop2(cps_solver *s, double v)
     ck(hipMemcpyAsync(&s->st->stop2, s->hscalar, sizeof(double), hipMemcpyHostToDevice, s->stream));
 }
 
-Tiling make_tiling(int nx, int ny, int nz, int ty, int target_blocks, int min_tz)
+Tiling make_tiling(int nx, int ny, int nz, int tw, int ty, int target_blocks, int min_tz)
 {
     Tiling t{};
+    t.tw = tw;
     t.ty = ty;
-    t.tiles_x = (nx - 2 + TX - 1) / TX;
+    t.tiles_x = (nx - 2 + tw - 1) / tw;
     t.tiles_y = (ny - 2 + ty - 1) / ty;
     int per_plane = t.tiles_x * t.tiles_y;
     int nzi = nz - 2;
@@ -180,6 +287,9 @@ Tiling make_tiling(int nx, int ny, int nz, int ty, int target_blocks, int min_tz
 #ifndef CPS_APPLY_BLOCKS
 #define CPS_APPLY_BLOCKS 2048
 #endif
+#ifndef CPS_ROW_BLOCKS
+#define CPS_ROW_BLOCKS 512
+#endif
 #ifndef CPS_FLAT_BLOCKS
 #define CPS_FLAT_BLOCKS 4096
 #endif
@@ -189,8 +299,9 @@ Geom make_geom(int nx, int ny, int nz)
     Geom g{};
     g.nx = nx; g.ny = ny; g.nz = nz;
     g.W = (nx + 31) / 32;
-    g.t4 = make_tiling(nx, ny, nz, 4, CPS_CHEB_BLOCKS, 8);
-    g.t8 = make_tiling(nx, ny, nz, 8, CPS_APPLY_BLOCKS, 8);
+    g.t4 = make_tiling(nx, ny, nz, TX, 4, CPS_CHEB_BLOCKS, 8);
+    g.t8 = make_tiling(nx, ny, nz, TX, 8, CPS_APPLY_BLOCKS, 8);
+    g.tr = make_tiling(nx, ny, nz, 4 * TX, TY, CPS_ROW_BLOCKS, 4);
     size_t nn = (size_t)nx * ny * nz;
     g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, CPS_FLAT_BLOCKS);
     return g;
@@ -215,7 +326,7 @@ template <typename T>
 void alloc_vecs(cps_solver *s, Vecs<T> &V)
 {
     if (V.ready) return;
-    T **all[] = {&V.r, &V.r0, &V.p, &V.ph, &V.v, &V.s, &V.sh, &V.t, &V.x, &V.c[0], &V.c[1], &V.c[2]};
+    T **all[] = {&V.r, &V.r0, &V.p, &V.ph, &V.v, &V.s, &V.sh, &V.t, &V.x, &V.c[0], &V.c[1], &V.c[2], &V.c[3]};
     for (T **p : all) {
         *p = dalloc<T>(s, s->nn);
         launch_fill<T>(s->stream, s->nn, *p, T(0));
@@ -233,7 +344,27 @@ hipEvent_t timing_event(cps_solver *s)
     return s->tev[s->tev_used++];
 }
 
-// p^ = M p: inner_iters Chebyshev steps; the first is fused with the vector update `kind`
+// Every kernel_timing-th sweep is bracketed by a pair of events (an event pair costs a few
+// microseconds of queue time, so timing is sampled); returns the closing event or null.
+hipEvent_t timed_sweep_begin(cps_solver *s)
+{
+    const int period = s->opt.kernel_timing;
+    if (period <= 0 || (s->sweep_count++ % period) != 0) return nullptr;
+    hipEvent_t e0 = timing_event(s), e1 = timing_event(s);
+    ck(hipEventRecord(e0, s->stream));
+    return e1;
+}
+
+// Fused two-step sweeps (k_cheb2) for the Chebyshev recursion; 0 runs every step singly.
+#ifndef CPS_FUSED_SWEEPS
+#define CPS_FUSED_SWEEPS 0
+#endif
+
+// p^ = M p: inner_iters Chebyshev steps.  The first is fused with the vector update `kind`;
+// with fused sweeps the rest run two per sweep (k_cheb2), after one single sweep when their
+// count is odd.
+// Iterate x_j (j < m) lives in V.c[j % 4]: a fused sweep reads x_{k-1}, x_k and writes
+// x_{k+1}, x_{k+2}, four distinct buffers; x_m goes to dst.
 template <typename T>
 void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T *v, T *dst, const double *c1,
                    const double *c2, const DevState *st)
@@ -243,20 +374,26 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
     Irr<T> ir;
     if constexpr (sizeof(T) == 8) { cf = s->cf64(); ir = s->ir64(); } else { cf = s->cf32(); ir = s->ir32(); }
     const int m = s->opt.inner_iters;
-    T *x1 = (m == 1) ? dst : V.c[0];
-    launch_first<T>(kind, L, cf, ir, r, ps, v, x1, c2[0], st);
-    for (int k = 1; k < m; ++k) {
-        const T *xc = V.c[(k - 1) % 3];
-        const T *xm1 = (k == 1) ? nullptr : V.c[(k - 2) % 3];
-        T *xn = (k == m - 1) ? dst : V.c[k % 3];
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (s->opt.kernel_timing) {
-            e0 = timing_event(s);
-            e1 = timing_event(s);
-            ck(hipEventRecord(e0, s->stream));
+    auto buf = [&](int j) { return (j == m) ? dst : V.c[j % 4]; };
+    launch_first<T>(kind, L, cf, ir, r, ps, v, buf(1), c2[0], st);
+    int k = 1;
+    if (!CPS_FUSED_SWEEPS) {
+        for (; k < m; ++k) {
+            hipEvent_t e1 = timed_sweep_begin(s);
+            launch_cheb<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), c1[k], c2[k], st);
+            if (e1) ck(hipEventRecord(e1, s->stream));
         }
-        launch_cheb<T>(L, cf, ir, xc, xm1, ps, xn, c1[k], c2[k], st);
-        if (s->opt.kernel_timing) ck(hipEventRecord(e1, s->stream));
+        return;
+    }
+    if ((m - 1) % 2 == 1) {
+        launch_cheb<T>(L, cf, ir, buf(1), nullptr, ps, buf(2), c1[1], c2[1], st);
+        k = 2;
+    }
+    for (; k + 1 < m; k += 2) {
+        hipEvent_t e1 = timed_sweep_begin(s);
+        launch_cheb2<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), buf(k + 2), c1[k], c2[k],
+                        c1[k + 1], c2[k + 1], st);
+        if (e1) ck(hipEventRecord(e1, s->stream));
     }
 }
 
@@ -295,11 +432,10 @@ DevState run_iterations(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget, const 
 void free_solver(cps_solver *s)
 {
     if (!s) return;
-    if (s->stream) (void)hipStreamSynchronize(s->stream);
-    for (void *p : s->allocs) (void)hipFree(p);
+    (void)hipStreamSynchronize(s->stream);
+    for (const auto &a : s->allocs) cache_release(a.p, a.bytes);
     s->allocs.clear();
-    if (s->hst) (void)hipHostFree(s->hst);
-    if (s->hscalar) (void)hipHostFree(s->hscalar);
+    pinned_put(s->hst);            // hscalar lives in the same block
     for (auto &e : s->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto e : s->tev) (void)hipEventDestroy(e);
@@ -338,7 +474,9 @@ int fill_stats(cps_solver *s, cps_stats *st, const DevState &ds, int iters, int 
         st->sweep_ms = tot;
         st->sweep_launches = (int64_t)(s->tev_used / 2);
     }
-    st->sweep_bytes_per_point = (s->opt.precision == CPS_MIXED) ? 16 : 32;
+    // a single sweep reads x_k, x_{k-1}, rho and writes x_{k+1}; a fused sweep also writes x_{k+2}
+    const int vb = (s->opt.precision == CPS_MIXED) ? 4 : 8;
+    st->sweep_bytes_per_point = (CPS_FUSED_SWEEPS ? 5 : 4) * vb;
     return status;
 }
 
@@ -441,12 +579,12 @@ template <typename T>
 void precond_standalone(cps_solver *s, const double *rho_dev, double *out_dev)
 {
     Vecs<T> V;
-    T *all[6];
+    T *all[7];
     for (auto &p : all) {
         p = dalloc<T>(s, s->nn);
         launch_fill<T>(s->stream, s->nn, p, T(0));
     }
-    V.c[0] = all[0]; V.c[1] = all[1]; V.c[2] = all[2];
+    V.c[0] = all[0]; V.c[1] = all[1]; V.c[2] = all[2]; V.c[3] = all[6];
     T *rin = all[3], *ps = all[4], *dst = all[5];
     launch_masked_copy<double, T>(s->stream, s->nn, s->type, rho_dev, rin);
     // state: alpha = 0 so that the fused first step computes x1 from rho itself
@@ -552,8 +690,10 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
     s->g = make_geom(nx, ny, nz);
     int rc = CPS_OK;
     try {
-        ck(hipHostMalloc((void **)&s->hst, 2 * sizeof(DevState), hipHostMallocDefault));
-        ck(hipHostMalloc((void **)&s->hscalar, 8 * sizeof(double), hipHostMallocDefault));
+        static_assert(2 * sizeof(DevState) <= PINNED_BLOCK / 2, "state copies fit half a pinned block");
+        void *blk = pinned_get();
+        s->hst = (DevState *)blk;
+        s->hscalar = (double *)((char *)blk + PINNED_BLOCK / 2);
         for (auto &e : s->ev) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         // coordinates: validated on the host (they are small)
         std::vector<double> hx(nx + ny + nz);
@@ -610,10 +750,15 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
             dfree(s, s->irr_node);
             s->irr_node = trimmed;
         }
-        s->skip = dalloc<uint32_t>(s, (size_t)s->g.W * ny * nz);
+        // two words of zero padding: vectorised kernels read skip words in pairs
+        s->skip = dalloc<uint32_t>(s, (size_t)s->g.W * ny * nz + 2);
+        launch_fill<uint32_t>(s->stream, (size_t)s->g.W * ny * nz + 2, s->skip, 0u);
         launch_skipbits(s->stream, s->g, s->type, s->skip);
+        s->irr_bits = dalloc<uint32_t>(s, (size_t)s->g.W * ny * nz);
+        s->irr_wstart = dalloc<int>(s, (size_t)s->g.W * ny * nz);
+        launch_irr_words(s->stream, s->g, s->type, s->irr_node, s->nirr, s->irr_bits, s->irr_wstart);
         // reduction scratch: enough for the largest launch
-        size_t maxblk = (size_t)std::max({s->g.t4.nblk, s->g.t8.nblk, s->g.nflat}) +
+        size_t maxblk = (size_t)std::max({s->g.t4.nblk, s->g.t8.nblk, s->g.tr.nblk, s->g.nflat}) +
                         (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
         s->partials = dalloc<double>(s, 2 * maxblk);
         s->ticket = dalloc<unsigned>(s, 1);
@@ -675,6 +820,7 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
     DevState ds{};
     try {
         s->tev_used = 0;
+        s->sweep_count = 0;
         const int m = s->opt.inner_iters;
         double c1[MAX_INNER], c2[MAX_INNER];
         cheb_coefficients(m, s->opt.lam_lo, s->opt.lam_hi, c1, c2);
@@ -829,7 +975,7 @@ int cps_precond(cps_solver *s, const double *rho, double *phi, int32_t precision
         if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
         double *out = dalloc<double>(s, s->nn);
         to_device(s, s->tmp64, rho, s->nn * sizeof(double));
-        bool timing = s->opt.kernel_timing;
+        const int timing = s->opt.kernel_timing;
         s->opt.kernel_timing = 0;
         if (precision == CPS_FP64) precond_standalone<double>(s, s->tmp64, out);
         else precond_standalone<float>(s, s->tmp64, out);

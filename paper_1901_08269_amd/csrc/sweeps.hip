@@ -370,6 +370,406 @@ __global__ void __launch_bounds__(NT) k_cheb(Geom g, Coef<T> cf, Irr<T> ir, cons
 }
 
 // ---------------------------------------------------------------------------------------
+// Vectorised rows: a wavefront owns a 256-node segment of an x-row, four consecutive nodes
+// per lane, loaded and stored as one 4-vector (rows start at any 4-byte boundary; the
+// hardware splits unaligned vector accesses).  x neighbours come from the adjacent lanes;
+// the two segment ends read theirs from memory.  A lane whose four nodes run past the row
+// end (ragged rows) loads and stores its valid nodes one by one.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct Vec4Of;
+template <>
+struct Vec4Of<float> {
+    typedef float type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct Vec4Of<double> {
+    typedef double type __attribute__((ext_vector_type(4), aligned(8)));
+};
+
+// The lane's nodes of a segment: i0 (first node), nv (valid nodes, <= 0 when none).
+struct Seg {
+    int i0, nv;
+    bool full;
+};
+
+__device__ __forceinline__ Seg seg_of(int nx, int segment, int lane)
+{
+    Seg q;
+    q.i0 = 1 + segment * (4 * TX) + 4 * lane;
+    q.nv = min(4, nx - 1 - q.i0);
+    q.full = q.nv == 4;
+    return q;
+}
+
+template <typename T>
+__device__ __forceinline__ typename Vec4Of<T>::type load4(const T *__restrict__ a, size_t e, const Seg &q)
+{
+    using V = typename Vec4Of<T>::type;
+    if (q.full) return *reinterpret_cast<const V *>(a + e);
+    V v = {T(0), T(0), T(0), T(0)};
+    if (q.nv > 0) v.x = a[e];
+    if (q.nv > 1) v.y = a[e + 1];
+    if (q.nv > 2) v.z = a[e + 2];
+    return v;
+}
+
+// the four row-type bits of nodes i0 .. i0 + 3 (skip words are read in pairs; the array
+// carries two words of padding)
+__device__ __forceinline__ uint32_t skip4(const uint32_t *__restrict__ w, int i0)
+{
+    const uint64_t pair = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+    return (uint32_t)(pair >> (i0 & 31)) & 0xFu;
+}
+
+// Single Chebyshev step on vectorised rows (same arithmetic as the per-node form):
+//   x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 (rho - K x_k) / diag K
+// Each wavefront marches in z through its segment; the operands of plane k + 2 are loaded
+// while plane k is computed (three register sets, loop unrolled by three).  Irregular rows
+// use their Shortley-Weller row in the leading blocks (one thread per row).
+template <typename T, bool PREV0>
+__global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
+                                              const T *__restrict__ xc, const T *__restrict__ xm1,
+                                              const T *__restrict__ rho, T *__restrict__ xn, T c1, T c2,
+                                              const DevState *st)
+{
+    using V = typename Vec4Of<T>::type;
+    if (st && st->done) return;
+    const int lane = threadIdx.x, wv = threadIdx.y;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t plane = (size_t)nx * ny;
+    const int nib = irr_blocks(ir.n, NT);
+    const int b = (int)blockIdx.x - nib;
+    if (b < 0) {
+        const int row = (int)blockIdx.x * NT + lane + wv * TX;
+        if (row >= ir.n) return;
+        const int e = ir.node[row];
+        const T *k7 = ir.k7 + 7 * row;
+        T z0 = xc[e];
+        T kx = k7[0] * z0 + k7[1] * xc[e - 1] + k7[2] * xc[e + 1] + k7[3] * xc[e - nx] + k7[4] * xc[e + nx] +
+               k7[5] * xc[e - plane] + k7[6] * xc[e + plane];
+        T prev = PREV0 ? T(0) : xm1[e];
+        xn[e] = z0 + c1 * (z0 - prev) + c2 * (rho[e] - kx) / k7[0];
+        return;
+    }
+    const Tiling &tl = g.tr;
+    int bs, by, bz;
+    if (!tile_of_block(tl, b, bs, by, bz)) return;
+    const int j = 1 + by * TY + wv;
+    if (j > ny - 2) return;                                   // whole wavefront
+    const Seg q = seg_of(nx, bs, lane);
+    const int k0 = 1 + bz * tl.TZ;
+    const int k1 = min(k0 + tl.TZ, nz - 1);
+    const int ic = q.nv > 0 ? q.i0 : 1;                        // lanes without nodes read valid memory
+    const size_t e0 = (size_t)ic + (size_t)nx * j;
+    T kax[4], kbx[4], kcx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const T *cx = cf.c[0] + 8 * (u < q.nv ? q.i0 + u : 1);
+        kax[u] = cx[5];
+        kbx[u] = cx[6];
+        kcx[u] = cx[7];
+    }
+    const T kay = cf.c[1][8 * j + 5], kby = cf.c[1][8 * j + 6], kcy = cf.c[1][8 * j + 7];
+    // the segment's outer neighbours: node i0 - 1 for lane 0, node i0 + nv for the last lane
+    const bool need_l = lane == 0;
+    const bool need_r = lane == TX - 1 || q.i0 + 4 >= nx - 1;
+    const int ir_off = q.nv > 0 ? q.nv : 0;
+    const size_t wrow = (size_t)j * g.W + (ic >> 5);
+    const size_t wplane = (size_t)ny * g.W;
+
+    struct Pl { V c, s, n, r, p; T l, rr, za, zb, zc; uint32_t sk; };
+    auto fetch = [&](Pl &P, int k) __attribute__((always_inline)) {
+        k = min(k, k1);
+        const size_t e = e0 + (size_t)k * plane;
+        P.c = load4(xc, e, q);
+        P.s = load4(xc, e - nx, q);
+        P.n = load4(xc, e + nx, q);
+        P.r = load4(rho, e, q);
+        if (!PREV0) P.p = load4(xm1, e, q);
+        P.l = need_l ? xc[e - 1] : T(0);
+        P.rr = need_r ? xc[e + ir_off] : T(0);
+        P.sk = skip4(skip + (size_t)k * wplane + wrow, ic);
+        const T *cz = cf.c[2] + 8 * k;
+        P.za = cz[5];
+        P.zb = cz[6];
+        P.zc = cz[7];
+    };
+    auto step = [&](const Pl &M, const Pl &C, const Pl &U, Pl &F, int k) __attribute__((always_inline)) {
+        // x neighbours across lanes (all lanes take part in the shuffles)
+        T left = __shfl_up(C.c.w, 1, TX);
+        T right = __shfl_down(C.c.x, 1, TX);
+        if (need_l) left = C.l;
+        if (need_r) right = C.rr;
+        const T cv[4] = {C.c.x, C.c.y, C.c.z, C.c.w};
+        const T sv[4] = {C.s.x, C.s.y, C.s.z, C.s.w};
+        const T nvv[4] = {C.n.x, C.n.y, C.n.z, C.n.w};
+        const T rv[4] = {C.r.x, C.r.y, C.r.z, C.r.w};
+        const T mv[4] = {M.c.x, M.c.y, M.c.z, M.c.w};
+        const T uv[4] = {U.c.x, U.c.y, U.c.z, U.c.w};
+        T pv[4] = {T(0), T(0), T(0), T(0)};
+        if (!PREV0) { pv[0] = C.p.x; pv[1] = C.p.y; pv[2] = C.p.z; pv[3] = C.p.w; }
+        T out[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T w = (u == 0) ? left : cv[u - 1];
+            const T ea = (u == 3) ? right : ((u + 1 < q.nv) ? cv[u + 1] : right);
+            const T kd = kbx[u] + kby + C.zb;
+            const T kx = kd * cv[u] + kax[u] * w + kcx[u] * ea + kay * sv[u] + kcy * nvv[u] + C.za * mv[u] + C.zc * uv[u];
+            out[u] = cv[u] + c1 * (cv[u] - pv[u]) + c2 * (rv[u] - kx) / kd;
+        }
+        const size_t e = e0 + (size_t)k * plane;
+        if (q.full && C.sk == 0u) {
+            V o = {out[0], out[1], out[2], out[3]};
+            *reinterpret_cast<V *>(xn + e) = o;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < q.nv && !((C.sk >> u) & 1u)) xn[e + u] = out[u];
+        }
+        fetch(F, k + 2);
+    };
+    Pl P0, P1, P2;
+    P2.c = load4(xc, e0 + (size_t)(k0 - 1) * plane, q);
+    fetch(P0, k0);
+    fetch(P1, k0 + 1);
+    for (int k = k0; k < k1; k += 3) {
+        step(P2, P0, P1, P2, k);
+        if (k + 1 >= k1) break;
+        step(P0, P1, P2, P0, k + 1);
+        if (k + 2 >= k1) break;
+        step(P1, P2, P0, P1, k + 2);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Two Chebyshev steps per sweep (temporal blocking):
+//   x_{k+1} = x_k     + c1a (x_k     - x_{k-1}) + c2a (rho - K x_k)     / diag K
+//   x_{k+2} = x_{k+1} + c1b (x_{k+1} - x_k)     + c2b (rho - K x_{k+1}) / diag K
+// A block owns a 64 x 8 column tile (two rows per thread) and marches in z.  x_k is staged
+// with a two-node halo in a four-plane LDS ring; the first step is computed on the tile
+// plus a one-node halo (every node the second step touches) into a three-plane LDS ring,
+// one plane ahead of the second step.  Irregular nodes use their stored Shortley-Weller
+// row, found through the irregular-node bit words; solid and wall nodes stay zero.  Each
+// step's arithmetic is that of k_cheb, so one fused sweep replaces two single sweeps and
+// moves 20 bytes per node (FP32) instead of 32.  Operands of a plane are loaded two planes
+// ahead into one of two register sets (the plane loop is unrolled by two).
+template <typename T, bool PREV0>
+__global__ void __launch_bounds__(NT) k_cheb2(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
+                                              const T *__restrict__ xk, const T *__restrict__ xkm1,
+                                              const T *__restrict__ rho, T *__restrict__ x1o, T *__restrict__ x2o,
+                                              T c1a, T c2a, T c1b, T c2b, const DevState *st)
+{
+    if (st && st->done) return;
+    constexpr int AY = 2 * TY;                                              // tile rows
+    constexpr int EW = TX + 2, EH = AY + 2, NE = EW * EH, NEP = (NE + NT - 1) / NT;   // first-step region
+    constexpr int SW = TX + 4, SH = AY + 4, NS = SW * SH, NLD = (NS + NT - 1) / NT;   // staged x_k region
+    __shared__ T xa[4][SH][SW];
+    __shared__ T xb[3][EH][EW];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ty * TX;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, W = g.W;
+    const size_t plane = (size_t)nx * ny;
+    const size_t wplane = (size_t)ny * W;
+    const Tiling &tl = g.t8;
+    int bx, by, bz;
+    if (!tile_of_block(tl, blockIdx.x, bx, by, bz)) return;
+    const int x0 = 1 + bx * TX, y0 = 1 + by * AY;
+    const int k0 = 1 + bz * tl.TZ;
+    const int k1 = min(k0 + tl.TZ, nz - 1);                 // second-step planes [k0, k1)
+    const T *cz = cf.c[2];
+
+    // staging slots of x_k (outside the grid: zero)
+    int soff[NLD], srow[NLD], scol[NLD];
+    bool sin[NLD], sok[NLD];
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        int idx = tid + q * NT;
+        sin[q] = idx < NS;
+        int r = sin[q] ? idx / SW : 0, c = sin[q] ? idx - r * SW : 0;
+        srow[q] = r;
+        scol[q] = c;
+        int gi = x0 - 2 + c, gj = y0 - 2 + r;
+        sok[q] = sin[q] && gi >= 0 && gi < nx && gj >= 0 && gj < ny;
+        soff[q] = sok[q] ? gi + nx * gj : 0;
+    }
+    // first-step nodes of this thread: the tile and its one-node halo
+    int eoff[NEP], erow[NEP], ecol[NEP], egi[NEP];
+    size_t eword[NEP];
+    bool evalid[NEP], eact[NEP], eown[NEP];
+    T ekax[NEP], ekbx[NEP], ekcx[NEP], ekay[NEP], ekby[NEP], ekcy[NEP];
+#pragma unroll
+    for (int q = 0; q < NEP; ++q) {
+        int idx = tid + q * NT;
+        evalid[q] = idx < NE;
+        int r = evalid[q] ? idx / EW : 0, c = evalid[q] ? idx - r * EW : 0;
+        erow[q] = r;
+        ecol[q] = c;
+        int gi = x0 - 1 + c, gj = y0 - 1 + r;
+        eact[q] = evalid[q] && gi >= 1 && gi <= nx - 2 && gj >= 1 && gj <= ny - 2;   // interior node
+        eown[q] = eact[q] && r >= 1 && r <= AY && c >= 1 && c <= TX;                // inside the tile
+        gi = eact[q] ? gi : 1;
+        gj = eact[q] ? gj : 1;
+        egi[q] = gi;
+        eoff[q] = gi + nx * gj;
+        eword[q] = (size_t)gj * W + (gi >> 5);
+        const T *cx = cf.c[0] + 8 * gi, *cy = cf.c[1] + 8 * gj;
+        ekax[q] = cx[5]; ekbx[q] = cx[6]; ekcx[q] = cx[7];
+        ekay[q] = cy[5]; ekby[q] = cy[6]; ekcy[q] = cy[7];
+    }
+    // second-step nodes of this thread: rows a = ty and b = ty + TY of the tile, column tx
+    const int i = x0 + tx, ja = y0 + ty, jb = ja + TY;
+    const bool iok = i <= nx - 2, aok = iok && ja <= ny - 2, bok = iok && jb <= ny - 2;
+    const int ic = iok ? i : 1, jac = aok ? ja : 1, jbc = bok ? jb : 1;
+    const size_t ea0 = (size_t)ic + (size_t)nx * jac, eb0 = (size_t)ic + (size_t)nx * jbc;
+    const size_t wa0 = (size_t)jac * W + (ic >> 5), wb0 = (size_t)jbc * W + (ic >> 5);
+    const T kax = cf.c[0][8 * ic + 5], kbx = cf.c[0][8 * ic + 6], kcx = cf.c[0][8 * ic + 7];
+    const T kaya = cf.c[1][8 * jac + 5], kbya = cf.c[1][8 * jac + 6], kcya = cf.c[1][8 * jac + 7];
+    const T kayb = cf.c[1][8 * jbc + 5], kbyb = cf.c[1][8 * jbc + 6], kcyb = cf.c[1][8 * jbc + 7];
+
+    struct Set {
+        T stg[NLD];                           // x_k of a plane, to be staged
+        T prev[NEP], r[NEP];                  // x_{k-1} and rho at the first-step nodes
+        uint32_t sk[NEP];                     // their skip words
+        T za, zb, zc;                         // K z coefficients of that plane
+        T ra, rb;                             // rho at the second-step nodes
+        uint32_t ska, skb;                    // their skip words
+        T wa, wb, wc;                         // K z coefficients of that plane
+    };
+    auto clampz = [&](int p) { return min(max(p, 0), nz - 1); };
+    auto stage_load = [&](Set &S, int p) __attribute__((always_inline)) {
+        const size_t kp = (size_t)clampz(p) * plane;
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) S.stg[q] = sok[q] ? xk[(size_t)soff[q] + kp] : T(0);
+    };
+    auto ext_load = [&](Set &S, int p) __attribute__((always_inline)) {
+        p = clampz(p);
+        const size_t kp = (size_t)p * plane, wp = (size_t)p * wplane;
+#pragma unroll
+        for (int q = 0; q < NEP; ++q) {
+            const size_t e = (size_t)eoff[q] + kp;
+            S.prev[q] = PREV0 ? T(0) : xkm1[e];
+            S.r[q] = rho[e];
+            S.sk[q] = skip[wp + eword[q]];
+        }
+        S.za = cz[8 * p + 5];
+        S.zb = cz[8 * p + 6];
+        S.zc = cz[8 * p + 7];
+    };
+    auto int_load = [&](Set &S, int p) __attribute__((always_inline)) {
+        p = clampz(p);
+        const size_t kp = (size_t)p * plane, wp = (size_t)p * wplane;
+        S.ra = rho[ea0 + kp];
+        S.rb = rho[eb0 + kp];
+        S.ska = aok ? skip[wp + wa0] : ~0u;
+        S.skb = bok ? skip[wp + wb0] : ~0u;
+        S.wa = cz[8 * p + 5];
+        S.wb = cz[8 * p + 6];
+        S.wc = cz[8 * p + 7];
+    };
+
+    // first step at plane p on the tile and its halo, into xb[p % 3]
+    auto step1 = [&](const Set &S, int p) __attribute__((always_inline)) {
+        const int s0 = p & 3, sm = (p + 3) & 3, sp = (p + 1) & 3;
+        const bool wallp = p <= 0 || p >= nz - 1;
+        const bool store = p >= k0 && p < k1;
+        const size_t kp = (size_t)p * plane;
+#pragma unroll
+        for (int q = 0; q < NEP; ++q) {
+            if (!evalid[q]) continue;
+            T v = T(0);
+            if (eact[q] && !wallp) {
+                const int r = erow[q] + 1, c = ecol[q] + 1;
+                const T z0 = xa[s0][r][c], xw = xa[s0][r][c - 1], xe = xa[s0][r][c + 1];
+                const T xs = xa[s0][r - 1][c], xn = xa[s0][r + 1][c];
+                const T zm = xa[sm][r][c], zp = xa[sp][r][c];
+                bool solid = false;
+                if (!((S.sk[q] >> (egi[q] & 31)) & 1u)) {
+                    T kd = ekbx[q] + ekby[q] + S.zb;
+                    T kx = kd * z0 + ekax[q] * xw + ekcx[q] * xe + ekay[q] * xs + ekcy[q] * xn + S.za * zm + S.zc * zp;
+                    v = z0 + c1a * (z0 - S.prev[q]) + c2a * (S.r[q] - kx) / kd;
+                } else {
+                    const size_t word = (size_t)p * wplane + eword[q];
+                    if ((ir.bits[word] >> (egi[q] & 31)) & 1u) {
+                        const T *k7 = ir.k7 + 7 * irr_row_of(ir, word, egi[q]);
+                        T kx = k7[0] * z0 + k7[1] * xw + k7[2] * xe + k7[3] * xs + k7[4] * xn + k7[5] * zm + k7[6] * zp;
+                        v = z0 + c1a * (z0 - S.prev[q]) + c2a * (S.r[q] - kx) / k7[0];
+                    } else {
+                        solid = true;
+                    }
+                }
+                if (eown[q] && store && !solid) x1o[(size_t)eoff[q] + kp] = v;
+            }
+            xb[p % 3][erow[q]][ecol[q]] = v;
+        }
+    };
+    // second step at plane q (k0 <= q < k1) for the thread's two tile rows
+    auto step2 = [&](const Set &S, int q) __attribute__((always_inline)) {
+        const int s0 = q % 3, sm = (q + 2) % 3, sp = (q + 1) % 3;
+        const size_t kp = (size_t)q * plane;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bool ok = h ? bok : aok;
+            const uint32_t sk = h ? S.skb : S.ska;
+            if (!ok) continue;
+            const int r = ty + h * TY + 1, c = tx + 1;
+            const T z0 = xb[s0][r][c], xw = xb[s0][r][c - 1], xe = xb[s0][r][c + 1];
+            const T xs = xb[s0][r - 1][c], xn = xb[s0][r + 1][c];
+            const T zm = xb[sm][r][c], zp = xb[sp][r][c];
+            const T xkq = xa[q & 3][r + 1][c + 1];
+            const T rq = h ? S.rb : S.ra;
+            const size_t e = (h ? eb0 : ea0) + kp;
+            if (!((sk >> (i & 31)) & 1u)) {
+                T kd = kbx + (h ? kbyb : kbya) + S.wb;
+                T kx = kd * z0 + kax * xw + kcx * xe + (h ? kayb : kaya) * xs + (h ? kcyb : kcya) * xn + S.wa * zm +
+                       S.wc * zp;
+                x2o[e] = z0 + c1b * (z0 - xkq) + c2b * (rq - kx) / kd;
+            } else {
+                const size_t word = (size_t)q * wplane + (h ? wb0 : wa0);
+                if ((ir.bits[word] >> (i & 31)) & 1u) {
+                    const T *k7 = ir.k7 + 7 * irr_row_of(ir, word, i);
+                    T kx = k7[0] * z0 + k7[1] * xw + k7[2] * xe + k7[3] * xs + k7[4] * xn + k7[5] * zm + k7[6] * zp;
+                    x2o[e] = z0 + c1b * (z0 - xkq) + c2b * (rq - kx) / k7[0];
+                }
+            }
+        }
+    };
+
+    const int p0 = k0 - 1;
+    // planes p0 - 1 and p0 of x_k go straight to LDS; the loop stages p + 1 at plane p
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        if (!sin[q]) continue;
+        xa[(p0 + 3) & 3][srow[q]][scol[q]] = (sok[q] && p0 >= 1) ? xk[(size_t)soff[q] + (size_t)(p0 - 1) * plane] : T(0);
+        xa[p0 & 3][srow[q]][scol[q]] = sok[q] ? xk[(size_t)soff[q] + (size_t)p0 * plane] : T(0);
+    }
+    Set A, B;
+    stage_load(A, p0 + 1);
+    stage_load(B, p0 + 2);
+    ext_load(A, p0);
+    ext_load(B, p0 + 1);
+    A.ra = A.rb = B.ra = B.rb = T(0);
+    A.ska = A.skb = B.ska = B.skb = ~0u;
+    A.wa = A.wb = A.wc = B.wa = B.wb = B.wc = T(0);
+    auto iter = [&](Set &S, int p) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q)
+            if (sin[q]) xa[(p + 1) & 3][srow[q]][scol[q]] = S.stg[q];
+        stage_load(S, p + 3);
+        __syncthreads();
+        step1(S, p);
+        ext_load(S, p + 2);
+        __syncthreads();
+        if (p - 1 >= k0) step2(S, p - 1);
+        int_load(S, p + 1);
+    };
+    for (int p = p0; p <= k1; p += 2) {
+        iter(A, p);
+        if (p + 1 > k1) break;
+        iter(B, p + 1);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // flat, vectorised pointwise kernels: blocks [0, nflat) stride over all nodes in groups of
 // 16 bytes per thread; wall and solid entries are 0 in every vector and stay 0
 // ---------------------------------------------------------------------------------------
@@ -657,11 +1057,24 @@ template <typename T>
 void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
                  double c1, double c2, const DevState *st)
 {
-    dim3 grid(L.g.t4.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
+    dim3 grid(L.g.tr.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
     if (xm1 == nullptr)
-        k_cheb<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st);
+        k_cheb4<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st);
     else
-        k_cheb<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st);
+        k_cheb4<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st);
+}
+
+template <typename T>
+void launch_cheb2(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xk, const T *xkm1, const T *rho,
+                  T *x1, T *x2, double c1a, double c2a, double c1b, double c2b, const DevState *st)
+{
+    dim3 grid(L.g.t8.nblk), blk = tile_block();
+    if (xkm1 == nullptr)
+        k_cheb2<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xk, xkm1, rho, x1, x2, (T)c1a, (T)c2a,
+                                                     (T)c1b, (T)c2b, st);
+    else
+        k_cheb2<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xk, xkm1, rho, x1, x2, (T)c1a, (T)c2a,
+                                                      (T)c1b, (T)c2b, st);
 }
 
 template <typename T>
@@ -734,6 +1147,11 @@ template void launch_cheb<double>(const Launch &, const Coef<double> &, const Ir
                                   const double *, const double *, double *, double, double, const DevState *);
 template void launch_cheb<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
                                  const float *, float *, double, double, const DevState *);
+template void launch_cheb2<double>(const Launch &, const Coef<double> &, const Irr<double> &, const double *,
+                                   const double *, const double *, double *, double *, double, double, double, double,
+                                   const DevState *);
+template void launch_cheb2<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
+                                  const float *, float *, float *, double, double, double, double, const DevState *);
 template void launch_first<double>(int, const Launch &, const Coef<double> &, const Irr<double> &, const double *,
                                    double *, const double *, double *, double, const DevState *);
 template void launch_first<float>(int, const Launch &, const Coef<float> &, const Irr<float> &, const float *, float *,
