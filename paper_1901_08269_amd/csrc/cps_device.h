@@ -25,6 +25,13 @@ constexpr int TY = 4;         // tile rows in y: one wavefront each
 constexpr int NT = TX * TY;   // threads per block
 constexpr int IRR_LANES = 16; // lanes per irregular row in the B pass
 constexpr int NXCD = 8;       // MI355X: 8 XCDs, blocks dispatched round-robin over them
+#ifndef CPS_RPW
+#define CPS_RPW 2
+#endif
+constexpr int RPW = CPS_RPW;  // rows per wavefront in the vectorised Chebyshev sweep
+// Vectors read by the vectorised sweeps carry this many zero elements past the last node:
+// a lane always loads four consecutive elements, also where some lie past the row end.
+constexpr size_t VEC_PAD = 8;
 
 // A tiling of the interior into (tw x ty) columns that march over z-chunks of TZ planes.
 struct Tiling {
@@ -42,6 +49,8 @@ struct Geom {
     Tiling t8;                 // 64 x 8 tiles (two rows per thread): the B apply
     Tiling tr;                 // 256 x 4 tiles: one x-row segment of 256 nodes per wavefront,
                                // four nodes per lane (vectorised Chebyshev sweeps)
+    Tiling tc;                 // 256 x 4 tiles of the fused two-step sweep (one row per
+                               // wavefront; rows of at most 256 interior nodes)
     int nflat;                 // blocks of the flat (vectorised) pointwise kernels
 };
 

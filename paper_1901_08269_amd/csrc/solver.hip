@@ -290,6 +290,9 @@ Tiling make_tiling(int nx, int ny, int nz, int tw, int ty, int target_blocks, in
 #ifndef CPS_ROW_BLOCKS
 #define CPS_ROW_BLOCKS 512
 #endif
+#ifndef CPS_FUSED_BLOCKS
+#define CPS_FUSED_BLOCKS 2048
+#endif
 #ifndef CPS_FLAT_BLOCKS
 #define CPS_FLAT_BLOCKS 4096
 #endif
@@ -301,7 +304,8 @@ Geom make_geom(int nx, int ny, int nz)
     g.W = (nx + 31) / 32;
     g.t4 = make_tiling(nx, ny, nz, TX, 4, CPS_CHEB_BLOCKS, 8);
     g.t8 = make_tiling(nx, ny, nz, TX, 8, CPS_APPLY_BLOCKS, 8);
-    g.tr = make_tiling(nx, ny, nz, 4 * TX, TY, CPS_ROW_BLOCKS, 4);
+    g.tr = make_tiling(nx, ny, nz, 4 * TX, TY * RPW, CPS_ROW_BLOCKS, 4);
+    g.tc = make_tiling(nx, ny, nz, 4 * TX, TY, CPS_FUSED_BLOCKS, 4);
     size_t nn = (size_t)nx * ny * nz;
     g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, CPS_FLAT_BLOCKS);
     return g;
@@ -328,8 +332,8 @@ void alloc_vecs(cps_solver *s, Vecs<T> &V)
     if (V.ready) return;
     T **all[] = {&V.r, &V.r0, &V.p, &V.ph, &V.v, &V.s, &V.sh, &V.t, &V.x, &V.c[0], &V.c[1], &V.c[2], &V.c[3]};
     for (T **p : all) {
-        *p = dalloc<T>(s, s->nn);
-        launch_fill<T>(s->stream, s->nn, *p, T(0));
+        *p = dalloc<T>(s, s->nn + VEC_PAD);
+        launch_fill<T>(s->stream, s->nn + VEC_PAD, *p, T(0));
     }
     V.ready = true;
 }
@@ -355,13 +359,17 @@ hipEvent_t timed_sweep_begin(cps_solver *s)
     return e1;
 }
 
-// Fused two-step sweeps (k_cheb2) for the Chebyshev recursion; 0 runs every step singly.
+// Fused two-step sweeps (k_cheb2w) for the Chebyshev recursion; 0 (the default) runs every
+// step singly.  The fused sweep moves 20 instead of 32 bytes per node for two steps but needs
+// about 220 registers per lane (two wavefronts per SIMD); on MI355X at 256^3 it measured
+// 114 us per pair without bodies against 2 x 47 us for single sweeps, and its in-loop
+// irregular-row lookups cost more with bodies.
 #ifndef CPS_FUSED_SWEEPS
 #define CPS_FUSED_SWEEPS 0
 #endif
 
 // p^ = M p: inner_iters Chebyshev steps.  The first is fused with the vector update `kind`;
-// with fused sweeps the rest run two per sweep (k_cheb2), after one single sweep when their
+// with fused sweeps the rest run two per sweep (k_cheb2w), after one single sweep when their
 // count is odd.
 // Iterate x_j (j < m) lives in V.c[j % 4]: a fused sweep reads x_{k-1}, x_k and writes
 // x_{k+1}, x_{k+2}, four distinct buffers; x_m goes to dst.
@@ -377,7 +385,8 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
     auto buf = [&](int j) { return (j == m) ? dst : V.c[j % 4]; };
     launch_first<T>(kind, L, cf, ir, r, ps, v, buf(1), c2[0], st);
     int k = 1;
-    if (!CPS_FUSED_SWEEPS) {
+    if (!CPS_FUSED_SWEEPS || s->nx - 2 > 4 * TX) {
+        // rows longer than one wavefront segment: single sweeps
         for (; k < m; ++k) {
             hipEvent_t e1 = timed_sweep_begin(s);
             launch_cheb<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), c1[k], c2[k], st);
@@ -476,7 +485,7 @@ int fill_stats(cps_solver *s, cps_stats *st, const DevState &ds, int iters, int 
     }
     // a single sweep reads x_k, x_{k-1}, rho and writes x_{k+1}; a fused sweep also writes x_{k+2}
     const int vb = (s->opt.precision == CPS_MIXED) ? 4 : 8;
-    st->sweep_bytes_per_point = (CPS_FUSED_SWEEPS ? 5 : 4) * vb;
+    st->sweep_bytes_per_point = ((CPS_FUSED_SWEEPS && s->nx - 2 <= 4 * TX) ? 5 : 4) * vb;
     return status;
 }
 
@@ -581,8 +590,8 @@ void precond_standalone(cps_solver *s, const double *rho_dev, double *out_dev)
     Vecs<T> V;
     T *all[7];
     for (auto &p : all) {
-        p = dalloc<T>(s, s->nn);
-        launch_fill<T>(s->stream, s->nn, p, T(0));
+        p = dalloc<T>(s, s->nn + VEC_PAD);
+        launch_fill<T>(s->stream, s->nn + VEC_PAD, p, T(0));
     }
     V.c[0] = all[0]; V.c[1] = all[1]; V.c[2] = all[2]; V.c[3] = all[6];
     T *rin = all[3], *ps = all[4], *dst = all[5];
@@ -758,7 +767,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->irr_wstart = dalloc<int>(s, (size_t)s->g.W * ny * nz);
         launch_irr_words(s->stream, s->g, s->type, s->irr_node, s->nirr, s->irr_bits, s->irr_wstart);
         // reduction scratch: enough for the largest launch
-        size_t maxblk = (size_t)std::max({s->g.t4.nblk, s->g.t8.nblk, s->g.tr.nblk, s->g.nflat}) +
+        size_t maxblk = (size_t)std::max({s->g.t4.nblk, s->g.t8.nblk, s->g.tr.nblk, s->g.tc.nblk, s->g.nflat}) +
                         (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
         s->partials = dalloc<double>(s, 2 * maxblk);
         s->ticket = dalloc<unsigned>(s, 1);

@@ -387,6 +387,19 @@ struct Vec4Of<double> {
     typedef double type __attribute__((ext_vector_type(4), aligned(8)));
 };
 
+// A wave-uniform value moved to a scalar register (it is the same in every lane).
+__device__ __forceinline__ float uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // The lane's nodes of a segment: i0 (first node), nv (valid nodes, <= 0 when none).
 struct Seg {
     int i0, nv;
@@ -402,15 +415,21 @@ __device__ __forceinline__ Seg seg_of(int nx, int segment, int lane)
     return q;
 }
 
+// One 4-vector load for every lane, nodes past the row end zeroed by selects: a branch
+// between a vector and a per-node path would make the compiler wait for all loads in
+// flight at the join.  The last elements of a vector are followed by VEC_PAD zeros, so the
+// four elements always lie inside the allocation.
 template <typename T>
 __device__ __forceinline__ typename Vec4Of<T>::type load4(const T *__restrict__ a, size_t e, const Seg &q)
 {
     using V = typename Vec4Of<T>::type;
-    if (q.full) return *reinterpret_cast<const V *>(a + e);
-    V v = {T(0), T(0), T(0), T(0)};
-    if (q.nv > 0) v.x = a[e];
-    if (q.nv > 1) v.y = a[e + 1];
-    if (q.nv > 2) v.z = a[e + 2];
+    V v = *reinterpret_cast<const V *>(a + e);
+    if (q.nv < 4) {
+        v.x = q.nv > 0 ? v.x : T(0);
+        v.y = q.nv > 1 ? v.y : T(0);
+        v.z = q.nv > 2 ? v.z : T(0);
+        v.w = T(0);
+    }
     return v;
 }
 
@@ -424,9 +443,14 @@ __device__ __forceinline__ uint32_t skip4(const uint32_t *__restrict__ w, int i0
 
 // Single Chebyshev step on vectorised rows (same arithmetic as the per-node form):
 //   x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 (rho - K x_k) / diag K
-// Each wavefront marches in z through its segment; the operands of plane k + 2 are loaded
-// while plane k is computed (three register sets, loop unrolled by three).  Irregular rows
-// use their Shortley-Weller row in the leading blocks (one thread per row).
+// Each wavefront owns RPW consecutive rows of a 256-node segment and marches in z.  At
+// plane k it loads the rows' x_k at plane k + 1 (their upper z neighbours, and the centre
+// of the next plane), the two outer y-neighbour rows, rho and x_{k-1}; the rows' x_k at
+// planes k - 1 and k are carried in registers.  Latency is hidden by occupancy: the sweep
+// is memory-latency bound, so the register budget goes to more wavefronts and more rows
+// per wavefront, not to prefetch.  Wave-uniform y and z coefficients live in scalar
+// registers.  Irregular rows use their Shortley-Weller row in the leading blocks (one thread
+// per row).
 template <typename T, bool PREV0>
 __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
                                               const T *__restrict__ xc, const T *__restrict__ xm1,
@@ -434,6 +458,7 @@ __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, con
                                               const DevState *st)
 {
     using V = typename Vec4Of<T>::type;
+    constexpr int R = RPW;
     if (st && st->done) return;
     const int lane = threadIdx.x, wv = threadIdx.y;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -455,13 +480,12 @@ __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, con
     const Tiling &tl = g.tr;
     int bs, by, bz;
     if (!tile_of_block(tl, b, bs, by, bz)) return;
-    const int j = 1 + by * TY + wv;
-    if (j > ny - 2) return;                                   // whole wavefront
+    const int j0 = 1 + (by * TY + wv) * R;                     // rows j0 .. j0 + R - 1
+    if (j0 > ny - 2) return;                                  // whole wavefront
     const Seg q = seg_of(nx, bs, lane);
     const int k0 = 1 + bz * tl.TZ;
     const int k1 = min(k0 + tl.TZ, nz - 1);
     const int ic = q.nv > 0 ? q.i0 : 1;                        // lanes without nodes read valid memory
-    const size_t e0 = (size_t)ic + (size_t)nx * j;
     T kax[4], kbx[4], kcx[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -470,302 +494,272 @@ __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, con
         kbx[u] = cx[6];
         kcx[u] = cx[7];
     }
-    const T kay = cf.c[1][8 * j + 5], kby = cf.c[1][8 * j + 6], kcy = cf.c[1][8 * j + 7];
+    // rows past ny - 2 read the wall row ny - 1 (zero in every iterate: the right y
+    // neighbour of the last interior row) and are not stored
+    bool rok[R];
+    size_t er[R], wr[R];
+    T kay[R], kby[R], kcy[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = j0 + r;
+        rok[r] = j <= ny - 2;
+        const int jc = rok[r] ? j : ny - 1;
+        er[r] = (size_t)ic + (size_t)nx * jc;
+        wr[r] = (size_t)jc * g.W + (ic >> 5);
+        kay[r] = uniform(cf.c[1][8 * jc + 5]);
+        kby[r] = uniform(cf.c[1][8 * jc + 6]);
+        kcy[r] = uniform(cf.c[1][8 * jc + 7]);
+    }
+    const size_t elo = (size_t)ic + (size_t)nx * (j0 - 1);                  // row j0 - 1 (>= 0)
+    const size_t ehi = (size_t)ic + (size_t)nx * min(j0 + R, ny - 1);       // row j0 + R (<= ny - 1)
     // the segment's outer neighbours: node i0 - 1 for lane 0, node i0 + nv for the last lane
-    const bool need_l = lane == 0;
-    const bool need_r = lane == TX - 1 || q.i0 + 4 >= nx - 1;
+    // (both walls, hence zero in every iterate, when one segment spans the row)
+    const bool one_seg = nx - 2 <= 4 * TX;
+    const bool need_l = lane == 0, need_r = lane == TX - 1 || q.i0 + 4 >= nx - 1;
     const int ir_off = q.nv > 0 ? q.nv : 0;
-    const size_t wrow = (size_t)j * g.W + (ic >> 5);
     const size_t wplane = (size_t)ny * g.W;
 
-    struct Pl { V c, s, n, r, p; T l, rr, za, zb, zc; uint32_t sk; };
-    auto fetch = [&](Pl &P, int k) __attribute__((always_inline)) {
-        k = min(k, k1);
-        const size_t e = e0 + (size_t)k * plane;
-        P.c = load4(xc, e, q);
-        P.s = load4(xc, e - nx, q);
-        P.n = load4(xc, e + nx, q);
-        P.r = load4(rho, e, q);
-        if (!PREV0) P.p = load4(xm1, e, q);
-        P.l = need_l ? xc[e - 1] : T(0);
-        P.rr = need_r ? xc[e + ir_off] : T(0);
-        P.sk = skip4(skip + (size_t)k * wplane + wrow, ic);
+    V cm[R], c0[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        cm[r] = load4(xc, er[r] + (size_t)(k0 - 1) * plane, q);
+        c0[r] = load4(xc, er[r] + (size_t)k0 * plane, q);
+    }
+    for (int k = k0; k < k1; ++k) {
+        const size_t kp = (size_t)k * plane, kn = kp + plane;
+        V cp[R], rv4[R], pv4[R];
+        uint32_t sk[R];
+        T lft[R], rgt[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cp[r] = load4(xc, er[r] + kn, q);
+            rv4[r] = load4(rho, er[r] + kp, q);
+            if (!PREV0) pv4[r] = load4(xm1, er[r] + kp, q);
+            sk[r] = skip4(skip + (size_t)k * wplane + wr[r], ic);
+            lft[r] = (!one_seg && need_l) ? xc[er[r] + kp - 1] : T(0);
+            rgt[r] = (!one_seg && need_r) ? xc[er[r] + kp + ir_off] : T(0);
+        }
+        const V ylo = load4(xc, elo + kp, q), yhi = load4(xc, ehi + kp, q);
         const T *cz = cf.c[2] + 8 * k;
-        P.za = cz[5];
-        P.zb = cz[6];
-        P.zc = cz[7];
-    };
-    auto step = [&](const Pl &M, const Pl &C, const Pl &U, Pl &F, int k) __attribute__((always_inline)) {
-        // x neighbours across lanes (all lanes take part in the shuffles)
-        T left = __shfl_up(C.c.w, 1, TX);
-        T right = __shfl_down(C.c.x, 1, TX);
-        if (need_l) left = C.l;
-        if (need_r) right = C.rr;
-        const T cv[4] = {C.c.x, C.c.y, C.c.z, C.c.w};
-        const T sv[4] = {C.s.x, C.s.y, C.s.z, C.s.w};
-        const T nvv[4] = {C.n.x, C.n.y, C.n.z, C.n.w};
-        const T rv[4] = {C.r.x, C.r.y, C.r.z, C.r.w};
-        const T mv[4] = {M.c.x, M.c.y, M.c.z, M.c.w};
-        const T uv[4] = {U.c.x, U.c.y, U.c.z, U.c.w};
-        T pv[4] = {T(0), T(0), T(0), T(0)};
-        if (!PREV0) { pv[0] = C.p.x; pv[1] = C.p.y; pv[2] = C.p.z; pv[3] = C.p.w; }
-        T out[4];
+        const T za = uniform(cz[5]), zb = uniform(cz[6]), zcc = uniform(cz[7]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const T w = (u == 0) ? left : cv[u - 1];
-            const T ea = (u == 3) ? right : ((u + 1 < q.nv) ? cv[u + 1] : right);
-            const T kd = kbx[u] + kby + C.zb;
-            const T kx = kd * cv[u] + kax[u] * w + kcx[u] * ea + kay * sv[u] + kcy * nvv[u] + C.za * mv[u] + C.zc * uv[u];
-            out[u] = cv[u] + c1 * (cv[u] - pv[u]) + c2 * (rv[u] - kx) / kd;
-        }
-        const size_t e = e0 + (size_t)k * plane;
-        if (q.full && C.sk == 0u) {
-            V o = {out[0], out[1], out[2], out[3]};
-            *reinterpret_cast<V *>(xn + e) = o;
-        } else {
+        for (int r = 0; r < R; ++r) {
+            const V &s4 = (r == 0) ? ylo : c0[r - 1];
+            const V &n4 = (r == R - 1) ? yhi : c0[r + 1];
+            const T cv[4] = {c0[r].x, c0[r].y, c0[r].z, c0[r].w};
+            T left = __shfl_up(cv[3], 1, TX);
+            T right = __shfl_down(cv[0], 1, TX);
+            if (need_l) left = lft[r];
+            if (need_r) right = rgt[r];
+            const T sv[4] = {s4.x, s4.y, s4.z, s4.w};
+            const T nvv[4] = {n4.x, n4.y, n4.z, n4.w};
+            const T mv[4] = {cm[r].x, cm[r].y, cm[r].z, cm[r].w};
+            const T uv[4] = {cp[r].x, cp[r].y, cp[r].z, cp[r].w};
+            const T rvv[4] = {rv4[r].x, rv4[r].y, rv4[r].z, rv4[r].w};
+            T pv[4] = {T(0), T(0), T(0), T(0)};
+            if (!PREV0) { pv[0] = pv4[r].x; pv[1] = pv4[r].y; pv[2] = pv4[r].z; pv[3] = pv4[r].w; }
+            T out[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (u < q.nv && !((C.sk >> u) & 1u)) xn[e + u] = out[u];
+            for (int u = 0; u < 4; ++u) {
+                const T w = (u == 0) ? left : cv[u - 1];
+                const T ea = (u + 1 < q.nv) ? cv[u + 1] : right;
+                const T kd = kbx[u] + kby[r] + zb;
+                const T kx = kd * cv[u] + kax[u] * w + kcx[u] * ea + kay[r] * sv[u] + kcy[r] * nvv[u] + za * mv[u] +
+                             zcc * uv[u];
+                out[u] = cv[u] + c1 * (cv[u] - pv[u]) + c2 * (rvv[u] - kx) / kd;
+            }
+            if (rok[r]) {
+                const size_t e = er[r] + kp;
+                if (q.full && sk[r] == 0u) {
+                    V o = {out[0], out[1], out[2], out[3]};
+                    *reinterpret_cast<V *>(xn + e) = o;
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (u < q.nv && !((sk[r] >> u) & 1u)) xn[e + u] = out[u];
+                }
+            }
         }
-        fetch(F, k + 2);
-    };
-    Pl P0, P1, P2;
-    P2.c = load4(xc, e0 + (size_t)(k0 - 1) * plane, q);
-    fetch(P0, k0);
-    fetch(P1, k0 + 1);
-    for (int k = k0; k < k1; k += 3) {
-        step(P2, P0, P1, P2, k);
-        if (k + 1 >= k1) break;
-        step(P0, P1, P2, P0, k + 1);
-        if (k + 2 >= k1) break;
-        step(P1, P2, P0, P1, k + 2);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cm[r] = c0[r];
+            c0[r] = cp[r];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// Two Chebyshev steps per sweep (temporal blocking):
-//   x_{k+1} = x_k     + c1a (x_k     - x_{k-1}) + c2a (rho - K x_k)     / diag K
-//   x_{k+2} = x_{k+1} + c1b (x_{k+1} - x_k)     + c2b (rho - K x_{k+1}) / diag K
-// A block owns a 64 x 8 column tile (two rows per thread) and marches in z.  x_k is staged
-// with a two-node halo in a four-plane LDS ring; the first step is computed on the tile
-// plus a one-node halo (every node the second step touches) into a three-plane LDS ring,
-// one plane ahead of the second step.  Irregular nodes use their stored Shortley-Weller
-// row, found through the irregular-node bit words; solid and wall nodes stay zero.  Each
-// step's arithmetic is that of k_cheb, so one fused sweep replaces two single sweeps and
-// moves 20 bytes per node (FP32) instead of 32.  Operands of a plane are loaded two planes
-// ahead into one of two register sets (the plane loop is unrolled by two).
+// Two Chebyshev steps per sweep with independent wavefronts (no LDS, no barriers).
+// For rows of at most 256 interior nodes a wavefront owns one whole x-row j (four nodes per
+// lane; the x neighbours at both ends are walls, zero in every iterate) and marches in z:
+// at plane p it takes the first step on rows j - 1, j, j + 1 (its row and the two rows the
+// second step needs as y neighbours) and the second step on row j at plane p - 1, all in
+// registers.  The rows j +- 1 are recomputed by the neighbouring wavefronts; their loads hit
+// L2, while HBM sees x_k, x_{k-1}, rho once and two outputs: 20 bytes per node (FP32) for
+// two steps instead of 32.  Latency is hidden by occupancy, as in k_cheb4.  Irregular nodes
+// take their stored Shortley-Weller row (through the irregular bit words); solid nodes
+// stay zero.  Each step's arithmetic is that of k_cheb4.
+#ifdef CPS_CHEB2W_WAVES
+#define CHEB2W_ATTR __attribute__((amdgpu_waves_per_eu(CPS_CHEB2W_WAVES)))
+#else
+#define CHEB2W_ATTR
+#endif
 template <typename T, bool PREV0>
-__global__ void __launch_bounds__(NT) k_cheb2(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
-                                              const T *__restrict__ xk, const T *__restrict__ xkm1,
-                                              const T *__restrict__ rho, T *__restrict__ x1o, T *__restrict__ x2o,
-                                              T c1a, T c2a, T c1b, T c2b, const DevState *st)
+__global__ void __launch_bounds__(NT) CHEB2W_ATTR k_cheb2w(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
+                                               const T *__restrict__ xk, const T *__restrict__ xkm1,
+                                               const T *__restrict__ rho, T *__restrict__ x1o, T *__restrict__ x2o,
+                                               T c1a, T c2a, T c1b, T c2b, const DevState *st)
 {
+    using V = typename Vec4Of<T>::type;
     if (st && st->done) return;
-    constexpr int AY = 2 * TY;                                              // tile rows
-    constexpr int EW = TX + 2, EH = AY + 2, NE = EW * EH, NEP = (NE + NT - 1) / NT;   // first-step region
-    constexpr int SW = TX + 4, SH = AY + 4, NS = SW * SH, NLD = (NS + NT - 1) / NT;   // staged x_k region
-    __shared__ T xa[4][SH][SW];
-    __shared__ T xb[3][EH][EW];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ty * TX;
-    const int nx = g.nx, ny = g.ny, nz = g.nz, W = g.W;
+    const int lane = threadIdx.x, wv = threadIdx.y;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
     const size_t plane = (size_t)nx * ny;
-    const size_t wplane = (size_t)ny * W;
-    const Tiling &tl = g.t8;
-    int bx, by, bz;
-    if (!tile_of_block(tl, blockIdx.x, bx, by, bz)) return;
-    const int x0 = 1 + bx * TX, y0 = 1 + by * AY;
+    const size_t wplane = (size_t)ny * g.W;
+    const Tiling &tl = g.tc;
+    int bs, by, bz;
+    if (!tile_of_block(tl, blockIdx.x, bs, by, bz)) return;
+    const int j = 1 + by * TY + wv;
+    if (j > ny - 2) return;                                   // whole wavefront
     const int k0 = 1 + bz * tl.TZ;
-    const int k1 = min(k0 + tl.TZ, nz - 1);                 // second-step planes [k0, k1)
-    const T *cz = cf.c[2];
-
-    // staging slots of x_k (outside the grid: zero)
-    int soff[NLD], srow[NLD], scol[NLD];
-    bool sin[NLD], sok[NLD];
+    const int k1 = min(k0 + tl.TZ, nz - 1);                   // second-step planes [k0, k1)
+    const Seg q = seg_of(nx, 0, lane);
+    const int ic = q.nv > 0 ? q.i0 : 1;
+    const bool last = lane == TX - 1 || q.i0 + 4 >= nx - 1;
+    T kax[4], kbx[4], kcx[4];
 #pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-        int idx = tid + q * NT;
-        sin[q] = idx < NS;
-        int r = sin[q] ? idx / SW : 0, c = sin[q] ? idx - r * SW : 0;
-        srow[q] = r;
-        scol[q] = c;
-        int gi = x0 - 2 + c, gj = y0 - 2 + r;
-        sok[q] = sin[q] && gi >= 0 && gi < nx && gj >= 0 && gj < ny;
-        soff[q] = sok[q] ? gi + nx * gj : 0;
+    for (int u = 0; u < 4; ++u) {
+        const T *cx = cf.c[0] + 8 * (u < q.nv ? q.i0 + u : 1);
+        kax[u] = cx[5];
+        kbx[u] = cx[6];
+        kcx[u] = cx[7];
     }
-    // first-step nodes of this thread: the tile and its one-node halo
-    int eoff[NEP], erow[NEP], ecol[NEP], egi[NEP];
-    size_t eword[NEP];
-    bool evalid[NEP], eact[NEP], eown[NEP];
-    T ekax[NEP], ekbx[NEP], ekcx[NEP], ekay[NEP], ekby[NEP], ekcy[NEP];
+    // rows j - 1, j, j + 1 (r = 0, 1, 2) and the outer y neighbours j - 2, j + 2
+    bool act[3];
+    size_t er[3], wr[3];
+    T kay[3], kby[3], kcy[3];
 #pragma unroll
-    for (int q = 0; q < NEP; ++q) {
-        int idx = tid + q * NT;
-        evalid[q] = idx < NE;
-        int r = evalid[q] ? idx / EW : 0, c = evalid[q] ? idx - r * EW : 0;
-        erow[q] = r;
-        ecol[q] = c;
-        int gi = x0 - 1 + c, gj = y0 - 1 + r;
-        eact[q] = evalid[q] && gi >= 1 && gi <= nx - 2 && gj >= 1 && gj <= ny - 2;   // interior node
-        eown[q] = eact[q] && r >= 1 && r <= AY && c >= 1 && c <= TX;                // inside the tile
-        gi = eact[q] ? gi : 1;
-        gj = eact[q] ? gj : 1;
-        egi[q] = gi;
-        eoff[q] = gi + nx * gj;
-        eword[q] = (size_t)gj * W + (gi >> 5);
-        const T *cx = cf.c[0] + 8 * gi, *cy = cf.c[1] + 8 * gj;
-        ekax[q] = cx[5]; ekbx[q] = cx[6]; ekcx[q] = cx[7];
-        ekay[q] = cy[5]; ekby[q] = cy[6]; ekcy[q] = cy[7];
+    for (int r = 0; r < 3; ++r) {
+        // rows j - 1 and j + 1 lie inside the grid (0 .. ny - 1); a wall row is loaded as it
+        // is (zero in every iterate) and gets no first step
+        const int jj = j - 1 + r;
+        act[r] = jj >= 1 && jj <= ny - 2;
+        er[r] = (size_t)ic + (size_t)nx * jj;
+        wr[r] = (size_t)jj * g.W + (ic >> 5);
+        kay[r] = uniform(cf.c[1][8 * jj + 5]);
+        kby[r] = uniform(cf.c[1][8 * jj + 6]);
+        kcy[r] = uniform(cf.c[1][8 * jj + 7]);
     }
-    // second-step nodes of this thread: rows a = ty and b = ty + TY of the tile, column tx
-    const int i = x0 + tx, ja = y0 + ty, jb = ja + TY;
-    const bool iok = i <= nx - 2, aok = iok && ja <= ny - 2, bok = iok && jb <= ny - 2;
-    const int ic = iok ? i : 1, jac = aok ? ja : 1, jbc = bok ? jb : 1;
-    const size_t ea0 = (size_t)ic + (size_t)nx * jac, eb0 = (size_t)ic + (size_t)nx * jbc;
-    const size_t wa0 = (size_t)jac * W + (ic >> 5), wb0 = (size_t)jbc * W + (ic >> 5);
-    const T kax = cf.c[0][8 * ic + 5], kbx = cf.c[0][8 * ic + 6], kcx = cf.c[0][8 * ic + 7];
-    const T kaya = cf.c[1][8 * jac + 5], kbya = cf.c[1][8 * jac + 6], kcya = cf.c[1][8 * jac + 7];
-    const T kayb = cf.c[1][8 * jbc + 5], kbyb = cf.c[1][8 * jbc + 6], kcyb = cf.c[1][8 * jbc + 7];
+    const size_t em2 = (size_t)ic + (size_t)nx * max(j - 2, 0), ep2 = (size_t)ic + (size_t)nx * min(j + 2, ny - 1);
 
-    struct Set {
-        T stg[NLD];                           // x_k of a plane, to be staged
-        T prev[NEP], r[NEP];                  // x_{k-1} and rho at the first-step nodes
-        uint32_t sk[NEP];                     // their skip words
-        T za, zb, zc;                         // K z coefficients of that plane
-        T ra, rb;                             // rho at the second-step nodes
-        uint32_t ska, skb;                    // their skip words
-        T wa, wb, wc;                         // K z coefficients of that plane
-    };
-    auto clampz = [&](int p) { return min(max(p, 0), nz - 1); };
-    auto stage_load = [&](Set &S, int p) __attribute__((always_inline)) {
-        const size_t kp = (size_t)clampz(p) * plane;
+    auto unpack = [](const V &v, T (&a)[4]) __attribute__((always_inline)) { a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w; };
+    // one Chebyshev step on the lane's four nodes of row jj at plane k
+    auto cheb4 = [&](const V &c4, const V &s4, const V &n4, const V &m4, const V &u4, const V &p4, const V &r4,
+                     uint32_t sk, T ky0, T ky1, T ky2, T z0, T z1, T z2, int k, int jj, T cc1, T cc2,
+                     T (&out)[4]) __attribute__((always_inline)) {
+        T cv[4], sv[4], nv[4], mv[4], uv[4], pv[4], rv[4];
+        unpack(c4, cv); unpack(s4, sv); unpack(n4, nv); unpack(m4, mv); unpack(u4, uv); unpack(p4, pv); unpack(r4, rv);
+        T left = __shfl_up(cv[3], 1, TX), right = __shfl_down(cv[0], 1, TX);
+        if (lane == 0) left = T(0);
+        if (last) right = T(0);
 #pragma unroll
-        for (int q = 0; q < NLD; ++q) S.stg[q] = sok[q] ? xk[(size_t)soff[q] + kp] : T(0);
-    };
-    auto ext_load = [&](Set &S, int p) __attribute__((always_inline)) {
-        p = clampz(p);
-        const size_t kp = (size_t)p * plane, wp = (size_t)p * wplane;
-#pragma unroll
-        for (int q = 0; q < NEP; ++q) {
-            const size_t e = (size_t)eoff[q] + kp;
-            S.prev[q] = PREV0 ? T(0) : xkm1[e];
-            S.r[q] = rho[e];
-            S.sk[q] = skip[wp + eword[q]];
+        for (int u = 0; u < 4; ++u) {
+            const T w = (u == 0) ? left : cv[u - 1];
+            const T ea = (u + 1 < q.nv) ? cv[u + 1] : right;
+            const T kd = kbx[u] + ky1 + z1;
+            const T kx = kd * cv[u] + kax[u] * w + kcx[u] * ea + ky0 * sv[u] + ky2 * nv[u] + z0 * mv[u] + z2 * uv[u];
+            out[u] = cv[u] + cc1 * (cv[u] - pv[u]) + cc2 * (rv[u] - kx) / kd;
         }
-        S.za = cz[8 * p + 5];
-        S.zb = cz[8 * p + 6];
-        S.zc = cz[8 * p + 7];
-    };
-    auto int_load = [&](Set &S, int p) __attribute__((always_inline)) {
-        p = clampz(p);
-        const size_t kp = (size_t)p * plane, wp = (size_t)p * wplane;
-        S.ra = rho[ea0 + kp];
-        S.rb = rho[eb0 + kp];
-        S.ska = aok ? skip[wp + wa0] : ~0u;
-        S.skb = bok ? skip[wp + wb0] : ~0u;
-        S.wa = cz[8 * p + 5];
-        S.wb = cz[8 * p + 6];
-        S.wc = cz[8 * p + 7];
-    };
-
-    // first step at plane p on the tile and its halo, into xb[p % 3]
-    auto step1 = [&](const Set &S, int p) __attribute__((always_inline)) {
-        const int s0 = p & 3, sm = (p + 3) & 3, sp = (p + 1) & 3;
-        const bool wallp = p <= 0 || p >= nz - 1;
-        const bool store = p >= k0 && p < k1;
-        const size_t kp = (size_t)p * plane;
+        if (sk != 0u) {
 #pragma unroll
-        for (int q = 0; q < NEP; ++q) {
-            if (!evalid[q]) continue;
-            T v = T(0);
-            if (eact[q] && !wallp) {
-                const int r = erow[q] + 1, c = ecol[q] + 1;
-                const T z0 = xa[s0][r][c], xw = xa[s0][r][c - 1], xe = xa[s0][r][c + 1];
-                const T xs = xa[s0][r - 1][c], xn = xa[s0][r + 1][c];
-                const T zm = xa[sm][r][c], zp = xa[sp][r][c];
-                bool solid = false;
-                if (!((S.sk[q] >> (egi[q] & 31)) & 1u)) {
-                    T kd = ekbx[q] + ekby[q] + S.zb;
-                    T kx = kd * z0 + ekax[q] * xw + ekcx[q] * xe + ekay[q] * xs + ekcy[q] * xn + S.za * zm + S.zc * zp;
-                    v = z0 + c1a * (z0 - S.prev[q]) + c2a * (S.r[q] - kx) / kd;
-                } else {
-                    const size_t word = (size_t)p * wplane + eword[q];
-                    if ((ir.bits[word] >> (egi[q] & 31)) & 1u) {
-                        const T *k7 = ir.k7 + 7 * irr_row_of(ir, word, egi[q]);
-                        T kx = k7[0] * z0 + k7[1] * xw + k7[2] * xe + k7[3] * xs + k7[4] * xn + k7[5] * zm + k7[6] * zp;
-                        v = z0 + c1a * (z0 - S.prev[q]) + c2a * (S.r[q] - kx) / k7[0];
-                    } else {
-                        solid = true;
-                    }
-                }
-                if (eown[q] && store && !solid) x1o[(size_t)eoff[q] + kp] = v;
-            }
-            xb[p % 3][erow[q]][ecol[q]] = v;
-        }
-    };
-    // second step at plane q (k0 <= q < k1) for the thread's two tile rows
-    auto step2 = [&](const Set &S, int q) __attribute__((always_inline)) {
-        const int s0 = q % 3, sm = (q + 2) % 3, sp = (q + 1) % 3;
-        const size_t kp = (size_t)q * plane;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const bool ok = h ? bok : aok;
-            const uint32_t sk = h ? S.skb : S.ska;
-            if (!ok) continue;
-            const int r = ty + h * TY + 1, c = tx + 1;
-            const T z0 = xb[s0][r][c], xw = xb[s0][r][c - 1], xe = xb[s0][r][c + 1];
-            const T xs = xb[s0][r - 1][c], xn = xb[s0][r + 1][c];
-            const T zm = xb[sm][r][c], zp = xb[sp][r][c];
-            const T xkq = xa[q & 3][r + 1][c + 1];
-            const T rq = h ? S.rb : S.ra;
-            const size_t e = (h ? eb0 : ea0) + kp;
-            if (!((sk >> (i & 31)) & 1u)) {
-                T kd = kbx + (h ? kbyb : kbya) + S.wb;
-                T kx = kd * z0 + kax * xw + kcx * xe + (h ? kayb : kaya) * xs + (h ? kcyb : kcya) * xn + S.wa * zm +
-                       S.wc * zp;
-                x2o[e] = z0 + c1b * (z0 - xkq) + c2b * (rq - kx) / kd;
-            } else {
-                const size_t word = (size_t)q * wplane + (h ? wb0 : wa0);
+            for (int u = 0; u < 4; ++u) {
+                if (!((sk >> u) & 1u)) continue;
+                out[u] = T(0);
+                const int i = q.i0 + u;
+                const size_t word = ((size_t)k * ny + jj) * g.W + (i >> 5);
                 if ((ir.bits[word] >> (i & 31)) & 1u) {
                     const T *k7 = ir.k7 + 7 * irr_row_of(ir, word, i);
-                    T kx = k7[0] * z0 + k7[1] * xw + k7[2] * xe + k7[3] * xs + k7[4] * xn + k7[5] * zm + k7[6] * zp;
-                    x2o[e] = z0 + c1b * (z0 - xkq) + c2b * (rq - kx) / k7[0];
+                    const T w = (u == 0) ? left : cv[u - 1];
+                    const T ea = (u + 1 < q.nv) ? cv[u + 1] : right;
+                    const T kx = k7[0] * cv[u] + k7[1] * w + k7[2] * ea + k7[3] * sv[u] + k7[4] * nv[u] + k7[5] * mv[u] +
+                                 k7[6] * uv[u];
+                    out[u] = cv[u] + cc1 * (cv[u] - pv[u]) + cc2 * (rv[u] - kx) / k7[0];
                 }
             }
         }
     };
-
-    const int p0 = k0 - 1;
-    // planes p0 - 1 and p0 of x_k go straight to LDS; the loop stages p + 1 at plane p
+    auto store4 = [&](T *dst, size_t e, const T (&out)[4], uint32_t sk) __attribute__((always_inline)) {
+        if (q.full && sk == 0u) {
+            V o = {out[0], out[1], out[2], out[3]};
+            *reinterpret_cast<V *>(dst + e) = o;
+        } else {
+            // regular and irregular nodes; solid nodes hold zero already
 #pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-        if (!sin[q]) continue;
-        xa[(p0 + 3) & 3][srow[q]][scol[q]] = (sok[q] && p0 >= 1) ? xk[(size_t)soff[q] + (size_t)(p0 - 1) * plane] : T(0);
-        xa[p0 & 3][srow[q]][scol[q]] = sok[q] ? xk[(size_t)soff[q] + (size_t)p0 * plane] : T(0);
-    }
-    Set A, B;
-    stage_load(A, p0 + 1);
-    stage_load(B, p0 + 2);
-    ext_load(A, p0);
-    ext_load(B, p0 + 1);
-    A.ra = A.rb = B.ra = B.rb = T(0);
-    A.ska = A.skb = B.ska = B.skb = ~0u;
-    A.wa = A.wb = A.wc = B.wa = B.wb = B.wc = T(0);
-    auto iter = [&](Set &S, int p) __attribute__((always_inline)) {
-#pragma unroll
-        for (int q = 0; q < NLD; ++q)
-            if (sin[q]) xa[(p + 1) & 3][srow[q]][scol[q]] = S.stg[q];
-        stage_load(S, p + 3);
-        __syncthreads();
-        step1(S, p);
-        ext_load(S, p + 2);
-        __syncthreads();
-        if (p - 1 >= k0) step2(S, p - 1);
-        int_load(S, p + 1);
+            for (int u = 0; u < 4; ++u)
+                if (u < q.nv) dst[e + u] = out[u];
+        }
     };
-    for (int p = p0; p <= k1; p += 2) {
-        iter(A, p);
-        if (p + 1 > k1) break;
-        iter(B, p + 1);
+    auto pack = [](const T (&a)[4]) __attribute__((always_inline)) { V v = {a[0], a[1], a[2], a[3]}; return v; };
+
+    const V zero4 = {T(0), T(0), T(0), T(0)};
+    int p = k0 - 1;
+    const size_t kpm = (size_t)max(p - 1, 0) * plane, kp0 = (size_t)p * plane;
+    V cm[3], c0[3];                                           // x_k rows at planes p - 1 and p
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        cm[r] = load4(xk, er[r] + kpm, q);
+        c0[r] = load4(xk, er[r] + kp0, q);
+    }
+    V x1mm = zero4, x1c[3] = {zero4, zero4, zero4};           // first-step rows: plane p - 2 (row j), p - 1
+    V rho_q = zero4;                                          // rho, skip, z coefficients at plane p - 1 (row j)
+    uint32_t sk_q = 0u;
+    T zq0 = T(0), zq1 = T(0), zq2 = T(0);
+    for (; p <= k1; ++p) {
+        const int pn = min(p + 1, nz - 1);
+        const size_t kp = (size_t)p * plane, kn = (size_t)pn * plane;
+        V cp[3], pr[3], rr[3];
+        uint32_t sk[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            cp[r] = load4(xk, er[r] + kn, q);
+            rr[r] = load4(rho, er[r] + kp, q);
+            pr[r] = PREV0 ? zero4 : load4(xkm1, er[r] + kp, q);
+            sk[r] = skip4(skip + (size_t)p * wplane + wr[r], ic);
+        }
+        const V ym2 = load4(xk, em2 + kp, q), yp2 = load4(xk, ep2 + kp, q);
+        const T *cz = cf.c[2] + 8 * p;
+        const T z0 = uniform(cz[5]), z1 = uniform(cz[6]), z2 = uniform(cz[7]);
+        // first step at plane p on rows j - 1, j, j + 1
+        const bool wallp = p <= 0 || p >= nz - 1;
+        V x1n[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            T out[4] = {T(0), T(0), T(0), T(0)};
+            const V &s4 = (r == 0) ? ym2 : c0[r - 1];
+            const V &n4 = (r == 2) ? yp2 : c0[r + 1];
+            if (act[r] && !wallp)
+                cheb4(c0[r], s4, n4, cm[r], cp[r], pr[r], rr[r], sk[r], kay[r], kby[r], kcy[r], z0, z1, z2, p, j - 1 + r,
+                      c1a, c2a, out);
+            x1n[r] = pack(out);
+            if (r == 1 && p >= k0 && p < k1) store4(x1o, er[1] + kp, out, sk[1]);
+        }
+        // second step at plane p - 1 on row j
+        if (p - 1 >= k0) {
+            T out[4];
+            cheb4(x1c[1], x1c[0], x1c[2], x1mm, x1n[1], cm[1], rho_q, sk_q, kay[1], kby[1], kcy[1], zq0, zq1, zq2, p - 1,
+                  j, c1b, c2b, out);
+            store4(x2o, er[1] + (size_t)(p - 1) * plane, out, sk_q);
+        }
+        x1mm = x1c[1];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            x1c[r] = x1n[r];
+            cm[r] = c0[r];
+            c0[r] = cp[r];
+        }
+        rho_q = rr[1];
+        sk_q = sk[1];
+        zq0 = z0; zq1 = z1; zq2 = z2;
     }
 }
 
@@ -1068,13 +1062,13 @@ template <typename T>
 void launch_cheb2(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xk, const T *xkm1, const T *rho,
                   T *x1, T *x2, double c1a, double c2a, double c1b, double c2b, const DevState *st)
 {
-    dim3 grid(L.g.t8.nblk), blk = tile_block();
+    dim3 grid(L.g.tc.nblk), blk = tile_block();
     if (xkm1 == nullptr)
-        k_cheb2<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xk, xkm1, rho, x1, x2, (T)c1a, (T)c2a,
-                                                     (T)c1b, (T)c2b, st);
-    else
-        k_cheb2<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xk, xkm1, rho, x1, x2, (T)c1a, (T)c2a,
+        k_cheb2w<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xk, xkm1, rho, x1, x2, (T)c1a, (T)c2a,
                                                       (T)c1b, (T)c2b, st);
+    else
+        k_cheb2w<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xk, xkm1, rho, x1, x2, (T)c1a, (T)c2a,
+                                                       (T)c1b, (T)c2b, st);
 }
 
 template <typename T>
