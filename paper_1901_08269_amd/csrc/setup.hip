@@ -368,26 +368,38 @@ __device__ bool small_solve(int m, double *A, double *rhs, double *w)
     return true;
 }
 
-struct RowAcc {
-    double val[NSLOT];
-    uint32_t used[(NSLOT + 31) / 32];
-    double rhs;
+// The contributions of one window, in the order they are made: (slot, value) for a
+// coefficient on an unknown, (-1, value) for a term moved to the right-hand side.  A window
+// makes at most 2 runs x 5 points (F-S-F) or 6 points (one run); 12 leaves room.
+constexpr int WIN_CAP = 12;
+struct WinList {
+    double v[WIN_CAP];
+    int16_t slot[WIN_CAP];
+    int n;
+    __device__ __forceinline__ void add(int sl, double c)
+    {
+        if (n < WIN_CAP) {
+            v[n] = c;
+            slot[n] = (int16_t)sl;
+        }
+        ++n;
+    }
+    __device__ __forceinline__ void rhs_add(double c) { add(-1, c); }
 };
 
 // coefficient c on the node at offset o (from the row node): unknown -> slot; wall -> RHS
-__device__ __forceinline__ void put(const Ctx &C, RowAcc &R, size_t rownode, const int o[3], double c)
+__device__ __forceinline__ void put(const Ctx &C, WinList &R, size_t rownode, const int o[3], double c)
 {
     size_t node = rownode + (ptrdiff_t)o[0] * (ptrdiff_t)C.stride[0] + (ptrdiff_t)o[1] * (ptrdiff_t)C.stride[1] +
                   (ptrdiff_t)o[2] * (ptrdiff_t)C.stride[2];
     int8_t ty = C.type[node];
     if (ty == 0) {
-        R.rhs -= c * C.g[node];
+        R.rhs_add(-c * C.g[node]);
         return;
     }
     int sl = slot_of(o);
     if (sl < 0) return;  // unreachable for marches of at most 5 cells
-    R.val[sl] += c;
-    R.used[sl >> 5] |= 1u << (sl & 31);
+    R.add(sl, c);
 }
 
 struct Pt {
@@ -399,7 +411,7 @@ struct Pt {
 
 // one fluid run [plo, phi_] (positions -1..1 along d of the window centred at `wc` = row
 // offset) of a window meeting the body
-__device__ void run_operator(const Ctx &C, RowAcc &R, size_t rownode, const int rowidx[3], int d, const int wc[3],
+__device__ __attribute__((noinline)) void run_operator(const Ctx &C, WinList &R, size_t rownode, const int rowidx[3], int d, const int wc[3],
                              int plo, int phi_, const bool sol[3], int nruns, const double Ld[3], double W, int &fb,
                              double &minhb, int *bad)
 {
@@ -481,7 +493,7 @@ __device__ void run_operator(const Ctx &C, RowAcc &R, size_t rownode, const int 
     for (int q = 0; q < np; ++q) {
         double c = W * w[q];
         if (P[q].ibi) {
-            R.rhs -= c * P[q].gval;
+            R.rhs_add(-c * P[q].gval);
         } else {
             int o[3] = {wc[0], wc[1], wc[2]};
             o[d] = P[q].off;
@@ -490,126 +502,182 @@ __device__ void run_operator(const Ctx &C, RowAcc &R, size_t rownode, const int 
     }
 }
 
-__global__ void __launch_bounds__(64) k_build_rows(Ctx C, int nirr, const int *__restrict__ nodes, int cap,
-                                                   int *__restrict__ ell_col, double *__restrict__ ell_val,
-                                                   int *__restrict__ len, double *__restrict__ rhs_row,
-                                                   double *__restrict__ k7, double *__restrict__ bdiag,
-                                                   double *__restrict__ minhb_row, int *__restrict__ fb_row,
-                                                   int *__restrict__ bad)
+// One irregular row per 32-lane group (four rows per 128-thread block).  Lanes 0..26 take
+// the 27 windows of Eq. lhsrhs_xxyyzz_mod (direction d = lane / 9, cross offsets from
+// lane % 9) and list their contributions in LDS; lane 27 forms the row's Q-bar term and its
+// Shortley-Weller K row.  The row's lanes then sum the lists in window order into the row's
+// slots (a fixed order: reruns are bitwise equal) and emit the row in slot order.
+constexpr int BR_ROWS = 4;          // rows per block
+constexpr int BR_LANES = 32;        // lanes per row
+__global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
+    Ctx C, int nirr, const int *__restrict__ nodes, int cap, int *__restrict__ ell_col, double *__restrict__ ell_val,
+    int *__restrict__ len, double *__restrict__ rhs_row, double *__restrict__ k7, double *__restrict__ bdiag,
+    double *__restrict__ minhb_row, int *__restrict__ fb_row, int *__restrict__ bad)
 {
-    int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= nirr) return;
-    const size_t rownode = (size_t)nodes[row];
+    __shared__ WinList wl[BR_ROWS][27];
+    __shared__ double qbar[BR_ROWS];
+    __shared__ int wfb[BR_ROWS][27];
+    __shared__ double wminhb[BR_ROWS][27];
+    const int grp = threadIdx.x / BR_LANES, lane = threadIdx.x % BR_LANES;
+    const int row = blockIdx.x * BR_ROWS + grp;
+    const bool live = row < nirr;
+    const size_t rownode = live ? (size_t)nodes[row] : 0;
     const int nx = C.n[0], ny = C.n[1];
     const int idx[3] = {(int)(rownode % nx), (int)((rownode / nx) % ny), (int)(rownode / ((size_t)nx * ny))};
     double L[3][3], Rr[3][3];
-    for (int d = 0; d < 3; ++d) {
-        const double *c = C.coef[d] + 8 * idx[d];
-        L[d][0] = c[0]; L[d][1] = 1.0; L[d][2] = c[1];
-        Rr[d][0] = c[2]; Rr[d][1] = c[3]; Rr[d][2] = c[4];
-    }
-    RowAcc R;
-    for (int q = 0; q < NSLOT; ++q) R.val[q] = 0.0;
-    for (int q = 0; q < (NSLOT + 31) / 32; ++q) R.used[q] = 0u;
-    R.rhs = 0.0;
-    int fb = 0;
-    double minhb = 1.0;
-    // Q-bar: the row's L_x L_y L_z weights on f at every non-solid node of the 3x3x3 box
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                size_t node = rownode + dx + (ptrdiff_t)dy * nx + (ptrdiff_t)dz * (ptrdiff_t)C.stride[2];
-                if (C.type[node] != 3) R.rhs += L[0][dx + 1] * L[1][dy + 1] * L[2][dz + 1] * C.f[node];
-            }
-    // 27 windows
-    for (int d = 0; d < 3; ++d) {
-        const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
-        for (int s1 = -1; s1 <= 1; ++s1)
-            for (int s2 = -1; s2 <= 1; ++s2) {
-                const double W = L[d1][s1 + 1] * L[d2][s2 + 1];
-                int wc[3] = {0, 0, 0};
-                wc[d1] = s1;
-                wc[d2] = s2;
-                bool sol[3];
-                int nsol = 0;
-                for (int p = -1; p <= 1; ++p) {
-                    int o[3] = {wc[0], wc[1], wc[2]};
-                    o[d] = p;
-                    size_t node = rownode + (ptrdiff_t)o[0] + (ptrdiff_t)o[1] * nx + (ptrdiff_t)o[2] * (ptrdiff_t)C.stride[2];
-                    sol[p + 1] = C.type[node] == 3;
-                    nsol += sol[p + 1];
-                }
-                if (nsol == 3) continue;   // window inside the body: dropped
-                if (nsol == 0) {
-                    for (int p = -1; p <= 1; ++p) {
-                        int o[3] = {wc[0], wc[1], wc[2]};
-                        o[d] = p;
-                        put(C, R, rownode, o, W * Rr[d][p + 1]);
-                    }
-                    continue;
-                }
-                int lo[2], hi[2], nr = 0;
-                for (int p = -1; p <= 1;) {
-                    if (sol[p + 1]) { ++p; continue; }
-                    int a = p;
-                    while (p < 1 && !sol[p + 2]) ++p;
-                    lo[nr] = a;
-                    hi[nr] = p;
-                    ++nr;
-                    ++p;
-                }
-                for (int q = 0; q < nr; ++q)
-                    run_operator(C, R, rownode, idx, d, wc, lo[q], hi[q], sol, nr, L[d], W, fb, minhb, bad);
-            }
-    }
-    // Shortley-Weller K row (Eqs. 2ndorder_coef_mod, A7_mod)
-    double kr[7];
-    kr[0] = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        int b0[3] = {idx[0], idx[1], idx[2]};
-        b0[d] = 0;
-        size_t line0 = (size_t)b0[0] * C.stride[0] + (size_t)b0[1] * C.stride[1] + (size_t)b0[2] * C.stride[2];
-        size_t nm = rownode - C.stride[d], npl = rownode + C.stride[d];
-        double hb = C.t[d][idx[d]] - C.t[d][idx[d] - 1], hf = C.t[d][idx[d] + 1] - C.t[d][idx[d]];
-        double gv, fr;
-        if (C.type[nm] == 3) hb = C.t[d][idx[d]] - ibi_on_segment(C, d, line0, idx[d], idx[d] - 1, &gv, &fr);
-        if (C.type[npl] == 3) hf = ibi_on_segment(C, d, line0, idx[d], idx[d] + 1, &gv, &fr) - C.t[d][idx[d]];
-        kr[0] += -2.0 / (hb * hf);
-        int8_t tm = C.type[nm], tp = C.type[npl];
-        kr[1 + 2 * d] = (tm == 1 || tm == 2) ? 2.0 / (hb * (hf + hb)) : 0.0;
-        kr[2 + 2 * d] = (tp == 1 || tp == 2) ? 2.0 / (hf * (hf + hb)) : 0.0;
-    }
-    for (int q = 0; q < 7; ++q) k7[7 * (size_t)row + q] = kr[q];
-    // emit the row in slot order
-    int cnt = 0;
-    for (int sl = 0; sl < NSLOT; ++sl) {
-        if (!((R.used[sl >> 5] >> (sl & 31)) & 1u)) continue;
-        int o[3];
-        if (sl < 27) {
-            o[0] = sl % 3 - 1; o[1] = (sl / 3) % 3 - 1; o[2] = sl / 9 - 1;
-        } else {
-            int q = sl - 27;
-            int t2 = q % 3 - 1; q /= 3;
-            int t1 = q % 3 - 1; q /= 3;
-            int m = q % 4 + 2; q /= 4;
-            int pos = q % 2; int far = q / 2;
-            o[far] = pos ? m : -m;
-            o[(far + 1) % 3] = t1;
-            o[(far + 2) % 3] = t2;
+    if (live) {
+        for (int d = 0; d < 3; ++d) {
+            const double *c = C.coef[d] + 8 * idx[d];
+            L[d][0] = c[0]; L[d][1] = 1.0; L[d][2] = c[1];
+            Rr[d][0] = c[2]; Rr[d][1] = c[3]; Rr[d][2] = c[4];
         }
-        size_t node = rownode + (ptrdiff_t)o[0] + (ptrdiff_t)o[1] * nx + (ptrdiff_t)o[2] * (ptrdiff_t)C.stride[2];
-        if (cnt < cap) {
-            ell_col[(size_t)row * cap + cnt] = (int)node;
-            ell_val[(size_t)row * cap + cnt] = R.val[sl];
-        }
-        ++cnt;
     }
-    len[row] = min(cnt, cap);
-    rhs_row[row] = R.rhs;
-    bdiag[row] = R.val[13];
-    minhb_row[row] = minhb;
-    fb_row[row] = fb;
-    if (cnt > cap) atomicOr(bad, 2);
+    if (live && lane < 27) {
+        // window `lane`: direction d, cross offsets (s1, s2) along d1, d2
+        WinList &R = wl[grp][lane];
+        R.n = 0;
+        int fb = 0;
+        double minhb = 1.0;
+        const int d = lane / 9, d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        const int s1 = (lane % 9) / 3 - 1, s2 = lane % 3 - 1;
+        const double W = L[d1][s1 + 1] * L[d2][s2 + 1];
+        int wc[3] = {0, 0, 0};
+        wc[d1] = s1;
+        wc[d2] = s2;
+        bool sol[3];
+        int nsol = 0;
+        for (int p = -1; p <= 1; ++p) {
+            int o[3] = {wc[0], wc[1], wc[2]};
+            o[d] = p;
+            size_t node = rownode + (ptrdiff_t)o[0] + (ptrdiff_t)o[1] * nx + (ptrdiff_t)o[2] * (ptrdiff_t)C.stride[2];
+            sol[p + 1] = C.type[node] == 3;
+            nsol += sol[p + 1];
+        }
+        if (nsol == 0) {
+            for (int p = -1; p <= 1; ++p) {
+                int o[3] = {wc[0], wc[1], wc[2]};
+                o[d] = p;
+                put(C, R, rownode, o, W * Rr[d][p + 1]);
+            }
+        } else if (nsol < 3) {      // a window inside the body is dropped
+            int lo[2], hi[2], nr = 0;
+            for (int p = -1; p <= 1;) {
+                if (sol[p + 1]) { ++p; continue; }
+                int a = p;
+                while (p < 1 && !sol[p + 2]) ++p;
+                lo[nr] = a;
+                hi[nr] = p;
+                ++nr;
+                ++p;
+            }
+            for (int q = 0; q < nr; ++q)
+                run_operator(C, R, rownode, idx, d, wc, lo[q], hi[q], sol, nr, L[d], W, fb, minhb, bad);
+        }
+        if (R.n > WIN_CAP) atomicOr(bad, 2);
+        wfb[grp][lane] = fb;
+        wminhb[grp][lane] = minhb;
+    } else if (live && lane == 27) {
+        // Q-bar: the row's L_x L_y L_z weights on f at every non-solid node of the 3x3x3 box
+        double q = 0.0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    size_t node = rownode + dx + (ptrdiff_t)dy * nx + (ptrdiff_t)dz * (ptrdiff_t)C.stride[2];
+                    if (C.type[node] != 3) q += L[0][dx + 1] * L[1][dy + 1] * L[2][dz + 1] * C.f[node];
+                }
+        qbar[grp] = q;
+        // Shortley-Weller K row (Eqs. 2ndorder_coef_mod, A7_mod)
+        double kr[7];
+        kr[0] = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            int b0[3] = {idx[0], idx[1], idx[2]};
+            b0[d] = 0;
+            size_t line0 = (size_t)b0[0] * C.stride[0] + (size_t)b0[1] * C.stride[1] + (size_t)b0[2] * C.stride[2];
+            size_t nm = rownode - C.stride[d], npl = rownode + C.stride[d];
+            double hb = C.t[d][idx[d]] - C.t[d][idx[d] - 1], hf = C.t[d][idx[d] + 1] - C.t[d][idx[d]];
+            double gv, fr;
+            if (C.type[nm] == 3) hb = C.t[d][idx[d]] - ibi_on_segment(C, d, line0, idx[d], idx[d] - 1, &gv, &fr);
+            if (C.type[npl] == 3) hf = ibi_on_segment(C, d, line0, idx[d], idx[d] + 1, &gv, &fr) - C.t[d][idx[d]];
+            kr[0] += -2.0 / (hb * hf);
+            int8_t tm = C.type[nm], tp = C.type[npl];
+            kr[1 + 2 * d] = (tm == 1 || tm == 2) ? 2.0 / (hb * (hf + hb)) : 0.0;
+            kr[2 + 2 * d] = (tp == 1 || tp == 2) ? 2.0 / (hf * (hf + hb)) : 0.0;
+        }
+        for (int q2 = 0; q2 < 7; ++q2) k7[7 * (size_t)row + q2] = kr[q2];
+    }
+    __syncthreads();
+    if (!live) return;
+    // Sum the windows' lists in window order: lane l owns the slots l, l + 32, ... and adds
+    // the entries for them in list order (the same order for every run), lane 0 the
+    // right-hand side, which starts from Q-bar.
+    constexpr int SPL = (NSLOT + BR_LANES - 1) / BR_LANES;   // slots per lane
+    double mine[SPL];
+    uint32_t mused = 0u;
+    for (int q = 0; q < SPL; ++q) mine[q] = 0.0;
+    double rhs = qbar[grp];
+    for (int w = 0; w < 27; ++w) {
+        const WinList &R = wl[grp][w];
+        const int n = min(R.n, WIN_CAP);
+        for (int e = 0; e < n; ++e) {
+            const int sl = R.slot[e];
+            if (sl < 0) {
+                if (lane == 0) rhs += R.v[e];
+            } else if (sl % BR_LANES == lane) {
+                mine[sl / BR_LANES] += R.v[e];
+                mused |= 1u << (sl / BR_LANES);
+            }
+        }
+    }
+    // emit in slot order: slot sl = lane + 32 q; its output position is the number of used
+    // slots before it (prefix over q, then over lanes)
+    int cnt_total = 0, base_q = 0;
+    for (int q = 0; q < SPL; ++q) {
+        const bool u = (mused >> q) & 1u;
+        // used slots with the same q on lower lanes
+        const uint64_t bal = __ballot(u);
+        const uint64_t grpmask = (uint64_t)0xffffffffu << (BR_LANES * (threadIdx.x / BR_LANES % 2));
+        const uint64_t mine_bits = bal & grpmask;
+        const int before = __popcll(mine_bits & ((1ull << (threadIdx.x % 64)) - 1ull));
+        const int here = __popcll(mine_bits);
+        if (u) {
+            const int sl = lane + BR_LANES * q;
+            int o[3];
+            if (sl < 27) {
+                o[0] = sl % 3 - 1; o[1] = (sl / 3) % 3 - 1; o[2] = sl / 9 - 1;
+            } else {
+                int r2 = sl - 27;
+                int t2 = r2 % 3 - 1; r2 /= 3;
+                int t1 = r2 % 3 - 1; r2 /= 3;
+                int m = r2 % 4 + 2; r2 /= 4;
+                int pos = r2 % 2; int far = r2 / 2;
+                o[far] = pos ? m : -m;
+                o[(far + 1) % 3] = t1;
+                o[(far + 2) % 3] = t2;
+            }
+            size_t node = rownode + (ptrdiff_t)o[0] + (ptrdiff_t)o[1] * nx + (ptrdiff_t)o[2] * (ptrdiff_t)C.stride[2];
+            const int at = base_q + before;
+            if (at < cap) {
+                ell_col[(size_t)row * cap + at] = (int)node;
+                ell_val[(size_t)row * cap + at] = mine[q];
+            }
+        }
+        base_q += here;
+        cnt_total = base_q;
+    }
+    if (lane == 13) bdiag[row] = mine[0];      // slot 13: the row's own node
+    if (lane == 0) {
+        int fb = 0;
+        double minhb = 1.0;
+        for (int w = 0; w < 27; ++w) {
+            fb += wfb[grp][w];
+            minhb = fmin(minhb, wminhb[grp][w]);
+        }
+        len[row] = min(cnt_total, cap);
+        rhs_row[row] = rhs;
+        minhb_row[row] = minhb;
+        fb_row[row] = fb;
+        if (cnt_total > cap) atomicOr(bad, 2);
+    }
 }
 
 void launch_build_rows(hipStream_t s, int nx, int ny, int nz, const double *x, const double *y, const double *z,
@@ -625,8 +693,8 @@ void launch_build_rows(hipStream_t s, int nx, int ny, int nz, const double *x, c
     int nmax = std::max(nx, std::max(ny, nz));
     for (int d = 0; d < 3; ++d) C.coef[d] = coef + (size_t)d * 8 * nmax;
     C.phi = phi; C.g = g; C.f = f; C.type = type;
-    k_build_rows<<<(nirr + 63) / 64, 64, 0, s>>>(C, nirr, nodes, cap, ell_col, ell_val, len, rhs_row, k7, bdiag, minhb,
-                                                 fallback, bad);
+    k_build_rows<<<(nirr + BR_ROWS - 1) / BR_ROWS, BR_ROWS * BR_LANES, 0, s>>>(
+        C, nirr, nodes, cap, ell_col, ell_val, len, rhs_row, k7, bdiag, minhb, fallback, bad);
 }
 
 __global__ void k_pack_rows(int nirr, int cap, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
