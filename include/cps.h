@@ -87,6 +87,9 @@ typedef struct cps_stats {
     int64_t sweep_points;       /* interior points one sweep processes */
     int32_t sweep_bytes_per_point; /* algorithmic bytes one timed sweep moves per point */
     int32_t pad;
+    double warm_alpha;          /* warm start: the factor it was scaled by -- 1 if its residual is
+                                 * at most ||b||_2, else argmin over alpha of ||b - alpha B u0||_2
+                                 * (0 rejects it); 0 without a warm start */
 } cps_stats;
 
 /* Fill `o` with the defaults: CPS_FP64, 8 inner iterations (Sec. 4), max_iters 20000,

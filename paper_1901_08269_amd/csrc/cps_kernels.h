@@ -43,6 +43,11 @@ template <typename TI, typename TO>
 void launch_masked_copy(hipStream_t s, size_t n, const int8_t *type, const TI *src, TO *dst);
 void launch_output(hipStream_t s, size_t n, const int8_t *type, const double *x, const double *gv, double *u);
 void launch_check_finite(hipStream_t s, size_t n, const int8_t *type, const double *x, int *flag);
+constexpr int DOT_BLOCKS = 1024;
+// partials[2 b], partials[2 b + 1]: block b's sums of a.b and b.b over the unknown nodes
+void launch_dot2_unknowns(hipStream_t s, size_t n, const int8_t *type, const double *a, const double *b,
+                          double *partials);
+void launch_scale(hipStream_t s, size_t n, double *x, double alpha);
 
 // setup.hip
 struct SetupOut {

@@ -58,6 +58,7 @@ struct cps_solver {
     double *phi = nullptr, *gf = nullptr, *f = nullptr;
     int8_t *type = nullptr;
     uint32_t *skip = nullptr;
+    double *dot_partials = nullptr;  // warm-start scaling: per-block partial dots
     uint32_t *irr_bits = nullptr;  // irregular-node bits (skip-word layout)
     int *irr_wstart = nullptr;     // irregular rows before each bit word
     int nirr = 0;
@@ -451,6 +452,35 @@ void free_solver(cps_solver *s)
     delete s;
 }
 
+// A warm start u0 whose residual exceeds that of a zero start, ||b - B u0||_2 > ||b||_2
+// (rows as stored), is scaled by the alpha that minimises ||b - alpha B u0||_2, so the start
+// is never worse than zero in that norm: a coarse-grid prediction can be close to the
+// solution and still have a residual far above ||b|| where the scheme's irregular rows carry
+// large one-sided weights.  A start at least as good as zero is kept (alpha = 1).  Returns
+// alpha.
+double scale_warm_start(cps_solver *s, double *x64)
+{
+    const Launch L = s->launch();
+    double *y = s->tmp64;    // B u0 at the unknown rows
+    launch_apply<double, double>(MODE_PLAIN, L, s->cf64(), s->ir64(), x64, y, nullptr, nullptr, nullptr);
+    if (!s->dot_partials) s->dot_partials = dalloc<double>(s, 2 * DOT_BLOCKS);
+    launch_dot2_unknowns(s->stream, s->nn, s->type, s->rhs, y, s->dot_partials);
+    std::vector<double> h(2 * DOT_BLOCKS);
+    ck(hipMemcpyAsync(h.data(), s->dot_partials, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    sync(s);
+    double by = 0.0, yy = 0.0;
+    for (int q = 0; q < DOT_BLOCKS; ++q) {
+        by += h[2 * q];
+        yy += h[2 * q + 1];
+    }
+    const double r2 = s->bn2 - 2.0 * by + yy;           // ||b - B u0||^2
+    double alpha = 1.0;
+    if (!(r2 <= s->bn2)) alpha = (yy > 0.0 && by > 0.0) ? by / yy : 0.0;
+    if (!(alpha == alpha)) alpha = 0.0;
+    if (alpha != 1.0) launch_scale(s->stream, s->nn, x64, alpha);
+    return alpha;
+}
+
 int fill_stats(cps_solver *s, cps_stats *st, const DevState &ds, int iters, int iters32, int refine, int restarts,
                int status, double solve_ms)
 {
@@ -826,6 +856,7 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
     auto t0 = std::chrono::steady_clock::now();
     int status = CPS_ENOCONV;
     int iters = 0, iters32 = 0, refine = 0, restarts = 0;
+    double warm_alpha = 0.0;
     DevState ds{};
     try {
         s->tev_used = 0;
@@ -850,6 +881,7 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
             int bad;
             std::memcpy(&bad, s->hscalar, sizeof(int));
             if (bad) launch_fill<double>(s->stream, s->nn, x64, 0.0);   // reject a NaN/Inf warm start
+            else warm_alpha = scale_warm_start(s, x64);
         } else {
             launch_fill<double>(s->stream, s->nn, x64, 0.0);
         }
@@ -913,6 +945,7 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
     }
     double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     fill_stats(s, stats, ds, iters, iters32, refine, restarts, status, ms);
+    if (stats) stats->warm_alpha = warm_alpha;
     return status;
 }
 

@@ -1070,6 +1070,39 @@ __global__ void k_check_finite(size_t n, const int8_t *__restrict__ type, const 
     }
 }
 
+// Per-block partial sums (a, b) and (b, b) over the unknown nodes, in a fixed order; the
+// host adds the DOT_BLOCKS partials in block order.
+__global__ void __launch_bounds__(256) k_dot2_unknowns(size_t n, const int8_t *__restrict__ type,
+                                                       const double *__restrict__ a, const double *__restrict__ b,
+                                                       double *__restrict__ partials)
+{
+    __shared__ double sh[2][256 / 64];
+    double acc[2] = {0.0, 0.0};
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        const int8_t t = type[e];
+        if (t == 1 || t == 2) {
+            acc[0] += a[e] * b[e];
+            acc[1] += b[e] * b[e];
+        }
+    }
+    for (int q = 0; q < 2; ++q) acc[q] = wave_sum(acc[q]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) { sh[0][wv] = acc[0]; sh[1][wv] = acc[1]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int w = 0; w < 256 / 64; ++w) { s0 += sh[0][w]; s1 += sh[1][w]; }
+        partials[2 * blockIdx.x] = s0;
+        partials[2 * blockIdx.x + 1] = s1;
+    }
+}
+
+__global__ void k_scale(size_t n, double *__restrict__ x, double alpha)
+{
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        x[e] *= alpha;
+}
+
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
@@ -1187,6 +1220,17 @@ void launch_output(hipStream_t s, size_t n, const int8_t *type, const double *x,
 void launch_check_finite(hipStream_t s, size_t n, const int8_t *type, const double *x, int *flag)
 {
     k_check_finite<<<flat_grid(n), 256, 0, s>>>(n, type, x, flag);
+}
+
+void launch_dot2_unknowns(hipStream_t s, size_t n, const int8_t *type, const double *a, const double *b,
+                          double *partials)
+{
+    k_dot2_unknowns<<<DOT_BLOCKS, 256, 0, s>>>(n, type, a, b, partials);
+}
+
+void launch_scale(hipStream_t s, size_t n, double *x, double alpha)
+{
+    k_scale<<<flat_grid(n), 256, 0, s>>>(n, x, alpha);
 }
 
 // explicit instantiations

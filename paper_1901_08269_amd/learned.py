@@ -300,6 +300,7 @@ def warm_start_gain(model, family, N, seeds, tol=1e-10, precision="mixed"):
         torch.cuda.synchronize()
         t_b = time.perf_counter() - t0
         rows.append({"seed": seed, "iters_zero": st_a["iters"], "iters_warm": st_b["iters"],
+                     "warm_alpha": st_b["warm_alpha"],
                      "solve_s_zero": st_a["solve_ms"] / 1e3, "solve_s_warm": t_b,
                      "diff": float(torch.max(torch.abs(u_a - u_b)) / torch.max(torch.abs(u_a)))})
         S.close()

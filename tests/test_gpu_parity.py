@@ -244,6 +244,26 @@ def test_warm_start_exact_and_nan():
     assert st["status"] == 0 and np.all(np.isfinite(_np(u)))
 
 
+def test_warm_start_scaled_never_worse():
+    """A warm start whose residual exceeds ||b|| is scaled by argmin ||b - alpha B u0||: an
+    exact start keeps alpha = 1, a start whose residual far exceeds ||b|| is scaled down and
+    costs at most as many iterations as a zero start (plus the rounding of a slightly
+    different start)."""
+    P, S, _ = _both("sphere_stretched")
+    t = P.types()
+    u_ref, _ = P.solve(1e-13)
+    u, st = S.solve(1e-10, u0=u_ref)
+    assert st["iters"] == 0 and abs(st["warm_alpha"] - 1.0) < 1e-9
+    _, st0 = S.solve(1e-10)
+    assert st0["warm_alpha"] == 0.0
+    rng = np.random.Generator(np.random.PCG64(3))
+    noisy = u_ref + 1e3 * rng.standard_normal(u_ref.shape) * ((t == 1) | (t == 2))
+    u, st = S.solve(1e-10, u0=noisy)
+    assert 0.0 <= st["warm_alpha"] < 1e-2
+    assert st["iters"] <= st0["iters"] + 2
+    assert st["rel_residual"] <= 1e-10
+
+
 def test_max_iters_exit():
     x, y, z, phi, g, f, _ = _case("sphere_stretched")
     S = cps.Solver(x, y, z, phi, g, f, max_iters=2)
