@@ -26,7 +26,7 @@ constexpr int NT = TX * TY;   // threads per block
 constexpr int IRR_LANES = 16; // lanes per irregular row in the B pass
 constexpr int NXCD = 8;       // MI355X: 8 XCDs, blocks dispatched round-robin over them
 #ifndef CPS_RPW
-#define CPS_RPW 2
+#define CPS_RPW 1
 #endif
 constexpr int RPW = CPS_RPW;  // rows per wavefront in the vectorised Chebyshev sweep
 // Vectors read by the vectorised sweeps carry this many zero elements past the last node:
@@ -45,7 +45,6 @@ struct Tiling {
 struct Geom {
     int nx, ny, nz;
     int W;                     // skip-bit words per x-line
-    Tiling t4;                 // 64 x 4 tiles: single-node-per-lane sweeps
     Tiling t8;                 // 64 x 8 tiles (two rows per thread): the B apply
     Tiling tr;                 // 256 x 4 tiles: one x-row segment of 256 nodes per wavefront,
                                // four nodes per lane (vectorised Chebyshev sweeps)

@@ -281,10 +281,7 @@ Tiling make_tiling(int nx, int ny, int nz, int tw, int ty, int target_blocks, in
     return t;
 }
 
-// Target block counts of the two stencil tilings (the z-chunk length follows from them).
-#ifndef CPS_CHEB_BLOCKS
-#define CPS_CHEB_BLOCKS 2048
-#endif
+// Target block count of the B-apply tiling (the z-chunk length follows from it).
 #ifndef CPS_APPLY_BLOCKS
 #define CPS_APPLY_BLOCKS 2048
 #endif
@@ -306,7 +303,6 @@ Geom make_geom(int nx, int ny, int nz)
     Geom g{};
     g.nx = nx; g.ny = ny; g.nz = nz;
     g.W = (nx + 31) / 32;
-    g.t4 = make_tiling(nx, ny, nz, TX, 4, CPS_CHEB_BLOCKS, 8);
     g.t8 = make_tiling(nx, ny, nz, TX, 8, CPS_APPLY_BLOCKS, 8);
     {
         const int per_plane = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY * RPW - 1) / (TY * RPW));
@@ -374,6 +370,9 @@ hipEvent_t timed_sweep_begin(cps_solver *s)
 #ifndef CPS_FUSED_SWEEPS
 #define CPS_FUSED_SWEEPS 0
 #endif
+#ifndef CPS_INPLACE_SWEEPS
+#define CPS_INPLACE_SWEEPS 1
+#endif
 
 // p^ = M p: inner_iters Chebyshev steps.  The first is fused with the vector update `kind`;
 // with fused sweeps the rest run two per sweep (k_cheb2w), after one single sweep when their
@@ -390,17 +389,20 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
     if constexpr (sizeof(T) == 8) { cf = s->cf64(); ir = s->ir64(); } else { cf = s->cf32(); ir = s->ir32(); }
     const int m = s->opt.inner_iters;
     auto buf = [&](int j) { return (j == m) ? dst : V.c[j % 4]; };
-    launch_first<T>(kind, L, cf, ir, r, ps, v, buf(1), c2[0], st);
     int k = 1;
     if (!CPS_FUSED_SWEEPS || s->nx - 2 > 4 * TX) {
-        // rows longer than one wavefront segment: single sweeps
+        // single sweeps: x_{k+1} overwrites x_{k-1} in place (each node's x_{k-1} is read
+        // only by the thread that writes its x_{k+1}), so one step touches three vectors
+        auto buf2 = [&](int j) { return (j == m) ? dst : V.c[CPS_INPLACE_SWEEPS ? j % 2 : j % 4]; };
+        launch_first<T>(kind, L, cf, ir, r, ps, v, buf2(1), c2[0], st);
         for (; k < m; ++k) {
             hipEvent_t e1 = timed_sweep_begin(s);
-            launch_cheb<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), c1[k], c2[k], st);
+            launch_cheb<T>(L, cf, ir, buf2(k), (k == 1) ? nullptr : buf2(k - 1), ps, buf2(k + 1), c1[k], c2[k], st);
             if (e1) ck(hipEventRecord(e1, s->stream));
         }
         return;
     }
+    launch_first<T>(kind, L, cf, ir, r, ps, v, buf(1), c2[0], st);
     if ((m - 1) % 2 == 1) {
         launch_cheb<T>(L, cf, ir, buf(1), nullptr, ps, buf(2), c1[1], c2[1], st);
         k = 2;
@@ -803,7 +805,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->irr_wstart = dalloc<int>(s, (size_t)s->g.W * ny * nz);
         launch_irr_words(s->stream, s->g, s->type, s->irr_node, s->nirr, s->irr_bits, s->irr_wstart);
         // reduction scratch: enough for the largest launch
-        size_t maxblk = (size_t)std::max({s->g.t4.nblk, s->g.t8.nblk, s->g.tr.nblk, s->g.tc.nblk, s->g.nflat}) +
+        size_t maxblk = (size_t)std::max({s->g.t8.nblk, s->g.tr.nblk, s->g.tc.nblk, s->g.nflat}) +
                         (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
         s->partials = dalloc<double>(s, 2 * maxblk);
         s->ticket = dalloc<unsigned>(s, 1);

@@ -12,9 +12,10 @@
 #include "cps_device.h"
 #include "cps_kernels.h"
 
-// Last reads of an operand carry the non-temporal hint, so that the operands still to be
-// reused (the preconditioner input, the newest iterates) stay in the 256 MB Infinity Cache:
-// measured at 256^3, the Chebyshev sweep drops from 51 to 46 us.
+// Last reads of an operand in the pointwise kernels carry the non-temporal hint, so that it
+// does not displace operands still to be reused from the 256 MB Infinity Cache.  The
+// Chebyshev sweeps need no hint: they write x_{k+1} over x_{k-1} in place, so the three
+// vectors one sweep touches (69 MB each at 256^3 in FP32) all stay cached.
 #ifndef CPS_NT_LAST
 #define CPS_NT_LAST 1
 #endif
@@ -289,94 +290,6 @@ __global__ void __launch_bounds__(NT) k_finalize(const double *partials, int nbl
 // ---------------------------------------------------------------------------------------
 // x_{m+1} = x_m + c1 (x_m - x_{m-1}) + c2 (rho - K x_m) / diag(K)
 // (Chebyshev acceleration of Jacobi for -K, Saad Alg. 12.1), x_{m-1} = 0 when PREV0.
-// Regular rows: K from the second-order 1D tables.  Each thread marches its column in z
-// with the three z-neighbours in registers and every operand of the next plane already in
-// flight while the current plane is computed; x and y neighbours come through L1.
-// Irregular rows use their stored Shortley-Weller row (one thread per row, same launch).
-template <typename T, bool PREV0>
-__global__ void __launch_bounds__(NT) k_cheb(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
-                                             const T *__restrict__ xc, const T *__restrict__ xm1,
-                                             const T *__restrict__ rho, T *__restrict__ xn, T c1, T c2,
-                                             const DevState *st)
-{
-    if (st && st->done) return;
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ty * TX;
-    const int nx = g.nx, ny = g.ny;
-    const size_t plane = (size_t)nx * ny;
-    const int nib = irr_blocks(ir.n, NT);
-    const int b = (int)blockIdx.x - nib;
-    const Tiling &tl = g.t4;
-    if (b >= 0) {
-        int bx, by, bz;
-        if (!tile_of_block(tl, b, bx, by, bz)) return;
-        const int i = 1 + bx * TX + tx, j = 1 + by * TY + ty;
-        if (i > nx - 2 || j > ny - 2) return;
-        const int k0 = 1 + bz * tl.TZ;
-        const int k1 = min(k0 + tl.TZ, g.nz - 1);
-        const T *cx = cf.c[0] + 8 * i;
-        const T *cy = cf.c[1] + 8 * j;
-        const T kax = cx[5], kbx = cx[6], kcx = cx[7];
-        const T kay = cy[5], kby = cy[6], kcy = cy[7];
-        const size_t e0 = (size_t)i + (size_t)nx * j;
-        // Software pipeline over three register sets, one per plane: plane k is computed
-        // from sets (k-1, k, k+1) and the set of plane k-1, dead after that, then receives
-        // plane k+2, so two planes of loads stay in flight.  Every operand of a plane (its
-        // skip word and z coefficients included) travels in its set: a load issued just
-        // before its use would make the in-order completion counter wait for the whole
-        // prefetch.  Fetches are unconditional, with the plane clamped to k1 <= nz - 1
-        // (planes past k1 are loaded but unused), and the loop is unrolled by three so that
-        // each set keeps a fixed register home.
-        struct Pl { T c, w, e, s, n, r, p, za, zb, zc; uint32_t sk; };
-        const size_t skw = (size_t)g.ny * g.W;
-        const uint32_t *skp = skip + (size_t)j * g.W + (i >> 5);
-        auto fetch = [&](Pl &P, int k) __attribute__((always_inline)) {
-            k = min(k, k1);
-            const size_t e = e0 + (size_t)k * plane;
-            const T *cz = cf.c[2] + 8 * k;
-            P.sk = skp[(size_t)k * skw];
-            P.c = xc[e];
-            P.w = xc[e - 1];
-            P.e = xc[e + 1];
-            P.s = xc[e - nx];
-            P.n = xc[e + nx];
-            P.r = rho[e];
-            P.p = PREV0 ? T(0) : xm1[e];
-            P.za = cz[5];
-            P.zb = cz[6];
-            P.zc = cz[7];
-        };
-        auto step = [&](const Pl &M, const Pl &C, const Pl &U, Pl &F, int k) __attribute__((always_inline)) {
-            T kd = kbx + kby + C.zb;
-            T kx = kd * C.c + kax * C.w + kcx * C.e + kay * C.s + kcy * C.n + C.za * M.c + C.zc * U.c;
-            T val = C.c + c1 * (C.c - C.p) + c2 * (C.r - kx) / kd;
-            if (!((C.sk >> (i & 31)) & 1u)) xn[e0 + (size_t)k * plane] = val;
-            fetch(F, k + 2);
-        };
-        Pl P0, P1, P2;
-        fetch(P2, k0 - 1);
-        fetch(P0, k0);
-        fetch(P1, k0 + 1);
-        for (int k = k0; k < k1; k += 3) {
-            step(P2, P0, P1, P2, k);
-            if (k + 1 >= k1) break;
-            step(P0, P1, P2, P0, k + 1);
-            if (k + 2 >= k1) break;
-            step(P1, P2, P0, P1, k + 2);
-        }
-    } else {
-        const int row = (int)blockIdx.x * NT + tid;
-        if (row >= ir.n) return;
-        const int e = ir.node[row];
-        const T *k7 = ir.k7 + 7 * row;
-        T z0 = xc[e];
-        T kx = k7[0] * z0 + k7[1] * xc[e - 1] + k7[2] * xc[e + 1] + k7[3] * xc[e - nx] + k7[4] * xc[e + nx] +
-               k7[5] * xc[e - plane] + k7[6] * xc[e + plane];
-        T prev = PREV0 ? T(0) : xm1[e];
-        xn[e] = z0 + c1 * (z0 - prev) + c2 * (rho[e] - kx) / k7[0];
-    }
-}
-
-// ---------------------------------------------------------------------------------------
 // Vectorised rows: a wavefront owns a 256-node segment of an x-row, four consecutive nodes
 // per lane, loaded and stored as one 4-vector (rows start at any 4-byte boundary; the
 // hardware splits unaligned vector accesses).  x neighbours come from the adjacent lanes;
@@ -440,27 +353,6 @@ __device__ __forceinline__ typename Vec4Of<T>::type load4(const T *__restrict__ 
     return v;
 }
 
-// load4 with the non-temporal hint: for an operand read for the last time (x_{k-1} in the
-// Chebyshev recurrence), so that it does not displace operands still to be reused from the
-// caches.
-template <typename T>
-__device__ __forceinline__ typename Vec4Of<T>::type load4_last(const T *__restrict__ a, size_t e, const Seg &q)
-{
-    using V = typename Vec4Of<T>::type;
-#if CPS_NT_LAST
-    V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(a + e));
-#else
-    V v = *reinterpret_cast<const V *>(a + e);
-#endif
-    if (q.nv < 4) {
-        v.x = q.nv > 0 ? v.x : T(0);
-        v.y = q.nv > 1 ? v.y : T(0);
-        v.z = q.nv > 2 ? v.z : T(0);
-        v.w = T(0);
-    }
-    return v;
-}
-
 // the four row-type bits of nodes i0 .. i0 + 3 (skip words are read in pairs; the array
 // carries two words of padding)
 __device__ __forceinline__ uint32_t skip4(const uint32_t *__restrict__ w, int i0)
@@ -474,15 +366,15 @@ __device__ __forceinline__ uint32_t skip4(const uint32_t *__restrict__ w, int i0
 // Each wavefront owns RPW consecutive rows of a 256-node segment and marches in z.  At
 // plane k it loads the rows' x_k at plane k + 1 (their upper z neighbours, and the centre
 // of the next plane), the two outer y-neighbour rows, rho and x_{k-1}; the rows' x_k at
-// planes k - 1 and k are carried in registers.  Latency is hidden by occupancy: the sweep
-// is memory-latency bound, so the register budget goes to more wavefronts and more rows
-// per wavefront, not to prefetch.  Wave-uniform y and z coefficients live in scalar
-// registers.  Irregular rows use their Shortley-Weller row in the leading blocks (one thread
-// per row).
+// planes k - 1 and k are carried in registers.  Latency is hidden by occupancy: issuing the
+// loads of two or four planes before computing them (fewer waits per plane, more registers)
+// measured no faster at 256^3, so the register budget goes to wavefronts and rows per
+// wavefront.  Wave-uniform y and z coefficients live in scalar registers.  Irregular rows
+// use their Shortley-Weller row in the leading blocks (one thread per row).
 template <typename T, bool PREV0>
 __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
-                                              const T *__restrict__ xc, const T *__restrict__ xm1,
-                                              const T *__restrict__ rho, T *__restrict__ xn, T c1, T c2,
+                                              const T *__restrict__ xc, const T *xm1,
+                                              const T *__restrict__ rho, T *xn, T c1, T c2,
                                               const DevState *st)
 {
     using V = typename Vec4Of<T>::type;
@@ -562,7 +454,7 @@ __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, con
         for (int r = 0; r < R; ++r) {
             cp[r] = load4(xc, er[r] + kn, q);
             rv4[r] = load4(rho, er[r] + kp, q);
-            if (!PREV0) pv4[r] = load4_last(xm1, er[r] + kp, q);
+            if (!PREV0) pv4[r] = load4(xm1, er[r] + kp, q);
             sk[r] = skip4(skip + (size_t)k * wplane + wr[r], ic);
             lft[r] = (!one_seg && need_l) ? xc[er[r] + kp - 1] : T(0);
             rgt[r] = (!one_seg && need_r) ? xc[er[r] + kp + ir_off] : T(0);
