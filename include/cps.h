@@ -92,7 +92,7 @@ typedef struct cps_stats {
                                  * (0 rejects it); 0 without a warm start */
 } cps_stats;
 
-/* Fill `o` with the defaults: CPS_FP64, 8 inner iterations (Sec. 4), max_iters 20000,
+/* Fill `o` with the defaults: CPS_FP64, 24 inner iterations, max_iters 20000,
  * max_refine 40, max_restarts 5, host pointers, inner_tol 1e-4, the default Chebyshev
  * interval, null stream, no kernel timing. */
 void cps_default_options(cps_options *o);

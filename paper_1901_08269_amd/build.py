@@ -1,6 +1,7 @@
 """Build the gfx950 shared library libcps.so in-tree with hipcc.
 
     python -m paper_1901_08269_amd.build          # compile every source, link _lib/libcps.so
+                                                  # (and _lib/stream_bench)
 
 Every HIP source is compiled for gfx950 only, with packed-FP32 instruction selection
 switched off, then linked into one shared library whose C-ABI is include/cps.h.
@@ -22,6 +23,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(LIBDIR, "libcps.so")
 
 SOURCES = ["setup.hip", "sweeps.hip", "solver.hip", "net.hip"]
+# a standalone program: the bandwidth plain streaming kernels get (the roofline's practical ceiling)
+STREAM_BENCH = os.path.join(LIBDIR, "stream_bench")
 
 
 def hipcc() -> str:
@@ -59,8 +62,12 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    cmd = [hipcc(), *common_flags(), os.path.join(CSRC, "stream_bench.hip"), "-o", STREAM_BENCH]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for stream_bench.hip:\n{r.stdout}\n{r.stderr}")
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", STREAM_BENCH)
     return LIB
 
 

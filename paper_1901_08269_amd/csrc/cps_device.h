@@ -45,7 +45,8 @@ struct Tiling {
 struct Geom {
     int nx, ny, nz;
     int W;                     // skip-bit words per x-line
-    Tiling t8;                 // 64 x 8 tiles (two rows per thread): the B apply
+    Tiling ta;                 // 256 x 4 tiles, one row per wavefront: the B apply and the
+                               // vector updates
     Tiling tr;                 // 256 x 4 tiles: one x-row segment of 256 nodes per wavefront,
                                // four nodes per lane (vectorised Chebyshev sweeps)
     Tiling tc;                 // 256 x 4 tiles of the fused two-step sweep (one row per

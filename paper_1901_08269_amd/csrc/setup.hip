@@ -62,53 +62,58 @@ void launch_coef(hipStream_t s, int n, const double *t, double *coef)
 // ---------------------------------------------------------------------------------------
 // classification
 // ---------------------------------------------------------------------------------------
-__global__ void k_classify(int nx, int ny, int nz, const double *__restrict__ phi, const double *__restrict__ g,
-                           const double *__restrict__ f, int8_t *__restrict__ type, int *flags)
+// one thread per node: x from the thread index, y and z from the grid (no 64-bit divisions)
+__global__ void __launch_bounds__(256) k_classify(int nx, int ny, int nz, const double *__restrict__ phi,
+                                                  const double *__restrict__ g, const double *__restrict__ f,
+                                                  int8_t *__restrict__ type, int *flags)
 {
-    size_t n = (size_t)nx * ny * nz;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        int i = (int)(e % nx);
-        int j = (int)((e / nx) % ny);
-        int k = (int)(e / ((size_t)nx * ny));
-        double p = phi[e];
-        if (!isfinite(p) || !isfinite(g[e]) || !isfinite(f[e])) atomicOr(flags, 1);
-        bool wall = i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1;
-        if (wall) {
-            if (!(p > 0.0)) atomicOr(flags, 2);
-            type[e] = 0;
-        } else {
-            type[e] = (p > 0.0) ? 1 : 3;
-        }
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int j = (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    const int k = (int)blockIdx.z;
+    if (i >= nx || j >= ny) return;
+    const size_t e = (size_t)i + (size_t)nx * j + (size_t)nx * ny * k;
+    const double p = phi[e];
+    if (!isfinite(p) || !isfinite(g[e]) || !isfinite(f[e])) atomicOr(flags, 1);
+    const bool wall = i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1;
+    if (wall) {
+        if (!(p > 0.0)) atomicOr(flags, 2);
+        type[e] = 0;
+    } else {
+        type[e] = (p > 0.0) ? 1 : 3;
     }
 }
 
 void launch_classify(hipStream_t s, int nx, int ny, int nz, const double *phi, const double *g, const double *f,
                      int8_t *type, int *flags)
 {
-    size_t n = (size_t)nx * ny * nz;
-    k_classify<<<(unsigned)std::min<size_t>((n + 255) / 256, 65536), 256, 0, s>>>(nx, ny, nz, phi, g, f, type, flags);
+    dim3 blk(64, 4), grid((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4), (unsigned)nz);
+    k_classify<<<grid, blk, 0, s>>>(nx, ny, nz, phi, g, f, type, flags);
 }
 
-// a fluid node with a solid node among its 26 neighbours is irregular
-__global__ void k_mark_irregular(int nx, int ny, int nz, int8_t *__restrict__ type)
+// a fluid node with a solid node among its 26 neighbours is irregular (one thread per
+// interior node; a neighbour read while it turns from regular to irregular is never solid)
+__global__ void __launch_bounds__(256) k_mark_irregular(int nx, int ny, int nz, int8_t *__restrict__ type)
 {
-    size_t n = (size_t)nx * ny * nz;
-    size_t plane = (size_t)nx * ny;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        if (type[e] != 1) continue;
-        bool irr = false;
-        for (int dz = -1; dz <= 1 && !irr; ++dz)
-            for (int dy = -1; dy <= 1 && !irr; ++dy)
-                for (int dx = -1; dx <= 1 && !irr; ++dx)
-                    irr = type[e + dx + (ptrdiff_t)dy * nx + (ptrdiff_t)dz * (ptrdiff_t)plane] == 3;
-        if (irr) type[e] = 2;
-    }
+    const int i = 1 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int j = 1 + (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    const int k = 1 + (int)blockIdx.z;
+    if (i > nx - 2 || j > ny - 2) return;
+    const size_t plane = (size_t)nx * ny;
+    const size_t e = (size_t)i + (size_t)nx * j + plane * k;
+    if (type[e] != 1) return;
+    bool irr = false;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+                irr |= type[e + dx + (ptrdiff_t)dy * nx + (ptrdiff_t)dz * (ptrdiff_t)plane] == 3;
+    if (irr) type[e] = 2;
 }
 
 void launch_mark_irregular(hipStream_t s, int nx, int ny, int nz, int8_t *type)
 {
-    size_t n = (size_t)nx * ny * nz;
-    k_mark_irregular<<<(unsigned)std::min<size_t>((n + 255) / 256, 65536), 256, 0, s>>>(nx, ny, nz, type);
+    if (nx < 3 || ny < 3 || nz < 3) return;
+    dim3 blk(64, 4), grid((unsigned)((nx - 2 + 63) / 64), (unsigned)((ny - 2 + 3) / 4), (unsigned)(nz - 2));
+    k_mark_irregular<<<grid, blk, 0, s>>>(nx, ny, nz, type);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -722,41 +727,53 @@ void launch_pack_rows(hipStream_t s, int nirr, int cap, const int *ell_col, cons
 // ---------------------------------------------------------------------------------------
 // right-hand side at regular rows: Q f (Eq. q) minus the known wall-node terms of Eq. A27
 // ---------------------------------------------------------------------------------------
-__global__ void k_rhs_regular(int nx, int ny, int nz, const double *__restrict__ coef, int nmax,
-                              const double *__restrict__ f, const double *__restrict__ g,
-                              const int8_t *__restrict__ type, double *__restrict__ rhs)
+__global__ void __launch_bounds__(256) k_rhs_regular(int nx, int ny, int nz, const double *__restrict__ coef, int nmax,
+                                                     const double *__restrict__ f, const double *__restrict__ g,
+                                                     const int8_t *__restrict__ type, double *__restrict__ rhs)
 {
-    size_t n = (size_t)nx * ny * nz;
-    size_t plane = (size_t)nx * ny;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        if (type[e] != 1) continue;
-        int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / plane);
-        const double *cx = coef + 8 * i, *cy = coef + 8 * (size_t)nmax + 8 * j, *cz = coef + 16 * (size_t)nmax + 8 * k;
-        double Lx[3] = {cx[0], 1.0, cx[1]}, Rx[3] = {cx[2], cx[3], cx[4]};
-        double Ly[3] = {cy[0], 1.0, cy[1]}, Ry[3] = {cy[2], cy[3], cy[4]};
-        double Lz[3] = {cz[0], 1.0, cz[1]}, Rz[3] = {cz[2], cz[3], cz[4]};
-        double acc = 0.0;
+    // one thread per interior node: x from the thread index, y and z from the grid
+    const int i = 1 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int j = 1 + (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    const int k = 1 + (int)blockIdx.z;
+    if (i > nx - 2 || j > ny - 2) return;
+    const size_t plane = (size_t)nx * ny;
+    const size_t e = (size_t)i + (size_t)nx * j + plane * k;
+    if (type[e] != 1) return;
+    const double *cx = coef + 8 * i, *cy = coef + 8 * (size_t)nmax + 8 * j, *cz = coef + 16 * (size_t)nmax + 8 * k;
+    const double Lx[3] = {cx[0], 1.0, cx[1]}, Ly[3] = {cy[0], 1.0, cy[1]}, Lz[3] = {cz[0], 1.0, cz[1]};
+    double acc = 0.0;
+    for (int r = 0; r < 3; ++r) {
+        double accy = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            const double *fr = f + e + (ptrdiff_t)(q - 1) * nx + (ptrdiff_t)(r - 1) * (ptrdiff_t)plane;
+            accy += Ly[q] * (Lx[0] * fr[-1] + fr[0] + Lx[2] * fr[1]);
+        }
+        acc += Lz[r] * accy;
+    }
+    // known (wall) neighbours move to the right-hand side; only rows next to a wall have them
+    // (a regular row has no solid neighbour)
+    if (i == 1 || j == 1 || k == 1 || i == nx - 2 || j == ny - 2 || k == nz - 2) {
+        const double Rx[3] = {cx[2], cx[3], cx[4]}, Ry[3] = {cy[2], cy[3], cy[4]}, Rz[3] = {cz[2], cz[3], cz[4]};
         for (int r = 0; r < 3; ++r)
             for (int q = 0; q < 3; ++q)
                 for (int p = 0; p < 3; ++p) {
-                    size_t nb = e + (p - 1) + (ptrdiff_t)(q - 1) * nx + (ptrdiff_t)(r - 1) * (ptrdiff_t)plane;
-                    acc += Lx[p] * Ly[q] * Lz[r] * f[nb];
+                    const size_t nb = e + (p - 1) + (ptrdiff_t)(q - 1) * nx + (ptrdiff_t)(r - 1) * (ptrdiff_t)plane;
                     if (type[nb] == 0) {
-                        double a = Rx[p] * Ly[q] * Lz[r] + Lx[p] * Ry[q] * Lz[r] + Lx[p] * Ly[q] * Rz[r];
+                        const double a = Rx[p] * Ly[q] * Lz[r] + Lx[p] * Ry[q] * Lz[r] + Lx[p] * Ly[q] * Rz[r];
                         acc -= a * g[nb];
                     }
                 }
-        rhs[e] = acc;
     }
+    rhs[e] = acc;
 }
 
 void launch_rhs_regular(hipStream_t s, int nx, int ny, int nz, const double *coef, const double *f, const double *g,
                         const int8_t *type, double *rhs)
 {
-    size_t n = (size_t)nx * ny * nz;
+    if (nx < 3 || ny < 3 || nz < 3) return;
     int nmax = std::max(nx, std::max(ny, nz));
-    k_rhs_regular<<<(unsigned)std::min<size_t>((n + 255) / 256, 65536), 256, 0, s>>>(nx, ny, nz, coef, nmax, f, g, type,
-                                                                                      rhs);
+    dim3 blk(64, 4), grid((unsigned)((nx - 2 + 63) / 64), (unsigned)((ny - 2 + 3) / 4), (unsigned)(nz - 2));
+    k_rhs_regular<<<grid, blk, 0, s>>>(nx, ny, nz, coef, nmax, f, g, type, rhs);
 }
 
 __global__ void k_scatter_rows(int nirr, const int *__restrict__ nodes, const double *__restrict__ rhs_row,

@@ -281,15 +281,17 @@ Tiling make_tiling(int nx, int ny, int nz, int tw, int ty, int target_blocks, in
     return t;
 }
 
-// Target block count of the B-apply tiling (the z-chunk length follows from it).
-#ifndef CPS_APPLY_BLOCKS
-#define CPS_APPLY_BLOCKS 2048
-#endif
 // The vectorised Chebyshev sweep splits z into this many chunks (each at least 4 planes):
-// measured best at both 256^3 (512 blocks, 45.7 us vs 49.7 with 1024) and 512^3 (2048
-// blocks, 486 us vs 644 with 512).
+// measured best at 256^3 (1024 blocks, 43.0 us per FP32 sweep; 8 chunks 51.4 us, 32 chunks
+// 47.5 us) and at 512^3.  Fewer chunks leave wavefronts idle; more chunks re-read more halo
+// planes and put the blocks in more than one round.
 #ifndef CPS_ROW_ZCHUNKS
 #define CPS_ROW_ZCHUNKS 16
+#endif
+// z-chunks of the vectorised B apply and vector updates (each at least 4 planes; 8 and 32
+// measured the same at 256^3)
+#ifndef CPS_APPLY_ZCHUNKS
+#define CPS_APPLY_ZCHUNKS 16
 #endif
 #ifndef CPS_FUSED_BLOCKS
 #define CPS_FUSED_BLOCKS 2048
@@ -303,7 +305,10 @@ Geom make_geom(int nx, int ny, int nz)
     Geom g{};
     g.nx = nx; g.ny = ny; g.nz = nz;
     g.W = (nx + 31) / 32;
-    g.t8 = make_tiling(nx, ny, nz, TX, 8, CPS_APPLY_BLOCKS, 8);
+    {
+        const int per_plane = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY - 1) / TY);
+        g.ta = make_tiling(nx, ny, nz, 4 * TX, TY, per_plane * CPS_APPLY_ZCHUNKS, 4);
+    }
     {
         const int per_plane = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY * RPW - 1) / (TY * RPW));
         g.tr = make_tiling(nx, ny, nz, 4 * TX, TY * RPW, per_plane * CPS_ROW_ZCHUNKS, 4);
@@ -591,7 +596,7 @@ int rhs_build(cps_solver *s)
         s->fallback = fbs;
     }
     // ||b||^2 and ||D^-1 b||^2: the residual kernel applied to x = 0
-    double *zero = dalloc<double>(s, s->nn);
+    double *zero = dalloc<double>(s, s->nn + VEC_PAD);
     double *outb = dalloc<double>(s, s->nn);
     launch_fill<double>(st, s->nn, zero, 0.0);
     launch_apply<double, double>(MODE_RES, s->launch(), s->cf64(), s->ir64(), zero, outb, nullptr, s->rhs, s->st);
@@ -805,7 +810,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->irr_wstart = dalloc<int>(s, (size_t)s->g.W * ny * nz);
         launch_irr_words(s->stream, s->g, s->type, s->irr_node, s->nirr, s->irr_bits, s->irr_wstart);
         // reduction scratch: enough for the largest launch
-        size_t maxblk = (size_t)std::max({s->g.t8.nblk, s->g.tr.nblk, s->g.tc.nblk, s->g.nflat}) +
+        size_t maxblk = (size_t)std::max({s->g.ta.nblk, s->g.tr.nblk, s->g.tc.nblk, s->g.nflat}) +
                         (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
         s->partials = dalloc<double>(s, 2 * maxblk);
         s->ticket = dalloc<unsigned>(s, 1);
@@ -876,7 +881,7 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
         const double tol2 = tol * tol;
         // FP64 solution vector (unknown entries only); the FP64 Krylov set only in FP64 mode
         if (s->opt.precision == CPS_FP64) alloc_vecs<double>(s, s->v64);
-        if (!s->x64) s->x64 = dalloc<double>(s, s->nn);
+        if (!s->x64) s->x64 = dalloc<double>(s, s->nn + VEC_PAD);
         double *x64 = (s->opt.precision == CPS_FP64) ? s->v64.x : s->x64;
         if (warm_start) {
             if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
@@ -962,7 +967,7 @@ int cps_residual(cps_solver *s, const double *u, double *r, double *rel)
     if (!s || !u) return CPS_EINVAL;
     try {
         if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
-        double *xin = dalloc<double>(s, s->nn);
+        double *xin = dalloc<double>(s, s->nn + VEC_PAD);
         double *rout = dalloc<double>(s, s->nn);
         to_device(s, s->tmp64, u, s->nn * sizeof(double));
         launch_masked_copy<double, double>(s->stream, s->nn, s->type, s->tmp64, xin);
@@ -991,7 +996,7 @@ int cps_apply(cps_solver *s, const double *x, double *y, int32_t precision)
         if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
         to_device(s, s->tmp64, x, s->nn * sizeof(double));
         if (precision == CPS_FP64) {
-            double *xin = dalloc<double>(s, s->nn), *yo = dalloc<double>(s, s->nn);
+            double *xin = dalloc<double>(s, s->nn + VEC_PAD), *yo = dalloc<double>(s, s->nn);
             launch_masked_copy<double, double>(s->stream, s->nn, s->type, s->tmp64, xin);
             launch_fill<double>(s->stream, s->nn, yo, 0.0);
             launch_apply<double, double>(MODE_PLAIN, s->launch(), s->cf64(), s->ir64(), xin, yo, nullptr, nullptr, nullptr);
@@ -1000,7 +1005,7 @@ int cps_apply(cps_solver *s, const double *x, double *y, int32_t precision)
             dfree(s, xin);
             dfree(s, yo);
         } else {
-            float *xin = dalloc<float>(s, s->nn), *yo = dalloc<float>(s, s->nn);
+            float *xin = dalloc<float>(s, s->nn + VEC_PAD), *yo = dalloc<float>(s, s->nn);
             launch_masked_copy<double, float>(s->stream, s->nn, s->type, s->tmp64, xin);
             launch_fill<float>(s->stream, s->nn, yo, 0.0f);
             launch_apply<float, float>(MODE_PLAIN, s->launch(), s->cf32(), s->ir32(), xin, yo, nullptr, nullptr, nullptr);

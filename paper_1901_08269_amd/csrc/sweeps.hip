@@ -3,29 +3,22 @@
 // sweeps of the preconditioner K, and the BiCGSTAB vector updates with their dot products
 // reduced in the same launch (Alg. 1 with the split of Eq. Bdec).
 //
-// Launch shape: the stencil kernels use 64 x 4 (Chebyshev) or 64 x 8 (B apply) column
-// tiles of the interior that march over z-chunks (XCD-aware tile order); the pointwise
-// kernels stride over all nodes with 16-byte vectors; blocks ahead of those process the
-// irregular rows.  Kernels that reduce write one partial per block; a one-block finalize
+// Launch shape: the stencil and update kernels run on vectorised rows -- a wavefront owns a
+// 256-node segment of an x-row, four nodes per lane -- in blocks of four wavefronts that
+// march over z-chunks of the interior (XCD-aware tile order); blocks before (or, for the B
+// apply, after) the tiles process the irregular rows; the restart kernel strides over all
+// nodes with 16-byte vectors.  Kernels that reduce write one partial per block; a one-block finalize
 // kernel that follows sums them in a fixed order (deterministic) and updates the
 // device-resident BiCGSTAB scalars, so the host never waits inside an iteration.
 #include "cps_device.h"
 #include "cps_kernels.h"
 
-// Last reads of an operand in the pointwise kernels carry the non-temporal hint, so that it
-// does not displace operands still to be reused from the 256 MB Infinity Cache.  The
-// Chebyshev sweeps need no hint: they write x_{k+1} over x_{k-1} in place, so the three
-// vectors one sweep touches (69 MB each at 256^3 in FP32) all stay cached.
-#ifndef CPS_NT_LAST
-#define CPS_NT_LAST 1
-#endif
-
 namespace cps {
 
-// Blocks that process irregular rows come first in every launch that has them, in a count
-// rounded up to a multiple of the XCD count: they are short, so they finish within the
-// first round of blocks instead of trailing behind the regular tiles, and the regular
-// tiles keep their XCD assignment (block index modulo the XCD count).
+// Blocks that process irregular rows come in a count rounded up to a multiple of the XCD
+// count, so that the regular tiles keep their XCD assignment (block index modulo the XCD
+// count).  Where a row is short (the Chebyshev and update kernels) they come first and
+// finish within the first round of blocks instead of trailing behind the tiles.
 __host__ __device__ __forceinline__ int irr_blocks(int nrows, int rows_per_block)
 {
     int nb = (nrows + rows_per_block - 1) / rows_per_block;
@@ -38,19 +31,15 @@ __host__ __device__ __forceinline__ int irr_blocks(int nrows, int rows_per_block
 // ---------------------------------------------------------------------------------------
 // Regular rows use sum factorisation of the tensor form
 //   A = R_x (x) L_y (x) L_z + L_x (x) R_y (x) L_z + L_x (x) L_y (x) R_z
-// with L = (a, 1, c) and R = (ar, br, cr) taken at the row's own index per direction.
-// A block owns a 64 x 8 column tile (two rows per thread) and marches in z: each plane of x
-// (with a one-node halo) is staged in a double-buffered LDS tile while the next two planes
-// are already being fetched into registers; every thread filters its 3 x 3 neighbourhood along
-// x, then y, from LDS and keeps the two y-filtered planes it still needs in registers.
-// One barrier per plane.
+// with L = (a, 1, c) and R = (ar, br, cr) taken at the row's own index per direction
+// (k_apply4 below, on vectorised rows).
 //
 // MODE_PLAIN  y = B x
 // MODE_V      v = B x;  partials (w, v), (v, v);  finalize: alpha = rho / (r0, v)
 // MODE_T      t = B x;  partials (t, w), (t, t);  finalize: omega = (t, s) / (t, t)
 // MODE_RES    y = b - B x; partials (y, y), (y/d, y/d); finalize stores the norms
 // `aux` is the second operand of the row's output: w[e] for MODE_V / MODE_T, b[e] for
-// MODE_RES (unused for MODE_PLAIN).  The regular tiles load it one pipeline stage ahead.
+// MODE_RES (unused for MODE_PLAIN).
 template <typename T, int MODE>
 using AuxT = typename std::conditional<MODE == MODE_RES, double, T>::type;
 
@@ -79,161 +68,6 @@ __device__ __forceinline__ AuxT<T, MODE> load_aux(size_t e, const T *__restrict_
     if (MODE == MODE_RES) return bvec[e];
     if (MODE == MODE_V || MODE == MODE_T) return w[e];
     return AuxT<T, MODE>(0);
-}
-
-template <typename T, typename TO, int MODE>
-__global__ void __launch_bounds__(NT) k_apply(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
-                                              const T *__restrict__ x, TO *__restrict__ y, const T *__restrict__ w,
-                                              const double *__restrict__ bvec, DevState *st, double *partials,
-                                              unsigned *ticket, int nblocks)
-{
-    constexpr int NV = (MODE == MODE_PLAIN) ? 0 : 2;
-    constexpr int AY = 2 * TY;                       // tile rows (two per thread)
-    constexpr int LW = TX + 2, LH = AY + 2;          // staged plane with a one-node halo
-    constexpr int NLD = (LW * LH + NT - 1) / NT;     // staging loads per thread and plane
-    if (MODE != MODE_PLAIN && MODE != MODE_RES && st->done) return;
-    __shared__ T su[2][LH][LW];
-    double acc[2] = {0.0, 0.0};
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + ty * TX;
-    const int nx = g.nx, ny = g.ny;
-    const size_t plane = (size_t)nx * ny;
-    const int nib = irr_blocks(ir.n, NT / IRR_LANES);
-    const int b = (int)blockIdx.x - nib;
-    const Tiling &tl = g.t8;
-    if (b >= 0) {
-        int bx, by, bz;
-        if (tile_of_block(tl, b, bx, by, bz)) {
-            const int x0 = 1 + bx * TX, y0 = 1 + by * AY;
-            const int i = x0 + tx, ja = y0 + ty, jb = ja + TY;
-            const int k0 = 1 + bz * tl.TZ;
-            const int k1 = min(k0 + tl.TZ, g.nz - 1);      // output planes [k0, k1)
-            const bool iok = i <= nx - 2, aok = iok && ja <= ny - 2, bok = iok && jb <= ny - 2;
-            // x-filtered values are computed per thread, so coefficients only need to be
-            // valid where they are used; out-of-range columns/rows read index 1
-            const T *cx = cf.c[0] + 8 * (iok ? i : 1);
-            const T *ca = cf.c[1] + 8 * (ja <= ny - 2 ? ja : 1);
-            const T *cb = cf.c[1] + 8 * (jb <= ny - 2 ? jb : 1);
-            const T ax = cx[0], ccx = cx[1], arx = cx[2], brx = cx[3], crx = cx[4];
-            const T aya = ca[0], cya = ca[1], arya = ca[2], brya = ca[3], crya = ca[4];
-            const T ayb = cb[0], cyb = cb[1], aryb = cb[2], bryb = cb[3], cryb = cb[4];
-            // staging slots of this thread
-            int soff[NLD], srow[NLD], scol[NLD];
-            bool sok[NLD], sin[NLD];
-#pragma unroll
-            for (int q = 0; q < NLD; ++q) {
-                int idx = tid + q * NT;
-                sin[q] = idx < LW * LH;
-                int r = sin[q] ? idx / LW : 0, c = sin[q] ? idx - r * LW : 0;
-                srow[q] = r;
-                scol[q] = c;
-                int gi = x0 - 1 + c, gj = y0 - 1 + r;
-                sok[q] = sin[q] && gi < nx && gj < ny;
-                soff[q] = sok[q] ? gi + nx * gj : 0;
-            }
-            // Two register sets serve alternate planes.  While plane kk sits in LDS, planes
-            // kk+1 and kk+2 of x are in flight, together with the skip words and the second
-            // operand (aux) of the output rows two steps ahead.  Every load of a step is
-            // issued after the waits of that step, so the in-order completion counter never
-            // forces a wait on a plane that is still being prefetched.  The loop is unrolled
-            // by two so that each set and each LDS buffer has a fixed role and no in-flight
-            // register is ever copied.
-            using AT = AuxT<T, MODE>;
-            struct Set { T r[NLD]; AT wa, wb; uint32_t sa, sb; T z[5]; };
-            Set A, B;
-            // lanes outside the grid address row 1, column 1 and are masked off by aok / bok
-            const int ic = iok ? i : 1;
-            const size_t ea0 = (size_t)ic + (size_t)nx * (aok ? ja : 1), eb0 = (size_t)ic + (size_t)nx * (bok ? jb : 1);
-            const uint32_t *ska = skip + (size_t)(aok ? ja : 1) * g.W + (ic >> 5);
-            const uint32_t *skb = skip + (size_t)(bok ? jb : 1) * g.W + (ic >> 5);
-            const size_t skw = (size_t)g.ny * g.W;
-            // x of plane kk (clamped to k1; planes past k1 are loaded but unused)
-            auto stage_fetch = [&](Set &S, int kk) __attribute__((always_inline)) {
-                const size_t kp = (size_t)min(kk, k1) * plane;
-#pragma unroll
-                for (int q = 0; q < NLD; ++q) S.r[q] = sok[q] ? x[(size_t)soff[q] + kp] : T(0);
-            };
-            // row-type bits, aux and z coefficients of output plane k (clamped to k1 - 1)
-            auto aux_fetch = [&](Set &S, int k) __attribute__((always_inline)) {
-                k = min(k, k1 - 1);
-                const size_t kp = (size_t)k * plane;
-                S.sa = aok ? ska[(size_t)k * skw] : ~0u;
-                S.sb = bok ? skb[(size_t)k * skw] : ~0u;
-                if (MODE != MODE_PLAIN) {
-                    S.wa = load_aux<T, MODE>(ea0 + kp, w, bvec);
-                    S.wb = load_aux<T, MODE>(eb0 + kp, w, bvec);
-                }
-                const T *cz = cf.c[2] + 8 * k;
-#pragma unroll
-                for (int q = 0; q < 5; ++q) S.z[q] = cz[q];
-            };
-            stage_fetch(A, k0 - 1);
-            stage_fetch(B, k0);
-            A.wa = A.wb = B.wa = B.wb = AT(0);
-            A.sa = A.sb = B.sa = B.sb = ~0u;
-#pragma unroll
-            for (int q = 0; q < 5; ++q) A.z[q] = B.z[q] = T(0);
-            T LLa0 = 0, LRa0 = 0, LLa1 = 0, LRa1 = 0, LLb0 = 0, LRb0 = 0, LLb1 = 0, LRb1 = 0;
-            auto plane_step = [&](Set &S, T (&lds)[LH][LW], int kk) __attribute__((always_inline)) {
-#pragma unroll
-                for (int q = 0; q < NLD; ++q)
-                    if (sin[q]) lds[srow[q]][scol[q]] = S.r[q];
-                stage_fetch(S, kk + 2);
-                __syncthreads();
-                // x filters of the three rows around row a (LDS rows ty..ty+2) and row b
-                T ul[6], ur[6];
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    T um = lds[ty + r][tx], u0 = lds[ty + r][tx + 1], up = lds[ty + r][tx + 2];
-                    ul[r] = ax * um + u0 + ccx * up;
-                    ur[r] = arx * um + brx * u0 + crx * up;
-                    T vm = lds[ty + TY + r][tx], v0 = lds[ty + TY + r][tx + 1], vp = lds[ty + TY + r][tx + 2];
-                    ul[3 + r] = ax * vm + v0 + ccx * vp;
-                    ur[3 + r] = arx * vm + brx * v0 + crx * vp;
-                }
-                T LLa2 = aya * ul[0] + ul[1] + cya * ul[2];
-                T LRa2 = (aya * ur[0] + ur[1] + cya * ur[2]) + (arya * ul[0] + brya * ul[1] + crya * ul[2]);
-                T LLb2 = ayb * ul[3] + ul[4] + cyb * ul[5];
-                T LRb2 = (ayb * ur[3] + ur[4] + cyb * ur[5]) + (aryb * ul[3] + bryb * ul[4] + cryb * ul[5]);
-                if (kk >= k0 + 1) {
-                    const int k = kk - 1;
-                    const size_t kp = (size_t)k * plane;
-                    const T az = S.z[0], ccz = S.z[1], arz = S.z[2], brz = S.z[3], crz = S.z[4];
-                    if (!((S.sa >> (i & 31)) & 1u)) {
-                        T v = az * LRa0 + LRa1 + ccz * LRa2 + arz * LLa0 + brz * LLa1 + crz * LLa2;
-                        emit<T, TO, MODE>(ea0 + kp, v, (double)(brx + brya + brz), S.wa, y, acc);
-                    }
-                    if (!((S.sb >> (i & 31)) & 1u)) {
-                        T v = az * LRb0 + LRb1 + ccz * LRb2 + arz * LLb0 + brz * LLb1 + crz * LLb2;
-                        emit<T, TO, MODE>(eb0 + kp, v, (double)(brx + bryb + brz), S.wb, y, acc);
-                    }
-                }
-                aux_fetch(S, kk + 1);
-                LLa0 = LLa1; LRa0 = LRa1; LLa1 = LLa2; LRa1 = LRa2;
-                LLb0 = LLb1; LRb0 = LRb1; LLb1 = LLb2; LRb1 = LRb2;
-            };
-            for (int kk = k0 - 1; kk <= k1; kk += 2) {
-                plane_step(A, su[0], kk);
-                if (kk + 1 > k1) break;
-                plane_step(B, su[1], kk + 1);
-            }
-        }
-    } else {
-        // irregular rows: IRR_LANES lanes per row gather the full row of B
-        const int rows_per_block = NT / IRR_LANES;
-        const int row = (int)blockIdx.x * rows_per_block + tid / IRR_LANES;
-        const int lane = tid % IRR_LANES;
-        double sacc = 0.0;
-        if (row < ir.n) {
-            for (int e = ir.ptr[row] + lane; e < ir.ptr[row + 1]; e += IRR_LANES)
-                sacc += (double)ir.val[e] * (double)x[ir.col[e]];
-        }
-        for (int o = IRR_LANES / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, IRR_LANES);
-        if (row < ir.n && lane == 0) {
-            const size_t e = (size_t)ir.node[row];
-            emit<T, TO, MODE>(e, (T)sacc, (double)ir.bdiag[row], load_aux<T, MODE>(e, w, bvec), y, acc);
-        }
-    }
-    if constexpr (NV > 0) write_partials<2>(acc, partials);
 }
 
 // One block: fixed-order totals of a reducing kernel's partials and the scalar updates of
@@ -509,6 +343,338 @@ __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, con
 }
 
 // ---------------------------------------------------------------------------------------
+// B apply on vectorised rows (modes above): a wavefront owns one
+// row of a 256-node segment, four nodes per lane, and marches in z.  At plane kk it loads x
+// of rows j - 1, j, j + 1 (the centre row's next plane from HBM, the outer rows mostly from
+// L2), filters them along x (neighbours from the adjacent lanes) and then along y, keeping
+// the y-filtered pairs (L_y L_x x, L_y R_x x + R_y L_x x) of planes kk - 2 .. kk; the z
+// filter then gives row j at plane kk - 1.  No LDS and no barriers: latency is hidden by
+// occupancy, as in the Chebyshev sweep (an LDS-staged 64 x 8 tile version with one barrier
+// per plane measured no faster).  Irregular rows gather their stored full row of B in the
+// blocks after the tiles, IRR_LANES lanes per row.
+// ---------------------------------------------------------------------------------------
+template <typename T, typename TO, int MODE>
+__global__ void __launch_bounds__(NT) k_apply4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
+                                               const T *__restrict__ x, TO *__restrict__ y, const T *__restrict__ w,
+                                               const double *__restrict__ bvec, DevState *st, double *partials)
+{
+    using V = typename Vec4Of<T>::type;
+    constexpr int NV = (MODE == MODE_PLAIN) ? 0 : 2;
+    if (MODE != MODE_PLAIN && MODE != MODE_RES && st->done) return;
+    double acc[2] = {0.0, 0.0};
+    const int lane = threadIdx.x, wv = threadIdx.y, tid = lane + wv * TX;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t plane = (size_t)nx * ny;
+    // the irregular rows come after the tiles here: a full row of B is a gather of about 50
+    // entries, and leading blocks of such rows held the tiles back (measured 65 against 52 us
+    // per FP32 apply at 256^3 with 8 spheres)
+    const int b = (int)blockIdx.x < g.ta.nblk ? (int)blockIdx.x : -1;
+    const int irr_block = (int)blockIdx.x - g.ta.nblk;
+    if (b >= 0) {
+        const Tiling &tl = g.ta;
+        int bs, by, bz;
+        if (tile_of_block(tl, b, bs, by, bz) && 1 + by * TY + wv <= ny - 2) {
+            const int jr = 1 + by * TY + wv;
+            const Seg q = seg_of(nx, bs, lane);
+            const int k0 = 1 + bz * tl.TZ;
+            const int k1 = min(k0 + tl.TZ, nz - 1);               // output planes [k0, k1)
+            const int ic = q.nv > 0 ? q.i0 : 1;
+            T ax[4], cxx[4], arx[4], brx[4], crx[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const T *cx = cf.c[0] + 8 * (u < q.nv ? q.i0 + u : 1);
+                ax[u] = cx[0]; cxx[u] = cx[1]; arx[u] = cx[2]; brx[u] = cx[3]; crx[u] = cx[4];
+            }
+            const T *cy = cf.c[1] + 8 * jr;
+            const T ay = uniform(cy[0]), cyy = uniform(cy[1]), ary = uniform(cy[2]), bry = uniform(cy[3]),
+                    cry = uniform(cy[4]);
+            const size_t e0 = (size_t)ic + (size_t)nx * jr;         // row j at plane 0
+            const size_t wr = (size_t)jr * g.W + (ic >> 5);
+            const size_t wplane = (size_t)ny * g.W;
+            const bool one_seg = nx - 2 <= 4 * TX;
+            const bool need_l = lane == 0, need_r = lane == TX - 1 || q.i0 + 4 >= nx - 1;
+            const int ir_off = q.nv > 0 ? q.nv : 0;
+            // x-filtered pair of one row at one plane: uL = L_x x, uR = R_x x
+            auto xfilter = [&](const V &v4, T lft, T rgt, T (&uL)[4], T (&uR)[4]) __attribute__((always_inline)) {
+                const T cv[4] = {v4.x, v4.y, v4.z, v4.w};
+                T left = __shfl_up(cv[3], 1, TX), right = __shfl_down(cv[0], 1, TX);
+                if (need_l) left = lft;
+                if (need_r) right = rgt;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const T wm = (u == 0) ? left : cv[u - 1];
+                    const T ep = (u + 1 < q.nv) ? cv[u + 1] : right;
+                    uL[u] = ax[u] * wm + cv[u] + cxx[u] * ep;
+                    uR[u] = arx[u] * wm + brx[u] * cv[u] + crx[u] * ep;
+                }
+            };
+            T LL0[4], LR0[4], LL1[4], LR1[4];                       // planes kk - 2, kk - 1
+#pragma unroll
+            for (int u = 0; u < 4; ++u) LL0[u] = LR0[u] = LL1[u] = LR1[u] = T(0);
+            for (int kk = k0 - 1; kk <= k1; ++kk) {
+                const size_t kp = (size_t)kk * plane;
+                const V xs = load4(x, e0 + kp - nx, q), xc = load4(x, e0 + kp, q), xn = load4(x, e0 + kp + nx, q);
+                T ls = T(0), rs = T(0), lc = T(0), rc = T(0), ln = T(0), rn = T(0);
+                if (!one_seg) {
+                    if (need_l) { ls = x[e0 + kp - nx - 1]; lc = x[e0 + kp - 1]; ln = x[e0 + kp + nx - 1]; }
+                    if (need_r) { rs = x[e0 + kp - nx + ir_off]; rc = x[e0 + kp + ir_off]; rn = x[e0 + kp + nx + ir_off]; }
+                }
+                // output plane k = kk - 1: row type bits and the second operand
+                const int k = kk - 1;
+                const bool out = k >= k0;
+                const int kc = out ? k : k0;
+                uint32_t sk = 0u;
+                AuxT<T, MODE> aux[4];
+                if (out) {
+                    sk = skip4(skip + (size_t)kc * wplane + wr, ic);
+                    if (MODE == MODE_RES) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) aux[u] = u < q.nv ? (AuxT<T, MODE>)bvec[e0 + (size_t)kc * plane + u] : 0;
+                    } else if (MODE == MODE_V || MODE == MODE_T) {
+                        const V a4 = load4(w, e0 + (size_t)kc * plane, q);
+                        aux[0] = a4.x; aux[1] = a4.y; aux[2] = a4.z; aux[3] = a4.w;
+                    }
+                }
+                T sL[4], sR[4], cL[4], cR[4], nL[4], nR[4];
+                xfilter(xs, ls, rs, sL, sR);
+                xfilter(xc, lc, rc, cL, cR);
+                xfilter(xn, ln, rn, nL, nR);
+                T LL2[4], LR2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    LL2[u] = ay * sL[u] + cL[u] + cyy * nL[u];
+                    LR2[u] = (ay * sR[u] + cR[u] + cyy * nR[u]) + (ary * sL[u] + bry * cL[u] + cry * nL[u]);
+                }
+                if (out) {
+                    const T *cz = cf.c[2] + 8 * k;
+                    const T az = uniform(cz[0]), ccz = uniform(cz[1]), arz = uniform(cz[2]), brz = uniform(cz[3]),
+                            crz = uniform(cz[4]);
+                    const size_t e = e0 + (size_t)k * plane;
+                    TO o[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const T v = az * LR0[u] + LR1[u] + ccz * LR2[u] + arz * LL0[u] + brz * LL1[u] + crz * LL2[u];
+                        const bool on = u < q.nv && !((sk >> u) & 1u);
+                        if (MODE == MODE_RES) {
+                            const double r = (double)aux[u] - (double)v, rd = r / (double)(brx[u] + bry + brz);
+                            o[u] = (TO)r;
+                            if (on) { acc[0] += r * r; acc[1] += rd * rd; }
+                        } else {
+                            o[u] = (TO)v;
+                            if ((MODE == MODE_V || MODE == MODE_T) && on) {
+                                acc[0] += (double)aux[u] * (double)v;
+                                acc[1] += (double)v * (double)v;
+                            }
+                        }
+                    }
+                    // one 4-vector store where all four nodes are regular rows, else node by node
+                    if (q.full && sk == 0u) {
+                        typename Vec4Of<TO>::type ov = {o[0], o[1], o[2], o[3]};
+                        *reinterpret_cast<typename Vec4Of<TO>::type *>(y + e) = ov;
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (u < q.nv && !((sk >> u) & 1u)) y[e + u] = o[u];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    LL0[u] = LL1[u]; LR0[u] = LR1[u];
+                    LL1[u] = LL2[u]; LR1[u] = LR2[u];
+                }
+            }
+        }
+    } else {
+        // irregular rows: IRR_LANES lanes per row gather the full row of B, four entries per
+        // lane at a time (their column and value loads, then their x loads, are issued
+        // together: three dependent memory round trips for a row of up to 64 entries)
+        const int rows_per_block = NT / IRR_LANES;
+        const int row = irr_block * rows_per_block + tid / IRR_LANES;
+        const int il = tid % IRR_LANES;
+        double sacc = 0.0;
+        if (row < ir.n) {
+            const int p0 = ir.ptr[row], p1 = ir.ptr[row + 1];
+            for (int e = p0 + il; e < p1; e += 4 * IRR_LANES) {
+                int c[4];
+                T v[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int ee = e + t * IRR_LANES;
+                    const int ec = ee < p1 ? ee : p0;       // entries past the row end read entry p0
+                    c[t] = ir.col[ec];
+                    const T vv = ir.val[ec];
+                    v[t] = ee < p1 ? vv : T(0);
+                }
+                T xv[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) xv[t] = x[c[t]];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) sacc += (double)v[t] * (double)xv[t];
+            }
+        }
+        for (int o = IRR_LANES / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, IRR_LANES);
+        if (row < ir.n && il == 0) {
+            const size_t e = (size_t)ir.node[row];
+            emit<T, TO, MODE>(e, (T)sacc, (double)ir.bdiag[row], load_aux<T, MODE>(e, w, bvec), y, acc);
+        }
+    }
+    if constexpr (NV > 0) write_partials<2>(acc, partials);
+}
+
+// ---------------------------------------------------------------------------------------
+// Vector updates of Alg. 1 on vectorised rows (same arithmetic as k_first / k_update): a
+// wavefront owns one row of a 256-node segment, four nodes per lane, and walks its z-chunk.
+// The diagonals of K and B are formed from the 1D tables with the x coefficients held per
+// lane and the y and z coefficients wave-uniform, so no node index is ever decoded.  Walls
+// are not touched (zero in every vector); irregular rows run in the leading blocks, one
+// thread per row.
+// ---------------------------------------------------------------------------------------
+template <typename T, int KIND>
+__global__ void __launch_bounds__(NT) k_first4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
+                                               const T *__restrict__ r, T *__restrict__ ps, const T *__restrict__ v,
+                                               T *__restrict__ x1, T c2, const DevState *st)
+{
+    using V = typename Vec4Of<T>::type;
+    if (st->done) return;
+    const T alpha = (T)st->alpha, beta = (T)st->beta, omega = (T)st->omega;
+    const int lane = threadIdx.x, wv = threadIdx.y;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t plane = (size_t)nx * ny;
+    const int nib = irr_blocks(ir.n, NT);
+    const int b = (int)blockIdx.x - nib;
+    if (b < 0) {
+        const int row = (int)blockIdx.x * NT + lane + wv * TX;
+        if (row >= ir.n) return;
+        const int e = ir.node[row];
+        const T val = (KIND == FIRST_P) ? r[e] + beta * (ps[e] - omega * v[e]) : r[e] - alpha * v[e];
+        ps[e] = val;
+        x1[e] = c2 * val / ir.k7[7 * row];
+        return;
+    }
+    const Tiling &tl = g.ta;
+    int bs, by, bz;
+    if (!tile_of_block(tl, b, bs, by, bz)) return;
+    const int jr = 1 + by * TY + wv;
+    if (jr > ny - 2) return;
+    const Seg q = seg_of(nx, bs, lane);
+    const int ic = q.nv > 0 ? q.i0 : 1;
+    const int k0 = 1 + bz * tl.TZ, k1 = min(k0 + tl.TZ, nz - 1);
+    T kbx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) kbx[u] = cf.c[0][8 * (u < q.nv ? q.i0 + u : 1) + 6];
+    const T kby = uniform(cf.c[1][8 * jr + 6]);
+    const size_t e0 = (size_t)ic + (size_t)nx * jr, wr = (size_t)jr * g.W + (ic >> 5), wplane = (size_t)ny * g.W;
+    for (int k = k0; k < k1; ++k) {
+        const size_t e = e0 + (size_t)k * plane;
+        const V r4 = load4(r, e, q), v4 = load4(v, e, q);
+        V p4 = {T(0), T(0), T(0), T(0)};
+        if (KIND == FIRST_P) p4 = load4(ps, e, q);
+        const uint32_t sk = skip4(skip + (size_t)k * wplane + wr, ic);
+        const T kz = uniform(cf.c[2][8 * k + 6]);
+        const T rv[4] = {r4.x, r4.y, r4.z, r4.w}, vv[4] = {v4.x, v4.y, v4.z, v4.w}, pv[4] = {p4.x, p4.y, p4.z, p4.w};
+        T out[4], xo[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            out[u] = (KIND == FIRST_P) ? rv[u] + beta * (pv[u] - omega * vv[u]) : rv[u] - alpha * vv[u];
+            xo[u] = c2 * out[u] / (kbx[u] + kby + kz);
+        }
+        if (q.full && sk == 0u) {
+            V o = {out[0], out[1], out[2], out[3]}, xq = {xo[0], xo[1], xo[2], xo[3]};
+            *reinterpret_cast<V *>(ps + e) = o;
+            *reinterpret_cast<V *>(x1 + e) = xq;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < q.nv && !((sk >> u) & 1u)) {
+                    ps[e + u] = out[u];
+                    x1[e + u] = xo[u];
+                }
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_update4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
+                                                T *__restrict__ xs, const T *__restrict__ ph, const T *__restrict__ sh,
+                                                const T *__restrict__ s, const T *__restrict__ t,
+                                                const T *__restrict__ r0, T *__restrict__ r, DevState *st,
+                                                double *partials)
+{
+    using V = typename Vec4Of<T>::type;
+    if (st->done) return;
+    const T alphaT = (T)st->alpha, omegaT = (T)st->omega;
+    double acc[2] = {0.0, 0.0};
+    const int lane = threadIdx.x, wv = threadIdx.y;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t plane = (size_t)nx * ny;
+    const int nib = irr_blocks(ir.n, NT);
+    const int b = (int)blockIdx.x - nib;
+    if (b < 0) {
+        // irregular rows: x and r are updated by the tiles like every node; here only the
+        // Jacobi-weighted norm with the row's own diagonal
+        const int row = (int)blockIdx.x * NT + lane + wv * TX;
+        if (row < ir.n) {
+            const int e = ir.node[row];
+            const T rv = s[e] - omegaT * t[e];
+            const double rd = (double)rv / (double)ir.bdiag[row];
+            acc[1] += rd * rd;
+        }
+    } else {
+        const Tiling &tl = g.ta;
+        int bs, by, bz;
+        const bool tile = tile_of_block(tl, b, bs, by, bz);
+        const int jr = tile ? 1 + by * TY + wv : ny;
+        if (jr <= ny - 2) {
+            const Seg q = seg_of(nx, bs, lane);
+            const int ic = q.nv > 0 ? q.i0 : 1;
+            const int k0 = 1 + bz * tl.TZ, k1 = min(k0 + tl.TZ, nz - 1);
+            T brx[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) brx[u] = cf.c[0][8 * (u < q.nv ? q.i0 + u : 1) + 3];
+            const T bry = uniform(cf.c[1][8 * jr + 3]);
+            const size_t e0 = (size_t)ic + (size_t)nx * jr, wr = (size_t)jr * g.W + (ic >> 5),
+                         wplane = (size_t)ny * g.W;
+            for (int k = k0; k < k1; ++k) {
+                const size_t e = e0 + (size_t)k * plane;
+                const V x4 = load4(xs, e, q), p4 = load4(ph, e, q), h4 = load4(sh, e, q), s4 = load4(s, e, q),
+                        t4 = load4(t, e, q), z4 = load4(r0, e, q);
+                const uint32_t sk = skip4(skip + (size_t)k * wplane + wr, ic);
+                const T brz = uniform(cf.c[2][8 * k + 3]);
+                const T xv[4] = {x4.x, x4.y, x4.z, x4.w}, pv[4] = {p4.x, p4.y, p4.z, p4.w},
+                        hv[4] = {h4.x, h4.y, h4.z, h4.w}, sv[4] = {s4.x, s4.y, s4.z, s4.w},
+                        tv[4] = {t4.x, t4.y, t4.z, t4.w}, zv[4] = {z4.x, z4.y, z4.z, z4.w};
+                T xo[4], ro[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    xo[u] = xv[u] + (alphaT * pv[u] + omegaT * hv[u]);
+                    ro[u] = sv[u] - omegaT * tv[u];
+                    if (u < q.nv) {
+                        acc[0] += (double)zv[u] * (double)ro[u];
+                        if (!((sk >> u) & 1u)) {
+                            const double rd = (double)ro[u] / ((double)brx[u] + (double)bry + (double)brz);
+                            acc[1] += rd * rd;
+                        }
+                    }
+                }
+                if (q.full) {
+                    V xq = {xo[0], xo[1], xo[2], xo[3]}, rq = {ro[0], ro[1], ro[2], ro[3]};
+                    *reinterpret_cast<V *>(xs + e) = xq;
+                    *reinterpret_cast<V *>(r + e) = rq;
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (u < q.nv) {
+                            xs[e + u] = xo[u];
+                            r[e + u] = ro[u];
+                        }
+                }
+            }
+        }
+    }
+    write_partials<2>(acc, partials);
+}
+
+// ---------------------------------------------------------------------------------------
 // Two Chebyshev steps per sweep with independent wavefronts (no LDS, no barriers).
 // For rows of at most 256 interior nodes a wavefront owns one whole x-row j (four nodes per
 // lane; the x neighbours at both ends are walls, zero in every iterate) and marches in z:
@@ -684,8 +850,8 @@ __global__ void __launch_bounds__(NT) CHEB2W_ATTR k_cheb2w(Geom g, Coef<T> cf, I
 }
 
 // ---------------------------------------------------------------------------------------
-// flat, vectorised pointwise kernels: blocks [0, nflat) stride over all nodes in groups of
-// 16 bytes per thread; wall and solid entries are 0 in every vector and stay 0
+// flat pointwise kernels: threads stride over all nodes in groups of 16 bytes; wall and
+// solid entries are 0 in every vector and stay 0
 // ---------------------------------------------------------------------------------------
 template <typename T>
 struct Vec16;
@@ -709,31 +875,6 @@ __device__ __forceinline__ void load16(const T *p, T (&v)[Vec16<T>::n])
     for (int u = 0; u < Vec16<T>::n; ++u) v[u] = a[u];
 }
 
-// load16 with the non-temporal hint, for an operand's last read in the iteration
-template <typename T>
-struct Ext16;
-template <>
-struct Ext16<float> {
-    typedef float type __attribute__((ext_vector_type(4)));
-};
-template <>
-struct Ext16<double> {
-    typedef double type __attribute__((ext_vector_type(2)));
-};
-
-template <typename T>
-__device__ __forceinline__ void load16_last(const T *p, T (&v)[Vec16<T>::n])
-{
-    using E = typename Ext16<T>::type;
-#if CPS_NT_LAST
-    E q = __builtin_nontemporal_load(reinterpret_cast<const E *>(p));
-#else
-    E q = *reinterpret_cast<const E *>(p);
-#endif
-#pragma unroll
-    for (int u = 0; u < Vec16<T>::n; ++u) v[u] = q[u];
-}
-
 template <typename T>
 __device__ __forceinline__ void store16(T *p, const T (&v)[Vec16<T>::n])
 {
@@ -742,151 +883,6 @@ __device__ __forceinline__ void store16(T *p, const T (&v)[Vec16<T>::n])
 #pragma unroll
     for (int u = 0; u < Vec16<T>::n; ++u) a[u] = v[u];
     *reinterpret_cast<typename Vec16<T>::type *>(p) = q;
-}
-
-// node coordinates of `base` and its successors
-struct NodeIt {
-    int i, j, k;
-    __device__ NodeIt(size_t base, int nx, int ny)
-    {
-        i = (int)(base % nx);
-        size_t r = base / nx;
-        j = (int)(r % ny);
-        k = (int)(r / ny);
-    }
-    __device__ void next(int nx, int ny)
-    {
-        if (++i == nx) {
-            i = 0;
-            if (++j == ny) { j = 0; ++k; }
-        }
-    }
-};
-
-// FIRST_P:  p = r + beta (p - omega v)   (search direction of Alg. 1; p = r after a (re)start: beta = 0)
-// FIRST_S:  s = r - alpha v              (intermediate residual of Alg. 1)
-// then x1 = c2 * (p or s) / diag(K), the first Chebyshev step from x0 = 0.  Irregular rows
-// (their K diagonal is the Shortley-Weller one) are done by the leading blocks.
-template <typename T, int KIND>
-__global__ void __launch_bounds__(NT) k_first(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
-                                              const T *__restrict__ r, T *__restrict__ ps, const T *__restrict__ v,
-                                              T *__restrict__ x1, T c2, const DevState *st)
-{
-    if (st->done) return;
-    constexpr int VN = Vec16<T>::n;
-    const T alpha = (T)st->alpha, beta = (T)st->beta, omega = (T)st->omega;
-    const int tid = threadIdx.x + threadIdx.y * TX;
-    const int nx = g.nx, ny = g.ny;
-    const size_t nn = (size_t)nx * ny * g.nz;
-    const int nib = irr_blocks(ir.n, NT);
-    const int b = (int)blockIdx.x - nib;
-    if (b >= 0) {
-        const size_t ngroups = nn / VN;
-        for (size_t q = (size_t)b * NT + tid; q < ngroups; q += (size_t)g.nflat * NT) {
-            const size_t base = q * VN;
-            T rv[VN], pv[VN], vv[VN], out[VN], xo[VN];
-            // r and v are read again by the s update (FIRST_P), for the last time there
-            if (KIND == FIRST_P) {
-                load16(r + base, rv);
-                load16(v + base, vv);
-                load16_last(ps + base, pv);
-            } else {
-                load16_last(r + base, rv);
-                load16_last(v + base, vv);
-            }
-            NodeIt it(base, nx, ny);
-            bool any_skip = false;
-#pragma unroll
-            for (int u = 0; u < VN; ++u) {
-                out[u] = (KIND == FIRST_P) ? rv[u] + beta * (pv[u] - omega * vv[u]) : rv[u] - alpha * vv[u];
-                T kd = cf.c[0][8 * it.i + 6] + cf.c[1][8 * it.j + 6] + cf.c[2][8 * it.k + 6];
-                xo[u] = c2 * out[u] / kd;
-                any_skip |= skip_bit(skip, g, it.i, it.j, it.k);
-                it.next(nx, ny);
-            }
-            if (!any_skip) {
-                store16(ps + base, out);
-                store16(x1 + base, xo);
-            } else {
-                NodeIt it2(base, nx, ny);
-#pragma unroll
-                for (int u = 0; u < VN; ++u) {
-                    if (!skip_bit(skip, g, it2.i, it2.j, it2.k)) {
-                        ps[base + u] = out[u];
-                        x1[base + u] = xo[u];
-                    }
-                    it2.next(nx, ny);
-                }
-            }
-        }
-        // tail nodes (nn not a multiple of VN) are wall nodes: nothing to do
-    } else {
-        const int row = (int)blockIdx.x * NT + tid;
-        if (row >= ir.n) return;
-        const int e = ir.node[row];
-        T val = (KIND == FIRST_P) ? r[e] + beta * (ps[e] - omega * v[e]) : r[e] - alpha * v[e];
-        ps[e] = val;
-        x1[e] = c2 * val / ir.k7[7 * row];
-    }
-}
-
-// Solution and residual updates of Alg. 1: x += alpha p^ + omega s^, r = s - omega t, partials of (r0, r) and of
-// ||D^-1 r||^2 (D = diag B; regular rows in the flat part, irregular rows by the leading
-// blocks); the finalize kernel forms beta and tests convergence.
-template <typename T>
-__global__ void __launch_bounds__(NT) k_update(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
-                                               T *__restrict__ xs, const T *__restrict__ ph, const T *__restrict__ sh,
-                                               const T *__restrict__ s, const T *__restrict__ t,
-                                               const T *__restrict__ r0, T *__restrict__ r, DevState *st,
-                                               double *partials, unsigned *ticket, int nblocks)
-{
-    if (st->done) return;
-    constexpr int VN = Vec16<T>::n;
-    const double alpha = st->alpha, omega = st->omega;
-    const T alphaT = (T)alpha, omegaT = (T)omega;
-    double acc[2] = {0.0, 0.0};
-    const int tid = threadIdx.x + threadIdx.y * TX;
-    const int nx = g.nx, ny = g.ny;
-    const size_t nn = (size_t)nx * ny * g.nz;
-    const int nib = irr_blocks(ir.n, NT);
-    const int b = (int)blockIdx.x - nib;
-    if (b >= 0) {
-        const size_t ngroups = nn / VN;
-        for (size_t q = (size_t)b * NT + tid; q < ngroups; q += (size_t)g.nflat * NT) {
-            const size_t base = q * VN;
-            T xv[VN], pv[VN], shv[VN], sv[VN], tv[VN], r0v[VN], rv[VN];
-            load16(xs + base, xv);
-            load16_last(ph + base, pv);
-            load16_last(sh + base, shv);
-            load16_last(s + base, sv);
-            load16_last(t + base, tv);
-            load16(r0 + base, r0v);
-            NodeIt it(base, nx, ny);
-#pragma unroll
-            for (int u = 0; u < VN; ++u) {
-                xv[u] = xv[u] + (alphaT * pv[u] + omegaT * shv[u]);
-                rv[u] = sv[u] - omegaT * tv[u];
-                acc[0] += (double)r0v[u] * (double)rv[u];
-                if (!skip_bit(skip, g, it.i, it.j, it.k)) {
-                    double d = (double)cf.c[0][8 * it.i + 3] + (double)cf.c[1][8 * it.j + 3] + (double)cf.c[2][8 * it.k + 3];
-                    double rd = (double)rv[u] / d;
-                    acc[1] += rd * rd;
-                }
-                it.next(nx, ny);
-            }
-            store16(xs + base, xv);
-            store16(r + base, rv);
-        }
-    } else {
-        const int row = (int)blockIdx.x * NT + tid;
-        if (row < ir.n) {
-            const int e = ir.node[row];
-            T rv = s[e] - omegaT * t[e];
-            double rd = (double)rv / (double)ir.bdiag[row];
-            acc[1] += rd * rd;
-        }
-    }
-    write_partials<2>(acc, partials);
 }
 
 // (re)start: r0 = r, p = v = 0, rho = (r, r); the recursive norm starts from the true one
@@ -1010,25 +1006,28 @@ template <typename T, typename TO>
 void launch_apply(int mode, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, TO *y, const T *w,
                   const double *bvec, DevState *st)
 {
-    int nb = L.g.t8.nblk + irr_blocks(ir.n, NT / IRR_LANES);
+    int nb = L.g.ta.nblk + irr_blocks(ir.n, NT / IRR_LANES);
     dim3 grid(nb), blk = tile_block();
+#define CPS_APPLY_LAUNCH(M) \
+    k_apply4<T, TO, M><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, y, w, bvec, st, L.partials)
     switch (mode) {
     case MODE_PLAIN:
-        k_apply<T, TO, MODE_PLAIN><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, y, w, bvec, st, L.partials, L.ticket, nb);
+        CPS_APPLY_LAUNCH(MODE_PLAIN);
         break;
     case MODE_V:
-        k_apply<T, TO, MODE_V><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, y, w, bvec, st, L.partials, L.ticket, nb);
+        CPS_APPLY_LAUNCH(MODE_V);
         finalize<FIN_V>(L, nb, st);
         break;
     case MODE_T:
-        k_apply<T, TO, MODE_T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, y, w, bvec, st, L.partials, L.ticket, nb);
+        CPS_APPLY_LAUNCH(MODE_T);
         finalize<FIN_T>(L, nb, st);
         break;
     case MODE_RES:
-        k_apply<T, TO, MODE_RES><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, y, w, bvec, st, L.partials, L.ticket, nb);
+        CPS_APPLY_LAUNCH(MODE_RES);
         finalize<FIN_RES>(L, nb, st);
         break;
     }
+#undef CPS_APPLY_LAUNCH
 }
 
 template <typename T>
@@ -1059,11 +1058,11 @@ template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st)
 {
-    dim3 grid(L.g.nflat + irr_blocks(ir.n, NT)), blk = tile_block();
+    dim3 grid(L.g.ta.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
     if (kind == FIRST_P)
-        k_first<T, FIRST_P><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, r, ps, v, x1, (T)c2, st);
+        k_first4<T, FIRST_P><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, r, ps, v, x1, (T)c2, st);
     else
-        k_first<T, FIRST_S><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, r, ps, v, x1, (T)c2, st);
+        k_first4<T, FIRST_S><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, r, ps, v, x1, (T)c2, st);
 }
 
 template <typename T, typename TX_>
@@ -1071,9 +1070,9 @@ void launch_update(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, TX_ *xs
                    const T *t, const T *r0, T *r, DevState *st)
 {
     static_assert(sizeof(T) == sizeof(TX_), "solution and Krylov vectors share a precision");
-    int nb = L.g.nflat + irr_blocks(ir.n, NT);
-    k_update<T><<<dim3(nb), tile_block(), 0, L.stream>>>(L.g, cf, ir, L.skip, (T *)xs, ph, sh, s, t, r0, r, st,
-                                                         L.partials, L.ticket, nb);
+    int nb = L.g.ta.nblk + irr_blocks(ir.n, NT);
+    k_update4<T><<<dim3(nb), tile_block(), 0, L.stream>>>(L.g, cf, ir, L.skip, (T *)xs, ph, sh, s, t, r0, r, st,
+                                                          L.partials);
     finalize<FIN_UPDATE>(L, nb, st);
 }
 
