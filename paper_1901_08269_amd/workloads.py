@@ -195,6 +195,67 @@ def fourier_field(seed, K, x, y, z):
 
 
 # ----------------------------------------------------------------------------------------
+# the same level sets and sources on the GPU (torch, FP64), for grids too large for the
+# CPU generators (512^3: 136 M nodes)
+# ----------------------------------------------------------------------------------------
+def union_level_torch(bodies, x, y, z, device="cuda"):
+    """union_level evaluated with torch on `device`; same formulas, shape (nz, ny, nx)."""
+    import torch
+    Z = torch.as_tensor(np.asarray(z, dtype=np.float64), device=device)[:, None, None]
+    Y = torch.as_tensor(np.asarray(y, dtype=np.float64), device=device)[None, :, None]
+    X = torch.as_tensor(np.asarray(x, dtype=np.float64), device=device)[None, None, :]
+    phi = torch.full((len(z), len(y), len(x)), float("inf"), dtype=torch.float64, device=device)
+    for b in bodies:
+        if isinstance(b, Sphere):
+            lv = torch.sqrt((X - b.c[0]) ** 2 + (Y - b.c[1]) ** 2 + (Z - b.c[2]) ** 2) - b.r
+        elif isinstance(b, Ellipsoid):
+            d = [X - b.c[0], Y - b.c[1], Z - b.c[2]]
+            acc = 0.0
+            for a in range(3):
+                q = float(b.rot[0, a]) * d[0] + float(b.rot[1, a]) * d[1] + float(b.rot[2, a]) * d[2]
+                acc = acc + (q / b.semi[a]) ** 2
+            lv = (torch.sqrt(acc) - 1.0) * min(b.semi)
+        elif isinstance(b, Star):
+            dx, dy, dz = X - b.c[0], Y - b.c[1], Z - b.c[2]
+            rho = torch.sqrt(dx * dx + dy * dy + dz * dz)
+            cos_t = torch.where(rho > 0, dz / torch.where(rho > 0, rho, torch.ones_like(rho)), torch.ones_like(rho))
+            theta = torch.arccos(torch.clamp(cos_t, -1.0, 1.0))
+            az = torch.atan2(dy, dx)
+            lv = rho - b.r0 * (1.0 + b.amp * torch.sin(5.0 * theta) * torch.cos(3.0 * az))
+        else:
+            raise TypeError(type(b))
+        phi = torch.minimum(phi, lv)
+    return phi
+
+
+def fourier_field_torch(seed, K, x, y, z, device="cuda"):
+    """fourier_field evaluated with torch on `device`, plane by plane."""
+    import torch
+    ks, amp, ph = fourier_modes(seed, K)
+    kt, at, pt = (torch.as_tensor(a, device=device) for a in (ks, amp, ph))
+    xt, yt, zt = (torch.as_tensor(np.asarray(a, dtype=np.float64), device=device) for a in (x, y, z))
+    Xc = torch.cos(PI * kt[:, 0:1] * xt[None, :] + pt[:, 0:1])
+    Yc = torch.cos(PI * kt[:, 1:2] * yt[None, :] + pt[:, 1:2])
+    Zc = torch.cos(PI * kt[:, 2:3] * zt[None, :] + pt[:, 2:3])
+    out = torch.empty((len(z), len(y), len(x)), dtype=torch.float64, device=device)
+    for k in range(len(z)):
+        out[k] = (Yc * (at * Zc[:, k])[:, None]).T @ Xc
+    return out
+
+
+def bodies16_fourier_torch(N: int = 512, beta: float = 2.0, seed: int = 1, K: int = 16, device="cuda"):
+    """The inputs of bodies16_fourier generated on the GPU: (x, bodies, phi, g, f), the last
+    three torch tensors on `device`."""
+    import torch
+    x = tanh_grid(N + 2, beta)
+    hc = float(np.max(np.diff(x)))
+    bodies = sample_bodies(seed, 8, 8, (0.04, 0.1), (0.04, 0.12), gap=6 * hc)
+    phi = union_level_torch(bodies, x, x, x, device)
+    f = fourier_field_torch(seed, K, x, x, x, device)
+    return x, bodies, phi, torch.zeros_like(f), f
+
+
+# ----------------------------------------------------------------------------------------
 # workloads
 # ----------------------------------------------------------------------------------------
 @dataclass

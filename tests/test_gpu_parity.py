@@ -352,3 +352,107 @@ def test_spheres8_256_mixed_vs_oracle_samples():
     rel = np.max(np.abs(_np(u).ravel()[nodes] - vals)) / umax
     print(f"fp64: max rel. difference vs oracle samples: {rel:.2e}")
     assert rel <= 1e-9
+
+
+def test_star_fourier_128_vs_oracle_samples():
+    """128^3, star-shaped body, random Fourier f, g = 0 (the learned warm start's family, at
+    its full size): the plain FP64 and the mixed solution at tol 1e-13 against the FP64
+    oracle solved to 1e-13, on the stored samples (every 7th irregular node plus uniformly
+    drawn fluid nodes).  The star's thin arms make short marches (fallback lines), which
+    both sides count alike."""
+    nodes, vals, umax = _samples("oracle_star_fourier_128.txt")
+    fb = None
+    for line in open(os.path.join(GOLD, "oracle_star_fourier_128.txt")):
+        if line.startswith("# info"):
+            fb = int(line.split("'fallback_lines': ")[1].split(",")[0])
+    w = W.star_fourier(128)
+    for prec in ("fp64", "mixed"):
+        print(f"[case] star_fourier 128 {prec}", flush=True)
+        S = cps.Solver.from_workload(w, precision=prec)
+        u, st = S.solve(1e-13)
+        assert st["rel_residual"] <= 1e-13 and st["rel_residual_jacobi"] <= 1e-13
+        assert st["fallback_lines"] == fb
+        rel = np.max(np.abs(_np(u).ravel()[nodes] - vals)) / umax
+        print(f"{prec}: max rel. difference vs oracle samples: {rel:.2e}")
+        assert rel <= 1e-9
+        S.close()
+
+
+def _subbox(x, body, margin):
+    """Index range [lo, hi] per axis covering the body's bounding sphere plus `margin` cells."""
+    lo, hi = [], []
+    for d in range(3):
+        a = int(np.searchsorted(x, body.c[d] - body.bound)) - margin
+        b = int(np.searchsorted(x, body.c[d] + body.bound)) + margin
+        lo.append(max(a, 0))
+        hi.append(min(b, len(x) - 1))
+    return lo, hi
+
+
+def test_bodies16_512_rows_vs_oracle():
+    """512^3, 8 spheres + 8 rotated ellipsoids, Fourier f with 2445 modes, g = 0: the scale
+    configuration, too large for an oracle solve.  The GPU's mixed solution to 1e-10 is
+    checked against the oracle's own system, row by row: around two bodies the oracle builds
+    the problem on a sub-box of the grid (its rows at least 6 cells inside the sub-box only
+    see nodes of the sub-box, and every row of the discretisation is local), and at every
+    irregular row and 2000 regular rows there it forms b_i - (B u)_i with the GPU solution.
+    Relative to the row's scale |b_i| + sum_j |B_ij u_j| these residuals must stay at the
+    solve's tolerance (1e-10; measured up to 2e-12), which a wrong coefficient anywhere in a
+    sampled row would exceed.  One sub-box around a sphere, one around an ellipsoid."""
+    import torch
+    x, bodies, phi, g, f = W.bodies16_fourier_torch(512)
+    n = len(x)
+    print("[case] bodies16_fourier 512 mixed", flush=True)
+    S = cps.Solver(x, x, x, phi, g, f, precision="mixed")
+    u, st = S.solve(1e-10)
+    assert st["rel_residual"] <= 1e-10 and st["rel_residual_jacobi"] <= 1e-10
+    assert st["fallback_lines"] == 0
+    S.close()
+    uflat = u.reshape(-1)
+    rng = np.random.Generator(np.random.PCG64(7))
+    done = set()
+    for b in bodies:
+        kind = type(b).__name__
+        if kind in done:
+            continue   # one sphere and one ellipsoid
+        lo, hi = _subbox(x, b, 8)
+        sl = (slice(lo[2], hi[2] + 1), slice(lo[1], hi[1] + 1), slice(lo[0], hi[0] + 1))
+        ph = phi[sl].cpu().numpy()
+        faces = [ph[0], ph[-1], ph[:, 0], ph[:, -1], ph[:, :, 0], ph[:, :, -1]]
+        if min(float(a.min()) for a in faces) <= 0.0:
+            continue   # another body crosses the sub-box boundary
+        xs, ys, zs = x[lo[0]:hi[0] + 1], x[lo[1]:hi[1] + 1], x[lo[2]:hi[2] + 1]
+        P = oracle.Problem(xs, ys, zs, ph, g[sl].cpu().numpy(), f[sl].cpu().numpy())
+        t = P.types()
+        nz_, ny_, nx_ = t.shape
+        K, J, I = np.meshgrid(np.arange(nz_), np.arange(ny_), np.arange(nx_), indexing="ij")
+        inner = (I >= 6) & (I <= nx_ - 7) & (J >= 6) & (J <= ny_ - 7) & (K >= 6) & (K <= nz_ - 7)
+        irr = np.nonzero((t == 2) & inner)
+        reg = np.nonzero((t == 1) & inner)
+        pick = rng.choice(len(reg[0]), size=min(2000, len(reg[0])), replace=False)
+        rows = [(k, j, i) for k, j, i in zip(*irr)] + [(reg[0][q], reg[1][q], reg[2][q]) for q in pick]
+        bsub = P.rhs()
+        cols_all, vals_all, owner = [], [], []
+        bvals = np.empty(len(rows))
+        for r, (k, j, i) in enumerate(rows):
+            e = int(i + nx_ * (j + ny_ * k))
+            c, v = P.row(e)
+            cols_all.append(c)
+            vals_all.append(v)
+            owner.append(np.full(len(c), r))
+            bvals[r] = bsub[k, j, i]
+        cols = np.concatenate(cols_all)
+        ci, cj, ck = cols % nx_, (cols // nx_) % ny_, cols // (nx_ * ny_)
+        full = (ci + lo[0]) + n * ((cj + lo[1]) + n * (ck + lo[2]))
+        uval = uflat[torch.as_tensor(full, device=uflat.device)].cpu().numpy()
+        vals = np.concatenate(vals_all)
+        own = np.concatenate(owner)
+        bu = np.bincount(own, weights=vals * uval, minlength=len(rows))
+        scale = np.abs(bvals) + np.bincount(own, weights=np.abs(vals * uval), minlength=len(rows))
+        ratio = np.max(np.abs(bvals - bu) / scale)
+        print(f"body {type(b).__name__} box {[h - l + 1 for l, h in zip(lo, hi)]}: {len(irr[0])} irregular "
+              f"+ {len(pick)} regular rows, max |b - Bu| / scale = {ratio:.2e}")
+        assert len(irr[0]) > 100
+        assert ratio <= 1e-10
+        done.add(kind)
+    assert done == {"Sphere", "Ellipsoid"}
