@@ -189,6 +189,11 @@ __global__ void k_scan(const int *__restrict__ in, int *__restrict__ out, int n)
 
 void launch_scan(hipStream_t s, const int *in, int *out, int n) { k_scan<<<1, 1024, 0, s>>>(in, out, n); }
 
+__global__ void k_copy_count(const int *__restrict__ src, int *__restrict__ dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
 void launch_compact(hipStream_t s, size_t n, const int8_t *type, int8_t want, int *blockcnt, int *list, int *count,
                     int nblocks)
 {
@@ -196,7 +201,7 @@ void launch_compact(hipStream_t s, size_t n, const int8_t *type, int8_t want, in
     k_count<<<nblocks, CMP_THREADS, 0, s>>>(n, type, want, blockcnt);
     k_scan<<<1, 1024, 0, s>>>(blockcnt, blockcnt + nblocks, nblocks);
     k_scatter<<<nblocks, CMP_THREADS, 0, s>>>(n, type, want, blockcnt + nblocks, list);
-    hipMemcpyAsync(count, blockcnt + 2 * nblocks, sizeof(int), hipMemcpyDeviceToDevice, s);
+    k_copy_count<<<1, 64, 0, s>>>(blockcnt + 2 * nblocks, count);   // the total, on the device
 }
 
 // skip bits: solid or irregular interior nodes
@@ -287,17 +292,24 @@ __device__ __forceinline__ int slot_of(const int o[3])
     return 27 + (((far * 2 + (o[far] > 0)) * 4 + (m - 2)) * 9 + (o[d1] + 1) * 3 + (o[d2] + 1));
 }
 
-// Interpolating polynomial of degree m-1 through (ts, vs) in Newton form (in place).
-__device__ void newton_coeffs(int m, const double *ts, double *c)
+// Interpolating polynomial of degree M-1 through (ts, vs) in Newton form (in place).  The
+// point count is a template parameter so that every array index is static and the arrays
+// stay in registers (a dynamically indexed private array lives in slow scratch memory).
+template <int M>
+__device__ __forceinline__ void newton_coeffs(const double (&ts)[M], double (&c)[M])
 {
-    for (int lvl = 1; lvl < m; ++lvl)
-        for (int q = m - 1; q >= lvl; --q) c[q] = (c[q] - c[q - 1]) / (ts[q] - ts[q - lvl]);
+#pragma unroll
+    for (int lvl = 1; lvl < M; ++lvl)
+#pragma unroll
+        for (int q = M - 1; q >= lvl; --q) c[q] = (c[q] - c[q - 1]) / (ts[q] - ts[q - lvl]);
 }
 
-__device__ double newton_eval(int m, const double *ts, const double *c, double t, double *deriv)
+template <int M>
+__device__ __forceinline__ double newton_eval(const double (&ts)[M], const double (&c)[M], double t, double *deriv)
 {
-    double p = c[m - 1], dp = 0.0;
-    for (int q = m - 2; q >= 0; --q) {
+    double p = c[M - 1], dp = 0.0;
+#pragma unroll
+    for (int q = M - 2; q >= 0; --q) {
         dp = dp * (t - ts[q]) + p;
         p = p * (t - ts[q]) + c[q];
     }
@@ -305,24 +317,22 @@ __device__ double newton_eval(int m, const double *ts, const double *c, double t
     return p;
 }
 
-// IBI on the segment between node index `ifl` (fluid) and `isol` (solid) of the grid line
-// along d through node `line0` (index 0 along d); returns its coordinate, g there, and the
-// fraction of the segment between the fluid node and the IBI.
-__device__ double ibi_on_segment(const Ctx &C, int d, size_t line0, int ifl, int isol, double *gval, double *frac)
+// IBI between grid indices `ifl` (fluid) and `isol` (solid) on the line along d through
+// node `line0`, from the M-point window starting at index lo.
+template <int M>
+__device__ __forceinline__ double ibi_window(const Ctx &C, int d, size_t line0, int lo, int ifl, int isol, double *gval,
+                                             double *frac)
 {
-    int n = C.n[d];
-    int m = n < 6 ? n : 6;
-    int lo = min(ifl, isol) - 2;
-    lo = max(0, min(lo, n - m));
-    double ts[6], cp[6], cg[6];
-    for (int q = 0; q < m; ++q) {
+    double ts[M], cp[M], cg[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
         size_t node = line0 + (size_t)(lo + q) * C.stride[d];
         ts[q] = C.t[d][lo + q];
         cp[q] = C.phi[node];
         cg[q] = C.g[node];
     }
-    newton_coeffs(m, ts, cp);
-    newton_coeffs(m, ts, cg);
+    newton_coeffs<M>(ts, cp);
+    newton_coeffs<M>(ts, cg);
     double tf = C.t[d][ifl], tsol = C.t[d][isol];
     double root;
     if (C.phi[line0 + (size_t)isol * C.stride[d]] == 0.0) {
@@ -332,7 +342,7 @@ __device__ double ibi_on_segment(const Ctx &C, int d, size_t line0, int ifl, int
         double a = tf, b = tsol;
         root = 0.5 * (a + b);
         for (int it = 0; it < 200; ++it) {
-            double dv, v = newton_eval(m, ts, cp, root, &dv);
+            double dv, v = newton_eval<M>(ts, cp, root, &dv);
             if (v > 0.0) a = root; else b = root;
             double nxt = (dv != 0.0) ? root - v / dv : 0.5 * (a + b);
             bool inside = (a < b) ? (nxt > a && nxt < b) : (nxt < a && nxt > b);
@@ -341,35 +351,106 @@ __device__ double ibi_on_segment(const Ctx &C, int d, size_t line0, int ifl, int
             root = nxt;
         }
     }
-    *gval = newton_eval(m, ts, cg, root, nullptr);
+    *gval = newton_eval<M>(ts, cg, root, nullptr);
     *frac = fabs(root - tf) / fabs(tsol - tf);
     return root;
 }
 
-// Solve the m x m system A w = rhs (row-major, destroyed) by elimination with row pivoting.
-__device__ bool small_solve(int m, double *A, double *rhs, double *w)
+// IBI on the segment between node index `ifl` (fluid) and `isol` (solid) of the grid line
+// along d through node `line0` (index 0 along d); returns its coordinate, g there, and the
+// fraction of the segment between the fluid node and the IBI.  The interpolation window
+// holds min(n, 6) nodes around the segment, shifted to stay in the grid.
+__device__ double ibi_on_segment(const Ctx &C, int d, size_t line0, int ifl, int isol, double *gval, double *frac)
 {
-    for (int c = 0; c < m; ++c) {
+    int n = C.n[d];
+    int m = n < 6 ? n : 6;
+    int lo = min(ifl, isol) - 2;
+    lo = max(0, min(lo, n - m));
+    switch (m) {
+    case 6: return ibi_window<6>(C, d, line0, lo, ifl, isol, gval, frac);
+    case 5: return ibi_window<5>(C, d, line0, lo, ifl, isol, gval, frac);
+    case 4: return ibi_window<4>(C, d, line0, lo, ifl, isol, gval, frac);
+    default: return ibi_window<3>(C, d, line0, lo, ifl, isol, gval, frac);
+    }
+}
+
+// Solve the NP x NP system A w = rhs by elimination with row pivoting (row swaps by
+// selects over static indices, so that A stays in registers).
+template <int NP>
+__device__ __forceinline__ bool small_solve(double (&A)[NP][NP], double (&rhs)[NP], double (&w)[NP])
+{
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
         int pr = c;
-        double best = fabs(A[c * m + c]);
-        for (int r = c + 1; r < m; ++r)
-            if (fabs(A[r * m + c]) > best) { best = fabs(A[r * m + c]); pr = r; }
+        double best = fabs(A[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < NP; ++r)
+            if (fabs(A[r][c]) > best) { best = fabs(A[r][c]); pr = r; }
         if (best == 0.0) return false;
-        if (pr != c) {
-            for (int q = 0; q < m; ++q) { double tmp = A[c * m + q]; A[c * m + q] = A[pr * m + q]; A[pr * m + q] = tmp; }
-            double tmp = rhs[c]; rhs[c] = rhs[pr]; rhs[pr] = tmp;
+#pragma unroll
+        for (int r = c + 1; r < NP; ++r) {
+            const bool sw = r == pr;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const double tc = A[c][q], tr = A[r][q];
+                A[c][q] = sw ? tr : tc;
+                A[r][q] = sw ? tc : tr;
+            }
+            const double bc = rhs[c], br = rhs[r];
+            rhs[c] = sw ? br : bc;
+            rhs[r] = sw ? bc : br;
         }
-        for (int r = c + 1; r < m; ++r) {
-            double l = A[r * m + c] / A[c * m + c];
-            for (int q = c; q < m; ++q) A[r * m + q] -= l * A[c * m + q];
+#pragma unroll
+        for (int r = c + 1; r < NP; ++r) {
+            double l = A[r][c] / A[c][c];
+#pragma unroll
+            for (int q = c; q < NP; ++q) A[r][q] -= l * A[c][q];
             rhs[r] -= l * rhs[c];
         }
     }
-    for (int r = m - 1; r >= 0; --r) {
+#pragma unroll
+    for (int r = NP - 1; r >= 0; --r) {
         double acc = rhs[r];
-        for (int q = r + 1; q < m; ++q) acc -= A[r * m + q] * w[q];
-        w[r] = acc / A[r * m + r];
+#pragma unroll
+        for (int q = r + 1; q < NP; ++q) acc -= A[r][q] * w[q];
+        w[r] = acc / A[r][r];
     }
+    return true;
+}
+
+// One-sided weights on NP points (coordinates pt) that reproduce sum over the run of
+// Ld[p] u''(x_p) for every polynomial of degree < NP: the moment conditions in coordinates
+// scaled by the reference point tref and the largest offset href.
+template <int NP>
+__device__ __forceinline__ bool onesided_weights(const double *pt, const double *tr, int plo, int phi_, const double Ld[3],
+                                                 double tref, double href, double *wout)
+{
+    double A[NP][NP], rhs[NP], w[NP];
+    double xi[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) xi[q] = (pt[q] - tref) / href;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        double s = 0.0;
+        if (m >= 2)
+            for (int p = plo; p <= phi_; ++p) {
+                double x = (tr[p] - tref) / href;
+                double pw = 1.0;
+                for (int q = 0; q < m - 2; ++q) pw *= x;
+                s += Ld[p + 1] * (double)(m * (m - 1)) * pw;
+            }
+        rhs[m] = s / (href * href);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            double pw = 1.0;
+#pragma unroll
+            for (int e = 0; e < m; ++e) pw *= xi[q];
+            A[m][q] = pw;
+        }
+    }
+    if (!small_solve<NP>(A, rhs, w)) return false;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) wout[q] = w[q];
     return true;
 }
 
@@ -407,18 +488,22 @@ __device__ __forceinline__ void put(const Ctx &C, WinList &R, size_t rownode, co
     R.add(sl, c);
 }
 
-struct Pt {
-    double t;
-    int off;       // offset along d from the window centre (grid node), or IBI marker
-    bool ibi;
-    double gval;
+// Working storage of one lane's one-sided operator: its points (coordinate, offset along
+// the line from the window centre, IBI or grid node, g at an IBI) and weights.  It lives
+// in LDS: the point list grows in a data-dependent order, and as a private array it would
+// sit in scratch memory.
+constexpr int PT_CAP = 8;
+struct PtBuf {
+    double *t, *g, *w;
+    signed char *off;
+    bool *ibi;
 };
 
 // one fluid run [plo, phi_] (positions -1..1 along d of the window centred at `wc` = row
 // offset) of a window meeting the body
 __device__ __attribute__((noinline)) void run_operator(const Ctx &C, WinList &R, size_t rownode, const int rowidx[3], int d, const int wc[3],
                              int plo, int phi_, const bool sol[3], int nruns, const double Ld[3], double W, int &fb,
-                             double &minhb, int *bad)
+                             double &minhb, int *bad, PtBuf P)
 {
     const int n = C.n[d];
     int cidx = rowidx[d];   // window centre index along d (same as the row's)
@@ -427,27 +512,33 @@ __device__ __attribute__((noinline)) void run_operator(const Ctx &C, WinList &R,
     size_t line0 = (size_t)base[0] * C.stride[0] + (size_t)base[1] * C.stride[1] + (size_t)base[2] * C.stride[2];
     bool sl = plo > -1 && sol[plo - 1 + 1];
     bool sr = phi_ < 1 && sol[phi_ + 1 + 1];
-    Pt P[8];
     int np = 0;
+    auto push = [&](double t, int off, bool ibi, double gv) {
+        P.t[np] = t;
+        P.off[np] = (signed char)off;
+        P.ibi[np] = ibi;
+        P.g[np] = gv;
+        ++np;
+    };
     bool shortened = false;
     double gv, fr;
     if (sl && sr) {
         double tl = ibi_on_segment(C, d, line0, cidx + plo, cidx + plo - 1, &gv, &fr);
         minhb = fmin(minhb, fr);
-        P[np++] = {tl, 0, true, gv};
-        for (int p = plo; p <= phi_; ++p) P[np++] = {C.t[d][cidx + p], p, false, 0.0};
+        push(tl, 0, true, gv);
+        for (int p = plo; p <= phi_; ++p) push(C.t[d][cidx + p], p, false, 0.0);
         double th = ibi_on_segment(C, d, line0, cidx + phi_, cidx + phi_ + 1, &gv, &fr);
         minhb = fmin(minhb, fr);
-        P[np++] = {th, 0, true, gv};
+        push(th, 0, true, gv);
         shortened = true;
     } else {
         const int want = (nruns == 2) ? 5 : 6;
-        for (int p = plo; p <= phi_; ++p) P[np++] = {C.t[d][cidx + p], p, false, 0.0};
+        for (int p = plo; p <= phi_; ++p) push(C.t[d][cidx + p], p, false, 0.0);
         int near = sr ? phi_ : plo;                 // run node next to the interface
         int step = sr ? -1 : 1;                     // march away from the interface
         double tb = ibi_on_segment(C, d, line0, cidx + near, cidx + near - step, &gv, &fr);
         minhb = fmin(minhb, fr);
-        P[np++] = {tb, 0, true, gv};
+        push(tb, 0, true, gv);
         int pos = sr ? plo : phi_;
         while (np < want) {
             int nxt = pos + step;
@@ -458,11 +549,11 @@ __device__ __attribute__((noinline)) void run_operator(const Ctx &C, WinList &R,
             if (ty == 3) {
                 double te = ibi_on_segment(C, d, line0, cidx + pos, gi, &gv, &fr);
                 minhb = fmin(minhb, fr);
-                P[np++] = {te, 0, true, gv};
+                push(te, 0, true, gv);
                 shortened = true;
                 break;
             }
-            P[np++] = {C.t[d][gi], nxt, false, 0.0};
+            push(C.t[d][gi], nxt, false, 0.0);
             pos = nxt;
             if (ty == 0) break;   // a wall node: known value, nothing beyond it
         }
@@ -472,36 +563,28 @@ __device__ __attribute__((noinline)) void run_operator(const Ctx &C, WinList &R,
     // moment conditions in scaled coordinates
     double tref = C.t[d][cidx + ((sl && sr) ? plo : (sr ? phi_ : plo))];
     double href = 0.0;
-    for (int q = 0; q < np; ++q) href = fmax(href, fabs(P[q].t - tref));
-    double A[64], rhs[8], w[8];
-    for (int m = 0; m < np; ++m) {
-        double s = 0.0;
-        if (m >= 2)
-            for (int p = plo; p <= phi_; ++p) {
-                double xi = (C.t[d][cidx + p] - tref) / href;
-                double pw = 1.0;
-                for (int q = 0; q < m - 2; ++q) pw *= xi;
-                s += Ld[p + 1] * (double)(m * (m - 1)) * pw;
-            }
-        rhs[m] = s / (href * href);
-        for (int q = 0; q < np; ++q) {
-            double xi = (P[q].t - tref) / href;
-            double pw = 1.0;
-            for (int e = 0; e < m; ++e) pw *= xi;
-            A[m * np + q] = pw;
-        }
+    for (int q = 0; q < np; ++q) href = fmax(href, fabs(P.t[q] - tref));
+    const double *tr = C.t[d] + cidx;
+    bool ok;
+    switch (np) {
+    case 2: ok = onesided_weights<2>(P.t, tr, plo, phi_, Ld, tref, href, P.w); break;
+    case 3: ok = onesided_weights<3>(P.t, tr, plo, phi_, Ld, tref, href, P.w); break;
+    case 4: ok = onesided_weights<4>(P.t, tr, plo, phi_, Ld, tref, href, P.w); break;
+    case 5: ok = onesided_weights<5>(P.t, tr, plo, phi_, Ld, tref, href, P.w); break;
+    case 6: ok = onesided_weights<6>(P.t, tr, plo, phi_, Ld, tref, href, P.w); break;
+    default: ok = false;
     }
-    if (!small_solve(np, A, rhs, w)) {
-        atomicOr(bad, 1);   // singular one-sided system: reported to the host
+    if (!ok) {
+        atomicOr(bad, 1);   // singular (or impossible) one-sided system: reported to the host
         return;
     }
     for (int q = 0; q < np; ++q) {
-        double c = W * w[q];
-        if (P[q].ibi) {
-            R.rhs_add(-c * P[q].gval);
+        double c = W * P.w[q];
+        if (P.ibi[q]) {
+            R.rhs_add(-c * P.g[q]);
         } else {
             int o[3] = {wc[0], wc[1], wc[2]};
-            o[d] = P[q].off;
+            o[d] = P.off[q];
             put(C, R, rownode, o, c);
         }
     }
@@ -520,6 +603,10 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
     double *__restrict__ minhb_row, int *__restrict__ fb_row, int *__restrict__ bad)
 {
     __shared__ WinList wl[BR_ROWS][27];
+    __shared__ double pt_t[BR_ROWS * BR_LANES][PT_CAP], pt_g[BR_ROWS * BR_LANES][PT_CAP],
+        pt_w[BR_ROWS * BR_LANES][PT_CAP];
+    __shared__ signed char pt_off[BR_ROWS * BR_LANES][PT_CAP];
+    __shared__ bool pt_ibi[BR_ROWS * BR_LANES][PT_CAP];
     __shared__ double qbar[BR_ROWS];
     __shared__ int wfb[BR_ROWS][27];
     __shared__ double wminhb[BR_ROWS][27];
@@ -575,8 +662,10 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
                 ++nr;
                 ++p;
             }
+            const PtBuf pb{pt_t[threadIdx.x], pt_g[threadIdx.x], pt_w[threadIdx.x], pt_off[threadIdx.x],
+                           pt_ibi[threadIdx.x]};
             for (int q = 0; q < nr; ++q)
-                run_operator(C, R, rownode, idx, d, wc, lo[q], hi[q], sol, nr, L[d], W, fb, minhb, bad);
+                run_operator(C, R, rownode, idx, d, wc, lo[q], hi[q], sol, nr, L[d], W, fb, minhb, bad, pb);
         }
         if (R.n > WIN_CAP) atomicOr(bad, 2);
         wfb[grp][lane] = fb;
