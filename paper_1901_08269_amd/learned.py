@@ -10,6 +10,7 @@ loops over batches.
 
     python -m paper_1901_08269_amd.learned train spheres8 --N 256 --train 96 --epochs 30
     python -m paper_1901_08269_amd.learned train star --N 128 --train 2000 --test 200
+    python -m paper_1901_08269_amd.learned eval spheres8 --N 256 --test 32 --report r.json
 """
 from __future__ import annotations
 
@@ -349,9 +350,22 @@ def smoke():
     m.close()
 
 
+def gain_report(rows):
+    """Mean, median and range of the iterations the warm start saves over a zero start."""
+    iz = np.array([r["iters_zero"] for r in rows])
+    iw = np.array([r["iters_warm"] for r in rows])
+    tz = np.array([r["solve_s_zero"] for r in rows])
+    tw = np.array([r["solve_s_warm"] for r in rows])
+    return {"iters_zero_mean": float(iz.mean()), "iters_warm_mean": float(iw.mean()),
+            "iters_saved_mean": float((iz - iw).mean()), "iters_saved_median": float(np.median(iz - iw)),
+            "iters_saved_range": [int((iz - iw).min()), int((iz - iw).max())],
+            "solve_s_zero_mean": float(tz.mean()), "solve_s_warm_mean": float(tw.mean()),
+            "max_rel_diff": float(max(r["diff"] for r in rows))}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train"])
+    ap.add_argument("cmd", choices=["train", "eval"])
     ap.add_argument("family", choices=["spheres8", "star"])
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--train", type=int, default=96)
@@ -360,17 +374,35 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--weights", default=None, help="eval: the weights to evaluate (default: the shipped ones)")
     ap.add_argument("--report", default=None)
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
+    te_seeds = list(range(100000, 100000 + a.test))
+    if a.cmd == "eval":
+        path = a.weights or (default_weights(a.N) if a.family == "spheres8" else
+                             os.path.join(WEIGHTS, f"warmstart_star_nc{a.N // 4}.bin"))
+        m = Model(a.N // 4, batch=1)
+        m.load(path)
+        rows = []
+        for q in range(0, len(te_seeds), 25):
+            rows += warm_start_gain(m, a.family, a.N, te_seeds[q:q + 25])
+            log(f"  evaluated {len(rows)}/{len(te_seeds)}")
+        rep = {"family": a.family, "N": a.N, "weights": os.path.basename(path), "test": a.test,
+               "precision": "mixed", "tol": 1e-10, **gain_report(rows), "rows": rows}
+        log(json.dumps({k: v for k, v in rep.items() if k != "rows"}))
+        if a.report:
+            with open(a.report, "w") as fh:
+                json.dump(rep, fh, indent=1)
+        return
+
     # training seeds 0..; test seeds from 100000; the benchmark problem (spheres8 seed 0 with
     # its own u) is neither, its geometry seed 0 is excluded from training
     base = 1000 if a.family == "spheres8" else 0
     tr_seeds = list(range(base, base + a.train))
-    te_seeds = list(range(100000, 100000 + a.test))
     log(f"generating {a.train} training instances ({a.family}, N={a.N})")
     X, Y = generate(a.family, a.N, tr_seeds, log=log)
     model = Model(a.N // 4, batch=a.batch, seed=1)
@@ -383,13 +415,8 @@ def main(argv=None):
     eval_model = Model(a.N // 4, batch=1)
     eval_model.load(out)
     rows = warm_start_gain(eval_model, a.family, a.N, te_seeds)
-    iz = np.array([r["iters_zero"] for r in rows])
-    iw = np.array([r["iters_warm"] for r in rows])
     rep = {"family": a.family, "N": a.N, "train": a.train, "test": a.test, "epochs": a.epochs, "steps": steps,
-           "train_s": secs, "final_loss": hist[-1], "loss_history": hist,
-           "iters_zero_mean": float(iz.mean()), "iters_warm_mean": float(iw.mean()),
-           "iters_saved_mean": float((iz - iw).mean()), "iters_saved_median": float(np.median(iz - iw)),
-           "iters_saved_range": [int((iz - iw).min()), int((iz - iw).max())], "rows": rows}
+           "train_s": secs, "final_loss": hist[-1], "loss_history": hist, **gain_report(rows), "rows": rows}
     log(json.dumps({k: v for k, v in rep.items() if k not in ("rows", "loss_history")}))
     if a.report:
         with open(a.report, "w") as fh:

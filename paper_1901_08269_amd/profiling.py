@@ -1,8 +1,11 @@
 """Summaries of rocprofv3 result databases as short markdown.
 
-Two reports:
+Three reports:
 
 ``stats``    per-kernel call counts and durations from a ``--kernel-trace --stats`` run.
+``kernels``  the solve kernels of such a run against the HBM roofline: algorithmic bytes
+             per interior point (each operand read or written once), GB/s from the average
+             launch duration, fraction of the 8 TB/s peak.
 ``traffic``  HBM bytes per launch of one kernel from two ``--pmc`` runs (``FETCH_SIZE`` and
              ``WRITE_SIZE``, each in its own pass), each counter scaled by what the same counter
              reads for a plain device copy of known size (the calibration runs).  The report
@@ -12,6 +15,7 @@ Two reports:
 Usage::
 
     python -m paper_1901_08269_amd.profiling stats DB --title T --cmd C [--top 20]
+    python -m paper_1901_08269_amd.profiling kernels DB --points P --title T --cmd C
     python -m paper_1901_08269_amd.profiling traffic --fetch DB --write DB \\
         --copy-fetch DB --copy-write DB --copy-bytes B --kernel NAME --units U --unit-bytes UB \\
         --title T --cmd C
@@ -67,6 +71,55 @@ def stats_report(db, title, cmd, top=20):
            "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
     for n, c, t, a, p in kernel_stats(db)[:top]:
         out.append(f"| `{short_name(n)}` | {c} | {t:.1f} | {a:.2f} | {p:.1f} |")
+    return "\n".join(out) + "\n"
+
+
+HBM_PEAK_GBS = 8000.0
+_SIZE = {"float": 4, "double": 8}
+
+
+def algorithmic_bytes(name):
+    """Bytes per interior point that a solve kernel must move (each operand once), or None.
+
+    k_cheb4       one Chebyshev step: x_k, x_{k-1}, rho in, x_{k+1} out (no x_{k-1}: first step)
+    k_first4      p = r + beta (p - omega v) (P) or s = r - alpha v (S), and x_1 = c p / diag K
+    k_apply4      y = B x with a second operand (V, T), y = B x (plain), r = b - B x (residual)
+    k_update4     x += alpha p^ + omega s^, r = s - omega t, with (r0, r)
+    """
+    n = short_name(name)
+    m = re.match(r"cps::(k_cheb4|k_first4|k_apply4|k_update4)<(.*)>$", n)
+    if not m:
+        return None
+    kern, args = m.group(1), [a.strip() for a in m.group(2).split(",")]
+    t = _SIZE.get(args[0])
+    if t is None:
+        return None
+    if kern == "k_cheb4":
+        return (3 if args[1] == "true" else 4) * t
+    if kern == "k_first4":
+        return (5 if args[1] == "0" else 4) * t
+    if kern == "k_update4":
+        return 8 * t
+    to, mode = _SIZE[args[1]], int(args[2])
+    if mode == 0:
+        return t + to
+    if mode in (1, 2):
+        return 2 * t + to
+    return t + 8 + to       # residual: x and b (FP64) in, r out
+
+
+def kernels_report(db, points, title, cmd):
+    out = [f"# {title}", "", "Command (run from the repository root on an MI355X):", "", "```", cmd, "```", "",
+           f"Solve kernels from `rocprofv3 --kernel-trace --stats`, {points} interior points per launch; "
+           "algorithmic bytes count each operand once per point (tables, halos, bits and the irregular "
+           f"rows as overhead); GB/s = bytes per launch / average duration; peak {HBM_PEAK_GBS:.0f} GB/s.", "",
+           "| kernel | calls | avg us | B / point | GB/s | of peak |", "|---|---:|---:|---:|---:|---:|"]
+    for n, c, t, a, p in kernel_stats(db):
+        b = algorithmic_bytes(n)
+        if b is None:
+            continue
+        gbs = b * points / (a * 1e-6) / 1e9
+        out.append(f"| `{short_name(n)}` | {c} | {a:.2f} | {b} | {gbs:.0f} | {gbs / HBM_PEAK_GBS:.2f} |")
     return "\n".join(out) + "\n"
 
 
@@ -126,6 +179,11 @@ def main(argv=None):
     s.add_argument("--title", required=True)
     s.add_argument("--cmd", required=True)
     s.add_argument("--top", type=int, default=20)
+    k = sub.add_parser("kernels")
+    k.add_argument("db")
+    k.add_argument("--points", type=int, required=True)
+    k.add_argument("--title", required=True)
+    k.add_argument("--cmd", required=True)
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "title", "cmd"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
@@ -135,6 +193,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.mode == "stats":
         print(stats_report(a.db, a.title, a.cmd, a.top), end="")
+    elif a.mode == "kernels":
+        print(kernels_report(a.db, a.points, a.title, a.cmd), end="")
     else:
         print(traffic_report(a), end="")
 
