@@ -51,3 +51,31 @@ def test_stats_report(tmp_path):
     con.close()
     rep = profiling.stats_report(str(db), "T", "cmd")
     assert "| `cps::k_update<float>` | 4 | 400.0 | 100.00 | 55.0 |" in rep
+
+
+def test_algorithmic_bytes_per_kernel():
+    ab = profiling.algorithmic_bytes
+    assert ab("void cps::k_cheb4<float, false>(cps::Geom, int)") == 16
+    assert ab("void cps::k_cheb4<float, true>(cps::Geom, int)") == 12
+    assert ab("void cps::k_cheb4<double, false>(cps::Geom, int)") == 32
+    assert ab("void cps::k_first4<float, 0>(cps::Geom)") == 20
+    assert ab("void cps::k_first4<float, 1>(cps::Geom)") == 16
+    assert ab("void cps::k_update4<double>(cps::Geom)") == 64
+    assert ab("void cps::k_apply4<float, float, 1>(cps::Geom)") == 12
+    assert ab("void cps::k_apply4<double, float, 3>(cps::Geom)") == 20
+    assert ab("void cps::k_apply4<double, double, 0>(cps::Geom)") == 16
+    assert ab("void cps::k_finalize<0>(double const*, int, cps::DevState*)") is None
+
+
+def test_kernels_report(tmp_path):
+    db = tmp_path / "s.db"
+    con = sqlite3.connect(db)
+    con.execute("create table top_kernels (name text, total_calls int, total_duration real, average real, percentage real)")
+    con.execute("insert into top_kernels values ('void cps::k_cheb4<float, false>(cps::Geom, int)', 10, 400.0, 40.0, 90.0)")
+    con.execute("insert into top_kernels values ('void cps::k_fill<float>(unsigned long, float*, float)', 2, 40.0, 20.0, 10.0)")
+    con.commit()
+    con.close()
+    rep = profiling.kernels_report(str(db), 1000000, "T", "cmd")
+    # 16 B x 1e6 points in 40 us = 400 GB/s = 0.05 of 8 TB/s
+    assert "| `cps::k_cheb4<float, false>` | 10 | 40.00 | 16 | 400 | 0.05 |" in rep
+    assert "k_fill" not in rep
