@@ -300,6 +300,34 @@ def test_smallest_grid():
     assert abs(_np(u)[1, 1, 1] - u_ref[1, 1, 1]) <= 1e-12 * abs(u_ref[1, 1, 1])
 
 
+def test_zero_rhs_and_no_unknowns():
+    """Degenerate problems: f = g = 0 gives b = 0, which a zero start already solves (no
+    iteration, no division by ||b|| = 0, also with a nonzero warm start, which the
+    residual-based scaling sends to zero); a body filling the whole interior leaves no
+    unknown at all, and the output is g on the walls and 0 inside."""
+    x = W.uniform_grid(10)
+    Z, Y, X = W.mesh(x, x, x)
+    phi = np.ones((10, 10, 10))
+    zero = np.zeros_like(phi)
+    for prec in ("fp64", "mixed"):
+        S = cps.Solver(x, x, x, phi, zero, zero, precision=prec)
+        u, st = S.solve(1e-10)
+        assert st["status"] == 0 and st["iters"] == 0 and np.all(_np(u) == 0.0)
+        u, st = S.solve(1e-10, u0=np.ones_like(phi))
+        assert st["status"] == 0 and np.all(_np(u) == 0.0)
+        S.close()
+    phi2 = -np.ones_like(phi)
+    wall = np.zeros(phi.shape, dtype=bool)
+    wall[0], wall[-1], wall[:, 0], wall[:, -1], wall[:, :, 0], wall[:, :, -1] = True, True, True, True, True, True
+    phi2[wall] = 1.0
+    g = np.broadcast_to(1.0 + X + 2.0 * Y, phi.shape).copy()
+    S = cps.Solver(x, x, x, phi2, g, np.ones_like(phi), precision="mixed")
+    u, st = S.solve(1e-10)
+    assert st["status"] == 0 and st["n_unknowns"] == 0 and st["iters"] == 0
+    uu = _np(u)
+    assert np.array_equal(uu[wall], g[wall]) and np.all(uu[~wall] == 0.0)
+
+
 # ----------------------------------------------------------------------------------------
 # full-size workloads against stored oracle samples
 # ----------------------------------------------------------------------------------------
