@@ -49,8 +49,6 @@ struct Geom {
                                // vector updates
     Tiling tr;                 // 256 x 4 tiles: one x-row segment of 256 nodes per wavefront,
                                // four nodes per lane (vectorised Chebyshev sweeps)
-    Tiling tc;                 // 256 x 4 tiles of the fused two-step sweep (one row per
-                               // wavefront; rows of at most 256 interior nodes)
     int nflat;                 // blocks of the flat (vectorised) pointwise kernels
 };
 

@@ -26,9 +26,6 @@ template <typename T>
 void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
                  double c1, double c2, const DevState *st);
 template <typename T>
-void launch_cheb2(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xk, const T *xkm1, const T *rho,
-                  T *x1, T *x2, double c1a, double c2a, double c1b, double c2b, const DevState *st);
-template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st);
 template <typename T, typename TX_>

@@ -39,7 +39,7 @@ constexpr int MAX_INNER = 64;
 template <typename T>
 struct Vecs {
     T *r = nullptr, *r0 = nullptr, *p = nullptr, *ph = nullptr, *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr;
-    T *x = nullptr, *c[4] = {nullptr, nullptr, nullptr, nullptr};
+    T *x = nullptr, *c[2] = {nullptr, nullptr};
     bool ready = false;
 };
 
@@ -293,9 +293,6 @@ Tiling make_tiling(int nx, int ny, int nz, int tw, int ty, int target_blocks, in
 #ifndef CPS_APPLY_ZCHUNKS
 #define CPS_APPLY_ZCHUNKS 16
 #endif
-#ifndef CPS_FUSED_BLOCKS
-#define CPS_FUSED_BLOCKS 2048
-#endif
 #ifndef CPS_FLAT_BLOCKS
 #define CPS_FLAT_BLOCKS 4096
 #endif
@@ -313,7 +310,6 @@ Geom make_geom(int nx, int ny, int nz)
         const int per_plane = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY * RPW - 1) / (TY * RPW));
         g.tr = make_tiling(nx, ny, nz, 4 * TX, TY * RPW, per_plane * CPS_ROW_ZCHUNKS, 4);
     }
-    g.tc = make_tiling(nx, ny, nz, 4 * TX, TY, CPS_FUSED_BLOCKS, 4);
     size_t nn = (size_t)nx * ny * nz;
     g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, CPS_FLAT_BLOCKS);
     return g;
@@ -338,7 +334,7 @@ template <typename T>
 void alloc_vecs(cps_solver *s, Vecs<T> &V)
 {
     if (V.ready) return;
-    T **all[] = {&V.r, &V.r0, &V.p, &V.ph, &V.v, &V.s, &V.sh, &V.t, &V.x, &V.c[0], &V.c[1], &V.c[2], &V.c[3]};
+    T **all[] = {&V.r, &V.r0, &V.p, &V.ph, &V.v, &V.s, &V.sh, &V.t, &V.x, &V.c[0], &V.c[1]};
     for (T **p : all) {
         *p = dalloc<T>(s, s->nn + VEC_PAD);
         launch_fill<T>(s->stream, s->nn + VEC_PAD, *p, T(0));
@@ -367,23 +363,13 @@ hipEvent_t timed_sweep_begin(cps_solver *s)
     return e1;
 }
 
-// Fused two-step sweeps (k_cheb2w) for the Chebyshev recursion; 0 (the default) runs every
-// step singly.  The fused sweep moves 20 instead of 32 bytes per node for two steps but needs
-// about 220 registers per lane (two wavefronts per SIMD); on MI355X at 256^3 it measured
-// 114 us per pair without bodies against 2 x 47 us for single sweeps, and its in-loop
-// irregular-row lookups cost more with bodies.
-#ifndef CPS_FUSED_SWEEPS
-#define CPS_FUSED_SWEEPS 0
-#endif
-#ifndef CPS_INPLACE_SWEEPS
-#define CPS_INPLACE_SWEEPS 1
-#endif
-
-// p^ = M p: inner_iters Chebyshev steps.  The first is fused with the vector update `kind`;
-// with fused sweeps the rest run two per sweep (k_cheb2w), after one single sweep when their
-// count is odd.
-// Iterate x_j (j < m) lives in V.c[j % 4]: a fused sweep reads x_{k-1}, x_k and writes
-// x_{k+1}, x_{k+2}, four distinct buffers; x_m goes to dst.
+// p^ = M p: inner_iters Chebyshev steps.  The first is fused with the vector update `kind`
+// (x_1 is pointwise from x_0 = 0); the rest are single sweeps in which x_{k+1} overwrites
+// x_{k-1} in place (each node's x_{k-1} is read only by the thread that writes its x_{k+1}),
+// so the iterates rotate through two buffers and one step touches three vectors (x_{k-1},
+// x_k and rho); x_m goes to dst.  A sweep fusing two steps (20 instead of 32 bytes per node
+// and pair) measured slower on MI355X (114 us per pair against 2 x 47 us for single sweeps at
+// 256^3, before the in-place rotation) and could not run in place, so it was removed.
 template <typename T>
 void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T *v, T *dst, const double *c1,
                    const double *c2, const DevState *st)
@@ -393,29 +379,11 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
     Irr<T> ir;
     if constexpr (sizeof(T) == 8) { cf = s->cf64(); ir = s->ir64(); } else { cf = s->cf32(); ir = s->ir32(); }
     const int m = s->opt.inner_iters;
-    auto buf = [&](int j) { return (j == m) ? dst : V.c[j % 4]; };
-    int k = 1;
-    if (!CPS_FUSED_SWEEPS || s->nx - 2 > 4 * TX) {
-        // single sweeps: x_{k+1} overwrites x_{k-1} in place (each node's x_{k-1} is read
-        // only by the thread that writes its x_{k+1}), so one step touches three vectors
-        auto buf2 = [&](int j) { return (j == m) ? dst : V.c[CPS_INPLACE_SWEEPS ? j % 2 : j % 4]; };
-        launch_first<T>(kind, L, cf, ir, r, ps, v, buf2(1), c2[0], st);
-        for (; k < m; ++k) {
-            hipEvent_t e1 = timed_sweep_begin(s);
-            launch_cheb<T>(L, cf, ir, buf2(k), (k == 1) ? nullptr : buf2(k - 1), ps, buf2(k + 1), c1[k], c2[k], st);
-            if (e1) ck(hipEventRecord(e1, s->stream));
-        }
-        return;
-    }
+    auto buf = [&](int j) { return (j == m) ? dst : V.c[j % 2]; };
     launch_first<T>(kind, L, cf, ir, r, ps, v, buf(1), c2[0], st);
-    if ((m - 1) % 2 == 1) {
-        launch_cheb<T>(L, cf, ir, buf(1), nullptr, ps, buf(2), c1[1], c2[1], st);
-        k = 2;
-    }
-    for (; k + 1 < m; k += 2) {
+    for (int k = 1; k < m; ++k) {
         hipEvent_t e1 = timed_sweep_begin(s);
-        launch_cheb2<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), buf(k + 2), c1[k], c2[k],
-                        c1[k + 1], c2[k + 1], st);
+        launch_cheb<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), c1[k], c2[k], st);
         if (e1) ck(hipEventRecord(e1, s->stream));
     }
 }
@@ -528,7 +496,7 @@ int fill_stats(cps_solver *s, cps_stats *st, const DevState &ds, int iters, int 
     }
     // a single sweep reads x_k, x_{k-1}, rho and writes x_{k+1}; a fused sweep also writes x_{k+2}
     const int vb = (s->opt.precision == CPS_MIXED) ? 4 : 8;
-    st->sweep_bytes_per_point = ((CPS_FUSED_SWEEPS && s->nx - 2 <= 4 * TX) ? 5 : 4) * vb;
+    st->sweep_bytes_per_point = 4 * vb;
     return status;
 }
 
@@ -631,13 +599,13 @@ template <typename T>
 void precond_standalone(cps_solver *s, const double *rho_dev, double *out_dev)
 {
     Vecs<T> V;
-    T *all[7];
+    T *all[5];
     for (auto &p : all) {
         p = dalloc<T>(s, s->nn + VEC_PAD);
         launch_fill<T>(s->stream, s->nn + VEC_PAD, p, T(0));
     }
-    V.c[0] = all[0]; V.c[1] = all[1]; V.c[2] = all[2]; V.c[3] = all[6];
-    T *rin = all[3], *ps = all[4], *dst = all[5];
+    V.c[0] = all[0]; V.c[1] = all[1];
+    T *rin = all[2], *ps = all[3], *dst = all[4];
     launch_masked_copy<double, T>(s->stream, s->nn, s->type, rho_dev, rin);
     // state: alpha = 0 so that the fused first step computes x1 from rho itself
     DevState zero{};
@@ -810,7 +778,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->irr_wstart = dalloc<int>(s, (size_t)s->g.W * ny * nz);
         launch_irr_words(s->stream, s->g, s->type, s->irr_node, s->nirr, s->irr_bits, s->irr_wstart);
         // reduction scratch: enough for the largest launch
-        size_t maxblk = (size_t)std::max({s->g.ta.nblk, s->g.tr.nblk, s->g.tc.nblk, s->g.nflat}) +
+        size_t maxblk = (size_t)std::max({s->g.ta.nblk, s->g.tr.nblk, s->g.nflat}) +
                         (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
         s->partials = dalloc<double>(s, 2 * maxblk);
         s->ticket = dalloc<unsigned>(s, 1);

@@ -675,181 +675,6 @@ __global__ void __launch_bounds__(NT) k_update4(Geom g, Coef<T> cf, Irr<T> ir, c
 }
 
 // ---------------------------------------------------------------------------------------
-// Two Chebyshev steps per sweep with independent wavefronts (no LDS, no barriers).
-// For rows of at most 256 interior nodes a wavefront owns one whole x-row j (four nodes per
-// lane; the x neighbours at both ends are walls, zero in every iterate) and marches in z:
-// at plane p it takes the first step on rows j - 1, j, j + 1 (its row and the two rows the
-// second step needs as y neighbours) and the second step on row j at plane p - 1, all in
-// registers.  The rows j +- 1 are recomputed by the neighbouring wavefronts; their loads hit
-// L2, while HBM sees x_k, x_{k-1}, rho once and two outputs: 20 bytes per node (FP32) for
-// two steps instead of 32.  Latency is hidden by occupancy, as in k_cheb4.  Irregular nodes
-// take their stored Shortley-Weller row (through the irregular bit words); solid nodes
-// stay zero.  Each step's arithmetic is that of k_cheb4.
-#ifdef CPS_CHEB2W_WAVES
-#define CHEB2W_ATTR __attribute__((amdgpu_waves_per_eu(CPS_CHEB2W_WAVES)))
-#else
-#define CHEB2W_ATTR
-#endif
-template <typename T, bool PREV0>
-__global__ void __launch_bounds__(NT) CHEB2W_ATTR k_cheb2w(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
-                                               const T *__restrict__ xk, const T *__restrict__ xkm1,
-                                               const T *__restrict__ rho, T *__restrict__ x1o, T *__restrict__ x2o,
-                                               T c1a, T c2a, T c1b, T c2b, const DevState *st)
-{
-    using V = typename Vec4Of<T>::type;
-    if (st && st->done) return;
-    const int lane = threadIdx.x, wv = threadIdx.y;
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const size_t plane = (size_t)nx * ny;
-    const size_t wplane = (size_t)ny * g.W;
-    const Tiling &tl = g.tc;
-    int bs, by, bz;
-    if (!tile_of_block(tl, blockIdx.x, bs, by, bz)) return;
-    const int j = 1 + by * TY + wv;
-    if (j > ny - 2) return;                                   // whole wavefront
-    const int k0 = 1 + bz * tl.TZ;
-    const int k1 = min(k0 + tl.TZ, nz - 1);                   // second-step planes [k0, k1)
-    const Seg q = seg_of(nx, 0, lane);
-    const int ic = q.nv > 0 ? q.i0 : 1;
-    const bool last = lane == TX - 1 || q.i0 + 4 >= nx - 1;
-    T kax[4], kbx[4], kcx[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const T *cx = cf.c[0] + 8 * (u < q.nv ? q.i0 + u : 1);
-        kax[u] = cx[5];
-        kbx[u] = cx[6];
-        kcx[u] = cx[7];
-    }
-    // rows j - 1, j, j + 1 (r = 0, 1, 2) and the outer y neighbours j - 2, j + 2
-    bool act[3];
-    size_t er[3], wr[3];
-    T kay[3], kby[3], kcy[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        // rows j - 1 and j + 1 lie inside the grid (0 .. ny - 1); a wall row is loaded as it
-        // is (zero in every iterate) and gets no first step
-        const int jj = j - 1 + r;
-        act[r] = jj >= 1 && jj <= ny - 2;
-        er[r] = (size_t)ic + (size_t)nx * jj;
-        wr[r] = (size_t)jj * g.W + (ic >> 5);
-        kay[r] = uniform(cf.c[1][8 * jj + 5]);
-        kby[r] = uniform(cf.c[1][8 * jj + 6]);
-        kcy[r] = uniform(cf.c[1][8 * jj + 7]);
-    }
-    const size_t em2 = (size_t)ic + (size_t)nx * max(j - 2, 0), ep2 = (size_t)ic + (size_t)nx * min(j + 2, ny - 1);
-
-    auto unpack = [](const V &v, T (&a)[4]) __attribute__((always_inline)) { a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w; };
-    // one Chebyshev step on the lane's four nodes of row jj at plane k
-    auto cheb4 = [&](const V &c4, const V &s4, const V &n4, const V &m4, const V &u4, const V &p4, const V &r4,
-                     uint32_t sk, T ky0, T ky1, T ky2, T z0, T z1, T z2, int k, int jj, T cc1, T cc2,
-                     T (&out)[4]) __attribute__((always_inline)) {
-        T cv[4], sv[4], nv[4], mv[4], uv[4], pv[4], rv[4];
-        unpack(c4, cv); unpack(s4, sv); unpack(n4, nv); unpack(m4, mv); unpack(u4, uv); unpack(p4, pv); unpack(r4, rv);
-        T left = __shfl_up(cv[3], 1, TX), right = __shfl_down(cv[0], 1, TX);
-        if (lane == 0) left = T(0);
-        if (last) right = T(0);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const T w = (u == 0) ? left : cv[u - 1];
-            const T ea = (u + 1 < q.nv) ? cv[u + 1] : right;
-            const T kd = kbx[u] + ky1 + z1;
-            const T kx = kd * cv[u] + kax[u] * w + kcx[u] * ea + ky0 * sv[u] + ky2 * nv[u] + z0 * mv[u] + z2 * uv[u];
-            out[u] = cv[u] + cc1 * (cv[u] - pv[u]) + cc2 * (rv[u] - kx) / kd;
-        }
-        if (sk != 0u) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (!((sk >> u) & 1u)) continue;
-                out[u] = T(0);
-                const int i = q.i0 + u;
-                const size_t word = ((size_t)k * ny + jj) * g.W + (i >> 5);
-                if ((ir.bits[word] >> (i & 31)) & 1u) {
-                    const T *k7 = ir.k7 + 7 * irr_row_of(ir, word, i);
-                    const T w = (u == 0) ? left : cv[u - 1];
-                    const T ea = (u + 1 < q.nv) ? cv[u + 1] : right;
-                    const T kx = k7[0] * cv[u] + k7[1] * w + k7[2] * ea + k7[3] * sv[u] + k7[4] * nv[u] + k7[5] * mv[u] +
-                                 k7[6] * uv[u];
-                    out[u] = cv[u] + cc1 * (cv[u] - pv[u]) + cc2 * (rv[u] - kx) / k7[0];
-                }
-            }
-        }
-    };
-    auto store4 = [&](T *dst, size_t e, const T (&out)[4], uint32_t sk) __attribute__((always_inline)) {
-        if (q.full && sk == 0u) {
-            V o = {out[0], out[1], out[2], out[3]};
-            *reinterpret_cast<V *>(dst + e) = o;
-        } else {
-            // regular and irregular nodes; solid nodes hold zero already
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (u < q.nv) dst[e + u] = out[u];
-        }
-    };
-    auto pack = [](const T (&a)[4]) __attribute__((always_inline)) { V v = {a[0], a[1], a[2], a[3]}; return v; };
-
-    const V zero4 = {T(0), T(0), T(0), T(0)};
-    int p = k0 - 1;
-    const size_t kpm = (size_t)max(p - 1, 0) * plane, kp0 = (size_t)p * plane;
-    V cm[3], c0[3];                                           // x_k rows at planes p - 1 and p
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        cm[r] = load4(xk, er[r] + kpm, q);
-        c0[r] = load4(xk, er[r] + kp0, q);
-    }
-    V x1mm = zero4, x1c[3] = {zero4, zero4, zero4};           // first-step rows: plane p - 2 (row j), p - 1
-    V rho_q = zero4;                                          // rho, skip, z coefficients at plane p - 1 (row j)
-    uint32_t sk_q = 0u;
-    T zq0 = T(0), zq1 = T(0), zq2 = T(0);
-    for (; p <= k1; ++p) {
-        const int pn = min(p + 1, nz - 1);
-        const size_t kp = (size_t)p * plane, kn = (size_t)pn * plane;
-        V cp[3], pr[3], rr[3];
-        uint32_t sk[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            cp[r] = load4(xk, er[r] + kn, q);
-            rr[r] = load4(rho, er[r] + kp, q);
-            pr[r] = PREV0 ? zero4 : load4(xkm1, er[r] + kp, q);
-            sk[r] = skip4(skip + (size_t)p * wplane + wr[r], ic);
-        }
-        const V ym2 = load4(xk, em2 + kp, q), yp2 = load4(xk, ep2 + kp, q);
-        const T *cz = cf.c[2] + 8 * p;
-        const T z0 = uniform(cz[5]), z1 = uniform(cz[6]), z2 = uniform(cz[7]);
-        // first step at plane p on rows j - 1, j, j + 1
-        const bool wallp = p <= 0 || p >= nz - 1;
-        V x1n[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            T out[4] = {T(0), T(0), T(0), T(0)};
-            const V &s4 = (r == 0) ? ym2 : c0[r - 1];
-            const V &n4 = (r == 2) ? yp2 : c0[r + 1];
-            if (act[r] && !wallp)
-                cheb4(c0[r], s4, n4, cm[r], cp[r], pr[r], rr[r], sk[r], kay[r], kby[r], kcy[r], z0, z1, z2, p, j - 1 + r,
-                      c1a, c2a, out);
-            x1n[r] = pack(out);
-            if (r == 1 && p >= k0 && p < k1) store4(x1o, er[1] + kp, out, sk[1]);
-        }
-        // second step at plane p - 1 on row j
-        if (p - 1 >= k0) {
-            T out[4];
-            cheb4(x1c[1], x1c[0], x1c[2], x1mm, x1n[1], cm[1], rho_q, sk_q, kay[1], kby[1], kcy[1], zq0, zq1, zq2, p - 1,
-                  j, c1b, c2b, out);
-            store4(x2o, er[1] + (size_t)(p - 1) * plane, out, sk_q);
-        }
-        x1mm = x1c[1];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            x1c[r] = x1n[r];
-            cm[r] = c0[r];
-            c0[r] = cp[r];
-        }
-        rho_q = rr[1];
-        sk_q = sk[1];
-        zq0 = z0; zq1 = z1; zq2 = z2;
-    }
-}
-
-// ---------------------------------------------------------------------------------------
 // flat pointwise kernels: threads stride over all nodes in groups of 16 bytes; wall and
 // solid entries are 0 in every vector and stay 0
 // ---------------------------------------------------------------------------------------
@@ -1042,19 +867,6 @@ void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *
 }
 
 template <typename T>
-void launch_cheb2(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xk, const T *xkm1, const T *rho,
-                  T *x1, T *x2, double c1a, double c2a, double c1b, double c2b, const DevState *st)
-{
-    dim3 grid(L.g.tc.nblk), blk = tile_block();
-    if (xkm1 == nullptr)
-        k_cheb2w<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xk, xkm1, rho, x1, x2, (T)c1a, (T)c2a,
-                                                      (T)c1b, (T)c2b, st);
-    else
-        k_cheb2w<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xk, xkm1, rho, x1, x2, (T)c1a, (T)c2a,
-                                                       (T)c1b, (T)c2b, st);
-}
-
-template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st)
 {
@@ -1135,11 +947,6 @@ template void launch_cheb<double>(const Launch &, const Coef<double> &, const Ir
                                   const double *, const double *, double *, double, double, const DevState *);
 template void launch_cheb<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
                                  const float *, float *, double, double, const DevState *);
-template void launch_cheb2<double>(const Launch &, const Coef<double> &, const Irr<double> &, const double *,
-                                   const double *, const double *, double *, double *, double, double, double, double,
-                                   const DevState *);
-template void launch_cheb2<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
-                                  const float *, float *, float *, double, double, double, double, const DevState *);
 template void launch_first<double>(int, const Launch &, const Coef<double> &, const Irr<double> &, const double *,
                                    double *, const double *, double *, double, const DevState *);
 template void launch_first<float>(int, const Launch &, const Coef<float> &, const Irr<float> &, const float *, float *,
