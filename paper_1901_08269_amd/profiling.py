@@ -27,17 +27,28 @@ import re
 import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# the sources that define the sweep kernels; a traffic report is stale once they change
-KERNEL_SOURCES = ("csrc/sweeps.hip", "csrc/cps_device.h", "csrc/cps_kernels.h")
+# what defines the measured sweep kernel: the data layout header, and in sweeps.hip the
+# Chebyshev section from its heading to the end of k_cheb4 (its helpers and the kernel);
+# a traffic report is stale once any of it changes
+KERNEL_HEADER = "csrc/cps_device.h"
+KERNEL_FILE = "csrc/sweeps.hip"
+KERNEL_START = "// Chebyshev-Jacobi steps on K phi = rho"
+KERNEL_NAME = " k_cheb4("
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
-def source_hash(files=KERNEL_SOURCES):
-    h = hashlib.sha256()
-    for f in files:
-        with open(os.path.join(HERE, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def kernel_source():
+    """The source text the sweep kernel is compiled from (see KERNEL_*)."""
+    with open(os.path.join(HERE, KERNEL_FILE)) as fh:
+        src = fh.read()
+    a = src.index(KERNEL_START)
+    b = src.index("\n}\n", src.index(KERNEL_NAME, a)) + 3
+    with open(os.path.join(HERE, KERNEL_HEADER)) as fh:
+        return fh.read() + src[a:b]
+
+
+def source_hash():
+    return hashlib.sha256(kernel_source().encode()).hexdigest()[:16]
 
 
 def short_name(n):
