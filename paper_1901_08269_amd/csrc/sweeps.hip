@@ -522,12 +522,19 @@ __global__ void __launch_bounds__(NT) k_apply4(Geom g, Coef<T> cf, Irr<T> ir, co
 }
 
 // ---------------------------------------------------------------------------------------
-// Vector updates of Alg. 1 on vectorised rows (same arithmetic as k_first / k_update): a
-// wavefront owns one row of a 256-node segment, four nodes per lane, and walks its z-chunk.
-// The diagonals of K and B are formed from the 1D tables with the x coefficients held per
-// lane and the y and z coefficients wave-uniform, so no node index is ever decoded.  Walls
-// are not touched (zero in every vector); irregular rows run in the leading blocks, one
-// thread per row.
+// Vector updates of Alg. 1 on vectorised rows:
+//   k_first4 FIRST_P  p = r + beta (p - omega v)   (search direction; p = r after a (re)start:
+//                                                  beta = 0)
+//            FIRST_S  s = r - alpha v              (intermediate residual)
+//            then x_1 = c2 * (p or s) / diag(K), the first Chebyshev step from x_0 = 0
+//   k_update4         u += alpha p^ + omega s^, r = s - omega t, partials of (r0, r) and of
+//                     ||D^-1 r||^2 (D = diag B); the finalize kernel forms beta and tests
+//                     convergence
+// A wavefront owns one row of a 256-node segment, four nodes per lane, and walks its
+// z-chunk.  The diagonals of K and B are formed from the 1D tables with the x coefficients
+// held per lane and the y and z coefficients wave-uniform, so no node index is ever
+// decoded.  Walls are not touched (zero in every vector); irregular rows (their own
+// diagonals) run in the leading blocks, one thread per row.
 // ---------------------------------------------------------------------------------------
 template <typename T, int KIND>
 __global__ void __launch_bounds__(NT) k_first4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
