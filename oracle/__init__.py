@@ -58,6 +58,9 @@ def lib():
         L.orc_apply.argtypes = [C.c_void_p, dp, dp]
         L.orc_apply_K.argtypes = [C.c_void_p, dp, dp]
         L.orc_precond.argtypes = [C.c_void_p, dp, dp, C.c_int, C.c_double, C.c_double]
+        L.orc_smooth.argtypes = [C.c_void_p, dp, dp, C.c_int, C.c_double, C.c_double]
+        L.orc_create_k.restype = C.c_void_p
+        L.orc_create_k.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, C.POINTER(C.c_int)]
         L.orc_solve.restype = C.c_int
         L.orc_solve.argtypes = [C.c_void_p, C.c_double, dp, C.c_void_p, dp]
         L.orc_residual.argtypes = [C.c_void_p, dp, dp, dp]
@@ -149,6 +152,26 @@ class Problem:
     @classmethod
     def from_workload(cls, w):
         return cls(w.x, w.y, w.z, w.phi, w.g, w.f)
+
+    @classmethod
+    def k_only(cls, x, y, z, phi):
+        """The grid, node types and K rows only (a coarse level of the multigrid preconditioner)."""
+        self = cls.__new__(cls)
+        self.x, self.y, self.z = _f64(x), _f64(y), _f64(z)
+        self.shape = (len(self.z), len(self.y), len(self.x))
+        self._phi = _f64(phi)
+        err = C.c_int(0)
+        self.h = lib().orc_create_k(len(self.x), len(self.y), len(self.z), _p(self.x), _p(self.y), _p(self.z),
+                                    _p(self._phi), C.byref(err))
+        if not self.h:
+            raise OracleError(err.value)
+        return self
+
+    def smooth(self, rho, x, iters, lo, hi):
+        """`iters` Chebyshev-Jacobi steps on K x = rho from x, spectrum interval [lo, hi]."""
+        out = _f64(x).copy()
+        lib().orc_smooth(self.h, _p(_f64(rho)), _p(out), iters, lo, hi)
+        return out
 
     def __del__(self):
         h = getattr(self, "h", None)

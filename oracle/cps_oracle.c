@@ -478,9 +478,11 @@ static void k_row(orc_prob *P, int i, int j, int k, double coef[7])
     }
 }
 
-/* returns NULL and *err < 0 on invalid input: -1 bad sizes/coords, -2 body touches wall */
-void *orc_create(int nx, int ny, int nz, const double *x, const double *y, const double *z,
-                 const double *phi, const double *g, const double *f, int *err)
+/* returns NULL and *err < 0 on invalid input: -1 bad sizes/coords, -2 body touches wall.
+ * k_only: classification and the K rows only (no rows of B, no right-hand side), for the
+ * coarse levels of the multigrid preconditioner. */
+static void *create(int nx, int ny, int nz, const double *x, const double *y, const double *z,
+                    const double *phi, const double *g, const double *f, int k_only, int *err)
 {
     *err = 0;
     if (nx < 3 || ny < 3 || nz < 3) { *err = -1; return NULL; }
@@ -555,8 +557,13 @@ void *orc_create(int nx, int ny, int nz, const double *x, const double *y, const
         if (r < 0) continue;
         int c[3];
         coords_of(P, e, c);
-        irregular_row(P, c[0], c[1], c[2], R);
         P->irr_node[r] = e;
+        if (k_only) {
+            P->irr_ptr[r + 1] = nnz;
+            k_row(P, c[0], c[1], c[2], &P->ksw[7 * r]);
+            continue;
+        }
+        irregular_row(P, c[0], c[1], c[2], R);
         if (nnz + R->cnt > cap) {
             cap = 2 * cap + R->cnt;
             P->irr_col = (i64 *)realloc(P->irr_col, sizeof(i64) * cap);
@@ -572,6 +579,7 @@ void *orc_create(int nx, int ny, int nz, const double *x, const double *y, const
         k_row(P, c[0], c[1], c[2], &P->ksw[7 * r]);
     }
     free(R);
+    if (k_only) return P;
     /* regular rows: Q f minus the known wall-node terms */
     for (int k = 1; k < nz - 1; ++k)
         for (int j = 1; j < ny - 1; ++j)
@@ -590,6 +598,23 @@ void *orc_create(int nx, int ny, int nz, const double *x, const double *y, const
                 P->rhs[e] = s;
             }
     return P;
+}
+
+void *orc_create(int nx, int ny, int nz, const double *x, const double *y, const double *z,
+                 const double *phi, const double *g, const double *f, int *err)
+{
+    return create(nx, ny, nz, x, y, z, phi, g, f, 0, err);
+}
+
+/* the grid, node types and K rows only (g = f = 0) */
+void *orc_create_k(int nx, int ny, int nz, const double *x, const double *y, const double *z, const double *phi,
+                   int *err)
+{
+    i64 nn = (i64)nx * ny * nz;
+    double *zero = dalloc(nn > 0 ? nn : 1);
+    void *h = create(nx, ny, nz, x, y, z, phi, zero, zero, 1, err);
+    free(zero);
+    return h;
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -737,6 +762,34 @@ static void cheb_coef(int iters, double lo, double hi, double *c1, double *c2)
         c2[k] = 2.0 * rho / delta;
         rho_prev = rho;
     }
+}
+
+/* `iters` Chebyshev-Jacobi steps on K x = rho from the initial guess in x (in place), for the
+ * spectrum of diag(K)^{-1} K in [lo, hi]: the multigrid smoother. */
+void orc_smooth(void *h, const double *rho, double *x, int iters, double lo, double hi)
+{
+    orc_prob *P = (orc_prob *)h;
+    double c1[64], c2[64];
+    if (iters > 64) iters = 64;
+    cheb_coef(iters, lo, hi, c1, c2);
+    double *xp = dalloc(P->nn), *xc = dalloc(P->nn), *xn = dalloc(P->nn);
+    memcpy(xc, x, sizeof(double) * P->nn);
+    memcpy(xp, x, sizeof(double) * P->nn);
+    for (int it = 0; it < iters; ++it) {
+        for (i64 e = 0; e < P->nn; ++e) {
+            if (!is_unknown(P, e)) { xn[e] = 0.0; continue; }
+            int c[3];
+            coords_of(P, e, c);
+            double co[7];
+            k_coef(P, e, c, co);
+            double kx = co[0] * xc[e];
+            for (int d = 0; d < 3; ++d) kx += co[1 + 2 * d] * xc[e - P->stride[d]] + co[2 + 2 * d] * xc[e + P->stride[d]];
+            xn[e] = xc[e] + c1[it] * (xc[e] - xp[e]) + c2[it] * (rho[e] - kx) / co[0];
+        }
+        double *tmp = xp; xp = xc; xc = xn; xn = tmp;
+    }
+    memcpy(x, xc, sizeof(double) * P->nn);
+    free(xp); free(xc); free(xn);
 }
 
 /* phi ~= K^{-1} rho: `iters` Chebyshev-Jacobi steps from phi_0 = 0 on -K phi = -rho
