@@ -49,6 +49,9 @@ extern "C" {
 #define CPS_FP64 0           /* plain mode: every sweep in FP64 */
 #define CPS_MIXED 1          /* FP32 inner BiCGSTAB inside an FP64 iterative-refinement loop */
 
+#define CPS_PRECOND_CHEBYSHEV 0  /* inner_iters Chebyshev-Jacobi steps on K per apply */
+#define CPS_PRECOND_MULTIGRID 1  /* one multigrid V-cycle on K per apply */
+
 typedef struct cps_solver cps_solver; /* opaque; owns all of its device memory */
 
 typedef struct cps_options {
@@ -67,6 +70,19 @@ typedef struct cps_options {
                             * hi = 2; lo = 0 selects max(hi / (4 inner_iters^2), lambda_1) with
                             * lambda_1 = (1/3) sum_d (1 - cos(pi / (n_d - 1)))) */
     void *stream;          /* hipStream_t the library launches on; NULL = null stream */
+    /* How K phi = rho is solved approximately inside the preconditioner (Sec. 3.3 leaves the
+     * inner solver open).  CPS_PRECOND_MULTIGRID: one V-cycle.  A coarser grid keeps the
+     * even-indexed points and the last point along every axis (while every axis has at least
+     * 17 points); its K is built from the level set at its nodes.  Prolongation is trilinear
+     * interpolation in the physical coordinates; restriction is its transpose with each row
+     * divided by its sum.  Smoother: mg_nu Chebyshev-Jacobi steps before and after each
+     * coarse correction on [mg_smooth_lo, lam_hi]; the coarsest grid takes mg_coarse_steps
+     * steps on [lambda_1, lam_hi] of that grid.  The cycle is a fixed linear map of rho. */
+    int32_t precond;         /* CPS_PRECOND_CHEBYSHEV (default) or CPS_PRECOND_MULTIGRID */
+    int32_t mg_levels;       /* most levels, this grid included, 1..16 (default 4) */
+    int32_t mg_nu;           /* smoothing steps before and after, 1..64 (default 3) */
+    int32_t mg_coarse_steps; /* steps on the coarsest grid, 1..64 (default 24) */
+    double mg_smooth_lo;     /* lower end of the smoother's interval, in (0, lam_hi) (default 0.5) */
 } cps_options;
 
 typedef struct cps_stats {
@@ -94,7 +110,8 @@ typedef struct cps_stats {
 
 /* Fill `o` with the defaults: CPS_FP64, 24 inner iterations, max_iters 20000,
  * max_refine 40, max_restarts 5, host pointers, inner_tol 1e-4, the default Chebyshev
- * interval, null stream, no kernel timing. */
+ * interval, null stream, no kernel timing, the Chebyshev preconditioner (multigrid
+ * settings 4 levels, 3 + 3 smoothing steps on [0.5, lam_hi], 24 coarsest-grid steps). */
 void cps_default_options(cps_options *o);
 
 /* Build the discrete problem (Secs. 2-3): classify nodes from the sign of phi (Sec. 2,
@@ -128,8 +145,9 @@ int cps_residual(cps_solver *s, const double *u, double *r, double *rel);
  * FP32 first, y widened back).  Entries of x at non-unknown nodes are ignored. */
 int cps_apply(cps_solver *s, const double *x, double *y, int32_t precision);
 
-/* phi = M rho: the preconditioner of Alg. 1 (applied to p and to s), i.e. inner_iters
- * Chebyshev-Jacobi steps on K phi = rho (Sec. 3.3) from phi = 0; FP64 or FP32 as above. */
+/* phi = M rho: the preconditioner of Alg. 1 (applied to p and to s): an approximate solve of
+ * K phi = rho (Sec. 3.3) from phi = 0 -- inner_iters Chebyshev-Jacobi steps, or one multigrid
+ * V-cycle (cps_options.precond); FP64 or FP32 as above. */
 int cps_precond(cps_solver *s, const double *rho, double *phi, int32_t precision);
 
 /* Copy out the right-hand side q + b (node array, 0 at non-unknowns) and the node types

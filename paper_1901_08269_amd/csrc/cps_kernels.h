@@ -25,6 +25,10 @@ void launch_apply(int mode, const Launch &L, const Coef<T> &cf, const Irr<T> &ir
 template <typename T>
 void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
                  double c1, double c2, const DevState *st);
+// r = rho - K x at the unknown nodes (r is written there only)
+template <typename T>
+void launch_resid(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, const T *rho, T *r,
+                  const DevState *st);
 template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st);
@@ -45,6 +49,26 @@ constexpr int DOT_BLOCKS = 1024;
 void launch_dot2_unknowns(hipStream_t s, size_t n, const int8_t *type, const double *a, const double *b,
                           double *partials);
 void launch_scale(hipStream_t s, size_t n, double *x, double alpha);
+
+// multigrid.hip: 1D transfer tables of one axis between a level and the next coarser one
+template <typename T>
+struct MgAxis {
+    const int *pa;   // fine index -> left coarse index (prolongation)
+    const T *pw;     // fine index -> weight of coarse node pa + 1
+    const int *ri;   // coarse index I -> fine indices ri[3I .. 3I + 2] (restriction)
+    const T *rw;     // their weights, divided by the row sum (0 for absent entries)
+};
+template <typename T>
+struct MgTransfer {
+    int nf[3], nc[3];
+    MgAxis<T> ax[3];
+};
+// rc = R r at the unknown coarse nodes (type_c), 0 at every other coarse node
+template <typename T>
+void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_c, const T *r, T *rc);
+// x += P e at the unknown fine nodes (type_f)
+template <typename T>
+void launch_mg_prolong_add(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_f, const T *e, T *x);
 
 // setup.hip
 struct SetupOut {
@@ -71,6 +95,12 @@ void launch_build_rows(hipStream_t s, int nx, int ny, int nz, const double *x, c
                        const double *coef, const double *phi, const double *g, const double *f, const int8_t *type,
                        int nirr, const int *nodes, int cap, int *ell_col, double *ell_val, int *len, double *rhs_row,
                        double *k7, double *bdiag, double *minhb, int *fallback, int *bad);
+// K rows (Shortley-Weller at nodes next to the body) of the irregular nodes only
+void launch_krows(hipStream_t s, int nx, int ny, int nz, const double *x, const double *y, const double *z,
+                  const double *phi, const int8_t *type, int nirr, const int *nodes, double *k7);
+// dst(I, J, K) = src(ix[I], iy[J], iz[K]) on a coarse grid of ncx x ncy x ncz nodes
+void launch_gather3(hipStream_t s, int ncx, int ncy, int ncz, int nfx, int nfy, const int *ix, const int *iy,
+                    const int *iz, const double *src, double *dst);
 void launch_scan(hipStream_t s, const int *in, int *out, int n);   // exclusive scan, out[n] = total
 void launch_pack_rows(hipStream_t s, int nirr, int cap, const int *ell_col, const double *ell_val, const int *len,
                       const int *ptr, int *col, double *val64, float *val32);

@@ -590,6 +590,51 @@ __device__ __attribute__((noinline)) void run_operator(const Ctx &C, WinList &R,
     }
 }
 
+// Shortley-Weller K row at the node `rownode` = (idx): Eqs. 2ndorder_coef_mod, A7_mod.  Output
+// [diag, -x, +x, -y, +y, -z, +z]; a neighbour that is not an unknown gets 0 (zero Dirichlet
+// data), a solid neighbour moves the arm to the interface intersection.
+__device__ void sw_krow(const Ctx &C, size_t rownode, const int idx[3], double *out)
+{
+    double kr[7];
+    kr[0] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        int b0[3] = {idx[0], idx[1], idx[2]};
+        b0[d] = 0;
+        size_t line0 = (size_t)b0[0] * C.stride[0] + (size_t)b0[1] * C.stride[1] + (size_t)b0[2] * C.stride[2];
+        size_t nm = rownode - C.stride[d], npl = rownode + C.stride[d];
+        double hb = C.t[d][idx[d]] - C.t[d][idx[d] - 1], hf = C.t[d][idx[d] + 1] - C.t[d][idx[d]];
+        double gv, fr;
+        if (C.type[nm] == 3) hb = C.t[d][idx[d]] - ibi_on_segment(C, d, line0, idx[d], idx[d] - 1, &gv, &fr);
+        if (C.type[npl] == 3) hf = ibi_on_segment(C, d, line0, idx[d], idx[d] + 1, &gv, &fr) - C.t[d][idx[d]];
+        kr[0] += -2.0 / (hb * hf);
+        int8_t tm = C.type[nm], tp = C.type[npl];
+        kr[1 + 2 * d] = (tm == 1 || tm == 2) ? 2.0 / (hb * (hf + hb)) : 0.0;
+        kr[2 + 2 * d] = (tp == 1 || tp == 2) ? 2.0 / (hf * (hf + hb)) : 0.0;
+    }
+    for (int q = 0; q < 7; ++q) out[q] = kr[q];
+}
+
+// K rows only (a coarse level of the multigrid preconditioner): one thread per irregular node.
+__global__ void k_krows(Ctx C, int nirr, const int *__restrict__ nodes, double *__restrict__ k7)
+{
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nirr) return;
+    const size_t rownode = (size_t)nodes[row];
+    const int nx = C.n[0], ny = C.n[1];
+    const int idx[3] = {(int)(rownode % nx), (int)((rownode / nx) % ny), (int)(rownode / ((size_t)nx * ny))};
+    sw_krow(C, rownode, idx, k7 + 7 * (size_t)row);
+}
+
+// gather of the coarse level set: coarse node (I, J, K) <- fine node (ix[I], iy[J], iz[K])
+__global__ void k_gather3(int ncx, int ncy, int ncz, int nfx, int nfy, const int *__restrict__ ix,
+                          const int *__restrict__ iy, const int *__restrict__ iz, const double *__restrict__ src,
+                          double *__restrict__ dst)
+{
+    const int I = (int)(blockIdx.x * blockDim.x + threadIdx.x), J = (int)blockIdx.y, K = (int)blockIdx.z;
+    if (I >= ncx) return;
+    dst[(size_t)I + (size_t)ncx * (J + (size_t)ncy * K)] = src[(size_t)ix[I] + (size_t)nfx * (iy[J] + (size_t)nfy * iz[K])];
+}
+
 // One irregular row per 32-lane group (four rows per 128-thread block).  Lanes 0..26 take
 // the 27 windows of Eq. lhsrhs_xxyyzz_mod (direction d = lane / 9, cross offsets from
 // lane % 9) and list their contributions in LDS; lane 27 forms the row's Q-bar term and its
@@ -680,24 +725,7 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
                     if (C.type[node] != 3) q += L[0][dx + 1] * L[1][dy + 1] * L[2][dz + 1] * C.f[node];
                 }
         qbar[grp] = q;
-        // Shortley-Weller K row (Eqs. 2ndorder_coef_mod, A7_mod)
-        double kr[7];
-        kr[0] = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            int b0[3] = {idx[0], idx[1], idx[2]};
-            b0[d] = 0;
-            size_t line0 = (size_t)b0[0] * C.stride[0] + (size_t)b0[1] * C.stride[1] + (size_t)b0[2] * C.stride[2];
-            size_t nm = rownode - C.stride[d], npl = rownode + C.stride[d];
-            double hb = C.t[d][idx[d]] - C.t[d][idx[d] - 1], hf = C.t[d][idx[d] + 1] - C.t[d][idx[d]];
-            double gv, fr;
-            if (C.type[nm] == 3) hb = C.t[d][idx[d]] - ibi_on_segment(C, d, line0, idx[d], idx[d] - 1, &gv, &fr);
-            if (C.type[npl] == 3) hf = ibi_on_segment(C, d, line0, idx[d], idx[d] + 1, &gv, &fr) - C.t[d][idx[d]];
-            kr[0] += -2.0 / (hb * hf);
-            int8_t tm = C.type[nm], tp = C.type[npl];
-            kr[1 + 2 * d] = (tm == 1 || tm == 2) ? 2.0 / (hb * (hf + hb)) : 0.0;
-            kr[2 + 2 * d] = (tp == 1 || tp == 2) ? 2.0 / (hf * (hf + hb)) : 0.0;
-        }
-        for (int q2 = 0; q2 < 7; ++q2) k7[7 * (size_t)row + q2] = kr[q2];
+        sw_krow(C, rownode, idx, k7 + 7 * (size_t)row);
     }
     __syncthreads();
     if (!live) return;
@@ -772,6 +800,26 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
         fb_row[row] = fb;
         if (cnt_total > cap) atomicOr(bad, 2);
     }
+}
+
+void launch_krows(hipStream_t s, int nx, int ny, int nz, const double *x, const double *y, const double *z,
+                  const double *phi, const int8_t *type, int nirr, const int *nodes, double *k7)
+{
+    if (nirr == 0) return;
+    Ctx C;
+    C.n[0] = nx; C.n[1] = ny; C.n[2] = nz;
+    C.stride[0] = 1; C.stride[1] = nx; C.stride[2] = (size_t)nx * ny;
+    C.t[0] = x; C.t[1] = y; C.t[2] = z;
+    for (int d = 0; d < 3; ++d) C.coef[d] = nullptr;
+    C.phi = phi; C.g = phi; C.f = nullptr; C.type = type;   // g at an IBI is not used for K
+    k_krows<<<(nirr + 127) / 128, 128, 0, s>>>(C, nirr, nodes, k7);
+}
+
+void launch_gather3(hipStream_t s, int ncx, int ncy, int ncz, int nfx, int nfy, const int *ix, const int *iy,
+                    const int *iz, const double *src, double *dst)
+{
+    k_gather3<<<dim3((unsigned)((ncx + 63) / 64), (unsigned)ncy, (unsigned)ncz), 64, 0, s>>>(ncx, ncy, ncz, nfx, nfy, ix,
+                                                                                             iy, iz, src, dst);
 }
 
 void launch_build_rows(hipStream_t s, int nx, int ny, int nz, const double *x, const double *y, const double *z,

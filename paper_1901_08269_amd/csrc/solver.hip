@@ -43,6 +43,33 @@ struct Vecs {
     bool ready = false;
 };
 
+// Multigrid preconditioner for K: a coarser level keeps the even-indexed points and the
+// last one along every axis while an axis has at least 2 MG_MIN_POINTS - 1 points.
+constexpr int MG_MIN_POINTS = 9;
+constexpr int MG_MAX_LEVELS = 16;
+
+// One level of the multigrid hierarchy.  Level 0 aliases the solver's own grid data; a
+// coarser level owns its coordinates, 1D tables, node types, skip bits and K rows (no B).
+struct MgLevel {
+    int n[3] = {0, 0, 0};
+    int nmax = 0;
+    size_t nn = 0;
+    Geom g{};
+    double *xyz = nullptr;
+    double *coef64 = nullptr;
+    float *coef32 = nullptr;
+    int8_t *type = nullptr;
+    uint32_t *skip = nullptr;
+    int nirr = 0;
+    int *irr_node = nullptr;
+    double *k64 = nullptr;
+    float *k32 = nullptr;
+    MgTransfer<double> t64{};   // transfers to the next coarser level
+    MgTransfer<float> t32{};
+    double *v64[3] = {nullptr, nullptr, nullptr};   // level right-hand side, two iterates
+    float *v32[3] = {nullptr, nullptr, nullptr};
+};
+
 }  // namespace
 
 struct cps_solver {
@@ -81,6 +108,12 @@ struct cps_solver {
     double *tmp64 = nullptr;      // user-facing staging (residual, apply, precond)
     double *x64 = nullptr;        // FP64 solution in mixed mode
     float *tmp32a = nullptr, *tmp32b = nullptr;
+    // multigrid preconditioner (opt.precond = CPS_PRECOND_MULTIGRID)
+    std::vector<MgLevel> mg;            // mg[0] is this grid
+    std::vector<double> mg_c1, mg_c2;   // smoother steps on [mg_smooth_lo, lam_hi]
+    std::vector<double> mg_cc1, mg_cc2; // coarsest-level steps on [lambda_1, lam_hi]
+    double *mg_zero64 = nullptr;        // zeros, the size of level 1
+    float *mg_zero32 = nullptr;
     // host-side facts
     long long n_unknown = 0, n_solid = 0, nnz = 0, fallback = 0;
     double min_hb = 1.0;
@@ -363,6 +396,142 @@ hipEvent_t timed_sweep_begin(cps_solver *s)
     return e1;
 }
 
+// ---- multigrid V-cycle on K (the inner solver of the preconditioner, Sec. 3.3) ----------
+template <typename T>
+T *const *mg_vecs(const MgLevel &Lv)
+{
+    if constexpr (sizeof(T) == 8) return Lv.v64; else return Lv.v32;
+}
+
+template <typename T>
+const MgTransfer<T> &mg_transfer(const MgLevel &Lv)
+{
+    if constexpr (sizeof(T) == 8) return Lv.t64; else return Lv.t32;
+}
+
+// level vectors of precision T (allocated and zeroed on first use)
+template <typename T>
+void mg_alloc(cps_solver *s)
+{
+    for (size_t l = 1; l < s->mg.size(); ++l) {
+        MgLevel &Lv = s->mg[l];
+        T **v;
+        if constexpr (sizeof(T) == 8) v = Lv.v64; else v = Lv.v32;
+        for (int q = 0; q < 3; ++q)
+            if (!v[q]) {
+                v[q] = dalloc<T>(s, Lv.nn + VEC_PAD);
+                launch_fill<T>(s->stream, Lv.nn + VEC_PAD, v[q], T(0));
+            }
+    }
+    if (s->mg.size() > 1) {
+        T **z;
+        if constexpr (sizeof(T) == 8) z = &s->mg_zero64; else z = &s->mg_zero32;
+        if (!*z) {
+            *z = dalloc<T>(s, s->mg[1].nn + VEC_PAD);
+            launch_fill<T>(s->stream, s->mg[1].nn + VEC_PAD, *z, T(0));
+        }
+    }
+}
+
+template <typename T>
+Coef<T> mg_coef(const MgLevel &Lv)
+{
+    Coef<T> c;
+    for (int d = 0; d < 3; ++d) {
+        if constexpr (sizeof(T) == 8) c.c[d] = Lv.coef64 + (size_t)d * 8 * Lv.nmax;
+        else c.c[d] = Lv.coef32 + (size_t)d * 8 * Lv.nmax;
+    }
+    return c;
+}
+
+// the K rows of a coarse level (the fields of B are not used by the K sweeps)
+template <typename T>
+Irr<T> mg_irr(const MgLevel &Lv)
+{
+    Irr<T> r{};
+    r.n = Lv.nirr;
+    r.node = Lv.irr_node;
+    if constexpr (sizeof(T) == 8) r.k7 = Lv.k64; else r.k7 = Lv.k32;
+    return r;
+}
+
+// Steps k0 .. n-1 of a Chebyshev-Jacobi iteration on K x = rho (coefficients c1, c2).
+// From x = 0 (x0 null; `zero` is read as x_0 when k0 = 0) the iterates alternate a, b, a, ...;
+// from x0 (which must be a) they alternate b, a, b, ...  Each step from the third on writes
+// over its x_{k-1} in place.  The last step writes dst if it is non-null.  Returns the
+// buffer that holds x_n.  Level-0 sweeps with an x_{k-1} are sampled by kernel_timing.
+template <typename T>
+T *mg_smooth(cps_solver *s, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *rho, T *x0, const T *zero,
+             T *a, T *b, T *dst, int k0, int n, const double *c1, const double *c2, const DevState *st, bool timed)
+{
+    T *odd = x0 ? b : a, *even = x0 ? a : b;
+    auto buf = [&](int j) -> T * { return j == 0 ? (x0 ? x0 : (T *)zero) : ((j & 1) ? odd : even); };
+    for (int k = k0; k < n; ++k) {
+        const T *xm1 = (k == 0) ? nullptr : (k == 1 ? (const T *)x0 : buf(k - 1));
+        T *out = (k == n - 1 && dst) ? dst : buf(k + 1);
+        hipEvent_t e1 = (timed && xm1) ? timed_sweep_begin(s) : nullptr;
+        launch_cheb<T>(L, cf, ir, buf(k), xm1, rho, out, c1[k], c2[k], st);
+        if (e1) ck(hipEventRecord(e1, s->stream));
+    }
+    return dst ? dst : buf(n);
+}
+
+// V-cycle on coarse level l >= 1 for K_l x = rho_l (rho_l in the level's first vector);
+// returns the buffer that holds x.
+template <typename T>
+T *mg_level(cps_solver *s, int l, const DevState *st)
+{
+    const MgLevel &Lv = s->mg[l];
+    T *const *V = mg_vecs<T>(Lv);
+    T *R = V[0], *A = V[1], *B = V[2];
+    const T *Z;
+    if constexpr (sizeof(T) == 8) Z = s->mg_zero64; else Z = s->mg_zero32;
+    const Launch L{Lv.g, s->stream, Lv.skip, s->partials, s->ticket};
+    const Coef<T> cf = mg_coef<T>(Lv);
+    const Irr<T> ir = mg_irr<T>(Lv);
+    if (l + 1 == (int)s->mg.size())
+        return mg_smooth<T>(s, L, cf, ir, R, nullptr, Z, A, B, nullptr, 0, s->opt.mg_coarse_steps, s->mg_cc1.data(),
+                            s->mg_cc2.data(), st, false);
+    const int nu = s->opt.mg_nu;
+    T *x = mg_smooth<T>(s, L, cf, ir, R, nullptr, Z, A, B, nullptr, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
+    T *r = (x == A) ? B : A;
+    launch_resid<T>(L, cf, ir, x, R, r, st);
+    launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), s->mg[l + 1].type, r, mg_vecs<T>(s->mg[l + 1])[0]);
+    T *e = mg_level<T>(s, l + 1, st);
+    launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.type, e, x);
+    return mg_smooth<T>(s, L, cf, ir, R, x, Z, x, r, nullptr, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
+}
+
+// dst = one V-cycle for K dst = ps on the problem's grid.  The first pre-smoothing step is
+// fused with the vector update `kind` that forms ps (as in the Chebyshev preconditioner);
+// the iterates use the two Chebyshev buffers of V.
+template <typename T>
+void mg_precond(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T *v, T *dst, const DevState *st)
+{
+    mg_alloc<T>(s);
+    const Launch L = s->launch();
+    Coef<T> cf;
+    Irr<T> ir;
+    if constexpr (sizeof(T) == 8) { cf = s->cf64(); ir = s->ir64(); } else { cf = s->cf32(); ir = s->ir32(); }
+    T *a = V.c[1], *b = V.c[0];
+    if (s->mg.size() == 1) {   // no coarser grid: the coarsest-level iteration on this grid
+        launch_first<T>(kind, L, cf, ir, r, ps, v, a, s->mg_cc2[0], st);
+        mg_smooth<T>(s, L, cf, ir, ps, nullptr, nullptr, a, b, dst, 1, s->opt.mg_coarse_steps, s->mg_cc1.data(),
+                     s->mg_cc2.data(), st, true);
+        return;
+    }
+    const int nu = s->opt.mg_nu;
+    launch_first<T>(kind, L, cf, ir, r, ps, v, a, s->mg_c2[0], st);
+    T *x = mg_smooth<T>(s, L, cf, ir, ps, nullptr, nullptr, a, b, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st,
+                        true);
+    T *res = (x == a) ? b : a;
+    launch_resid<T>(L, cf, ir, x, ps, res, st);
+    launch_mg_restrict<T>(s->stream, mg_transfer<T>(s->mg[0]), s->mg[1].type, res, mg_vecs<T>(s->mg[1])[0]);
+    T *e = mg_level<T>(s, 1, st);
+    launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(s->mg[0]), s->type, e, x);
+    mg_smooth<T>(s, L, cf, ir, ps, x, nullptr, x, res, dst, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, true);
+}
+
 // p^ = M p: inner_iters Chebyshev steps.  The first is fused with the vector update `kind`
 // (x_1 is pointwise from x_0 = 0); the rest are single sweeps in which x_{k+1} overwrites
 // x_{k-1} in place (each node's x_{k-1} is read only by the thread that writes its x_{k+1}),
@@ -374,6 +543,10 @@ template <typename T>
 void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T *v, T *dst, const double *c1,
                    const double *c2, const DevState *st)
 {
+    if (s->opt.precond == CPS_PRECOND_MULTIGRID) {
+        mg_precond<T>(s, V, kind, r, ps, v, dst, st);
+        return;
+    }
     const Launch L = s->launch();
     Coef<T> cf;
     Irr<T> ir;
@@ -577,13 +750,13 @@ int rhs_build(cps_solver *s)
     return CPS_OK;
 }
 
-int count_type(cps_solver *s, int8_t want, int *list, long long *count)
+int count_nodes(cps_solver *s, size_t nn, const int8_t *type, int8_t want, int *list, long long *count)
 {
-    int nb = compact_blocks(s->nn);
+    int nb = compact_blocks(nn);
     int *bc = dalloc<int>(s, 2 * (size_t)nb + 1);
     int *dcount = dalloc<int>(s, 1);
-    int *lst = list ? list : dalloc<int>(s, s->nn);
-    launch_compact(s->stream, s->nn, s->type, want, bc, lst, dcount, nb);
+    int *lst = list ? list : dalloc<int>(s, nn);
+    launch_compact(s->stream, nn, type, want, bc, lst, dcount, nb);
     ck(hipMemcpyAsync(s->hscalar, dcount, sizeof(int), hipMemcpyDeviceToHost, s->stream));
     sync(s);
     int c;
@@ -593,6 +766,172 @@ int count_type(cps_solver *s, int8_t want, int *list, long long *count)
     dfree(s, dcount);
     if (!list) dfree(s, lst);
     return CPS_OK;
+}
+
+int count_type(cps_solver *s, int8_t want, int *list, long long *count)
+{
+    return count_nodes(s, s->nn, s->type, want, list, count);
+}
+
+// 1D multigrid tables of one axis: fine coordinates xf[nf], the coarse points' indices idx.
+// Prolongation: the left coarse index a (the last one at most nc - 2) and the weight of
+// coarse point a + 1 from the physical coordinates.  Restriction: P^T, each coarse row
+// divided by its sum, at most three nonzero entries per row (padded with weight 0).
+void mg_axis_tables(const double *xf, int nf, const std::vector<int> &idx, std::vector<int> &pa,
+                    std::vector<double> &pw, std::vector<int> &ri, std::vector<double> &rw)
+{
+    const int nc = (int)idx.size();
+    pa.assign(nf, 0);
+    pw.assign(nf, 0.0);
+    int a = 0;
+    for (int i = 0; i < nf; ++i) {
+        while (a + 1 <= nc - 2 && idx[a + 1] <= i) ++a;
+        pa[i] = a;
+        pw[i] = (xf[i] - xf[idx[a]]) / (xf[idx[a + 1]] - xf[idx[a]]);
+    }
+    ri.assign(3 * (size_t)nc, 0);
+    rw.assign(3 * (size_t)nc, 0.0);
+    std::vector<int> cnt(nc, 0);
+    std::vector<double> sum(nc, 0.0);
+    auto add = [&](int I, int i, double w) {
+        if (w == 0.0) return;
+        if (cnt[I] == 3) throw CPS_EINVAL;
+        ri[3 * I + cnt[I]] = i;
+        rw[3 * I + cnt[I]] = w;
+        ++cnt[I];
+        sum[I] += w;
+    };
+    for (int i = 0; i < nf; ++i) {
+        add(pa[i], i, 1.0 - pw[i]);
+        add(pa[i] + 1, i, pw[i]);
+    }
+    for (int I = 0; I < nc; ++I) {
+        for (int q = 0; q < 3; ++q) {
+            if (q >= cnt[I]) ri[3 * I + q] = idx[I];
+            else rw[3 * I + q] /= sum[I];
+        }
+    }
+}
+
+template <typename D>
+D *upload(cps_solver *s, const std::vector<D> &h)
+{
+    D *d = dalloc<D>(s, h.size());
+    ck(hipMemcpyAsync(d, h.data(), h.size() * sizeof(D), hipMemcpyHostToDevice, s->stream));
+    return d;
+}
+
+// The multigrid hierarchy below the problem's grid (coordinates hx = x | y | z on the host),
+// and the smoother and coarsest-level Chebyshev coefficients.
+void mg_build(cps_solver *s, const std::vector<double> &hx0)
+{
+    s->mg.clear();
+    s->mg.reserve(MG_MAX_LEVELS);
+    {
+        MgLevel L0;
+        L0.n[0] = s->nx; L0.n[1] = s->ny; L0.n[2] = s->nz;
+        L0.nmax = s->nmax;
+        L0.nn = s->nn;
+        L0.g = s->g;
+        L0.xyz = s->xyz;
+        L0.coef64 = s->coef64;
+        L0.coef32 = s->coef32;
+        L0.type = s->type;
+        L0.skip = s->skip;
+        L0.nirr = s->nirr;
+        L0.irr_node = s->irr_node;
+        L0.k64 = s->irr_k64;
+        L0.k32 = s->irr_k32;
+        s->mg.push_back(L0);
+    }
+    std::vector<double> hx = hx0;
+    const double *phi_f = s->phi;
+    std::vector<void *> temps;
+    while ((int)s->mg.size() < s->opt.mg_levels) {
+        MgLevel &F = s->mg.back();
+        if (std::min({F.n[0], F.n[1], F.n[2]}) < 2 * MG_MIN_POINTS - 1) break;
+        MgLevel C;
+        std::vector<int> idx[3], gidx;
+        std::vector<double> hc;
+        size_t off = 0;
+        for (int d = 0; d < 3; ++d) {
+            for (int i = 0; i < F.n[d] - 1; i += 2) idx[d].push_back(i);
+            if (idx[d].back() != F.n[d] - 1) idx[d].push_back(F.n[d] - 1);
+            C.n[d] = (int)idx[d].size();
+            for (int i : idx[d]) {
+                hc.push_back(hx[off + i]);
+                gidx.push_back(i);
+            }
+            std::vector<int> pa, ri;
+            std::vector<double> pw, rw;
+            mg_axis_tables(hx.data() + off, F.n[d], idx[d], pa, pw, ri, rw);
+            std::vector<float> pw32(pw.begin(), pw.end()), rw32(rw.begin(), rw.end());
+            const int *dpa = upload(s, pa), *dri = upload(s, ri);
+            F.t64.ax[d] = MgAxis<double>{dpa, upload(s, pw), dri, upload(s, rw)};
+            F.t32.ax[d] = MgAxis<float>{dpa, upload(s, pw32), dri, upload(s, rw32)};
+            F.t64.nf[d] = F.t32.nf[d] = F.n[d];
+            F.t64.nc[d] = F.t32.nc[d] = C.n[d];
+            off += F.n[d];
+        }
+        const int cx = C.n[0], cy = C.n[1], cz = C.n[2];
+        C.nmax = std::max({cx, cy, cz});
+        C.nn = (size_t)cx * cy * cz;
+        C.g = make_geom(cx, cy, cz);
+        C.xyz = upload(s, hc);
+        const int *dg = upload(s, gidx);
+        double *phic = dalloc<double>(s, C.nn);
+        temps.push_back(phic);
+        launch_gather3(s->stream, cx, cy, cz, F.n[0], F.n[1], dg, dg + cx, dg + cx + cy, phi_f, phic);
+        C.coef64 = dalloc<double>(s, (size_t)3 * 8 * C.nmax);
+        C.coef32 = dalloc<float>(s, (size_t)3 * 8 * C.nmax);
+        launch_fill<double>(s->stream, (size_t)3 * 8 * C.nmax, C.coef64, 0.0);
+        launch_coef(s->stream, cx, C.xyz, C.coef64);
+        launch_coef(s->stream, cy, C.xyz + cx, C.coef64 + (size_t)8 * C.nmax);
+        launch_coef(s->stream, cz, C.xyz + cx + cy, C.coef64 + (size_t)16 * C.nmax);
+        launch_to_float(s->stream, (size_t)3 * 8 * C.nmax, C.coef64, C.coef32);
+        // node types from the coarse level set (it is also passed as g and f, which the
+        // classification only checks for finiteness)
+        C.type = dalloc<int8_t>(s, C.nn);
+        ck(hipMemsetAsync(s->dflag, 0, sizeof(int), s->stream));
+        launch_classify(s->stream, cx, cy, cz, phic, phic, phic, C.type, s->dflag);
+        ck(hipMemcpyAsync(s->hscalar, s->dflag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        sync(s);
+        int flags;
+        std::memcpy(&flags, s->hscalar, sizeof(int));
+        if (flags) throw CPS_EGEOM;
+        launch_mark_irregular(s->stream, cx, cy, cz, C.type);
+        int *lst = dalloc<int>(s, C.nn);
+        temps.push_back(lst);
+        long long cnt;
+        count_nodes(s, C.nn, C.type, 2, lst, &cnt);
+        C.nirr = (int)cnt;
+        C.irr_node = dalloc<int>(s, C.nirr);
+        if (C.nirr) ck(hipMemcpyAsync(C.irr_node, lst, C.nirr * sizeof(int), hipMemcpyDeviceToDevice, s->stream));
+        C.k64 = dalloc<double>(s, (size_t)7 * C.nirr);
+        C.k32 = dalloc<float>(s, (size_t)7 * C.nirr);
+        launch_krows(s->stream, cx, cy, cz, C.xyz, C.xyz + cx, C.xyz + cx + cy, phic, C.type, C.nirr, C.irr_node, C.k64);
+        launch_to_float(s->stream, (size_t)7 * C.nirr, C.k64, C.k32);
+        C.skip = dalloc<uint32_t>(s, (size_t)C.g.W * cy * cz + 2);
+        launch_fill<uint32_t>(s->stream, (size_t)C.g.W * cy * cz + 2, C.skip, 0u);
+        launch_skipbits(s->stream, C.g, C.type, C.skip);
+        s->mg.push_back(C);
+        hx = hc;
+        phi_f = phic;
+    }
+    sync(s);
+    for (void *p : temps) dfree(s, p);
+    const int nmax = std::max(s->opt.mg_nu, s->opt.mg_coarse_steps);
+    s->mg_c1.assign(nmax, 0.0);
+    s->mg_c2.assign(nmax, 0.0);
+    s->mg_cc1.assign(nmax, 0.0);
+    s->mg_cc2.assign(nmax, 0.0);
+    cheb_coefficients(nmax, s->opt.mg_smooth_lo, s->opt.lam_hi, s->mg_c1.data(), s->mg_c2.data());
+    const MgLevel &Lc = s->mg.back();
+    const double pi = 3.14159265358979323846;
+    double lam1 = 0.0;
+    for (int d = 0; d < 3; ++d) lam1 += 1.0 - std::cos(pi / (Lc.n[d] - 1));
+    lam1 /= 3.0;
+    cheb_coefficients(nmax, lam1, s->opt.lam_hi, s->mg_cc1.data(), s->mg_cc2.data());
 }
 
 template <typename T>
@@ -656,6 +995,11 @@ void cps_default_options(cps_options *o)
     o->lam_lo = 0.0;
     o->lam_hi = DEFAULT_LAM_HI;
     o->stream = nullptr;
+    o->precond = CPS_PRECOND_CHEBYSHEV;
+    o->mg_levels = 4;
+    o->mg_nu = 3;
+    o->mg_coarse_steps = 24;
+    o->mg_smooth_lo = 0.5;
 }
 
 const char *cps_strerror(int code)
@@ -697,6 +1041,11 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         o.lam_lo = std::max(o.lam_hi / (4.0 * (double)o.inner_iters * (double)o.inner_iters), lam1);
     }
     if (!(o.lam_hi > o.lam_lo)) return CPS_EINVAL;
+    if (o.precond != CPS_PRECOND_CHEBYSHEV && o.precond != CPS_PRECOND_MULTIGRID) return CPS_EINVAL;
+    if (o.mg_levels < 1 || o.mg_levels > MG_MAX_LEVELS || o.mg_nu < 1 || o.mg_nu > MAX_INNER ||
+        o.mg_coarse_steps < 1 || o.mg_coarse_steps > MAX_INNER || !(o.mg_smooth_lo > 0.0) ||
+        !(o.mg_smooth_lo < o.lam_hi))
+        return CPS_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return CPS_EDEVICE;
     auto t0 = std::chrono::steady_clock::now();
@@ -787,6 +1136,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         ck(hipMemsetAsync(s->st, 0, sizeof(DevState), s->stream));
         s->rhs = dalloc<double>(s, s->nn);
         rc = rhs_build(s);
+        if (rc == CPS_OK && o.precond == CPS_PRECOND_MULTIGRID) mg_build(s, hx);
         sync(s);
     } catch (int code) {
         rc = code;
@@ -849,6 +1199,9 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
         const double tol2 = tol * tol;
         // FP64 solution vector (unknown entries only); the FP64 Krylov set only in FP64 mode
         if (s->opt.precision == CPS_FP64) alloc_vecs<double>(s, s->v64);
+        if (s->opt.precond == CPS_PRECOND_MULTIGRID) {
+            if (s->opt.precision == CPS_FP64) mg_alloc<double>(s); else mg_alloc<float>(s);
+        }
         if (!s->x64) s->x64 = dalloc<double>(s, s->nn + VEC_PAD);
         double *x64 = (s->opt.precision == CPS_FP64) ? s->v64.x : s->x64;
         if (warm_start) {

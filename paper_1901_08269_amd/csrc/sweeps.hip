@@ -204,12 +204,13 @@ __device__ __forceinline__ uint32_t skip4(const uint32_t *__restrict__ w, int i0
 // loads of two or four planes before computing them (fewer waits per plane, more registers)
 // measured no faster at 256^3, so the register budget goes to wavefronts and rows per
 // wavefront.  Wave-uniform y and z coefficients live in scalar registers.  Irregular rows
-// use their Shortley-Weller row in the leading blocks (one thread per row).
-template <typename T, bool PREV0>
-__global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
-                                              const T *__restrict__ xc, const T *xm1,
-                                              const T *__restrict__ rho, T *xn, T c1, T c2,
-                                              const DevState *st)
+// use their Shortley-Weller row in the leading blocks (one thread per row).  With RES the
+// same rows give the residual rho - K x_k instead (multigrid), with no x_{k-1}.
+template <typename T, bool PREV0, bool RES>
+__device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, const Irr<T> &ir,
+                                           const uint32_t *__restrict__ skip, const T *__restrict__ xc,
+                                           const T *xm1, const T *__restrict__ rho, T *xn, T c1, T c2,
+                                           const DevState *st)
 {
     using V = typename Vec4Of<T>::type;
     constexpr int R = RPW;
@@ -228,7 +229,7 @@ __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, con
         T kx = k7[0] * z0 + k7[1] * xc[e - 1] + k7[2] * xc[e + 1] + k7[3] * xc[e - nx] + k7[4] * xc[e + nx] +
                k7[5] * xc[e - plane] + k7[6] * xc[e + plane];
         T prev = PREV0 ? T(0) : xm1[e];
-        xn[e] = z0 + c1 * (z0 - prev) + c2 * (rho[e] - kx) / k7[0];
+        xn[e] = RES ? rho[e] - kx : z0 + c1 * (z0 - prev) + c2 * (rho[e] - kx) / k7[0];
         return;
     }
     const Tiling &tl = g.tr;
@@ -320,7 +321,7 @@ __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, con
                 const T kd = kbx[u] + kby[r] + zb;
                 const T kx = kd * cv[u] + kax[u] * w + kcx[u] * ea + kay[r] * sv[u] + kcy[r] * nvv[u] + za * mv[u] +
                              zcc * uv[u];
-                out[u] = cv[u] + c1 * (cv[u] - pv[u]) + c2 * (rvv[u] - kx) / kd;
+                out[u] = RES ? rvv[u] - kx : cv[u] + c1 * (cv[u] - pv[u]) + c2 * (rvv[u] - kx) / kd;
             }
             if (rok[r]) {
                 const size_t e = er[r] + kp;
@@ -340,6 +341,24 @@ __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, con
             c0[r] = cp[r];
         }
     }
+}
+
+template <typename T, bool PREV0>
+__global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
+                                              const T *__restrict__ xc, const T *xm1,
+                                              const T *__restrict__ rho, T *xn, T c1, T c2,
+                                              const DevState *st)
+{
+    cheb4_rows<T, PREV0, false>(g, cf, ir, skip, xc, xm1, rho, xn, c1, c2, st);
+}
+
+// r = rho - K x at the unknown nodes (the residual of a multigrid level; same rows)
+template <typename T>
+__global__ void __launch_bounds__(NT) k_resid4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
+                                               const T *__restrict__ x, const T *__restrict__ rho, T *r,
+                                               const DevState *st)
+{
+    cheb4_rows<T, true, true>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -874,6 +893,14 @@ void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *
 }
 
 template <typename T>
+void launch_resid(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, const T *rho, T *r,
+                  const DevState *st)
+{
+    dim3 grid(L.g.tr.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
+    k_resid4<T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st);
+}
+
+template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st)
 {
@@ -954,6 +981,10 @@ template void launch_cheb<double>(const Launch &, const Coef<double> &, const Ir
                                   const double *, const double *, double *, double, double, const DevState *);
 template void launch_cheb<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
                                  const float *, float *, double, double, const DevState *);
+template void launch_resid<double>(const Launch &, const Coef<double> &, const Irr<double> &, const double *,
+                                   const double *, double *, const DevState *);
+template void launch_resid<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
+                                  float *, const DevState *);
 template void launch_first<double>(int, const Launch &, const Coef<double> &, const Irr<double> &, const double *,
                                    double *, const double *, double *, double, const DevState *);
 template void launch_first<float>(int, const Launch &, const Coef<float> &, const Irr<float> &, const float *, float *,
