@@ -55,8 +55,8 @@ template <typename T>
 struct MgAxis {
     const int *pa;   // fine index -> left coarse index (prolongation)
     const T *pw;     // fine index -> weight of coarse node pa + 1
-    const int *ri;   // coarse index I -> fine indices ri[3I .. 3I + 2] (restriction)
-    const T *rw;     // their weights, divided by the row sum (0 for absent entries)
+    const T *rw;     // interior coarse index I -> weights rw[3I + q] of fine points 2I - 1 + q
+                     // (restriction), divided by the row sum
 };
 template <typename T>
 struct MgTransfer {

@@ -9,10 +9,11 @@
 // Both act on unknown nodes only: every other node holds 0 on every level.
 //
 // 1D tables per axis (built on the host from the coordinates):
-//   prolongation  for each fine index i: the left coarse index a[i] and the weight w[i] of
-//                 coarse node a[i] + 1 (fine value = (1 - w) e[a] + w e[a + 1])
-//   restriction   for each coarse index I: three fine indices ri[3I + q] and their weights
-//                 rw[3I + q], already divided by the row sum (absent entries have weight 0)
+//   prolongation  for each fine index i: the left coarse index a[i] = min(i / 2, nc - 2) and
+//                 the weight w[i] of coarse node a[i] + 1 (fine value = (1 - w) e[a] +
+//                 w e[a + 1]); the weights carry 4 zeros of padding
+//   restriction   for each interior coarse index I (fine point 2I): the weights rw[3I + q]
+//                 of fine points 2I - 1 + q, q = 0 .. 2, already divided by the row sum
 #include <hip/hip_runtime.h>
 
 #include "cps_kernels.h"
@@ -23,54 +24,127 @@ namespace {
 
 __device__ __forceinline__ bool unknown(int8_t t) { return t == 1 || t == 2; }
 
-// coarse rho(I, J, K) = sum over the 3 x 3 x 3 fine nodes of rwx rwy rwz r at unknown
-// coarse nodes, 0 elsewhere (every coarse node is written)
 template <typename T>
-__global__ void k_mg_restrict(int ncx, int ncy, int ncz, int nfx, int nfy, MgAxis<T> ax, MgAxis<T> ay, MgAxis<T> az,
-                              const int8_t *__restrict__ type_c, const T *__restrict__ r, T *__restrict__ rc)
+struct MgVec4;
+template <>
+struct MgVec4<float> {
+    typedef float type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct MgVec4<double> {
+    typedef double type __attribute__((ext_vector_type(4), aligned(8)));
+};
+
+// Coarse rho(I, J, K) = sum over the 3 x 3 x 3 fine nodes (2I - 1 .. 2I + 1, ...) of
+// rwx rwy rwz r at the unknown coarse nodes, 0 at the other interior nodes (the walls of rc
+// are never written and stay 0).  Block 64 x 4: lane l takes the interior coarse nodes
+// I0 = 1 + 128 blockIdx.x + 2 l and I0 + 1 of row J = 1 + 4 blockIdx.y + wavefront, plane
+// K = 1 + blockIdx.z; it reads fine nodes 2 I0 - 1 .. 2 I0 + 3 of each of the nine fine
+// rows as a 4-vector and one more value.  Every load is issued whatever the node types.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mg_restrict(int ncx, int ncy, int nfx, int nfy, MgAxis<T> ax, MgAxis<T> ay,
+                                                     MgAxis<T> az, const int8_t *__restrict__ type_c,
+                                                     const T *__restrict__ r, T *__restrict__ rc)
 {
-    const int I = (int)(blockIdx.x * blockDim.x + threadIdx.x), J = (int)blockIdx.y, K = (int)blockIdx.z;
-    if (I >= ncx) return;
-    const size_t ec = (size_t)I + (size_t)ncx * (J + (size_t)ncy * K);
-    T acc = T(0);
-    if (unknown(type_c[ec])) {
-        const size_t fplane = (size_t)nfx * nfy;
+    using V = typename MgVec4<T>::type;
+    const int I0 = 1 + (int)(blockIdx.x * 128 + 2 * threadIdx.x), J = 1 + (int)(blockIdx.y * 4 + threadIdx.y);
+    const int K = 1 + (int)blockIdx.z;
+    if (I0 > ncx - 2 || J > ncy - 2) return;
+    const bool two = I0 + 1 <= ncx - 2;
+    const int I1 = two ? I0 + 1 : I0;
+    T w0[3], w1[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const T wz = az.rw[3 * K + c];
-            const size_t kz = (size_t)az.ri[3 * K + c] * fplane;
+    for (int a = 0; a < 3; ++a) {
+        w0[a] = ax.rw[3 * I0 + a];
+        w1[a] = ax.rw[3 * I1 + a];
+    }
+    const size_t ec = (size_t)I0 + (size_t)ncx * (J + (size_t)ncy * K);
+    const bool unk0 = unknown(type_c[ec]), unk1 = two && unknown(type_c[ec + 1]);
+    const size_t fplane = (size_t)nfx * nfy;
+    const int f0 = 2 * I0 - 1;                      // first fine node of the lane
+    const int f4 = min(f0 + 4, nfx - 1);            // fifth node (I0 + 1's last), in the row
+    T acc0 = T(0), acc1 = T(0);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const T wyz = wz * ay.rw[3 * J + b];
-                const size_t jy = kz + (size_t)ay.ri[3 * J + b] * nfx;
-                T sx = T(0);
+    for (int c = 0; c < 3; ++c) {
+        const T wz = az.rw[3 * K + c];
+        const size_t kz = (size_t)(2 * K - 1 + c) * fplane;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) sx += ax.rw[3 * I + a] * r[jy + ax.ri[3 * I + a]];
-                acc += wyz * sx;
-            }
+        for (int b = 0; b < 3; ++b) {
+            const T wyz = wz * ay.rw[3 * J + b];
+            const T *row = r + kz + (size_t)(2 * J - 1 + b) * nfx;
+            const V v = *reinterpret_cast<const V *>(row + f0);
+            const T v4 = row[f4];
+            acc0 += wyz * (w0[0] * v.x + w0[1] * v.y + w0[2] * v.z);
+            acc1 += wyz * (w1[0] * v.z + w1[1] * v.w + w1[2] * v4);
         }
     }
-    rc[ec] = acc;
+    rc[ec] = unk0 ? acc0 : T(0);
+    if (two) rc[ec + 1] = unk1 ? acc1 : T(0);
 }
 
-// x(i, j, k) += (P e)(i, j, k) at unknown fine nodes
+// x(i, j, k) += (P e)(i, j, k) at the unknown fine nodes.  Block 64 x 4: lane l of
+// wavefront w takes the interior nodes i0 .. i0 + 3 (i0 = 1 + 256 blockIdx.x + 4 l) of row
+// j = 1 + 4 blockIdx.y + w in plane k = 1 + blockIdx.z.  A fine point i lies in the coarse
+// interval starting at min(i / 2, nc - 2) (coarse point I is fine point 2I, the last one
+// excepted), so the lane's nodes interpolate from the four coarse x points a0 .. a0 + 3.
+// Every load is issued at once (4-vectors: x, the four coarse rows, the x weights; vectors
+// and weight tables carry padding past their ends): the four coarse rows are combined in y
+// and z, then each node interpolates in x.  x is stored as one 4-vector where all four
+// nodes are unknowns.
 template <typename T>
-__global__ void k_mg_prolong_add(int nfx, int nfy, int nfz, int ncx, int ncy, MgAxis<T> ax, MgAxis<T> ay,
-                                 MgAxis<T> az, const int8_t *__restrict__ type_f, const T *__restrict__ e,
-                                 T *__restrict__ x)
+__global__ void __launch_bounds__(256) k_mg_prolong_add(int nfx, int nfy, int ncx, int ncy, int ncz, MgAxis<T> ax,
+                                                        MgAxis<T> ay, MgAxis<T> az,
+                                                        const int8_t *__restrict__ type_f, const T *__restrict__ e,
+                                                        T *__restrict__ x)
 {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x), j = (int)blockIdx.y, k = (int)blockIdx.z;
-    if (i >= nfx) return;
-    const size_t ef = (size_t)i + (size_t)nfx * (j + (size_t)nfy * k);
-    if (!unknown(type_f[ef])) return;
-    const int a = ax.pa[i], b = ay.pa[j], c = az.pa[k];
-    const T wx = ax.pw[i], wy = ay.pw[j], wz = az.pw[k];
+    using V = typename MgVec4<T>::type;
+    const int j = 1 + (int)(blockIdx.y * 4 + threadIdx.y), k = 1 + (int)blockIdx.z;
+    const int i0 = 1 + (int)(blockIdx.x * 256 + 4 * threadIdx.x);
+    if (j > nfy - 2 || i0 > nfx - 2) return;
+    const int nv = min(4, nfx - 1 - i0);
+    const size_t ef = (size_t)i0 + (size_t)nfx * (j + (size_t)nfy * k);
+    const int a0 = min(i0 >> 1, ncx - 2), b = min(j >> 1, ncy - 2), c = min(k >> 1, ncz - 2);
     const size_t cplane = (size_t)ncx * ncy;
-    const T *e0 = e + (size_t)c * cplane + (size_t)b * ncx + a;   // (a, b, c)
-    const T *e1 = e0 + cplane;                                     // (a, b, c + 1)
-    const T lo = (T(1) - wy) * ((T(1) - wx) * e0[0] + wx * e0[1]) + wy * ((T(1) - wx) * e0[ncx] + wx * e0[ncx + 1]);
-    const T hi = (T(1) - wy) * ((T(1) - wx) * e1[0] + wx * e1[1]) + wy * ((T(1) - wx) * e1[ncx] + wx * e1[ncx + 1]);
-    x[ef] += (T(1) - wz) * lo + wz * hi;
+    const T *e00 = e + (size_t)c * cplane + (size_t)b * ncx + a0;   // coarse (a0, b, c)
+    V xv = *reinterpret_cast<const V *>(x + ef);
+    const V q00 = *reinterpret_cast<const V *>(e00);
+    const V q10 = *reinterpret_cast<const V *>(e00 + ncx);
+    const V q01 = *reinterpret_cast<const V *>(e00 + cplane);
+    const V q11 = *reinterpret_cast<const V *>(e00 + cplane + ncx);
+    const V wxv = *reinterpret_cast<const V *>(ax.pw + i0);
+    int8_t ty[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ty[u] = type_f[ef + min(u, nv - 1)];
+    const T wy = ay.pw[j], wz = az.pw[k];
+    const T c00 = (T(1) - wz) * (T(1) - wy), c10 = (T(1) - wz) * wy, c01 = wz * (T(1) - wy), c11 = wz * wy;
+    const T ryz[4] = {c00 * q00.x + c10 * q10.x + c01 * q01.x + c11 * q11.x,
+                      c00 * q00.y + c10 * q10.y + c01 * q01.y + c11 * q11.y,
+                      c00 * q00.z + c10 * q10.z + c01 * q01.z + c11 * q11.z,
+                      c00 * q00.w + c10 * q10.w + c01 * q01.w + c11 * q11.w};
+    const T wx[4] = {wxv.x, wxv.y, wxv.z, wxv.w};
+    T add[4];
+    bool m[4];
+    bool all = nv == 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int d = min((i0 + u) >> 1, ncx - 2) - a0;   // 0 .. 2
+        const T lo = d == 0 ? ryz[0] : (d == 1 ? ryz[1] : ryz[2]);
+        const T hi = d == 0 ? ryz[1] : (d == 1 ? ryz[2] : ryz[3]);
+        add[u] = (T(1) - wx[u]) * lo + wx[u] * hi;
+        m[u] = u < nv && unknown(ty[u]);
+        all = all && m[u];
+    }
+    if (all) {
+        xv.x += add[0];
+        xv.y += add[1];
+        xv.z += add[2];
+        xv.w += add[3];
+        *reinterpret_cast<V *>(x + ef) = xv;
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (m[u]) x[ef + u] += add[u];
+    }
 }
 
 }  // namespace
@@ -78,17 +152,17 @@ __global__ void k_mg_prolong_add(int nfx, int nfy, int nfz, int ncx, int ncy, Mg
 template <typename T>
 void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_c, const T *r, T *rc)
 {
-    dim3 grid((unsigned)((t.nc[0] + 63) / 64), (unsigned)t.nc[1], (unsigned)t.nc[2]);
-    k_mg_restrict<T><<<grid, 64, 0, s>>>(t.nc[0], t.nc[1], t.nc[2], t.nf[0], t.nf[1], t.ax[0], t.ax[1], t.ax[2],
-                                         type_c, r, rc);
+    dim3 grid((unsigned)((t.nc[0] - 2 + 127) / 128), (unsigned)((t.nc[1] - 2 + 3) / 4), (unsigned)(t.nc[2] - 2));
+    k_mg_restrict<T><<<grid, dim3(64, 4), 0, s>>>(t.nc[0], t.nc[1], t.nf[0], t.nf[1], t.ax[0], t.ax[1], t.ax[2], type_c,
+                                                  r, rc);
 }
 
 template <typename T>
 void launch_mg_prolong_add(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_f, const T *e, T *x)
 {
-    dim3 grid((unsigned)((t.nf[0] + 63) / 64), (unsigned)t.nf[1], (unsigned)t.nf[2]);
-    k_mg_prolong_add<T><<<grid, 64, 0, s>>>(t.nf[0], t.nf[1], t.nf[2], t.nc[0], t.nc[1], t.ax[0], t.ax[1], t.ax[2],
-                                            type_f, e, x);
+    dim3 grid((unsigned)((t.nf[0] - 2 + 255) / 256), (unsigned)((t.nf[1] - 2 + 3) / 4), (unsigned)(t.nf[2] - 2));
+    k_mg_prolong_add<T><<<grid, dim3(64, 4), 0, s>>>(t.nf[0], t.nf[1], t.nc[0], t.nc[1], t.nc[2], t.ax[0], t.ax[1],
+                                                     t.ax[2], type_f, e, x);
 }
 
 template void launch_mg_restrict<double>(hipStream_t, const MgTransfer<double> &, const int8_t *, const double *,

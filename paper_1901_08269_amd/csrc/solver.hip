@@ -330,7 +330,13 @@ Tiling make_tiling(int nx, int ny, int nz, int tw, int ty, int target_blocks, in
 #define CPS_FLAT_BLOCKS 4096
 #endif
 
-Geom make_geom(int nx, int ny, int nz)
+// coarse = true (a coarse multigrid level): the sweep tiling aims at CPS_COARSE_TILES tiles
+// of at least one plane each, since a small grid's sweep is bound by the latency of its
+// z-march rather than by bandwidth
+#ifndef CPS_COARSE_TILES
+#define CPS_COARSE_TILES 2048
+#endif
+Geom make_geom(int nx, int ny, int nz, bool coarse = false)
 {
     Geom g{};
     g.nx = nx; g.ny = ny; g.nz = nz;
@@ -341,7 +347,8 @@ Geom make_geom(int nx, int ny, int nz)
     }
     {
         const int per_plane = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY * RPW - 1) / (TY * RPW));
-        g.tr = make_tiling(nx, ny, nz, 4 * TX, TY * RPW, per_plane * CPS_ROW_ZCHUNKS, 4);
+        g.tr = coarse ? make_tiling(nx, ny, nz, 4 * TX, TY * RPW, CPS_COARSE_TILES, 1)
+                      : make_tiling(nx, ny, nz, 4 * TX, TY * RPW, per_plane * CPS_ROW_ZCHUNKS, 4);
     }
     size_t nn = (size_t)nx * ny * nz;
     g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, CPS_FLAT_BLOCKS);
@@ -773,12 +780,13 @@ int count_type(cps_solver *s, int8_t want, int *list, long long *count)
     return count_nodes(s, s->nn, s->type, want, list, count);
 }
 
-// 1D multigrid tables of one axis: fine coordinates xf[nf], the coarse points' indices idx.
-// Prolongation: the left coarse index a (the last one at most nc - 2) and the weight of
-// coarse point a + 1 from the physical coordinates.  Restriction: P^T, each coarse row
-// divided by its sum, at most three nonzero entries per row (padded with weight 0).
+// 1D multigrid tables of one axis: fine coordinates xf[nf], the coarse points' indices idx
+// (2I for every coarse point I but the last).  Prolongation: the left coarse index a (the
+// last one at most nc - 2) and the weight of coarse point a + 1 from the physical
+// coordinates.  Restriction: P^T, each interior coarse row divided by its sum; its nonzero
+// entries lie on fine points 2I - 1 .. 2I + 1, stored at rw[3I + (i - 2I + 1)].
 void mg_axis_tables(const double *xf, int nf, const std::vector<int> &idx, std::vector<int> &pa,
-                    std::vector<double> &pw, std::vector<int> &ri, std::vector<double> &rw)
+                    std::vector<double> &pw, std::vector<double> &rw)
 {
     const int nc = (int)idx.size();
     pa.assign(nf, 0);
@@ -789,28 +797,21 @@ void mg_axis_tables(const double *xf, int nf, const std::vector<int> &idx, std::
         pa[i] = a;
         pw[i] = (xf[i] - xf[idx[a]]) / (xf[idx[a + 1]] - xf[idx[a]]);
     }
-    ri.assign(3 * (size_t)nc, 0);
     rw.assign(3 * (size_t)nc, 0.0);
-    std::vector<int> cnt(nc, 0);
     std::vector<double> sum(nc, 0.0);
     auto add = [&](int I, int i, double w) {
-        if (w == 0.0) return;
-        if (cnt[I] == 3) throw CPS_EINVAL;
-        ri[3 * I + cnt[I]] = i;
-        rw[3 * I + cnt[I]] = w;
-        ++cnt[I];
+        if (w == 0.0 || I == 0 || I == nc - 1) return;   // wall rows are never restricted to
+        const int q = i - (2 * I - 1);
+        if (q < 0 || q > 2) throw CPS_EINVAL;
+        rw[3 * I + q] += w;
         sum[I] += w;
     };
     for (int i = 0; i < nf; ++i) {
         add(pa[i], i, 1.0 - pw[i]);
         add(pa[i] + 1, i, pw[i]);
     }
-    for (int I = 0; I < nc; ++I) {
-        for (int q = 0; q < 3; ++q) {
-            if (q >= cnt[I]) ri[3 * I + q] = idx[I];
-            else rw[3 * I + q] /= sum[I];
-        }
-    }
+    for (int I = 1; I < nc - 1; ++I)
+        for (int q = 0; q < 3; ++q) rw[3 * I + q] /= sum[I];
 }
 
 template <typename D>
@@ -862,13 +863,14 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
                 hc.push_back(hx[off + i]);
                 gidx.push_back(i);
             }
-            std::vector<int> pa, ri;
+            std::vector<int> pa;
             std::vector<double> pw, rw;
-            mg_axis_tables(hx.data() + off, F.n[d], idx[d], pa, pw, ri, rw);
+            mg_axis_tables(hx.data() + off, F.n[d], idx[d], pa, pw, rw);
+            pw.resize(pw.size() + 4, 0.0);   // padding: 4-vector loads of the weights
             std::vector<float> pw32(pw.begin(), pw.end()), rw32(rw.begin(), rw.end());
-            const int *dpa = upload(s, pa), *dri = upload(s, ri);
-            F.t64.ax[d] = MgAxis<double>{dpa, upload(s, pw), dri, upload(s, rw)};
-            F.t32.ax[d] = MgAxis<float>{dpa, upload(s, pw32), dri, upload(s, rw32)};
+            const int *dpa = upload(s, pa);
+            F.t64.ax[d] = MgAxis<double>{dpa, upload(s, pw), upload(s, rw)};
+            F.t32.ax[d] = MgAxis<float>{dpa, upload(s, pw32), upload(s, rw32)};
             F.t64.nf[d] = F.t32.nf[d] = F.n[d];
             F.t64.nc[d] = F.t32.nc[d] = C.n[d];
             off += F.n[d];
@@ -876,7 +878,7 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
         const int cx = C.n[0], cy = C.n[1], cz = C.n[2];
         C.nmax = std::max({cx, cy, cz});
         C.nn = (size_t)cx * cy * cz;
-        C.g = make_geom(cx, cy, cz);
+        C.g = make_geom(cx, cy, cz, true);
         C.xyz = upload(s, hc);
         const int *dg = upload(s, gidx);
         double *phic = dalloc<double>(s, C.nn);

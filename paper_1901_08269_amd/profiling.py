@@ -52,6 +52,7 @@ def source_hash():
 
 
 def short_name(n):
+    n = n.replace("(anonymous namespace)::", "")
     n = re.sub(r"\(cps::Geom.*", "", n)
     n = re.sub(r"\(.*", "", n)
     return n.replace("void ", "")
