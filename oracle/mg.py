@@ -81,7 +81,7 @@ def lambda_1(shape):
 
 
 class Multigrid:
-    def __init__(self, x, y, z, phi, levels=4, nu=3, smooth_lo=0.5, coarse_steps=24, min_points=9):
+    def __init__(self, x, y, z, phi, levels=4, nu=4, smooth_lo=0.5, coarse_steps=24, min_points=9):
         self.nu, self.smooth_lo, self.coarse_steps = nu, smooth_lo, coarse_steps
         self.lv = []
         xs, phis = (np.asarray(x, float), np.asarray(y, float), np.asarray(z, float)), np.asarray(phi, float)

@@ -999,7 +999,7 @@ void cps_default_options(cps_options *o)
     o->stream = nullptr;
     o->precond = CPS_PRECOND_CHEBYSHEV;
     o->mg_levels = 4;
-    o->mg_nu = 3;
+    o->mg_nu = 4;
     o->mg_coarse_steps = 24;
     o->mg_smooth_lo = 0.5;
 }

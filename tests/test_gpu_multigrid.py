@@ -55,7 +55,7 @@ def _random_rho(phi_shape, types, seed):
 def test_vcycle_matches_oracle(name):
     w = _case(name)
     print(f"[case] multigrid {name} shape {w.phi.shape}", flush=True)
-    M = mg.Multigrid(w.x, w.y, w.z, w.phi)          # 4 levels at most, 3 + 3 steps, 24 coarse
+    M = mg.Multigrid(w.x, w.y, w.z, w.phi)          # 4 levels at most, 4 + 4 steps, 24 coarse
     rho = _random_rho(w.phi.shape, M.lv[0]["P"].types(), 31)
     ref = M.apply(rho)
     scale = np.max(np.abs(ref))
@@ -116,3 +116,23 @@ def test_solve_with_multigrid_matches_oracle(name, precision):
     rel = np.max(np.abs(u - u_ref)[fl]) / np.max(np.abs(u_ref[fl]))
     assert rel <= 1e-9, rel
     assert np.all(u[t == 3] == 0.0)
+
+
+def test_spheres8_256_multigrid_vs_oracle_samples():
+    """256^3 with 8 spheres, the multigrid preconditioner, both precisions: at tol 1e-10 the
+    residual bounds hold; at tol 1e-13 the solution matches the stored FP64 oracle solution
+    (solved to 1e-13) to <= 1e-9 relative max-norm on the sampled nodes."""
+    from test_gpu_parity import _samples
+    nodes, vals, umax = _samples("oracle_spheres8_256.txt")
+    w = W.spheres8(256)
+    for precision in ("mixed", "fp64"):
+        print(f"[case] spheres8 256 multigrid {precision}", flush=True)
+        S = cps.Solver.from_workload(w, precision=precision, precond="multigrid")
+        u, st = S.solve(1e-10)
+        assert st["rel_residual"] <= 1e-10 and st["rel_residual_jacobi"] <= 1e-10
+        u, st = S.solve(1e-13)
+        assert st["rel_residual"] <= 1e-13 and st["rel_residual_jacobi"] <= 1e-13
+        rel = np.max(np.abs(_np(u).ravel()[nodes] - vals)) / umax
+        print(f"{precision}: {st['iters']} iterations, max rel. difference vs oracle samples {rel:.2e}")
+        assert rel <= 1e-9
+        S.close()
