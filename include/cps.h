@@ -73,13 +73,14 @@ typedef struct cps_options {
     /* How K phi = rho is solved approximately inside the preconditioner (Sec. 3.3 leaves the
      * inner solver open).  CPS_PRECOND_MULTIGRID: one V-cycle.  A coarser grid keeps the
      * even-indexed points and the last point along every axis (while every axis has at least
-     * 17 points); its K is built from the level set at its nodes.  Prolongation is trilinear
+     * 17 points and the grid has more than 4096 interior points); its K is built from the
+     * level set at its nodes.  Prolongation is trilinear
      * interpolation in the physical coordinates; restriction is its transpose with each row
      * divided by its sum.  Smoother: mg_nu Chebyshev-Jacobi steps before and after each
      * coarse correction on [mg_smooth_lo, lam_hi]; the coarsest grid takes mg_coarse_steps
      * steps on [lambda_1, lam_hi] of that grid.  The cycle is a fixed linear map of rho. */
     int32_t precond;         /* CPS_PRECOND_CHEBYSHEV (default) or CPS_PRECOND_MULTIGRID */
-    int32_t mg_levels;       /* most levels, this grid included, 1..16 (default 4) */
+    int32_t mg_levels;       /* most levels, this grid included, 1..16 (default 16) */
     int32_t mg_nu;           /* smoothing steps before and after, 1..64 (default 4) */
     int32_t mg_coarse_steps; /* steps on the coarsest grid, 1..64 (default 24) */
     double mg_smooth_lo;     /* lower end of the smoother's interval, in (0, lam_hi) (default 0.5) */
@@ -111,7 +112,7 @@ typedef struct cps_stats {
 /* Fill `o` with the defaults: CPS_FP64, 24 inner iterations, max_iters 20000,
  * max_refine 40, max_restarts 5, host pointers, inner_tol 1e-4, the default Chebyshev
  * interval, null stream, no kernel timing, the Chebyshev preconditioner (multigrid
- * settings 4 levels, 4 + 4 smoothing steps on [0.5, lam_hi], 24 coarsest-grid steps). */
+ * settings up to 16 levels, 4 + 4 smoothing steps on [0.5, lam_hi], 24 coarsest-grid steps). */
 void cps_default_options(cps_options *o);
 
 /* Build the discrete problem (Secs. 2-3): classify nodes from the sign of phi (Sec. 2,

@@ -11,7 +11,8 @@ smoother), so that it can be checked by eye against this definition:
   even-indexed points and the last point (a wall); its level set is the finer level set at
   those nodes, and its K (Eqs. 2ndorder_coef, A7, with Shortley-Weller rows at nodes next
   to the body, Eqs. 2ndorder_coef_mod, A7_mod) is built on its own coordinates.  Coarsening
-  stops after `levels` levels or when an axis would have fewer than `min_points` points.
+  stops after `levels` levels, when an axis would have fewer than `min_points` points, or
+  once a level has at most `coarse_interior` interior points.
 * Transfer.  Prolongation P is the tensor product of 1D linear interpolation in the
   physical coordinate: a fine node that is a coarse node takes its value, a fine node
   between coarse nodes a and b takes (1 - w) e_a + w e_b with w = (x - x_a) / (x_b - x_a).
@@ -81,7 +82,8 @@ def lambda_1(shape):
 
 
 class Multigrid:
-    def __init__(self, x, y, z, phi, levels=4, nu=4, smooth_lo=0.5, coarse_steps=24, min_points=9):
+    def __init__(self, x, y, z, phi, levels=16, nu=4, smooth_lo=0.5, coarse_steps=24, min_points=9,
+                 coarse_interior=4096):
         self.nu, self.smooth_lo, self.coarse_steps = nu, smooth_lo, coarse_steps
         self.lv = []
         xs, phis = (np.asarray(x, float), np.asarray(y, float), np.asarray(z, float)), np.asarray(phi, float)
@@ -89,7 +91,8 @@ class Multigrid:
             P = oracle.Problem.k_only(xs[0], xs[1], xs[2], phis)
             t = P.types()
             self.lv.append({"P": P, "x": xs, "unk": ((t == 1) | (t == 2)).astype(float), "shape": phis.shape})
-            if l + 1 == levels or min(len(c) for c in xs) < 2 * min_points - 1:
+            interior = np.prod([len(c) - 2 for c in xs])
+            if l + 1 == levels or min(len(c) for c in xs) < 2 * min_points - 1 or interior <= coarse_interior:
                 break
             idx = [coarse_indices(len(c)) for c in xs]
             xc = tuple(c[i] for c, i in zip(xs, idx))

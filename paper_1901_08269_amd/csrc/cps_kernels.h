@@ -66,6 +66,17 @@ struct MgTransfer {
 // rc = R r at the unknown coarse nodes (type_c), 0 at every other coarse node
 template <typename T>
 void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_c, const T *r, T *rc);
+// The coarsest level's `steps` Chebyshev steps (coefficients c1, c2) from 0 in one workgroup
+// of MG_LDS_THREADS threads; the level has at most MG_LDS_NODES interior nodes.  irr_map:
+// irregular row of each irregular node.  Writes out at the unknown nodes.
+constexpr int MG_LDS_NODES = 4096;
+constexpr int MG_LDS_THREADS = 1024;
+template <typename T>
+void launch_mg_coarsest(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf, const int8_t *type,
+                        const int *irr_map, const T *k7, const T *rho, T *out, int steps, const T *c1, const T *c2,
+                        const DevState *st);
+// map[nodes[r]] = r for the nirr irregular rows
+void launch_mg_irr_map(hipStream_t s, int nirr, const int *nodes, int *map);
 // x += P e at the unknown fine nodes (type_f)
 template <typename T>
 void launch_mg_prolong_add(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_f, const T *e, T *x);

@@ -147,6 +147,112 @@ __global__ void __launch_bounds__(256) k_mg_prolong_add(int nfx, int nfy, int nc
     }
 }
 
+// The coarsest level's Chebyshev-Jacobi iteration on K x = rho from x = 0, all `steps` steps
+// in one workgroup (the level has at most MG_LDS_NODES interior nodes): x_k lives in LDS
+// (interior nodes, x fastest); each thread keeps, for its nodes q = t + MG_LDS_THREADS u,
+// x_{k-1} and the K row and rho divided by the row's diagonal (the tables' regular row, or
+// the stored Shortley-Weller row of an irregular node) in registers.  A barrier separates the reads of x_k from the writes of
+// x_{k+1}.  Wall neighbours hold 0 in every iterate and get coefficient 0; solid nodes are
+// never written.  x_steps goes to the unknown nodes of out.
+template <typename T>
+__global__ void __launch_bounds__(MG_LDS_THREADS) k_mg_coarsest(int nx, int ny, int nz, Coef<T> cf,
+                                                                const int8_t *__restrict__ type,
+                                                                const int *__restrict__ irr_map,
+                                                                const T *__restrict__ k7, const T *__restrict__ rho,
+                                                                T *__restrict__ out, int steps,
+                                                                const T *__restrict__ c1, const T *__restrict__ c2,
+                                                                const DevState *st)
+{
+    constexpr int NPT = MG_LDS_NODES / MG_LDS_THREADS;
+    __shared__ T xs[MG_LDS_NODES];
+    if (st && st->done) return;
+    const int ni = nx - 2, nj = ny - 2, nk = nz - 2, nij = ni * nj, nint = nij * nk;
+    const int t = (int)threadIdx.x;
+    T kd[NPT], ko[NPT][6], rh[NPT], xp[NPT];
+    unsigned inm[NPT];                 // bit v: neighbour v (-x, +x, -y, +y, -z, +z) is interior
+    bool act[NPT];
+    auto node_of = [&](int q) {
+        const int i = 1 + q % ni, j = 1 + (q / ni) % nj, k = 1 + q / nij;
+        return (size_t)i + (size_t)nx * (j + (size_t)ny * k);
+    };
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        const int q = t + MG_LDS_THREADS * u;
+        xs[q] = T(0);
+        xp[u] = T(0);
+        act[u] = false;
+        kd[u] = T(1);
+        rh[u] = T(0);
+        inm[u] = 0u;
+#pragma unroll
+        for (int v = 0; v < 6; ++v) ko[u][v] = T(0);
+        if (q >= nint) continue;
+        const int i = 1 + q % ni, j = 1 + (q / ni) % nj, k = 1 + q / nij;
+        const size_t e = node_of(q);
+        const int8_t ty = type[e];
+        act[u] = ty == 1 || ty == 2;
+        if (!act[u]) continue;
+        rh[u] = rho[e];
+        if (ty == 2) {
+            const T *row = k7 + 7 * (size_t)irr_map[e];
+            kd[u] = row[0];
+#pragma unroll
+            for (int v = 0; v < 6; ++v) ko[u][v] = row[1 + v];
+        } else {
+            const T *cx = cf.c[0] + 8 * i, *cy = cf.c[1] + 8 * j, *cz = cf.c[2] + 8 * k;
+            kd[u] = cx[6] + cy[6] + cz[6];
+            ko[u][0] = cx[5]; ko[u][1] = cx[7];
+            ko[u][2] = cy[5]; ko[u][3] = cy[7];
+            ko[u][4] = cz[5]; ko[u][5] = cz[7];
+        }
+        // a wall neighbour is read as the node itself with coefficient 0
+        inm[u] = (i > 1 ? 1u : 0u) | (i < nx - 2 ? 2u : 0u) | (j > 1 ? 4u : 0u) | (j < ny - 2 ? 8u : 0u) |
+                 (k > 1 ? 16u : 0u) | (k < nz - 2 ? 32u : 0u);
+#pragma unroll
+        for (int v = 0; v < 6; ++v)
+            if (!((inm[u] >> v) & 1u)) ko[u][v] = T(0);
+    }
+    // rows scaled by 1 / diag K: (rho - K x) / diag = rho' - x - sum_v ko'_v x_v
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        const T rd = T(1) / kd[u];
+        rh[u] *= rd;
+#pragma unroll
+        for (int v = 0; v < 6; ++v) ko[u][v] *= rd;
+    }
+    __syncthreads();
+    const int d[6] = {-1, 1, -ni, ni, -nij, nij};
+    for (int s = 0; s < steps; ++s) {
+        const T a1 = c1[s], a2 = c2[s];
+        T xn[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int q = t + MG_LDS_THREADS * u;
+            const T x0 = xs[q];
+            T kx = x0;
+#pragma unroll
+            for (int v = 0; v < 6; ++v) kx += ko[u][v] * xs[((inm[u] >> v) & 1u) ? q + d[v] : q];
+            xn[u] = x0 + a1 * (x0 - xp[u]) + a2 * (rh[u] - kx);
+            xp[u] = x0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NPT; ++u)
+            if (act[u]) xs[t + MG_LDS_THREADS * u] = xn[u];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < NPT; ++u)
+        if (act[u]) out[node_of(t + MG_LDS_THREADS * u)] = xs[t + MG_LDS_THREADS * u];
+}
+
+// map[node] = irregular row of the node (the rows list nodes in increasing order)
+__global__ void k_mg_irr_map(int nirr, const int *__restrict__ nodes, int *__restrict__ map)
+{
+    const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (r < nirr) map[nodes[r]] = r;
+}
+
 }  // namespace
 
 template <typename T>
@@ -165,6 +271,25 @@ void launch_mg_prolong_add(hipStream_t s, const MgTransfer<T> &t, const int8_t *
                                                      t.ax[2], type_f, e, x);
 }
 
+template <typename T>
+void launch_mg_coarsest(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf, const int8_t *type,
+                        const int *irr_map, const T *k7, const T *rho, T *out, int steps, const T *c1, const T *c2,
+                        const DevState *st)
+{
+    k_mg_coarsest<T><<<1, MG_LDS_THREADS, 0, s>>>(nx, ny, nz, cf, type, irr_map, k7, rho, out, steps, c1, c2, st);
+}
+
+void launch_mg_irr_map(hipStream_t s, int nirr, const int *nodes, int *map)
+{
+    if (nirr > 0) k_mg_irr_map<<<(nirr + 255) / 256, 256, 0, s>>>(nirr, nodes, map);
+}
+
+template void launch_mg_coarsest<double>(hipStream_t, int, int, int, const Coef<double> &, const int8_t *, const int *,
+                                         const double *, const double *, double *, int, const double *, const double *,
+                                         const DevState *);
+template void launch_mg_coarsest<float>(hipStream_t, int, int, int, const Coef<float> &, const int8_t *, const int *,
+                                        const float *, const float *, float *, int, const float *, const float *,
+                                        const DevState *);
 template void launch_mg_restrict<double>(hipStream_t, const MgTransfer<double> &, const int8_t *, const double *,
                                          double *);
 template void launch_mg_restrict<float>(hipStream_t, const MgTransfer<float> &, const int8_t *, const float *, float *);

@@ -44,7 +44,9 @@ struct Vecs {
 };
 
 // Multigrid preconditioner for K: a coarser level keeps the even-indexed points and the
-// last one along every axis while an axis has at least 2 MG_MIN_POINTS - 1 points.
+// last one along every axis while every axis has at least 2 MG_MIN_POINTS - 1 points and
+// the level has more than MG_LDS_NODES interior points (a level that small is solved in one
+// workgroup).
 constexpr int MG_MIN_POINTS = 9;
 constexpr int MG_MAX_LEVELS = 16;
 
@@ -64,6 +66,7 @@ struct MgLevel {
     int *irr_node = nullptr;
     double *k64 = nullptr;
     float *k32 = nullptr;
+    int *irr_map = nullptr;     // coarsest level solved in one workgroup: node -> irregular row
     MgTransfer<double> t64{};   // transfers to the next coarser level
     MgTransfer<float> t32{};
     double *v64[3] = {nullptr, nullptr, nullptr};   // level right-hand side, two iterates
@@ -114,6 +117,8 @@ struct cps_solver {
     std::vector<double> mg_cc1, mg_cc2; // coarsest-level steps on [lambda_1, lam_hi]
     double *mg_zero64 = nullptr;        // zeros, the size of level 1
     float *mg_zero32 = nullptr;
+    double *mg_ccd64 = nullptr;         // mg_cc1 | mg_cc2 on the device (one-workgroup coarsest solve)
+    float *mg_ccd32 = nullptr;
     // host-side facts
     long long n_unknown = 0, n_solid = 0, nnz = 0, fallback = 0;
     double min_hb = 1.0;
@@ -496,9 +501,17 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
     const Launch L{Lv.g, s->stream, Lv.skip, s->partials, s->ticket};
     const Coef<T> cf = mg_coef<T>(Lv);
     const Irr<T> ir = mg_irr<T>(Lv);
-    if (l + 1 == (int)s->mg.size())
+    if (l + 1 == (int)s->mg.size()) {
+        if (Lv.irr_map) {
+            const T *cc;
+            if constexpr (sizeof(T) == 8) cc = s->mg_ccd64; else cc = s->mg_ccd32;
+            launch_mg_coarsest<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, A,
+                                  s->opt.mg_coarse_steps, cc, cc + s->mg_cc1.size(), st);
+            return A;
+        }
         return mg_smooth<T>(s, L, cf, ir, R, nullptr, Z, A, B, nullptr, 0, s->opt.mg_coarse_steps, s->mg_cc1.data(),
                             s->mg_cc2.data(), st, false);
+    }
     const int nu = s->opt.mg_nu;
     T *x = mg_smooth<T>(s, L, cf, ir, R, nullptr, Z, A, B, nullptr, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
     T *r = (x == A) ? B : A;
@@ -851,6 +864,7 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
     while ((int)s->mg.size() < s->opt.mg_levels) {
         MgLevel &F = s->mg.back();
         if (std::min({F.n[0], F.n[1], F.n[2]}) < 2 * MG_MIN_POINTS - 1) break;
+        if ((size_t)(F.n[0] - 2) * (F.n[1] - 2) * (F.n[2] - 2) <= (size_t)MG_LDS_NODES) break;
         MgLevel C;
         std::vector<int> idx[3], gidx;
         std::vector<double> hc;
@@ -934,6 +948,18 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
     for (int d = 0; d < 3; ++d) lam1 += 1.0 - std::cos(pi / (Lc.n[d] - 1));
     lam1 /= 3.0;
     cheb_coefficients(nmax, lam1, s->opt.lam_hi, s->mg_cc1.data(), s->mg_cc2.data());
+    // a coarsest level below the problem's grid that fits one workgroup is solved there
+    MgLevel &Lc2 = s->mg.back();
+    if (s->mg.size() > 1 && (size_t)(Lc2.n[0] - 2) * (Lc2.n[1] - 2) * (Lc2.n[2] - 2) <= (size_t)MG_LDS_NODES) {
+        Lc2.irr_map = dalloc<int>(s, Lc2.nn);
+        launch_mg_irr_map(s->stream, Lc2.nirr, Lc2.irr_node, Lc2.irr_map);
+        std::vector<double> cc(s->mg_cc1);
+        cc.insert(cc.end(), s->mg_cc2.begin(), s->mg_cc2.end());
+        std::vector<float> cc32(cc.begin(), cc.end());
+        s->mg_ccd64 = upload(s, cc);
+        s->mg_ccd32 = upload(s, cc32);
+        sync(s);
+    }
 }
 
 template <typename T>
@@ -998,7 +1024,7 @@ void cps_default_options(cps_options *o)
     o->lam_hi = DEFAULT_LAM_HI;
     o->stream = nullptr;
     o->precond = CPS_PRECOND_CHEBYSHEV;
-    o->mg_levels = 4;
+    o->mg_levels = MG_MAX_LEVELS;
     o->mg_nu = 4;
     o->mg_coarse_steps = 24;
     o->mg_smooth_lo = 0.5;

@@ -18,7 +18,7 @@ def _np(t):
 
 
 def _case(name):
-    if name == "sphere_stretched":        # 40^3: three levels (40, 21, 11)
+    if name == "sphere_stretched":        # 40^3: three levels (40, 21, 11), the last in one workgroup
         w = W.sphere_sin(38, beta=1.4, r=0.27, c=(0.52, 0.47, 0.5))
     elif name == "two_bodies_aniso":      # (70, 41, 29): two levels
         x, y, z = W.tanh_grid(70, 1.5), W.tanh_grid(41, 1.0), W.uniform_grid(29)
@@ -31,6 +31,12 @@ def _case(name):
         x, y, z = W.tanh_grid(283, 1.3), W.tanh_grid(70, 0.9), W.uniform_grid(45)
         bodies = [W.Sphere((0.3, 0.5, 0.5), 0.2), W.Sphere((0.72, 0.42, 0.55), 0.14)]
         w = W.polynomial_case(0, bodies, rng_seed=21, grids=(x, y, z))
+    elif name == "ragged_lds":            # (44, 37, 35) -> (23, 19, 18) -> (12, 10, 10): the coarsest
+        # grid (640 interior points) is solved in one workgroup
+        x, y, z = W.tanh_grid(44, 1.2), W.uniform_grid(37), W.tanh_grid(35, 0.8)
+        bodies = [W.Ellipsoid((0.48, 0.52, 0.5), (0.22, 0.15, 0.18),
+                              W._random_rotation(np.random.Generator(np.random.PCG64(8))))]
+        w = W.polynomial_case(0, bodies, rng_seed=5, grids=(x, y, z))
     elif name == "single_level":          # (300, 14, 11): too small to coarsen
         x, y, z = W.tanh_grid(300, 1.1), W.uniform_grid(14), W.uniform_grid(11)
         w = W.polynomial_case(0, [W.Sphere((0.78, 0.5, 0.47), 0.22)], rng_seed=11, grids=(x, y, z))
@@ -51,11 +57,11 @@ def _random_rho(phi_shape, types, seed):
     return rng.standard_normal(phi_shape) * ((types == 1) | (types == 2))
 
 
-@pytest.mark.parametrize("name", ["sphere_stretched", "two_bodies_aniso", "wide_ragged", "single_level"])
+@pytest.mark.parametrize("name", ["sphere_stretched", "two_bodies_aniso", "wide_ragged", "ragged_lds", "single_level"])
 def test_vcycle_matches_oracle(name):
     w = _case(name)
     print(f"[case] multigrid {name} shape {w.phi.shape}", flush=True)
-    M = mg.Multigrid(w.x, w.y, w.z, w.phi)          # 4 levels at most, 4 + 4 steps, 24 coarse
+    M = mg.Multigrid(w.x, w.y, w.z, w.phi)          # default levels, 4 + 4 steps, 24 coarse
     rho = _random_rho(w.phi.shape, M.lv[0]["P"].types(), 31)
     ref = M.apply(rho)
     scale = np.max(np.abs(ref))
@@ -100,7 +106,7 @@ def test_one_level_is_the_chebyshev_iteration():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("name", ["sphere_stretched", "wide_ragged"])
+@pytest.mark.parametrize("name", ["sphere_stretched", "wide_ragged", "ragged_lds"])
 def test_solve_with_multigrid_matches_oracle(name, precision):
     w = _case(name)
     print(f"[case] multigrid solve {name} {precision}", flush=True)

@@ -101,7 +101,7 @@ def test_vcycle_is_linear_and_converges_as_a_stationary_iteration():
     """M is a fixed linear map, and x <- x + M (rho - K x) contracts the error of the dense
     direct solution of K x = rho by a grid-independent factor (here < 0.6 per cycle over 8)."""
     x, phi = _sphere_problem(22)
-    M = mg.Multigrid(x, x, x, phi, levels=3, min_points=5)
+    M = mg.Multigrid(x, x, x, phi, levels=3, min_points=5, coarse_interior=0)
     assert len(M.lv) == 3
     K0 = M.lv[0]["P"]
     unk = M.lv[0]["unk"].astype(bool)
