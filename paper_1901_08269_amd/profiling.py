@@ -6,9 +6,10 @@ Three reports:
 ``kernels``  the solve kernels of such a run against the HBM roofline: algorithmic bytes
              per interior point (each operand read or written once), GB/s from the average
              launch duration, fraction of the 8 TB/s peak.
-``traffic``  HBM bytes per launch of one kernel from two ``--pmc`` runs (``FETCH_SIZE`` and
-             ``WRITE_SIZE``, each in its own pass), each counter scaled by what the same counter
-             reads for a plain device copy of known size (the calibration runs).  The report
+``traffic``  HBM bytes per launch of one kernel on the problem's grid from two ``--pmc`` runs
+             (``FETCH_SIZE`` and ``WRITE_SIZE``, each in its own pass), each counter scaled by
+             what the same counter reads for a plain device copy of known size (the
+             calibration runs).  The report
              ends with machine-readable ``key: value`` lines, including a hash of the kernel
              sources, so a reader can tell whether the counters still describe the code.
 
@@ -66,15 +67,24 @@ def kernel_stats(db):
 
 
 def pmc_per_kernel(db):
-    """{short kernel name: (dispatches, mean counter value, mean duration ns)}"""
+    """{short kernel name: (dispatches, mean counter value, mean duration ns)} over each
+    kernel's dispatches on the problem's grid: a kernel that also runs on coarser multigrid
+    levels has one launch grid per level, and the problem's grid is the one whose launches
+    take longest."""
     con = sqlite3.connect(db)
     acc = {}
-    for name, val, dur in con.execute("select name,counter_value,duration from pmc_events"):
-        n = short_name(name)
-        c, v, d = acc.get(n, (0, 0.0, 0.0))
-        acc[n] = (c + 1, v + val, d + dur)
+    rows = con.execute("select p.name, p.counter_value, p.duration, k.grid_x * k.grid_y * k.grid_z "
+                       "from pmc_events p join kernels k on p.dispatch_id = k.dispatch_id")
+    for name, val, dur, size in rows:
+        key = (short_name(name), size)
+        c, v, d = acc.get(key, (0, 0.0, 0.0))
+        acc[key] = (c + 1, v + val, d + dur)
     con.close()
-    return {k: (c, v / c, d / c) for k, (c, v, d) in acc.items()}
+    best = {}
+    for (n, size), (c, v, d) in acc.items():
+        if n not in best or d / c > best[n][3] / best[n][1]:
+            best[n] = (size, c, v, d)
+    return {n: (c, v / c, d / c) for n, (size, c, v, d) in best.items()}
 
 
 def stats_report(db, title, cmd, top=20):
@@ -97,9 +107,12 @@ def algorithmic_bytes(name):
     k_first4      p = r + beta (p - omega v) (P) or s = r - alpha v (S), and x_1 = c p / diag K
     k_apply4      y = B x with a second operand (V, T), y = B x (plain), r = b - B x (residual)
     k_update4     x += alpha p^ + omega s^, r = s - omega t, with (r0, r)
+    k_resid4      r = rho - K x (multigrid): x, rho in, r out
+    k_mg_restrict fine r in, coarse rho out (1/8 of a value per fine point)
+    k_mg_prolong_add  x += P e: x in and out, the coarse e in (1/8 per fine point)
     """
     n = short_name(name)
-    m = re.match(r"cps::(k_cheb4|k_first4|k_apply4|k_update4)<(.*)>$", n)
+    m = re.match(r"cps::(k_cheb4|k_first4|k_apply4|k_update4|k_resid4|k_mg_restrict|k_mg_prolong_add)<(.*)>$", n)
     if not m:
         return None
     kern, args = m.group(1), [a.strip() for a in m.group(2).split(",")]
@@ -108,6 +121,12 @@ def algorithmic_bytes(name):
         return None
     if kern == "k_cheb4":
         return (3 if args[1] == "true" else 4) * t
+    if kern == "k_resid4":
+        return 3 * t
+    if kern == "k_mg_restrict":
+        return t + t / 8
+    if kern == "k_mg_prolong_add":
+        return 2 * t + t / 8
     if kern == "k_first4":
         return (5 if args[1] == "0" else 4) * t
     if kern == "k_update4":
@@ -120,18 +139,39 @@ def algorithmic_bytes(name):
     return t + 8 + to       # residual: x and b (FP64) in, r out
 
 
+def fine_grid_launches(db):
+    """Per solve kernel, its launches on the problem's grid: multigrid kernels also run on the
+    coarser grids, one launch grid per level, and the problem's grid is the one whose
+    launches take longest.  [(name, calls, avg us)]"""
+    con = sqlite3.connect(db)
+    groups = {}
+    for name, gx, gy, gz, dur in con.execute("select name, grid_x, grid_y, grid_z, duration from kernels"):
+        key = (name, gx * gy * gz)
+        c, d = groups.get(key, (0, 0.0))
+        groups[key] = (c + 1, d + dur)
+    con.close()
+    best = {}
+    for (name, size), (c, d) in groups.items():
+        if name not in best or d / c > best[name][2] / best[name][1]:
+            best[name] = (size, c, d)
+    rows = [(name, c, d / c / 1e3) for name, (size, c, d) in best.items()]
+    return sorted(rows, key=lambda r: -r[1] * r[2])
+
+
 def kernels_report(db, points, title, cmd):
     out = [f"# {title}", "", "Command (run from the repository root on an MI355X):", "", "```", cmd, "```", "",
-           f"Solve kernels from `rocprofv3 --kernel-trace --stats`, {points} interior points per launch; "
-           "algorithmic bytes count each operand once per point (tables, halos, bits and the irregular "
-           f"rows as overhead); GB/s = bytes per launch / average duration; peak {HBM_PEAK_GBS:.0f} GB/s.", "",
+           f"Solve kernels from `rocprofv3 --kernel-trace --stats`, launches on the problem's grid only "
+           f"({points} interior points per launch; a multigrid kernel's launches on coarser grids are left "
+           "out); algorithmic bytes count each operand once per point (tables, halos, bits and the "
+           f"irregular rows as overhead); GB/s = bytes per launch / average duration; peak "
+           f"{HBM_PEAK_GBS:.0f} GB/s.", "",
            "| kernel | calls | avg us | B / point | GB/s | of peak |", "|---|---:|---:|---:|---:|---:|"]
-    for n, c, t, a, p in kernel_stats(db):
+    for n, c, a in fine_grid_launches(db):
         b = algorithmic_bytes(n)
         if b is None:
             continue
         gbs = b * points / (a * 1e-6) / 1e9
-        out.append(f"| `{short_name(n)}` | {c} | {a:.2f} | {b} | {gbs:.0f} | {gbs / HBM_PEAK_GBS:.2f} |")
+        out.append(f"| `{short_name(n)}` | {c} | {a:.2f} | {b:g} | {gbs:.0f} | {gbs / HBM_PEAK_GBS:.2f} |")
     return "\n".join(out) + "\n"
 
 

@@ -7,9 +7,13 @@ from paper_1901_08269_amd import profiling
 
 
 def _pmc_db(path, rows):
+    """rows: (name, counter value, duration) or (name, counter value, duration, grid_x)."""
     con = sqlite3.connect(path)
-    con.execute("create table pmc_events (name text, counter_value real, duration real)")
-    con.executemany("insert into pmc_events values (?,?,?)", rows)
+    con.execute("create table pmc_events (name text, counter_value real, duration real, dispatch_id int)")
+    con.execute("create table kernels (dispatch_id int, grid_x int, grid_y int, grid_z int)")
+    for q, r in enumerate(rows):
+        con.execute("insert into pmc_events values (?,?,?,?)", (r[0], r[1], r[2], q))
+        con.execute("insert into kernels values (?,?,1,1)", (q, r[3] if len(r) > 3 else 256))
     con.commit()
     con.close()
     return str(path)
@@ -20,7 +24,9 @@ def test_traffic_report_scales_by_copy_calibration(tmp_path):
     cf = _pmc_db(tmp_path / "cf.db", [(profiling.COPY_KERNEL, 512.0, 10.0)] * 3)     # counter reads half
     cw = _pmc_db(tmp_path / "cw.db", [(profiling.COPY_KERNEL, 1024.0, 10.0)] * 3)    # counter exact
     k = "void cps::k_cheb<float, false>(cps::Geom, int)"
-    f = _pmc_db(tmp_path / "f.db", [(k, 100.0, 2000.0), (k, 300.0, 4000.0), ("other", 9.0, 1.0)])
+    # the shorter launches of another launch grid (a coarser multigrid level) are left out
+    f = _pmc_db(tmp_path / "f.db", [(k, 100.0, 2000.0), (k, 300.0, 4000.0), ("other", 9.0, 1.0),
+                                    (k, 7.0, 100.0, 512), (k, 5.0, 100.0, 512)])
     w = _pmc_db(tmp_path / "w.db", [(k, 50.0, 2000.0)] * 2)
     a = argparse.Namespace(fetch=f, write=w, copy_fetch=cf, copy_write=cw, copy_bytes=copy_bytes,
                            kernel="cps::k_cheb<float, false>", units=1000, unit_bytes=16.0,
@@ -65,17 +71,28 @@ def test_algorithmic_bytes_per_kernel():
     assert ab("void cps::k_apply4<double, float, 3>(cps::Geom)") == 20
     assert ab("void cps::k_apply4<double, double, 0>(cps::Geom)") == 16
     assert ab("void cps::k_finalize<0>(double const*, int, cps::DevState*)") is None
+    assert ab("void cps::k_resid4<float>(cps::Geom)") == 12
+    assert ab("void cps::(anonymous namespace)::k_mg_prolong_add<double>(int, int)") == 17
 
 
 def test_kernels_report(tmp_path):
+    """Only each kernel's launches on the problem's grid (its longest launches) are reported."""
     db = tmp_path / "s.db"
     con = sqlite3.connect(db)
-    con.execute("create table top_kernels (name text, total_calls int, total_duration real, average real, percentage real)")
-    con.execute("insert into top_kernels values ('void cps::k_cheb4<float, false>(cps::Geom, int)', 10, 400.0, 40.0, 90.0)")
-    con.execute("insert into top_kernels values ('void cps::k_fill<float>(unsigned long, float*, float)', 2, 40.0, 20.0, 10.0)")
+    con.execute("create table kernels (name text, grid_x int, grid_y int, grid_z int, duration real)")
+    sweep = "void cps::k_cheb4<float, false>(cps::Geom, int)"
+    for _ in range(10):
+        con.execute("insert into kernels values (?, 79872, 4, 1, 40000.0)", (sweep,))
+    for _ in range(7):                                   # a coarse level: shorter launches, left out
+        con.execute("insert into kernels values (?, 135168, 4, 1, 12000.0)", (sweep,))
+    con.execute("insert into kernels values ('void cps::(anonymous namespace)::k_mg_restrict<float>(int)', "
+                "64, 128, 128, 20000.0)")
+    con.execute("insert into kernels values ('void cps::k_fill<float>(unsigned long, float*, float)', 256, 1, 1, 2e4)")
     con.commit()
     con.close()
     rep = profiling.kernels_report(str(db), 1000000, "T", "cmd")
     # 16 B x 1e6 points in 40 us = 400 GB/s = 0.05 of 8 TB/s
     assert "| `cps::k_cheb4<float, false>` | 10 | 40.00 | 16 | 400 | 0.05 |" in rep
+    # restriction: 4.5 B per fine point in 20 us = 225 GB/s
+    assert "| `cps::k_mg_restrict<float>` | 1 | 20.00 | 4.5 | 225 | 0.03 |" in rep
     assert "k_fill" not in rep
