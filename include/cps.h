@@ -82,7 +82,7 @@ typedef struct cps_options {
     int32_t precond;         /* CPS_PRECOND_CHEBYSHEV (default) or CPS_PRECOND_MULTIGRID */
     int32_t mg_levels;       /* most levels, this grid included, 1..16 (default 16) */
     int32_t mg_nu;           /* smoothing steps before and after, 1..64 (default 4) */
-    int32_t mg_coarse_steps; /* steps on the coarsest grid, 1..64 (default 24) */
+    int32_t mg_coarse_steps; /* steps on the coarsest grid, 1..64 (default 16) */
     double mg_smooth_lo;     /* lower end of the smoother's interval, in (0, lam_hi) (default 0.5) */
 } cps_options;
 
@@ -112,7 +112,7 @@ typedef struct cps_stats {
 /* Fill `o` with the defaults: CPS_FP64, 24 inner iterations, max_iters 20000,
  * max_refine 40, max_restarts 5, host pointers, inner_tol 1e-4, the default Chebyshev
  * interval, null stream, no kernel timing, the Chebyshev preconditioner (multigrid
- * settings up to 16 levels, 4 + 4 smoothing steps on [0.5, lam_hi], 24 coarsest-grid steps). */
+ * settings up to 16 levels, 4 + 4 smoothing steps on [0.5, lam_hi], 16 coarsest-grid steps). */
 void cps_default_options(cps_options *o);
 
 /* Build the discrete problem (Secs. 2-3): classify nodes from the sign of phi (Sec. 2,

@@ -82,7 +82,7 @@ def lambda_1(shape):
 
 
 class Multigrid:
-    def __init__(self, x, y, z, phi, levels=16, nu=4, smooth_lo=0.5, coarse_steps=24, min_points=9,
+    def __init__(self, x, y, z, phi, levels=16, nu=4, smooth_lo=0.5, coarse_steps=16, min_points=9,
                  coarse_interior=4096):
         self.nu, self.smooth_lo, self.coarse_steps = nu, smooth_lo, coarse_steps
         self.lv = []

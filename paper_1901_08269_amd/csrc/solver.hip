@@ -1026,7 +1026,7 @@ void cps_default_options(cps_options *o)
     o->precond = CPS_PRECOND_CHEBYSHEV;
     o->mg_levels = MG_MAX_LEVELS;
     o->mg_nu = 4;
-    o->mg_coarse_steps = 24;
+    o->mg_coarse_steps = 16;
     o->mg_smooth_lo = 0.5;
 }
 
