@@ -417,7 +417,8 @@ def _subbox(x, body, margin):
     return lo, hi
 
 
-def test_bodies16_512_rows_vs_oracle():
+@pytest.mark.parametrize("precond", ["chebyshev", "multigrid"])
+def test_bodies16_512_rows_vs_oracle(precond):
     """512^3, 8 spheres + 8 rotated ellipsoids, Fourier f with 2445 modes, g = 0: the scale
     configuration, too large for an oracle solve.  The GPU's mixed solution to 1e-10 is
     checked against the oracle's own system, row by row: around two bodies the oracle builds
@@ -430,8 +431,8 @@ def test_bodies16_512_rows_vs_oracle():
     import torch
     x, bodies, phi, g, f = W.bodies16_fourier_torch(512)
     n = len(x)
-    print("[case] bodies16_fourier 512 mixed", flush=True)
-    S = cps.Solver(x, x, x, phi, g, f, precision="mixed")
+    print(f"[case] bodies16_fourier 512 mixed, {precond}", flush=True)
+    S = cps.Solver(x, x, x, phi, g, f, precision="mixed", precond=precond)
     u, st = S.solve(1e-10)
     assert st["rel_residual"] <= 1e-10 and st["rel_residual_jacobi"] <= 1e-10
     assert st["fallback_lines"] == 0

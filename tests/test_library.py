@@ -36,3 +36,24 @@ def test_struct_layouts_and_host_only_calls():
     # argument validation happens before any device call
     h = ctypes.c_void_p()
     assert lib.cps_setup(ctypes.byref(h), 2, 5, 5, None, None, None, None, None, None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(cps.LIB_PATH), reason="libcps.so not built")
+def test_multigrid_options_validated_before_device_calls():
+    """Out-of-range preconditioner settings are rejected (CPS_EINVAL) before any HIP call."""
+    import numpy as np
+    lib = cps.load_library()
+    n = 6
+    x = np.linspace(0.0, 1.0, n)
+    a = np.ones((n, n, n))
+    dp = lambda arr: arr.ctypes.data_as(ctypes.c_void_p)
+    bad = [("precond", 2), ("mg_levels", 0), ("mg_levels", 17), ("mg_nu", 0), ("mg_nu", 65),
+           ("mg_coarse_steps", 0), ("mg_smooth_lo", 0.0), ("mg_smooth_lo", 2.0)]
+    for name, val in bad:
+        o = cps.CpsOptions()
+        lib.cps_default_options(ctypes.byref(o))
+        o.precond = cps.CPS_PRECOND_MULTIGRID
+        setattr(o, name, val)
+        h = ctypes.c_void_p()
+        rc = lib.cps_setup(ctypes.byref(h), n, n, n, dp(x), dp(x), dp(x), dp(a), dp(a), dp(a), ctypes.byref(o))
+        assert rc == -1, (name, val, rc)
