@@ -827,11 +827,14 @@ void mg_axis_tables(const double *xf, int nf, const std::vector<int> &idx, std::
         for (int q = 0; q < 3; ++q) rw[3 * I + q] /= sum[I];
 }
 
+// Device copy of a small host table.  The copy is asynchronous, so its source is first moved
+// into `keep`, which the caller holds until the stream has been synchronised.
 template <typename D>
-D *upload(cps_solver *s, const std::vector<D> &h)
+D *upload(cps_solver *s, const std::vector<D> &h, std::vector<std::vector<char>> &keep)
 {
+    keep.emplace_back(reinterpret_cast<const char *>(h.data()), reinterpret_cast<const char *>(h.data() + h.size()));
     D *d = dalloc<D>(s, h.size());
-    ck(hipMemcpyAsync(d, h.data(), h.size() * sizeof(D), hipMemcpyHostToDevice, s->stream));
+    ck(hipMemcpyAsync(d, keep.back().data(), h.size() * sizeof(D), hipMemcpyHostToDevice, s->stream));
     return d;
 }
 
@@ -861,6 +864,11 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
     std::vector<double> hx = hx0;
     const double *phi_f = s->phi;
     std::vector<void *> temps;
+    std::vector<std::vector<char>> keep;   // sources of the asynchronous table uploads
+    struct SyncFirst {                     // destroyed before `keep`, also when a step throws
+        hipStream_t st;
+        ~SyncFirst() { (void)hipStreamSynchronize(st); }
+    } sync_first{s->stream};
     while ((int)s->mg.size() < s->opt.mg_levels) {
         MgLevel &F = s->mg.back();
         if (std::min({F.n[0], F.n[1], F.n[2]}) < 2 * MG_MIN_POINTS - 1) break;
@@ -882,9 +890,9 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
             mg_axis_tables(hx.data() + off, F.n[d], idx[d], pa, pw, rw);
             pw.resize(pw.size() + 4, 0.0);   // padding: 4-vector loads of the weights
             std::vector<float> pw32(pw.begin(), pw.end()), rw32(rw.begin(), rw.end());
-            const int *dpa = upload(s, pa);
-            F.t64.ax[d] = MgAxis<double>{dpa, upload(s, pw), upload(s, rw)};
-            F.t32.ax[d] = MgAxis<float>{dpa, upload(s, pw32), upload(s, rw32)};
+            const int *dpa = upload(s, pa, keep);
+            F.t64.ax[d] = MgAxis<double>{dpa, upload(s, pw, keep), upload(s, rw, keep)};
+            F.t32.ax[d] = MgAxis<float>{dpa, upload(s, pw32, keep), upload(s, rw32, keep)};
             F.t64.nf[d] = F.t32.nf[d] = F.n[d];
             F.t64.nc[d] = F.t32.nc[d] = C.n[d];
             off += F.n[d];
@@ -893,8 +901,8 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
         C.nmax = std::max({cx, cy, cz});
         C.nn = (size_t)cx * cy * cz;
         C.g = make_geom(cx, cy, cz, true);
-        C.xyz = upload(s, hc);
-        const int *dg = upload(s, gidx);
+        C.xyz = upload(s, hc, keep);
+        const int *dg = upload(s, gidx, keep);
         double *phic = dalloc<double>(s, C.nn);
         temps.push_back(phic);
         launch_gather3(s->stream, cx, cy, cz, F.n[0], F.n[1], dg, dg + cx, dg + cx + cy, phi_f, phic);
@@ -956,8 +964,8 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
         std::vector<double> cc(s->mg_cc1);
         cc.insert(cc.end(), s->mg_cc2.begin(), s->mg_cc2.end());
         std::vector<float> cc32(cc.begin(), cc.end());
-        s->mg_ccd64 = upload(s, cc);
-        s->mg_ccd32 = upload(s, cc32);
+        s->mg_ccd64 = upload(s, cc, keep);
+        s->mg_ccd32 = upload(s, cc32, keep);
         sync(s);
     }
 }
