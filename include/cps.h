@@ -6,6 +6,9 @@
  *     Laplacian u = f  in the fluid region (level set phi > 0),
  *     u = g            on the box walls and on the interface Gamma (phi = 0),
  *     u = 0            inside the bodies (phi <= 0),
+ * The fluid region may also be the inside of a closed interface (the interior problem of
+ * Sec. 4, Problem 4): wall nodes may then lie in phi <= 0, provided no fluid node is among
+ * their neighbours (no row of the scheme reaches them; they keep the value g).
  * on a tensor-product nonuniform grid (Sec. 2), with the fourth-order compact 27-point
  * scheme (Sec. 2.1, Eqs. A27/As_qs/q), modified at irregular points next to Gamma
  * (Secs. 2.2-2.3, Eqs. A27_mod/bc/cor and their multiple-intersection forms), and solves
@@ -39,7 +42,8 @@ extern "C" {
 
 #define CPS_OK 0
 #define CPS_EINVAL (-1)      /* bad sizes, non-increasing coordinates, NaN/Inf input, bad option */
-#define CPS_EGEOM (-2)       /* a body touches a wall node (phi <= 0 on the boundary) */
+#define CPS_EGEOM (-2)       /* a wall node inside a body (phi <= 0) has a fluid neighbour, or a
+                              * modified line is singular */
 #define CPS_ENOMEM (-3)      /* device or host allocation failed */
 #define CPS_EDEVICE (-4)     /* a HIP runtime call failed or no device is present */
 #define CPS_EBREAKDOWN (-5)  /* BiCGSTAB broke down more often than max_restarts allows */

@@ -478,7 +478,8 @@ static void k_row(orc_prob *P, int i, int j, int k, double coef[7])
     }
 }
 
-/* returns NULL and *err < 0 on invalid input: -1 bad sizes/coords, -2 body touches wall.
+/* returns NULL and *err < 0 on invalid input: -1 bad sizes/coords, -2 a fluid node next to a
+ * wall node that lies in a body.
  * k_only: classification and the K rows only (no rows of B, no right-hand side), for the
  * coarse levels of the multigrid preconditioner. */
 static void *create(int nx, int ny, int nz, const double *x, const double *y, const double *z,
@@ -519,7 +520,20 @@ static void *create(int nx, int ny, int nz, const double *x, const double *y, co
                 i64 e = nid(P, i, j, k);
                 int wall = (i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1);
                 if (wall) {
-                    if (phi[e] <= 0.0) { *err = -2; orc_destroy(P); return NULL; }
+                    /* A wall node may lie in a body (an interior problem: the fluid region is
+                     * inside Gamma and the walls outside it) as long as no fluid node is among
+                     * its neighbours, so that no row of the scheme reaches it.  On a coarse
+                     * level of the multigrid hierarchy (k_only) this is not checked: there a
+                     * wall node is a zero Dirichlet node of the correction equation. */
+                    if (phi[e] <= 0.0 && !k_only) {
+                        for (int r = -1; r <= 1; ++r)
+                            for (int q = -1; q <= 1; ++q)
+                                for (int p = -1; p <= 1; ++p) {
+                                    int a = i + p, b = j + q, c = k + r;
+                                    if (a < 1 || b < 1 || c < 1 || a > nx - 2 || b > ny - 2 || c > nz - 2) continue;
+                                    if (phi[nid(P, a, b, c)] > 0.0) { *err = -2; orc_destroy(P); return NULL; }
+                                }
+                    }
                     P->type[e] = T_BOUND;
                 } else {
                     P->type[e] = phi[e] <= 0.0 ? T_SOLID : T_REG;

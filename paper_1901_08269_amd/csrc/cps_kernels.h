@@ -90,7 +90,8 @@ struct SetupOut {
 
 // 1D tables (FP64) from coordinates; t holds the three coordinate arrays
 void launch_coef(hipStream_t s, int n, const double *t, double *coef);
-// classify nodes; flags: bit0 invalid input (NaN/Inf), bit1 body touches a wall
+// classify nodes; flags: bit0 invalid input (NaN/Inf), bit1 a wall node inside a body has a
+// fluid neighbour
 void launch_classify(hipStream_t s, int nx, int ny, int nz, const double *phi, const double *g, const double *f,
                      int8_t *type, int *flags);
 void launch_mark_irregular(hipStream_t s, int nx, int ny, int nz, int8_t *type);

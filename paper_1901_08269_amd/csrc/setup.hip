@@ -76,7 +76,19 @@ __global__ void __launch_bounds__(256) k_classify(int nx, int ny, int nz, const 
     if (!isfinite(p) || !isfinite(g[e]) || !isfinite(f[e])) atomicOr(flags, 1);
     const bool wall = i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1;
     if (wall) {
-        if (!(p > 0.0)) atomicOr(flags, 2);
+        // A wall node may lie in a body (an interior problem) as long as no fluid node is
+        // among its interior neighbours, so that no row of the scheme reaches it.
+        if (!(p > 0.0)) {
+            bool fluid_nb = false;
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int a = i + dx, b = j + dy, c = k + dz;
+                        if (a < 1 || b < 1 || c < 1 || a > nx - 2 || b > ny - 2 || c > nz - 2) continue;
+                        if (phi[(size_t)a + (size_t)nx * b + (size_t)nx * ny * c] > 0.0) fluid_nb = true;
+                    }
+            if (fluid_nb) atomicOr(flags, 2);
+        }
         type[e] = 0;
     } else {
         type[e] = (p > 0.0) ? 1 : 3;

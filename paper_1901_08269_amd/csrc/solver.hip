@@ -922,7 +922,9 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
         sync(s);
         int flags;
         std::memcpy(&flags, s->hscalar, sizeof(int));
-        if (flags) throw CPS_EGEOM;
+        // bit 1 (a wall node in a body next to a fluid node) is not an error on a coarse
+        // level: there a wall node is a zero Dirichlet node of the correction equation
+        if (flags & 1) throw CPS_EINVAL;
         launch_mark_irregular(s->stream, cx, cy, cz, C.type);
         int *lst = dalloc<int>(s, C.nn);
         temps.push_back(lst);
@@ -1043,7 +1045,7 @@ const char *cps_strerror(int code)
     switch (code) {
     case CPS_OK: return "ok";
     case CPS_EINVAL: return "invalid argument (sizes, coordinates, NaN/Inf input or options)";
-    case CPS_EGEOM: return "invalid geometry (a body touches the wall, or a singular modified line)";
+    case CPS_EGEOM: return "invalid geometry (a fluid node next to a wall node inside a body, or a singular modified line)";
     case CPS_ENOMEM: return "out of memory";
     case CPS_EDEVICE: return "HIP runtime error or no GPU";
     case CPS_EBREAKDOWN: return "BiCGSTAB breakdown beyond max_restarts";

@@ -48,6 +48,17 @@ def tanh_grid(n: int, beta: float) -> np.ndarray:
     return x
 
 
+def sinh_grid(n: int, beta: float, L: float, H: float, y0: float = 0.0) -> np.ndarray:
+    """Interior clustering (Eqs. p2_y, p4_y, p4_z): n points on [y0, y0 + H], densest at
+    y0 + L, y(eta) = y0 + L (1 + sinh(beta (eta - s)) / sinh(beta s)) with s of Eq. p2_s,
+    which makes y(1) = y0 + H.  Both ends are set exactly."""
+    s = math.log((1.0 + (math.exp(beta) - 1.0) * (L / H)) / (1.0 + (math.exp(-beta) - 1.0) * (L / H))) / (2.0 * beta)
+    eta = np.arange(n, dtype=np.float64) / (n - 1)
+    y = y0 + L * (1.0 + np.sinh(beta * (eta - s)) / math.sinh(beta * s))
+    y[0], y[-1] = y0, y0 + H
+    return y
+
+
 def random_grid(n: int, rng: np.random.Generator, jitter: float = 0.35) -> np.ndarray:
     """A strictly increasing irregular grid on [0,1] (spacings vary by up to +-jitter)."""
     h = 1.0 + jitter * (2.0 * rng.random(n - 1) - 1.0)
@@ -381,10 +392,33 @@ def sphere_sin(N: int, beta: float = 0.0, r: float = 0.2, c=(0.5, 0.5, 0.5)) -> 
         {"N": N, "beta": beta, "r": r})
 
 
+def interior_exp(n: int, sigma: float = -10.0, semi=(0.4, 0.1, 0.1)) -> Workload:
+    """An interior problem in the setting of the paper's Problem 4 (Eq. p4): the fluid region
+    is the inside of a closed body and the box walls lie outside it.  Grid of Eqs. p4_y /
+    p4_z: x uniform on [0, 1], y on [0, 0.5] clustered at 0.14 (beta = 2), z on [0.35, 0.65]
+    clustered at 0.5 (beta = 4), n points each.  The paper's stenosed pipe is given only by
+    a figure; an ellipsoid around the clustering line (centre (0.5, 0.14, 0.5), semi-axes
+    `semi`) stands in for it.  u = exp(sigma r), r = |x - (0.5, 0.5, 0.5)|^2, f =
+    2 sigma exp(sigma r)(3 + 2 sigma r), g = u."""
+    x = uniform_grid(n)
+    y = sinh_grid(n, 2.0, 0.14, 0.5)
+    z = sinh_grid(n, 4.0, 0.15, 0.3, 0.35)
+    body = Ellipsoid((0.5, 0.14, 0.5), tuple(semi), np.eye(3))
+    Z, Y, X = mesh(x, y, z)
+    r = (X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2
+    shape = (len(z), len(y), len(x))
+    u = np.broadcast_to(np.exp(sigma * r), shape).astype(np.float64).copy()
+    f = np.broadcast_to(2.0 * sigma * np.exp(sigma * r) * (3.0 + 2.0 * sigma * r), shape).astype(np.float64).copy()
+    phi = -union_level([body], x, y, z)            # positive inside the body
+    return Workload(f"interior_exp_{n}", x, y, z, phi, u.copy(), f, u, [body],
+                    {"n": n, "sigma": sigma, "semi": tuple(semi)})
+
+
 WORKLOADS = {
     "uniform_sine": uniform_sine,
     "sphere_exp": sphere_exp,
     "spheres8": spheres8,
     "star_fourier": star_fourier,
     "bodies16_fourier": bodies16_fourier,
+    "interior_exp": interior_exp,
 }

@@ -59,10 +59,16 @@ def _case(name):
         x, y, z = W.tanh_grid(300, 1.1), W.uniform_grid(14), W.uniform_grid(11)
         w = W.polynomial_case(0, [W.Sphere((0.78, 0.5, 0.47), 0.22)], rng_seed=11, grids=(x, y, z))
         return w.x, w.y, w.z, w.phi, w.g, w.f, w.u_exact
+    if name == "interior":
+        # the fluid region inside an ellipsoid, walls outside it (Problem 4's setting), on the
+        # sinh grids of Eqs. p4_y / p4_z
+        w = W.interior_exp(42)
+        return w.x, w.y, w.z, w.phi, w.g, w.f, w.u_exact
     raise KeyError(name)
 
 
-CASES = ["nobody_ragged", "sphere_stretched", "two_bodies_aniso", "plates_fsf_sfs", "near_coincident", "wide_rows"]
+CASES = ["nobody_ragged", "sphere_stretched", "two_bodies_aniso", "plates_fsf_sfs", "near_coincident", "wide_rows",
+         "interior"]
 
 
 def _both(name, **kw):
