@@ -513,7 +513,7 @@ struct PtBuf {
 
 // one fluid run [plo, phi_] (positions -1..1 along d of the window centred at `wc` = row
 // offset) of a window meeting the body
-__device__ __attribute__((noinline)) void run_operator(const Ctx &C, WinList &R, size_t rownode, const int rowidx[3], int d, const int wc[3],
+__device__ __forceinline__ void run_operator(const Ctx &C, WinList &R, size_t rownode, const int rowidx[3], int d, const int wc[3],
                              int plo, int phi_, const bool sol[3], int nruns, const double Ld[3], double W, int &fb,
                              double &minhb, int *bad, PtBuf P)
 {
