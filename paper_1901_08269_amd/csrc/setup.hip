@@ -626,15 +626,46 @@ __device__ void sw_krow(const Ctx &C, size_t rownode, const int idx[3], double *
     for (int q = 0; q < 7; ++q) out[q] = kr[q];
 }
 
-// K rows only (a coarse level of the multigrid preconditioner): one thread per irregular node.
-__global__ void k_krows(Ctx C, int nirr, const int *__restrict__ nodes, double *__restrict__ k7)
+// K rows only (a coarse level of the multigrid preconditioner), the arithmetic of sw_krow
+// spread over eight lanes per row: lane 2d + s (s = 0: -d side, 1: +d side; lanes 6, 7 idle)
+// finds its arm length (to the neighbour, or to the interface when the neighbour is solid)
+// and its off-diagonal entry; lane 0 sums the three diagonal terms in the order d = 0, 1, 2.
+__global__ void __launch_bounds__(256) k_krows(Ctx C, int nirr, const int *__restrict__ nodes,
+                                               double *__restrict__ k7)
 {
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= nirr) return;
-    const size_t rownode = (size_t)nodes[row];
-    const int nx = C.n[0], ny = C.n[1];
-    const int idx[3] = {(int)(rownode % nx), (int)((rownode / nx) % ny), (int)(rownode / ((size_t)nx * ny))};
-    sw_krow(C, rownode, idx, k7 + 7 * (size_t)row);
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int row = t >> 3, lane = t & 7;
+    const bool live = row < nirr && lane < 6;
+    const int d = live ? lane >> 1 : 0, side = lane & 1;
+    double h = 1.0;
+    int8_t tn = 0;
+    if (live) {
+        const size_t rownode = (size_t)nodes[row];
+        const int nx = C.n[0], ny = C.n[1];
+        const int idx[3] = {(int)(rownode % nx), (int)((rownode / nx) % ny), (int)(rownode / ((size_t)nx * ny))};
+        const int id = d == 0 ? idx[0] : (d == 1 ? idx[1] : idx[2]);
+        const size_t sd = d == 0 ? C.stride[0] : (d == 1 ? C.stride[1] : C.stride[2]);
+        const double *td = d == 0 ? C.t[0] : (d == 1 ? C.t[1] : C.t[2]);
+        const size_t line0 = rownode - (size_t)id * sd;
+        const size_t nb = side ? rownode + sd : rownode - sd;
+        tn = C.type[nb];
+        const int in = side ? id + 1 : id - 1;
+        h = side ? td[id + 1] - td[id] : td[id] - td[id - 1];
+        if (tn == 3) {
+            double gv, fr;
+            const double tb = ibi_on_segment(C, d, line0, id, in, &gv, &fr);
+            h = side ? tb - td[id] : td[id] - tb;
+        }
+    }
+    const double other = __shfl_xor(h, 1, 8);          // the opposite arm of direction d
+    const double hb = side ? other : h, hf = side ? h : other;
+    const double diag = -2.0 / (hb * hf);
+    const double off = (tn == 1 || tn == 2) ? (side ? 2.0 / (hf * (hf + hb)) : 2.0 / (hb * (hf + hb))) : 0.0;
+    const double d1 = __shfl(diag, 2, 8), d2 = __shfl(diag, 4, 8);
+    if (!live) return;
+    double *out = k7 + 7 * (size_t)row;
+    out[1 + lane] = off;
+    if (lane == 0) out[0] = ((0.0 + diag) + d1) + d2;
 }
 
 // gather of the coarse level set: coarse node (I, J, K) <- fine node (ix[I], iy[J], iz[K])
@@ -824,7 +855,7 @@ void launch_krows(hipStream_t s, int nx, int ny, int nz, const double *x, const 
     C.t[0] = x; C.t[1] = y; C.t[2] = z;
     for (int d = 0; d < 3; ++d) C.coef[d] = nullptr;
     C.phi = phi; C.g = phi; C.f = nullptr; C.type = type;   // g at an IBI is not used for K
-    k_krows<<<(nirr + 127) / 128, 128, 0, s>>>(C, nirr, nodes, k7);
+    k_krows<<<(unsigned)((8 * (size_t)nirr + 255) / 256), 256, 0, s>>>(C, nirr, nodes, k7);
 }
 
 void launch_gather3(hipStream_t s, int ncx, int ncy, int ncz, int nfx, int nfy, const int *ix, const int *iy,

@@ -914,17 +914,11 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
         launch_coef(s->stream, cz, C.xyz + cx + cy, C.coef64 + (size_t)16 * C.nmax);
         launch_to_float(s->stream, (size_t)3 * 8 * C.nmax, C.coef64, C.coef32);
         // node types from the coarse level set (it is also passed as g and f, which the
-        // classification only checks for finiteness)
+        // classification only checks for finiteness).  Its flags are not read: the coarse
+        // level set is a subset of the validated one, and a wall node in a body next to a
+        // fluid node is no error on a coarse level (a zero Dirichlet node of the correction)
         C.type = dalloc<int8_t>(s, C.nn);
-        ck(hipMemsetAsync(s->dflag, 0, sizeof(int), s->stream));
         launch_classify(s->stream, cx, cy, cz, phic, phic, phic, C.type, s->dflag);
-        ck(hipMemcpyAsync(s->hscalar, s->dflag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-        sync(s);
-        int flags;
-        std::memcpy(&flags, s->hscalar, sizeof(int));
-        // bit 1 (a wall node in a body next to a fluid node) is not an error on a coarse
-        // level: there a wall node is a zero Dirichlet node of the correction equation
-        if (flags & 1) throw CPS_EINVAL;
         launch_mark_irregular(s->stream, cx, cy, cz, C.type);
         int *lst = dalloc<int>(s, C.nn);
         temps.push_back(lst);
