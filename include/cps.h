@@ -15,7 +15,8 @@
  * the resulting system B u = q + b (Sec. 3, Eq. Bu=q, split B = A-bar + C of Eq. Bdec)
  * by right-preconditioned BiCGSTAB (Sec. 3.2, Alg. 1) whose preconditioner is the
  * second-order 7-point operator K with Shortley-Weller rows at Gamma (Sec. 3.3, Eqs.
- * A7/A7_mod), solved approximately by a fixed number of inner iterations.
+ * A7/A7_mod), solved approximately by a fixed linear inner solver: one multigrid V-cycle
+ * (default) or a fixed number of Chebyshev-Jacobi steps (cps_options.precond).
  *
  * Conventions shared by every entry point
  *   - Grid: nx, ny, nz points per direction INCLUDING both wall planes; coordinates
@@ -83,7 +84,7 @@ typedef struct cps_options {
      * divided by its sum.  Smoother: mg_nu Chebyshev-Jacobi steps before and after each
      * coarse correction on [mg_smooth_lo, lam_hi]; the coarsest grid takes mg_coarse_steps
      * steps on [lambda_1, lam_hi] of that grid.  The cycle is a fixed linear map of rho. */
-    int32_t precond;         /* CPS_PRECOND_CHEBYSHEV (default) or CPS_PRECOND_MULTIGRID */
+    int32_t precond;         /* CPS_PRECOND_MULTIGRID (default) or CPS_PRECOND_CHEBYSHEV */
     int32_t mg_levels;       /* most levels, this grid included, 1..16 (default 16) */
     int32_t mg_nu;           /* smoothing steps before and after, 1..64 (default 4) */
     int32_t mg_coarse_steps; /* steps on the coarsest grid, 1..64 (default 16) */
@@ -115,8 +116,8 @@ typedef struct cps_stats {
 
 /* Fill `o` with the defaults: CPS_FP64, 24 inner iterations, max_iters 20000,
  * max_refine 40, max_restarts 5, host pointers, inner_tol 1e-4, the default Chebyshev
- * interval, null stream, no kernel timing, the Chebyshev preconditioner (multigrid
- * settings up to 16 levels, 4 + 4 smoothing steps on [0.5, lam_hi], 16 coarsest-grid steps). */
+ * interval, null stream, no kernel timing, the multigrid preconditioner (up to 16 levels,
+ * 4 + 4 smoothing steps on [0.5, lam_hi], 16 coarsest-grid steps). */
 void cps_default_options(cps_options *o);
 
 /* Build the discrete problem (Secs. 2-3): classify nodes from the sign of phi (Sec. 2,

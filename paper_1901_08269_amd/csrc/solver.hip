@@ -1027,7 +1027,7 @@ void cps_default_options(cps_options *o)
     o->lam_lo = 0.0;
     o->lam_hi = DEFAULT_LAM_HI;
     o->stream = nullptr;
-    o->precond = CPS_PRECOND_CHEBYSHEV;
+    o->precond = CPS_PRECOND_MULTIGRID;
     o->mg_levels = MG_MAX_LEVELS;
     o->mg_nu = 4;
     o->mg_coarse_steps = 16;

@@ -98,7 +98,7 @@ def test_one_level_is_the_chebyshev_iteration():
     w = _case("sphere_stretched")
     lam1 = mg.lambda_1(w.phi.shape)
     Sm = cps.Solver.from_workload(w, precond="multigrid", mg_levels=1, mg_coarse_steps=12)
-    Sc = cps.Solver.from_workload(w, inner_iters=12, lam_lo=lam1)
+    Sc = cps.Solver.from_workload(w, inner_iters=12, lam_lo=lam1, precond="chebyshev")
     P = oracle.Problem.k_only(w.x, w.y, w.z, w.phi)
     rho = _random_rho(w.phi.shape, P.types(), 3)
     a, b = _np(Sm.precond(rho, "fp64")), _np(Sc.precond(rho, "fp64"))
@@ -114,7 +114,7 @@ def test_solve_with_multigrid_matches_oracle(name, precision):
     fl = (t == 1) | (t == 2)
     S = cps.Solver.from_workload(w, precision=precision, precond="multigrid")
     u, st = S.solve(1e-11)
-    Sc = cps.Solver.from_workload(w, precision=precision)
+    Sc = cps.Solver.from_workload(w, precision=precision, precond="chebyshev")
     _, stc = Sc.solve(1e-11)
     print(f"iterations: multigrid {st['iters']}, chebyshev {stc['iters']}")
     assert st["rel_residual"] <= 1e-11 and st["rel_residual_jacobi"] <= 1e-11

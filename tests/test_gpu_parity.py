@@ -72,9 +72,12 @@ CASES = ["nobody_ragged", "sphere_stretched", "two_bodies_aniso", "plates_fsf_sf
 
 
 def _both(name, **kw):
+    """The oracle's problem and the library's, the latter with the oracle's (Chebyshev)
+    inner solver unless `precond` says otherwise."""
     x, y, z, phi, g, f, ue = _case(name)
     print(f"[case] {name} shape {phi.shape}", flush=True)
     P = oracle.Problem(x, y, z, phi, g, f)
+    kw.setdefault("precond", "chebyshev")
     S = cps.Solver(x, y, z, phi, g, f, **kw)
     return P, S, ue
 
@@ -179,7 +182,7 @@ def test_precond_fp64_and_fp32(name):
     rho = _random_field(P, 12)
     # default interval policy on both sides (lo = hi / (4 m^2)), and one explicit interval
     for m, lo in ((1, None), (8, 0.03), (24, None)):
-        S2 = cps.Solver(*_case(name)[:6], inner_iters=m, lam_lo=lo)
+        S2 = cps.Solver(*_case(name)[:6], inner_iters=m, lam_lo=lo, precond="chebyshev")
         ref = P.precond(rho, iters=m, lo=lo)
         scale = np.max(np.abs(ref))
         got = _np(S2.precond(rho, "fp64"))
