@@ -53,8 +53,7 @@ void launch_scale(hipStream_t s, size_t n, double *x, double alpha);
 // multigrid.hip: 1D transfer tables of one axis between a level and the next coarser one
 template <typename T>
 struct MgAxis {
-    const int *pa;   // fine index -> left coarse index (prolongation)
-    const T *pw;     // fine index -> weight of coarse node pa + 1
+    const T *pw;     // fine index i -> weight of coarse node min(i / 2, nc - 2) + 1 (prolongation)
     const T *rw;     // interior coarse index I -> weights rw[3I + q] of fine points 2I - 1 + q
                      // (restriction), divided by the row sum
 };
@@ -63,9 +62,21 @@ struct MgTransfer {
     int nf[3], nc[3];
     MgAxis<T> ax[3];
 };
-// rc = R r at the unknown coarse nodes (type_c), 0 at every other coarse node
+// The coarse level's first Chebyshev step from zero, fused with the restriction: x1 = c2 rc /
+// diag K at its unknown nodes (cf: the level's tables; irr_map: irregular row of each
+// irregular node, k7: their K rows).  x1 = null: no first step.
 template <typename T>
-void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_c, const T *r, T *rc);
+struct MgFirst {
+    T *x1;
+    T c2;
+    Coef<T> cf;
+    const int *irr_map;
+    const T *k7;
+};
+// rc = R r at the unknown coarse interior nodes (type_c), 0 at the other interior nodes
+template <typename T>
+void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_c, const T *r, T *rc,
+                        const MgFirst<T> &first);
 // The coarsest level's `steps` Chebyshev steps (coefficients c1, c2) from 0 in one workgroup
 // of MG_LDS_THREADS threads; the level has at most MG_LDS_NODES interior nodes.  irr_map:
 // irregular row of each irregular node.  Writes out at the unknown nodes.

@@ -9,8 +9,8 @@
 // Both act on unknown nodes only: every other node holds 0 on every level.
 //
 // 1D tables per axis (built on the host from the coordinates):
-//   prolongation  for each fine index i: the left coarse index a[i] = min(i / 2, nc - 2) and
-//                 the weight w[i] of coarse node a[i] + 1 (fine value = (1 - w) e[a] +
+//   prolongation  for each fine index i, whose left coarse index is a = min(i / 2, nc - 2):
+//                 the weight w[i] of coarse node a + 1 (fine value = (1 - w) e[a] +
 //                 w e[a + 1]); the weights carry 4 zeros of padding
 //   restriction   for each interior coarse index I (fine point 2I): the weights rw[3I + q]
 //                 of fine points 2I - 1 + q, q = 0 .. 2, already divided by the row sum
@@ -41,10 +41,13 @@ struct MgVec4<double> {
 // I0 = 1 + 128 blockIdx.x + 2 l and I0 + 1 of row J = 1 + 4 blockIdx.y + wavefront, plane
 // K = 1 + blockIdx.z; it reads fine nodes 2 I0 - 1 .. 2 I0 + 3 of each of the nine fine
 // rows as a 4-vector and one more value.  Every load is issued whatever the node types.
+// With a first step F (F.x1 non-null) it also writes the coarse level's first Chebyshev
+// step from zero, x1 = c2 rho / diag K, at its unknown nodes (the diagonal from the 1D
+// tables, or the stored row of an irregular node).
 template <typename T>
 __global__ void __launch_bounds__(256) k_mg_restrict(int ncx, int ncy, int nfx, int nfy, MgAxis<T> ax, MgAxis<T> ay,
                                                      MgAxis<T> az, const int8_t *__restrict__ type_c,
-                                                     const T *__restrict__ r, T *__restrict__ rc)
+                                                     const T *__restrict__ r, T *__restrict__ rc, MgFirst<T> F)
 {
     using V = typename MgVec4<T>::type;
     const int I0 = 1 + (int)(blockIdx.x * 128 + 2 * threadIdx.x), J = 1 + (int)(blockIdx.y * 4 + threadIdx.y);
@@ -80,6 +83,17 @@ __global__ void __launch_bounds__(256) k_mg_restrict(int ncx, int ncy, int nfx, 
     }
     rc[ec] = unk0 ? acc0 : T(0);
     if (two) rc[ec + 1] = unk1 ? acc1 : T(0);
+    if (F.x1) {
+        const T dyz = F.cf.c[1][8 * J + 6] + F.cf.c[2][8 * K + 6];
+        if (unk0) {
+            const T dg = type_c[ec] == 2 ? F.k7[7 * (size_t)F.irr_map[ec]] : F.cf.c[0][8 * I0 + 6] + dyz;
+            F.x1[ec] = F.c2 * acc0 / dg;
+        }
+        if (unk1) {
+            const T dg = type_c[ec + 1] == 2 ? F.k7[7 * (size_t)F.irr_map[ec + 1]] : F.cf.c[0][8 * (I0 + 1) + 6] + dyz;
+            F.x1[ec + 1] = F.c2 * acc1 / dg;
+        }
+    }
 }
 
 // x(i, j, k) += (P e)(i, j, k) at the unknown fine nodes.  Block 64 x 4: lane l of
@@ -256,11 +270,12 @@ __global__ void k_mg_irr_map(int nirr, const int *__restrict__ nodes, int *__res
 }  // namespace
 
 template <typename T>
-void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_c, const T *r, T *rc)
+void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_c, const T *r, T *rc,
+                        const MgFirst<T> &first)
 {
     dim3 grid((unsigned)((t.nc[0] - 2 + 127) / 128), (unsigned)((t.nc[1] - 2 + 3) / 4), (unsigned)(t.nc[2] - 2));
     k_mg_restrict<T><<<grid, dim3(64, 4), 0, s>>>(t.nc[0], t.nc[1], t.nf[0], t.nf[1], t.ax[0], t.ax[1], t.ax[2], type_c,
-                                                  r, rc);
+                                                  r, rc, first);
 }
 
 template <typename T>
@@ -291,8 +306,9 @@ template void launch_mg_coarsest<float>(hipStream_t, int, int, int, const Coef<f
                                         const float *, const float *, float *, int, const float *, const float *,
                                         const DevState *);
 template void launch_mg_restrict<double>(hipStream_t, const MgTransfer<double> &, const int8_t *, const double *,
-                                         double *);
-template void launch_mg_restrict<float>(hipStream_t, const MgTransfer<float> &, const int8_t *, const float *, float *);
+                                         double *, const MgFirst<double> &);
+template void launch_mg_restrict<float>(hipStream_t, const MgTransfer<float> &, const int8_t *, const float *, float *,
+                                        const MgFirst<float> &);
 template void launch_mg_prolong_add<double>(hipStream_t, const MgTransfer<double> &, const int8_t *, const double *,
                                             double *);
 template void launch_mg_prolong_add<float>(hipStream_t, const MgTransfer<float> &, const int8_t *, const float *,

@@ -66,7 +66,8 @@ struct MgLevel {
     int *irr_node = nullptr;
     double *k64 = nullptr;
     float *k32 = nullptr;
-    int *irr_map = nullptr;     // coarsest level solved in one workgroup: node -> irregular row
+    int *irr_map = nullptr;     // node -> irregular row (coarse levels)
+    bool lds = false;           // the coarsest level, solved in one workgroup
     MgTransfer<double> t64{};   // transfers to the next coarser level
     MgTransfer<float> t32{};
     double *v64[3] = {nullptr, nullptr, nullptr};   // level right-hand side, two iterates
@@ -488,7 +489,25 @@ T *mg_smooth(cps_solver *s, const Launch &L, const Coef<T> &cf, const Irr<T> &ir
     return dst ? dst : buf(n);
 }
 
-// V-cycle on coarse level l >= 1 for K_l x = rho_l (rho_l in the level's first vector);
+// What the restriction into coarse level l writes besides rho_l: the level's first
+// Chebyshev step from zero into its first iterate buffer, except on the last level (whose
+// own iteration starts from zero).
+template <typename T>
+MgFirst<T> mg_first(cps_solver *s, int l)
+{
+    MgFirst<T> f{};
+    if (l + 1 == (int)s->mg.size()) return f;
+    const MgLevel &Lv = s->mg[l];
+    f.x1 = mg_vecs<T>(Lv)[1];
+    f.c2 = (T)s->mg_c2[0];
+    f.cf = mg_coef<T>(Lv);
+    f.irr_map = Lv.irr_map;
+    f.k7 = mg_irr<T>(Lv).k7;
+    return f;
+}
+
+// V-cycle on coarse level l >= 1 for K_l x = rho_l (rho_l in the level's first vector and,
+// unless l is the last level, its first step x_1 in the second, both from the restriction);
 // returns the buffer that holds x.
 template <typename T>
 T *mg_level(cps_solver *s, int l, const DevState *st)
@@ -502,7 +521,7 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
     const Coef<T> cf = mg_coef<T>(Lv);
     const Irr<T> ir = mg_irr<T>(Lv);
     if (l + 1 == (int)s->mg.size()) {
-        if (Lv.irr_map) {
+        if (Lv.lds) {
             const T *cc;
             if constexpr (sizeof(T) == 8) cc = s->mg_ccd64; else cc = s->mg_ccd32;
             launch_mg_coarsest<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, A,
@@ -513,10 +532,11 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
                             s->mg_cc2.data(), st, false);
     }
     const int nu = s->opt.mg_nu;
-    T *x = mg_smooth<T>(s, L, cf, ir, R, nullptr, Z, A, B, nullptr, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
+    T *x = mg_smooth<T>(s, L, cf, ir, R, nullptr, Z, A, B, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
     T *r = (x == A) ? B : A;
     launch_resid<T>(L, cf, ir, x, R, r, st);
-    launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), s->mg[l + 1].type, r, mg_vecs<T>(s->mg[l + 1])[0]);
+    launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), s->mg[l + 1].type, r, mg_vecs<T>(s->mg[l + 1])[0],
+                          mg_first<T>(s, l + 1));
     T *e = mg_level<T>(s, l + 1, st);
     launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.type, e, x);
     return mg_smooth<T>(s, L, cf, ir, R, x, Z, x, r, nullptr, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
@@ -546,7 +566,8 @@ void mg_precond(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T 
                         true);
     T *res = (x == a) ? b : a;
     launch_resid<T>(L, cf, ir, x, ps, res, st);
-    launch_mg_restrict<T>(s->stream, mg_transfer<T>(s->mg[0]), s->mg[1].type, res, mg_vecs<T>(s->mg[1])[0]);
+    launch_mg_restrict<T>(s->stream, mg_transfer<T>(s->mg[0]), s->mg[1].type, res, mg_vecs<T>(s->mg[1])[0],
+                          mg_first<T>(s, 1));
     T *e = mg_level<T>(s, 1, st);
     launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(s->mg[0]), s->type, e, x);
     mg_smooth<T>(s, L, cf, ir, ps, x, nullptr, x, res, dst, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, true);
@@ -808,6 +829,7 @@ void mg_axis_tables(const double *xf, int nf, const std::vector<int> &idx, std::
     for (int i = 0; i < nf; ++i) {
         while (a + 1 <= nc - 2 && idx[a + 1] <= i) ++a;
         pa[i] = a;
+        if (a != std::min(i / 2, nc - 2)) throw CPS_EINVAL;   // the kernels derive a from i
         pw[i] = (xf[i] - xf[idx[a]]) / (xf[idx[a + 1]] - xf[idx[a]]);
     }
     rw.assign(3 * (size_t)nc, 0.0);
@@ -890,9 +912,8 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
             mg_axis_tables(hx.data() + off, F.n[d], idx[d], pa, pw, rw);
             pw.resize(pw.size() + 4, 0.0);   // padding: 4-vector loads of the weights
             std::vector<float> pw32(pw.begin(), pw.end()), rw32(rw.begin(), rw.end());
-            const int *dpa = upload(s, pa, keep);
-            F.t64.ax[d] = MgAxis<double>{dpa, upload(s, pw, keep), upload(s, rw, keep)};
-            F.t32.ax[d] = MgAxis<float>{dpa, upload(s, pw32, keep), upload(s, rw32, keep)};
+            F.t64.ax[d] = MgAxis<double>{upload(s, pw, keep), upload(s, rw, keep)};
+            F.t32.ax[d] = MgAxis<float>{upload(s, pw32, keep), upload(s, rw32, keep)};
             F.t64.nf[d] = F.t32.nf[d] = F.n[d];
             F.t64.nc[d] = F.t32.nc[d] = C.n[d];
             off += F.n[d];
@@ -931,6 +952,8 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
         C.k32 = dalloc<float>(s, (size_t)7 * C.nirr);
         launch_krows(s->stream, cx, cy, cz, C.xyz, C.xyz + cx, C.xyz + cx + cy, phic, C.type, C.nirr, C.irr_node, C.k64);
         launch_to_float(s->stream, (size_t)7 * C.nirr, C.k64, C.k32);
+        C.irr_map = dalloc<int>(s, C.nn);
+        launch_mg_irr_map(s->stream, C.nirr, C.irr_node, C.irr_map);
         C.skip = dalloc<uint32_t>(s, (size_t)C.g.W * cy * cz + 2);
         launch_fill<uint32_t>(s->stream, (size_t)C.g.W * cy * cz + 2, C.skip, 0u);
         launch_skipbits(s->stream, C.g, C.type, C.skip);
@@ -955,8 +978,7 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
     // a coarsest level below the problem's grid that fits one workgroup is solved there
     MgLevel &Lc2 = s->mg.back();
     if (s->mg.size() > 1 && (size_t)(Lc2.n[0] - 2) * (Lc2.n[1] - 2) * (Lc2.n[2] - 2) <= (size_t)MG_LDS_NODES) {
-        Lc2.irr_map = dalloc<int>(s, Lc2.nn);
-        launch_mg_irr_map(s->stream, Lc2.nirr, Lc2.irr_node, Lc2.irr_map);
+        Lc2.lds = true;
         std::vector<double> cc(s->mg_cc1);
         cc.insert(cc.end(), s->mg_cc2.begin(), s->mg_cc2.end());
         std::vector<float> cc32(cc.begin(), cc.end());
