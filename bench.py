@@ -112,9 +112,10 @@ def main():
     t0 = time.perf_counter()
     stats = []
     for q in range(args.steps):
-        # every 16th preconditioner sweep is timed with a pair of HIP events on the solver's
-        # stream (an event pair costs a few microseconds of queue time)
-        u, st = step("mixed", 16)
+        # every 4th run of consecutive full-traffic preconditioner sweeps on the problem's grid
+        # is timed with one pair of HIP events on the solver's stream (a pair costs a few
+        # microseconds of queue time); runs queued after convergence are left out
+        u, st = step("mixed", 4)
         stats.append(st)
         print(f"# step {q}: {st['iters']} iters, {st['refine_steps']} refinements, "
               f"rel res {st['rel_residual']:.2e}", file=sys.stderr, flush=True)

@@ -68,8 +68,10 @@ typedef struct cps_options {
     int32_t max_refine;    /* CPS_MIXED: cap on refinement steps */
     int32_t max_restarts;  /* restarts after breakdown or a failed true-residual check */
     int32_t device_ptrs;   /* 1: array arguments are device pointers */
-    int32_t kernel_timing; /* n > 0: time every n-th preconditioner sweep with HIP events
-                            * (stats; each timed sweep adds a few microseconds); 0: off */
+    int32_t kernel_timing; /* n > 0: time every n-th run of consecutive preconditioner sweeps
+                            * on the problem's grid that read an x_{k-1}, with one pair of HIP
+                            * events per run (stats; each pair adds a few microseconds); runs
+                            * queued after convergence are left out; 0: off */
     double inner_tol;      /* CPS_MIXED: residual reduction asked of each FP32 inner solve */
     double lam_lo, lam_hi; /* Chebyshev interval for the spectrum of diag(K)^-1 K (default
                             * hi = 2; lo = 0 selects max(hi / (4 inner_iters^2), lambda_1) with
@@ -103,9 +105,9 @@ typedef struct cps_stats {
     double rel_residual_jacobi; /* ||D^-1 (b - B u)||_2 / ||D^-1 b||_2, D = diag(B) */
     double min_ibi_frac;        /* min over IBIs of |x_fluid - x_IBI| / segment length */
     double setup_ms, solve_ms;
-    double sweep_ms;            /* kernel_timing: summed duration of the timed preconditioner
-                                 * sweeps */
-    int64_t sweep_launches;     /* kernel_timing: number of sweeps timed */
+    double sweep_ms;            /* kernel_timing: summed duration of the timed runs of
+                                 * preconditioner sweeps (launch gaps inside a run included) */
+    int64_t sweep_launches;     /* kernel_timing: number of sweeps in them */
     int64_t sweep_points;       /* interior points one sweep processes */
     int32_t sweep_bytes_per_point; /* algorithmic bytes one timed sweep moves per point */
     int32_t pad;

@@ -107,6 +107,10 @@ struct cps_solver {
     std::vector<hipEvent_t> tev;  // sweep timing events
     size_t tev_used = 0;
     int64_t sweep_count = 0;      // sweeps enqueued since the solve started (timing sample)
+    int64_t iter_enq = 0;         // BiCGSTAB iterations enqueued since the solve started
+    std::vector<int64_t> tev_iter;  // per timed run of sweeps: the iteration it belongs to
+    std::vector<char> tev_ok;       // per timed run: ran (not after the solve had converged)
+    std::vector<int> tev_n;         // per timed run: sweeps in it
     Vecs<double> v64;
     Vecs<float> v32;
     double *tmp64 = nullptr;      // user-facing staging (residual, apply, precond)
@@ -398,13 +402,25 @@ hipEvent_t timing_event(cps_solver *s)
     return s->tev[s->tev_used++];
 }
 
-// Every kernel_timing-th sweep is bracketed by a pair of events (an event pair costs a few
-// microseconds of queue time, so timing is sampled); returns the closing event or null.
-hipEvent_t timed_sweep_begin(cps_solver *s)
+// Sweep timing: a run of `nsweeps` consecutive preconditioner sweeps on the problem's grid
+// that all read an x_{k-1} (the sweep kernel's full traffic) is bracketed by one pair of
+// events, every kernel_timing-th such run (an event pair costs a few microseconds of queue
+// time, so timing is sampled; the run's time includes the launch gaps between its sweeps).
+// Returns the closing event, to be recorded after the run, or null.
+hipEvent_t timed_run_begin(cps_solver *s, int nsweeps)
 {
     const int period = s->opt.kernel_timing;
-    if (period <= 0 || (s->sweep_count++ % period) != 0) return nullptr;
+    if (period <= 0 || nsweeps <= 0 || (s->sweep_count++ % period) != 0) return nullptr;
     hipEvent_t e0 = timing_event(s), e1 = timing_event(s);
+    const size_t pair = s->tev_used / 2 - 1;
+    if (s->tev_iter.size() <= pair) {
+        s->tev_iter.resize(pair + 1);
+        s->tev_ok.resize(pair + 1);
+        s->tev_n.resize(pair + 1);
+    }
+    s->tev_iter[pair] = s->iter_enq;
+    s->tev_ok[pair] = 1;
+    s->tev_n[pair] = nsweeps;
     ck(hipEventRecord(e0, s->stream));
     return e1;
 }
@@ -479,13 +495,15 @@ T *mg_smooth(cps_solver *s, const Launch &L, const Coef<T> &cf, const Irr<T> &ir
 {
     T *odd = x0 ? b : a, *even = x0 ? a : b;
     auto buf = [&](int j) -> T * { return j == 0 ? (x0 ? x0 : (T *)zero) : ((j & 1) ? odd : even); };
+    const int kf = std::max(k0, x0 ? 1 : 2);     // the first step with an x_{k-1}
+    hipEvent_t e1 = nullptr;
     for (int k = k0; k < n; ++k) {
         const T *xm1 = (k == 0) ? nullptr : (k == 1 ? (const T *)x0 : buf(k - 1));
         T *out = (k == n - 1 && dst) ? dst : buf(k + 1);
-        hipEvent_t e1 = (timed && xm1) ? timed_sweep_begin(s) : nullptr;
+        if (timed && k == kf) e1 = timed_run_begin(s, n - kf);
         launch_cheb<T>(L, cf, ir, buf(k), xm1, rho, out, c1[k], c2[k], st);
-        if (e1) ck(hipEventRecord(e1, s->stream));
     }
+    if (e1) ck(hipEventRecord(e1, s->stream));
     return dst ? dst : buf(n);
 }
 
@@ -595,11 +613,12 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
     const int m = s->opt.inner_iters;
     auto buf = [&](int j) { return (j == m) ? dst : V.c[j % 2]; };
     launch_first<T>(kind, L, cf, ir, r, ps, v, buf(1), c2[0], st);
+    hipEvent_t e1 = nullptr;
     for (int k = 1; k < m; ++k) {
-        hipEvent_t e1 = timed_sweep_begin(s);
+        if (k == 2) e1 = timed_run_begin(s, m - 2);   // steps 2 .. m-1 read an x_{k-1}
         launch_cheb<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), c1[k], c2[k], st);
-        if (e1) ck(hipEventRecord(e1, s->stream));
     }
+    if (e1) ck(hipEventRecord(e1, s->stream));
 }
 
 // one BiCGSTAB iteration (Alg. 1) entirely on the device
@@ -620,10 +639,11 @@ void enqueue_iteration(cps_solver *s, Vecs<T> &V, TXS *xsol, const double *c1, c
 // run iterations until the device reports done or `budget` iterations were enqueued;
 // the host polls the state of iteration n-1 while iteration n is queued.
 template <typename T, typename TXS>
-DevState run_iterations(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget, const double *c1, const double *c2)
+DevState run_iterations_enqueue(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget, const double *c1, const double *c2)
 {
     for (int n = 0; n < budget; ++n) {
         enqueue_iteration<T, TXS>(s, V, xsol, c1, c2);
+        ++s->iter_enq;
         ck(hipMemcpyAsync(&s->hst[n & 1], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
         ck(hipEventRecord(s->ev[n & 1], s->stream));
         if (n >= 1) {
@@ -632,6 +652,20 @@ DevState run_iterations(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget, const 
         }
     }
     return read_state(s);
+}
+
+template <typename T, typename TXS>
+DevState run_iterations(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget, const double *c1, const double *c2)
+{
+    const int64_t base = s->iter_enq;
+    const int it0 = read_state(s).iters;
+    DevState out = run_iterations_enqueue<T, TXS>(s, V, xsol, budget, c1, c2);
+    // the iterations queued after the converged one return at once: their timed sweeps are
+    // left out of the sweep timing
+    const int64_t done = base + (out.iters - it0);
+    for (size_t p = 0; p < s->tev_iter.size() && 2 * p + 1 < s->tev_used; ++p)
+        if (s->tev_iter[p] >= done && s->tev_iter[p] < s->iter_enq) s->tev_ok[p] = 0;
+    return out;
 }
 
 void free_solver(cps_solver *s)
@@ -701,14 +735,19 @@ int fill_stats(cps_solver *s, cps_stats *st, const DevState &ds, int iters, int 
     st->sweep_points = (int64_t)(s->nx - 2) * (s->ny - 2) * (s->nz - 2);
     if (s->opt.kernel_timing && s->tev_used >= 2) {
         double tot = 0.0;
+        int64_t n = 0;
         for (size_t q = 0; q + 1 < s->tev_used; q += 2) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, s->tev[q], s->tev[q + 1]) == hipSuccess) tot += ms;
+            if (!s->tev_ok[q / 2]) continue;     // sweeps queued after convergence return at once
+            if (hipEventElapsedTime(&ms, s->tev[q], s->tev[q + 1]) == hipSuccess) {
+                tot += ms;
+                n += s->tev_n[q / 2];
+            }
         }
         st->sweep_ms = tot;
-        st->sweep_launches = (int64_t)(s->tev_used / 2);
+        st->sweep_launches = n;
     }
-    // a single sweep reads x_k, x_{k-1}, rho and writes x_{k+1}; a fused sweep also writes x_{k+2}
+    // a timed sweep reads x_k, x_{k-1}, rho and writes x_{k+1}
     const int vb = (s->opt.precision == CPS_MIXED) ? 4 : 8;
     st->sweep_bytes_per_point = 4 * vb;
     return status;
@@ -1246,6 +1285,7 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
     try {
         s->tev_used = 0;
         s->sweep_count = 0;
+        s->iter_enq = 0;
         const int m = s->opt.inner_iters;
         double c1[MAX_INNER], c2[MAX_INNER];
         cheb_coefficients(m, s->opt.lam_lo, s->opt.lam_hi, c1, c2);

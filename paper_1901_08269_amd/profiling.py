@@ -66,25 +66,38 @@ def kernel_stats(db):
     return rows
 
 
+def _problem_grid(groups):
+    """Pick the launches on the problem's grid from {key: [(duration, value), ...]} groups of
+    one kernel by launch grid.  A multigrid kernel runs on every level, one launch grid per
+    level, and the problem's grid is the one whose launches take longest; two levels can
+    share a launch grid, so within a group the launches shorter than 0.4 of its 90th
+    percentile duration (a much smaller level) are left out."""
+    best = None
+    for key, items in groups.items():
+        d = sorted(x[0] for x in items)
+        cut = 0.4 * d[min(len(d) - 1, int(0.9 * len(d)))]
+        kept = [x for x in items if x[0] >= cut]
+        mean = sum(x[0] for x in kept) / len(kept)
+        if best is None or mean > best[0]:
+            best = (mean, kept)
+    return best[1]
+
+
 def pmc_per_kernel(db):
     """{short kernel name: (dispatches, mean counter value, mean duration ns)} over each
-    kernel's dispatches on the problem's grid: a kernel that also runs on coarser multigrid
-    levels has one launch grid per level, and the problem's grid is the one whose launches
-    take longest."""
+    kernel's dispatches on the problem's grid (see _problem_grid)."""
     con = sqlite3.connect(db)
     acc = {}
     rows = con.execute("select p.name, p.counter_value, p.duration, k.grid_x * k.grid_y * k.grid_z "
                        "from pmc_events p join kernels k on p.dispatch_id = k.dispatch_id")
     for name, val, dur, size in rows:
-        key = (short_name(name), size)
-        c, v, d = acc.get(key, (0, 0.0, 0.0))
-        acc[key] = (c + 1, v + val, d + dur)
+        acc.setdefault(short_name(name), {}).setdefault(size, []).append((dur, val))
     con.close()
-    best = {}
-    for (n, size), (c, v, d) in acc.items():
-        if n not in best or d / c > best[n][3] / best[n][1]:
-            best[n] = (size, c, v, d)
-    return {n: (c, v / c, d / c) for n, (size, c, v, d) in best.items()}
+    out = {}
+    for n, groups in acc.items():
+        kept = _problem_grid(groups)
+        out[n] = (len(kept), sum(v for _, v in kept) / len(kept), sum(d for d, _ in kept) / len(kept))
+    return out
 
 
 def stats_report(db, title, cmd, top=20):
@@ -140,21 +153,17 @@ def algorithmic_bytes(name):
 
 
 def fine_grid_launches(db):
-    """Per solve kernel, its launches on the problem's grid: multigrid kernels also run on the
-    coarser grids, one launch grid per level, and the problem's grid is the one whose
-    launches take longest.  [(name, calls, avg us)]"""
+    """Per solve kernel, its launches on the problem's grid (see _problem_grid).
+    [(name, calls, avg us)]"""
     con = sqlite3.connect(db)
     groups = {}
     for name, gx, gy, gz, dur in con.execute("select name, grid_x, grid_y, grid_z, duration from kernels"):
-        key = (name, gx * gy * gz)
-        c, d = groups.get(key, (0, 0.0))
-        groups[key] = (c + 1, d + dur)
+        groups.setdefault(name, {}).setdefault(gx * gy * gz, []).append((dur, 0.0))
     con.close()
-    best = {}
-    for (name, size), (c, d) in groups.items():
-        if name not in best or d / c > best[name][2] / best[name][1]:
-            best[name] = (size, c, d)
-    rows = [(name, c, d / c / 1e3) for name, (size, c, d) in best.items()]
+    rows = []
+    for name, g in groups.items():
+        kept = _problem_grid(g)
+        rows.append((name, len(kept), sum(d for d, _ in kept) / len(kept) / 1e3))
     return sorted(rows, key=lambda r: -r[1] * r[2])
 
 

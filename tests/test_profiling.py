@@ -96,3 +96,19 @@ def test_kernels_report(tmp_path):
     # restriction: 4.5 B per fine point in 20 us = 225 GB/s
     assert "| `cps::k_mg_restrict<float>` | 1 | 20.00 | 4.5 | 225 | 0.03 |" in rep
     assert "k_fill" not in rep
+
+
+def test_kernels_report_separates_levels_sharing_a_launch_grid(tmp_path):
+    """Two multigrid levels can launch the sweep with the same grid (a coarse level's latency
+    tiling): the much shorter launches of the smaller level are left out."""
+    db = tmp_path / "s.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, grid_x int, grid_y int, grid_z int, duration real)")
+    sweep = "void cps::k_cheb4<float, false>(cps::Geom, int)"
+    for _ in range(10):
+        con.execute("insert into kernels values (?, 65536, 4, 1, 40000.0)", (sweep,))
+        con.execute("insert into kernels values (?, 65536, 4, 1, 5000.0)", (sweep,))
+    con.commit()
+    con.close()
+    rep = profiling.kernels_report(str(db), 1000000, "T", "cmd")
+    assert "| `cps::k_cheb4<float, false>` | 10 | 40.00 | 16 | 400 | 0.05 |" in rep
