@@ -22,13 +22,14 @@ struct Launch {
 template <typename T, typename TO>
 void launch_apply(int mode, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, TO *y, const T *w,
                   const double *bvec, DevState *st);
+// rev: march down in z (consecutive sweeps alternate, see k_cheb4)
 template <typename T>
 void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
-                 double c1, double c2, const DevState *st);
+                 double c1, double c2, const DevState *st, int rev);
 // r = rho - K x at the unknown nodes (r is written there only)
 template <typename T>
 void launch_resid(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, const T *rho, T *r,
-                  const DevState *st);
+                  const DevState *st, int rev);
 template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st);

@@ -122,6 +122,7 @@ struct cps_solver {
     std::vector<double> mg_cc1, mg_cc2; // coarsest-level steps on [lambda_1, lam_hi]
     double *mg_zero64 = nullptr;        // zeros, the size of level 1
     float *mg_zero32 = nullptr;
+    int sweep_rev[MG_MAX_LEVELS] = {};  // per level: z direction of its next sweep (alternates)
     double *mg_ccd64 = nullptr;         // mg_cc1 | mg_cc2 on the device (one-workgroup coarsest solve)
     float *mg_ccd32 = nullptr;
     // host-side facts
@@ -489,9 +490,19 @@ Irr<T> mg_irr(const MgLevel &Lv)
 // from x0 (which must be a) they alternate b, a, b, ...  Each step from the third on writes
 // over its x_{k-1} in place.  The last step writes dst if it is non-null.  Returns the
 // buffer that holds x_n.  Level-0 sweeps with an x_{k-1} are sampled by kernel_timing.
+// z direction of the next sweep on level l: consecutive sweeps of a level alternate, each
+// starting on the planes the previous one touched last
+int next_rev(cps_solver *s, int l)
+{
+    const int r = s->sweep_rev[l];
+    s->sweep_rev[l] ^= 1;
+    return r;
+}
+
 template <typename T>
-T *mg_smooth(cps_solver *s, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *rho, T *x0, const T *zero,
-             T *a, T *b, T *dst, int k0, int n, const double *c1, const double *c2, const DevState *st, bool timed)
+T *mg_smooth(cps_solver *s, int lvl, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *rho, T *x0,
+             const T *zero, T *a, T *b, T *dst, int k0, int n, const double *c1, const double *c2, const DevState *st,
+             bool timed)
 {
     T *odd = x0 ? b : a, *even = x0 ? a : b;
     auto buf = [&](int j) -> T * { return j == 0 ? (x0 ? x0 : (T *)zero) : ((j & 1) ? odd : even); };
@@ -501,7 +512,7 @@ T *mg_smooth(cps_solver *s, const Launch &L, const Coef<T> &cf, const Irr<T> &ir
         const T *xm1 = (k == 0) ? nullptr : (k == 1 ? (const T *)x0 : buf(k - 1));
         T *out = (k == n - 1 && dst) ? dst : buf(k + 1);
         if (timed && k == kf) e1 = timed_run_begin(s, n - kf);
-        launch_cheb<T>(L, cf, ir, buf(k), xm1, rho, out, c1[k], c2[k], st);
+        launch_cheb<T>(L, cf, ir, buf(k), xm1, rho, out, c1[k], c2[k], st, next_rev(s, lvl));
     }
     if (e1) ck(hipEventRecord(e1, s->stream));
     return dst ? dst : buf(n);
@@ -546,18 +557,18 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
                                   s->opt.mg_coarse_steps, cc, cc + s->mg_cc1.size(), st);
             return A;
         }
-        return mg_smooth<T>(s, L, cf, ir, R, nullptr, Z, A, B, nullptr, 0, s->opt.mg_coarse_steps, s->mg_cc1.data(),
+        return mg_smooth<T>(s, l, L, cf, ir, R, nullptr, Z, A, B, nullptr, 0, s->opt.mg_coarse_steps, s->mg_cc1.data(),
                             s->mg_cc2.data(), st, false);
     }
     const int nu = s->opt.mg_nu;
-    T *x = mg_smooth<T>(s, L, cf, ir, R, nullptr, Z, A, B, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
+    T *x = mg_smooth<T>(s, l, L, cf, ir, R, nullptr, Z, A, B, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
     T *r = (x == A) ? B : A;
-    launch_resid<T>(L, cf, ir, x, R, r, st);
+    launch_resid<T>(L, cf, ir, x, R, r, st, next_rev(s, l));
     launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), s->mg[l + 1].type, r, mg_vecs<T>(s->mg[l + 1])[0],
                           mg_first<T>(s, l + 1));
     T *e = mg_level<T>(s, l + 1, st);
     launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.type, e, x);
-    return mg_smooth<T>(s, L, cf, ir, R, x, Z, x, r, nullptr, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
+    return mg_smooth<T>(s, l, L, cf, ir, R, x, Z, x, r, nullptr, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
 }
 
 // dst = one V-cycle for K dst = ps on the problem's grid.  The first pre-smoothing step is
@@ -574,21 +585,21 @@ void mg_precond(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T 
     T *a = V.c[1], *b = V.c[0];
     if (s->mg.size() == 1) {   // no coarser grid: the coarsest-level iteration on this grid
         launch_first<T>(kind, L, cf, ir, r, ps, v, a, s->mg_cc2[0], st);
-        mg_smooth<T>(s, L, cf, ir, ps, nullptr, nullptr, a, b, dst, 1, s->opt.mg_coarse_steps, s->mg_cc1.data(),
+        mg_smooth<T>(s, 0, L, cf, ir, ps, nullptr, nullptr, a, b, dst, 1, s->opt.mg_coarse_steps, s->mg_cc1.data(),
                      s->mg_cc2.data(), st, true);
         return;
     }
     const int nu = s->opt.mg_nu;
     launch_first<T>(kind, L, cf, ir, r, ps, v, a, s->mg_c2[0], st);
-    T *x = mg_smooth<T>(s, L, cf, ir, ps, nullptr, nullptr, a, b, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st,
+    T *x = mg_smooth<T>(s, 0, L, cf, ir, ps, nullptr, nullptr, a, b, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st,
                         true);
     T *res = (x == a) ? b : a;
-    launch_resid<T>(L, cf, ir, x, ps, res, st);
+    launch_resid<T>(L, cf, ir, x, ps, res, st, next_rev(s, 0));
     launch_mg_restrict<T>(s->stream, mg_transfer<T>(s->mg[0]), s->mg[1].type, res, mg_vecs<T>(s->mg[1])[0],
                           mg_first<T>(s, 1));
     T *e = mg_level<T>(s, 1, st);
     launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(s->mg[0]), s->type, e, x);
-    mg_smooth<T>(s, L, cf, ir, ps, x, nullptr, x, res, dst, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, true);
+    mg_smooth<T>(s, 0, L, cf, ir, ps, x, nullptr, x, res, dst, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, true);
 }
 
 // p^ = M p: inner_iters Chebyshev steps.  The first is fused with the vector update `kind`
@@ -616,7 +627,8 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
     hipEvent_t e1 = nullptr;
     for (int k = 1; k < m; ++k) {
         if (k == 2) e1 = timed_run_begin(s, m - 2);   // steps 2 .. m-1 read an x_{k-1}
-        launch_cheb<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), c1[k], c2[k], st);
+        launch_cheb<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), c1[k], c2[k], st,
+                       next_rev(s, 0));
     }
     if (e1) ck(hipEventRecord(e1, s->stream));
 }

@@ -206,7 +206,7 @@ __device__ __forceinline__ uint32_t skip4(const uint32_t *__restrict__ w, int i0
 // wavefront.  Wave-uniform y and z coefficients live in scalar registers.  Irregular rows
 // use their Shortley-Weller row in the leading blocks (one thread per row).  With RES the
 // same rows give the residual rho - K x_k instead (multigrid), with no x_{k-1}.
-template <typename T, bool PREV0, bool RES>
+template <typename T, bool PREV0, bool RES, bool REV>
 __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, const Irr<T> &ir,
                                            const uint32_t *__restrict__ skip, const T *__restrict__ xc,
                                            const T *xm1, const T *__restrict__ rho, T *xn, T c1, T c2,
@@ -274,20 +274,26 @@ __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, con
     const int ir_off = q.nv > 0 ? q.nv : 0;
     const size_t wplane = (size_t)ny * g.W;
 
-    V cm[R], c0[R];
+    // The march runs up in z, or down when rev is set: consecutive sweeps alternate, so that
+    // each starts on the planes the previous one touched last (still in the caches).  `cb`
+    // is the plane behind the march, `ca` the one ahead.
+    constexpr int dir = REV ? -1 : 1;
+    const int ks = REV ? k1 - 1 : k0;
+    V cb[R], c0[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        cm[r] = load4(xc, er[r] + (size_t)(k0 - 1) * plane, q);
-        c0[r] = load4(xc, er[r] + (size_t)k0 * plane, q);
+        cb[r] = load4(xc, er[r] + (size_t)(ks - dir) * plane, q);
+        c0[r] = load4(xc, er[r] + (size_t)ks * plane, q);
     }
-    for (int k = k0; k < k1; ++k) {
-        const size_t kp = (size_t)k * plane, kn = kp + plane;
-        V cp[R], rv4[R], pv4[R];
+    for (int t = 0; t < k1 - k0; ++t) {
+        const int k = ks + dir * t;
+        const size_t kp = (size_t)k * plane, kn = (size_t)(k + dir) * plane;
+        V ca[R], rv4[R], pv4[R];
         uint32_t sk[R];
         T lft[R], rgt[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            cp[r] = load4(xc, er[r] + kn, q);
+            ca[r] = load4(xc, er[r] + kn, q);
             rv4[r] = load4(rho, er[r] + kp, q);
             if (!PREV0) pv4[r] = load4(xm1, er[r] + kp, q);
             sk[r] = skip4(skip + (size_t)k * wplane + wr[r], ic);
@@ -308,8 +314,9 @@ __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, con
             if (need_r) right = rgt[r];
             const T sv[4] = {s4.x, s4.y, s4.z, s4.w};
             const T nvv[4] = {n4.x, n4.y, n4.z, n4.w};
-            const T mv[4] = {cm[r].x, cm[r].y, cm[r].z, cm[r].w};
-            const T uv[4] = {cp[r].x, cp[r].y, cp[r].z, cp[r].w};
+            const V &lo4 = REV ? ca[r] : cb[r], &hi4 = REV ? cb[r] : ca[r];   // planes k - 1, k + 1
+            const T mv[4] = {lo4.x, lo4.y, lo4.z, lo4.w};
+            const T uv[4] = {hi4.x, hi4.y, hi4.z, hi4.w};
             const T rvv[4] = {rv4[r].x, rv4[r].y, rv4[r].z, rv4[r].w};
             T pv[4] = {T(0), T(0), T(0), T(0)};
             if (!PREV0) { pv[0] = pv4[r].x; pv[1] = pv4[r].y; pv[2] = pv4[r].z; pv[3] = pv4[r].w; }
@@ -337,8 +344,8 @@ __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, con
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            cm[r] = c0[r];
-            c0[r] = cp[r];
+            cb[r] = c0[r];
+            c0[r] = ca[r];
         }
     }
 }
@@ -347,18 +354,20 @@ template <typename T, bool PREV0>
 __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
                                               const T *__restrict__ xc, const T *xm1,
                                               const T *__restrict__ rho, T *xn, T c1, T c2,
-                                              const DevState *st)
+                                              const DevState *st, int rev)
 {
-    cheb4_rows<T, PREV0, false>(g, cf, ir, skip, xc, xm1, rho, xn, c1, c2, st);
+    if (rev) cheb4_rows<T, PREV0, false, true>(g, cf, ir, skip, xc, xm1, rho, xn, c1, c2, st);
+    else cheb4_rows<T, PREV0, false, false>(g, cf, ir, skip, xc, xm1, rho, xn, c1, c2, st);
 }
 
 // r = rho - K x at the unknown nodes (the residual of a multigrid level; same rows)
 template <typename T>
 __global__ void __launch_bounds__(NT) k_resid4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
                                                const T *__restrict__ x, const T *__restrict__ rho, T *r,
-                                               const DevState *st)
+                                               const DevState *st, int rev)
 {
-    cheb4_rows<T, true, true>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
+    if (rev) cheb4_rows<T, true, true, true>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
+    else cheb4_rows<T, true, true, false>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -883,21 +892,21 @@ void launch_apply(int mode, const Launch &L, const Coef<T> &cf, const Irr<T> &ir
 
 template <typename T>
 void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
-                 double c1, double c2, const DevState *st)
+                 double c1, double c2, const DevState *st, int rev)
 {
     dim3 grid(L.g.tr.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
     if (xm1 == nullptr)
-        k_cheb4<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st);
+        k_cheb4<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
     else
-        k_cheb4<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st);
+        k_cheb4<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
 }
 
 template <typename T>
 void launch_resid(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, const T *rho, T *r,
-                  const DevState *st)
+                  const DevState *st, int rev)
 {
     dim3 grid(L.g.tr.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
-    k_resid4<T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st);
+    k_resid4<T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st, rev);
 }
 
 template <typename T>
@@ -978,13 +987,13 @@ template void launch_apply<double, float>(int, const Launch &, const Coef<double
 template void launch_apply<float, float>(int, const Launch &, const Coef<float> &, const Irr<float> &, const float *,
                                          float *, const float *, const double *, DevState *);
 template void launch_cheb<double>(const Launch &, const Coef<double> &, const Irr<double> &, const double *,
-                                  const double *, const double *, double *, double, double, const DevState *);
+                                  const double *, const double *, double *, double, double, const DevState *, int);
 template void launch_cheb<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
-                                 const float *, float *, double, double, const DevState *);
+                                 const float *, float *, double, double, const DevState *, int);
 template void launch_resid<double>(const Launch &, const Coef<double> &, const Irr<double> &, const double *,
-                                   const double *, double *, const DevState *);
+                                   const double *, double *, const DevState *, int);
 template void launch_resid<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
-                                  float *, const DevState *);
+                                  float *, const DevState *, int);
 template void launch_first<double>(int, const Launch &, const Coef<double> &, const Irr<double> &, const double *,
                                    double *, const double *, double *, double, const DevState *);
 template void launch_first<float>(int, const Launch &, const Coef<float> &, const Irr<float> &, const float *, float *,
