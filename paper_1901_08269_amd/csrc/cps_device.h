@@ -49,6 +49,9 @@ struct Geom {
                                // vector updates
     Tiling tr;                 // 256 x 4 tiles: one x-row segment of 256 nodes per wavefront,
                                // four nodes per lane (vectorised Chebyshev sweeps)
+    int lg;                    // coarse multigrid levels whose rows are at most 128 nodes
+                               // long: 2^lg lanes per row, 64 / 2^lg rows per wavefront
+                               // (tr then has (4 * 2^lg) x (4 * 64 / 2^lg) tiles); 6 otherwise
     int nflat;                 // blocks of the flat (vectorised) pointwise kernels
 };
 

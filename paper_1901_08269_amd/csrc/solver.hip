@@ -343,9 +343,10 @@ Tiling make_tiling(int nx, int ny, int nz, int tw, int ty, int target_blocks, in
 
 // coarse = true (a coarse multigrid level): the sweep tiling aims at CPS_COARSE_TILES tiles
 // of at least one plane each, since a small grid's sweep is bound by the latency of its
-// z-march rather than by bandwidth
+// z-march rather than by bandwidth (spheres8 256^3, mixed multigrid solve: 1024 tiles
+// 25.1 ms, 512 25.2 ms, 2048 25.6 ms)
 #ifndef CPS_COARSE_TILES
-#define CPS_COARSE_TILES 2048
+#define CPS_COARSE_TILES 1024
 #endif
 Geom make_geom(int nx, int ny, int nz, bool coarse = false)
 {
@@ -356,9 +357,13 @@ Geom make_geom(int nx, int ny, int nz, bool coarse = false)
         const int per_plane = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY - 1) / TY);
         g.ta = make_tiling(nx, ny, nz, 4 * TX, TY, per_plane * CPS_APPLY_ZCHUNKS, 4);
     }
+    // a coarse level whose rows need at most 32 lanes packs 64 / 2^lg rows into a wavefront
+    g.lg = 6;
+    if (coarse && RPW == 1)
+        while (g.lg > 3 && 4 * (1 << (g.lg - 1)) >= nx - 2) --g.lg;
     {
         const int per_plane = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY * RPW - 1) / (TY * RPW));
-        g.tr = coarse ? make_tiling(nx, ny, nz, 4 * TX, TY * RPW, CPS_COARSE_TILES, 1)
+        g.tr = coarse ? make_tiling(nx, ny, nz, 4 << g.lg, TY * RPW * (TX >> g.lg), CPS_COARSE_TILES, 1)
                       : make_tiling(nx, ny, nz, 4 * TX, TY * RPW, per_plane * CPS_ROW_ZCHUNKS, 4);
     }
     size_t nn = (size_t)nx * ny * nz;

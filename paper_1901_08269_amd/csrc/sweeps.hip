@@ -206,7 +206,10 @@ __device__ __forceinline__ uint32_t skip4(const uint32_t *__restrict__ w, int i0
 // wavefront.  Wave-uniform y and z coefficients live in scalar registers.  Irregular rows
 // use their Shortley-Weller row in the leading blocks (one thread per row).  With RES the
 // same rows give the residual rho - K x_k instead (multigrid), with no x_{k-1}.
-template <typename T, bool PREV0, bool RES, bool REV>
+// With MR (a coarse multigrid level whose rows fit in fewer than 64 lanes) each group of
+// 2^g.lg lanes owns one whole row, so a wavefront carries 64 / 2^g.lg rows and no lane idles;
+// the rows' y coefficients are then per lane.
+template <typename T, bool PREV0, bool RES, bool REV, bool MR = false>
 __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, const Irr<T> &ir,
                                            const uint32_t *__restrict__ skip, const T *__restrict__ xc,
                                            const T *xm1, const T *__restrict__ rho, T *xn, T c1, T c2,
@@ -214,14 +217,17 @@ __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, con
 {
     using V = typename Vec4Of<T>::type;
     constexpr int R = RPW;
+    static_assert(!MR || RPW == 1, "multi-row wavefronts take one row per lane group");
     if (st && st->done) return;
-    const int lane = threadIdx.x, wv = threadIdx.y;
+    const int wv = threadIdx.y;
+    const int lw = MR ? 1 << g.lg : TX;                          // lanes per row
+    const int lane = MR ? (int)threadIdx.x & (lw - 1) : (int)threadIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const size_t plane = (size_t)nx * ny;
     const int nib = irr_blocks(ir.n, NT);
     const int b = (int)blockIdx.x - nib;
     if (b < 0) {
-        const int row = (int)blockIdx.x * NT + lane + wv * TX;
+        const int row = (int)blockIdx.x * NT + (int)threadIdx.x + wv * TX;
         if (row >= ir.n) return;
         const int e = ir.node[row];
         const T *k7 = ir.k7 + 7 * row;
@@ -235,9 +241,18 @@ __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, con
     const Tiling &tl = g.tr;
     int bs, by, bz;
     if (!tile_of_block(tl, b, bs, by, bz)) return;
-    const int j0 = 1 + (by * TY + wv) * R;                     // rows j0 .. j0 + R - 1
-    if (j0 > ny - 2) return;                                  // whole wavefront
-    const Seg q = seg_of(nx, bs, lane);
+    const int jw = 1 + (by * TY + wv) * (MR ? TX / lw : R);    // the wavefront's first row
+    if (jw > ny - 2) return;                                  // whole wavefront
+    // rows j0 .. j0 + R - 1 (MR: one row per lane group, clamped to the wall row)
+    const int j0 = MR ? min(jw + (int)threadIdx.x / lw, ny - 1) : jw;
+    Seg q;
+    if (MR) {
+        q.i0 = 1 + bs * (4 * lw) + 4 * lane;
+        q.nv = min(4, nx - 1 - q.i0);
+        q.full = q.nv == 4;
+    } else {
+        q = seg_of(nx, bs, lane);
+    }
     const int k0 = 1 + bz * tl.TZ;
     const int k1 = min(k0 + tl.TZ, nz - 1);
     const int ic = q.nv > 0 ? q.i0 : 1;                        // lanes without nodes read valid memory
@@ -261,16 +276,16 @@ __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, con
         const int jc = rok[r] ? j : ny - 1;
         er[r] = (size_t)ic + (size_t)nx * jc;
         wr[r] = (size_t)jc * g.W + (ic >> 5);
-        kay[r] = uniform(cf.c[1][8 * jc + 5]);
-        kby[r] = uniform(cf.c[1][8 * jc + 6]);
-        kcy[r] = uniform(cf.c[1][8 * jc + 7]);
+        kay[r] = MR ? cf.c[1][8 * jc + 5] : uniform(cf.c[1][8 * jc + 5]);
+        kby[r] = MR ? cf.c[1][8 * jc + 6] : uniform(cf.c[1][8 * jc + 6]);
+        kcy[r] = MR ? cf.c[1][8 * jc + 7] : uniform(cf.c[1][8 * jc + 7]);
     }
     const size_t elo = (size_t)ic + (size_t)nx * (j0 - 1);                  // row j0 - 1 (>= 0)
     const size_t ehi = (size_t)ic + (size_t)nx * min(j0 + R, ny - 1);       // row j0 + R (<= ny - 1)
     // the segment's outer neighbours: node i0 - 1 for lane 0, node i0 + nv for the last lane
     // (both walls, hence zero in every iterate, when one segment spans the row)
-    const bool one_seg = nx - 2 <= 4 * TX;
-    const bool need_l = lane == 0, need_r = lane == TX - 1 || q.i0 + 4 >= nx - 1;
+    const bool one_seg = nx - 2 <= 4 * lw;
+    const bool need_l = lane == 0, need_r = lane == lw - 1 || q.i0 + 4 >= nx - 1;
     const int ir_off = q.nv > 0 ? q.nv : 0;
     const size_t wplane = (size_t)ny * g.W;
 
@@ -308,8 +323,8 @@ __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, con
             const V &s4 = (r == 0) ? ylo : c0[r - 1];
             const V &n4 = (r == R - 1) ? yhi : c0[r + 1];
             const T cv[4] = {c0[r].x, c0[r].y, c0[r].z, c0[r].w};
-            T left = __shfl_up(cv[3], 1, TX);
-            T right = __shfl_down(cv[0], 1, TX);
+            T left = MR ? __shfl_up(cv[3], 1, lw) : __shfl_up(cv[3], 1, TX);
+            T right = MR ? __shfl_down(cv[0], 1, lw) : __shfl_down(cv[0], 1, TX);
             if (need_l) left = lft[r];
             if (need_r) right = rgt[r];
             const T sv[4] = {s4.x, s4.y, s4.z, s4.w};
@@ -368,6 +383,26 @@ __global__ void __launch_bounds__(NT) k_resid4(Geom g, Coef<T> cf, Irr<T> ir, co
 {
     if (rev) cheb4_rows<T, true, true, true>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
     else cheb4_rows<T, true, true, false>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
+}
+
+// the same two kernels for coarse levels with several rows per wavefront (g.lg < 6)
+template <typename T, bool PREV0>
+__global__ void __launch_bounds__(NT) k_cheb4m(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
+                                               const T *__restrict__ xc, const T *xm1,
+                                               const T *__restrict__ rho, T *xn, T c1, T c2,
+                                               const DevState *st, int rev)
+{
+    if (rev) cheb4_rows<T, PREV0, false, true, true>(g, cf, ir, skip, xc, xm1, rho, xn, c1, c2, st);
+    else cheb4_rows<T, PREV0, false, false, true>(g, cf, ir, skip, xc, xm1, rho, xn, c1, c2, st);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_resid4m(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
+                                                const T *__restrict__ x, const T *__restrict__ rho, T *r,
+                                                const DevState *st, int rev)
+{
+    if (rev) cheb4_rows<T, true, true, true, true>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
+    else cheb4_rows<T, true, true, false, true>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -578,7 +613,7 @@ __global__ void __launch_bounds__(NT) k_first4(Geom g, Coef<T> cf, Irr<T> ir, co
     const int nib = irr_blocks(ir.n, NT);
     const int b = (int)blockIdx.x - nib;
     if (b < 0) {
-        const int row = (int)blockIdx.x * NT + lane + wv * TX;
+        const int row = (int)blockIdx.x * NT + (int)threadIdx.x + wv * TX;
         if (row >= ir.n) return;
         const int e = ir.node[row];
         const T val = (KIND == FIRST_P) ? r[e] + beta * (ps[e] - omega * v[e]) : r[e] - alpha * v[e];
@@ -647,7 +682,7 @@ __global__ void __launch_bounds__(NT) k_update4(Geom g, Coef<T> cf, Irr<T> ir, c
     if (b < 0) {
         // irregular rows: x and r are updated by the tiles like every node; here only the
         // Jacobi-weighted norm with the row's own diagonal
-        const int row = (int)blockIdx.x * NT + lane + wv * TX;
+        const int row = (int)blockIdx.x * NT + (int)threadIdx.x + wv * TX;
         if (row < ir.n) {
             const int e = ir.node[row];
             const T rv = s[e] - omegaT * t[e];
@@ -895,10 +930,14 @@ void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *
                  double c1, double c2, const DevState *st, int rev)
 {
     dim3 grid(L.g.tr.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
-    if (xm1 == nullptr)
-        k_cheb4<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
-    else
-        k_cheb4<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
+    const bool mr = L.g.lg < 6;
+    if (xm1 == nullptr) {
+        if (mr) k_cheb4m<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
+        else k_cheb4<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
+    } else {
+        if (mr) k_cheb4m<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
+        else k_cheb4<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
+    }
 }
 
 template <typename T>
@@ -906,7 +945,8 @@ void launch_resid(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T 
                   const DevState *st, int rev)
 {
     dim3 grid(L.g.tr.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
-    k_resid4<T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st, rev);
+    if (L.g.lg < 6) k_resid4m<T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st, rev);
+    else k_resid4<T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st, rev);
 }
 
 template <typename T>
