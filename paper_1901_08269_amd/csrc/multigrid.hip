@@ -39,8 +39,9 @@ struct MgVec4<double> {
 // rwx rwy rwz r at the unknown coarse nodes, 0 at the other interior nodes (the walls of rc
 // are never written and stay 0).  Block 64 x 4: lane l takes the interior coarse nodes
 // I0 = 1 + 128 blockIdx.x + 2 l and I0 + 1 of row J = 1 + 4 blockIdx.y + wavefront, plane
-// K = 1 + blockIdx.z; it reads fine nodes 2 I0 - 1 .. 2 I0 + 3 of each of the nine fine
-// rows as a 4-vector and one more value.  Every load is issued whatever the node types.
+// K = 1 + blockIdx.z; it reads fine nodes 2 I0 - 1 .. 2 I0 + 2 of each of the nine fine
+// rows as a 4-vector, and node 2 I0 + 3 from the next lane.  Every load is issued whatever
+// the node types.
 // With a first step F (F.x1 non-null) it also writes the coarse level's first Chebyshev
 // step from zero, x1 = c2 rho / diag K, at its unknown nodes (the diagonal from the 1D
 // tables, or the stored row of an irregular node).
@@ -66,6 +67,9 @@ __global__ void __launch_bounds__(256) k_mg_restrict(int ncx, int ncy, int nfx, 
     const size_t fplane = (size_t)nfx * nfy;
     const int f0 = 2 * I0 - 1;                      // first fine node of the lane
     const int f4 = min(f0 + 4, nfx - 1);            // fifth node (I0 + 1's last), in the row
+    // the fifth node is the next lane's first one, taken by a shuffle unless that lane has no
+    // coarse node (then the lane loads it)
+    const bool self4 = threadIdx.x == 63 || I0 + 2 > ncx - 2;
     T acc0 = T(0), acc1 = T(0);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -76,7 +80,8 @@ __global__ void __launch_bounds__(256) k_mg_restrict(int ncx, int ncy, int nfx, 
             const T wyz = wz * ay.rw[3 * J + b];
             const T *row = r + kz + (size_t)(2 * J - 1 + b) * nfx;
             const V v = *reinterpret_cast<const V *>(row + f0);
-            const T v4 = row[f4];
+            T v4 = __shfl_down(v.x, 1, 64);
+            if (self4) v4 = row[f4];
             acc0 += wyz * (w0[0] * v.x + w0[1] * v.y + w0[2] * v.z);
             acc1 += wyz * (w1[0] * v.z + w1[1] * v.w + w1[2] * v4);
         }
@@ -98,66 +103,80 @@ __global__ void __launch_bounds__(256) k_mg_restrict(int ncx, int ncy, int nfx, 
 
 // x(i, j, k) += (P e)(i, j, k) at the unknown fine nodes.  Block 64 x 4: lane l of
 // wavefront w takes the interior nodes i0 .. i0 + 3 (i0 = 1 + 256 blockIdx.x + 4 l) of row
-// j = 1 + 4 blockIdx.y + w in plane k = 1 + blockIdx.z.  A fine point i lies in the coarse
-// interval starting at min(i / 2, nc - 2) (coarse point I is fine point 2I, the last one
-// excepted), so the lane's nodes interpolate from the four coarse x points a0 .. a0 + 3.
-// Every load is issued at once (4-vectors: x, the four coarse rows, the x weights; vectors
-// and weight tables carry padding past their ends): the four coarse rows are combined in y
-// and z, then each node interpolates in x.  x is stored as one 4-vector where all four
-// nodes are unknowns.
+// j = 1 + 4 blockIdx.y + w in the planes k = 2 blockIdx.z and 2 blockIdx.z + 1 (the interior
+// ones), which interpolate from the same two coarse planes.  A fine point i lies in the
+// coarse interval starting at min(i / 2, nc - 2) (coarse point I is fine point 2I, the last
+// one excepted), so the lane's nodes interpolate from the four coarse x points a0 .. a0 + 3
+// of four coarse rows.  Every load is issued at once (4-vectors: x of both planes, the four
+// coarse rows, the x weights; vectors and weight tables carry padding past their ends): the
+// coarse rows are combined in y, then in z for each plane, then each node interpolates in
+// x.  x is stored as one 4-vector where all four nodes are unknowns.
 template <typename T>
-__global__ void __launch_bounds__(256) k_mg_prolong_add(int nfx, int nfy, int ncx, int ncy, int ncz, MgAxis<T> ax,
-                                                        MgAxis<T> ay, MgAxis<T> az,
+__global__ void __launch_bounds__(256) k_mg_prolong_add(int nfx, int nfy, int nfz, int ncx, int ncy, int ncz,
+                                                        MgAxis<T> ax, MgAxis<T> ay, MgAxis<T> az,
                                                         const int8_t *__restrict__ type_f, const T *__restrict__ e,
                                                         T *__restrict__ x)
 {
     using V = typename MgVec4<T>::type;
-    const int j = 1 + (int)(blockIdx.y * 4 + threadIdx.y), k = 1 + (int)blockIdx.z;
+    const int j = 1 + (int)(blockIdx.y * 4 + threadIdx.y), kp = 2 * (int)blockIdx.z;
     const int i0 = 1 + (int)(blockIdx.x * 256 + 4 * threadIdx.x);
     if (j > nfy - 2 || i0 > nfx - 2) return;
     const int nv = min(4, nfx - 1 - i0);
-    const size_t ef = (size_t)i0 + (size_t)nfx * (j + (size_t)nfy * k);
-    const int a0 = min(i0 >> 1, ncx - 2), b = min(j >> 1, ncy - 2), c = min(k >> 1, ncz - 2);
-    const size_t cplane = (size_t)ncx * ncy;
+    const int a0 = min(i0 >> 1, ncx - 2), b = min(j >> 1, ncy - 2), c = min(kp >> 1, ncz - 2);
+    const size_t cplane = (size_t)ncx * ncy, fplane = (size_t)nfx * nfy;
     const T *e00 = e + (size_t)c * cplane + (size_t)b * ncx + a0;   // coarse (a0, b, c)
-    V xv = *reinterpret_cast<const V *>(x + ef);
+    bool ok[2];
+    size_t ef[2];
+    V xv[2];
+    int8_t ty[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = kp + h;
+        ok[h] = k >= 1 && k <= nfz - 2;
+        ef[h] = (size_t)i0 + (size_t)nfx * j + (size_t)(ok[h] ? k : 1) * fplane;
+        xv[h] = *reinterpret_cast<const V *>(x + ef[h]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ty[h][u] = type_f[ef[h] + min(u, nv - 1)];
+    }
     const V q00 = *reinterpret_cast<const V *>(e00);
     const V q10 = *reinterpret_cast<const V *>(e00 + ncx);
     const V q01 = *reinterpret_cast<const V *>(e00 + cplane);
     const V q11 = *reinterpret_cast<const V *>(e00 + cplane + ncx);
     const V wxv = *reinterpret_cast<const V *>(ax.pw + i0);
-    int8_t ty[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) ty[u] = type_f[ef + min(u, nv - 1)];
-    const T wy = ay.pw[j], wz = az.pw[k];
-    const T c00 = (T(1) - wz) * (T(1) - wy), c10 = (T(1) - wz) * wy, c01 = wz * (T(1) - wy), c11 = wz * wy;
-    const T ryz[4] = {c00 * q00.x + c10 * q10.x + c01 * q01.x + c11 * q11.x,
-                      c00 * q00.y + c10 * q10.y + c01 * q01.y + c11 * q11.y,
-                      c00 * q00.z + c10 * q10.z + c01 * q01.z + c11 * q11.z,
-                      c00 * q00.w + c10 * q10.w + c01 * q01.w + c11 * q11.w};
+    const T wy = ay.pw[j];
+    const V lo = (T(1) - wy) * q00 + wy * q10, hi = (T(1) - wy) * q01 + wy * q11;   // y, coarse planes c, c + 1
     const T wx[4] = {wxv.x, wxv.y, wxv.z, wxv.w};
-    T add[4];
-    bool m[4];
-    bool all = nv == 4;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int d = min((i0 + u) >> 1, ncx - 2) - a0;   // 0 .. 2
-        const T lo = d == 0 ? ryz[0] : (d == 1 ? ryz[1] : ryz[2]);
-        const T hi = d == 0 ? ryz[1] : (d == 1 ? ryz[2] : ryz[3]);
-        add[u] = (T(1) - wx[u]) * lo + wx[u] * hi;
-        m[u] = u < nv && unknown(ty[u]);
-        all = all && m[u];
-    }
-    if (all) {
-        xv.x += add[0];
-        xv.y += add[1];
-        xv.z += add[2];
-        xv.w += add[3];
-        *reinterpret_cast<V *>(x + ef) = xv;
-    } else {
+    for (int h = 0; h < 2; ++h) {
+        if (!ok[h]) continue;
+        const T wz = az.pw[kp + h];
+        const V r4 = (T(1) - wz) * lo + wz * hi;
+        const T ryz[4] = {r4.x, r4.y, r4.z, r4.w};
+        T add[4];
+        bool m[4];
+        bool all = nv == 4;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (m[u]) x[ef + u] += add[u];
+        for (int u = 0; u < 4; ++u) {
+            const int d = min((i0 + u) >> 1, ncx - 2) - a0;   // 0 .. 2
+            const T l = d == 0 ? ryz[0] : (d == 1 ? ryz[1] : ryz[2]);
+            const T r = d == 0 ? ryz[1] : (d == 1 ? ryz[2] : ryz[3]);
+            add[u] = (T(1) - wx[u]) * l + wx[u] * r;
+            m[u] = u < nv && unknown(ty[h][u]);
+            all = all && m[u];
+        }
+        V xo = xv[h];
+        if (all) {
+            xo.x += add[0];
+            xo.y += add[1];
+            xo.z += add[2];
+            xo.w += add[3];
+            *reinterpret_cast<V *>(x + ef[h]) = xo;
+        } else {
+            const T xs[4] = {xo.x, xo.y, xo.z, xo.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (m[u]) x[ef[h] + u] = xs[u] + add[u];
+        }
     }
 }
 
@@ -281,9 +300,10 @@ void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const int8_t *typ
 template <typename T>
 void launch_mg_prolong_add(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_f, const T *e, T *x)
 {
-    dim3 grid((unsigned)((t.nf[0] - 2 + 255) / 256), (unsigned)((t.nf[1] - 2 + 3) / 4), (unsigned)(t.nf[2] - 2));
-    k_mg_prolong_add<T><<<grid, dim3(64, 4), 0, s>>>(t.nf[0], t.nf[1], t.nc[0], t.nc[1], t.nc[2], t.ax[0], t.ax[1],
-                                                     t.ax[2], type_f, e, x);
+    // blockIdx.z = p covers fine planes 2p and 2p + 1 (interior planes 1 .. nf[2] - 2)
+    dim3 grid((unsigned)((t.nf[0] - 2 + 255) / 256), (unsigned)((t.nf[1] - 2 + 3) / 4), (unsigned)((t.nf[2] - 2) / 2 + 1));
+    k_mg_prolong_add<T><<<grid, dim3(64, 4), 0, s>>>(t.nf[0], t.nf[1], t.nf[2], t.nc[0], t.nc[1], t.nc[2], t.ax[0],
+                                                     t.ax[1], t.ax[2], type_f, e, x);
 }
 
 template <typename T>
