@@ -658,6 +658,12 @@ void enqueue_iteration(cps_solver *s, Vecs<T> &V, TXS *xsol, const double *c1, c
 template <typename T, typename TXS>
 DevState run_iterations_enqueue(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget, const double *c1, const double *c2)
 {
+    // Iteration n is queued before the state of iteration n - 1 is read back, so the GPU
+    // does not wait for the host.  An iteration queued after the converged one still costs
+    // its launches (each kernel returns at once: about 0.25 ms at 256^3 with the multigrid
+    // preconditioner), so when the last two residuals predict that iteration n converges,
+    // its state is read before n + 1 is queued: a wrong prediction costs a short idle gap.
+    double r1 = -1.0, r2 = -1.0;    // rn2s of the last two iterations read, r1 the later
     for (int n = 0; n < budget; ++n) {
         enqueue_iteration<T, TXS>(s, V, xsol, c1, c2);
         ++s->iter_enq;
@@ -665,7 +671,16 @@ DevState run_iterations_enqueue(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget
         ck(hipEventRecord(s->ev[n & 1], s->stream));
         if (n >= 1) {
             ck(hipEventSynchronize(s->ev[(n - 1) & 1]));
-            if (s->hst[(n - 1) & 1].done) break;
+            const DevState &h = s->hst[(n - 1) & 1];
+            if (h.done) break;
+            r2 = r1;
+            r1 = h.rn2s;
+            // predicted rn2s of iteration n: r1 times the last reduction factor (at most 1),
+            // within a factor 16 of the threshold
+            if (r2 > 0.0 && r1 * std::min(1.0, r1 / r2) <= 16.0 * h.stop2) {
+                ck(hipEventSynchronize(s->ev[n & 1]));
+                if (s->hst[n & 1].done) break;
+            }
         }
     }
     return read_state(s);
