@@ -426,20 +426,28 @@ __global__ void k_pack_weights(int ci, int co, int cip, const float *__restrict_
 // ---------------------------------------------------------------------------------------
 // fine grid <-> coarse grid
 // ---------------------------------------------------------------------------------------
-// sums of g^2 and (f / 3 pi^2)^2 over all nodes (per-block partials)
-__global__ void k_scale_partial(size_t nn, const double *__restrict__ f, const double *__restrict__ g,
-                                double *__restrict__ part)
+// sums of g^2 and (f / 3 pi^2)^2 over all nodes (per-block partials; 1024 threads per
+// block, 16-byte loads: a pass over two fine-grid FP64 arrays)
+__global__ void __launch_bounds__(1024) k_scale_partial(size_t nn, const double *__restrict__ f,
+                                                        const double *__restrict__ g, double *__restrict__ part)
 {
-    __shared__ double sh[256];
+    __shared__ double sh[1024];
     const double k = 1.0 / (3.0 * M_PI * M_PI);
     double s = 0.0;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < nn; e += (size_t)gridDim.x * 256) {
-        double a = g[e], b = f[e] * k;
+    const size_t n2 = nn / 2;
+    const double2 *f2 = reinterpret_cast<const double2 *>(f), *g2 = reinterpret_cast<const double2 *>(g);
+    for (size_t e = (size_t)blockIdx.x * 1024 + threadIdx.x; e < n2; e += (size_t)gridDim.x * 1024) {
+        const double2 a = g2[e], b = f2[e];
+        const double b0 = b.x * k, b1 = b.y * k;
+        s += (a.x * a.x + b0 * b0) + (a.y * a.y + b1 * b1);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (nn & 1)) {
+        const double a = g[nn - 1], b = f[nn - 1] * k;
         s += a * a + b * b;
     }
     sh[threadIdx.x] = s;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = 512; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
@@ -609,7 +617,17 @@ void launch_conv(cps_model *m, int n, int V, int Cin, int Cout, const bf16 *X, c
 {
     const int groups = Cout / 16;
     int NG = (groups % 4 == 0) ? 4 : (groups % 3 == 0) ? 3 : (groups % 2 == 0) ? 2 : 1;
-    dim3 grid(nblk((size_t)((V + 15) / 16) * 64), groups / NG);
+    // A wavefront computes NG groups of 16 output channels from one load of its inputs.  On
+    // the coarse levels (few voxels) that leaves most of the GPU idle, so there each
+    // wavefront takes fewer groups and more blocks share the work (every output's sum runs
+    // in the same order either way).
+    const unsigned vblk = nblk((size_t)((V + 15) / 16) * 64);
+    while (NG > 1 && (size_t)vblk * (groups / NG) < 1024) {
+        int ng = NG - 1;
+        while (groups % ng) --ng;
+        NG = ng;
+    }
+    dim3 grid(vblk, groups / NG);
     hipStream_t s = m->stream;
 #define CONV(NGv)                                                                                                    \
     if (NG == NGv) {                                                                                                 \
@@ -894,7 +912,7 @@ int cps_model_restrict(cps_model *m, cps_solver *s, const double *u, float *inpu
     if (nx - 2 != 4 * nc || ny - 2 != 4 * nc || nz - 2 != 4 * nc || m->spec.in_ch != 3) return CPS_EINVAL;
     try {
         const size_t nn = (size_t)nx * ny * nz;
-        k_scale_partial<<<256, 256, 0, m->stream>>>(nn, f, g, m->lpart);
+        k_scale_partial<<<256, 1024, 0, m->stream>>>(nn, f, g, m->lpart);
         k_scale_final<<<1, 64, 0, m->stream>>>(256, nn, m->lpart, m->sig);
         k_restrict<<<nblk((size_t)nc * nc * nc), 256, 0, m->stream>>>(nx, ny, nc, f, phi, g, m->sig, inputs);
         if (u && target) k_restrict_u<<<nblk((size_t)nc * nc * nc), 256, 0, m->stream>>>(nx, ny, nc, u, m->sig, target);
