@@ -76,3 +76,24 @@ def conv3_bwd(inp, W, dout):
 
 def bf16(v):
     return _L().onet_bf16(float(v))
+
+
+LAYERS = ("E0a", "E0b", "E1a", "E1b", "E2a", "E2b", "E3a", "E3b", "D2a", "D2b", "D1a", "D1b", "D0a", "D0b")
+
+
+def layer_slices(ch=(16, 32, 48, 64), cin=3):
+    """(name, slice) of every parameter tensor in the flat layout of net_oracle.c: per 3x3x3
+    layer its weights W[co][ci][3][3][3] then its bias b[co], then the head's c0 weights and
+    its bias.  Decoder layer D_l a takes [upsampled level l + 1, skip of level l]."""
+    dims = [(cin, ch[0]), (ch[0], ch[0]), (ch[0], ch[1]), (ch[1], ch[1]), (ch[1], ch[2]), (ch[2], ch[2]),
+            (ch[2], ch[3]), (ch[3], ch[3]), (ch[3] + ch[2], ch[2]), (ch[2], ch[2]), (ch[2] + ch[1], ch[1]),
+            (ch[1], ch[1]), (ch[1] + ch[0], ch[0]), (ch[0], ch[0])]
+    out, o = [], 0
+    for name, (ci, co) in zip(LAYERS, dims):
+        out.append((name + ".W", slice(o, o + co * ci * 27)))
+        o += co * ci * 27
+        out.append((name + ".b", slice(o, o + co)))
+        o += co
+    out.append(("head.W", slice(o, o + ch[0])))
+    out.append(("head.b", slice(o + ch[0], o + ch[0] + 1)))
+    return out

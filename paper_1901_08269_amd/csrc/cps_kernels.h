@@ -15,7 +15,6 @@ struct Launch {
     hipStream_t stream;
     const uint32_t *skip;
     double *partials;   // >= 2 doubles per block of the largest launch
-    unsigned *ticket;   // one counter, 0 between launches
 };
 
 // sweeps.hip

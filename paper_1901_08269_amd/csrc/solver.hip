@@ -98,7 +98,6 @@ struct cps_solver {
     float *irr_val32 = nullptr, *irr_k32 = nullptr, *irr_bd32 = nullptr;
     double *rhs = nullptr;
     double *partials = nullptr;
-    unsigned *ticket = nullptr;
     DevState *st = nullptr;
     int *dflag = nullptr;
     DevState *hst = nullptr;      // pinned, 2 slots
@@ -136,7 +135,7 @@ struct cps_solver {
     };
     std::vector<Alloc> allocs;    // device blocks owned by this solver
 
-    Launch launch() const { return Launch{g, stream, skip, partials, ticket}; }
+    Launch launch() const { return Launch{g, stream, skip, partials}; }
     Coef<double> cf64() const
     {
         Coef<double> c;
@@ -329,25 +328,18 @@ Tiling make_tiling(int nx, int ny, int nz, int tw, int ty, int target_blocks, in
 // measured best at 256^3 (1024 blocks, 43.0 us per FP32 sweep; 8 chunks 51.4 us, 32 chunks
 // 47.5 us) and at 512^3.  Fewer chunks leave wavefronts idle; more chunks re-read more halo
 // planes and put the blocks in more than one round.
-#ifndef CPS_ROW_ZCHUNKS
-#define CPS_ROW_ZCHUNKS 16
-#endif
+constexpr int ROW_ZCHUNKS = 16;
 // z-chunks of the vectorised B apply and vector updates (each at least 4 planes; 8 and 32
 // measured the same at 256^3)
-#ifndef CPS_APPLY_ZCHUNKS
-#define CPS_APPLY_ZCHUNKS 16
-#endif
-#ifndef CPS_FLAT_BLOCKS
-#define CPS_FLAT_BLOCKS 4096
-#endif
+constexpr int APPLY_ZCHUNKS = 16;
+// grid-stride kernels over all nodes (fills, copies, restart) use at most this many blocks
+constexpr int FLAT_BLOCKS = 4096;
 
-// coarse = true (a coarse multigrid level): the sweep tiling aims at CPS_COARSE_TILES tiles
+// coarse = true (a coarse multigrid level): the sweep tiling aims at COARSE_TILES tiles
 // of at least one plane each, since a small grid's sweep is bound by the latency of its
 // z-march rather than by bandwidth (spheres8 256^3, mixed multigrid solve: 1024 tiles
 // 25.1 ms, 512 25.2 ms, 2048 25.6 ms)
-#ifndef CPS_COARSE_TILES
-#define CPS_COARSE_TILES 1024
-#endif
+constexpr int COARSE_TILES = 1024;
 Geom make_geom(int nx, int ny, int nz, bool coarse = false)
 {
     Geom g{};
@@ -355,7 +347,7 @@ Geom make_geom(int nx, int ny, int nz, bool coarse = false)
     g.W = (nx + 31) / 32;
     {
         const int per_plane = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY - 1) / TY);
-        g.ta = make_tiling(nx, ny, nz, 4 * TX, TY, per_plane * CPS_APPLY_ZCHUNKS, 4);
+        g.ta = make_tiling(nx, ny, nz, 4 * TX, TY, per_plane * APPLY_ZCHUNKS, 4);
     }
     // a coarse level whose rows need at most 32 lanes packs 64 / 2^lg rows into a wavefront
     g.lg = 6;
@@ -363,11 +355,11 @@ Geom make_geom(int nx, int ny, int nz, bool coarse = false)
         while (g.lg > 3 && 4 * (1 << (g.lg - 1)) >= nx - 2) --g.lg;
     {
         const int per_plane = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY * RPW - 1) / (TY * RPW));
-        g.tr = coarse ? make_tiling(nx, ny, nz, 4 << g.lg, TY * RPW * (TX >> g.lg), CPS_COARSE_TILES, 1)
-                      : make_tiling(nx, ny, nz, 4 * TX, TY * RPW, per_plane * CPS_ROW_ZCHUNKS, 4);
+        g.tr = coarse ? make_tiling(nx, ny, nz, 4 << g.lg, TY * RPW * (TX >> g.lg), COARSE_TILES, 1)
+                      : make_tiling(nx, ny, nz, 4 * TX, TY * RPW, per_plane * ROW_ZCHUNKS, 4);
     }
     size_t nn = (size_t)nx * ny * nz;
-    g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, CPS_FLAT_BLOCKS);
+    g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, FLAT_BLOCKS);
     return g;
 }
 
@@ -551,7 +543,7 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
     T *R = V[0], *A = V[1], *B = V[2];
     const T *Z;
     if constexpr (sizeof(T) == 8) Z = s->mg_zero64; else Z = s->mg_zero32;
-    const Launch L{Lv.g, s->stream, Lv.skip, s->partials, s->ticket};
+    const Launch L{Lv.g, s->stream, Lv.skip, s->partials};
     const Coef<T> cf = mg_coef<T>(Lv);
     const Irr<T> ir = mg_irr<T>(Lv);
     if (l + 1 == (int)s->mg.size()) {
@@ -1255,8 +1247,6 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         size_t maxblk = (size_t)std::max({s->g.ta.nblk, s->g.tr.nblk, s->g.nflat}) +
                         (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
         s->partials = dalloc<double>(s, 2 * maxblk);
-        s->ticket = dalloc<unsigned>(s, 1);
-        launch_fill<unsigned>(s->stream, 1, s->ticket, 0u);
         s->st = dalloc<DevState>(s, 1);
         ck(hipMemsetAsync(s->st, 0, sizeof(DevState), s->stream));
         s->rhs = dalloc<double>(s, s->nn);

@@ -783,7 +783,7 @@ __device__ __forceinline__ void store16(T *p, const T (&v)[Vec16<T>::n])
 // (re)start: r0 = r, p = v = 0, rho = (r, r); the recursive norm starts from the true one
 template <typename T>
 __global__ void __launch_bounds__(NT) k_restart(Geom g, const T *__restrict__ r, T *__restrict__ r0, T *__restrict__ p,
-                                                T *__restrict__ v, DevState *st, double *partials, unsigned *ticket,
+                                                T *__restrict__ v, DevState *st, double *partials,
                                                 int nblocks)
 {
     constexpr int VN = Vec16<T>::n;
@@ -975,7 +975,7 @@ template <typename T>
 void launch_restart(const Launch &L, const Irr<T> &ir, const T *r, T *r0, T *p, T *v, DevState *st)
 {
     int nb = L.g.nflat;
-    k_restart<T><<<dim3(nb), tile_block(), 0, L.stream>>>(L.g, r, r0, p, v, st, L.partials, L.ticket, nb);
+    k_restart<T><<<dim3(nb), tile_block(), 0, L.stream>>>(L.g, r, r0, p, v, st, L.partials, nb);
     finalize<FIN_RESTART>(L, nb, st);
 }
 

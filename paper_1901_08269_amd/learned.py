@@ -331,26 +331,6 @@ def load_default(N):
     return WarmStart(N, path)
 
 
-def smoke():
-    """One forward/backward step of the network on cuda:0, checked against the CPU oracle."""
-    import torch
-
-    import oracle.net as onet
-    nc, B = 8, 2
-    m = Model(nc, batch=B, seed=3)
-    rng = np.random.Generator(np.random.PCG64(5))
-    inp = torch.tensor(rng.standard_normal((B, 3, nc, nc, nc)), dtype=torch.float32, device="cuda")
-    tgt = torch.tensor(rng.standard_normal((B, nc, nc, nc)), dtype=torch.float32, device="cuda")
-    loss = m.train_step(inp, tgt, update=False)
-    w, g = m.params(grads=True)
-    loss_ref, _, g_ref = onet.run(w.astype(np.float64), inp.cpu().numpy().astype(np.float64),
-                                  tgt.cpu().numpy().astype(np.float64), None, ch=CHANNELS, bf16=True)
-    rel = float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
-    print(f"smoke: network loss {loss:.6e} (oracle {loss_ref:.6e}), gradient rel. difference {rel:.2e}")
-    assert abs(loss - loss_ref) <= 1e-2 * abs(loss_ref) and rel <= 5e-2
-    m.close()
-
-
 def gain_report(rows):
     """Mean, median and range of the iterations the warm start saves over a zero start."""
     iz = np.array([r["iters_zero"] for r in rows])

@@ -25,6 +25,15 @@ def _batch(nc, B, seed):
     return inp, tgt, msk
 
 
+# Bars for the BF16 network (both sides round weights, inputs, stored activations and the
+# gradient entering each layer's backward pass to BF16 at the same places; they differ in
+# FP32 vs FP64 accumulation and its order, which can move a stored BF16 value by one unit of
+# its last place, 2^-8 relative): the prediction's and each parameter tensor's gradient's
+# max-abs difference relative to that tensor's max.
+PRED_BAR = 1e-2
+GRAD_BAR = 2e-2
+
+
 @pytest.mark.parametrize("nc,B", [(8, 2), (16, 1)])
 def test_forward_backward_vs_oracle(nc, B):
     print(f"[case] net nc={nc} B={B}", flush=True)
@@ -33,18 +42,52 @@ def test_forward_backward_vs_oracle(nc, B):
     loss = m.train_step(inp, tgt, msk, update=False)
     pred = m.forward(inp).cpu().numpy()
     w, g = m.params(grads=True)
+    assert onet.param_count(CH, 3) == m.nparam
     loss_ref, pred_ref, g_ref = onet.run(w.astype(np.float64), inp.cpu().numpy().astype(np.float64),
                                          tgt.cpu().numpy().astype(np.float64), msk.cpu().numpy().astype(np.float64),
                                          ch=CH, bf16=True)
-    rel_pred = np.linalg.norm(pred - pred_ref) / np.linalg.norm(pred_ref)
-    rel_grad = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
-    print(f"loss {loss:.6e} / {loss_ref:.6e}; pred rel {rel_pred:.2e}; grad rel {rel_grad:.2e}")
+    rel_pred = np.max(np.abs(pred - pred_ref)) / np.max(np.abs(pred_ref))
+    print(f"loss {loss:.6e} / {loss_ref:.6e}; prediction max rel {rel_pred:.2e}")
     assert abs(loss - loss_ref) <= 2e-3 * abs(loss_ref)
-    assert rel_pred <= 5e-3
-    assert rel_grad <= 2e-2
-    # every layer's gradient, not just the total
-    L = onet.param_count(CH, 3)
-    assert L == m.nparam
+    assert rel_pred <= PRED_BAR
+    # every parameter tensor's gradient on its own scale
+    worst = 0.0
+    for name, sl in onet.layer_slices(CH, 3):
+        ref = g_ref[sl]
+        err = float(np.max(np.abs(g[sl] - ref)) / np.max(np.abs(ref)))
+        print(f"  {name:7s} {sl.stop - sl.start:7d} params  grad max rel {err:.2e}")
+        assert np.max(np.abs(ref)) > 0.0, name
+        worst = max(worst, err)
+        assert err <= GRAD_BAR, name
+    print(f"worst tensor {worst:.2e}")
+
+
+def test_adam_steps_vs_oracle():
+    """Two training steps with the Adam update: the parameters after each step against the
+    oracle's Adam (Kingma & Ba, Algorithm 1) applied to the same starting parameters and the
+    gradients the library reports for each step."""
+    import oracle.warmstart as ows
+    print("[case] adam two steps nc=8", flush=True)
+    m = learned.Model(8, batch=2, seed=5)
+    inp, tgt, msk = _batch(8, 2, 13)
+    w0 = m.params().astype(np.float64)
+    lr = 1e-3
+    ws, gs = [], []
+    for _ in range(2):
+        m.train_step(inp, tgt, msk, lr=lr, update=True)
+        w, g = m.params(grads=True)
+        ws.append(w.astype(np.float64))
+        gs.append(g.astype(np.float64))
+    refs = ows.adam(w0, gs, lr=lr)
+    for q, (w, ref) in enumerate(zip(ws, refs)):
+        err = np.abs(w - ref)
+        bar = 2e-7 * np.abs(ref) + 1e-4 * lr
+        print(f"step {q + 1}: max |w - w_ref| {err.max():.2e}, max moved {np.max(np.abs(ref - w0)):.2e}")
+        assert np.all(err <= bar)
+    # the first step moves every parameter with a clear gradient by lr (m^ = g, v^ = g^2)
+    live = np.abs(gs[0]) > 1e-5
+    assert live.sum() > 1000
+    np.testing.assert_allclose(np.abs(ws[0] - w0)[live], lr, rtol=1e-2)
 
 
 def test_training_reduces_loss_and_save_load(tmp_path):
@@ -64,24 +107,72 @@ def test_training_reduces_loss_and_save_load(tmp_path):
     assert float((p1 - p2).abs().max()) == 0.0
 
 
-def test_restrict_and_prolong():
+def test_restrict_all_channels_vs_oracle():
+    """The network input of a problem (cell means of f, phi, g with the sigma scaling, and the
+    target's cell means of u) against the oracle's restriction, every channel."""
     import torch
+    import oracle.warmstart as ows
     N = 32
+    print(f"[case] restrict N={N}", flush=True)
     w = W.sphere_sin(N, beta=1.2, r=0.2)
     S = cps.Solver.from_workload(w)
     m = learned.Model(N // 4, batch=1)
     u = torch.tensor(w.u_exact, device="cuda")
     inp, tgt, sigma = m.restrict(S, u)
-    f, g, phi = w.f, w.g, w.phi
-    k = 1.0 / (3 * np.pi ** 2)
-    sig = np.sqrt(np.mean(g ** 2 + (f * k) ** 2))
-    assert abs(sigma - sig) <= 1e-12 * sig
+    ref, sig = ows.restrict_inputs(w.f, w.phi, w.g, N // 4)
+    assert abs(sigma - sig) <= 1e-13 * sig
+    got = inp[0].cpu().numpy().astype(np.float64)
+    for c in range(3):
+        err = np.max(np.abs(got[c] - ref[c])) / np.max(np.abs(ref[c]))
+        print(f"channel {c}: max rel {err:.2e}")
+        assert err <= 2e-7          # an FP32 rounding of an FP64 mean
+    assert np.max(np.abs(ref[1])) < 1.0 and np.min(ref[1]) < 0.0 < np.max(ref[1])   # phi unclamped, both signs
+    tref = ows.restrict_target(w.u_exact, sig, N // 4)
+    assert np.max(np.abs(tgt[0].cpu().numpy() - tref)) <= 2e-7 * np.max(np.abs(tref))
 
-    def blocks(a):
-        return a[1:-1, 1:-1, 1:-1].reshape(N // 4, 4, N // 4, 4, N // 4, 4).mean(axis=(1, 3, 5))
-    np.testing.assert_allclose(inp[0, 0].cpu().numpy(), blocks(f) * k / sig, rtol=1e-5, atol=1e-6)
-    np.testing.assert_allclose(inp[0, 2].cpu().numpy(), blocks(g) / sig, rtol=1e-5, atol=1e-6)
-    np.testing.assert_allclose(tgt[0].cpu().numpy(), blocks(w.u_exact) / sig, rtol=1e-5, atol=1e-6)
+
+def test_prolong_vs_oracle():
+    """cps_model_predict = sigma x trilinear (index-space) prolongation of the network's
+    prediction: the library's u0 against the oracle's prolongation of the prediction the
+    library's forward pass gives for the same input (the kernels are deterministic)."""
+    import oracle.warmstart as ows
+    N = 32
+    print(f"[case] prolong N={N}", flush=True)
+    w = W.sphere_sin(N, beta=1.2, r=0.2)
+    S = cps.Solver.from_workload(w)
+    m = learned.Model(N // 4, batch=1, seed=4)
+    inp, _, sigma = m.restrict(S)
+    pred = m.forward(inp)[0].cpu().numpy().astype(np.float64)
+    u0 = m.predict(S).cpu().numpy()
+    ref = ows.prolong(pred, sigma, u0.shape)
+    err = np.max(np.abs(u0 - ref)) / np.max(np.abs(ref))
+    print(f"prolongation max rel {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_headline_mixed_learned_vs_oracle_samples():
+    """The benchmark path: 256^3, 8 spheres, mixed precision from the shipped network's warm
+    start.  At tol 1e-10 both residual norms meet the bound; at tol 1e-13 the solution matches
+    the FP64 oracle (solved to 1e-13) to <= 1e-9 relative max-norm on the stored samples.
+    (At 1e-10 the iteration error of this system, condition ~1e7, is ~1e-8 relative.)"""
+    from gold import samples
+    nodes, vals, umax = samples("oracle_spheres8_256.txt")
+    w = W.spheres8(256)
+    print("[case] spheres8 256 mixed + learned warm start", flush=True)
+    S = cps.Solver.from_workload(w, precision="mixed")
+    ws_ = learned.load_default(256)
+    u0 = ws_.predict(S)
+    u, st = S.solve(1e-10, u0=u0)
+    print(f"tol 1e-10: {st['iters']} iterations, alpha {st['warm_alpha']:.3f}, rel res {st['rel_residual']:.2e}")
+    assert st["rel_residual"] <= 1e-10 and st["rel_residual_jacobi"] <= 1e-10
+    assert st["warm_alpha"] > 0.0
+    rel10 = np.max(np.abs(u.reshape(-1).cpu().numpy()[nodes] - vals)) / umax
+    u, st = S.solve(1e-13, u0=u0)
+    assert st["rel_residual"] <= 1e-13 and st["rel_residual_jacobi"] <= 1e-13
+    rel = np.max(np.abs(u.reshape(-1).cpu().numpy()[nodes] - vals)) / umax
+    print(f"vs oracle samples: tol 1e-10 {rel10:.2e}, tol 1e-13 {rel:.2e} ({st['iters']} iterations)")
+    assert rel <= 1e-9
+    S.close()
 
 
 @pytest.mark.slow
