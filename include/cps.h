@@ -213,6 +213,17 @@ int cps_model_train_step(cps_model *m, const float *inputs, const float *target,
  * cell means of u / sigma as target.  The solver grid must have 4 nc interior points per
  * direction.  u, inputs, target: device pointers; sigma: host (may be NULL). */
 int cps_model_restrict(cps_model *m, cps_solver *s, const double *u, float *inputs, float *target, double *sigma);
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): cps_model_restrict with the same arguments, results
+ * and errors, that calls no allocating routine.  Its scratch (the 256 per-block partial sums of
+ * the sigma reduction and sigma itself: 257 doubles, 2 KiB) is a fixed device array of the
+ * library, one per device, kept until the process ends; the reduction uses 256 blocks at every
+ * grid size, so no size exceeds it.  Every call on a device shares that array: calls that
+ * overlap on one device (other streams, other threads) race and must be serialised by the
+ * caller.  The first call on a device looks up the array's address there; later calls only
+ * launch kernels, copy sigma out and synchronise the model's stream. */
+int cps_model_restrict_noalloc(cps_model *m, cps_solver *s, const double *u, float *inputs, float *target,
+                               double *sigma);
 /* u0 (device, nx*ny*nz FP64) = sigma * trilinear prolongation of the network's prediction
  * for the solver's problem; pass it to cps_solve as the warm start. */
 int cps_model_predict(cps_model *m, cps_solver *s, double *u0);

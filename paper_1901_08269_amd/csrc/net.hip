@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -535,6 +536,16 @@ __global__ void k_prolong(int nx, int ny, int nz, int nc, const float *__restric
 
 }  // namespace cpsnet
 
+// The sigma reduction of the restriction runs on SCALE_BLOCKS blocks whatever the grid size
+// (grid-stride loop), so its scratch has a fixed size.
+constexpr int SCALE_BLOCKS = 256;
+
+// Scratch of cps_model_restrict_noalloc: [0, SCALE_BLOCKS) per-block partial sums of the
+// sigma reduction, [SCALE_BLOCKS] sigma.  Every element is written before it is read in a
+// call, so nothing needs clearing.  Each device holds one copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for that device.
+static __device__ __align__(256) double scratch[SCALE_BLOCKS + 1];
+
 // =========================================================================================
 // model object and its C-ABI
 // =========================================================================================
@@ -567,6 +578,7 @@ struct cps_model {
     double *lpart = nullptr, *lossv = nullptr, *sig = nullptr;
     float *hpart = nullptr;
     int adam_t = 0;
+    int device = 0;             // the device current at creation (its stream's device)
     std::vector<void *> allocs;
 };
 
@@ -579,6 +591,53 @@ struct NetFail {
 void nck(hipError_t e)
 {
     if (e != hipSuccess) throw NetFail{CPS_EDEVICE};
+}
+
+inline unsigned nblk(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// Device address of `scratch` on device `dev`, looked up once per device with that device
+// current (the previous current device is restored).
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double *scratch_dev[MAX_DEVICES] = {};
+
+double *scratch_address(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) throw NetFail{CPS_EDEVICE};
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        int cur = 0;
+        nck(hipGetDevice(&cur));
+        if (cur != dev) nck(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) nck(hipSetDevice(cur));
+        if (e != hipSuccess || !p) throw NetFail{CPS_EDEVICE};
+        scratch_dev[dev] = static_cast<double *>(p);
+    }
+    return scratch_dev[dev];
+}
+
+// The network input of the solver's problem (and the target's cell means of u), with the
+// sigma reduction's partial sums in part[SCALE_BLOCKS] and sigma in sig[0] (device).
+int restrict_into(cps_model *m, cps_solver *s, const double *u, float *inputs, float *target, double *sigma,
+                  double *part, double *sig)
+{
+    const double *phi, *g, *f;
+    int nx, ny, nz;
+    void *sst;
+    cps_internal_fields(s, &phi, &g, &f, &nx, &ny, &nz, &sst);
+    const int nc = m->spec.nc;
+    if (nx - 2 != 4 * nc || ny - 2 != 4 * nc || nz - 2 != 4 * nc || m->spec.in_ch != 3) return CPS_EINVAL;
+    const size_t nn = (size_t)nx * ny * nz;
+    k_scale_partial<<<SCALE_BLOCKS, 1024, 0, m->stream>>>(nn, f, g, part);
+    k_scale_final<<<1, 64, 0, m->stream>>>(SCALE_BLOCKS, nn, part, sig);
+    k_restrict<<<nblk((size_t)nc * nc * nc), 256, 0, m->stream>>>(nx, ny, nc, f, phi, g, sig, inputs);
+    if (u && target) k_restrict_u<<<nblk((size_t)nc * nc * nc), 256, 0, m->stream>>>(nx, ny, nc, u, sig, target);
+    nck(hipGetLastError());
+    if (sigma) nck(hipMemcpyAsync(sigma, sig, sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    nck(hipStreamSynchronize(m->stream));
+    return CPS_OK;
 }
 
 template <typename T>
@@ -608,7 +667,6 @@ void layer_table(const int ch[4], int cin, LayerInfo L[NLAYER])
     }
 }
 
-inline unsigned nblk(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 int skip_of(int q) { return q == 8 ? 5 : (q == 10 ? 3 : 1); }
 
@@ -755,6 +813,7 @@ int cps_model_create(cps_model **out, const cps_model_spec *spec, void *stream)
     m->spec = *spec;
     m->stream = (hipStream_t)stream;
     try {
+        nck(hipGetDevice(&m->device));
         layer_table(spec->channels, spec->in_ch, m->L);
         m->head_off = m->L[NLAYER - 1].off + (long)m->L[NLAYER - 1].co * m->L[NLAYER - 1].ci * 27 + m->L[NLAYER - 1].co;
         m->nparam = m->head_off + spec->channels[0] + 1;
@@ -904,24 +963,23 @@ int cps_model_train_step(cps_model *m, const float *inputs, const float *target,
 int cps_model_restrict(cps_model *m, cps_solver *s, const double *u, float *inputs, float *target, double *sigma)
 {
     if (!m || !s || !inputs) return CPS_EINVAL;
-    const double *phi, *g, *f;
-    int nx, ny, nz;
-    void *sst;
-    cps_internal_fields(s, &phi, &g, &f, &nx, &ny, &nz, &sst);
-    const int nc = m->spec.nc;
-    if (nx - 2 != 4 * nc || ny - 2 != 4 * nc || nz - 2 != 4 * nc || m->spec.in_ch != 3) return CPS_EINVAL;
     try {
-        const size_t nn = (size_t)nx * ny * nz;
-        k_scale_partial<<<256, 1024, 0, m->stream>>>(nn, f, g, m->lpart);
-        k_scale_final<<<1, 64, 0, m->stream>>>(256, nn, m->lpart, m->sig);
-        k_restrict<<<nblk((size_t)nc * nc * nc), 256, 0, m->stream>>>(nx, ny, nc, f, phi, g, m->sig, inputs);
-        if (u && target) k_restrict_u<<<nblk((size_t)nc * nc * nc), 256, 0, m->stream>>>(nx, ny, nc, u, m->sig, target);
-        if (sigma) nck(hipMemcpyAsync(sigma, m->sig, sizeof(double), hipMemcpyDeviceToHost, m->stream));
-        nck(hipStreamSynchronize(m->stream));
+        return restrict_into(m, s, u, inputs, target, sigma, m->lpart, m->sig);
     } catch (NetFail &f_) {
         return f_.code;
     }
-    return CPS_OK;
+}
+
+int cps_model_restrict_noalloc(cps_model *m, cps_solver *s, const double *u, float *inputs, float *target,
+                               double *sigma)
+{
+    if (!m || !s || !inputs) return CPS_EINVAL;
+    try {
+        double *sp = scratch_address(m->device);
+        return restrict_into(m, s, u, inputs, target, sigma, sp, sp + SCALE_BLOCKS);
+    } catch (NetFail &f_) {
+        return f_.code;
+    }
 }
 
 int cps_model_predict(cps_model *m, cps_solver *s, double *u0)

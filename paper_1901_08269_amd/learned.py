@@ -48,13 +48,15 @@ def _bind(L):
     L.cps_model_forward.argtypes = [vp, vp, C.c_int32, vp]
     L.cps_model_train_step.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_int32, C.POINTER(C.c_double)]
     L.cps_model_restrict.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double)]
+    L.cps_model_restrict_noalloc.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double)]
     L.cps_model_predict.argtypes = [vp, vp, vp]
     L.cps_model_save.argtypes = [vp, C.c_char_p]
     L.cps_model_load.argtypes = [vp, C.c_char_p]
     L.cps_model_destroy.argtypes = [vp]
     L.cps_model_destroy.restype = None
     for n in ("cps_model_create", "cps_model_set_params", "cps_model_get_params", "cps_model_forward",
-              "cps_model_train_step", "cps_model_restrict", "cps_model_predict", "cps_model_save", "cps_model_load"):
+              "cps_model_train_step", "cps_model_restrict", "cps_model_restrict_noalloc", "cps_model_predict",
+              "cps_model_save", "cps_model_load"):
         getattr(L, n).restype = C.c_int
     L._net_bound = True
     return L
@@ -128,14 +130,21 @@ class Model:
                                              int(update), C.byref(loss)), "train_step")
         return loss.value
 
-    def restrict(self, solver, u=None):
+    def restrict(self, solver, u=None, out=None, noalloc=False):
+        """Network input (and with u the target) of the solver's problem, and sigma.  out:
+        optional preallocated (inputs, target) tensors; noalloc selects the entry point that
+        allocates nothing (cps_model_restrict_noalloc)."""
         torch = self.torch
         nc = self.nc
-        inp = torch.zeros((1, 3) + (nc,) * 3, dtype=torch.float32, device="cuda")
-        tgt = torch.zeros((1,) + (nc,) * 3, dtype=torch.float32, device="cuda") if u is not None else None
+        if out is None:
+            inp = torch.zeros((1, 3) + (nc,) * 3, dtype=torch.float32, device="cuda")
+            tgt = torch.zeros((1,) + (nc,) * 3, dtype=torch.float32, device="cuda") if u is not None else None
+        else:
+            inp, tgt = out
         sig = C.c_double()
-        self._ck(self.L.cps_model_restrict(self.h, solver.h, _p(u) if u is not None else None, _p(inp), _p(tgt),
-                                           C.byref(sig)), "restrict")
+        fn = self.L.cps_model_restrict_noalloc if noalloc else self.L.cps_model_restrict
+        self._ck(fn(self.h, solver.h, _p(u) if u is not None else None, _p(inp), _p(tgt), C.byref(sig)),
+                 "restrict")
         return inp, tgt, sig.value
 
     def predict(self, solver, w=None):
