@@ -86,6 +86,28 @@ template <typename T>
 void launch_mg_coarsest(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf, const int8_t *type,
                         const int *irr_map, const T *k7, const T *rho, T *out, int steps, const T *c1, const T *c2,
                         const DevState *st);
+// Several Chebyshev-Jacobi steps on a coarse level in one launch (temporal blocking): each
+// workgroup owns an MG_TB_TS^3 tile of interior nodes, loads the tile and MG_TB_H layers
+// around it into LDS and runs the steps there, recomputing the layers around the tile (the
+// outermost layer's values go stale one layer per step, never reaching the tile).  Steps
+// S.c1[s], S.c2[s], s < S.n <= MG_TB_H (one fewer with a residual), from x = xin with x_{-1}
+// = 0 (the step before is either the level's first step from 0, or the first step of a pass,
+// whose c1 is 0).  Writes x at the unknown nodes of xout (!= xin) and, with rout, r = rho - K x
+// there.
+constexpr int MG_TB_TS = 8;
+constexpr int MG_TB_H = 4;
+constexpr int MG_TB_THREADS = 1024;
+// coarse levels with at most this many interior points smooth with temporal blocking
+constexpr long long MG_TB_MAX_POINTS = 300000;
+template <typename T>
+struct MgSteps {
+    int n;
+    T c1[MG_TB_H], c2[MG_TB_H];
+};
+template <typename T>
+void launch_mg_smooth_tb(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf, const int8_t *type,
+                         const int *irr_map, const T *k7, const T *rho, const T *xin, T *xout, T *rout,
+                         const MgSteps<T> &S, const DevState *st);
 // map[nodes[r]] = r for the nirr irregular rows
 void launch_mg_irr_map(hipStream_t s, int nirr, const int *nodes, int *map);
 // x += P e at the unknown fine nodes (type_f)

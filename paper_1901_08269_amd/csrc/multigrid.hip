@@ -279,6 +279,111 @@ __global__ void __launch_bounds__(MG_LDS_THREADS) k_mg_coarsest(int nx, int ny, 
         if (act[u]) out[node_of(t + MG_LDS_THREADS * u)] = xs[t + MG_LDS_THREADS * u];
 }
 
+// Temporally blocked Chebyshev-Jacobi steps on a coarse level (launch_mg_smooth_tb).  The
+// block's extended tile has E = MG_TB_TS + 2 MG_TB_H nodes per direction starting at node
+// 1 + MG_TB_TS blockIdx - MG_TB_H; point q = t + MG_TB_THREADS u of it (x fastest) belongs to
+// thread t.  x_k of the extended tile lives in LDS (0 at nodes that are not unknowns and at
+// nodes outside the grid's interior); each thread keeps x_{k-1}, rho and the K row of its
+// points in registers (the regular rows' from the 1D tables, an irregular row's stored
+// Shortley-Weller row).  A neighbour outside the extended tile reads 0: that error enters the
+// outermost layer at the first step and moves in one layer per step, so after s <= MG_TB_H
+// steps the tile (and, for s < MG_TB_H, its first neighbour layer, which the residual reads)
+// holds exactly the values of s single sweeps.  The arithmetic is that of the single sweep
+// (k_cheb4m): K x = diag x + the six neighbour terms, x_{k+1} = x_k + c1 (x_k - x_{k-1}) +
+// c2 (rho - K x) / diag.  The levels this runs on are small enough that a sweep is bound by
+// its launch and latency, not by bandwidth: the redundant work on the layers around the tile
+// costs less than the launches it saves.
+constexpr int MG_TB_E = MG_TB_TS + 2 * MG_TB_H;
+constexpr int MG_TB_E3 = MG_TB_E * MG_TB_E * MG_TB_E;
+constexpr int MG_TB_NPT = (MG_TB_E3 + MG_TB_THREADS - 1) / MG_TB_THREADS;
+
+template <typename T, bool RES>
+__global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, int nz, Coef<T> cf,
+                                                                const int8_t *__restrict__ type,
+                                                                const int *__restrict__ irr_map,
+                                                                const T *__restrict__ k7, const T *__restrict__ rho,
+                                                                const T *__restrict__ xin, T *__restrict__ xout,
+                                                                T *__restrict__ rout, MgSteps<T> S, const DevState *st)
+{
+    constexpr int E = MG_TB_E, E2 = E * E, NPT = MG_TB_NPT;
+    __shared__ T xs[MG_TB_E3];
+    if (st && st->done) return;
+    const int t = (int)threadIdx.x;
+    const int o[3] = {1 + MG_TB_TS * (int)blockIdx.x - MG_TB_H, 1 + MG_TB_TS * (int)blockIdx.y - MG_TB_H,
+                      1 + MG_TB_TS * (int)blockIdx.z - MG_TB_H};
+    T xp[NPT], rh[NPT], kd[NPT], ko[NPT][6];
+    bool act[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        const int q = t + MG_TB_THREADS * u;
+        const int ii = q % E, jj = (q / E) % E, kk = q / E2;
+        const int i = o[0] + ii, j = o[1] + jj, k = o[2] + kk;
+        const bool in = q < MG_TB_E3 && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2;
+        const size_t e = in ? (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k) : 0;
+        const int8_t ty = in ? type[e] : (int8_t)0;
+        act[u] = ty == 1 || ty == 2;
+        if (q < MG_TB_E3) xs[q] = act[u] ? xin[e] : T(0);
+        rh[u] = act[u] ? rho[e] : T(0);
+        xp[u] = T(0);
+        kd[u] = T(1);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) ko[u][v] = T(0);
+        if (ty == 2) {
+            const T *r = k7 + 7 * (size_t)irr_map[e];
+            kd[u] = r[0];
+#pragma unroll
+            for (int v = 0; v < 6; ++v) ko[u][v] = r[1 + v];
+        } else if (ty == 1) {
+            const T *cx = cf.c[0] + 8 * i, *cy = cf.c[1] + 8 * j, *cz = cf.c[2] + 8 * k;
+            kd[u] = (cx[6] + cy[6]) + cz[6];
+            ko[u][0] = cx[5]; ko[u][1] = cx[7];
+            ko[u][2] = cy[5]; ko[u][3] = cy[7];
+            ko[u][4] = cz[5]; ko[u][5] = cz[7];
+        }
+    }
+    __syncthreads();
+    // K x at point q of the LDS tile (neighbours outside the extended tile read 0)
+    auto kx_of = [&](int u, int q, T x0) {
+        const int ii = q % E, jj = (q / E) % E, kk = q / E2;
+        const T w = ii > 0 ? xs[q - 1] : T(0), ea = ii < E - 1 ? xs[q + 1] : T(0);
+        const T sv = jj > 0 ? xs[q - E] : T(0), nv = jj < E - 1 ? xs[q + E] : T(0);
+        const T mv = kk > 0 ? xs[q - E2] : T(0), uv = kk < E - 1 ? xs[q + E2] : T(0);
+        return kd[u] * x0 + ko[u][0] * w + ko[u][1] * ea + ko[u][2] * sv + ko[u][3] * nv + ko[u][4] * mv +
+               ko[u][5] * uv;
+    };
+    for (int s = 0; s < S.n; ++s) {
+        const T c1 = S.c1[s], c2 = S.c2[s];
+        T xn[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int q = t + MG_TB_THREADS * u;
+            xn[u] = T(0);
+            if (!act[u]) continue;
+            const T x0 = xs[q];
+            const T kx = kx_of(u, q, x0);
+            xn[u] = x0 + c1 * (x0 - xp[u]) + c2 * (rh[u] - kx) / kd[u];
+            xp[u] = x0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NPT; ++u)
+            if (act[u]) xs[t + MG_TB_THREADS * u] = xn[u];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        const int q = t + MG_TB_THREADS * u;
+        const int ii = q % E, jj = (q / E) % E, kk = q / E2;
+        if (!act[u] || ii < MG_TB_H || ii >= MG_TB_H + MG_TB_TS || jj < MG_TB_H || jj >= MG_TB_H + MG_TB_TS ||
+            kk < MG_TB_H || kk >= MG_TB_H + MG_TB_TS)
+            continue;
+        const size_t e = (size_t)(o[0] + ii) + (size_t)nx * ((size_t)(o[1] + jj) + (size_t)ny * (o[2] + kk));
+        const T x0 = xs[q];
+        xout[e] = x0;
+        if (RES) rout[e] = rh[u] - kx_of(u, q, x0);
+    }
+}
+
 // map[node] = irregular row of the node (the rows list nodes in increasing order)
 __global__ void k_mg_irr_map(int nirr, const int *__restrict__ nodes, int *__restrict__ map)
 {
@@ -314,6 +419,21 @@ void launch_mg_coarsest(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf
     k_mg_coarsest<T><<<1, MG_LDS_THREADS, 0, s>>>(nx, ny, nz, cf, type, irr_map, k7, rho, out, steps, c1, c2, st);
 }
 
+template <typename T>
+void launch_mg_smooth_tb(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf, const int8_t *type,
+                         const int *irr_map, const T *k7, const T *rho, const T *xin, T *xout, T *rout,
+                         const MgSteps<T> &S, const DevState *st)
+{
+    const dim3 grid((unsigned)((nx - 2 + MG_TB_TS - 1) / MG_TB_TS), (unsigned)((ny - 2 + MG_TB_TS - 1) / MG_TB_TS),
+                    (unsigned)((nz - 2 + MG_TB_TS - 1) / MG_TB_TS));
+    if (rout)
+        k_mg_smooth_tb<T, true><<<grid, MG_TB_THREADS, 0, s>>>(nx, ny, nz, cf, type, irr_map, k7, rho, xin, xout, rout,
+                                                               S, st);
+    else
+        k_mg_smooth_tb<T, false><<<grid, MG_TB_THREADS, 0, s>>>(nx, ny, nz, cf, type, irr_map, k7, rho, xin, xout,
+                                                                nullptr, S, st);
+}
+
 void launch_mg_irr_map(hipStream_t s, int nirr, const int *nodes, int *map)
 {
     if (nirr > 0) k_mg_irr_map<<<(nirr + 255) / 256, 256, 0, s>>>(nirr, nodes, map);
@@ -325,6 +445,12 @@ template void launch_mg_coarsest<double>(hipStream_t, int, int, int, const Coef<
 template void launch_mg_coarsest<float>(hipStream_t, int, int, int, const Coef<float> &, const int8_t *, const int *,
                                         const float *, const float *, float *, int, const float *, const float *,
                                         const DevState *);
+template void launch_mg_smooth_tb<double>(hipStream_t, int, int, int, const Coef<double> &, const int8_t *,
+                                          const int *, const double *, const double *, const double *, double *,
+                                          double *, const MgSteps<double> &, const DevState *);
+template void launch_mg_smooth_tb<float>(hipStream_t, int, int, int, const Coef<float> &, const int8_t *, const int *,
+                                         const float *, const float *, const float *, float *, float *,
+                                         const MgSteps<float> &, const DevState *);
 template void launch_mg_restrict<double>(hipStream_t, const MgTransfer<double> &, const int8_t *, const double *,
                                          double *, const MgFirst<double> &);
 template void launch_mg_restrict<float>(hipStream_t, const MgTransfer<float> &, const int8_t *, const float *, float *,

@@ -70,8 +70,8 @@ struct MgLevel {
     bool lds = false;           // the coarsest level, solved in one workgroup
     MgTransfer<double> t64{};   // transfers to the next coarser level
     MgTransfer<float> t32{};
-    double *v64[3] = {nullptr, nullptr, nullptr};   // level right-hand side, two iterates
-    float *v32[3] = {nullptr, nullptr, nullptr};
+    double *v64[4] = {nullptr, nullptr, nullptr, nullptr};   // level right-hand side, two iterates, residual
+    float *v32[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 }  // namespace
@@ -444,7 +444,7 @@ void mg_alloc(cps_solver *s)
         MgLevel &Lv = s->mg[l];
         T **v;
         if constexpr (sizeof(T) == 8) v = Lv.v64; else v = Lv.v32;
-        for (int q = 0; q < 3; ++q)
+        for (int q = 0; q < 4; ++q)
             if (!v[q]) {
                 v[q] = dalloc<T>(s, Lv.nn + VEC_PAD);
                 launch_fill<T>(s->stream, Lv.nn + VEC_PAD, v[q], T(0));
@@ -532,6 +532,19 @@ MgFirst<T> mg_first(cps_solver *s, int l)
     return f;
 }
 
+// smoother steps k0 .. n - 1 (at most MG_TB_H) of a coarse level's pass, for one launch
+template <typename T>
+MgSteps<T> mg_steps(const cps_solver *s, int k0, int n)
+{
+    MgSteps<T> S{};
+    S.n = n - k0;
+    for (int q = 0; q < S.n; ++q) {
+        S.c1[q] = (T)s->mg_c1[k0 + q];
+        S.c2[q] = (T)s->mg_c2[k0 + q];
+    }
+    return S;
+}
+
 // V-cycle on coarse level l >= 1 for K_l x = rho_l (rho_l in the level's first vector and,
 // unless l is the last level, its first step x_1 in the second, both from the restriction);
 // returns the buffer that holds x.
@@ -558,6 +571,21 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
                             s->mg_cc2.data(), st, false);
     }
     const int nu = s->opt.mg_nu;
+    if (nu <= MG_TB_H && (long long)(Lv.n[0] - 2) * (Lv.n[1] - 2) * (Lv.n[2] - 2) <= MG_TB_MAX_POINTS) {
+        // each smoothing pass in one temporally blocked launch: steps 1 .. nu - 1 from the
+        // restriction's first step x_1 (in A) and the residual; after the coarse correction,
+        // steps 0 .. nu - 1 from the corrected iterate
+        T *Rr = V[3];
+        launch_mg_smooth_tb<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, A, B, Rr,
+                               mg_steps<T>(s, 1, nu), st);
+        launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), s->mg[l + 1].type, Rr, mg_vecs<T>(s->mg[l + 1])[0],
+                              mg_first<T>(s, l + 1));
+        T *e = mg_level<T>(s, l + 1, st);
+        launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.type, e, B);
+        launch_mg_smooth_tb<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, B, A, nullptr,
+                               mg_steps<T>(s, 0, nu), st);
+        return A;
+    }
     T *x = mg_smooth<T>(s, l, L, cf, ir, R, nullptr, Z, A, B, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
     T *r = (x == A) ? B : A;
     launch_resid<T>(L, cf, ir, x, R, r, st, next_rev(s, l));
