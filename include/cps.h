@@ -69,7 +69,8 @@ typedef struct cps_options {
     int32_t max_restarts;  /* restarts after breakdown or a failed true-residual check */
     int32_t device_ptrs;   /* 1: array arguments are device pointers */
     int32_t kernel_timing; /* n > 0: time every n-th run of consecutive preconditioner sweeps
-                            * on the problem's grid that read an x_{k-1}, with one pair of HIP
+                            * on the problem's grid (multigrid: a post-smoothing pass;
+                            * Chebyshev: steps 2 .. inner_iters - 1), with one pair of HIP
                             * events per run (stats; each pair adds a few microseconds); runs
                             * queued after convergence are left out; 0: off */
     double inner_tol;      /* CPS_MIXED: residual reduction asked of each FP32 inner solve */
@@ -88,9 +89,9 @@ typedef struct cps_options {
      * steps on [lambda_1, lam_hi] of that grid.  The cycle is a fixed linear map of rho. */
     int32_t precond;         /* CPS_PRECOND_MULTIGRID (default) or CPS_PRECOND_CHEBYSHEV */
     int32_t mg_levels;       /* most levels, this grid included, 1..16 (default 16) */
-    int32_t mg_nu;           /* smoothing steps before and after, 1..64 (default 4) */
-    int32_t mg_coarse_steps; /* steps on the coarsest grid, 1..64 (default 16) */
-    double mg_smooth_lo;     /* lower end of the smoother's interval, in (0, lam_hi) (default 0.5) */
+    int32_t mg_nu;           /* smoothing steps before and after, 1..64 (default 2) */
+    int32_t mg_coarse_steps; /* steps on the coarsest grid, 1..64 (default 8) */
+    double mg_smooth_lo;     /* lower end of the smoother's interval, in (0, lam_hi) (default 0.2) */
 } cps_options;
 
 typedef struct cps_stats {
@@ -109,8 +110,8 @@ typedef struct cps_stats {
                                  * preconditioner sweeps (launch gaps inside a run included) */
     int64_t sweep_launches;     /* kernel_timing: number of sweeps in them */
     int64_t sweep_points;       /* interior points one sweep processes */
-    int32_t sweep_bytes_per_point; /* algorithmic bytes one timed sweep moves per point */
-    int32_t pad;
+    double sweep_bytes;         /* kernel_timing: algorithmic bytes the timed sweeps move (every
+                                 * vector a sweep reads or writes, once per interior point) */
     double warm_alpha;          /* warm start: the factor it was scaled by -- 1 if its residual is
                                  * at most ||b||_2, else argmin over alpha of ||b - alpha B u0||_2
                                  * (0 rejects it); 0 without a warm start */
@@ -119,7 +120,7 @@ typedef struct cps_stats {
 /* Fill `o` with the defaults: CPS_FP64, 24 inner iterations, max_iters 20000,
  * max_refine 40, max_restarts 5, host pointers, inner_tol 1e-4, the default Chebyshev
  * interval, null stream, no kernel timing, the multigrid preconditioner (up to 16 levels,
- * 4 + 4 smoothing steps on [0.5, lam_hi], 16 coarsest-grid steps). */
+ * 2 + 2 smoothing steps on [0.2, lam_hi], 8 coarsest-grid steps). */
 void cps_default_options(cps_options *o);
 
 /* Build the discrete problem (Secs. 2-3): classify nodes from the sign of phi (Sec. 2,
@@ -210,7 +211,8 @@ int cps_model_train_step(cps_model *m, const float *inputs, const float *target,
                          float lr, int32_t update, double *loss_out);
 /* Network input of one problem: cell means over 4^3 blocks of interior nodes of f, phi, g
  * (scaled: sigma = RMS over nodes of sqrt(g^2 + (f / 3 pi^2)^2)); with u non-NULL also the
- * cell means of u / sigma as target.  The solver grid must have 4 nc interior points per
+ * target: cell means over the same blocks of u / sigma, with g in place of u at nodes inside
+ * a body (phi <= 0), i.e. of the solution's continuation by g.  The solver grid must have 4 nc interior points per
  * direction.  u, inputs, target: device pointers; sigma: host (may be NULL). */
 int cps_model_restrict(cps_model *m, cps_solver *s, const double *u, float *inputs, float *target, double *sigma);
 /* For callers that cannot allocate device memory (code under stream capture, tight serving

@@ -20,7 +20,9 @@ smoother), so that it can be checked by eye against this definition:
   unknown (fluid interior) nodes carry values; others are 0 on every level.
 * V-cycle on level l for K_l x = rho: `nu` Chebyshev-Jacobi steps from x = 0 on the
   spectrum interval [smooth_lo, 2] of diag(K)^-1 K; residual r = rho - K_l x; x += P (V-cycle
-  on level l + 1 of R r); `nu` more steps from x.  On the coarsest level: `coarse_steps`
+  on level l + 1 of R r) at the regular unknown nodes (an irregular node, next to the body,
+  gets no coarse correction: the coarse grid sees the interface elsewhere, and its
+  interpolated correction there is what the post-smoothing must undo); `nu` more steps from x.  On the coarsest level: `coarse_steps`
   steps from 0 on [lambda_1, 2], lambda_1 = (1/3) sum_d (1 - cos(pi / (n_d - 1))).
 
 The cycle is a fixed linear map of rho, as right-preconditioned BiCGSTAB requires.
@@ -82,7 +84,7 @@ def lambda_1(shape):
 
 
 class Multigrid:
-    def __init__(self, x, y, z, phi, levels=16, nu=4, smooth_lo=0.5, coarse_steps=16, min_points=9,
+    def __init__(self, x, y, z, phi, levels=16, nu=2, smooth_lo=0.2, coarse_steps=8, min_points=9,
                  coarse_interior=4096):
         self.nu, self.smooth_lo, self.coarse_steps = nu, smooth_lo, coarse_steps
         self.lv = []
@@ -90,7 +92,8 @@ class Multigrid:
         for l in range(levels):
             P = oracle.Problem.k_only(xs[0], xs[1], xs[2], phis)
             t = P.types()
-            self.lv.append({"P": P, "x": xs, "unk": ((t == 1) | (t == 2)).astype(float), "shape": phis.shape})
+            self.lv.append({"P": P, "x": xs, "unk": ((t == 1) | (t == 2)).astype(float), "reg": (t == 1).astype(float),
+                            "shape": phis.shape})
             interior = np.prod([len(c) - 2 for c in xs])
             if l + 1 == levels or min(len(c) for c in xs) < 2 * min_points - 1 or interior <= coarse_interior:
                 break
@@ -110,7 +113,7 @@ class Multigrid:
         r = (rho - L["P"].apply_K(x)) * L["unk"]
         rc = restrict(r, L["ax"], self.lv[l + 1]["shape"])
         ec = self.vcycle(l + 1, rc)
-        x = x + prolong(ec, L["ax"]) * L["unk"]
+        x = x + prolong(ec, L["ax"]) * L["reg"]
         x = L["P"].smooth(rho, x, self.nu, self.smooth_lo, HI)
         return x * L["unk"]
 

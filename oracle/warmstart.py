@@ -10,7 +10,9 @@ written out plainly in FP64 numpy so that each can be checked by eye:
   nodes 1 + 4c ... 4 + 4c; its value is the mean over the 4^3 nodes of the block.
   sigma = sqrt(mean over ALL nodes of g^2 + (f / 3 pi^2)^2) (1 if that is 0).  Channels:
   0: mean(f) / (3 pi^2 sigma), 1: clamp(mean(phi) nc / 8, -1, 1), 2: mean(g) / sigma.
-  Target: mean(u) / sigma.  Arrays are [z][y][x], x fastest, like the node arrays.
+  Target: mean(v) / sigma with v = u where phi > 0 and v = g where phi <= 0 (the solution
+  continued into the bodies by g, which is smooth across the interface where the solution
+  jumps to 0).  Arrays are [z][y][x], x fastest, like the node arrays.
 * Prolongation of a coarse field p (one value per cell) to the fine nodes, in index space:
   along each axis, fine node i sits at coarse coordinate s = (i - 2.5) / 4 (cell c's centre
   is at fine index 2.5 + 4c), clamped to [0, nc - 1]; the value is the tensor product of
@@ -53,9 +55,10 @@ def restrict_inputs(f, phi, g, nc):
     return out, sigma
 
 
-def restrict_target(u, sigma, nc):
-    """Training target [nc]^3: the cell means of u / sigma."""
-    return block_means(u, nc) / sigma
+def restrict_target(u, phi, g, sigma, nc):
+    """Training target [nc]^3: the cell means of (u where phi > 0, else g) / sigma."""
+    v = np.where(np.asarray(phi) > 0.0, np.asarray(u, dtype=np.float64), np.asarray(g, dtype=np.float64))
+    return block_means(v, nc) / sigma
 
 
 def hat_matrix(n_fine, nc):

@@ -489,9 +489,12 @@ __global__ void k_restrict(int nx, int ny, int nc, const double *__restrict__ f,
     out[2 * nc3 + q] = (float)(sg * inv / s);
 }
 
-// target restriction: cell means of u / sigma over the same blocks (FP32 [nc^3])
-__global__ void k_restrict_u(int nx, int ny, int nc, const double *__restrict__ u, const double *__restrict__ sigma,
-                             float *__restrict__ out)
+// target restriction: cell means over the same blocks of the solution's smooth extension
+// (u at fluid nodes, g at nodes inside a body, phi <= 0), divided by sigma (FP32 [nc^3]).
+// The solution itself is 0 inside the bodies; a cell mean that mixes those zeros with the
+// fluid values interpolates badly next to the interface, where g continues u.
+__global__ void k_restrict_u(int nx, int ny, int nc, const double *__restrict__ u, const double *__restrict__ phi,
+                             const double *__restrict__ g, const double *__restrict__ sigma, float *__restrict__ out)
 {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nc * nc * nc) return;
@@ -499,8 +502,11 @@ __global__ void k_restrict_u(int nx, int ny, int nc, const double *__restrict__ 
     double s = 0.0;
     for (int dz = 0; dz < 4; ++dz)
         for (int dy = 0; dy < 4; ++dy)
-            for (int dx = 0; dx < 4; ++dx)
-                s += u[(size_t)(1 + 4 * cx + dx) + (size_t)nx * ((1 + 4 * cy + dy) + (size_t)ny * (1 + 4 * cz + dz))];
+            for (int dx = 0; dx < 4; ++dx) {
+                const size_t e =
+                    (size_t)(1 + 4 * cx + dx) + (size_t)nx * ((1 + 4 * cy + dy) + (size_t)ny * (1 + 4 * cz + dz));
+                s += phi[e] > 0.0 ? u[e] : g[e];
+            }
     out[q] = (float)(s / 64.0 / sigma[0]);
 }
 
@@ -633,7 +639,8 @@ int restrict_into(cps_model *m, cps_solver *s, const double *u, float *inputs, f
     k_scale_partial<<<SCALE_BLOCKS, 1024, 0, m->stream>>>(nn, f, g, part);
     k_scale_final<<<1, 64, 0, m->stream>>>(SCALE_BLOCKS, nn, part, sig);
     k_restrict<<<nblk((size_t)nc * nc * nc), 256, 0, m->stream>>>(nx, ny, nc, f, phi, g, sig, inputs);
-    if (u && target) k_restrict_u<<<nblk((size_t)nc * nc * nc), 256, 0, m->stream>>>(nx, ny, nc, u, sig, target);
+    if (u && target)
+        k_restrict_u<<<nblk((size_t)nc * nc * nc), 256, 0, m->stream>>>(nx, ny, nc, u, phi, g, sig, target);
     nck(hipGetLastError());
     if (sigma) nck(hipMemcpyAsync(sigma, sig, sizeof(double), hipMemcpyDeviceToHost, m->stream));
     nck(hipStreamSynchronize(m->stream));

@@ -110,6 +110,7 @@ struct cps_solver {
     std::vector<int64_t> tev_iter;  // per timed run of sweeps: the iteration it belongs to
     std::vector<char> tev_ok;       // per timed run: ran (not after the solve had converged)
     std::vector<int> tev_n;         // per timed run: sweeps in it
+    std::vector<int> tev_vec;       // per timed run: vectors its sweeps read and write, summed
     Vecs<double> v64;
     Vecs<float> v32;
     double *tmp64 = nullptr;      // user-facing staging (residual, apply, precond)
@@ -401,11 +402,11 @@ hipEvent_t timing_event(cps_solver *s)
 }
 
 // Sweep timing: a run of `nsweeps` consecutive preconditioner sweeps on the problem's grid
-// that all read an x_{k-1} (the sweep kernel's full traffic) is bracketed by one pair of
-// events, every kernel_timing-th such run (an event pair costs a few microseconds of queue
-// time, so timing is sampled; the run's time includes the launch gaps between its sweeps).
-// Returns the closing event, to be recorded after the run, or null.
-hipEvent_t timed_run_begin(cps_solver *s, int nsweeps)
+// (which together read and write `nvec` vectors) is bracketed by one pair of events, every
+// kernel_timing-th such run (an event pair costs a few microseconds of queue time, so timing
+// is sampled; the run's time includes the launch gaps between its sweeps).  Returns the
+// closing event, to be recorded after the run, or null.
+hipEvent_t timed_run_begin(cps_solver *s, int nsweeps, int nvec)
 {
     const int period = s->opt.kernel_timing;
     if (period <= 0 || nsweeps <= 0 || (s->sweep_count++ % period) != 0) return nullptr;
@@ -415,10 +416,12 @@ hipEvent_t timed_run_begin(cps_solver *s, int nsweeps)
         s->tev_iter.resize(pair + 1);
         s->tev_ok.resize(pair + 1);
         s->tev_n.resize(pair + 1);
+        s->tev_vec.resize(pair + 1);
     }
     s->tev_iter[pair] = s->iter_enq;
     s->tev_ok[pair] = 1;
     s->tev_n[pair] = nsweeps;
+    s->tev_vec[pair] = nvec;
     ck(hipEventRecord(e0, s->stream));
     return e1;
 }
@@ -503,12 +506,13 @@ T *mg_smooth(cps_solver *s, int lvl, const Launch &L, const Coef<T> &cf, const I
 {
     T *odd = x0 ? b : a, *even = x0 ? a : b;
     auto buf = [&](int j) -> T * { return j == 0 ? (x0 ? x0 : (T *)zero) : ((j & 1) ? odd : even); };
-    const int kf = std::max(k0, x0 ? 1 : 2);     // the first step with an x_{k-1}
     hipEvent_t e1 = nullptr;
     for (int k = k0; k < n; ++k) {
         const T *xm1 = (k == 0) ? nullptr : (k == 1 ? (const T *)x0 : buf(k - 1));
         T *out = (k == n - 1 && dst) ? dst : buf(k + 1);
-        if (timed && k == kf) e1 = timed_run_begin(s, n - kf);
+        // a timed pass is a whole post-smoothing pass (steps 0 .. n - 1 from x0): step 0 reads
+        // x_0 and rho and writes x_1, each later step also reads its x_{k-1}
+        if (timed && x0 && k == 0) e1 = timed_run_begin(s, n, 3 + 4 * (n - 1));
         launch_cheb<T>(L, cf, ir, buf(k), xm1, rho, out, c1[k], c2[k], st, next_rev(s, lvl));
     }
     if (e1) ck(hipEventRecord(e1, s->stream));
@@ -651,7 +655,7 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
     launch_first<T>(kind, L, cf, ir, r, ps, v, buf(1), c2[0], st);
     hipEvent_t e1 = nullptr;
     for (int k = 1; k < m; ++k) {
-        if (k == 2) e1 = timed_run_begin(s, m - 2);   // steps 2 .. m-1 read an x_{k-1}
+        if (k == 2) e1 = timed_run_begin(s, m - 2, 4 * (m - 2));   // steps 2 .. m-1 read an x_{k-1}
         launch_cheb<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), c1[k], c2[k], st,
                        next_rev(s, 0));
     }
@@ -787,21 +791,21 @@ int fill_stats(cps_solver *s, cps_stats *st, const DevState &ds, int iters, int 
     st->sweep_points = (int64_t)(s->nx - 2) * (s->ny - 2) * (s->nz - 2);
     if (s->opt.kernel_timing && s->tev_used >= 2) {
         double tot = 0.0;
-        int64_t n = 0;
+        int64_t n = 0, nvec = 0;
         for (size_t q = 0; q + 1 < s->tev_used; q += 2) {
             float ms = 0.f;
             if (!s->tev_ok[q / 2]) continue;     // sweeps queued after convergence return at once
             if (hipEventElapsedTime(&ms, s->tev[q], s->tev[q + 1]) == hipSuccess) {
                 tot += ms;
                 n += s->tev_n[q / 2];
+                nvec += s->tev_vec[q / 2];
             }
         }
         st->sweep_ms = tot;
         st->sweep_launches = n;
+        const int vb = (s->opt.precision == CPS_MIXED) ? 4 : 8;
+        st->sweep_bytes = (double)nvec * vb * (double)st->sweep_points;
     }
-    // a timed sweep reads x_k, x_{k-1}, rho and writes x_{k+1}
-    const int vb = (s->opt.precision == CPS_MIXED) ? 4 : 8;
-    st->sweep_bytes_per_point = 4 * vb;
     return status;
 }
 
@@ -1142,9 +1146,9 @@ void cps_default_options(cps_options *o)
     o->stream = nullptr;
     o->precond = CPS_PRECOND_MULTIGRID;
     o->mg_levels = MG_MAX_LEVELS;
-    o->mg_nu = 4;
-    o->mg_coarse_steps = 16;
-    o->mg_smooth_lo = 0.5;
+    o->mg_nu = 2;
+    o->mg_coarse_steps = 8;
+    o->mg_smooth_lo = 0.2;
 }
 
 const char *cps_strerror(int code)

@@ -384,7 +384,7 @@ def main(argv=None):
             rows += warm_start_gain(m, a.family, a.N, te_seeds[q:q + 25], precond=a.precond)
             log(f"  evaluated {len(rows)}/{len(te_seeds)}")
         rep = {"family": a.family, "N": a.N, "weights": os.path.basename(path), "test": a.test,
-               "precision": "mixed", "tol": 1e-10, **gain_report(rows), "rows": rows}
+               "precision": "mixed", "tol": 1e-10, "precond": a.precond, **gain_report(rows), "rows": rows}
         log(json.dumps({k: v for k, v in rep.items() if k != "rows"}))
         if a.report:
             with open(a.report, "w") as fh:
@@ -408,6 +408,7 @@ def main(argv=None):
     eval_model.load(out)
     rows = warm_start_gain(eval_model, a.family, a.N, te_seeds, precond=a.precond)
     rep = {"family": a.family, "N": a.N, "train": a.train, "test": a.test, "epochs": a.epochs, "steps": steps,
+           "precond": a.precond,
            "train_s": secs, "final_loss": hist[-1], "loss_history": hist, **gain_report(rows), "rows": rows}
     log(json.dumps({k: v for k, v in rep.items() if k not in ("rows", "loss_history")}))
     if a.report:

@@ -61,7 +61,7 @@ def _random_rho(phi_shape, types, seed):
 def test_vcycle_matches_oracle(name):
     w = _case(name)
     print(f"[case] multigrid {name} shape {w.phi.shape}", flush=True)
-    M = mg.Multigrid(w.x, w.y, w.z, w.phi)          # default levels, 4 + 4 steps, 16 coarse
+    M = mg.Multigrid(w.x, w.y, w.z, w.phi)          # default levels, 2 + 2 steps, 8 coarse
     rho = _random_rho(w.phi.shape, M.lv[0]["P"].types(), 31)
     ref = M.apply(rho)
     scale = np.max(np.abs(ref))

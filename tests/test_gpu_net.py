@@ -127,7 +127,8 @@ def test_restrict_all_channels_vs_oracle():
         print(f"channel {c}: max rel {err:.2e}")
         assert err <= 2e-7          # an FP32 rounding of an FP64 mean
     assert np.max(np.abs(ref[1])) < 1.0 and np.min(ref[1]) < 0.0 < np.max(ref[1])   # phi unclamped, both signs
-    tref = ows.restrict_target(w.u_exact, sig, N // 4)
+    tref = ows.restrict_target(w.u_exact, w.phi, w.g, sig, N // 4)
+    assert np.any(w.phi[1:-1, 1:-1, 1:-1] <= 0.0)    # the body's nodes take g
     assert np.max(np.abs(tgt[0].cpu().numpy() - tref)) <= 2e-7 * np.max(np.abs(tref))
 
 

@@ -29,7 +29,7 @@ def test_struct_layouts_and_host_only_calls():
     assert o.struct_size == ctypes.sizeof(cps.CpsOptions) == 88
     assert o.inner_iters == 24 and o.precision == cps.CPS_FP64
     assert o.precond == cps.CPS_PRECOND_MULTIGRID
-    assert (o.mg_levels, o.mg_nu, o.mg_coarse_steps, o.mg_smooth_lo) == (16, 4, 16, 0.5)
+    assert (o.mg_levels, o.mg_nu, o.mg_coarse_steps, o.mg_smooth_lo) == (16, 2, 8, 0.2)
     # lam_lo = 0 selects max(lam_hi / (4 inner_iters^2), lambda_1 of the grid) at setup
     assert abs(o.inner_tol - 1e-4) < 1e-18 and o.lam_hi == 2.0 and o.lam_lo == 0.0
     assert lib.cps_strerror(-2).decode().startswith("invalid geometry")

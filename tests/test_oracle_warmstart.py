@@ -61,9 +61,19 @@ def test_restrict_inputs_channels_and_sigma():
     np.testing.assert_allclose(inp2, inp, rtol=1e-15)
     # a zero problem keeps sigma = 1
     assert ws.scale_sigma(np.zeros(8), np.zeros(8)) == 1.0
-    # the target is the cell mean of u / sigma
-    u = 2.0 * f / (3.0 * np.pi ** 2)
-    np.testing.assert_allclose(ws.restrict_target(u, 2.5, nc), 4.0 / 2.5, rtol=1e-15)
+    # the target is the cell mean of u / sigma, with g in place of u where phi <= 0
+    u = 2.0 * f / (3.0 * np.pi ** 2)                  # 4 everywhere
+    np.testing.assert_allclose(ws.restrict_target(u, np.ones_like(phi), g, 2.5, nc), 4.0 / 2.5, rtol=1e-15)
+    # cells with cx = 0 lie in phi = -1: their target is g = 1.5 (not u = 4, not 0)
+    t = ws.restrict_target(u, phi, g, 2.5, nc)
+    np.testing.assert_allclose(t[..., 0], 1.5 / 2.5, rtol=1e-15)
+    np.testing.assert_allclose(t[..., 1], 4.0 / 2.5, rtol=1e-15)
+    # a block with one node inside the body: (63 u + g) / 64
+    phi2 = np.ones_like(phi)
+    phi2[1, 1, 1] = -0.5
+    t2 = ws.restrict_target(u, phi2, g, 1.0, nc)
+    assert t2[0, 0, 0] == pytest.approx((63 * 4.0 + 1.5) / 64, rel=1e-15)
+    assert t2[1, 1, 1] == pytest.approx(4.0, rel=1e-15)
 
 
 def test_prolong_exact_on_trilinear_fields():
