@@ -11,6 +11,7 @@ loops over batches.
     python -m paper_1901_08269_amd.learned train spheres8 --N 256 --train 96 --epochs 30
     python -m paper_1901_08269_amd.learned train star --N 128 --train 2000 --test 200
     python -m paper_1901_08269_amd.learned eval spheres8 --N 256 --test 32 --report r.json
+    python -m paper_1901_08269_amd.learned time spheres8 --N 256 --batch 8
 """
 from __future__ import annotations
 
@@ -353,9 +354,52 @@ def gain_report(rows):
             "max_rel_diff": float(max(r["diff"] for r in rows))}
 
 
+def conv_flops(nc, channels=CHANNELS, cin=3):
+    """Multiply-add FLOPs (2 per MAC) of one forward pass of the network on an nc^3 input:
+    the 3x3x3 layers of each level (inputs of decoder layers include the skip channels) and
+    the 1x1x1 head."""
+    c = channels
+    layers = [(0, cin, c[0]), (0, c[0], c[0]), (1, c[0], c[1]), (1, c[1], c[1]), (2, c[1], c[2]), (2, c[2], c[2]),
+              (3, c[2], c[3]), (3, c[3], c[3]), (2, c[3] + c[2], c[2]), (2, c[2], c[2]), (1, c[2] + c[1], c[1]),
+              (1, c[1], c[1]), (0, c[1] + c[0], c[0]), (0, c[0], c[0])]
+    fl = sum(2.0 * 27 * ci * co * (nc >> lv) ** 3 for lv, ci, co in layers)
+    return fl + 2.0 * c[0] * nc ** 3
+
+
+def time_network(N, batch, reps=20):
+    """Event-timed inference (cps_model_predict on the 8-sphere problem, restriction and
+    prolongation included) and training steps (forward + backward + Adam, batch `batch` of
+    synthetic inputs) of the network for an N^3 problem."""
+    import torch
+    nc = N // 4
+    x, y, z, phi, g, f = make_problem("spheres8", N, 100000)
+    S = Solver(x, y, z, phi, g, f, precision="mixed")
+    m = Model(nc, batch=1)
+    mt = Model(nc, batch=batch, seed=1)
+    rng = np.random.Generator(np.random.PCG64(0))
+    inp = torch.tensor(rng.standard_normal((batch, 3, nc, nc, nc)), dtype=torch.float32, device="cuda")
+    tgt = torch.tensor(rng.standard_normal((batch, nc, nc, nc)), dtype=torch.float32, device="cuda")
+    out = {"N": N, "nc": nc, "batch": batch, "reps": reps, "forward_flops_per_sample": conv_flops(nc)}
+    for name, fn, fl in (("predict", lambda: m.predict(S), conv_flops(nc)),
+                         ("train_step", lambda: mt.train_step(inp, tgt, lr=1e-4), 3.0 * batch * conv_flops(nc))):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "conv_tflops": fl / (ms * 1e-3) / 1e12}
+    S.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("cmd", choices=["train", "eval", "time"])
     ap.add_argument("family", choices=["spheres8", "star"])
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--train", type=int, default=96)
@@ -374,6 +418,9 @@ def main(argv=None):
         print(msg, flush=True)
 
     te_seeds = list(range(100000, 100000 + a.test))
+    if a.cmd == "time":
+        print(json.dumps(time_network(a.N, a.batch)), flush=True)
+        return
     if a.cmd == "eval":
         path = a.weights or (default_weights(a.N) if a.family == "spheres8" else
                              os.path.join(WEIGHTS, f"warmstart_star_nc{a.N // 4}.bin"))
