@@ -16,7 +16,8 @@
  * by right-preconditioned BiCGSTAB (Sec. 3.2, Alg. 1) whose preconditioner is the
  * second-order 7-point operator K with Shortley-Weller rows at Gamma (Sec. 3.3, Eqs.
  * A7/A7_mod), solved approximately by a fixed linear inner solver: one multigrid V-cycle
- * (default) or a fixed number of Chebyshev-Jacobi steps (cps_options.precond).
+ * (default), a fixed number of Chebyshev-Jacobi steps, or a fixed number of iterations of
+ * the strongly implicit procedure (cps_options.precond).
  *
  * Conventions shared by every entry point
  *   - Grid: nx, ny, nz points per direction INCLUDING both wall planes; coordinates
@@ -56,6 +57,7 @@ extern "C" {
 
 #define CPS_PRECOND_CHEBYSHEV 0  /* inner_iters Chebyshev-Jacobi steps on K per apply */
 #define CPS_PRECOND_MULTIGRID 1  /* one multigrid V-cycle on K per apply */
+#define CPS_PRECOND_SIP 2        /* sip_iters iterations of the strongly implicit procedure on K */
 
 typedef struct cps_solver cps_solver; /* opaque; owns all of its device memory */
 
@@ -92,6 +94,17 @@ typedef struct cps_options {
     int32_t mg_nu;           /* smoothing steps before and after, 1..64 (default 2) */
     int32_t mg_coarse_steps; /* steps on the coarsest grid, 1..64 (default 8) */
     double mg_smooth_lo;     /* lower end of the smoother's interval, in (0, lam_hi) (default 0.2) */
+    /* CPS_PRECOND_SIP: the strongly implicit procedure (Stone's partial-cancellation incomplete
+     * factorisation of K, L U with unit upper diagonal, unknowns in x-fastest order; the
+     * unknowns one factor entry beyond K's stencil reaches are approximated by sip_alpha x
+     * (the two stencil neighbours it lies between minus the centre); sip_alpha = 0 is the
+     * incomplete factorisation without fill), sip_iters iterations from phi = 0 per apply
+     * (the paper runs 8 inner iterations of its modified strongly implicit procedure,
+     * Sec. 4).  The substitutions run hyperplane by hyperplane (i + j + k = const), one
+     * launch each: far slower on a GPU than the parallel inner solvers. */
+    int32_t sip_iters;       /* 1..64 (default 8) */
+    int32_t pad;
+    double sip_alpha;        /* in [0, 1] (default 0.9) */
 } cps_options;
 
 typedef struct cps_stats {
@@ -120,7 +133,8 @@ typedef struct cps_stats {
 /* Fill `o` with the defaults: CPS_FP64, 24 inner iterations, max_iters 20000,
  * max_refine 40, max_restarts 5, host pointers, inner_tol 1e-4, the default Chebyshev
  * interval, null stream, no kernel timing, the multigrid preconditioner (up to 16 levels,
- * 2 + 2 smoothing steps on [0.2, lam_hi], 8 coarsest-grid steps). */
+ * 2 + 2 smoothing steps on [0.2, lam_hi], 8 coarsest-grid steps), 8 strongly implicit
+ * iterations with alpha 0.9 when that preconditioner is chosen. */
 void cps_default_options(cps_options *o);
 
 /* Build the discrete problem (Secs. 2-3): classify nodes from the sign of phi (Sec. 2,
@@ -155,8 +169,9 @@ int cps_residual(cps_solver *s, const double *u, double *r, double *rel);
 int cps_apply(cps_solver *s, const double *x, double *y, int32_t precision);
 
 /* phi = M rho: the preconditioner of Alg. 1 (applied to p and to s): an approximate solve of
- * K phi = rho (Sec. 3.3) from phi = 0 -- inner_iters Chebyshev-Jacobi steps, or one multigrid
- * V-cycle (cps_options.precond); FP64 or FP32 as above. */
+ * K phi = rho (Sec. 3.3) from phi = 0 -- inner_iters Chebyshev-Jacobi steps, one multigrid
+ * V-cycle, or sip_iters strongly implicit iterations (cps_options.precond); FP64 or FP32 as
+ * above. */
 int cps_precond(cps_solver *s, const double *rho, double *phi, int32_t precision);
 
 /* Copy out the right-hand side q + b (node array, 0 at non-unknowns) and the node types

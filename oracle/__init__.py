@@ -66,6 +66,8 @@ def lib():
         L.orc_residual.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_compact_coef.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp]
         L.orc_second_coef.argtypes = [C.c_int, dp, dp, dp, dp]
+        L.orc_sip_factor.argtypes = [C.c_void_p, C.c_double, dp]
+        L.orc_sip_precond.argtypes = [C.c_void_p, dp, dp, dp, C.c_int]
         L.orc_onesided_weights.restype = C.c_int
         L.orc_onesided_weights.argtypes = [C.c_int, dp, C.c_int, dp, dp, C.c_double, C.c_double, dp]
         _lib = L
@@ -238,6 +240,22 @@ class Problem:
         rho = _f64(rho).reshape(self.shape)
         phi = np.zeros(self.shape)
         lib().orc_precond(self.h, _p(rho), _p(phi), iters, lo, hi)
+        return phi
+
+    def sip_factors(self, alpha):
+        """Factors of the strongly implicit procedure for K: array (7,) + shape holding b, c,
+        d, e, f, g, h per node (see orc_sip_factor)."""
+        F = np.zeros(self.shape + (7,))
+        lib().orc_sip_factor(self.h, float(alpha), _p(F))
+        return np.moveaxis(F, -1, 0).copy()
+
+    def precond_sip(self, rho, iters=8, alpha=0.5, factors=None):
+        """`iters` iterations of the strongly implicit procedure on K phi = rho from 0."""
+        F = self.sip_factors(alpha) if factors is None else factors
+        Fn = np.ascontiguousarray(np.moveaxis(F, 0, -1))
+        rho = _f64(rho).reshape(self.shape)
+        phi = np.zeros(self.shape)
+        lib().orc_sip_precond(self.h, _p(Fn), _p(rho), _p(phi), int(iters))
         return phi
 
     def solve(self, tol=1e-10, u0=None, mixed=False, inner_iters=DEFAULT_INNER, max_iters=20000,

@@ -835,6 +835,90 @@ void orc_precond(void *h, const double *rho, double *phi, int iters, double lo, 
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Strongly implicit procedure for K phi = rho (the family of the paper's inner solver)  */
+/* ------------------------------------------------------------------------------------ */
+/* Sec. 3.3 solves the preconditioned system with the modified strongly implicit procedure
+ * of Zedan & Schneider (ref. 24), whose recurrences the paper does not give.  This is the
+ * strongly implicit procedure in its original form (Stone's partial-cancellation incomplete
+ * factorisation, extended to the 7-point operator in three dimensions), derived here:
+ *
+ * K is approximated by M = L U with L lower triangular (entries b, c, d at the -z, -y, -x
+ * neighbours B, S, W and e on the diagonal) and U upper triangular with unit diagonal
+ * (entries f, g, h at the +x, +y, +z neighbours E, N, T), unknowns in lexicographic order
+ * (x fastest).  L U has, besides K's seven positions, six more at B+E, B+N, S+E, S+T, W+N,
+ * W+T with values X1 = b f_B, X2 = b g_B, X3 = c f_S, X4 = c h_S, X5 = d g_W, X6 = d h_W.
+ * The value of the unknown at such a position is approximated by the first-order Taylor
+ * combination of two stencil points, phi_{Q+R} ~ alpha (phi_Q + phi_R - phi_P), and M is
+ * made to equal K at K's positions with those terms moved onto them:
+ *   b = K_B / (1 + alpha (f_B + g_B)),  c = K_S / (1 + alpha (f_S + h_S)),
+ *   d = K_W / (1 + alpha (g_W + h_W)),
+ *   e = K_P - b h_B - c g_S - d f_W + alpha (X1 + ... + X6),
+ *   f = (K_E - alpha (X1 + X3)) / e,  g = (K_N - alpha (X2 + X5)) / e,
+ *   h = (K_T - alpha (X4 + X6)) / e,
+ * with every factor entry toward a node that is not an unknown (wall or solid) taken as 0.
+ * alpha = 0 gives the incomplete factorisation with no fill, ILU(0).  One iteration: r =
+ * rho - K phi, L v = r (forward, increasing order), U delta = v (backward), phi += delta;
+ * from phi = 0, a fixed number of iterations is a fixed linear map of rho. */
+
+/* factors per node: out[7 e + q], q = b, c, d, e, f, g, h (0 at nodes that are not unknowns) */
+void orc_sip_factor(void *h, double alpha, double *out)
+{
+    orc_prob *P = (orc_prob *)h;
+    memset(out, 0, sizeof(double) * 7 * (size_t)P->nn);
+    for (i64 e = 0; e < P->nn; ++e) {
+        if (!is_unknown(P, e)) continue;
+        int c[3];
+        coords_of(P, e, c);
+        double co[7];
+        k_coef(P, e, c, co);
+        const i64 nB = e - P->stride[2], nS = e - P->stride[1], nW = e - 1;
+        const double *FB = out + 7 * nB, *FS = out + 7 * nS, *FW = out + 7 * nW;
+        /* factor entries of neighbours that are not unknowns are 0 (out is zeroed there) */
+        double b = co[5] / (1.0 + alpha * (FB[4] + FB[5]));
+        double cc = co[3] / (1.0 + alpha * (FS[4] + FS[6]));
+        double d = co[1] / (1.0 + alpha * (FW[5] + FW[6]));
+        double X1 = b * FB[4], X2 = b * FB[5], X3 = cc * FS[4], X4 = cc * FS[6], X5 = d * FW[5], X6 = d * FW[6];
+        double ee = co[0] - b * FB[6] - cc * FS[5] - d * FW[4] + alpha * (X1 + X2 + X3 + X4 + X5 + X6);
+        double *F = out + 7 * e;
+        F[0] = b;
+        F[1] = cc;
+        F[2] = d;
+        F[3] = ee;
+        F[4] = is_unknown(P, e + 1) ? (co[2] - alpha * (X1 + X3)) / ee : 0.0;
+        F[5] = is_unknown(P, e + P->stride[1]) ? (co[4] - alpha * (X2 + X5)) / ee : 0.0;
+        F[6] = is_unknown(P, e + P->stride[2]) ? (co[6] - alpha * (X4 + X6)) / ee : 0.0;
+    }
+}
+
+/* phi = `iters` iterations of the strongly implicit procedure from phi = 0 with the
+ * factors of orc_sip_factor */
+void orc_sip_precond(void *h, const double *F, const double *rho, double *phi, int iters)
+{
+    orc_prob *P = (orc_prob *)h;
+    i64 nn = P->nn;
+    double *r = dalloc(nn), *v = dalloc(nn);
+    memset(phi, 0, sizeof(double) * nn);
+    for (int it = 0; it < iters; ++it) {
+        orc_apply_K(P, phi, r);
+        for (i64 e = 0; e < nn; ++e) r[e] = is_unknown(P, e) ? rho[e] - r[e] : 0.0;
+        for (i64 e = 0; e < nn; ++e) {             /* L v = r */
+            if (!is_unknown(P, e)) { v[e] = 0.0; continue; }
+            const double *Fe = F + 7 * e;
+            v[e] = (r[e] - Fe[0] * v[e - P->stride[2]] - Fe[1] * v[e - P->stride[1]] - Fe[2] * v[e - 1]) / Fe[3];
+        }
+        for (i64 e = nn - 1; e >= 0; --e) {        /* U delta = v (delta in v) */
+            if (!is_unknown(P, e)) continue;
+            const double *Fe = F + 7 * e;
+            v[e] -= Fe[4] * v[e + 1] + Fe[5] * v[e + P->stride[1]] + Fe[6] * v[e + P->stride[2]];
+        }
+        for (i64 e = 0; e < nn; ++e)
+            if (is_unknown(P, e)) phi[e] += v[e];
+    }
+    free(r);
+    free(v);
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* BiCGSTAB (Alg. 1 with the split of Eq. Bdec)                                          */
 /* ------------------------------------------------------------------------------------ */
 

@@ -21,6 +21,7 @@ CPS_FP64 = 0
 CPS_MIXED = 1
 CPS_PRECOND_CHEBYSHEV = 0
 CPS_PRECOND_MULTIGRID = 1
+CPS_PRECOND_SIP = 2
 ERRORS = {0: "ok", -1: "EINVAL", -2: "EGEOM", -3: "ENOMEM", -4: "EDEVICE", -5: "EBREAKDOWN", -6: "ENOCONV",
           -7: "ENAN"}
 
@@ -31,7 +32,8 @@ class CpsOptions(C.Structure):
                 ("device_ptrs", C.c_int32), ("kernel_timing", C.c_int32), ("inner_tol", C.c_double),
                 ("lam_lo", C.c_double), ("lam_hi", C.c_double), ("stream", C.c_void_p),
                 ("precond", C.c_int32), ("mg_levels", C.c_int32), ("mg_nu", C.c_int32),
-                ("mg_coarse_steps", C.c_int32), ("mg_smooth_lo", C.c_double)]
+                ("mg_coarse_steps", C.c_int32), ("mg_smooth_lo", C.c_double), ("sip_iters", C.c_int32),
+                ("pad", C.c_int32), ("sip_alpha", C.c_double)]
 
 
 class CpsStats(C.Structure):
@@ -128,7 +130,8 @@ class Solver:
 
     def __init__(self, x, y, z, phi, g, f, precision="fp64", inner_iters=None, lam_lo=None, lam_hi=None,
                  inner_tol=1e-4, max_iters=20000, max_refine=40, max_restarts=5, kernel_timing=False,
-                 precond=None, mg_levels=None, mg_nu=None, mg_coarse_steps=None, mg_smooth_lo=None):
+                 precond=None, mg_levels=None, mg_nu=None, mg_coarse_steps=None, mg_smooth_lo=None,
+                 sip_iters=None, sip_alpha=None):
         torch = _torch()
         L = load_library()
         self.L = L
@@ -147,10 +150,11 @@ class Solver:
         o.max_refine = max_refine
         o.max_restarts = max_restarts
         o.kernel_timing = int(kernel_timing)   # True: every sweep; n: every n-th
-        if precond is not None:                # "chebyshev" or "multigrid"
-            o.precond = {"chebyshev": CPS_PRECOND_CHEBYSHEV, "multigrid": CPS_PRECOND_MULTIGRID}[precond]
+        if precond is not None:                # "chebyshev", "multigrid" or "sip"
+            o.precond = {"chebyshev": CPS_PRECOND_CHEBYSHEV, "multigrid": CPS_PRECOND_MULTIGRID,
+                         "sip": CPS_PRECOND_SIP}[precond]
         for name, val in (("mg_levels", mg_levels), ("mg_nu", mg_nu), ("mg_coarse_steps", mg_coarse_steps),
-                          ("mg_smooth_lo", mg_smooth_lo)):
+                          ("mg_smooth_lo", mg_smooth_lo), ("sip_iters", sip_iters), ("sip_alpha", sip_alpha)):
             if val is not None:
                 setattr(o, name, val)
         o.device_ptrs = 1

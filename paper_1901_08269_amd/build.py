@@ -22,7 +22,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(LIBDIR, "libcps.so")
 
-SOURCES = ["setup.hip", "sweeps.hip", "multigrid.hip", "solver.hip", "net.hip"]
+SOURCES = ["setup.hip", "sweeps.hip", "multigrid.hip", "sip.hip", "solver.hip", "net.hip"]
 # a standalone program: the bandwidth plain streaming kernels get (the roofline's practical ceiling)
 STREAM_BENCH = os.path.join(LIBDIR, "stream_bench")
 

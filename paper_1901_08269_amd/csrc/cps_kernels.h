@@ -114,6 +114,14 @@ void launch_mg_irr_map(hipStream_t s, int nirr, const int *nodes, int *map);
 template <typename T>
 void launch_mg_prolong_add(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_f, const T *e, T *x);
 
+// sip.hip: the strongly implicit procedure for K (factors per node: b, c, d, e, f, g, h, 0)
+void launch_sip_factor(hipStream_t st, int nx, int ny, int nz, const Coef<double> &cf, const int8_t *type,
+                       const int *irr_map, const double *k7, double alpha, double *F, float *F32);
+// one iteration: L v = r, U delta = v (delta over v), phi = delta (first) or phi += delta
+template <typename T>
+void launch_sip_iteration(hipStream_t st, int nx, int ny, int nz, const int8_t *type, const T *F, const T *r, T *v,
+                          T *phi, int first, const DevState *dst);
+
 // setup.hip
 struct SetupOut {
     int n_irr;

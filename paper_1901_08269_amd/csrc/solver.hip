@@ -125,6 +125,14 @@ struct cps_solver {
     int sweep_rev[MG_MAX_LEVELS] = {};  // per level: z direction of its next sweep (alternates)
     double *mg_ccd64 = nullptr;         // mg_cc1 | mg_cc2 on the device (one-workgroup coarsest solve)
     float *mg_ccd32 = nullptr;
+    // strongly implicit procedure (opt.precond = CPS_PRECOND_SIP): factors b, c, d, e, f, g, h
+    // (and a zero) per node in FP64 and FP32, the irregular row of each irregular node, and
+    // per precision the residual and substitution vectors
+    double *sip64 = nullptr;
+    float *sip32 = nullptr;
+    int *sip_map = nullptr;
+    double *sip_w64[2] = {nullptr, nullptr};
+    float *sip_w32[2] = {nullptr, nullptr};
     // host-side facts
     long long n_unknown = 0, n_solid = 0, nnz = 0, fallback = 0;
     double min_hb = 1.0;
@@ -631,6 +639,45 @@ void mg_precond(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T 
     mg_smooth<T>(s, 0, L, cf, ir, ps, x, nullptr, x, res, dst, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, true);
 }
 
+// phi (dst) = sip_iters iterations of the strongly implicit procedure on K phi = ps from 0
+template <typename T>
+void sip_precond(cps_solver *s, const T *ps, T *dst, const DevState *st)
+{
+    T **w;
+    const T *F;
+    if constexpr (sizeof(T) == 8) { w = s->sip_w64; F = s->sip64; } else { w = s->sip_w32; F = s->sip32; }
+    for (int q = 0; q < 2; ++q)
+        if (!w[q]) {
+            w[q] = dalloc<T>(s, s->nn + VEC_PAD);
+            launch_fill<T>(s->stream, s->nn + VEC_PAD, w[q], T(0));
+        }
+    const Launch L = s->launch();
+    Coef<T> cf;
+    Irr<T> ir;
+    if constexpr (sizeof(T) == 8) { cf = s->cf64(); ir = s->ir64(); } else { cf = s->cf32(); ir = s->ir32(); }
+    for (int it = 0; it < s->opt.sip_iters; ++it) {
+        const T *rin = ps;
+        if (it > 0) {
+            launch_resid<T>(L, cf, ir, dst, ps, w[0], st, next_rev(s, 0));
+            rin = w[0];
+        }
+        launch_sip_iteration<T>(s->stream, s->nx, s->ny, s->nz, s->type, F, rin, w[1], dst, it == 0, st);
+    }
+}
+
+// factors of the strongly implicit procedure (setup)
+void sip_build(cps_solver *s)
+{
+    s->sip_map = dalloc<int>(s, s->nn);
+    launch_mg_irr_map(s->stream, s->nirr, s->irr_node, s->sip_map);
+    s->sip64 = dalloc<double>(s, 8 * s->nn);
+    s->sip32 = dalloc<float>(s, 8 * s->nn);
+    launch_fill<double>(s->stream, 8 * s->nn, s->sip64, 0.0);
+    launch_fill<float>(s->stream, 8 * s->nn, s->sip32, 0.0f);
+    launch_sip_factor(s->stream, s->nx, s->ny, s->nz, s->cf64(), s->type, s->sip_map, s->irr_k64, s->opt.sip_alpha,
+                      s->sip64, s->sip32);
+}
+
 // p^ = M p: inner_iters Chebyshev steps.  The first is fused with the vector update `kind`
 // (x_1 is pointwise from x_0 = 0); the rest are single sweeps in which x_{k+1} overwrites
 // x_{k-1} in place (each node's x_{k-1} is read only by the thread that writes its x_{k+1}),
@@ -644,6 +691,16 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
 {
     if (s->opt.precond == CPS_PRECOND_MULTIGRID) {
         mg_precond<T>(s, V, kind, r, ps, v, dst, st);
+        return;
+    }
+    if (s->opt.precond == CPS_PRECOND_SIP) {
+        // the vector update that forms ps (its fused first Chebyshev step lands, unused, in a
+        // rotating buffer), then the strongly implicit iterations
+        Coef<T> cf;
+        Irr<T> ir;
+        if constexpr (sizeof(T) == 8) { cf = s->cf64(); ir = s->ir64(); } else { cf = s->cf32(); ir = s->ir32(); }
+        launch_first<T>(kind, s->launch(), cf, ir, r, ps, v, V.c[0], 0.0, st);
+        sip_precond<T>(s, ps, dst, st);
         return;
     }
     const Launch L = s->launch();
@@ -1149,6 +1206,9 @@ void cps_default_options(cps_options *o)
     o->mg_nu = 2;
     o->mg_coarse_steps = 8;
     o->mg_smooth_lo = 0.2;
+    o->sip_iters = 8;
+    o->pad = 0;
+    o->sip_alpha = 0.9;
 }
 
 const char *cps_strerror(int code)
@@ -1190,7 +1250,9 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         o.lam_lo = std::max(o.lam_hi / (4.0 * (double)o.inner_iters * (double)o.inner_iters), lam1);
     }
     if (!(o.lam_hi > o.lam_lo)) return CPS_EINVAL;
-    if (o.precond != CPS_PRECOND_CHEBYSHEV && o.precond != CPS_PRECOND_MULTIGRID) return CPS_EINVAL;
+    if (o.precond != CPS_PRECOND_CHEBYSHEV && o.precond != CPS_PRECOND_MULTIGRID && o.precond != CPS_PRECOND_SIP)
+        return CPS_EINVAL;
+    if (o.sip_iters < 1 || o.sip_iters > MAX_INNER || !(o.sip_alpha >= 0.0 && o.sip_alpha <= 1.0)) return CPS_EINVAL;
     if (o.mg_levels < 1 || o.mg_levels > MG_MAX_LEVELS || o.mg_nu < 1 || o.mg_nu > MAX_INNER ||
         o.mg_coarse_steps < 1 || o.mg_coarse_steps > MAX_INNER || !(o.mg_smooth_lo > 0.0) ||
         !(o.mg_smooth_lo < o.lam_hi))
@@ -1284,6 +1346,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->rhs = dalloc<double>(s, s->nn);
         rc = rhs_build(s);
         if (rc == CPS_OK && o.precond == CPS_PRECOND_MULTIGRID) mg_build(s, hx);
+        if (rc == CPS_OK && o.precond == CPS_PRECOND_SIP) sip_build(s);
         sync(s);
     } catch (int code) {
         rc = code;

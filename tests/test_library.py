@@ -26,10 +26,11 @@ def test_struct_layouts_and_host_only_calls():
     lib = cps.load_library()
     o = cps.CpsOptions()
     lib.cps_default_options(ctypes.byref(o))
-    assert o.struct_size == ctypes.sizeof(cps.CpsOptions) == 88
+    assert o.struct_size == ctypes.sizeof(cps.CpsOptions) == 104
     assert o.inner_iters == 24 and o.precision == cps.CPS_FP64
     assert o.precond == cps.CPS_PRECOND_MULTIGRID
     assert (o.mg_levels, o.mg_nu, o.mg_coarse_steps, o.mg_smooth_lo) == (16, 2, 8, 0.2)
+    assert (o.sip_iters, o.sip_alpha) == (8, 0.9)
     # lam_lo = 0 selects max(lam_hi / (4 inner_iters^2), lambda_1 of the grid) at setup
     assert abs(o.inner_tol - 1e-4) < 1e-18 and o.lam_hi == 2.0 and o.lam_lo == 0.0
     assert lib.cps_strerror(-2).decode().startswith("invalid geometry")
@@ -47,8 +48,9 @@ def test_multigrid_options_validated_before_device_calls():
     x = np.linspace(0.0, 1.0, n)
     a = np.ones((n, n, n))
     dp = lambda arr: arr.ctypes.data_as(ctypes.c_void_p)
-    bad = [("precond", 2), ("mg_levels", 0), ("mg_levels", 17), ("mg_nu", 0), ("mg_nu", 65),
-           ("mg_coarse_steps", 0), ("mg_smooth_lo", 0.0), ("mg_smooth_lo", 2.0)]
+    bad = [("precond", 3), ("precond", -1), ("mg_levels", 0), ("mg_levels", 17), ("mg_nu", 0), ("mg_nu", 65),
+           ("mg_coarse_steps", 0), ("mg_smooth_lo", 0.0), ("mg_smooth_lo", 2.0), ("sip_iters", 0),
+           ("sip_iters", 65), ("sip_alpha", -0.5), ("sip_alpha", 1.01)]
     for name, val in bad:
         o = cps.CpsOptions()
         lib.cps_default_options(ctypes.byref(o))
