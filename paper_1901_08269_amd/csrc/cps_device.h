@@ -28,6 +28,10 @@ constexpr int NXCD = 8;       // MI355X: 8 XCDs, blocks dispatched round-robin o
 // rows per wavefront in the vectorised Chebyshev sweep: one row beats two (43.1 against
 // 43.4 us per FP32 sweep at 256^3, with 1024 blocks instead of 512)
 constexpr int RPW = 1;
+// rows per wavefront of the sweeps that read two vectors (the first step of a smoothing pass,
+// without an x_{k-1}, and the residual): they are bound by the latency of their plane steps,
+// and two rows per wavefront put more bytes in flight per step
+constexpr int RPW2 = 2;
 // Vectors read by the vectorised sweeps carry this many zero elements past the last node:
 // a lane always loads four consecutive elements, also where some lie past the row end.
 constexpr size_t VEC_PAD = 8;
@@ -48,6 +52,7 @@ struct Geom {
                                // vector updates
     Tiling tr;                 // 256 x 4 tiles: one x-row segment of 256 nodes per wavefront,
                                // four nodes per lane (vectorised Chebyshev sweeps)
+    Tiling tr2;                // 256 x (4 RPW2) tiles: RPW2 rows per wavefront (two-vector sweeps)
     int lg;                    // coarse multigrid levels whose rows are at most 128 nodes
                                // long: 2^lg lanes per row, 64 / 2^lg rows per wavefront
                                // (tr then has (4 * 2^lg) x (4 * 64 / 2^lg) tiles); 6 otherwise

@@ -366,6 +366,8 @@ Geom make_geom(int nx, int ny, int nz, bool coarse = false)
         const int per_plane = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY * RPW - 1) / (TY * RPW));
         g.tr = coarse ? make_tiling(nx, ny, nz, 4 << g.lg, TY * RPW * (TX >> g.lg), COARSE_TILES, 1)
                       : make_tiling(nx, ny, nz, 4 * TX, TY * RPW, per_plane * ROW_ZCHUNKS, 4);
+        const int per_plane2 = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY * RPW2 - 1) / (TY * RPW2));
+        g.tr2 = make_tiling(nx, ny, nz, 4 * TX, TY * RPW2, per_plane2 * ROW_ZCHUNKS, 4);
     }
     size_t nn = (size_t)nx * ny * nz;
     g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, FLAT_BLOCKS);
@@ -1338,7 +1340,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->irr_wstart = dalloc<int>(s, (size_t)s->g.W * ny * nz);
         launch_irr_words(s->stream, s->g, s->type, s->irr_node, s->nirr, s->irr_bits, s->irr_wstart);
         // reduction scratch: enough for the largest launch
-        size_t maxblk = (size_t)std::max({s->g.ta.nblk, s->g.tr.nblk, s->g.nflat}) +
+        size_t maxblk = (size_t)std::max({s->g.ta.nblk, s->g.tr.nblk, s->g.tr2.nblk, s->g.nflat}) +
                         (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
         s->partials = dalloc<double>(s, 2 * maxblk);
         s->st = dalloc<DevState>(s, 1);

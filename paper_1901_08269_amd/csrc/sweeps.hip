@@ -209,15 +209,15 @@ __device__ __forceinline__ uint32_t skip4(const uint32_t *__restrict__ w, int i0
 // With MR (a coarse multigrid level whose rows fit in fewer than 64 lanes) each group of
 // 2^g.lg lanes owns one whole row, so a wavefront carries 64 / 2^g.lg rows and no lane idles;
 // the rows' y coefficients are then per lane.
-template <typename T, bool PREV0, bool RES, bool REV, bool MR = false>
+template <typename T, bool PREV0, bool RES, bool REV, bool MR = false, int R = RPW>
 __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, const Irr<T> &ir,
                                            const uint32_t *__restrict__ skip, const T *__restrict__ xc,
                                            const T *xm1, const T *__restrict__ rho, T *xn, T c1, T c2,
                                            const DevState *st)
 {
     using V = typename Vec4Of<T>::type;
-    constexpr int R = RPW;
-    static_assert(!MR || RPW == 1, "multi-row wavefronts take one row per lane group");
+    static_assert(!MR || R == 1, "multi-row wavefronts take one row per lane group");
+    static_assert(R == RPW || R == RPW2, "the tilings hold these row counts");
     if (st && st->done) return;
     const int wv = threadIdx.y;
     const int lw = MR ? 1 << g.lg : TX;                          // lanes per row
@@ -238,7 +238,7 @@ __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, con
         xn[e] = RES ? rho[e] - kx : z0 + c1 * (z0 - prev) + c2 * (rho[e] - kx) / k7[0];
         return;
     }
-    const Tiling &tl = g.tr;
+    const Tiling &tl = (R == RPW) ? g.tr : g.tr2;
     int bs, by, bz;
     if (!tile_of_block(tl, b, bs, by, bz)) return;
     const int jw = 1 + (by * TY + wv) * (MR ? TX / lw : R);    // the wavefront's first row
@@ -365,24 +365,24 @@ __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, con
     }
 }
 
-template <typename T, bool PREV0>
+template <typename T, bool PREV0, int R = RPW>
 __global__ void __launch_bounds__(NT) k_cheb4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
                                               const T *__restrict__ xc, const T *xm1,
                                               const T *__restrict__ rho, T *xn, T c1, T c2,
                                               const DevState *st, int rev)
 {
-    if (rev) cheb4_rows<T, PREV0, false, true>(g, cf, ir, skip, xc, xm1, rho, xn, c1, c2, st);
-    else cheb4_rows<T, PREV0, false, false>(g, cf, ir, skip, xc, xm1, rho, xn, c1, c2, st);
+    if (rev) cheb4_rows<T, PREV0, false, true, false, R>(g, cf, ir, skip, xc, xm1, rho, xn, c1, c2, st);
+    else cheb4_rows<T, PREV0, false, false, false, R>(g, cf, ir, skip, xc, xm1, rho, xn, c1, c2, st);
 }
 
 // r = rho - K x at the unknown nodes (the residual of a multigrid level; same rows)
-template <typename T>
+template <typename T, int R = RPW>
 __global__ void __launch_bounds__(NT) k_resid4(Geom g, Coef<T> cf, Irr<T> ir, const uint32_t *__restrict__ skip,
                                                const T *__restrict__ x, const T *__restrict__ rho, T *r,
                                                const DevState *st, int rev)
 {
-    if (rev) cheb4_rows<T, true, true, true>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
-    else cheb4_rows<T, true, true, false>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
+    if (rev) cheb4_rows<T, true, true, true, false, R>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
+    else cheb4_rows<T, true, true, false, false, R>(g, cf, ir, skip, x, nullptr, rho, r, T(0), T(0), st);
 }
 
 // the same two kernels for coarse levels with several rows per wavefront (g.lg < 6)
@@ -932,8 +932,11 @@ void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *
     dim3 grid(L.g.tr.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
     const bool mr = L.g.lg < 6;
     if (xm1 == nullptr) {
+        // the sweep without an x_{k-1} moves less per plane step: RPW2 rows per wavefront
+        dim3 grid2(L.g.tr2.nblk + irr_blocks(ir.n, NT));
         if (mr) k_cheb4m<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
-        else k_cheb4<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
+        else k_cheb4<T, true, RPW2><<<grid2, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st,
+                                                               rev);
     } else {
         if (mr) k_cheb4m<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
         else k_cheb4<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
@@ -945,8 +948,9 @@ void launch_resid(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T 
                   const DevState *st, int rev)
 {
     dim3 grid(L.g.tr.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
+    dim3 grid2(L.g.tr2.nblk + irr_blocks(ir.n, NT));
     if (L.g.lg < 6) k_resid4m<T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st, rev);
-    else k_resid4<T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st, rev);
+    else k_resid4<T, RPW2><<<grid2, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st, rev);
 }
 
 template <typename T>
