@@ -243,8 +243,8 @@ def main():
             got = u.reshape(-1)[samples[0]]
             parity["headline_solution_vs_oracle_rel_maxdiff"] = float(torch.max(torch.abs(got - samples[1])) / samples[2])
 
-    # roofline of the dominant kernel: the FP32 sweeps of the multigrid smoother on the
-    # problem's grid (k_cheb4<float>), timed live by the library in whole post-smoothing passes
+    # roofline of the dominant kernel: the FP32 sweep of the multigrid smoother on the
+    # problem's grid (k_cheb4<float>, the steps that read an x_{k-1}), timed live by the library
     sweeps = sum(s_["sweep_launches"] for s_ in stats)
     sweep_ms = sum(s_["sweep_ms"] for s_ in stats)
     sweep_bytes = sum(s_["sweep_bytes"] for s_ in stats)
@@ -254,14 +254,15 @@ def main():
     # describes the kernel sources (the report carries their hash) and this workload
     from paper_1901_08269_amd import profiling
     traffic, traffic_note = None, "no counter report for this workload"
-    rep = profiling.read_traffic(os.path.join(ROOT, "profiles", f"k_cheb4_spheres8_{args.N}_traffic.md"))
+    tag = f"{args.workload}_{args.N}"
+    rep = profiling.read_traffic(os.path.join(ROOT, "profiles", f"k_cheb4_{tag}_traffic.md"))
     if rep is not None:
         if rep.get("kernel_source_sha256_16") == profiling.source_hash():
             traffic = float(rep["traffic_bytes_per_launch"])
-            traffic_note = f"profiles/k_cheb4_spheres8_{args.N}_traffic.md (FETCH_SIZE+WRITE_SIZE, copy-calibrated)"
+            traffic_note = f"profiles/k_cheb4_{tag}_traffic.md (FETCH_SIZE+WRITE_SIZE, copy-calibrated)"
         else:
             traffic_note = "kernel sources changed since the counters were taken"
-    roofline = {"kernel": "k_cheb4<float> (smoother sweeps on the problem's grid, post-smoothing passes)",
+    roofline = {"kernel": "k_cheb4<float, false> (smoother sweep on the problem's grid)",
                 "bound": "hbm", "achieved": achieved, "peak": metrics.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / metrics.MI355X_HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                 "traffic_source": traffic_note,

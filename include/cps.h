@@ -71,8 +71,9 @@ typedef struct cps_options {
     int32_t max_restarts;  /* restarts after breakdown or a failed true-residual check */
     int32_t device_ptrs;   /* 1: array arguments are device pointers */
     int32_t kernel_timing; /* n > 0: time every n-th run of consecutive preconditioner sweeps
-                            * on the problem's grid (multigrid: a post-smoothing pass;
-                            * Chebyshev: steps 2 .. inner_iters - 1), with one pair of HIP
+                            * on the problem's grid that read an x_{k-1} (multigrid: steps
+                            * 1 .. mg_nu - 1 of a post-smoothing pass; Chebyshev: steps
+                            * 2 .. inner_iters - 1), with one pair of HIP
                             * events per run (stats; each pair adds a few microseconds); runs
                             * queued after convergence are left out; 0: off */
     double inner_tol;      /* CPS_MIXED: residual reduction asked of each FP32 inner solve */

@@ -520,9 +520,9 @@ T *mg_smooth(cps_solver *s, int lvl, const Launch &L, const Coef<T> &cf, const I
     for (int k = k0; k < n; ++k) {
         const T *xm1 = (k == 0) ? nullptr : (k == 1 ? (const T *)x0 : buf(k - 1));
         T *out = (k == n - 1 && dst) ? dst : buf(k + 1);
-        // a timed pass is a whole post-smoothing pass (steps 0 .. n - 1 from x0): step 0 reads
-        // x_0 and rho and writes x_1, each later step also reads its x_{k-1}
-        if (timed && x0 && k == 0) e1 = timed_run_begin(s, n, 3 + 4 * (n - 1));
+        // a timed run is the full-traffic part of a post-smoothing pass (steps 1 .. n - 1 from
+        // x0, each reading x_k, x_{k-1} and rho and writing x_{k+1})
+        if (timed && x0 && k == 1) e1 = timed_run_begin(s, n - 1, 4 * (n - 1));
         launch_cheb<T>(L, cf, ir, buf(k), xm1, rho, out, c1[k], c2[k], st, next_rev(s, lvl));
     }
     if (e1) ck(hipEventRecord(e1, s->stream));

@@ -6,6 +6,7 @@ Three reports:
 ``kernels``  the solve kernels of such a run against the HBM roofline: algorithmic bytes
              per interior point (each operand read or written once), GB/s from the average
              launch duration, fraction of the 8 TB/s peak.
+``mfma``     MFMA busy share and BF16 matrix FLOP rate of the network's kernels from one ``--pmc`` run.
 ``traffic``  HBM bytes per launch of one kernel on the problem's grid from two ``--pmc`` runs
              (``FETCH_SIZE`` and ``WRITE_SIZE``, each in its own pass), each counter scaled by
              what the same counter reads for a plain device copy of known size (the
@@ -17,6 +18,7 @@ Usage::
 
     python -m paper_1901_08269_amd.profiling stats DB --title T --cmd C [--top 20]
     python -m paper_1901_08269_amd.profiling kernels DB --points P --title T --cmd C
+    python -m paper_1901_08269_amd.profiling mfma DB --title T --cmd C
     python -m paper_1901_08269_amd.profiling traffic --fetch DB --write DB \\
         --copy-fetch DB --copy-write DB --copy-bytes B --kernel NAME --units U --unit-bytes UB \\
         --title T --cmd C
@@ -220,6 +222,54 @@ def traffic_report(a):
     return "\n".join(out)
 
 
+SIMDS = 256 * 4                 # MI355X: 256 compute units of 4 SIMDs
+BF16_PEAK_TFLOPS = 2500.0       # dense BF16 matrix peak
+
+
+def mfma_report(db, title, cmd):
+    """Per network kernel (one --pmc pass of SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE and
+    SQ_INSTS_VALU_MFMA_MOPS_BF16): dispatches, mean duration, MFMA busy share (busy cycles
+    over active cycles times the SIMD count, as rocprofv3's MfmaUtil) and BF16 matrix FLOPs
+    (512 per MOPS unit) per second against the dense BF16 peak."""
+    con = sqlite3.connect(db)
+    acc = {}
+    for name, disp, dur, cname, val in con.execute(
+            "select name, dispatch_id, duration, counter_name, counter_value from pmc_events"):
+        if "cpsnet" not in name:
+            continue
+        k = acc.setdefault(short_name(name), {})
+        d = k.setdefault(disp, {"dur": dur})
+        d[cname] = d.get(cname, 0.0) + val
+    con.close()
+    out = [f"# {title}", "", "Command (run from the repository root on an MI355X):", "", "```", cmd, "```", "",
+           f"MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x {SIMDS} SIMDs); BF16 TFLOP/s = "
+           f"512 x SQ_INSTS_VALU_MFMA_MOPS_BF16 / duration, against {BF16_PEAK_TFLOPS:.0f} TFLOP/s dense.", "",
+           "| kernel | dispatches | mean us | MFMA busy % | BF16 TFLOP/s | of peak |",
+           "|---|---:|---:|---:|---:|---:|"]
+    rows = []
+    tot_dur = tot_fl = tot_busy = tot_act = 0.0
+    for n, disps in acc.items():
+        ds = list(disps.values())
+        dur = sum(d["dur"] for d in ds)
+        busy = sum(d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for d in ds)
+        act = sum(d.get("GRBM_GUI_ACTIVE", 0.0) for d in ds)
+        fl = 512.0 * sum(d.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) for d in ds)
+        rows.append((dur, n, len(ds), busy, act, fl))
+        tot_dur += dur
+        tot_fl += fl
+        tot_busy += busy
+        tot_act += act
+    for dur, n, c, busy, act, fl in sorted(rows, reverse=True):
+        tf = fl / (dur * 1e-9) / 1e12 if dur else 0.0
+        util = 100.0 * busy / (act * SIMDS) if act else 0.0
+        out.append(f"| `{n}` | {c} | {dur / c / 1e3:.2f} | {util:.1f} | {tf:.1f} | {tf / BF16_PEAK_TFLOPS:.4f} |")
+    tf = tot_fl / (tot_dur * 1e-9) / 1e12 if tot_dur else 0.0
+    util = 100.0 * tot_busy / (tot_act * SIMDS) if tot_act else 0.0
+    out.append(f"| all network kernels | {sum(r[2] for r in rows)} | {tot_dur / 1e3:.1f} total | {util:.1f} | "
+               f"{tf:.1f} | {tf / BF16_PEAK_TFLOPS:.4f} |")
+    return "\n".join(out) + "\n"
+
+
 def read_traffic(path):
     """The machine-readable lines of a traffic report, or None if absent."""
     if not os.path.exists(path):
@@ -245,6 +295,10 @@ def main(argv=None):
     k.add_argument("--points", type=int, required=True)
     k.add_argument("--title", required=True)
     k.add_argument("--cmd", required=True)
+    mf = sub.add_parser("mfma")
+    mf.add_argument("db")
+    mf.add_argument("--title", required=True)
+    mf.add_argument("--cmd", required=True)
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "title", "cmd"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
@@ -256,6 +310,8 @@ def main(argv=None):
         print(stats_report(a.db, a.title, a.cmd, a.top), end="")
     elif a.mode == "kernels":
         print(kernels_report(a.db, a.points, a.title, a.cmd), end="")
+    elif a.mode == "mfma":
+        print(mfma_report(a.db, a.title, a.cmd), end="")
     else:
         print(traffic_report(a), end="")
 
