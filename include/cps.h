@@ -49,7 +49,9 @@ extern "C" {
 #define CPS_ENOMEM (-3)      /* device or host allocation failed */
 #define CPS_EDEVICE (-4)     /* a HIP runtime call failed or no device is present */
 #define CPS_EBREAKDOWN (-5)  /* BiCGSTAB broke down more often than max_restarts allows */
-#define CPS_ENOCONV (-6)     /* max_iters reached; u holds the last iterate, stats are filled */
+#define CPS_ENOCONV (-6)     /* max_iters reached (CPS_MIXED with fp64_finish 0: also a stagnating
+                              * or max_refine-long refinement); u holds the last iterate, stats
+                              * are filled */
 #define CPS_ENAN (-7)        /* the iteration produced NaN/Inf */
 
 #define CPS_FP64 0           /* plain mode: every sweep in FP64 */
@@ -67,7 +69,7 @@ typedef struct cps_options {
     int32_t inner_iters;   /* Chebyshev-Jacobi steps per preconditioner apply (default 24; the
                             * paper's MSI preconditioner runs 8 inner iterations, Sec. 4) */
     int32_t max_iters;     /* cap on BiCGSTAB iterations (summed over refinement steps) */
-    int32_t max_refine;    /* CPS_MIXED: cap on refinement steps */
+    int32_t max_refine;    /* CPS_MIXED: cap on FP32 refinement steps (see fp64_finish) */
     int32_t max_restarts;  /* restarts after breakdown or a failed true-residual check */
     int32_t device_ptrs;   /* 1: array arguments are device pointers */
     int32_t kernel_timing; /* n > 0: time every n-th run of consecutive preconditioner sweeps
@@ -104,7 +106,12 @@ typedef struct cps_options {
      * Sec. 4).  The substitutions run hyperplane by hyperplane (i + j + k = const), one
      * launch each: far slower on a GPU than the parallel inner solvers. */
     int32_t sip_iters;       /* 1..64 (default 8) */
-    int32_t pad;
+    int32_t fp64_finish;     /* CPS_MIXED, 1 (default): when a refinement step reduces
+                              * ||D^-1 r||_2 by less than sqrt(2) (the FP32 solve no longer
+                              * resolves the correction), or max_refine steps or max_restarts
+                              * restarts are spent, continue with FP64 BiCGSTAB from the
+                              * current iterate (stats: iters - iters_fp32 FP64 iterations);
+                              * 0: return CPS_ENOCONV / CPS_EBREAKDOWN there */
     double sip_alpha;        /* in [0, 1] (default 0.9) */
 } cps_options;
 
@@ -156,9 +163,24 @@ int cps_set_rhs(cps_solver *s, const double *f, const double *g);
  * FP64.  u: nx*ny*nz float64; if warm_start is nonzero its unknown entries are the initial
  * guess (NaN/Inf there -> the guess is discarded and 0 used), else the guess is 0.  On
  * return u holds the solution at unknowns, g at wall nodes and 0 at solid nodes.  st may
- * be NULL.  Returns CPS_OK, CPS_ENOCONV, CPS_EBREAKDOWN or CPS_ENAN (u then holds the
- * last finite iterate). */
+ * be NULL.  CPS_MIXED: FP32 BiCGSTAB solves of the correction equation inside FP64
+ * iterative refinement, finished in FP64 if they stagnate (cps_options.fp64_finish).
+ * Returns CPS_OK, CPS_ENOCONV, CPS_EBREAKDOWN or CPS_ENAN (u then holds the last finite
+ * iterate). */
 int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stats *st);
+
+/* Residual history of the last cps_solve on s (Alg. 1's recursive residual).
+ * iter_res[q], q < *n_iter (= stats.iters): ||D^-1 r||_2 / ||D^-1 b||_2 (D = diag B) of the
+ * recursive residual r after the solve's (q+1)-th BiCGSTAB iteration, in the order run; in
+ * CPS_MIXED the FP32 iterations' r is that of the correction equation, which estimates the
+ * FP64 residual of the corrected solution.  true_res[2q], true_res[2q+1], q < *n_true: the
+ * FP64 true residual ||b - B u||_2 / ||b||_2 and ||D^-1 (b - B u)||_2 / ||D^-1 b||_2 before
+ * each restart pass or refinement step, and at the end (the last pair is the final
+ * residual).  At most cap_iter values and cap_true pairs are copied (host pointers; an array
+ * may be NULL when its cap is 0); *n_iter and *n_true (either may be NULL) receive the full
+ * lengths.  CPS_EINVAL for a negative cap or a NULL array with a positive cap. */
+int cps_get_history(cps_solver *s, double *iter_res, int32_t cap_iter, int32_t *n_iter, double *true_res,
+                    int32_t cap_true, int32_t *n_true);
 
 /* r = b - B u at unknown nodes (0 elsewhere), FP64, using the unknown entries of u.
  * r may be NULL.  rel[0] = ||r||_2/||b||_2, rel[1] = ||D^-1 r||_2/||D^-1 b||_2 (rel may be NULL). */
@@ -245,7 +267,16 @@ int cps_model_restrict_noalloc(cps_model *m, cps_solver *s, const double *u, flo
 /* u0 (device, nx*ny*nz FP64) = sigma * trilinear prolongation of the network's prediction
  * for the solver's problem; pass it to cps_solve as the warm start. */
 int cps_model_predict(cps_model *m, cps_solver *s, double *u0);
-int cps_model_save(cps_model *m, const char *path);   /* raw binary with a header */
+/* Write the weights to `path` (raw binary: magic "CPSNET01", the spec, the parameter count,
+ * the FP32 weights).  CPS_EINVAL if the file cannot be written. */
+int cps_model_save(cps_model *m, const char *path);
+/* A training checkpoint: the weights plus the optimiser's state -- Adam's step count and its
+ * two FP32 moment vectors (magic "CPSNET02") -- so that cps_model_train_step continues after
+ * cps_model_load exactly as it would have without the interruption. */
+int cps_model_save_checkpoint(cps_model *m, const char *path);
+/* Read either file into m (whose spec must have the same parameter count).  Weights only:
+ * Adam starts afresh (zero moments, step 0); a checkpoint restores its state too.
+ * CPS_EINVAL for a missing, short or foreign file. */
 int cps_model_load(cps_model *m, const char *path);
 void cps_model_destroy(cps_model *m);
 

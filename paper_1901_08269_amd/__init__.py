@@ -22,6 +22,7 @@ CPS_MIXED = 1
 CPS_PRECOND_CHEBYSHEV = 0
 CPS_PRECOND_MULTIGRID = 1
 CPS_PRECOND_SIP = 2
+CPS_OK, CPS_EINVAL, CPS_EGEOM, CPS_ENOMEM, CPS_EDEVICE, CPS_EBREAKDOWN, CPS_ENOCONV, CPS_ENAN = 0, -1, -2, -3, -4, -5, -6, -7
 ERRORS = {0: "ok", -1: "EINVAL", -2: "EGEOM", -3: "ENOMEM", -4: "EDEVICE", -5: "EBREAKDOWN", -6: "ENOCONV",
           -7: "ENAN"}
 
@@ -33,7 +34,7 @@ class CpsOptions(C.Structure):
                 ("lam_lo", C.c_double), ("lam_hi", C.c_double), ("stream", C.c_void_p),
                 ("precond", C.c_int32), ("mg_levels", C.c_int32), ("mg_nu", C.c_int32),
                 ("mg_coarse_steps", C.c_int32), ("mg_smooth_lo", C.c_double), ("sip_iters", C.c_int32),
-                ("pad", C.c_int32), ("sip_alpha", C.c_double)]
+                ("fp64_finish", C.c_int32), ("sip_alpha", C.c_double)]
 
 
 class CpsStats(C.Structure):
@@ -84,11 +85,13 @@ def load_library(path: str = LIB_PATH):
     L.cps_get_rhs.argtypes = [vp, dp, dp]
     L.cps_get_info.argtypes = [vp, C.POINTER(C.c_int64)]
     L.cps_get_irregular.argtypes = [vp, dp, dp, dp, dp, dp]
+    pi32 = C.POINTER(C.c_int32)
+    L.cps_get_history.argtypes = [vp, dp, i32, pi32, dp, i32, pi32]
     L.cps_destroy.argtypes = [vp]
     L.cps_strerror.restype = C.c_char_p
     L.cps_strerror.argtypes = [C.c_int]
     for name in ("cps_setup", "cps_set_rhs", "cps_solve", "cps_residual", "cps_apply", "cps_precond", "cps_get_rhs",
-                 "cps_get_info", "cps_get_irregular"):
+                 "cps_get_info", "cps_get_irregular", "cps_get_history"):
         getattr(L, name).restype = C.c_int
     L.cps_destroy.restype = None
     _lib = L
@@ -131,7 +134,7 @@ class Solver:
     def __init__(self, x, y, z, phi, g, f, precision="fp64", inner_iters=None, lam_lo=None, lam_hi=None,
                  inner_tol=1e-4, max_iters=20000, max_refine=40, max_restarts=5, kernel_timing=False,
                  precond=None, mg_levels=None, mg_nu=None, mg_coarse_steps=None, mg_smooth_lo=None,
-                 sip_iters=None, sip_alpha=None):
+                 sip_iters=None, sip_alpha=None, fp64_finish=None):
         torch = _torch()
         L = load_library()
         self.L = L
@@ -154,7 +157,8 @@ class Solver:
             o.precond = {"chebyshev": CPS_PRECOND_CHEBYSHEV, "multigrid": CPS_PRECOND_MULTIGRID,
                          "sip": CPS_PRECOND_SIP}[precond]
         for name, val in (("mg_levels", mg_levels), ("mg_nu", mg_nu), ("mg_coarse_steps", mg_coarse_steps),
-                          ("mg_smooth_lo", mg_smooth_lo), ("sip_iters", sip_iters), ("sip_alpha", sip_alpha)):
+                          ("mg_smooth_lo", mg_smooth_lo), ("sip_iters", sip_iters), ("sip_alpha", sip_alpha),
+                          ("fp64_finish", None if fp64_finish is None else int(fp64_finish))):
             if val is not None:
                 setattr(o, name, val)
         o.device_ptrs = 1
@@ -209,6 +213,19 @@ class Solver:
         if check and rc != 0:
             raise CpsError(rc, "cps_solve")
         return out, stats
+
+    def history(self):
+        """Residual history of the last solve (numpy): the recursive ||D^-1 r|| / ||D^-1 b||
+        after every BiCGSTAB iteration, and the true (||r|| / ||b||, ||D^-1 r|| / ||D^-1 b||)
+        before every restart pass or refinement step and at the end (shape (n, 2))."""
+        import numpy as np
+        ni, nt = C.c_int32(), C.c_int32()
+        self._check(self.L.cps_get_history(self.h, None, 0, C.byref(ni), None, 0, C.byref(nt)), "cps_get_history")
+        it = np.zeros(max(ni.value, 1))
+        tr = np.zeros((max(nt.value, 1), 2))
+        self._check(self.L.cps_get_history(self.h, it.ctypes.data, ni.value, C.byref(ni), tr.ctypes.data, nt.value,
+                                           C.byref(nt)), "cps_get_history")
+        return it[:ni.value], tr[:nt.value]
 
     def residual(self, u):
         torch = _torch()

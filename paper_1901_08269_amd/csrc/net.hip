@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -1010,20 +1011,42 @@ int cps_model_predict(cps_model *m, cps_solver *s, double *u0)
     return CPS_OK;
 }
 
-int cps_model_save(cps_model *m, const char *path)
+namespace {
+
+// File layout: 8-byte magic, the spec, nparam (long), then the FP32 weights; a checkpoint
+// ("CPSNET02") adds the Adam step count (int64) and the two FP32 moment vectors.
+int write_model(cps_model *m, const char *path, bool with_optimizer)
 {
     if (!m || !path) return CPS_EINVAL;
-    std::vector<float> h(m->nparam);
-    if (cps_model_get_params(m, h.data(), nullptr, m->nparam) != CPS_OK) return CPS_EDEVICE;
+    const size_t n = (size_t)m->nparam;
+    std::vector<float> h(with_optimizer ? 3 * n : n);
+    try {
+        nck(hipMemcpyAsync(h.data(), m->w, sizeof(float) * n, hipMemcpyDeviceToHost, m->stream));
+        if (with_optimizer) {
+            nck(hipMemcpyAsync(h.data() + n, m->m1, sizeof(float) * n, hipMemcpyDeviceToHost, m->stream));
+            nck(hipMemcpyAsync(h.data() + 2 * n, m->m2, sizeof(float) * n, hipMemcpyDeviceToHost, m->stream));
+        }
+        nck(hipStreamSynchronize(m->stream));
+    } catch (NetFail &f) {
+        return f.code;
+    }
     FILE *fp = std::fopen(path, "wb");
     if (!fp) return CPS_EINVAL;
-    const char magic[8] = {'C', 'P', 'S', 'N', 'E', 'T', '0', '1'};
+    const char *magic = with_optimizer ? "CPSNET02" : "CPSNET01";
+    const int64_t t = m->adam_t;
     bool ok = std::fwrite(magic, 1, 8, fp) == 8 && std::fwrite(&m->spec, sizeof(m->spec), 1, fp) == 1 &&
               std::fwrite(&m->nparam, sizeof(m->nparam), 1, fp) == 1 &&
+              (!with_optimizer || std::fwrite(&t, sizeof(t), 1, fp) == 1) &&
               std::fwrite(h.data(), sizeof(float), h.size(), fp) == h.size();
-    std::fclose(fp);
+    ok = (std::fclose(fp) == 0) && ok;
     return ok ? CPS_OK : CPS_EINVAL;
 }
+
+}  // namespace
+
+int cps_model_save(cps_model *m, const char *path) { return write_model(m, path, false); }
+
+int cps_model_save_checkpoint(cps_model *m, const char *path) { return write_model(m, path, true); }
 
 int cps_model_load(cps_model *m, const char *path)
 {
@@ -1033,16 +1056,31 @@ int cps_model_load(cps_model *m, const char *path)
     char magic[8];
     cps_model_spec sp;
     long np = 0;
-    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, "CPSNET01", 8) == 0 &&
-              std::fread(&sp, sizeof(sp), 1, fp) == 1 && std::fread(&np, sizeof(np), 1, fp) == 1 && np == m->nparam;
+    int64_t t = 0;
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::fread(&sp, sizeof(sp), 1, fp) == 1 &&
+              std::fread(&np, sizeof(np), 1, fp) == 1 && np == m->nparam;
+    const bool ckpt = ok && std::memcmp(magic, "CPSNET02", 8) == 0;
+    ok = ok && (ckpt || std::memcmp(magic, "CPSNET01", 8) == 0);
+    if (ok && ckpt) ok = std::fread(&t, sizeof(t), 1, fp) == 1 && t >= 0 && t <= (int64_t)INT32_MAX;
     std::vector<float> h;
     if (ok) {
-        h.resize(np);
+        h.resize(ckpt ? 3 * (size_t)np : (size_t)np);
         ok = std::fread(h.data(), sizeof(float), h.size(), fp) == h.size();
     }
     std::fclose(fp);
     if (!ok) return CPS_EINVAL;
-    return cps_model_set_params(m, h.data(), np);
+    // the weights (and a fresh optimiser); a checkpoint then restores Adam's moments and step
+    const int rc = cps_model_set_params(m, h.data(), np);
+    if (rc != CPS_OK || !ckpt) return rc;
+    try {
+        nck(hipMemcpyAsync(m->m1, h.data() + np, sizeof(float) * np, hipMemcpyHostToDevice, m->stream));
+        nck(hipMemcpyAsync(m->m2, h.data() + 2 * np, sizeof(float) * np, hipMemcpyHostToDevice, m->stream));
+        nck(hipStreamSynchronize(m->stream));
+    } catch (NetFail &f) {
+        return f.code;
+    }
+    m->adam_t = (int)t;
+    return CPS_OK;
 }
 
 void cps_model_destroy(cps_model *m) { free_model(m); }

@@ -111,6 +111,11 @@ struct cps_solver {
     std::vector<char> tev_ok;       // per timed run: ran (not after the solve had converged)
     std::vector<int> tev_n;         // per timed run: sweeps in it
     std::vector<int> tev_vec;       // per timed run: vectors its sweeps read and write, summed
+    // residual history of the last solve: per iteration the recursive ||D^-1 r|| / ||D^-1 b||,
+    // per restart pass or refinement step the true (||r||/||b||, ||D^-1 r||/||D^-1 b||)
+    std::vector<double> hist_iter, hist_true;
+    int hist_it0 = 0;               // DevState.iters when the current run of iterations began
+    int hist_run = 0;               // iterations of the current run recorded
     Vecs<double> v64;
     Vecs<float> v32;
     double *tmp64 = nullptr;      // user-facing staging (residual, apply, precond)
@@ -736,6 +741,24 @@ void enqueue_iteration(cps_solver *s, Vecs<T> &V, TXS *xsol, const double *c1, c
     launch_update<T, TXS>(L, cf, ir, xsol, V.ph, V.sh, V.s, V.t, V.r0, V.r, s->st);  // x, r, beta
 }
 
+// Residual history: record the recursive residual of every iteration of the current run
+// that the state h has completed (each iteration's state is read once it is done; an
+// iteration whose state was never read, which the polling below does not produce, would
+// be recorded as NaN).
+void note_state(cps_solver *s, const DevState &h)
+{
+    const int k = h.iters - s->hist_it0;
+    const double bs = s->bs2 > 0.0 ? s->bs2 : 1.0;
+    for (; s->hist_run < k; ++s->hist_run)
+        s->hist_iter.push_back(s->hist_run == k - 1 ? std::sqrt(h.rn2s / bs) : std::nan(""));
+}
+
+void note_true(cps_solver *s, const DevState &d)
+{
+    s->hist_true.push_back(std::sqrt(d.res2 / (s->bn2 > 0.0 ? s->bn2 : 1.0)));
+    s->hist_true.push_back(std::sqrt(d.res2s / (s->bs2 > 0.0 ? s->bs2 : 1.0)));
+}
+
 // run iterations until the device reports done or `budget` iterations were enqueued;
 // the host polls the state of iteration n-1 while iteration n is queued.
 template <typename T, typename TXS>
@@ -755,6 +778,7 @@ DevState run_iterations_enqueue(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget
         if (n >= 1) {
             ck(hipEventSynchronize(s->ev[(n - 1) & 1]));
             const DevState &h = s->hst[(n - 1) & 1];
+            note_state(s, h);
             if (h.done) break;
             r2 = r1;
             r1 = h.rn2s;
@@ -762,6 +786,7 @@ DevState run_iterations_enqueue(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget
             // within a factor 16 of the threshold
             if (r2 > 0.0 && r1 * std::min(1.0, r1 / r2) <= 16.0 * h.stop2) {
                 ck(hipEventSynchronize(s->ev[n & 1]));
+                note_state(s, s->hst[n & 1]);
                 if (s->hst[n & 1].done) break;
             }
         }
@@ -774,7 +799,10 @@ DevState run_iterations(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget, const 
 {
     const int64_t base = s->iter_enq;
     const int it0 = read_state(s).iters;
+    s->hist_it0 = it0;
+    s->hist_run = 0;
     DevState out = run_iterations_enqueue<T, TXS>(s, V, xsol, budget, c1, c2);
+    note_state(s, out);
     // the iterations queued after the converged one return at once: their timed sweeps are
     // left out of the sweep timing
     const int64_t done = base + (out.iters - it0);
@@ -1209,7 +1237,7 @@ void cps_default_options(cps_options *o)
     o->mg_coarse_steps = 8;
     o->mg_smooth_lo = 0.2;
     o->sip_iters = 8;
-    o->pad = 0;
+    o->fp64_finish = 1;
     o->sip_alpha = 0.9;
 }
 
@@ -1255,6 +1283,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
     if (o.precond != CPS_PRECOND_CHEBYSHEV && o.precond != CPS_PRECOND_MULTIGRID && o.precond != CPS_PRECOND_SIP)
         return CPS_EINVAL;
     if (o.sip_iters < 1 || o.sip_iters > MAX_INNER || !(o.sip_alpha >= 0.0 && o.sip_alpha <= 1.0)) return CPS_EINVAL;
+    if (o.fp64_finish != 0 && o.fp64_finish != 1) return CPS_EINVAL;
     if (o.mg_levels < 1 || o.mg_levels > MG_MAX_LEVELS || o.mg_nu < 1 || o.mg_nu > MAX_INNER ||
         o.mg_coarse_steps < 1 || o.mg_coarse_steps > MAX_INNER || !(o.mg_smooth_lo > 0.0) ||
         !(o.mg_smooth_lo < o.lam_hi))
@@ -1405,13 +1434,15 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
         s->tev_used = 0;
         s->sweep_count = 0;
         s->iter_enq = 0;
+        s->hist_iter.clear();
+        s->hist_true.clear();
         const int m = s->opt.inner_iters;
         double c1[MAX_INNER], c2[MAX_INNER];
         cheb_coefficients(m, s->opt.lam_lo, s->opt.lam_hi, c1, c2);
         const Launch L = s->launch();
         const double tol2 = tol * tol;
         // FP64 solution vector (unknown entries only); the FP64 Krylov set only in FP64 mode
-        if (s->opt.precision == CPS_FP64) alloc_vecs<double>(s, s->v64);
+        if (s->opt.precision == CPS_FP64) alloc_vecs<double>(s, s->v64);   // x64 is its x
         if (s->opt.precond == CPS_PRECOND_MULTIGRID) {
             if (s->opt.precision == CPS_FP64) mg_alloc<double>(s); else mg_alloc<float>(s);
         }
@@ -1440,32 +1471,60 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
             if (d.res2 > tol2 * s->bn2 && d.res2 > 0.0) t2 = std::min(t2, d.res2s * (tol2 * s->bn2 / d.res2));
             return t2;
         };
-        if (s->opt.precision == CPS_FP64) {
+        // FP64 BiCGSTAB from the current x64 until the true residual converges; a new pass
+        // restarts from the true residual after a breakdown or when the recursive residual
+        // reached its target but the true one did not
+        auto fp64_passes = [&]() -> int {
+            alloc_vecs<double>(s, s->v64);
+            if (s->opt.precond == CPS_PRECOND_MULTIGRID) mg_alloc<double>(s);
             Vecs<double> &V = s->v64;
-            for (int pass = 0;; ++pass) {
+            for (int pass = 0, r64 = 0;; ++pass) {
                 launch_apply<double, double>(MODE_RES, L, s->cf64(), s->ir64(), x64, V.r, nullptr, s->rhs, s->st);
                 ds = read_state(s);
-                if (!(ds.res2 == ds.res2) || !(ds.res2s == ds.res2s)) { status = CPS_ENAN; break; }
-                if (converged(ds)) { status = CPS_OK; break; }
-                if (iters >= s->opt.max_iters) { status = CPS_ENOCONV; break; }
-                if (pass > 0 && ++restarts > s->opt.max_restarts) { status = CPS_EBREAKDOWN; break; }
+                note_true(s, ds);
+                if (!(ds.res2 == ds.res2) || !(ds.res2s == ds.res2s)) return CPS_ENAN;
+                if (converged(ds)) return CPS_OK;
+                if (iters >= s->opt.max_iters) return CPS_ENOCONV;
+                if (pass > 0) {
+                    ++restarts;
+                    if (++r64 > s->opt.max_restarts) return CPS_EBREAKDOWN;
+                }
                 set_stop2(s, jacobi_target(ds));
                 launch_restart<double>(L, s->ir64(), V.r, V.r0, V.p, V.v, s->st);
                 DevState d0 = read_state(s);
                 DevState d1 = d0.done ? d0 : run_iterations<double, double>(s, V, x64, s->opt.max_iters - iters, c1, c2);
                 iters += d1.iters - d0.iters;
-                if (d1.done == 3) { status = CPS_ENAN; break; }
+                if (d1.done == 3) return CPS_ENAN;
             }
+        };
+        if (s->opt.precision == CPS_FP64) {
+            status = fp64_passes();
         } else {
             alloc_vecs<float>(s, s->v32);
             Vecs<float> &V = s->v32;
+            double prev2 = -1.0;     // ||D^-1 r||^2 before the last refinement step
+            bool finish64 = false;
             for (refine = 0;; ++refine) {
                 launch_apply<double, float>(MODE_RES, L, s->cf64(), s->ir64(), x64, V.r, nullptr, s->rhs, s->st);
                 ds = read_state(s);
+                note_true(s, ds);
                 if (!(ds.res2 == ds.res2) || !(ds.res2s == ds.res2s)) { status = CPS_ENAN; break; }
                 if (converged(ds)) { status = CPS_OK; break; }
-                if (iters >= s->opt.max_iters || refine >= s->opt.max_refine) { status = CPS_ENOCONV; break; }
-                if (restarts > s->opt.max_restarts) { status = CPS_EBREAKDOWN; break; }
+                if (iters >= s->opt.max_iters) { status = CPS_ENOCONV; break; }
+                // Every step asks its FP32 solve for at least a 4x reduction of ||D^-1 r||^2;
+                // one that reduced it by less than 2x has stagnated (FP32 cannot resolve the
+                // correction).  Then, or when the step or restart budget is spent, the solve
+                // continues in FP64 (fp64_finish) or stops.
+                const bool stalled = prev2 >= 0.0 && !(ds.res2s <= 0.5 * prev2);
+                if (stalled || refine >= s->opt.max_refine || restarts > s->opt.max_restarts) {
+                    if (s->opt.fp64_finish) {
+                        finish64 = true;
+                    } else {
+                        status = (restarts > s->opt.max_restarts) ? CPS_EBREAKDOWN : CPS_ENOCONV;
+                    }
+                    break;
+                }
+                prev2 = ds.res2s;
                 // each FP32 solve reduces the residual by inner_tol, the last one just enough
                 double target2 = std::max(s->opt.inner_tol * s->opt.inner_tol * ds.res2s, 0.25 * jacobi_target(ds));
                 set_stop2(s, target2);
@@ -1478,6 +1537,10 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
                 if (d1.done == 3) { ++restarts; continue; }   // discard a non-finite correction
                 if (d1.done == 2) ++restarts;
                 launch_add_correction(s->stream, s->nn, x64, V.x);
+            }
+            if (finish64) {
+                s->hist_true.resize(s->hist_true.size() - 2);   // the first FP64 pass recomputes it
+                status = fp64_passes();
             }
         }
         // output: unknowns, g on the walls, 0 in the bodies
@@ -1625,6 +1688,19 @@ int cps_get_irregular(cps_solver *s, int64_t *node, int64_t *ptr, int64_t *col, 
     } catch (HipFail &) {
         return CPS_EDEVICE;
     }
+    return CPS_OK;
+}
+
+int cps_get_history(cps_solver *s, double *iter_res, int32_t cap_iter, int32_t *n_iter, double *true_res,
+                    int32_t cap_true, int32_t *n_true)
+{
+    if (!s || cap_iter < 0 || cap_true < 0 || (cap_iter > 0 && !iter_res) || (cap_true > 0 && !true_res))
+        return CPS_EINVAL;
+    const size_t ni = s->hist_iter.size(), nt = s->hist_true.size() / 2;
+    std::copy_n(s->hist_iter.begin(), std::min<size_t>(ni, (size_t)cap_iter), iter_res);
+    std::copy_n(s->hist_true.begin(), 2 * std::min<size_t>(nt, (size_t)cap_true), true_res);
+    if (n_iter) *n_iter = (int32_t)ni;
+    if (n_true) *n_true = (int32_t)nt;
     return CPS_OK;
 }
 

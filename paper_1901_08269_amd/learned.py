@@ -52,12 +52,13 @@ def _bind(L):
     L.cps_model_restrict_noalloc.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double)]
     L.cps_model_predict.argtypes = [vp, vp, vp]
     L.cps_model_save.argtypes = [vp, C.c_char_p]
+    L.cps_model_save_checkpoint.argtypes = [vp, C.c_char_p]
     L.cps_model_load.argtypes = [vp, C.c_char_p]
     L.cps_model_destroy.argtypes = [vp]
     L.cps_model_destroy.restype = None
     for n in ("cps_model_create", "cps_model_set_params", "cps_model_get_params", "cps_model_forward",
               "cps_model_train_step", "cps_model_restrict", "cps_model_restrict_noalloc", "cps_model_predict",
-              "cps_model_save", "cps_model_load"):
+              "cps_model_save", "cps_model_save_checkpoint", "cps_model_load"):
         getattr(L, n).restype = C.c_int
     L._net_bound = True
     return L
@@ -158,7 +159,13 @@ class Model:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         self._ck(self.L.cps_model_save(self.h, path.encode()), "save")
 
+    def save_checkpoint(self, path):
+        """Weights plus Adam's step count and moments, so training resumes exactly."""
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        self._ck(self.L.cps_model_save_checkpoint(self.h, path.encode()), "save_checkpoint")
+
     def load(self, path):
+        """Weights (Adam restarts) or a checkpoint (Adam's state restored too)."""
         self._ck(self.L.cps_model_load(self.h, path.encode()), "load")
 
 

@@ -107,6 +107,41 @@ def test_training_reduces_loss_and_save_load(tmp_path):
     assert float((p1 - p2).abs().max()) == 0.0
 
 
+def test_checkpoint_resumes_training_exactly(tmp_path):
+    """A checkpoint carries Adam's step count and moments: training resumed from it takes the
+    same steps as uninterrupted training, bit for bit (the kernels reduce in a fixed order).
+    A weights-only file restarts Adam, which then takes a different step."""
+    inp, tgt, msk = _batch(8, 2, 11)
+    m = learned.Model(8, batch=2, seed=5)
+    for _ in range(3):
+        m.train_step(inp, tgt, msk, lr=2e-3)
+    ck = str(tmp_path / "ck.bin")
+    wo = str(tmp_path / "w.bin")
+    m.save_checkpoint(ck)
+    m.save(wo)
+    assert os.path.getsize(ck) > 2.9 * os.path.getsize(wo)
+    for _ in range(2):
+        m.train_step(inp, tgt, msk, lr=2e-3)
+    ref = m.params()
+    r = learned.Model(8, batch=2, seed=77)
+    r.load(ck)
+    for _ in range(2):
+        r.train_step(inp, tgt, msk, lr=2e-3)
+    got = r.params()
+    print(f"resumed vs uninterrupted: max |dw| {np.abs(got - ref).max():.3e}")
+    assert np.array_equal(got, ref)
+    f = learned.Model(8, batch=2, seed=77)
+    f.load(wo)
+    for _ in range(2):
+        f.train_step(inp, tgt, msk, lr=2e-3)
+    assert not np.array_equal(f.params(), ref)
+    bad = str(tmp_path / "bad.bin")
+    with open(bad, "wb") as fh:
+        fh.write(b"CPSNET03" + bytes(64))
+    with pytest.raises(cps.CpsError):
+        r.load(bad)
+
+
 def test_restrict_all_channels_vs_oracle():
     """The network input of a problem (cell means of f, phi, g with the sigma scaling, and the
     target's cell means of u) against the oracle's restriction, every channel."""
