@@ -72,11 +72,11 @@ typedef struct cps_options {
     int32_t max_refine;    /* CPS_MIXED: cap on FP32 refinement steps (see fp64_finish) */
     int32_t max_restarts;  /* restarts after breakdown or a failed true-residual check */
     int32_t device_ptrs;   /* 1: array arguments are device pointers */
-    int32_t kernel_timing; /* n > 0: time every n-th run of consecutive preconditioner sweeps
-                            * on the problem's grid that read an x_{k-1} (multigrid: steps
-                            * 1 .. mg_nu - 1 of a post-smoothing pass; Chebyshev: steps
-                            * 2 .. inner_iters - 1), with one pair of HIP
-                            * events per run (stats; each pair adds a few microseconds); runs
+    int32_t kernel_timing; /* n > 0: time the preconditioner sweeps on the problem's grid that
+                            * read an x_{k-1} (multigrid: steps 1 .. mg_nu - 1 of a
+                            * post-smoothing pass; Chebyshev: steps 2 .. inner_iters - 1) in
+                            * every n-th such run of sweeps, each by a pair of HIP events that
+                            * its launch stamps with the kernel's start and end (stats); sweeps
                             * queued after convergence are left out; 0: off */
     double inner_tol;      /* CPS_MIXED: residual reduction asked of each FP32 inner solve */
     double lam_lo, lam_hi; /* Chebyshev interval for the spectrum of diag(K)^-1 K (default
@@ -127,8 +127,8 @@ typedef struct cps_stats {
     double rel_residual_jacobi; /* ||D^-1 (b - B u)||_2 / ||D^-1 b||_2, D = diag(B) */
     double min_ibi_frac;        /* min over IBIs of |x_fluid - x_IBI| / segment length */
     double setup_ms, solve_ms;
-    double sweep_ms;            /* kernel_timing: summed duration of the timed runs of
-                                 * preconditioner sweeps (launch gaps inside a run included) */
+    double sweep_ms;            /* kernel_timing: summed execution time of the timed sweeps
+                                 * (kernel start to end; no launch gaps) */
     int64_t sweep_launches;     /* kernel_timing: number of sweeps in them */
     int64_t sweep_points;       /* interior points one sweep processes */
     double sweep_bytes;         /* kernel_timing: algorithmic bytes the timed sweeps move (every

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "cps.h"
@@ -105,12 +106,12 @@ struct cps_solver {
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> tev;  // sweep timing events
     size_t tev_used = 0;
-    int64_t sweep_count = 0;      // sweeps enqueued since the solve started (timing sample)
+    int64_t sweep_count = 0;      // runs of full-traffic sweeps since the solve started (timing sample)
     int64_t iter_enq = 0;         // BiCGSTAB iterations enqueued since the solve started
-    std::vector<int64_t> tev_iter;  // per timed run of sweeps: the iteration it belongs to
-    std::vector<char> tev_ok;       // per timed run: ran (not after the solve had converged)
-    std::vector<int> tev_n;         // per timed run: sweeps in it
-    std::vector<int> tev_vec;       // per timed run: vectors its sweeps read and write, summed
+    std::vector<int64_t> tev_iter;  // per timed sweep: the iteration it belongs to
+    std::vector<char> tev_ok;       // per timed sweep: ran (not after the solve had converged)
+    std::vector<int> tev_n;         // per timed sweep: sweeps (1)
+    std::vector<int> tev_vec;       // per timed sweep: vectors it reads and writes
     // residual history of the last solve: per iteration the recursive ||D^-1 r|| / ||D^-1 b||,
     // per restart pass or refinement step the true (||r||/||b||, ||D^-1 r||/||D^-1 b||)
     std::vector<double> hist_iter, hist_true;
@@ -416,15 +417,19 @@ hipEvent_t timing_event(cps_solver *s)
     return s->tev[s->tev_used++];
 }
 
-// Sweep timing: a run of `nsweeps` consecutive preconditioner sweeps on the problem's grid
-// (which together read and write `nvec` vectors) is bracketed by one pair of events, every
-// kernel_timing-th such run (an event pair costs a few microseconds of queue time, so timing
-// is sampled; the run's time includes the launch gaps between its sweeps).  Returns the
-// closing event, to be recorded after the run, or null.
-hipEvent_t timed_run_begin(cps_solver *s, int nsweeps, int nvec)
+// Sweep timing: every kernel_timing-th run of consecutive full-traffic preconditioner sweeps
+// on the problem's grid is sampled (sampled_run); each of its sweeps gets a pair of events
+// that its launch stamps with the kernel's own start and end (timed_sweep), so the timing
+// holds the sweeps' execution and no launch gaps or queue time.
+bool sampled_run(cps_solver *s)
 {
     const int period = s->opt.kernel_timing;
-    if (period <= 0 || nsweeps <= 0 || (s->sweep_count++ % period) != 0) return nullptr;
+    return period > 0 && (s->sweep_count++ % period) == 0;
+}
+
+// events for one timed sweep that reads and writes `nvec` vectors
+std::pair<hipEvent_t, hipEvent_t> timed_sweep(cps_solver *s, int nvec)
+{
     hipEvent_t e0 = timing_event(s), e1 = timing_event(s);
     const size_t pair = s->tev_used / 2 - 1;
     if (s->tev_iter.size() <= pair) {
@@ -435,10 +440,9 @@ hipEvent_t timed_run_begin(cps_solver *s, int nsweeps, int nvec)
     }
     s->tev_iter[pair] = s->iter_enq;
     s->tev_ok[pair] = 1;
-    s->tev_n[pair] = nsweeps;
+    s->tev_n[pair] = 1;
     s->tev_vec[pair] = nvec;
-    ck(hipEventRecord(e0, s->stream));
-    return e1;
+    return {e0, e1};
 }
 
 // ---- multigrid V-cycle on K (the inner solver of the preconditioner, Sec. 3.3) ----------
@@ -521,16 +525,16 @@ T *mg_smooth(cps_solver *s, int lvl, const Launch &L, const Coef<T> &cf, const I
 {
     T *odd = x0 ? b : a, *even = x0 ? a : b;
     auto buf = [&](int j) -> T * { return j == 0 ? (x0 ? x0 : (T *)zero) : ((j & 1) ? odd : even); };
-    hipEvent_t e1 = nullptr;
+    // a timed run is the full-traffic part of a post-smoothing pass (steps 1 .. n - 1 from
+    // x0, each reading x_k, x_{k-1} and rho and writing x_{k+1})
+    const bool sample = timed && x0 && k0 <= 1 && n > 1 && sampled_run(s);
     for (int k = k0; k < n; ++k) {
         const T *xm1 = (k == 0) ? nullptr : (k == 1 ? (const T *)x0 : buf(k - 1));
         T *out = (k == n - 1 && dst) ? dst : buf(k + 1);
-        // a timed run is the full-traffic part of a post-smoothing pass (steps 1 .. n - 1 from
-        // x0, each reading x_k, x_{k-1} and rho and writing x_{k+1})
-        if (timed && x0 && k == 1) e1 = timed_run_begin(s, n - 1, 4 * (n - 1));
-        launch_cheb<T>(L, cf, ir, buf(k), xm1, rho, out, c1[k], c2[k], st, next_rev(s, lvl));
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        if (sample && k >= 1) ev = timed_sweep(s, 4);
+        launch_cheb<T>(L, cf, ir, buf(k), xm1, rho, out, c1[k], c2[k], st, next_rev(s, lvl), ev.first, ev.second);
     }
-    if (e1) ck(hipEventRecord(e1, s->stream));
     return dst ? dst : buf(n);
 }
 
@@ -717,13 +721,13 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
     const int m = s->opt.inner_iters;
     auto buf = [&](int j) { return (j == m) ? dst : V.c[j % 2]; };
     launch_first<T>(kind, L, cf, ir, r, ps, v, buf(1), c2[0], st);
-    hipEvent_t e1 = nullptr;
+    const bool sample = m > 2 && sampled_run(s);     // steps 2 .. m-1 read an x_{k-1}
     for (int k = 1; k < m; ++k) {
-        if (k == 2) e1 = timed_run_begin(s, m - 2, 4 * (m - 2));   // steps 2 .. m-1 read an x_{k-1}
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        if (sample && k >= 2) ev = timed_sweep(s, 4);
         launch_cheb<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), c1[k], c2[k], st,
-                       next_rev(s, 0));
+                       next_rev(s, 0), ev.first, ev.second);
     }
-    if (e1) ck(hipEventRecord(e1, s->stream));
 }
 
 // one BiCGSTAB iteration (Alg. 1) entirely on the device

@@ -10,6 +10,8 @@
 // nodes with 16-byte vectors.  Kernels that reduce write one partial per block; a one-block finalize
 // kernel that follows sums them in a fixed order (deterministic) and updates the
 // device-resident BiCGSTAB scalars, so the host never waits inside an iteration.
+#include <hip/hip_ext.h>
+
 #include "cps_device.h"
 #include "cps_kernels.h"
 
@@ -927,7 +929,7 @@ void launch_apply(int mode, const Launch &L, const Coef<T> &cf, const Irr<T> &ir
 
 template <typename T>
 void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
-                 double c1, double c2, const DevState *st, int rev)
+                 double c1, double c2, const DevState *st, int rev, hipEvent_t ev0, hipEvent_t ev1)
 {
     dim3 grid(L.g.tr.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
     const bool mr = L.g.lg < 6;
@@ -939,6 +941,9 @@ void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *
                                                                rev);
     } else {
         if (mr) k_cheb4m<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
+        else if (ev0)
+            hipExtLaunchKernelGGL((k_cheb4<T, false>), grid, blk, 0, L.stream, ev0, ev1, 0, L.g, cf, ir, L.skip, xc, xm1,
+                                  rho, xn, (T)c1, (T)c2, st, rev);
         else k_cheb4<T, false><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
     }
 }
@@ -1031,9 +1036,10 @@ template void launch_apply<double, float>(int, const Launch &, const Coef<double
 template void launch_apply<float, float>(int, const Launch &, const Coef<float> &, const Irr<float> &, const float *,
                                          float *, const float *, const double *, DevState *);
 template void launch_cheb<double>(const Launch &, const Coef<double> &, const Irr<double> &, const double *,
-                                  const double *, const double *, double *, double, double, const DevState *, int);
+                                  const double *, const double *, double *, double, double, const DevState *, int,
+                                  hipEvent_t, hipEvent_t);
 template void launch_cheb<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
-                                 const float *, float *, double, double, const DevState *, int);
+                                 const float *, float *, double, double, const DevState *, int, hipEvent_t, hipEvent_t);
 template void launch_resid<double>(const Launch &, const Coef<double> &, const Irr<double> &, const double *,
                                    const double *, double *, const DevState *, int);
 template void launch_resid<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,

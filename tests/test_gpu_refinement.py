@@ -1,7 +1,7 @@
 """GPU tests of the bookkeeping around Alg. 1: the residual history cps_get_history returns,
-checked against the oracle's residual of the same iterate, and the FP64 finish of a
+checked against the oracle's residual of the same iterate; the FP64 finish of a
 mixed-precision solve whose FP32 refinement is cut short, checked against the oracle's
-solution."""
+solution; and the sweep timing, which must count the right sweeps and change nothing."""
 import math
 
 import numpy as np
@@ -91,3 +91,22 @@ def test_mixed_solve_finishes_in_fp64_when_refinement_is_cut_short():
     S0 = cps.Solver.from_workload(w, precision="mixed", max_refine=1, fp64_finish=False)
     _, st0 = S0.solve(1e-12, check=False)
     assert st0["status"] == cps.CPS_ENOCONV and st0["iters"] == st0["iters_fp32"] == st["iters_fp32"]
+
+
+@pytest.mark.parametrize("precond", ["multigrid", "chebyshev"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sweep_timing_counts_and_leaves_the_solution_unchanged(precision, precond):
+    """kernel_timing stamps the full-traffic sweeps' own start and end: the stats count them,
+    their bytes are 4 vectors per interior point per sweep, and the solve is bitwise the one
+    without timing."""
+    print(f"[case] sweep timing sphere 40^3 {precision} {precond}", flush=True)
+    w = _sphere()
+    u0, st0 = cps.Solver.from_workload(w, precision=precision, precond=precond).solve(1e-10)
+    u1, st1 = cps.Solver.from_workload(w, precision=precision, precond=precond, kernel_timing=1).solve(1e-10)
+    n, pts = st1["sweep_launches"], st1["sweep_points"]
+    vb = 4 if precision == "mixed" else 8
+    print(f"{n} timed sweeps, {1e3 * st1['sweep_ms'] / max(n, 1):.2f} us each")
+    assert pts == 38 ** 3 and n > 0 and st1["sweep_bytes"] == n * 4 * vb * pts
+    assert 0.0 < st1["sweep_ms"] / n < 5.0
+    assert st0["sweep_launches"] == 0 and st0["sweep_ms"] == 0.0
+    assert st1["iters"] == st0["iters"] and bool((u0 == u1).all())
