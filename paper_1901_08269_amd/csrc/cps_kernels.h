@@ -133,7 +133,8 @@ struct SetupOut {
 };
 
 // 1D tables (FP64) from coordinates; t holds the three coordinate arrays
-void launch_coef(hipStream_t s, int n, const double *t, double *coef);
+// the 1D tables of all three axes (8 values per index; FP64 and FP32, 3 * 8 * nmax each)
+void launch_coef(hipStream_t s, int nx, int ny, int nz, int nmax, const double *xyz, double *coef, float *coef32);
 // classify nodes; flags: bit0 invalid input (NaN/Inf), bit1 a wall node inside a body has a
 // fluid neighbour
 void launch_classify(hipStream_t s, int nx, int ny, int nz, const double *phi, const double *g, const double *f,
@@ -146,11 +147,13 @@ int compact_blocks(size_t n);
 void launch_skipbits(hipStream_t s, const Geom &g, const int8_t *type, uint32_t *skip);
 void launch_irr_words(hipStream_t s, const Geom &g, const int8_t *type, const int *nodes, int nirr, uint32_t *bits,
                       int *wstart);
-// build irregular rows in a fixed-stride scratch (cap entries per row)
+// build irregular rows in a fixed-stride scratch (cap entries per row); ibi_tab: 12 nirr
+// doubles of scratch for the table of IBIs next to the irregular nodes
 void launch_build_rows(hipStream_t s, int nx, int ny, int nz, const double *x, const double *y, const double *z,
                        const double *coef, const double *phi, const double *g, const double *f, const int8_t *type,
-                       int nirr, const int *nodes, int cap, int *ell_col, double *ell_val, int *len, double *rhs_row,
-                       double *k7, double *bdiag, double *minhb, int *fallback, int *bad);
+                       int nirr, const int *nodes, const uint32_t *irr_bits, const int *irr_wstart, double *ibi_tab,
+                       int cap, int *ell_col, double *ell_val, int *len, double *rhs_row, double *k7, double *bdiag,
+                       double *minhb, int *fallback, int *bad);
 // K rows (Shortley-Weller at nodes next to the body) of the irregular nodes only
 void launch_krows(hipStream_t s, int nx, int ny, int nz, const double *x, const double *y, const double *z,
                   const double *phi, const int8_t *type, int nirr, const int *nodes, double *k7);
@@ -164,6 +167,14 @@ void launch_rhs_regular(hipStream_t s, int nx, int ny, int nz, const double *coe
                         const int8_t *type, double *rhs);
 void launch_scatter_rows(hipStream_t s, int nirr, const int *nodes, const double *rhs_row, double *rhs);
 void launch_to_float(hipStream_t s, size_t n, const double *a, float *b);
-void launch_min_reduce(hipStream_t s, int n, const double *a, const int *fb, double *out_min, long long *out_sum);
+// min of a[n] (from 1) and sum of fb[n]; part: 2 * MINR_PARTS doubles of scratch
+constexpr int MINR_PARTS = 128;
+void launch_min_reduce(hipStream_t s, int n, const double *a, const int *fb, double *part, double *out_min,
+                       long long *out_sum);
+// cnt[t] += number of nodes of type t, t = 0..3 (cnt zeroed by the caller)
+void launch_type_hist(hipStream_t s, size_t n, const int8_t *type, int *cnt);
+// per-block partials (||b||^2, ||D^-1 b||^2) over the unknowns, 2 * nblocks doubles
+void launch_bnorms(hipStream_t s, int nx, int ny, int nz, const double *coef, const int8_t *type, const double *b,
+                   int nirr, const int *nodes, const double *bdiag, double *partials, int nblocks);
 
 }  // namespace cps

@@ -27,36 +27,47 @@ namespace cps {
 // ---------------------------------------------------------------------------------------
 // 1D coefficient tables
 // ---------------------------------------------------------------------------------------
-__global__ void k_coef(int n, const double *__restrict__ t, double *__restrict__ coef)
+// The tables of all three axes in one launch: axis d = blockIdx.y, 8 values per index in FP64
+// and FP32; indices n_d .. nmax - 1 of a shorter axis are zero.
+__global__ void k_coef(int nx, int ny, int nz, int nmax, const double *__restrict__ xyz, double *__restrict__ coef,
+                       float *__restrict__ coef32)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double *o = coef + 8 * (size_t)i;
-    for (int q = 0; q < 8; ++q) o[q] = 0.0;
+    const int d = (int)blockIdx.y;
+    const int n = d == 0 ? nx : (d == 1 ? ny : nz);
+    const double *t = xyz + (d == 0 ? 0 : (d == 1 ? nx : nx + ny));
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= nmax) return;
+    double o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (i == 0 || i == n - 1) {
         // wall indices: never used by a row; nonzero diagonals keep flat pointwise
         // kernels finite on the (zero) wall entries
         o[3] = -1.0;
         o[6] = -1.0;
-        return;
+    } else if (i < n) {
+        double hf = t[i + 1] - t[i], hb = t[i] - t[i - 1];
+        // Eq. (app_xxx): denominator (hf + hb)(hf^2 + 3 hf hb + hb^2)
+        double den = hf * hf * hf + 4.0 * hf * hf * hb + 4.0 * hf * hb * hb + hb * hb * hb;
+        o[0] = hf * (hb * hb + hb * hf - hf * hf) / den;        // a
+        o[1] = hb * (hf * hf + hb * hf - hb * hb) / den;        // c
+        o[2] = 12.0 * hf / den;                                 // ar
+        o[3] = -12.0 / (hf * hf + 3.0 * hf * hb + hb * hb);     // br
+        o[4] = 12.0 * hb / den;                                 // cr
+        // Eq. (2ndorder_coef)
+        o[5] = 2.0 / (hb * (hf + hb));
+        o[6] = -2.0 / (hb * hf);
+        o[7] = 2.0 / (hf * (hf + hb));
     }
-    double hf = t[i + 1] - t[i], hb = t[i] - t[i - 1];
-    // Eq. (app_xxx): denominator (hf + hb)(hf^2 + 3 hf hb + hb^2)
-    double den = hf * hf * hf + 4.0 * hf * hf * hb + 4.0 * hf * hb * hb + hb * hb * hb;
-    o[0] = hf * (hb * hb + hb * hf - hf * hf) / den;        // a
-    o[1] = hb * (hf * hf + hb * hf - hb * hb) / den;        // c
-    o[2] = 12.0 * hf / den;                                 // ar
-    o[3] = -12.0 / (hf * hf + 3.0 * hf * hb + hb * hb);     // br
-    o[4] = 12.0 * hb / den;                                 // cr
-    // Eq. (2ndorder_coef)
-    o[5] = 2.0 / (hb * (hf + hb));
-    o[6] = -2.0 / (hb * hf);
-    o[7] = 2.0 / (hf * (hf + hb));
+    const size_t at = 8 * ((size_t)d * nmax + i);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        coef[at + q] = o[q];
+        coef32[at + q] = (float)o[q];
+    }
 }
 
-void launch_coef(hipStream_t s, int n, const double *t, double *coef)
+void launch_coef(hipStream_t s, int nx, int ny, int nz, int nmax, const double *xyz, double *coef, float *coef32)
 {
-    k_coef<<<(n + 255) / 256, 256, 0, s>>>(n, t, coef);
+    k_coef<<<dim3((unsigned)((nmax + 255) / 256), 3), 256, 0, s>>>(nx, ny, nz, nmax, xyz, coef, coef32);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -131,7 +142,25 @@ void launch_mark_irregular(hipStream_t s, int nx, int ny, int nz, int8_t *type)
 // ---------------------------------------------------------------------------------------
 // ordered stream compaction (counts per block -> scan -> scatter)
 // ---------------------------------------------------------------------------------------
-constexpr int CMP_THREADS = 256, CMP_PER_THREAD = 16, CMP_CHUNK = CMP_THREADS * CMP_PER_THREAD;
+constexpr int CMP_THREADS = 256, CMP_PER_THREAD = 32, CMP_CHUNK = CMP_THREADS * CMP_PER_THREAD;
+
+// the CMP_PER_THREAD node types of one thread (from 16-byte loads where the chunk is whole)
+__device__ __forceinline__ void load_types(size_t n, const int8_t *__restrict__ type, size_t base,
+                                           int8_t (&t)[CMP_PER_THREAD])
+{
+    if (base + CMP_PER_THREAD <= n) {
+#pragma unroll
+        for (int h = 0; h < CMP_PER_THREAD / 16; ++h) {
+            const int4 v = *reinterpret_cast<const int4 *>(type + base + 16 * h);
+            const int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int u = 0; u < 16; ++u) t[16 * h + u] = (int8_t)((w[u >> 2] >> (8 * (u & 3))) & 0xff);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < CMP_PER_THREAD; ++q) t[q] = base + q < n ? type[base + q] : (int8_t)-1;
+    }
+}
 
 int compact_blocks(size_t n) { return (int)((n + CMP_CHUNK - 1) / CMP_CHUNK); }
 
@@ -139,9 +168,11 @@ __global__ void k_count(size_t n, const int8_t *__restrict__ type, int8_t want, 
 {
     __shared__ int sh[CMP_THREADS];
     size_t base = (size_t)blockIdx.x * CMP_CHUNK + (size_t)threadIdx.x * CMP_PER_THREAD;
+    int8_t t[CMP_PER_THREAD];
+    load_types(n, type, base, t);
     int c = 0;
-    for (int q = 0; q < CMP_PER_THREAD; ++q)
-        if (base + q < n && type[base + q] == want) ++c;
+#pragma unroll
+    for (int q = 0; q < CMP_PER_THREAD; ++q) c += t[q] == want;
     sh[threadIdx.x] = c;
     __syncthreads();
     for (int o = CMP_THREADS / 2; o > 0; o >>= 1) {
@@ -156,9 +187,11 @@ __global__ void k_scatter(size_t n, const int8_t *__restrict__ type, int8_t want
 {
     __shared__ int sh[CMP_THREADS];
     size_t base = (size_t)blockIdx.x * CMP_CHUNK + (size_t)threadIdx.x * CMP_PER_THREAD;
+    int8_t t[CMP_PER_THREAD];
+    load_types(n, type, base, t);
     int c = 0;
-    for (int q = 0; q < CMP_PER_THREAD; ++q)
-        if (base + q < n && type[base + q] == want) ++c;
+#pragma unroll
+    for (int q = 0; q < CMP_PER_THREAD; ++q) c += t[q] == want;
     sh[threadIdx.x] = c;
     __syncthreads();
     // inclusive scan (Hillis-Steele) over the block
@@ -169,21 +202,30 @@ __global__ void k_scatter(size_t n, const int8_t *__restrict__ type, int8_t want
         __syncthreads();
     }
     int pos = offs[blockIdx.x] + sh[threadIdx.x] - c;
+#pragma unroll
     for (int q = 0; q < CMP_PER_THREAD; ++q)
-        if (base + q < n && type[base + q] == want) list[pos++] = (int)(base + q);
+        if (t[q] == want) list[pos++] = (int)(base + q);
 }
 
-// exclusive scan of n ints by one block; out[n] = total
-__global__ void k_scan(const int *__restrict__ in, int *__restrict__ out, int n)
+// exclusive scan of n ints by one block; out[n] = total.  Each round covers SCAN_PT
+// consecutive elements per thread: a thread sums its run, the block scans the 1024 run sums
+// (Hillis-Steele in LDS), and each thread writes its run's prefixes.
+constexpr int SCAN_PT = 16;
+__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ in, int *__restrict__ out, int n)
 {
     __shared__ int sh[1024];
     __shared__ int carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int base = 0; base < n; base += 1024) {
-        int idx = base + threadIdx.x;
-        int v = idx < n ? in[idx] : 0;
-        sh[threadIdx.x] = v;
+    for (int base = 0; base < n; base += 1024 * SCAN_PT) {
+        const int b0 = base + (int)threadIdx.x * SCAN_PT;
+        int v[SCAN_PT], sum = 0;
+#pragma unroll
+        for (int u = 0; u < SCAN_PT; ++u) {
+            v[u] = b0 + u < n ? in[b0 + u] : 0;
+            sum += v[u];
+        }
+        sh[threadIdx.x] = sum;
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {
             int a = ((int)threadIdx.x >= o) ? sh[threadIdx.x - o] : 0;
@@ -191,7 +233,12 @@ __global__ void k_scan(const int *__restrict__ in, int *__restrict__ out, int n)
             sh[threadIdx.x] += a;
             __syncthreads();
         }
-        if (idx < n) out[idx] = carry + sh[threadIdx.x] - v;
+        int run = carry + sh[threadIdx.x] - sum;
+#pragma unroll
+        for (int u = 0; u < SCAN_PT; ++u) {
+            if (b0 + u < n) out[b0 + u] = run;
+            run += v[u];
+        }
         __syncthreads();
         if (threadIdx.x == 1023) carry += sh[1023];
         __syncthreads();
@@ -284,6 +331,14 @@ struct Ctx {
     const double *coef[3];
     const double *phi, *g, *f;
     const int8_t *type;
+    // optional table of the IBIs next to the irregular nodes (null: found where needed):
+    // entry 6 row + 2 d + s is the IBI on the segment from the row's node toward its -d
+    // (s = 0) or +d (s = 1) neighbour when that neighbour is solid; the row of a node comes
+    // from the irregular-node bits (W words per grid row) and the per-word row counts
+    const double *ibi_t, *ibi_g;
+    const uint32_t *irr_bits;
+    const int *irr_wstart;
+    int W;
 };
 
 constexpr int NSLOT = 27 + 3 * 2 * 4 * 9;   // 3x3x3 box + extra points 2..5 cells out along a line
@@ -386,6 +441,52 @@ __device__ double ibi_on_segment(const Ctx &C, int d, size_t line0, int ifl, int
     }
 }
 
+// The IBI between node index `ifl` (fluid) and its neighbour `isol` (solid) on the line along
+// d through the node with coordinates `base` (base[d] ignored; line0 is its index with
+// base[d] = 0): read from the table when the fluid node is irregular (always, when the
+// neighbour is solid: a fluid node next to a solid one is irregular), else found here.  The
+// table holds the values ibi_on_segment returns, so both routes give the same bits.
+__device__ double ibi_cached(const Ctx &C, int d, const int base[3], size_t line0, int ifl, int isol, double *gval,
+                             double *frac)
+{
+    if (C.ibi_t) {
+        int c[3] = {base[0], base[1], base[2]};
+        c[d] = ifl;
+        const size_t word = ((size_t)c[2] * C.n[1] + c[1]) * C.W + (c[0] >> 5);
+        const uint32_t bits = C.irr_bits[word];
+        if ((bits >> (c[0] & 31)) & 1u) {
+            const size_t row = (size_t)C.irr_wstart[word] + __popc(bits & ((1u << (c[0] & 31)) - 1u));
+            const size_t ent = 6 * row + 2 * d + (isol > ifl ? 1 : 0);
+            const double root = C.ibi_t[ent];
+            const double tf = C.t[d][ifl], tsol = C.t[d][isol];
+            *gval = C.ibi_g[ent];
+            *frac = fabs(root - tf) / fabs(tsol - tf);
+            return root;
+        }
+    }
+    return ibi_on_segment(C, d, line0, ifl, isol, gval, frac);
+}
+
+// The IBI table: one thread per (irregular row, arm); arms toward a neighbour that is not
+// solid are left untouched (never read).
+__global__ void __launch_bounds__(256) k_ibi_table(Ctx C, int nirr, const int *__restrict__ nodes,
+                                                   double *__restrict__ ibi_t, double *__restrict__ ibi_g)
+{
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int row = t / 6, arm = t % 6;
+    if (row >= nirr) return;
+    const int d = arm >> 1, side = arm & 1;
+    const size_t rownode = (size_t)nodes[row];
+    const int nx = C.n[0], ny = C.n[1];
+    const int idx[3] = {(int)(rownode % nx), (int)((rownode / nx) % ny), (int)(rownode / ((size_t)nx * ny))};
+    const size_t nb = side ? rownode + C.stride[d] : rownode - C.stride[d];
+    if (C.type[nb] != 3) return;
+    const size_t line0 = rownode - (size_t)idx[d] * C.stride[d];
+    double gv, fr;
+    ibi_t[6 * (size_t)row + arm] = ibi_on_segment(C, d, line0, idx[d], side ? idx[d] + 1 : idx[d] - 1, &gv, &fr);
+    ibi_g[6 * (size_t)row + arm] = gv;
+}
+
 // Solve the NP x NP system A w = rhs by elimination with row pivoting (row swaps by
 // selects over static indices, so that A stays in registers).
 template <int NP>
@@ -430,11 +531,23 @@ __device__ __forceinline__ bool small_solve(double (&A)[NP][NP], double (&rhs)[N
     return true;
 }
 
+// Three values picked by a run-time index through selects: a private array indexed at run
+// time would live in scratch memory.
+struct D3 {
+    double v0, v1, v2;
+    __device__ __forceinline__ double operator[](int q) const { return q == 0 ? v0 : (q == 1 ? v1 : v2); }
+};
+__device__ __forceinline__ D3 pick3(int d, const D3 &a, const D3 &b, const D3 &c)
+{
+    return D3{d == 0 ? a.v0 : (d == 1 ? b.v0 : c.v0), d == 0 ? a.v1 : (d == 1 ? b.v1 : c.v1),
+              d == 0 ? a.v2 : (d == 1 ? b.v2 : c.v2)};
+}
+
 // One-sided weights on NP points (coordinates pt) that reproduce sum over the run of
 // Ld[p] u''(x_p) for every polynomial of degree < NP: the moment conditions in coordinates
 // scaled by the reference point tref and the largest offset href.
 template <int NP>
-__device__ __forceinline__ bool onesided_weights(const double *pt, const double *tr, int plo, int phi_, const double Ld[3],
+__device__ __forceinline__ bool onesided_weights(const double *pt, const double *tr, int plo, int phi_, const D3 Ld,
                                                  double tref, double href, double *wout)
 {
     double A[NP][NP], rhs[NP], w[NP];
@@ -504,7 +617,7 @@ __device__ __forceinline__ void put(const Ctx &C, WinList &R, size_t rownode, co
 // the line from the window centre, IBI or grid node, g at an IBI) and weights.  It lives
 // in LDS: the point list grows in a data-dependent order, and as a private array it would
 // sit in scratch memory.
-constexpr int PT_CAP = 8;
+constexpr int PT_CAP = 6;   // one run: <= 2 nodes + IBI + march to 6 points; S-F-S: 3
 struct PtBuf {
     double *t, *g, *w;
     signed char *off;
@@ -514,7 +627,7 @@ struct PtBuf {
 // one fluid run [plo, phi_] (positions -1..1 along d of the window centred at `wc` = row
 // offset) of a window meeting the body
 __device__ __forceinline__ void run_operator(const Ctx &C, WinList &R, size_t rownode, const int rowidx[3], int d, const int wc[3],
-                             int plo, int phi_, const bool sol[3], int nruns, const double Ld[3], double W, int &fb,
+                             int plo, int phi_, const bool sol[3], int nruns, const D3 Ld, double W, int &fb,
                              double &minhb, int *bad, PtBuf P)
 {
     const int n = C.n[d];
@@ -526,6 +639,7 @@ __device__ __forceinline__ void run_operator(const Ctx &C, WinList &R, size_t ro
     bool sr = phi_ < 1 && sol[phi_ + 1 + 1];
     int np = 0;
     auto push = [&](double t, int off, bool ibi, double gv) {
+        if (np >= PT_CAP) return;
         P.t[np] = t;
         P.off[np] = (signed char)off;
         P.ibi[np] = ibi;
@@ -535,11 +649,11 @@ __device__ __forceinline__ void run_operator(const Ctx &C, WinList &R, size_t ro
     bool shortened = false;
     double gv, fr;
     if (sl && sr) {
-        double tl = ibi_on_segment(C, d, line0, cidx + plo, cidx + plo - 1, &gv, &fr);
+        double tl = ibi_cached(C, d, base, line0, cidx + plo, cidx + plo - 1, &gv, &fr);
         minhb = fmin(minhb, fr);
         push(tl, 0, true, gv);
         for (int p = plo; p <= phi_; ++p) push(C.t[d][cidx + p], p, false, 0.0);
-        double th = ibi_on_segment(C, d, line0, cidx + phi_, cidx + phi_ + 1, &gv, &fr);
+        double th = ibi_cached(C, d, base, line0, cidx + phi_, cidx + phi_ + 1, &gv, &fr);
         minhb = fmin(minhb, fr);
         push(th, 0, true, gv);
         shortened = true;
@@ -548,7 +662,7 @@ __device__ __forceinline__ void run_operator(const Ctx &C, WinList &R, size_t ro
         for (int p = plo; p <= phi_; ++p) push(C.t[d][cidx + p], p, false, 0.0);
         int near = sr ? phi_ : plo;                 // run node next to the interface
         int step = sr ? -1 : 1;                     // march away from the interface
-        double tb = ibi_on_segment(C, d, line0, cidx + near, cidx + near - step, &gv, &fr);
+        double tb = ibi_cached(C, d, base, line0, cidx + near, cidx + near - step, &gv, &fr);
         minhb = fmin(minhb, fr);
         push(tb, 0, true, gv);
         int pos = sr ? plo : phi_;
@@ -559,7 +673,7 @@ __device__ __forceinline__ void run_operator(const Ctx &C, WinList &R, size_t ro
             size_t node = line0 + (size_t)gi * C.stride[d];
             int8_t ty = C.type[node];
             if (ty == 3) {
-                double te = ibi_on_segment(C, d, line0, cidx + pos, gi, &gv, &fr);
+                double te = ibi_cached(C, d, base, line0, cidx + pos, gi, &gv, &fr);
                 minhb = fmin(minhb, fr);
                 push(te, 0, true, gv);
                 shortened = true;
@@ -616,8 +730,8 @@ __device__ void sw_krow(const Ctx &C, size_t rownode, const int idx[3], double *
         size_t nm = rownode - C.stride[d], npl = rownode + C.stride[d];
         double hb = C.t[d][idx[d]] - C.t[d][idx[d] - 1], hf = C.t[d][idx[d] + 1] - C.t[d][idx[d]];
         double gv, fr;
-        if (C.type[nm] == 3) hb = C.t[d][idx[d]] - ibi_on_segment(C, d, line0, idx[d], idx[d] - 1, &gv, &fr);
-        if (C.type[npl] == 3) hf = ibi_on_segment(C, d, line0, idx[d], idx[d] + 1, &gv, &fr) - C.t[d][idx[d]];
+        if (C.type[nm] == 3) hb = C.t[d][idx[d]] - ibi_cached(C, d, b0, line0, idx[d], idx[d] - 1, &gv, &fr);
+        if (C.type[npl] == 3) hf = ibi_cached(C, d, b0, line0, idx[d], idx[d] + 1, &gv, &fr) - C.t[d][idx[d]];
         kr[0] += -2.0 / (hb * hf);
         int8_t tm = C.type[nm], tp = C.type[npl];
         kr[1 + 2 * d] = (tm == 1 || tm == 2) ? 2.0 / (hb * (hf + hb)) : 0.0;
@@ -691,10 +805,9 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
     double *__restrict__ minhb_row, int *__restrict__ fb_row, int *__restrict__ bad)
 {
     __shared__ WinList wl[BR_ROWS][27];
-    __shared__ double pt_t[BR_ROWS * BR_LANES][PT_CAP], pt_g[BR_ROWS * BR_LANES][PT_CAP],
-        pt_w[BR_ROWS * BR_LANES][PT_CAP];
-    __shared__ signed char pt_off[BR_ROWS * BR_LANES][PT_CAP];
-    __shared__ bool pt_ibi[BR_ROWS * BR_LANES][PT_CAP];
+    __shared__ double pt_t[BR_ROWS * 27][PT_CAP], pt_g[BR_ROWS * 27][PT_CAP], pt_w[BR_ROWS * 27][PT_CAP];
+    __shared__ signed char pt_off[BR_ROWS * 27][PT_CAP];
+    __shared__ bool pt_ibi[BR_ROWS * 27][PT_CAP];
     __shared__ double qbar[BR_ROWS];
     __shared__ int wfb[BR_ROWS][27];
     __shared__ double wminhb[BR_ROWS][27];
@@ -704,13 +817,13 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
     const size_t rownode = live ? (size_t)nodes[row] : 0;
     const int nx = C.n[0], ny = C.n[1];
     const int idx[3] = {(int)(rownode % nx), (int)((rownode / nx) % ny), (int)(rownode / ((size_t)nx * ny))};
-    double L[3][3], Rr[3][3];
+    // the row's compact weights along x, y, z: L (left-hand side) and R (second derivative)
+    D3 Lx{0, 1, 0}, Ly{0, 1, 0}, Lz{0, 1, 0}, Rx{0, 0, 0}, Ry{0, 0, 0}, Rz{0, 0, 0};
     if (live) {
-        for (int d = 0; d < 3; ++d) {
-            const double *c = C.coef[d] + 8 * idx[d];
-            L[d][0] = c[0]; L[d][1] = 1.0; L[d][2] = c[1];
-            Rr[d][0] = c[2]; Rr[d][1] = c[3]; Rr[d][2] = c[4];
-        }
+        const double *cx = C.coef[0] + 8 * idx[0], *cy = C.coef[1] + 8 * idx[1], *cz = C.coef[2] + 8 * idx[2];
+        Lx = D3{cx[0], 1.0, cx[1]}; Rx = D3{cx[2], cx[3], cx[4]};
+        Ly = D3{cy[0], 1.0, cy[1]}; Ry = D3{cy[2], cy[3], cy[4]};
+        Lz = D3{cz[0], 1.0, cz[1]}; Rz = D3{cz[2], cz[3], cz[4]};
     }
     if (live && lane < 27) {
         // window `lane`: direction d, cross offsets (s1, s2) along d1, d2
@@ -720,7 +833,8 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
         double minhb = 1.0;
         const int d = lane / 9, d1 = (d + 1) % 3, d2 = (d + 2) % 3;
         const int s1 = (lane % 9) / 3 - 1, s2 = lane % 3 - 1;
-        const double W = L[d1][s1 + 1] * L[d2][s2 + 1];
+        const D3 Ld = pick3(d, Lx, Ly, Lz), Rd = pick3(d, Rx, Ry, Rz);
+        const double W = pick3(d1, Lx, Ly, Lz)[s1 + 1] * pick3(d2, Lx, Ly, Lz)[s2 + 1];
         int wc[3] = {0, 0, 0};
         wc[d1] = s1;
         wc[d2] = s2;
@@ -737,7 +851,7 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
             for (int p = -1; p <= 1; ++p) {
                 int o[3] = {wc[0], wc[1], wc[2]};
                 o[d] = p;
-                put(C, R, rownode, o, W * Rr[d][p + 1]);
+                put(C, R, rownode, o, W * Rd[p + 1]);
             }
         } else if (nsol < 3) {      // a window inside the body is dropped
             int lo[2], hi[2], nr = 0;
@@ -750,10 +864,10 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
                 ++nr;
                 ++p;
             }
-            const PtBuf pb{pt_t[threadIdx.x], pt_g[threadIdx.x], pt_w[threadIdx.x], pt_off[threadIdx.x],
-                           pt_ibi[threadIdx.x]};
+            const int pw = grp * 27 + lane;
+            const PtBuf pb{pt_t[pw], pt_g[pw], pt_w[pw], pt_off[pw], pt_ibi[pw]};
             for (int q = 0; q < nr; ++q)
-                run_operator(C, R, rownode, idx, d, wc, lo[q], hi[q], sol, nr, L[d], W, fb, minhb, bad, pb);
+                run_operator(C, R, rownode, idx, d, wc, lo[q], hi[q], sol, nr, Ld, W, fb, minhb, bad, pb);
         }
         if (R.n > WIN_CAP) atomicOr(bad, 2);
         wfb[grp][lane] = fb;
@@ -761,11 +875,14 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
     } else if (live && lane == 27) {
         // Q-bar: the row's L_x L_y L_z weights on f at every non-solid node of the 3x3x3 box
         double q = 0.0;
+#pragma unroll
         for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
                     size_t node = rownode + dx + (ptrdiff_t)dy * nx + (ptrdiff_t)dz * (ptrdiff_t)C.stride[2];
-                    if (C.type[node] != 3) q += L[0][dx + 1] * L[1][dy + 1] * L[2][dz + 1] * C.f[node];
+                    if (C.type[node] != 3) q += Lx[dx + 1] * Ly[dy + 1] * Lz[dz + 1] * C.f[node];
                 }
         qbar[grp] = q;
         sw_krow(C, rownode, idx, k7 + 7 * (size_t)row);
@@ -778,6 +895,7 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
     constexpr int SPL = (NSLOT + BR_LANES - 1) / BR_LANES;   // slots per lane
     double mine[SPL];
     uint32_t mused = 0u;
+#pragma unroll
     for (int q = 0; q < SPL; ++q) mine[q] = 0.0;
     double rhs = qbar[grp];
     for (int w = 0; w < 27; ++w) {
@@ -788,14 +906,18 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
             if (sl < 0) {
                 if (lane == 0) rhs += R.v[e];
             } else if (sl % BR_LANES == lane) {
-                mine[sl / BR_LANES] += R.v[e];
-                mused |= 1u << (sl / BR_LANES);
+                const int qs = sl / BR_LANES;
+#pragma unroll
+                for (int q = 0; q < SPL; ++q)       // static indices keep mine[] in registers
+                    if (q == qs) mine[q] += R.v[e];
+                mused |= 1u << qs;
             }
         }
     }
     // emit in slot order: slot sl = lane + 32 q; its output position is the number of used
     // slots before it (prefix over q, then over lanes)
     int cnt_total = 0, base_q = 0;
+#pragma unroll
     for (int q = 0; q < SPL; ++q) {
         const bool u = (mused >> q) & 1u;
         // used slots with the same q on lower lanes
@@ -855,6 +977,10 @@ void launch_krows(hipStream_t s, int nx, int ny, int nz, const double *x, const 
     C.t[0] = x; C.t[1] = y; C.t[2] = z;
     for (int d = 0; d < 3; ++d) C.coef[d] = nullptr;
     C.phi = phi; C.g = phi; C.f = nullptr; C.type = type;   // g at an IBI is not used for K
+    C.ibi_t = C.ibi_g = nullptr;
+    C.irr_bits = nullptr;
+    C.irr_wstart = nullptr;
+    C.W = 0;
     k_krows<<<(unsigned)((8 * (size_t)nirr + 255) / 256), 256, 0, s>>>(C, nirr, nodes, k7);
 }
 
@@ -867,8 +993,9 @@ void launch_gather3(hipStream_t s, int ncx, int ncy, int ncz, int nfx, int nfy, 
 
 void launch_build_rows(hipStream_t s, int nx, int ny, int nz, const double *x, const double *y, const double *z,
                        const double *coef, const double *phi, const double *g, const double *f, const int8_t *type,
-                       int nirr, const int *nodes, int cap, int *ell_col, double *ell_val, int *len, double *rhs_row,
-                       double *k7, double *bdiag, double *minhb, int *fallback, int *bad)
+                       int nirr, const int *nodes, const uint32_t *irr_bits, const int *irr_wstart, double *ibi_tab,
+                       int cap, int *ell_col, double *ell_val, int *len, double *rhs_row, double *k7, double *bdiag,
+                       double *minhb, int *fallback, int *bad)
 {
     if (nirr == 0) return;
     Ctx C;
@@ -878,20 +1005,36 @@ void launch_build_rows(hipStream_t s, int nx, int ny, int nz, const double *x, c
     int nmax = std::max(nx, std::max(ny, nz));
     for (int d = 0; d < 3; ++d) C.coef[d] = coef + (size_t)d * 8 * nmax;
     C.phi = phi; C.g = g; C.f = f; C.type = type;
+    C.ibi_t = C.ibi_g = nullptr;
+    C.irr_bits = irr_bits;
+    C.irr_wstart = irr_wstart;
+    C.W = (nx + 31) / 32;
+    // every IBI next to an irregular node once, then the rows read them
+    k_ibi_table<<<(unsigned)((6 * (size_t)nirr + 255) / 256), 256, 0, s>>>(C, nirr, nodes, ibi_tab,
+                                                                          ibi_tab + 6 * (size_t)nirr);
+    C.ibi_t = ibi_tab;
+    C.ibi_g = ibi_tab + 6 * (size_t)nirr;
     k_build_rows<<<(nirr + BR_ROWS - 1) / BR_ROWS, BR_ROWS * BR_LANES, 0, s>>>(
         C, nirr, nodes, cap, ell_col, ell_val, len, rhs_row, k7, bdiag, minhb, fallback, bad);
 }
 
-__global__ void k_pack_rows(int nirr, int cap, const int *__restrict__ ell_col, const double *__restrict__ ell_val,
-                            const int *__restrict__ len, const int *__restrict__ ptr, int *__restrict__ col,
-                            double *__restrict__ val64, float *__restrict__ val32)
+// ELL scratch -> CSR: PACK_LANES consecutive lanes copy one row, so that each load and store
+// of a wavefront covers contiguous entries of a few rows
+constexpr int PACK_LANES = 16;
+__global__ void __launch_bounds__(256) k_pack_rows(int nirr, int cap, const int *__restrict__ ell_col,
+                                                   const double *__restrict__ ell_val, const int *__restrict__ len,
+                                                   const int *__restrict__ ptr, int *__restrict__ col,
+                                                   double *__restrict__ val64, float *__restrict__ val32)
 {
-    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int row = t / PACK_LANES, l = t % PACK_LANES;
     if (row >= nirr) return;
-    int n = min(len[row], cap), o = ptr[row];
-    for (int q = 0; q < n; ++q) {
-        col[o + q] = ell_col[(size_t)row * cap + q];
-        double v = ell_val[(size_t)row * cap + q];
+    const int n = min(len[row], cap), o = ptr[row];
+    const int *ec = ell_col + (size_t)row * cap;
+    const double *ev = ell_val + (size_t)row * cap;
+    for (int q = l; q < n; q += PACK_LANES) {
+        col[o + q] = ec[q];
+        const double v = ev[q];
         val64[o + q] = v;
         val32[o + q] = (float)v;
     }
@@ -901,61 +1044,129 @@ void launch_pack_rows(hipStream_t s, int nirr, int cap, const int *ell_col, cons
                       const int *ptr, int *col, double *val64, float *val32)
 {
     if (nirr == 0) return;
-    k_pack_rows<<<(nirr + 255) / 256, 256, 0, s>>>(nirr, cap, ell_col, ell_val, len, ptr, col, val64, val32);
+    const size_t threads = (size_t)nirr * PACK_LANES;
+    k_pack_rows<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(nirr, cap, ell_col, ell_val, len, ptr, col, val64,
+                                                                  val32);
 }
 
 // ---------------------------------------------------------------------------------------
 // right-hand side at regular rows: Q f (Eq. q) minus the known wall-node terms of Eq. A27
 // ---------------------------------------------------------------------------------------
 // Right-hand side of the regular rows: Q-bar f (the row's L_x L_y L_z weights on the 3 x 3 x 3
-// box, Eq. q) minus the terms of known wall neighbours (Eq. bc).  One wavefront covers 62
-// consecutive nodes of an x-row (its two outer lanes only supply neighbours): each lane
-// loads f at its own node in the nine rows of the box and takes its x neighbours from the
-// adjacent lanes, so f is read 9 instead of 27 times per node.
+// box, Eq. q); k_rhs_walls then subtracts the terms of known wall neighbours (Eq. bc) at the
+// rows next to a wall.  One wavefront covers 62
+// consecutive nodes of an x-row (its two outer lanes only supply neighbours) in RHS_NK
+// consecutive planes: each lane loads f at its own column in the three rows j - 1 .. j + 1 of
+// the RHS_NK + 2 planes involved (all loads issued before any use), filters them along y once
+// per plane and along z per output plane, and takes its x neighbours from the adjacent lanes.
+// Blocks are numbered so that each XCD (blocks b = XCD mod NXCD) takes a contiguous range of
+// z-chunks, whose halo planes its neighbours loaded into the same L2.
 constexpr int RHS_SPAN = 62;
+constexpr int RHS_NK = 8;
 __global__ void __launch_bounds__(256) k_rhs_regular(int nx, int ny, int nz, const double *__restrict__ coef, int nmax,
                                                      const double *__restrict__ f, const double *__restrict__ g,
-                                                     const int8_t *__restrict__ type, double *__restrict__ rhs)
+                                                     const int8_t *__restrict__ type, double *__restrict__ rhs,
+                                                     int nbx, int nby, int total)
 {
+    const int per = (int)gridDim.x / NXCD;
+    const int qb = ((int)blockIdx.x % NXCD) * per + (int)blockIdx.x / NXCD;
+    if (qb >= total) return;
+    const int bx = qb % nbx, by = (qb / nbx) % nby, bz = qb / (nbx * nby);
     const int lane = threadIdx.x;
-    const int i = (int)blockIdx.x * RHS_SPAN + lane;            // lanes 1..62 own nodes
-    const int j = 1 + (int)(blockIdx.y * blockDim.y + threadIdx.y);
-    const int k = 1 + (int)blockIdx.z;
+    const int i = bx * RHS_SPAN + lane;                         // lanes 1..62 own nodes
+    const int j = 1 + (int)(by * blockDim.y + threadIdx.y);
+    const int k0 = 1 + bz * RHS_NK;
     if (j > ny - 2) return;                                     // whole wavefront
+    const int nk = min(RHS_NK, nz - 1 - k0);                    // output planes k0 .. k0 + nk - 1
     const int ic = min(i, nx - 1);                              // lanes past the row read valid memory
     const size_t plane = (size_t)nx * ny;
-    const size_t e = (size_t)ic + (size_t)nx * j + plane * k;
-    const double *cy = coef + 8 * (size_t)nmax + 8 * j, *cz = coef + 16 * (size_t)nmax + 8 * k;
-    const double Ly[3] = {cy[0], 1.0, cy[1]}, Lz[3] = {cz[0], 1.0, cz[1]};
-    // y and z filtered f at this lane's column: sum_{q,r} Ly[q] Lz[r] f(i, j+q-1, k+r-1)
-    double fyz = 0.0;
+    const size_t col = (size_t)ic + (size_t)nx * j;             // this lane's column, plane 0
+    const double *cy = coef + 8 * (size_t)nmax + 8 * j;
+    const double Ly[3] = {cy[0], 1.0, cy[1]};
+    const double *cx = coef + 8 * ic;
+    const double cx0 = cx[0], cx1 = cx[1];
+    // f in rows j-1..j+1 of planes k0-1 .. k0+nk (clamped to the grid for a short last chunk)
+    double fr3[RHS_NK + 2][3];
+    int8_t te[RHS_NK];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int p = 0; p < RHS_NK + 2; ++p) {
+        const int kk = min(k0 - 1 + p, nz - 1);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) fr3[p][q] = f[col + (ptrdiff_t)(q - 1) * nx + plane * kk];
+    }
+#pragma unroll
+    for (int u = 0; u < RHS_NK; ++u) te[u] = type[col + plane * min(k0 + u, nz - 1)];
+    // y-filtered f per plane: sum_q Ly[q] f(i, j+q-1, k)
+    double fy[RHS_NK + 2];
+#pragma unroll
+    for (int p = 0; p < RHS_NK + 2; ++p) {
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) acc += Ly[q] * f[e + (ptrdiff_t)(q - 1) * nx + (ptrdiff_t)(r - 1) * (ptrdiff_t)plane];
-        fyz += Lz[r] * acc;
+        for (int q = 0; q < 3; ++q) acc += Ly[q] * fr3[p][q];
+        fy[p] = acc;
     }
-    const double fl = __shfl_up(fyz, 1, 64), fr = __shfl_down(fyz, 1, 64);
     const bool own = lane >= 1 && lane <= RHS_SPAN && i <= nx - 2;
-    if (!own || type[e] != 1) return;
-    const double *cx = coef + 8 * i;
-    const double Lx[3] = {cx[0], 1.0, cx[1]};
-    double acc = Lx[0] * fl + fyz + Lx[2] * fr;
-    // known (wall) neighbours move to the right-hand side; only rows next to a wall have them
-    // (a regular row has no solid neighbour)
-    if (i == 1 || j == 1 || k == 1 || i == nx - 2 || j == ny - 2 || k == nz - 2) {
-        const double Rx[3] = {cx[2], cx[3], cx[4]}, Ry[3] = {cy[2], cy[3], cy[4]}, Rz[3] = {cz[2], cz[3], cz[4]};
-        for (int r = 0; r < 3; ++r)
-            for (int q = 0; q < 3; ++q)
-                for (int p = 0; p < 3; ++p) {
-                    const size_t nb = e + (p - 1) + (ptrdiff_t)(q - 1) * nx + (ptrdiff_t)(r - 1) * (ptrdiff_t)plane;
-                    if (type[nb] == 0) {
-                        const double a = Rx[p] * Ly[q] * Lz[r] + Lx[p] * Ry[q] * Lz[r] + Lx[p] * Ly[q] * Rz[r];
-                        acc -= a * g[nb];
-                    }
-                }
+    const double Lx[3] = {cx0, 1.0, cx1};
+#pragma unroll
+    for (int u = 0; u < RHS_NK; ++u) {
+        if (u >= nk) break;                                     // uniform over the wavefront
+        const int k = k0 + u;
+        const double *cz = coef + 16 * (size_t)nmax + 8 * k;
+        const double Lz[3] = {cz[0], 1.0, cz[1]};
+        double fyz = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) fyz += Lz[r] * fy[u + r];
+        const double fl = __shfl_up(fyz, 1, 64), fr = __shfl_down(fyz, 1, 64);
+        if (!own || te[u] != 1) continue;
+        rhs[col + plane * k] = Lx[0] * fl + fyz + Lx[2] * fr;
     }
+}
+
+// The known (wall) neighbour terms of Eq. bc for the regular rows next to a wall, subtracted
+// from the Q-bar f that k_rhs_regular stored, in the same order as a single pass would: a
+// regular row has no solid neighbour, and the only other known nodes are the box walls, so a
+// neighbour is known exactly when one of its indices is 0 or n - 1.  Face f = blockIdx.z
+// (x-low, x-high, y-low, y-high, z-low, z-high) owns the interior nodes on it that no earlier
+// face owns, so each such node is handled once.
+__global__ void __launch_bounds__(256) k_rhs_walls(int nx, int ny, int nz, const double *__restrict__ coef, int nmax,
+                                                   const double *__restrict__ g, const int8_t *__restrict__ type,
+                                                   double *__restrict__ rhs)
+{
+    const int face = (int)blockIdx.z, u = (int)(blockIdx.x * blockDim.x + threadIdx.x), v = (int)blockIdx.y;
+    int i, j, k;
+    if (face < 2) {                     // i fixed; j = 1 + u, k = 1 + v
+        i = face == 0 ? 1 : nx - 2; j = 1 + u; k = 1 + v;
+        if (j > ny - 2 || k > nz - 2) return;
+    } else if (face < 4) {              // j fixed; i = 2 + u, k = 1 + v
+        j = face == 2 ? 1 : ny - 2; i = 2 + u; k = 1 + v;
+        if (i > nx - 3 || k > nz - 2) return;
+    } else {                            // k fixed; i = 2 + u, j = 2 + v
+        k = face == 4 ? 1 : nz - 2; i = 2 + u; j = 2 + v;
+        if (i > nx - 3 || j > ny - 3) return;
+    }
+    // a grid thinner than 3 interior points along an axis puts both faces on one plane
+    if ((face == 1 && nx - 2 == 1) || (face == 3 && ny - 2 == 1) || (face == 5 && nz - 2 == 1)) return;
+    const size_t plane = (size_t)nx * ny;
+    const size_t e = (size_t)i + (size_t)nx * j + plane * k;
+    if (type[e] != 1) return;
+    const double *cx = coef + 8 * i, *cy = coef + 8 * (size_t)nmax + 8 * j, *cz = coef + 16 * (size_t)nmax + 8 * k;
+    const double Lx[3] = {cx[0], 1.0, cx[1]}, Ly[3] = {cy[0], 1.0, cy[1]}, Lz[3] = {cz[0], 1.0, cz[1]};
+    const double Rx[3] = {cx[2], cx[3], cx[4]}, Ry[3] = {cy[2], cy[3], cy[4]}, Rz[3] = {cz[2], cz[3], cz[4]};
+    double acc = rhs[e];
+    // every neighbour's g is loaded (no branch between the loads); a term that is not a
+    // wall's subtracts 0 * g = 0 (g is finite), which leaves acc unchanged
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const int ii = i + p - 1, jj = j + q - 1, kk = k + r - 1;
+                const bool wall = ii == 0 || ii == nx - 1 || jj == 0 || jj == ny - 1 || kk == 0 || kk == nz - 1;
+                const size_t nb = e + (p - 1) + (ptrdiff_t)(q - 1) * nx + (ptrdiff_t)(r - 1) * (ptrdiff_t)plane;
+                const double a = Rx[p] * Ly[q] * Lz[r] + Lx[p] * Ry[q] * Lz[r] + Lx[p] * Ly[q] * Rz[r];
+                acc -= (wall ? a : 0.0) * g[nb];
+            }
     rhs[e] = acc;
 }
 
@@ -964,8 +1175,12 @@ void launch_rhs_regular(hipStream_t s, int nx, int ny, int nz, const double *coe
 {
     if (nx < 3 || ny < 3 || nz < 3) return;
     int nmax = std::max(nx, std::max(ny, nz));
-    dim3 blk(64, 4), grid((unsigned)((nx - 2 + RHS_SPAN - 1) / RHS_SPAN), (unsigned)((ny - 2 + 3) / 4), (unsigned)(nz - 2));
-    k_rhs_regular<<<grid, blk, 0, s>>>(nx, ny, nz, coef, nmax, f, g, type, rhs);
+    const int nbx = (nx - 2 + RHS_SPAN - 1) / RHS_SPAN, nby = (ny - 2 + 3) / 4;
+    const int nbz = (nz - 2 + RHS_NK - 1) / RHS_NK, total = nbx * nby * nbz;
+    const int nb = (total + NXCD - 1) / NXCD * NXCD;
+    k_rhs_regular<<<nb, dim3(64, 4), 0, s>>>(nx, ny, nz, coef, nmax, f, g, type, rhs, nbx, nby, total);
+    const int fu = std::max(nx, ny), fv = std::max(ny, nz);
+    k_rhs_walls<<<dim3((unsigned)((fu + 255) / 256), (unsigned)fv, 6), 256, 0, s>>>(nx, ny, nz, coef, nmax, g, type, rhs);
 }
 
 __global__ void k_scatter_rows(int nirr, const int *__restrict__ nodes, const double *__restrict__ rhs_row,
@@ -993,17 +1208,19 @@ void launch_to_float(hipStream_t s, size_t n, const double *a, float *b)
     k_to_float<<<(unsigned)std::min<size_t>((n + 255) / 256, 65536), 256, 0, s>>>(n, a, b);
 }
 
-// min of a[] and sum of fb[] by one block
-__global__ void k_min_reduce(int n, const double *__restrict__ a, const int *__restrict__ fb, double *out_min,
-                             long long *out_sum)
+// min of a[] (starting from 1) and sum of fb[]: MINR_PARTS blocks write partials, then one
+// block combines them (min and an integer sum do not depend on the order)
+template <bool FINAL>
+__global__ void __launch_bounds__(256) k_min_reduce(int n, const double *__restrict__ a, const long long *__restrict__ fb,
+                                                    const int *__restrict__ fbi, double *out_min, long long *out_sum)
 {
     __shared__ double smin[256];
     __shared__ long long ssum[256];
     double mn = 1.0;
     long long sm = 0;
-    for (int q = threadIdx.x; q < n; q += 256) {
+    for (int q = (int)(blockIdx.x * blockDim.x + threadIdx.x); q < n; q += (int)(gridDim.x * blockDim.x)) {
         mn = fmin(mn, a[q]);
-        sm += fb[q];
+        sm += FINAL ? fb[q] : (long long)fbi[q];
     }
     smin[threadIdx.x] = mn;
     ssum[threadIdx.x] = sm;
@@ -1016,14 +1233,110 @@ __global__ void k_min_reduce(int n, const double *__restrict__ a, const int *__r
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        *out_min = smin[0];
-        *out_sum = ssum[0];
+        out_min[blockIdx.x] = smin[0];
+        out_sum[blockIdx.x] = ssum[0];
     }
 }
 
-void launch_min_reduce(hipStream_t s, int n, const double *a, const int *fb, double *out_min, long long *out_sum)
+void launch_min_reduce(hipStream_t s, int n, const double *a, const int *fb, double *part, double *out_min,
+                       long long *out_sum)
 {
-    k_min_reduce<<<1, 256, 0, s>>>(n, a, fb, out_min, out_sum);
+    double *pmin = part;
+    long long *psum = (long long *)(part + MINR_PARTS);
+    k_min_reduce<false><<<MINR_PARTS, 256, 0, s>>>(n, a, nullptr, fb, pmin, psum);
+    k_min_reduce<true><<<1, 256, 0, s>>>(MINR_PARTS, pmin, psum, nullptr, out_min, out_sum);
+}
+
+// counts of the node types 0..3 (cnt[4], zeroed by the caller): 16 nodes per 16-byte load, a
+// block sum per type and one atomic add per block and type
+__global__ void __launch_bounds__(256) k_type_hist(size_t n, const int8_t *__restrict__ type, int *cnt)
+{
+    __shared__ int sh[4][4];
+    int c[4] = {0, 0, 0, 0};
+    const size_t n16 = n / 16;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n16; q += (size_t)gridDim.x * blockDim.x) {
+        const int4 v = *reinterpret_cast<const int4 *>(type + 16 * q);
+        const int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int t = (w[u] >> (8 * b)) & 0xff;
+                c[0] += t == 0; c[1] += t == 1; c[2] += t == 2; c[3] += t == 3;
+            }
+    }
+    if (blockIdx.x == 0)
+        for (size_t e = 16 * n16 + threadIdx.x; e < n; e += blockDim.x) {
+            const int t = type[e];
+            c[0] += t == 0; c[1] += t == 1; c[2] += t == 2; c[3] += t == 3;
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        int v = c[t];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) sh[t][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int v = sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] + sh[threadIdx.x][3];
+        if (v) atomicAdd(cnt + threadIdx.x, v);
+    }
+}
+
+void launch_type_hist(hipStream_t s, size_t n, const int8_t *type, int *cnt)
+{
+    const unsigned nb = (unsigned)std::min<size_t>((n / 16 + 255) / 256 + 1, 256);
+    k_type_hist<<<nb, 256, 0, s>>>(n, type, cnt);
+}
+
+// ||b||^2 and ||D^-1 b||^2 over the unknowns (D = diag B): regular nodes take the diagonal
+// from the 1D tables (sum of the three centre weights, as the apply kernels form it), the
+// irregular rows their stored diagonal.  Per-block partials (2 per block) in a fixed order.
+__global__ void __launch_bounds__(256) k_bnorms(int nx, int ny, int nz, const double *__restrict__ coef, int nmax,
+                                                const int8_t *__restrict__ type, const double *__restrict__ b,
+                                                int nirr, const int *__restrict__ nodes,
+                                                const double *__restrict__ bdiag, double *__restrict__ partials)
+{
+    __shared__ double sh[2][4];
+    double a0 = 0.0, a1 = 0.0;
+    const double *cx = coef, *cy = coef + 8 * (size_t)nmax, *cz = coef + 16 * (size_t)nmax;
+    for (int r = (int)blockIdx.x; r < ny * nz; r += (int)gridDim.x) {
+        const int j = r % ny, k = r / ny;
+        if (j < 1 || j > ny - 2 || k < 1 || k > nz - 2) continue;
+        const size_t e0 = ((size_t)k * ny + j) * nx;
+        const double dyz = cy[8 * j + 3], dz = cz[8 * k + 3];
+        for (int i = 1 + (int)threadIdx.x; i <= nx - 2; i += (int)blockDim.x) {
+            if (type[e0 + i] != 1) continue;
+            const double v = b[e0 + i], rd = v / ((cx[8 * i + 3] + dyz) + dz);
+            a0 += v * v;
+            a1 += rd * rd;
+        }
+    }
+    for (int q = (int)(blockIdx.x * blockDim.x + threadIdx.x); q < nirr; q += (int)(gridDim.x * blockDim.x)) {
+        const double v = b[nodes[q]], rd = v / bdiag[q];
+        a0 += v * v;
+        a1 += rd * rd;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, 64);
+        a1 += __shfl_xor(a1, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = a0;
+        sh[1][threadIdx.x >> 6] = a1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = ((sh[0][0] + sh[0][1]) + sh[0][2]) + sh[0][3];
+        partials[2 * blockIdx.x + 1] = ((sh[1][0] + sh[1][1]) + sh[1][2]) + sh[1][3];
+    }
+}
+
+void launch_bnorms(hipStream_t s, int nx, int ny, int nz, const double *coef, const int8_t *type, const double *b,
+                   int nirr, const int *nodes, const double *bdiag, double *partials, int nblocks)
+{
+    const int nmax = std::max(nx, std::max(ny, nz));
+    k_bnorms<<<nblocks, 256, 0, s>>>(nx, ny, nz, coef, nmax, type, b, nirr, nodes, bdiag, partials);
 }
 
 }  // namespace cps

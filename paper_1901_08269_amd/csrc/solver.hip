@@ -916,10 +916,11 @@ int rhs_build(cps_solver *s)
         s->irr_bd64 = dalloc<double>(s, n);
         s->irr_ptr = dalloc<int>(s, n + 1);
     }
+    double *ibi_tab = dalloc<double>(s, 12 * (size_t)n + 1);
     ck(hipMemsetAsync(s->dflag, 0, sizeof(int), st));
     launch_build_rows(st, s->nx, s->ny, s->nz, s->xyz, s->xyz + s->nx, s->xyz + s->nx + s->ny, s->coef64, s->phi, s->gf,
-                      s->f, s->type, n, s->irr_node, ELL_CAP, ell_col, ell_val, len, rhs_row, s->irr_k64, s->irr_bd64,
-                      minhb, fb, s->dflag);
+                      s->f, s->type, n, s->irr_node, s->irr_bits, s->irr_wstart, ibi_tab, ELL_CAP, ell_col, ell_val,
+                      len, rhs_row, s->irr_k64, s->irr_bd64, minhb, fb, s->dflag);
     launch_scan(st, len, s->irr_ptr, n);
     int total = 0, bad = 0;
     ck(hipMemcpyAsync(s->hscalar, s->irr_ptr + n, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -928,7 +929,8 @@ int rhs_build(cps_solver *s)
     std::memcpy(&total, s->hscalar, sizeof(int));
     std::memcpy(&bad, s->hscalar + 1, sizeof(int));
     if (bad) {
-        for (void *p : {(void *)ell_col, (void *)ell_val, (void *)len, (void *)rhs_row, (void *)minhb, (void *)fb})
+        for (void *p : {(void *)ell_col, (void *)ell_val, (void *)len, (void *)rhs_row, (void *)minhb, (void *)fb,
+                        (void *)ibi_tab})
             dfree(s, p);
         return CPS_EGEOM;   // a singular one-sided system
     }
@@ -953,8 +955,9 @@ int rhs_build(cps_solver *s)
     launch_scatter_rows(st, n, s->irr_node, rhs_row, s->rhs);
     long long *dsum = dalloc<long long>(s, 1);
     double *dmin = dalloc<double>(s, 1);
+    double *mpart = dalloc<double>(s, 2 * MINR_PARTS);
     if (n > 0) {
-        launch_min_reduce(st, n, minhb, fb, dmin, dsum);
+        launch_min_reduce(st, n, minhb, fb, mpart, dmin, dsum);
         ck(hipMemcpyAsync(s->hscalar, dmin, sizeof(double), hipMemcpyDeviceToHost, st));
         ck(hipMemcpyAsync(s->hscalar + 1, dsum, sizeof(long long), hipMemcpyDeviceToHost, st));
         sync(s);
@@ -963,16 +966,21 @@ int rhs_build(cps_solver *s)
         std::memcpy(&fbs, s->hscalar + 1, sizeof(long long));
         s->fallback = fbs;
     }
-    // ||b||^2 and ||D^-1 b||^2: the residual kernel applied to x = 0
-    double *zero = dalloc<double>(s, s->nn + VEC_PAD);
-    double *outb = dalloc<double>(s, s->nn);
-    launch_fill<double>(st, s->nn, zero, 0.0);
-    launch_apply<double, double>(MODE_RES, s->launch(), s->cf64(), s->ir64(), zero, outb, nullptr, s->rhs, s->st);
-    DevState ds = read_state(s);
-    s->bn2 = ds.res2;
-    s->bs2 = ds.res2s;
+    // ||b||^2 and ||D^-1 b||^2 over the unknowns, summed on the host in block order
+    if (!s->dot_partials) s->dot_partials = dalloc<double>(s, 2 * DOT_BLOCKS);
+    launch_bnorms(st, s->nx, s->ny, s->nz, s->coef64, s->type, s->rhs, n, s->irr_node, s->irr_bd64, s->dot_partials,
+                  DOT_BLOCKS);
+    std::vector<double> hp(2 * DOT_BLOCKS);
+    ck(hipMemcpyAsync(hp.data(), s->dot_partials, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(s);
+    s->bn2 = 0.0;
+    s->bs2 = 0.0;
+    for (int q = 0; q < DOT_BLOCKS; ++q) {
+        s->bn2 += hp[2 * q];
+        s->bs2 += hp[2 * q + 1];
+    }
     for (void *p : {(void *)ell_col, (void *)ell_val, (void *)len, (void *)rhs_row, (void *)minhb, (void *)fb,
-                    (void *)dsum, (void *)dmin, (void *)zero, (void *)outb})
+                    (void *)dsum, (void *)dmin, (void *)mpart, (void *)ibi_tab})
         dfree(s, p);
     return CPS_OK;
 }
@@ -1046,6 +1054,28 @@ D *upload(cps_solver *s, const std::vector<D> &h, std::vector<std::vector<char>>
     return d;
 }
 
+// Host tables gathered into one buffer (each 256-byte aligned) and uploaded by one copy: a
+// copy from pageable host memory costs the host several microseconds whatever its size.
+struct Staging {
+    std::vector<char> buf;
+    template <typename D>
+    size_t add(const std::vector<D> &h)
+    {
+        const size_t off = (buf.size() + 255) & ~(size_t)255;
+        buf.resize(off + h.size() * sizeof(D));
+        if (!h.empty()) std::memcpy(buf.data() + off, h.data(), h.size() * sizeof(D));
+        return off;
+    }
+    char *flush(cps_solver *s, std::vector<std::vector<char>> &keep)
+    {
+        keep.push_back(std::move(buf));
+        buf.clear();
+        char *d = dalloc<char>(s, keep.back().size());
+        ck(hipMemcpyAsync(d, keep.back().data(), keep.back().size(), hipMemcpyHostToDevice, s->stream));
+        return d;
+    }
+};
+
 // The multigrid hierarchy below the problem's grid (coordinates hx = x | y | z on the host),
 // and the smoother and coarsest-level Chebyshev coefficients.
 void mg_build(cps_solver *s, const std::vector<double> &hx0)
@@ -1085,6 +1115,10 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
         std::vector<int> idx[3], gidx;
         std::vector<double> hc;
         size_t off = 0;
+        // the level's host tables (transfer weights of every axis, coordinates, gather
+        // indices) go up in one copy
+        Staging stg;
+        size_t o_pw[3], o_rw[3], o_pw32[3], o_rw32[3];
         for (int d = 0; d < 3; ++d) {
             for (int i = 0; i < F.n[d] - 1; i += 2) idx[d].push_back(i);
             if (idx[d].back() != F.n[d] - 1) idx[d].push_back(F.n[d] - 1);
@@ -1098,28 +1132,32 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
             mg_axis_tables(hx.data() + off, F.n[d], idx[d], pa, pw, rw);
             pw.resize(pw.size() + 4, 0.0);   // padding: 4-vector loads of the weights
             std::vector<float> pw32(pw.begin(), pw.end()), rw32(rw.begin(), rw.end());
-            F.t64.ax[d] = MgAxis<double>{upload(s, pw, keep), upload(s, rw, keep)};
-            F.t32.ax[d] = MgAxis<float>{upload(s, pw32, keep), upload(s, rw32, keep)};
+            o_pw[d] = stg.add(pw);
+            o_rw[d] = stg.add(rw);
+            o_pw32[d] = stg.add(pw32);
+            o_rw32[d] = stg.add(rw32);
             F.t64.nf[d] = F.t32.nf[d] = F.n[d];
             F.t64.nc[d] = F.t32.nc[d] = C.n[d];
             off += F.n[d];
+        }
+        const size_t o_xyz = stg.add(hc), o_g = stg.add(gidx);
+        char *dev = stg.flush(s, keep);
+        for (int d = 0; d < 3; ++d) {
+            F.t64.ax[d] = MgAxis<double>{(const double *)(dev + o_pw[d]), (const double *)(dev + o_rw[d])};
+            F.t32.ax[d] = MgAxis<float>{(const float *)(dev + o_pw32[d]), (const float *)(dev + o_rw32[d])};
         }
         const int cx = C.n[0], cy = C.n[1], cz = C.n[2];
         C.nmax = std::max({cx, cy, cz});
         C.nn = (size_t)cx * cy * cz;
         C.g = make_geom(cx, cy, cz, true);
-        C.xyz = upload(s, hc, keep);
-        const int *dg = upload(s, gidx, keep);
+        C.xyz = (double *)(dev + o_xyz);
+        const int *dg = (const int *)(dev + o_g);
         double *phic = dalloc<double>(s, C.nn);
         temps.push_back(phic);
         launch_gather3(s->stream, cx, cy, cz, F.n[0], F.n[1], dg, dg + cx, dg + cx + cy, phi_f, phic);
         C.coef64 = dalloc<double>(s, (size_t)3 * 8 * C.nmax);
         C.coef32 = dalloc<float>(s, (size_t)3 * 8 * C.nmax);
-        launch_fill<double>(s->stream, (size_t)3 * 8 * C.nmax, C.coef64, 0.0);
-        launch_coef(s->stream, cx, C.xyz, C.coef64);
-        launch_coef(s->stream, cy, C.xyz + cx, C.coef64 + (size_t)8 * C.nmax);
-        launch_coef(s->stream, cz, C.xyz + cx + cy, C.coef64 + (size_t)16 * C.nmax);
-        launch_to_float(s->stream, (size_t)3 * 8 * C.nmax, C.coef64, C.coef32);
+        launch_coef(s->stream, cx, cy, cz, C.nmax, C.xyz, C.coef64, C.coef32);
         // node types from the coarse level set (it is also passed as g and f, which the
         // classification only checks for finiteness).  Its flags are not read: the coarse
         // level set is a subset of the validated one, and a wall node in a body next to a
@@ -1333,11 +1371,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         // 1D tables
         s->coef64 = dalloc<double>(s, (size_t)3 * 8 * s->nmax);
         s->coef32 = dalloc<float>(s, (size_t)3 * 8 * s->nmax);
-        launch_fill<double>(s->stream, (size_t)3 * 8 * s->nmax, s->coef64, 0.0);
-        launch_coef(s->stream, nx, s->xyz, s->coef64);
-        launch_coef(s->stream, ny, s->xyz + nx, s->coef64 + (size_t)8 * s->nmax);
-        launch_coef(s->stream, nz, s->xyz + nx + ny, s->coef64 + (size_t)16 * s->nmax);
-        launch_to_float(s->stream, (size_t)3 * 8 * s->nmax, s->coef64, s->coef32);
+        launch_coef(s->stream, nx, ny, nz, s->nmax, s->xyz, s->coef64, s->coef32);
         // classification
         s->type = dalloc<int8_t>(s, s->nn);
         s->dflag = dalloc<int>(s, 1);
@@ -1354,10 +1388,20 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->irr_node = dalloc<int>(s, s->nn);   // trimmed below
         count_type(s, 2, s->irr_node, &cnt);
         s->nirr = (int)cnt;
-        count_type(s, 3, nullptr, &s->n_solid);
-        long long nreg;
-        count_type(s, 1, nullptr, &nreg);
-        s->n_unknown = nreg + s->nirr;
+        {
+            // solid and regular counts from one pass over the node types
+            int *cnt = dalloc<int>(s, 4);
+            ck(hipMemsetAsync(cnt, 0, 4 * sizeof(int), s->stream));
+            launch_type_hist(s->stream, s->nn, s->type, cnt);
+            int hc[4];
+            ck(hipMemcpyAsync(s->hscalar, cnt, sizeof(hc), hipMemcpyDeviceToHost, s->stream));
+            sync(s);
+            std::memcpy(hc, s->hscalar, sizeof(hc));
+            dfree(s, cnt);
+            if (hc[2] != s->nirr) throw CPS_EDEVICE;   // the two counts of the irregular nodes disagree
+            s->n_solid = hc[3];
+            s->n_unknown = (long long)hc[1] + s->nirr;
+        }
         {
             int *trimmed = dalloc<int>(s, s->nirr);
             if (s->nirr) ck(hipMemcpyAsync(trimmed, s->irr_node, s->nirr * sizeof(int), hipMemcpyDeviceToDevice, s->stream));
