@@ -73,6 +73,12 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1901_08269_amd.build`")
+    # torch first: it ships its own HIP runtime, and the library must bind to that same one,
+    # or pointers and streams torch hands over belong to a runtime the library does not use
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     vp, dp, i32 = C.c_void_p, C.c_void_p, C.c_int32
     L.cps_default_options.argtypes = [C.POINTER(CpsOptions)]
