@@ -152,7 +152,7 @@ def main():
             ta = time.perf_counter()
             u0 = learned.predict(S, w)     # returns after the model's stream has synchronised
             pms = (time.perf_counter() - ta) * 1e3
-        u, st = S.solve(tol or args.tol, u0=u0)
+        u, st = S.solve(tol or args.tol, u0=u0, inplace=u0 is not None)
         st["predict_ms"] = pms
         S.close()
         return u, st
@@ -163,9 +163,9 @@ def main():
     t0 = time.perf_counter()
     stats = []
     for q in range(args.steps):
-        # every 4th run of consecutive full-traffic preconditioner sweeps on the problem's grid
-        # is timed with one pair of HIP events on the solver's stream (a pair costs a few
-        # microseconds of queue time); runs queued after convergence are left out
+        # the full-traffic preconditioner sweeps on the problem's grid in every 4th run of them
+        # are timed by events that each sweep's launch stamps with the kernel's own start and
+        # end; sweeps queued after convergence are left out
         u, st = step("mixed", 4)
         stats.append(st)
         print(f"# step {q}: {st['iters']} iters, {st['refine_steps']} refinements, "

@@ -203,14 +203,24 @@ class Solver:
         ff, gg = _dev64(f, self.shape), _dev64(g, self.shape)
         self._check(self.L.cps_set_rhs(self.h, _ptr(ff), _ptr(gg)), "cps_set_rhs")
 
-    def solve(self, tol=1e-10, u0=None, check=True, out=None):
+    def solve(self, tol=1e-10, u0=None, check=True, out=None, inplace=False):
+        """Solve to `tol`; returns (u, stats).  u0: optional warm start.  out: optional
+        (nz, ny, nx) float64 CUDA tensor for the solution.  inplace: solve in u0's own storage
+        (u0 must then be a contiguous float64 CUDA tensor of the grid's shape; it is
+        overwritten by the solution), sparing a copy."""
         torch = _torch()
-        if out is None:
-            out = torch.zeros(self.shape, dtype=torch.float64, device="cuda")
         warm = 0
-        if u0 is not None:
-            out.copy_(_dev64(u0, self.shape))
-            warm = 1
+        if u0 is not None and inplace:
+            if not (torch.is_tensor(u0) and u0.is_cuda and u0.dtype == torch.float64 and u0.is_contiguous()
+                    and tuple(u0.shape) == self.shape):
+                raise ValueError("inplace needs u0 as a contiguous float64 CUDA tensor of the grid's shape")
+            out, warm = u0, 1
+        else:
+            if out is None:   # the library writes every node
+                out = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+            if u0 is not None:
+                out.copy_(_dev64(u0, self.shape))
+                warm = 1
         st = CpsStats()
         st.struct_size = C.sizeof(CpsStats)
         rc = self.L.cps_solve(self.h, tol, _ptr(out), warm, C.byref(st))

@@ -79,18 +79,36 @@ __global__ void __launch_bounds__(256) k_conv3(int n, int V, int Cin, int Cout, 
     f32x4 acc[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 27; ++tap) {
-        const int zz = z + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
-        const bool ok = vin && zz >= 0 && yy >= 0 && xx >= 0 && zz < n && yy < n && xx < n;
-        const bf16 *xp = X + (size_t)(b * n3 + (zz * n + yy) * n + xx) * Cin + 4 * kq;
-        for (int c0 = 0; c0 < Cin; c0 += 16) {
-            bf16x4 a = ok ? load4(xp + c0) : bf16x4{0, 0, 0, 0};
+    // The nine taps of one z-offset at a time: all their input and weight loads are issued
+    // before the first of their MFMAs, so a wavefront waits for memory three times per
+    // 16-channel slice instead of at every tap.  Sums run over (z-offset, channel slice, tap
+    // in the plane): a fixed order.
+    for (int tz = 0; tz < 3; ++tz) {
+        const int zz = z + tz - 1;
+        const bf16 *xp[9];
+        bool ok[9];
 #pragma unroll
-            for (int g = 0; g < NG; ++g) {
-                const int co = (g0 + g) * 16 + row;
-                bf16x4 w = load4(Wk + ((size_t)co * 27 + tap) * Cin + c0 + 4 * kq);
-                acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w, acc[g], 0, 0, 0);
+        for (int t9 = 0; t9 < 9; ++t9) {
+            const int yy = y + t9 / 3 - 1, xx = x + t9 % 3 - 1;
+            ok[t9] = vin && zz >= 0 && yy >= 0 && xx >= 0 && zz < n && yy < n && xx < n;
+            xp[t9] = X + (size_t)(b * n3 + (zz * n + yy) * n + xx) * Cin + 4 * kq;
+        }
+        for (int c0 = 0; c0 < Cin; c0 += 16) {
+            bf16x4 a[9], w[9][NG];
+#pragma unroll
+            for (int t9 = 0; t9 < 9; ++t9) {
+                a[t9] = ok[t9] ? load4(xp[t9] + c0) : bf16x4{0, 0, 0, 0};
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const int co = (g0 + g) * 16 + row;
+                    w[t9][g] = load4(Wk + ((size_t)co * 27 + tz * 9 + t9) * Cin + c0 + 4 * kq);
+                }
             }
+#pragma unroll
+            for (int t9 = 0; t9 < 9; ++t9)
+#pragma unroll
+                for (int g = 0; g < NG; ++g)
+                    acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t9], w[t9][g], acc[g], 0, 0, 0);
         }
     }
     // D[voxel 4 kq + i][co = row]
@@ -513,13 +531,13 @@ __global__ void k_restrict_u(int nx, int ny, int nc, const double *__restrict__ 
 
 // u0 at fine nodes: trilinear interpolation in index space of the coarse cell values
 // (cell c centred at fine index 2.5 + 4c), constant beyond the outer cell centres
+// one thread per node: x from the thread index, y and z from the grid (no index divisions)
 __global__ void k_prolong(int nx, int ny, int nz, int nc, const float *__restrict__ p, const double *__restrict__ sigma,
                           double *__restrict__ u0)
 {
-    size_t nn = (size_t)nx * ny * nz;
-    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nn) return;
-    int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / ((size_t)nx * ny));
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x), j = (int)blockIdx.y, k = (int)blockIdx.z;
+    if (i >= nx) return;
+    const size_t e = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
     int idx[3] = {i, j, k};
     int c0[3];
     float w[3];
@@ -1003,7 +1021,8 @@ int cps_model_predict(cps_model *m, cps_solver *s, double *u0)
         if (rc) return rc;
         forward(m, 1);
         size_t nn = (size_t)nx * ny * nz;
-        k_prolong<<<nblk(nn), 256, 0, m->stream>>>(nx, ny, nz, nc, m->pred, m->sig, u0);
+        k_prolong<<<dim3(nblk((size_t)nx), (unsigned)ny, (unsigned)nz), 256, 0, m->stream>>>(nx, ny, nz, nc, m->pred,
+                                                                                            m->sig, u0);
         nck(hipStreamSynchronize(m->stream));
     } catch (NetFail &f_) {
         return f_.code;

@@ -837,6 +837,7 @@ void free_solver(cps_solver *s)
 double scale_warm_start(cps_solver *s, double *x64)
 {
     const Launch L = s->launch();
+    if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
     double *y = s->tmp64;    // B u0 at the unknown rows
     launch_apply<double, double>(MODE_PLAIN, L, s->cf64(), s->ir64(), x64, y, nullptr, nullptr, nullptr);
     if (!s->dot_partials) s->dot_partials = dalloc<double>(s, 2 * DOT_BLOCKS);
@@ -1497,9 +1498,14 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
         if (!s->x64) s->x64 = dalloc<double>(s, s->nn + VEC_PAD);
         double *x64 = (s->opt.precision == CPS_FP64) ? s->v64.x : s->x64;
         if (warm_start) {
-            if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
-            to_device(s, s->tmp64, u, s->nn * sizeof(double));
-            launch_masked_copy<double, double>(s->stream, s->nn, s->type, s->tmp64, x64);
+            // a device array is read in place; a host one is staged first
+            const double *u_dev = u;
+            if (!s->opt.device_ptrs) {
+                if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
+                to_device(s, s->tmp64, u, s->nn * sizeof(double));
+                u_dev = s->tmp64;
+            }
+            launch_masked_copy<double, double>(s->stream, s->nn, s->type, u_dev, x64);
             ck(hipMemsetAsync(s->dflag, 0, sizeof(int), s->stream));
             launch_check_finite(s->stream, s->nn, s->type, x64, s->dflag);
             ck(hipMemcpyAsync(s->hscalar, s->dflag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
@@ -1591,10 +1597,14 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
                 status = fp64_passes();
             }
         }
-        // output: unknowns, g on the walls, 0 in the bodies
-        if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
-        launch_output(s->stream, s->nn, s->type, x64, s->gf, s->tmp64);
-        from_device(s, u, s->tmp64, s->nn * sizeof(double));
+        // output: unknowns, g on the walls, 0 in the bodies (into a device array directly)
+        if (s->opt.device_ptrs) {
+            launch_output(s->stream, s->nn, s->type, x64, s->gf, u);
+        } else {
+            if (!s->tmp64) s->tmp64 = dalloc<double>(s, s->nn);
+            launch_output(s->stream, s->nn, s->type, x64, s->gf, s->tmp64);
+            from_device(s, u, s->tmp64, s->nn * sizeof(double));
+        }
         sync(s);
     } catch (HipFail &) {
         return CPS_EDEVICE;

@@ -151,7 +151,7 @@ class Model:
 
     def predict(self, solver, w=None):
         torch = self.torch
-        u0 = torch.zeros(solver.shape, dtype=torch.float64, device="cuda")
+        u0 = torch.empty(solver.shape, dtype=torch.float64, device="cuda")   # every node is written
         self._ck(self.L.cps_model_predict(self.h, solver.h, _p(u0)), "predict")
         return u0
 
