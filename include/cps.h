@@ -72,10 +72,10 @@ typedef struct cps_options {
     int32_t max_refine;    /* CPS_MIXED: cap on FP32 refinement steps (see fp64_finish) */
     int32_t max_restarts;  /* restarts after breakdown or a failed true-residual check */
     int32_t device_ptrs;   /* 1: array arguments are device pointers */
-    int32_t kernel_timing; /* n > 0: time the preconditioner sweeps on the problem's grid that
-                            * read an x_{k-1} (multigrid: steps 1 .. mg_nu - 1 of a
-                            * post-smoothing pass; Chebyshev: steps 2 .. inner_iters - 1) in
-                            * every n-th such run of sweeps, each by a pair of HIP events that
+    int32_t kernel_timing; /* n > 0: time the preconditioner's Chebyshev sweeps on the problem's
+                            * grid (multigrid: every smoothing step there but the pointwise first
+                            * step of a pre-smoothing pass; Chebyshev: steps 1 .. inner_iters - 1)
+                            * in every n-th preconditioner apply, each by a pair of HIP events that
                             * its launch stamps with the kernel's start and end (stats); sweeps
                             * queued after convergence are left out; 0: off */
     double inner_tol;      /* CPS_MIXED: residual reduction asked of each FP32 inner solve */
@@ -132,7 +132,11 @@ typedef struct cps_stats {
     int64_t sweep_launches;     /* kernel_timing: number of sweeps in them */
     int64_t sweep_points;       /* interior points one sweep processes */
     double sweep_bytes;         /* kernel_timing: algorithmic bytes the timed sweeps move (every
-                                 * vector a sweep reads or writes, once per interior point) */
+                                 * vector a sweep reads or writes, once per interior point: three
+                                 * for the first step of a pass, four for the others) */
+    double sweep_full_ms;       /* kernel_timing: the part of sweep_ms spent in full-traffic
+                                 * sweeps (those that read an x_{k-1}: four vectors) */
+    int64_t sweep_full_launches;
     double warm_alpha;          /* warm start: the factor it was scaled by -- 1 if its residual is
                                  * at most ||b||_2, else argmin over alpha of ||b - alpha B u0||_2
                                  * (0 rejects it); 0 without a warm start */

@@ -45,7 +45,7 @@ class CpsStats(C.Structure):
                 ("rel_residual", C.c_double), ("rel_residual_jacobi", C.c_double), ("min_ibi_frac", C.c_double),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("sweep_ms", C.c_double),
                 ("sweep_launches", C.c_int64), ("sweep_points", C.c_int64), ("sweep_bytes", C.c_double),
-                ("warm_alpha", C.c_double)]
+                ("sweep_full_ms", C.c_double), ("sweep_full_launches", C.c_int64), ("warm_alpha", C.c_double)]
 
     def to_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "struct_size"}

@@ -22,8 +22,8 @@ template <typename T, typename TO>
 void launch_apply(int mode, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, TO *y, const T *w,
                   const double *bvec, DevState *st);
 // rev: march down in z (consecutive sweeps alternate, see k_cheb4).  ev0/ev1 (optional, used
-// by a sweep with an x_{k-1} on a grid whose rows fill a wavefront): events that the launch
-// itself stamps with the kernel's start and end (hipExtLaunchKernelGGL)
+// on a grid whose rows fill a wavefront): events that the launch itself stamps with the
+// kernel's start and end (hipExtLaunchKernelGGL)
 template <typename T>
 void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *xc, const T *xm1, const T *rho, T *xn,
                  double c1, double c2, const DevState *st, int rev, hipEvent_t ev0 = nullptr,

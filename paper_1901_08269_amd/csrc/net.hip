@@ -132,61 +132,79 @@ __global__ void __launch_bounds__(256) k_conv3(int n, int V, int Cin, int Cout, 
 // weight gradient: P[chunk][co][tap][ci] = sum_{v in chunk} G[v][co] X[v+tap][ci]
 // ---------------------------------------------------------------------------------------
 constexpr int WG_CHUNK = 1024;   // voxels per block
+constexpr int WG_VS = 64;        // voxels staged in LDS per barrier: four 16-voxel MFMA steps
 constexpr int WG_MAXT = 7;       // 16x16 tiles per wave (Cout/16 * Cin/16 <= 28)
 
+// A block stages WG_VS voxels of G and of the tap-shifted X at a time (8-byte loads).  With
+// at least four 16x16 output tiles, wave w takes tiles w, w + 4, ... over all staged voxels;
+// with fewer (the 16-channel layers, which run on the largest grids), wave w takes the w-th
+// 16-voxel step of every tile and the four waves' sums are added in wave order at the end,
+// so that no wave idles.
 __global__ void __launch_bounds__(256) k_wgrad(int n, int V, int Cin, int Cout, const bf16 *__restrict__ G,
                                                const bf16 *__restrict__ X, float *__restrict__ P)
 {
-    __shared__ bf16 sG[16][64 + 4];
-    __shared__ bf16 sX[16][112 + 4];
+    __shared__ bf16 sG[WG_VS][64 + 4];
+    __shared__ bf16 sX[WG_VS][112 + 4];
+    __shared__ f32x4 red[3][3][64];
     const int tap = blockIdx.y, chunk = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n3 = n * n * n;
     const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
     const int tco = Cout / 16, tci = Cin / 16, ntiles = tco * tci;
+    const bool split = ntiles < 4;
     f32x4 acc[WG_MAXT];
 #pragma unroll
     for (int t = 0; t < WG_MAXT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int vbeg = chunk * WG_CHUNK, vend = min(vbeg + WG_CHUNK, V);
-    for (int vs = vbeg; vs < vend; vs += 16) {
-        // stage 16 voxels of G (Cout channels) and of the shifted X (Cin channels)
-        for (int q = tid; q < 16 * Cout; q += 256) {
-            int r = q / Cout, c = q - r * Cout;
-            int v = vs + r;
-            sG[r][c] = (v < vend) ? G[(size_t)v * Cout + c] : (bf16)0;
+    const int g4 = Cout / 4, x4 = Cin / 4;
+    const int m = lane & 15, kq = lane >> 4;
+    for (int vs = vbeg; vs < vend; vs += WG_VS) {
+        for (int q = tid; q < WG_VS * g4; q += 256) {
+            const int r = q / g4, c = 4 * (q - r * g4), v = vs + r;
+            const bf16x4 val = (v < vend) ? load4(G + (size_t)v * Cout + c) : bf16x4{0, 0, 0, 0};
+            *reinterpret_cast<bf16x4 *>(&sG[r][c]) = val;
         }
-        for (int q = tid; q < 16 * Cin; q += 256) {
-            int r = q / Cin, c = q - r * Cin;
-            int v = vs + r;
-            bf16 val = 0;
+        for (int q = tid; q < WG_VS * x4; q += 256) {
+            const int r = q / x4, c = 4 * (q - r * x4), v = vs + r;
+            bf16x4 val{0, 0, 0, 0};
             if (v < vend) {
-                int b = v / n3, rr = v - b * n3;
-                int z = rr / (n * n) + dz, y = (rr / n) % n + dy, x = rr % n + dx;
+                const int b = v / n3, rr = v - b * n3;
+                const int z = rr / (n * n) + dz, y = (rr / n) % n + dy, x = rr % n + dx;
                 if (z >= 0 && y >= 0 && x >= 0 && z < n && y < n && x < n)
-                    val = X[(size_t)(b * n3 + (z * n + y) * n + x) * Cin + c];
+                    val = load4(X + (size_t)(b * n3 + (z * n + y) * n + x) * Cin + c);
             }
-            sX[r][c] = val;
+            *reinterpret_cast<bf16x4 *>(&sX[r][c]) = val;
         }
         __syncthreads();
-        const int m = lane & 15, kq = lane >> 4;
+        for (int ks = 0; ks < WG_VS / 16; ++ks) {
+            if (split && ks != wv) continue;
 #pragma unroll
-        for (int t = 0; t < WG_MAXT; ++t) {
-            const int tile = wv + 4 * t;
-            if (tile >= ntiles) break;
-            const int cog = tile / tci, cig = tile - cog * tci;
-            bf16x4 a, bb;
-            for (int j = 0; j < 4; ++j) {
-                a[j] = (short)sG[4 * kq + j][cog * 16 + m];    // A[co][v]
-                bb[j] = (short)sX[4 * kq + j][cig * 16 + m];   // B[v][ci]
+            for (int t = 0; t < WG_MAXT; ++t) {
+                const int tile = split ? t : wv + 4 * t;
+                if (tile >= ntiles) break;
+                const int cog = tile / tci, cig = tile - cog * tci;
+                bf16x4 a, bb;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    a[j] = (short)sG[16 * ks + 4 * kq + j][cog * 16 + m];    // A[co][v]
+                    bb[j] = (short)sX[16 * ks + 4 * kq + j][cig * 16 + m];   // B[v][ci]
+                }
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[t], 0, 0, 0);
             }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[t], 0, 0, 0);
         }
         __syncthreads();
     }
-    const int m = lane & 15, kq = lane >> 4;
+    if (split) {
+        if (wv > 0)
+            for (int t = 0; t < ntiles; ++t) red[wv - 1][t][lane] = acc[t];
+        __syncthreads();
+        if (wv > 0) return;
+        for (int t = 0; t < ntiles; ++t)
+            for (int w = 0; w < 3; ++w) acc[t] += red[w][t][lane];
+    }
 #pragma unroll
     for (int t = 0; t < WG_MAXT; ++t) {
-        const int tile = wv + 4 * t;
+        const int tile = split ? t : wv + 4 * t;
         if (tile >= ntiles) break;
         const int cog = tile / tci, cig = tile - cog * tci;
         for (int i = 0; i < 4; ++i) {
@@ -209,20 +227,36 @@ __global__ void k_wgrad_reduce(int nchunk, int Cin, int Cout, int ci_real, const
     gW[q] = s;
 }
 
-// db[c] = sum_v G[v][c]: one block per channel, fixed-order tree
-__global__ void k_colsum(int V, int C, const bf16 *__restrict__ G, float *__restrict__ out)
+// db[c] = sum_v G[v][c] in two fixed-order passes.  Pass 1: COLSUM_BLOCKS blocks; thread t of
+// a block takes channel t % C and every (256 / C)-th voxel of the block's stride (consecutive
+// threads read consecutive elements), and the block sums its voxel lanes per channel in LDS
+// in lane order.  Pass 2: one thread per channel adds the block partials in block order.
+constexpr int COLSUM_BLOCKS = 512;
+__global__ void __launch_bounds__(256) k_colsum_part(int V, int C, const bf16 *__restrict__ G, float *__restrict__ part)
 {
     __shared__ float sh[256];
-    int c = blockIdx.x;
+    const int lanes = 256 / C, t = (int)threadIdx.x;    // voxel lanes per block (C <= 256)
+    const int c = t % C, vl = t / C;
     float s = 0.f;
-    for (int v = threadIdx.x; v < V; v += 256) s += bf2f(G[(size_t)v * C + c]);
-    sh[threadIdx.x] = s;
+    if (vl < lanes)
+        for (size_t v = (size_t)blockIdx.x * lanes + vl; v < (size_t)V; v += (size_t)gridDim.x * lanes)
+            s += bf2f(G[v * C + c]);
+    sh[t] = s;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
+    if (t < C) {
+        float acc = 0.f;
+        for (int l = 0; l < lanes; ++l) acc += sh[l * C + t];
+        part[(size_t)blockIdx.x * C + t] = acc;
     }
-    if (threadIdx.x == 0) out[c] = sh[0];
+}
+
+__global__ void k_colsum_final(int nb, int C, const float *__restrict__ part, float *__restrict__ out)
+{
+    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (c >= C) return;
+    float acc = 0.f;
+    for (int b = 0; b < nb; ++b) acc += part[(size_t)b * C + c];
+    out[c] = acc;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -377,6 +411,7 @@ __global__ void k_loss_final(int nb, const double *__restrict__ part, double *__
 }
 
 // head backward: dp = 2 m (p - t) / sum m; gact[v][c] = dp hw[c]; partials of dhw, dhb
+constexpr int HEAD_BLOCKS = 512;    // blocks of the head's backward reduction
 __global__ void k_head_bwd(int V, int C, const float *__restrict__ p, const float *__restrict__ t,
                            const float *__restrict__ mask, const double *__restrict__ lossw,
                            const bf16 *__restrict__ act, const float *__restrict__ hw, float *__restrict__ gact,
@@ -384,19 +419,26 @@ __global__ void k_head_bwd(int V, int C, const float *__restrict__ p, const floa
 {
     __shared__ float sh[256][17];
     const double inv = 1.0 / lossw[1];
+    // C <= 16: the channel loops run over 16 with a guard, so that loc stays in registers
     float loc[17];
-    for (int c = 0; c <= C; ++c) loc[c] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 17; ++c) loc[c] = 0.f;
     for (int v = blockIdx.x * 256 + threadIdx.x; v < V; v += gridDim.x * 256) {
         float m = mask ? mask[v] : 1.f;
         float dp = (float)(2.0 * m * ((double)p[v] - (double)t[v]) * inv);
-        for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            if (c >= C) break;
             float a = bf2f(act[(size_t)v * C + c]);
             gact[(size_t)v * C + c] = dp * hw[c];
             loc[c] += dp * a;
         }
-        loc[C] += dp;
+        loc[16] += dp;
     }
-    for (int c = 0; c <= C; ++c) sh[threadIdx.x][c] = loc[c];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        if (c < C) sh[threadIdx.x][c] = loc[c];
+    sh[threadIdx.x][C] = loc[16];
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o)
@@ -602,6 +644,7 @@ struct cps_model {
     float *pred = nullptr, *tgt = nullptr, *msk = nullptr, *inp = nullptr;
     double *lpart = nullptr, *lossv = nullptr, *sig = nullptr;
     float *hpart = nullptr;
+    float *cpart = nullptr;    // bias-gradient column-sum partials (COLSUM_BLOCKS x channels)
     int adam_t = 0;
     int device = 0;             // the device current at creation (its stream's device)
     std::vector<void *> allocs;
@@ -772,7 +815,7 @@ void backward(cps_model *m, int B)
         const int n = nc >> l.lvl;
         nck(hipMemsetAsync(m->gout[q], 0, sizeof(float) * (size_t)B * n * n * n * l.co, m->stream));
     }
-    const int nhb = 64;
+    const int nhb = HEAD_BLOCKS;
     k_head_bwd<<<nhb, 256, 0, m->stream>>>(V0, C0, m->pred, m->tgt, m->msk, m->lossv, m->out[NLAYER - 1],
                                            m->w + m->head_off, m->gout[NLAYER - 1], m->hpart);
     k_head_bwd_final<<<1, 64, 0, m->stream>>>(nhb, C0, m->hpart, m->g + m->head_off);
@@ -787,7 +830,9 @@ void backward(cps_model *m, int B)
         k_wgrad<<<dim3(nchunk, 27), 256, 0, m->stream>>>(n, V, l.cip, l.co, m->gb, m->in[q], m->wpart);
         k_wgrad_reduce<<<nblk((size_t)l.co * l.ci * 27), 256, 0, m->stream>>>(nchunk, l.cip, l.co, l.ci, m->wpart,
                                                                               m->g + l.off);
-        k_colsum<<<l.co, 256, 0, m->stream>>>(V, l.co, m->gb, m->g + l.off + (long)l.co * l.ci * 27);
+        k_colsum_part<<<COLSUM_BLOCKS, 256, 0, m->stream>>>(V, l.co, m->gb, m->cpart);
+        k_colsum_final<<<nblk((size_t)l.co), 256, 0, m->stream>>>(COLSUM_BLOCKS, l.co, m->cpart,
+                                                                 m->g + l.off + (long)l.co * l.ci * 27);
         if (q == 0) break;
         // data gradient into the producer of this layer's input
         launch_conv(m, n, V, l.co, l.cip, m->gb, m->Wf[q], nullptr, false, m->gtmp, true);
@@ -884,7 +929,8 @@ int cps_model_create(cps_model **out, const cps_model_spec *spec, void *stream)
         m->lpart = nalloc<double>(m, 256);
         m->lossv = nalloc<double>(m, 2);
         m->sig = nalloc<double>(m, 1);
-        m->hpart = nalloc<float>(m, 64 * 17);
+        m->hpart = nalloc<float>(m, HEAD_BLOCKS * 17);
+        m->cpart = nalloc<float>(m, (size_t)COLSUM_BLOCKS * 64);   // channels are at most 64
         // He-normal initialisation from the spec's seed (host, deterministic)
         std::vector<float> h(m->nparam, 0.f);
         uint64_t st = spec->seed * 6364136223846793005ULL + 1442695040888963407ULL;

@@ -106,7 +106,7 @@ struct cps_solver {
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> tev;  // sweep timing events
     size_t tev_used = 0;
-    int64_t sweep_count = 0;      // runs of full-traffic sweeps since the solve started (timing sample)
+    int64_t sweep_count = 0;      // preconditioner applies since the solve started (timing sample)
     int64_t iter_enq = 0;         // BiCGSTAB iterations enqueued since the solve started
     std::vector<int64_t> tev_iter;  // per timed sweep: the iteration it belongs to
     std::vector<char> tev_ok;       // per timed sweep: ran (not after the solve had converged)
@@ -417,10 +417,10 @@ hipEvent_t timing_event(cps_solver *s)
     return s->tev[s->tev_used++];
 }
 
-// Sweep timing: every kernel_timing-th run of consecutive full-traffic preconditioner sweeps
-// on the problem's grid is sampled (sampled_run); each of its sweeps gets a pair of events
-// that its launch stamps with the kernel's own start and end (timed_sweep), so the timing
-// holds the sweeps' execution and no launch gaps or queue time.
+// Sweep timing: every kernel_timing-th preconditioner apply is sampled (sampled_run); each of
+// its sweeps on the problem's grid gets a pair of events that its launch stamps with the
+// kernel's own start and end (timed_sweep), so the timing holds the sweeps' execution and no
+// launch gaps or queue time.
 bool sampled_run(cps_solver *s)
 {
     const int period = s->opt.kernel_timing;
@@ -525,14 +525,14 @@ T *mg_smooth(cps_solver *s, int lvl, const Launch &L, const Coef<T> &cf, const I
 {
     T *odd = x0 ? b : a, *even = x0 ? a : b;
     auto buf = [&](int j) -> T * { return j == 0 ? (x0 ? x0 : (T *)zero) : ((j & 1) ? odd : even); };
-    // a timed run is the full-traffic part of a post-smoothing pass (steps 1 .. n - 1 from
-    // x0, each reading x_k, x_{k-1} and rho and writing x_{k+1})
-    const bool sample = timed && x0 && k0 <= 1 && n > 1 && sampled_run(s);
+    // timed: a smoothing pass on the problem's grid in a sampled cycle; each sweep reads x_k
+    // and rho (and x_{k-1} except in a pass's first step) and writes x_{k+1}
+    const bool sample = timed && n > k0;
     for (int k = k0; k < n; ++k) {
         const T *xm1 = (k == 0) ? nullptr : (k == 1 ? (const T *)x0 : buf(k - 1));
         T *out = (k == n - 1 && dst) ? dst : buf(k + 1);
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-        if (sample && k >= 1) ev = timed_sweep(s, 4);
+        if (sample) ev = timed_sweep(s, xm1 ? 4 : 3);
         launch_cheb<T>(L, cf, ir, buf(k), xm1, rho, out, c1[k], c2[k], st, next_rev(s, lvl), ev.first, ev.second);
     }
     return dst ? dst : buf(n);
@@ -631,23 +631,26 @@ void mg_precond(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T 
     Irr<T> ir;
     if constexpr (sizeof(T) == 8) { cf = s->cf64(); ir = s->ir64(); } else { cf = s->cf32(); ir = s->ir32(); }
     T *a = V.c[1], *b = V.c[0];
+    // every kernel_timing-th cycle times both smoothing passes on this grid (sampling single
+    // passes would alias with the two passes of a cycle)
+    const bool samp = sampled_run(s);
     if (s->mg.size() == 1) {   // no coarser grid: the coarsest-level iteration on this grid
         launch_first<T>(kind, L, cf, ir, r, ps, v, a, s->mg_cc2[0], st);
         mg_smooth<T>(s, 0, L, cf, ir, ps, nullptr, nullptr, a, b, dst, 1, s->opt.mg_coarse_steps, s->mg_cc1.data(),
-                     s->mg_cc2.data(), st, true);
+                     s->mg_cc2.data(), st, samp);
         return;
     }
     const int nu = s->opt.mg_nu;
     launch_first<T>(kind, L, cf, ir, r, ps, v, a, s->mg_c2[0], st);
     T *x = mg_smooth<T>(s, 0, L, cf, ir, ps, nullptr, nullptr, a, b, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st,
-                        true);
+                        samp);
     T *res = (x == a) ? b : a;
     launch_resid<T>(L, cf, ir, x, ps, res, st, next_rev(s, 0));
     launch_mg_restrict<T>(s->stream, mg_transfer<T>(s->mg[0]), s->mg[1].type, res, mg_vecs<T>(s->mg[1])[0],
                           mg_first<T>(s, 1));
     T *e = mg_level<T>(s, 1, st);
     launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(s->mg[0]), s->type, e, x);
-    mg_smooth<T>(s, 0, L, cf, ir, ps, x, nullptr, x, res, dst, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, true);
+    mg_smooth<T>(s, 0, L, cf, ir, ps, x, nullptr, x, res, dst, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, samp);
 }
 
 // phi (dst) = sip_iters iterations of the strongly implicit procedure on K phi = ps from 0
@@ -721,10 +724,10 @@ void precond_apply(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const
     const int m = s->opt.inner_iters;
     auto buf = [&](int j) { return (j == m) ? dst : V.c[j % 2]; };
     launch_first<T>(kind, L, cf, ir, r, ps, v, buf(1), c2[0], st);
-    const bool sample = m > 2 && sampled_run(s);     // steps 2 .. m-1 read an x_{k-1}
+    const bool sample = m > 1 && sampled_run(s);     // step 1 reads x_1 and p; 2 .. m-1 also x_{k-1}
     for (int k = 1; k < m; ++k) {
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-        if (sample && k >= 2) ev = timed_sweep(s, 4);
+        if (sample) ev = timed_sweep(s, k >= 2 ? 4 : 3);
         launch_cheb<T>(L, cf, ir, buf(k), (k == 1) ? nullptr : buf(k - 1), ps, buf(k + 1), c1[k], c2[k], st,
                        next_rev(s, 0), ev.first, ev.second);
     }
@@ -882,8 +885,8 @@ int fill_stats(cps_solver *s, cps_stats *st, const DevState &ds, int iters, int 
     st->solve_ms = solve_ms;
     st->sweep_points = (int64_t)(s->nx - 2) * (s->ny - 2) * (s->nz - 2);
     if (s->opt.kernel_timing && s->tev_used >= 2) {
-        double tot = 0.0;
-        int64_t n = 0, nvec = 0;
+        double tot = 0.0, full = 0.0;
+        int64_t n = 0, nvec = 0, nfull = 0;
         for (size_t q = 0; q + 1 < s->tev_used; q += 2) {
             float ms = 0.f;
             if (!s->tev_ok[q / 2]) continue;     // sweeps queued after convergence return at once
@@ -891,10 +894,16 @@ int fill_stats(cps_solver *s, cps_stats *st, const DevState &ds, int iters, int 
                 tot += ms;
                 n += s->tev_n[q / 2];
                 nvec += s->tev_vec[q / 2];
+                if (s->tev_vec[q / 2] == 4) {
+                    full += ms;
+                    ++nfull;
+                }
             }
         }
         st->sweep_ms = tot;
         st->sweep_launches = n;
+        st->sweep_full_ms = full;
+        st->sweep_full_launches = nfull;
         const int vb = (s->opt.precision == CPS_MIXED) ? 4 : 8;
         st->sweep_bytes = (double)nvec * vb * (double)st->sweep_points;
     }

@@ -937,6 +937,9 @@ void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *
         // the sweep without an x_{k-1} moves less per plane step: RPW2 rows per wavefront
         dim3 grid2(L.g.tr2.nblk + irr_blocks(ir.n, NT));
         if (mr) k_cheb4m<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
+        else if (ev0)
+            hipExtLaunchKernelGGL((k_cheb4<T, true, RPW2>), grid2, blk, 0, L.stream, ev0, ev1, 0, L.g, cf, ir, L.skip, xc,
+                                  xm1, rho, xn, (T)c1, (T)c2, st, rev);
         else k_cheb4<T, true, RPW2><<<grid2, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st,
                                                                rev);
     } else {

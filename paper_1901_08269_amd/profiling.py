@@ -7,7 +7,8 @@ Three reports:
              per interior point (each operand read or written once), GB/s from the average
              launch duration, fraction of the 8 TB/s peak.
 ``mfma``     MFMA busy share and BF16 matrix FLOP rate of the network's kernels from one ``--pmc`` run.
-``traffic``  HBM bytes per launch of one kernel on the problem's grid from two ``--pmc`` runs
+``traffic``  HBM bytes per launch of one kernel (or several counted together, as the
+             instantiations of one kernel template) on the problem's grid from two ``--pmc`` runs
              (``FETCH_SIZE`` and ``WRITE_SIZE``, each in its own pass), each counter scaled by
              what the same counter reads for a plain device copy of known size (the
              calibration runs).  The report
@@ -20,7 +21,7 @@ Usage::
     python -m paper_1901_08269_amd.profiling kernels DB --points P --title T --cmd C
     python -m paper_1901_08269_amd.profiling mfma DB --title T --cmd C
     python -m paper_1901_08269_amd.profiling traffic --fetch DB --write DB \\
-        --copy-fetch DB --copy-write DB --copy-bytes B --kernel NAME --units U --unit-bytes UB \\
+        --copy-fetch DB --copy-write DB --copy-bytes B --kernel NAME=BYTES_PER_UNIT [--kernel ...] --units U \\
         --title T --cmd C
 """
 import argparse
@@ -187,32 +188,42 @@ def kernels_report(db, points, title, cmd):
 
 
 def traffic_report(a):
+    """Calibrated FETCH_SIZE + WRITE_SIZE of one kernel or of several (a.kernel: "NAME=B" items,
+    B the algorithmic bytes per unit of that kernel): the per-launch figures are averages over
+    all their launches on the problem's grid."""
     cf = pmc_per_kernel(a.copy_fetch)[COPY_KERNEL]
     cw = pmc_per_kernel(a.copy_write)[COPY_KERNEL]
     kib = a.copy_bytes / 1024.0
     sf, sw = kib / cf[1], kib / cw[1]
-    f = pmc_per_kernel(a.fetch)[a.kernel]
-    w = pmc_per_kernel(a.write)[a.kernel]
-    rd, wr = f[1] * sf * 1024.0, w[1] * sw * 1024.0
-    alg = a.units * a.unit_bytes
+    fetch, write = pmc_per_kernel(a.fetch), pmc_per_kernel(a.write)
+    kernels = [(k.rsplit("=", 1)[0], float(k.rsplit("=", 1)[1])) for k in a.kernel]
+    rows, nf, nw, rd_sum, wr_sum, alg_sum, dur_sum = [], 0, 0, 0.0, 0.0, 0.0, 0.0
+    for name, ub in kernels:
+        f, w = fetch[name], write[name]
+        rd, wr, alg = f[1] * sf * 1024.0, w[1] * sw * 1024.0, a.units * ub
+        rows.append(f"| `{name}` | {f[0]} / {w[0]} | {f[1]:.1f} | {w[1]:.1f} | {rd + wr:.4g} | {alg:.4g} | "
+                    f"{(rd + wr) / alg:.3f} | {f[2] / 1e3:.1f} |")
+        nf += f[0]
+        nw += w[0]
+        rd_sum += f[0] * rd
+        wr_sum += w[0] * wr
+        alg_sum += f[0] * alg
+        dur_sum += f[0] * f[2]
+    rd, wr, alg = rd_sum / nf, wr_sum / nw, alg_sum / nf
+    names = ", ".join(n for n, _ in kernels)
     out = [f"# {a.title}", "", "Commands (run from the repository root on an MI355X, each counter in its own pass):",
            "", "```", a.cmd, "```", "",
            f"Calibration: a device copy of {a.copy_bytes} bytes (`{COPY_KERNEL}`) reads "
            f"FETCH_SIZE = {cf[1]:.1f} KiB and WRITE_SIZE = {cw[1]:.1f} KiB per dispatch, so the counters are "
            f"scaled by {sf:.4f} (fetch) and {sw:.4f} (write).", "",
-           "| quantity | value |", "|---|---:|",
-           f"| kernel | `{a.kernel}` |",
-           f"| dispatches (fetch pass / write pass) | {f[0]} / {w[0]} |",
-           f"| FETCH_SIZE per dispatch, raw KiB | {f[1]:.1f} |",
-           f"| WRITE_SIZE per dispatch, raw KiB | {w[1]:.1f} |",
-           f"| HBM read per launch, bytes (scaled) | {rd:.4g} |",
-           f"| HBM write per launch, bytes (scaled) | {wr:.4g} |",
-           f"| HBM traffic per launch, bytes | {rd + wr:.4g} |",
-           f"| algorithmic bytes per launch ({a.units} units x {a.unit_bytes} B) | {alg:.4g} |",
-           f"| traffic / algorithmic | {(rd + wr) / alg:.3f} |",
-           f"| mean duration under counters, us | {f[2] / 1e3:.1f} |", "",
+           "| kernel | dispatches (fetch / write pass) | FETCH_SIZE raw KiB | WRITE_SIZE raw KiB | "
+           "HBM traffic per launch, B | algorithmic per launch, B | traffic / algorithmic | mean us under counters |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|", *rows, "",
+           f"Over all {nf} launches: HBM read {rd:.4g} B and write {wr:.4g} B per launch (scaled), traffic "
+           f"{rd + wr:.4g} B against {alg:.4g} algorithmic ({a.units} units per launch): "
+           f"{(rd + wr) / alg:.3f}; mean duration under counters {dur_sum / nf / 1e3:.1f} us.", "",
            "Machine-readable:", "", "```",
-           f"kernel: {a.kernel}",
+           f"kernel: {names}",
            f"traffic_bytes_per_launch: {rd + wr:.6g}",
            f"read_bytes_per_launch: {rd:.6g}",
            f"write_bytes_per_launch: {wr:.6g}",
@@ -300,11 +311,12 @@ def main(argv=None):
     mf.add_argument("--title", required=True)
     mf.add_argument("--cmd", required=True)
     t = sub.add_parser("traffic")
-    for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "title", "cmd"):
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "title", "cmd"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    t.add_argument("--kernel", action="append", required=True,
+                   help="NAME=BYTES_PER_UNIT (repeat for several kernels counted together)")
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--units", type=int, required=True)
-    t.add_argument("--unit-bytes", type=float, required=True)
     a = ap.parse_args(argv)
     if a.mode == "stats":
         print(stats_report(a.db, a.title, a.cmd, a.top), end="")

@@ -96,17 +96,19 @@ def test_mixed_solve_finishes_in_fp64_when_refinement_is_cut_short():
 @pytest.mark.parametrize("precond", ["multigrid", "chebyshev"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_sweep_timing_counts_and_leaves_the_solution_unchanged(precision, precond):
-    """kernel_timing stamps the full-traffic sweeps' own start and end: the stats count them,
-    their bytes are 4 vectors per interior point per sweep, and the solve is bitwise the one
+    """kernel_timing stamps the smoother sweeps' own start and end on the problem's grid: the
+    stats count them, their bytes are 3 vectors per interior point for a pass's first step and
+    4 for the others (the full-traffic sweeps, counted apart), and the solve is bitwise the one
     without timing."""
     print(f"[case] sweep timing sphere 40^3 {precision} {precond}", flush=True)
     w = _sphere()
     u0, st0 = cps.Solver.from_workload(w, precision=precision, precond=precond).solve(1e-10)
     u1, st1 = cps.Solver.from_workload(w, precision=precision, precond=precond, kernel_timing=1).solve(1e-10)
-    n, pts = st1["sweep_launches"], st1["sweep_points"]
+    n, nf, pts = st1["sweep_launches"], st1["sweep_full_launches"], st1["sweep_points"]
     vb = 4 if precision == "mixed" else 8
-    print(f"{n} timed sweeps, {1e3 * st1['sweep_ms'] / max(n, 1):.2f} us each")
-    assert pts == 38 ** 3 and n > 0 and st1["sweep_bytes"] == n * 4 * vb * pts
-    assert 0.0 < st1["sweep_ms"] / n < 5.0
+    print(f"{n} timed sweeps ({nf} full-traffic), {1e3 * st1['sweep_ms'] / max(n, 1):.2f} us each")
+    assert pts == 38 ** 3 and 0 < nf < n
+    assert st1["sweep_bytes"] == (3 * (n - nf) + 4 * nf) * vb * pts
+    assert 0.0 < st1["sweep_full_ms"] < st1["sweep_ms"] and 0.0 < st1["sweep_ms"] / n < 5.0
     assert st0["sweep_launches"] == 0 and st0["sweep_ms"] == 0.0
     assert st1["iters"] == st0["iters"] and bool((u0 == u1).all())

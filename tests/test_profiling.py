@@ -29,8 +29,7 @@ def test_traffic_report_scales_by_copy_calibration(tmp_path):
                                     (k, 7.0, 100.0, 512), (k, 5.0, 100.0, 512)])
     w = _pmc_db(tmp_path / "w.db", [(k, 50.0, 2000.0)] * 2)
     a = argparse.Namespace(fetch=f, write=w, copy_fetch=cf, copy_write=cw, copy_bytes=copy_bytes,
-                           kernel="cps::k_cheb<float, false>", units=1000, unit_bytes=16.0,
-                           title="t", cmd="c")
+                           kernel=["cps::k_cheb<float, false>=16"], units=1000, title="t", cmd="c")
     rep = profiling.traffic_report(a)
     p = tmp_path / "rep.md"
     p.write_text(rep)
@@ -42,6 +41,25 @@ def test_traffic_report_scales_by_copy_calibration(tmp_path):
     assert float(kv["algorithmic_bytes_per_launch"]) == 16000.0
     assert kv["kernel_source_sha256_16"] == profiling.source_hash()
     assert len(profiling.source_hash()) == 16
+
+
+def test_traffic_report_averages_several_kernels_over_their_launches(tmp_path):
+    """Two instantiations counted together: per-launch figures are launch-weighted means."""
+    copy_bytes = 1 << 20
+    cf = _pmc_db(tmp_path / "cf.db", [(profiling.COPY_KERNEL, 1024.0, 10.0)])
+    cw = _pmc_db(tmp_path / "cw.db", [(profiling.COPY_KERNEL, 1024.0, 10.0)])
+    a_, b_ = "cps::k_cheb<float, true>", "cps::k_cheb<float, false>"
+    f = _pmc_db(tmp_path / "f.db", [(a_, 100.0, 10.0)] * 2 + [(b_, 400.0, 10.0)])     # 2 + 1 launches
+    w = _pmc_db(tmp_path / "w.db", [(a_, 10.0, 10.0)] * 2 + [(b_, 40.0, 10.0)])
+    a = argparse.Namespace(fetch=f, write=w, copy_fetch=cf, copy_write=cw, copy_bytes=copy_bytes,
+                           kernel=[a_ + "=12", b_ + "=16"], units=100, title="t", cmd="c")
+    p = tmp_path / "rep.md"
+    p.write_text(profiling.traffic_report(a))
+    kv = profiling.read_traffic(str(p))
+    assert abs(float(kv["read_bytes_per_launch"]) - (2 * 100 + 400) / 3 * 1024) < 1.0
+    assert abs(float(kv["write_bytes_per_launch"]) - (2 * 10 + 40) / 3 * 1024) < 1.0
+    assert abs(float(kv["algorithmic_bytes_per_launch"]) - (2 * 1200 + 1600) / 3) < 1e-2   # 6 digits printed
+    assert kv["kernel"] == f"{a_}, {b_}"
 
 
 def test_read_traffic_missing(tmp_path):
