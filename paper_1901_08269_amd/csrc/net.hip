@@ -131,7 +131,13 @@ __global__ void __launch_bounds__(256) k_conv3(int n, int V, int Cin, int Cout, 
 // ---------------------------------------------------------------------------------------
 // weight gradient: P[chunk][co][tap][ci] = sum_{v in chunk} G[v][co] X[v+tap][ci]
 // ---------------------------------------------------------------------------------------
-constexpr int WG_CHUNK = 1024;   // voxels per block
+// voxels per block: enough blocks to fill the GPU (about 2048 with the 27 taps), at most 4096
+// voxels (fewer chunk partials to reduce), a multiple of WG_VS
+inline int wgrad_chunk(int V)
+{
+    const int c = (int)std::min<long>(4096, std::max<long>(256, (long)V * 27 / 2048));
+    return (c + 63) / 64 * 64;
+}
 constexpr int WG_VS = 64;        // voxels staged in LDS per barrier: four 16-voxel MFMA steps
 constexpr int WG_MAXT = 7;       // 16x16 tiles per wave (Cout/16 * Cin/16 <= 28)
 
@@ -140,7 +146,7 @@ constexpr int WG_MAXT = 7;       // 16x16 tiles per wave (Cout/16 * Cin/16 <= 28
 // with fewer (the 16-channel layers, which run on the largest grids), wave w takes the w-th
 // 16-voxel step of every tile and the four waves' sums are added in wave order at the end,
 // so that no wave idles.
-__global__ void __launch_bounds__(256) k_wgrad(int n, int V, int Cin, int Cout, const bf16 *__restrict__ G,
+__global__ void __launch_bounds__(256) k_wgrad(int n, int V, int Cin, int Cout, int wchunk, const bf16 *__restrict__ G,
                                                const bf16 *__restrict__ X, float *__restrict__ P)
 {
     __shared__ bf16 sG[WG_VS][64 + 4];
@@ -155,7 +161,7 @@ __global__ void __launch_bounds__(256) k_wgrad(int n, int V, int Cin, int Cout, 
     f32x4 acc[WG_MAXT];
 #pragma unroll
     for (int t = 0; t < WG_MAXT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int vbeg = chunk * WG_CHUNK, vend = min(vbeg + WG_CHUNK, V);
+    const int vbeg = chunk * wchunk, vend = min(vbeg + wchunk, V);
     const int g4 = Cout / 4, x4 = Cin / 4;
     const int m = lane & 15, kq = lane >> 4;
     for (int vs = vbeg; vs < vend; vs += WG_VS) {
@@ -218,13 +224,14 @@ __global__ void __launch_bounds__(256) k_wgrad(int n, int V, int Cin, int Cout, 
 __global__ void k_wgrad_reduce(int nchunk, int Cin, int Cout, int ci_real, const float *__restrict__ P,
                                float *__restrict__ gW)
 {
+    // thread order (co, tap, ci): consecutive threads read consecutive partials of a chunk
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     int total = Cout * ci_real * 27;
     if (q >= total) return;
-    int tap = q % 27, ci = (q / 27) % ci_real, co = q / (27 * ci_real);
+    int ci = q % ci_real, tap = (q / ci_real) % 27, co = q / (27 * ci_real);
     float s = 0.f;
     for (int c = 0; c < nchunk; ++c) s += P[(((size_t)c * Cout + co) * 27 + tap) * Cin + ci];
-    gW[q] = s;
+    gW[((size_t)co * ci_real + ci) * 27 + tap] = s;
 }
 
 // db[c] = sum_v G[v][c] in two fixed-order passes.  Pass 1: COLSUM_BLOCKS blocks; thread t of
@@ -250,13 +257,21 @@ __global__ void __launch_bounds__(256) k_colsum_part(int V, int C, const bf16 *_
     }
 }
 
-__global__ void k_colsum_final(int nb, int C, const float *__restrict__ part, float *__restrict__ out)
+// one block per channel: thread t adds partials t, t + 256, ...; then a tree in LDS
+__global__ void __launch_bounds__(256) k_colsum_final(int nb, int C, const float *__restrict__ part,
+                                                      float *__restrict__ out)
 {
-    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (c >= C) return;
+    __shared__ float sh[256];
+    const int c = (int)blockIdx.x, t = (int)threadIdx.x;
     float acc = 0.f;
-    for (int b = 0; b < nb; ++b) acc += part[(size_t)b * C + c];
-    out[c] = acc;
+    for (int b = t; b < nb; b += 256) acc += part[(size_t)b * C + c];
+    sh[t] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) sh[t] += sh[t + o];
+        __syncthreads();
+    }
+    if (t == 0) out[c] = sh[0];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -449,13 +464,21 @@ __global__ void k_head_bwd(int V, int C, const float *__restrict__ p, const floa
         for (int c = 0; c <= C; ++c) part[(size_t)blockIdx.x * (C + 1) + c] = sh[0][c];
 }
 
-__global__ void k_head_bwd_final(int nb, int C, const float *__restrict__ part, float *__restrict__ g)
+// one block per output (C weights and the bias): partials t, t + 256, ... then a tree
+__global__ void __launch_bounds__(256) k_head_bwd_final(int nb, int C, const float *__restrict__ part,
+                                                        float *__restrict__ g)
 {
-    int c = threadIdx.x;
-    if (c > C) return;
+    __shared__ float sh[256];
+    const int c = (int)blockIdx.x, t = (int)threadIdx.x;
     float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += part[(size_t)b * (C + 1) + c];
-    g[c] = s;
+    for (int b = t; b < nb; b += 256) s += part[(size_t)b * (C + 1) + c];
+    sh[t] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) sh[t] += sh[t + o];
+        __syncthreads();
+    }
+    if (t == 0) g[c] = sh[0];
 }
 
 // Adam on the FP32 master parameters (Kingma & Ba), step t >= 1
@@ -818,7 +841,7 @@ void backward(cps_model *m, int B)
     const int nhb = HEAD_BLOCKS;
     k_head_bwd<<<nhb, 256, 0, m->stream>>>(V0, C0, m->pred, m->tgt, m->msk, m->lossv, m->out[NLAYER - 1],
                                            m->w + m->head_off, m->gout[NLAYER - 1], m->hpart);
-    k_head_bwd_final<<<1, 64, 0, m->stream>>>(nhb, C0, m->hpart, m->g + m->head_off);
+    k_head_bwd_final<<<C0 + 1, 256, 0, m->stream>>>(nhb, C0, m->hpart, m->g + m->head_off);
     for (int q = NLAYER - 1; q >= 0; --q) {
         const LayerInfo &l = m->L[q];
         const int n = nc >> l.lvl;
@@ -826,12 +849,12 @@ void backward(cps_model *m, int B)
         size_t nout = (size_t)V * l.co;
         k_relu_bwd<<<nblk(nout), 256, 0, m->stream>>>(nout, m->gout[q], m->out[q], m->gb);
         // weight and bias gradients
-        int nchunk = (V + WG_CHUNK - 1) / WG_CHUNK;
-        k_wgrad<<<dim3(nchunk, 27), 256, 0, m->stream>>>(n, V, l.cip, l.co, m->gb, m->in[q], m->wpart);
+        const int wchunk = wgrad_chunk(V), nchunk = (V + wchunk - 1) / wchunk;
+        k_wgrad<<<dim3(nchunk, 27), 256, 0, m->stream>>>(n, V, l.cip, l.co, wchunk, m->gb, m->in[q], m->wpart);
         k_wgrad_reduce<<<nblk((size_t)l.co * l.ci * 27), 256, 0, m->stream>>>(nchunk, l.cip, l.co, l.ci, m->wpart,
                                                                               m->g + l.off);
         k_colsum_part<<<COLSUM_BLOCKS, 256, 0, m->stream>>>(V, l.co, m->gb, m->cpart);
-        k_colsum_final<<<nblk((size_t)l.co), 256, 0, m->stream>>>(COLSUM_BLOCKS, l.co, m->cpart,
+        k_colsum_final<<<l.co, 256, 0, m->stream>>>(COLSUM_BLOCKS, l.co, m->cpart,
                                                                  m->g + l.off + (long)l.co * l.ci * 27);
         if (q == 0) break;
         // data gradient into the producer of this layer's input
@@ -904,8 +927,12 @@ int cps_model_create(cps_model **out, const cps_model_spec *spec, void *stream)
             m->gout[q] = nalloc<float>(m, V * l.co);
             maxci = std::max(maxci, V * l.cip);
             maxco = std::max(maxco, V * l.co);
-            size_t nchunk = (V + WG_CHUNK - 1) / WG_CHUNK;
-            m->wpart_n = std::max(m->wpart_n, nchunk * l.co * 27 * l.cip);
+            // the chunk count for every batch size up to B (the chunk size depends on V)
+            for (int bb = 1; bb <= B; ++bb) {
+                const size_t Vb = (size_t)bb * n * n * n;
+                const size_t wchunk = wgrad_chunk((int)Vb), nchunk = (Vb + wchunk - 1) / wchunk;
+                m->wpart_n = std::max(m->wpart_n, nchunk * l.co * 27 * l.cip);
+            }
         }
         for (int q = 0; q < NLAYER; ++q) {
             LayerInfo &l = m->L[q];
