@@ -32,6 +32,10 @@ void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *
 template <typename T>
 void launch_resid(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, const T *rho, T *r,
                   const DevState *st, int rev);
+// r = rho - K x at the irregular nodes only (one thread per irregular row)
+template <typename T>
+void launch_resid_irregular(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, const T *rho, T *r,
+                            const DevState *st);
 template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st);
@@ -65,21 +69,33 @@ struct MgTransfer {
     int nf[3], nc[3];
     MgAxis<T> ax[3];
 };
-// The coarse level's first Chebyshev step from zero, fused with the restriction: x1 = c2 rc /
-// diag K at its unknown nodes (cf: the level's tables; irr_map: irregular row of each
-// irregular node, k7: their K rows).  x1 = null: no first step.
+// What the restriction writes besides rho on a coarse level: diag, the diagonal of the
+// level's K at its unknown nodes and 0 at every other node (it marks the unknowns), and,
+// with x1 non-null, the level's first Chebyshev step from zero, x1 = c2 rc / diag K, at its
+// unknown nodes.
 template <typename T>
 struct MgFirst {
     T *x1;
     T c2;
-    Coef<T> cf;
-    const int *irr_map;
-    const T *k7;
+    const T *diag;
 };
-// rc = R r at the unknown coarse interior nodes (type_c), 0 at the other interior nodes
+// rc = R r at the unknown coarse interior nodes (first.diag non-zero), 0 at the other
+// interior nodes
 template <typename T>
-void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_c, const T *r, T *rc,
-                        const MgFirst<T> &first);
+void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const T *r, T *rc, const MgFirst<T> &first);
+// diag = the diagonal of K at the unknown nodes of a level (1D tables cf, or the stored row
+// of an irregular node), 0 at its other nodes
+template <typename T>
+void launch_mg_diag(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf, const int8_t *type, const int *irr_map,
+                    const T *k7, T *diag);
+// rc = R (rho - K x) from the problem's grid (geometry g, skip bits, tables cf) into the
+// first coarse level, the fine residual never stored: ri holds the residual at the
+// irregular nodes (launch_resid_irregular) and 0 at the solid ones.  first: as for
+// launch_mg_restrict.
+template <typename T>
+void launch_mg_resid_restrict(hipStream_t s, const Geom &g, const Coef<T> &cf, const uint32_t *skip, const T *x,
+                              const T *rho, const T *ri, const MgTransfer<T> &t, T *rc, const MgFirst<T> &first,
+                              const DevState *st);
 // The coarsest level's `steps` Chebyshev steps (coefficients c1, c2) from 0 in one workgroup
 // of MG_LDS_THREADS threads; the level has at most MG_LDS_NODES interior nodes.  irr_map:
 // irregular row of each irregular node.  Writes out at the unknown nodes.

@@ -44,12 +44,11 @@ struct MgVec4<double> {
 // rows as a 4-vector, and node 2 I0 + 3 from the next lane.  Every load is issued whatever
 // the node types.
 // With a first step F (F.x1 non-null) it also writes the coarse level's first Chebyshev
-// step from zero, x1 = c2 rho / diag K, at its unknown nodes (the diagonal from the 1D
-// tables, or the stored row of an irregular node).
+// step from zero, x1 = c2 rho / diag K, at its unknown nodes.
 template <typename T>
 __global__ void __launch_bounds__(256) k_mg_restrict(int ncx, int ncy, int nfx, int nfy, MgAxis<T> ax, MgAxis<T> ay,
-                                                     MgAxis<T> az, const int8_t *__restrict__ type_c,
-                                                     const T *__restrict__ r, T *__restrict__ rc, MgFirst<T> F)
+                                                     MgAxis<T> az, const T *__restrict__ r, T *__restrict__ rc,
+                                                     MgFirst<T> F)
 {
     using V = typename MgVec4<T>::type;
     const int I0 = 1 + (int)(blockIdx.x * 128 + 2 * threadIdx.x), J = 1 + (int)(blockIdx.y * 4 + threadIdx.y);
@@ -64,7 +63,8 @@ __global__ void __launch_bounds__(256) k_mg_restrict(int ncx, int ncy, int nfx, 
         w1[a] = ax.rw[3 * I1 + a];
     }
     const size_t ec = (size_t)I0 + (size_t)ncx * (J + (size_t)ncy * K);
-    const bool unk0 = unknown(type_c[ec]), unk1 = two && unknown(type_c[ec + 1]);
+    const T dg0 = F.diag[ec], dg1 = two ? F.diag[ec + 1] : T(0);
+    const bool unk0 = dg0 != T(0), unk1 = dg1 != T(0);
     const size_t fplane = (size_t)nfx * nfy;
     const int f0 = 2 * I0 - 1;                      // first fine node of the lane
     const int f4 = min(f0 + 4, nfx - 1);            // fifth node (I0 + 1's last), in the row
@@ -90,14 +90,312 @@ __global__ void __launch_bounds__(256) k_mg_restrict(int ncx, int ncy, int nfx, 
     rc[ec] = unk0 ? acc0 : T(0);
     if (two) rc[ec + 1] = unk1 ? acc1 : T(0);
     if (F.x1) {
-        const T dyz = F.cf.c[1][8 * J + 6] + F.cf.c[2][8 * K + 6];
-        if (unk0) {
-            const T dg = type_c[ec] == 2 ? F.k7[7 * (size_t)F.irr_map[ec]] : F.cf.c[0][8 * I0 + 6] + dyz;
-            F.x1[ec] = F.c2 * acc0 / dg;
+        if (unk0) F.x1[ec] = F.c2 * acc0 / dg0;
+        if (unk1) F.x1[ec + 1] = F.c2 * acc1 / dg1;
+    }
+}
+
+// A wave-uniform value moved to a scalar register.
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// rho - K x at a regular node from its seven x values (centre c, then the -x, +x, -y, +y,
+// -z, +z neighbours) and the 1D tables of its three indices (Eq. 2ndorder_coef).
+template <typename T>
+__device__ __forceinline__ T mg_reg_resid(T rh, T c, T w, T e, T s, T n, T m, T u, T kax, T kbx, T kcx, T kay,
+                                          T kby, T kcy, T za, T zb, T zc)
+{
+    const T kd = kbx + kby + zb;
+    return rh - (kd * c + kax * w + kcx * e + kay * s + kcy * n + za * m + zc * u);
+}
+
+// Residual and restriction in one pass on the problem's grid: rc = R (rho - K x) at the
+// unknown coarse nodes, 0 at the other interior ones (the sums of k_mg_restrict, in its
+// order), with no fine residual stored.  A wavefront owns coarse row J of a 128-node coarse
+// segment bs and the coarse planes K0 .. K1 - 1 of a chunk.  Lane l takes coarse nodes
+// I0 = 1 + 128 bs + 2 l and I0 + 1, whose fine points are f0 = 2 I0 - 1 .. f0 + 4: it forms
+// the residual at f0 .. f0 + 3 (the four-node layout of the vectorised sweeps) and takes
+// the one at f0 + 4 from the next lane; the last lane forms its own fifth node when its
+// segment owns I0 + 1 and f0 + 4 is interior.  The wavefront marches over the fine planes
+// 2 K0 - 1 .. 2 K1 - 1: at each it forms the residual of fine rows 2J - 1 .. 2J + 1 from x
+// on rows 2J - 2 .. 2J + 2 (the planes below and above carried in registers), combines it
+// in x and y, and adds it to the coarse planes that the fine plane belongs to; coarse plane
+// K is complete, and stored, after fine plane 2K + 1.  Fine rows 2J - 1 and 2J + 1 are formed
+// by both wavefronts that need them, the first fine plane of a chunk by both chunks.
+// Irregular and solid fine nodes (skip bits) take their residual from ri, which holds it
+// at the irregular nodes (the irregular rows of the residual kernel, run before) and 0 at
+// the solid ones; walls give 0.  With a first step F (F.x1 non-null) the coarse level's first Chebyshev
+// step from zero is written too, as k_mg_restrict does.
+// Loads through a buffer resource based at a wave-uniform address (one plane of an
+// array): the 32-bit byte offset of each lane goes in a vector register and the base in
+// scalar registers, so an address costs no 64-bit vector arithmetic (this kernel issues
+// about twenty loads per plane step, and its throughput is bound by instruction issue).
+typedef uint32_t MgU4 __attribute__((ext_vector_type(4)));
+struct MgF4 {
+    float v[4];
+};
+struct MgD2 {
+    double v[2];
+};
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base)
+{
+    // raw buffer (stride 0), range 4 GiB from the base, 32-bit data format (CDNA)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ typename MgVec4<T>::type bload4(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ MgVec4<float>::type bload4<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    const MgF4 f = __builtin_bit_cast(MgF4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    return MgVec4<float>::type{f.v[0], f.v[1], f.v[2], f.v[3]};
+}
+template <>
+__device__ __forceinline__ MgVec4<double>::type bload4<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    const MgD2 a = __builtin_bit_cast(MgD2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const MgD2 b = __builtin_bit_cast(MgD2, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0));
+    return MgVec4<double>::type{a.v[0], a.v[1], b.v[0], b.v[1]};
+}
+template <typename T>
+__device__ __forceinline__ T bload1(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float bload1<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double bload1<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ uint32_t bload_u32(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+template <typename T, bool FIFTH>
+__global__ void __launch_bounds__(256) k_mg_resid_restrict(Geom g, Tiling tl, Coef<T> cf,
+                                                           const uint32_t *__restrict__ skip,
+                                                           const T *__restrict__ x, const T *__restrict__ rho,
+                                                           const T *__restrict__ ri, int ncx, int ncy, int ncz,
+                                                           MgAxis<T> ax, MgAxis<T> ay, MgAxis<T> az,
+                                                           T *__restrict__ rc, MgFirst<T> F, const DevState *st)
+{
+    using V = typename MgVec4<T>::type;
+    if (st && st->done) return;
+    int bs, by, bz;
+    if (!tile_of_block(tl, (int)blockIdx.x, bs, by, bz)) return;
+    const int J = 1 + by * 4 + (int)threadIdx.y;
+    if (J > ncy - 2) return;                                   // whole wavefront
+    const int lane = (int)threadIdx.x;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t plane = (size_t)nx * ny, wplane = (size_t)ny * g.W;
+    const int I0 = 1 + 128 * bs + 2 * lane;
+    const bool own0 = I0 <= ncx - 2, own1 = I0 + 1 <= ncx - 2;
+    const int f0 = 2 * I0 - 1;
+    const int nv = min(4, nx - 1 - f0);                       // interior fine nodes of the lane
+    // the lane's loads start at node ic: f0, or the wall node for lanes past the row end.
+    // Values past the lane's valid nodes are never used: their residuals are zeroed, and
+    // the +x neighbour of the last interior node is the wall node (0 in every vector).
+    const int ic = min(f0, nx - 1);
+    const bool need5 = FIFTH && lane == 63 && own1 && f0 + 4 <= nx - 2;
+    const bool needl = lane == 0 && bs > 0;                   // node f0 - 1 is interior
+    // the skip bits that matter: the lane's interior nodes, and the fifth node where formed
+    const uint32_t smask = ((1u << max(nv, 0)) - 1u) | (need5 ? 0x10u : 0u);
+    T w0[3], w1[3];
+    {
+        const int a0 = own0 ? I0 : 1, a1 = own1 ? I0 + 1 : a0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            w0[a] = ax.rw[3 * a0 + a];
+            w1[a] = ax.rw[3 * a1 + a];
         }
-        if (unk1) {
-            const T dg = type_c[ec + 1] == 2 ? F.k7[7 * (size_t)F.irr_map[ec + 1]] : F.cf.c[0][8 * (I0 + 1) + 6] + dyz;
-            F.x1[ec + 1] = F.c2 * acc1 / dg;
+    }
+    T kax[5], kbx[5], kcx[5];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+        const bool ok = u < 4 ? u < nv : need5;
+        const T *cx = cf.c[0] + 8 * (ok ? f0 + u : 1);
+        kax[u] = cx[5];
+        kbx[u] = cx[6];
+        kcx[u] = cx[7];
+    }
+    // in-plane byte offsets of node ic on x rows 2J - 2 .. 2J + 2 (the last clamped to the
+    // wall row, where x is 0); the residual rows 2J - 1 .. 2J + 1 are x rows 1 .. 3, the last
+    // of them possibly the wall row; ow: byte offsets of their skip words
+    uint32_t ox[5], ow[3];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) ox[c] = (uint32_t)((ic + nx * min(2 * J - 2 + c, ny - 1)) * sizeof(T));
+    bool rok[3];
+    T kay[3], kby[3], kcy[3], wy[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int j = 2 * J - 1 + b;
+        rok[b] = j <= ny - 2;
+        const int jc = min(j, ny - 1);
+        ow[b] = (uint32_t)((jc * g.W + (ic >> 5)) * sizeof(uint32_t));
+        kay[b] = wave_uniform(cf.c[1][8 * jc + 5]);
+        kby[b] = wave_uniform(cf.c[1][8 * jc + 6]);
+        kcy[b] = wave_uniform(cf.c[1][8 * jc + 7]);
+        wy[b] = wave_uniform(ay.rw[3 * J + b]);
+    }
+
+    const int K0 = 1 + bz * tl.TZ, K1 = min(K0 + tl.TZ, ncz - 1);
+    const int p0 = 2 * K0 - 1, p1 = 2 * K1 - 1;
+    // x of the residual rows at the plane below (m) and at the current one (c); the fifth
+    // node's in m5, c5
+    V xm[3], xc[3];
+    T m5[3], c5[3];
+    {
+        const __amdgpu_buffer_rsrc_t xb = plane_rsrc(x + (size_t)(p0 - 1) * plane), x0 = plane_rsrc(x + (size_t)p0 * plane);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            xm[b] = bload4<T>(xb, ox[b + 1]);
+            xc[b] = bload4<T>(x0, ox[b + 1]);
+            m5[b] = need5 ? bload1<T>(xb, ox[b + 1] + 4 * sizeof(T)) : T(0);
+            c5[b] = need5 ? bload1<T>(x0, ox[b + 1] + 4 * sizeof(T)) : T(0);
+        }
+    }
+    // the coarse plane being summed: the diagonals of its nodes (0 where not an unknown),
+    // loaded when the plane opens and used when it is stored two fine planes later
+    T acc0 = T(0), acc1 = T(0), dg0 = T(0), dg1 = T(0);
+    auto open = [&](int K) {
+        acc0 = T(0);
+        acc1 = T(0);
+        const size_t ec = (size_t)(own0 ? I0 : 1) + (size_t)ncx * (J + (size_t)ncy * K);
+        dg0 = own0 ? F.diag[ec] : T(0);
+        dg1 = own1 ? F.diag[ec + 1] : T(0);
+    };
+    auto emit = [&](int K) {
+        const size_t ec = (size_t)(own0 ? I0 : 1) + (size_t)ncx * (J + (size_t)ncy * K);
+        if (own0) rc[ec] = dg0 != T(0) ? acc0 : T(0);
+        if (own1) rc[ec + 1] = dg1 != T(0) ? acc1 : T(0);
+        if (F.x1) {
+            if (dg0 != T(0)) F.x1[ec] = F.c2 * acc0 / dg0;
+            if (dg1 != T(0)) F.x1[ec + 1] = F.c2 * acc1 / dg1;
+        }
+    };
+    // skip bits of nodes ic .. ic + 4 on the residual rows of plane q (words read in pairs;
+    // the array carries two words of padding), loaded one plane ahead
+    auto skip_bits = [&](int q, int b) -> uint32_t {
+        const __amdgpu_buffer_rsrc_t sq = plane_rsrc(skip + (size_t)q * wplane);
+        const uint64_t pair = (uint64_t)bload_u32(sq, ow[b]) | ((uint64_t)bload_u32(sq, ow[b] + 4) << 32);
+        return (uint32_t)(pair >> (ic & 31)) & smask;
+    };
+    uint32_t skn[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) skn[b] = skip_bits(p0, b);
+    for (int p = p0; p <= p1; ++p) {
+        const bool pv = p <= nz - 2;                          // fine plane p is interior
+        const size_t kp = (size_t)p * plane;
+        const __amdgpu_buffer_rsrc_t xk = plane_rsrc(x + kp), xn = plane_rsrc(x + (size_t)min(p + 1, nz - 1) * plane);
+        const __amdgpu_buffer_rsrc_t rk = plane_rsrc(rho + kp), rik = plane_rsrc(ri + kp);
+        V xp[3], rh[3], ri4[3];
+        uint32_t sk[3];
+        T lf[3], p5[3], q5[3], h5[3], ri5[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const uint32_t o = ox[b + 1];
+            sk[b] = skn[b];
+            skn[b] = skip_bits(min(p + 1, nz - 1), b);
+            xp[b] = bload4<T>(xn, o);
+            rh[b] = bload4<T>(rk, o);
+            // the residual at the lane's solid and irregular nodes (issued with the other loads)
+            if (sk[b]) ri4[b] = bload4<T>(rik, o);
+            else ri4[b] = V{T(0), T(0), T(0), T(0)};
+            ri5[b] = (FIFTH && ((sk[b] >> 4) & 1u)) ? bload1<T>(rik, o + 4 * sizeof(T)) : T(0);
+            lf[b] = needl ? bload1<T>(xk, o - sizeof(T)) : T(0);
+            p5[b] = need5 ? bload1<T>(xn, o + 4 * sizeof(T)) : T(0);
+            q5[b] = need5 ? bload1<T>(xk, o + 5 * sizeof(T)) : T(0);
+            h5[b] = need5 ? bload1<T>(rk, o + 4 * sizeof(T)) : T(0);
+        }
+        const V y0 = bload4<T>(xk, ox[0]), y4 = bload4<T>(xk, ox[4]);
+        const T y05 = need5 ? bload1<T>(xk, ox[0] + 4 * sizeof(T)) : T(0);
+        const T y45 = need5 ? bload1<T>(xk, ox[4] + 4 * sizeof(T)) : T(0);
+        const T *cz = cf.c[2] + 8 * p;
+        const T za = wave_uniform(cz[5]), zb = wave_uniform(cz[6]), zc = wave_uniform(cz[7]);
+        T xr0[3], xr1[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const V &s4 = b == 0 ? y0 : xc[b - 1];
+            const V &n4 = b == 2 ? y4 : xc[b + 1];
+            const T cv[5] = {xc[b].x, xc[b].y, xc[b].z, xc[b].w, c5[b]};
+            const T sv[5] = {s4.x, s4.y, s4.z, s4.w, b == 0 ? y05 : c5[b - 1]};
+            const T nw[5] = {n4.x, n4.y, n4.z, n4.w, b == 2 ? y45 : c5[b + 1]};
+            const T mv[5] = {xm[b].x, xm[b].y, xm[b].z, xm[b].w, m5[b]};
+            const T uv[5] = {xp[b].x, xp[b].y, xp[b].z, xp[b].w, p5[b]};
+            const T rv[5] = {rh[b].x, rh[b].y, rh[b].z, rh[b].w, h5[b]};
+            T left = __shfl_up(cv[3], 1, 64), right = __shfl_down(cv[0], 1, 64);
+            if (lane == 0) left = lf[b];
+            if (lane == 63) right = c5[b];
+            // x neighbours of the five nodes: node u's -x one is wxn[u], its +x one exn[u]
+            const T wxn[5] = {left, cv[0], cv[1], cv[2], cv[3]};
+            const T exn[5] = {cv[1], cv[2], cv[3], right, q5[b]};
+            T r[5];
+#pragma unroll
+            for (int u = 0; u < 5; ++u)
+                r[u] = mg_reg_resid(rv[u], cv[u], wxn[u], exn[u], sv[u], nw[u], mv[u], uv[u], kax[u], kbx[u],
+                                    kcx[u], kay[b], kby[b], kcy[b], za, zb, zc);
+            // solid or irregular nodes: their residual from ri (0 at a solid node)
+            const T qv[5] = {ri4[b].x, ri4[b].y, ri4[b].z, ri4[b].w, ri5[b]};
+#pragma unroll
+            for (int u = 0; u < 5; ++u) r[u] = ((sk[b] >> u) & 1u) ? qv[u] : r[u];
+            const bool live = pv && rok[b];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) r[u] = (live && u < nv) ? r[u] : T(0);
+            T v4 = __shfl_down(r[0], 1, 64);
+            if (lane == 63) v4 = (live && need5) ? r[4] : T(0);
+            xr0[b] = w0[0] * r[0] + w0[1] * r[1] + w0[2] * r[2];
+            xr1[b] = w1[0] * r[2] + w1[1] * r[3] + w1[2] * v4;
+        }
+        if (p & 1) {
+            // fine plane 2K + 1: the last of coarse plane K, the first of K + 1
+            const int K = (p - 1) >> 1;
+            if (K >= K0) {
+                const T wz = wave_uniform(az.rw[3 * K + 2]);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const T wyz = wz * wy[b];
+                    acc0 += wyz * xr0[b];
+                    acc1 += wyz * xr1[b];
+                }
+                emit(K);
+            }
+            if (K + 1 < K1) {
+                open(K + 1);
+                const T wz = wave_uniform(az.rw[3 * (K + 1)]);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const T wyz = wz * wy[b];
+                    acc0 += wyz * xr0[b];
+                    acc1 += wyz * xr1[b];
+                }
+            }
+        } else {
+            const T wz = wave_uniform(az.rw[3 * (p >> 1) + 1]);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const T wyz = wz * wy[b];
+                acc0 += wyz * xr0[b];
+                acc1 += wyz * xr1[b];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            xm[b] = xc[b];
+            xc[b] = xp[b];
+            m5[b] = c5[b];
+            c5[b] = p5[b];
         }
     }
 }
@@ -391,6 +689,23 @@ __global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, 
 }
 
 // map[node] = irregular row of the node (the rows list nodes in increasing order)
+// diag[e] = the diagonal of K at node e if it is an unknown (the 1D tables of a regular node,
+// summed as cx + (cy + cz), or the stored row of an irregular one), 0 otherwise
+template <typename T>
+__global__ void k_mg_diag(int nx, int ny, int nz, Coef<T> cf, const int8_t *__restrict__ type,
+                          const int *__restrict__ irr_map, const T *__restrict__ k7, T *__restrict__ diag)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % nx), j = (int)((e / nx) % ny), k = (int)(e / ((size_t)nx * ny));
+        const int8_t t = type[e];
+        T d = T(0);
+        if (t == 1) d = cf.c[0][8 * i + 6] + (cf.c[1][8 * j + 6] + cf.c[2][8 * k + 6]);
+        else if (t == 2) d = k7[7 * (size_t)irr_map[e]];
+        diag[e] = d;
+    }
+}
+
 __global__ void k_mg_irr_map(int nirr, const int *__restrict__ nodes, int *__restrict__ map)
 {
     const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -400,12 +715,61 @@ __global__ void k_mg_irr_map(int nirr, const int *__restrict__ nodes, int *__res
 }  // namespace
 
 template <typename T>
-void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_c, const T *r, T *rc,
-                        const MgFirst<T> &first)
+void launch_mg_diag(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf, const int8_t *type, const int *irr_map,
+                    const T *k7, T *diag)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    k_mg_diag<T><<<(unsigned)std::min<size_t>((n + 255) / 256, 4096), 256, 0, s>>>(nx, ny, nz, cf, type, irr_map, k7,
+                                                                                  diag);
+}
+
+template <typename T>
+void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const T *r, T *rc, const MgFirst<T> &first)
 {
     dim3 grid((unsigned)((t.nc[0] - 2 + 127) / 128), (unsigned)((t.nc[1] - 2 + 3) / 4), (unsigned)(t.nc[2] - 2));
-    k_mg_restrict<T><<<grid, dim3(64, 4), 0, s>>>(t.nc[0], t.nc[1], t.nf[0], t.nf[1], t.ax[0], t.ax[1], t.ax[2], type_c,
-                                                  r, rc, first);
+    k_mg_restrict<T><<<grid, dim3(64, 4), 0, s>>>(t.nc[0], t.nc[1], t.nf[0], t.nf[1], t.ax[0], t.ax[1], t.ax[2], r,
+                                                  rc, first);
+}
+
+template <typename T>
+void launch_mg_resid_restrict(hipStream_t s, const Geom &g, const Coef<T> &cf, const uint32_t *skip, const T *x,
+                              const T *rho, const T *ri, const MgTransfer<T> &t, T *rc, const MgFirst<T> &first,
+                              const DevState *st)
+{
+    // the fifth-node path (more registers) only where a further segment exists
+    const int ncx = t.nc[0], ncy = t.nc[1], ncz = t.nc[2];
+    const bool fifth = (ncx - 2 + 127) / 128 > 1;
+    const void *fn = fifth ? reinterpret_cast<const void *>(&k_mg_resid_restrict<T, true>)
+                           : reinterpret_cast<const void *>(&k_mg_resid_restrict<T, false>);
+    // The march is bound by the latency of its plane steps: all blocks run in one round,
+    // as many as fit on the device at once (z-chunks of at least two coarse planes).
+    static int per_cu[2] = {0, 0};
+    if (!per_cu[fifth]) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess || nb < 1) nb = 1;
+        per_cu[fifth] = nb;
+    }
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        ncu = 256;
+    Tiling tl{};
+    tl.tw = 128;
+    tl.ty = 4;
+    tl.tiles_x = (ncx - 2 + 127) / 128;
+    tl.tiles_y = (ncy - 2 + 3) / 4;
+    const int nzi = ncz - 2, per_plane = tl.tiles_x * tl.tiles_y;
+    const int want = std::max(1, per_cu[fifth] * ncu / per_plane);
+    tl.TZ = std::max(std::min(2, nzi), (nzi + want - 1) / want);
+    tl.zchunks = (nzi + tl.TZ - 1) / tl.TZ;
+    tl.ntiles = per_plane * tl.zchunks;
+    tl.nblk = (tl.ntiles + NXCD - 1) / NXCD * NXCD;
+    if (fifth)
+        k_mg_resid_restrict<T, true><<<tl.nblk, dim3(64, 4), 0, s>>>(g, tl, cf, skip, x, rho, ri, ncx, ncy, ncz,
+                                                                     t.ax[0], t.ax[1], t.ax[2], rc, first, st);
+    else
+        k_mg_resid_restrict<T, false><<<tl.nblk, dim3(64, 4), 0, s>>>(g, tl, cf, skip, x, rho, ri, ncx, ncy, ncz,
+                                                                      t.ax[0], t.ax[1], t.ax[2], rc, first, st);
 }
 
 template <typename T>
@@ -457,10 +821,20 @@ template void launch_mg_smooth_tb<double>(hipStream_t, int, int, int, const Coef
 template void launch_mg_smooth_tb<float>(hipStream_t, int, int, int, const Coef<float> &, const int8_t *, const int *,
                                          const float *, const float *, const float *, float *, float *,
                                          const MgSteps<float> &, const DevState *);
-template void launch_mg_restrict<double>(hipStream_t, const MgTransfer<double> &, const int8_t *, const double *,
-                                         double *, const MgFirst<double> &);
-template void launch_mg_restrict<float>(hipStream_t, const MgTransfer<float> &, const int8_t *, const float *, float *,
+template void launch_mg_restrict<double>(hipStream_t, const MgTransfer<double> &, const double *, double *,
+                                         const MgFirst<double> &);
+template void launch_mg_restrict<float>(hipStream_t, const MgTransfer<float> &, const float *, float *,
                                         const MgFirst<float> &);
+template void launch_mg_diag<double>(hipStream_t, int, int, int, const Coef<double> &, const int8_t *, const int *,
+                                     const double *, double *);
+template void launch_mg_diag<float>(hipStream_t, int, int, int, const Coef<float> &, const int8_t *, const int *,
+                                    const float *, float *);
+template void launch_mg_resid_restrict<double>(hipStream_t, const Geom &, const Coef<double> &, const uint32_t *, const double *, const double *,
+                                                const double *, const MgTransfer<double> &, double *,
+                                                const MgFirst<double> &, const DevState *);
+template void launch_mg_resid_restrict<float>(hipStream_t, const Geom &, const Coef<float> &, const uint32_t *, const float *, const float *,
+                                               const float *, const MgTransfer<float> &, float *,
+                                               const MgFirst<float> &, const DevState *);
 template void launch_mg_prolong_add<double>(hipStream_t, const MgTransfer<double> &, const int8_t *, const double *,
                                             double *);
 template void launch_mg_prolong_add<float>(hipStream_t, const MgTransfer<float> &, const int8_t *, const float *,

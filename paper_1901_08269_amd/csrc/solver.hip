@@ -68,6 +68,8 @@ struct MgLevel {
     double *k64 = nullptr;
     float *k32 = nullptr;
     int *irr_map = nullptr;     // node -> irregular row (coarse levels)
+    double *dg64 = nullptr;     // diagonal of K at the unknown nodes, 0 elsewhere (coarse
+    float *dg32 = nullptr;      // levels, built on first use of the precision)
     bool lds = false;           // the coarsest level, solved in one workgroup
     MgTransfer<double> t64{};   // transfers to the next coarser level
     MgTransfer<float> t32{};
@@ -538,20 +540,18 @@ T *mg_smooth(cps_solver *s, int lvl, const Launch &L, const Coef<T> &cf, const I
     return dst ? dst : buf(n);
 }
 
-// What the restriction into coarse level l writes besides rho_l: the level's first
-// Chebyshev step from zero into its first iterate buffer, except on the last level (whose
-// own iteration starts from zero).
+// What the restriction into coarse level l needs besides rho_l: the level's diagonal (which
+// marks its unknowns) and, except on the last level (whose own iteration starts from zero),
+// the first iterate buffer that takes the level's first Chebyshev step from zero.
 template <typename T>
 MgFirst<T> mg_first(cps_solver *s, int l)
 {
     MgFirst<T> f{};
-    if (l + 1 == (int)s->mg.size()) return f;
     const MgLevel &Lv = s->mg[l];
+    if constexpr (sizeof(T) == 8) f.diag = Lv.dg64; else f.diag = Lv.dg32;
+    if (l + 1 == (int)s->mg.size()) return f;
     f.x1 = mg_vecs<T>(Lv)[1];
     f.c2 = (T)s->mg_c2[0];
-    f.cf = mg_coef<T>(Lv);
-    f.irr_map = Lv.irr_map;
-    f.k7 = mg_irr<T>(Lv).k7;
     return f;
 }
 
@@ -601,8 +601,7 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
         T *Rr = V[3];
         launch_mg_smooth_tb<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, A, B, Rr,
                                mg_steps<T>(s, 1, nu), st);
-        launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), s->mg[l + 1].type, Rr, mg_vecs<T>(s->mg[l + 1])[0],
-                              mg_first<T>(s, l + 1));
+        launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), Rr, mg_vecs<T>(s->mg[l + 1])[0], mg_first<T>(s, l + 1));
         T *e = mg_level<T>(s, l + 1, st);
         launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.type, e, B);
         launch_mg_smooth_tb<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, B, A, nullptr,
@@ -612,8 +611,7 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
     T *x = mg_smooth<T>(s, l, L, cf, ir, R, nullptr, Z, A, B, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
     T *r = (x == A) ? B : A;
     launch_resid<T>(L, cf, ir, x, R, r, st, next_rev(s, l));
-    launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), s->mg[l + 1].type, r, mg_vecs<T>(s->mg[l + 1])[0],
-                          mg_first<T>(s, l + 1));
+    launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), r, mg_vecs<T>(s->mg[l + 1])[0], mg_first<T>(s, l + 1));
     T *e = mg_level<T>(s, l + 1, st);
     launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.type, e, x);
     return mg_smooth<T>(s, l, L, cf, ir, R, x, Z, x, r, nullptr, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
@@ -626,6 +624,16 @@ template <typename T>
 void mg_precond(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T *v, T *dst, const DevState *st)
 {
     mg_alloc<T>(s);
+    for (size_t l = 1; l < s->mg.size(); ++l) {
+        MgLevel &Lv = s->mg[l];
+        T **dg;
+        if constexpr (sizeof(T) == 8) dg = &Lv.dg64; else dg = &Lv.dg32;
+        if (!*dg) {
+            *dg = dalloc<T>(s, Lv.nn);
+            launch_mg_diag<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], mg_coef<T>(Lv), Lv.type, Lv.irr_map,
+                              mg_irr<T>(Lv).k7, *dg);
+        }
+    }
     const Launch L = s->launch();
     Coef<T> cf;
     Irr<T> ir;
@@ -644,10 +652,13 @@ void mg_precond(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T 
     launch_first<T>(kind, L, cf, ir, r, ps, v, a, s->mg_c2[0], st);
     T *x = mg_smooth<T>(s, 0, L, cf, ir, ps, nullptr, nullptr, a, b, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st,
                         samp);
+    // the residual goes straight into the coarse right-hand side; the other buffer (0 at
+    // the solid nodes, like every iterate) first takes the residual at the irregular nodes,
+    // then serves as the post-smoothing's second iterate
     T *res = (x == a) ? b : a;
-    launch_resid<T>(L, cf, ir, x, ps, res, st, next_rev(s, 0));
-    launch_mg_restrict<T>(s->stream, mg_transfer<T>(s->mg[0]), s->mg[1].type, res, mg_vecs<T>(s->mg[1])[0],
-                          mg_first<T>(s, 1));
+    launch_resid_irregular<T>(L, cf, ir, x, ps, res, st);
+    launch_mg_resid_restrict<T>(s->stream, s->g, cf, L.skip, x, ps, res, mg_transfer<T>(s->mg[0]),
+                                mg_vecs<T>(s->mg[1])[0], mg_first<T>(s, 1), st);
     T *e = mg_level<T>(s, 1, st);
     launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(s->mg[0]), s->type, e, x);
     mg_smooth<T>(s, 0, L, cf, ir, ps, x, nullptr, x, res, dst, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, samp);

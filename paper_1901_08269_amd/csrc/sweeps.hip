@@ -962,6 +962,15 @@ void launch_resid(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T 
 }
 
 template <typename T>
+void launch_resid_irregular(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *x, const T *rho, T *r,
+                            const DevState *st)
+{
+    // a grid of irregular-row blocks only: no tile work
+    const int nib = irr_blocks(ir.n, NT);
+    if (nib > 0) k_resid4<T, RPW2><<<dim3(nib), tile_block(), 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st, 0);
+}
+
+template <typename T>
 void launch_first(int kind, const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *r, T *ps, const T *v, T *x1,
                   double c2, const DevState *st)
 {
@@ -1043,6 +1052,10 @@ template void launch_cheb<double>(const Launch &, const Coef<double> &, const Ir
                                   hipEvent_t, hipEvent_t);
 template void launch_cheb<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
                                  const float *, float *, double, double, const DevState *, int, hipEvent_t, hipEvent_t);
+template void launch_resid_irregular<double>(const Launch &, const Coef<double> &, const Irr<double> &,
+                                             const double *, const double *, double *, const DevState *);
+template void launch_resid_irregular<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *,
+                                            const float *, float *, const DevState *);
 template void launch_resid<double>(const Launch &, const Coef<double> &, const Irr<double> &, const double *,
                                    const double *, double *, const DevState *, int);
 template void launch_resid<float>(const Launch &, const Coef<float> &, const Irr<float> &, const float *, const float *,
