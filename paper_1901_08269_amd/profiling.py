@@ -124,11 +124,14 @@ def algorithmic_bytes(name):
     k_apply4      y = B x with a second operand (V, T), y = B x (plain), r = b - B x (residual)
     k_update4     x += alpha p^ + omega s^, r = s - omega t, with (r0, r)
     k_resid4      r = rho - K x (multigrid): x, rho in, r out
-    k_mg_restrict fine r in, coarse rho out (1/8 of a value per fine point)
+    k_mg_restrict fine r in; coarse rho and first step out, coarse diagonal in (1/8 of a
+                  value each per fine point)
+    k_mg_resid_restrict  x, rho in; coarse rho and first step out, coarse diagonal in
     k_mg_prolong_add  x += P e: x in and out, the coarse e in (1/8 per fine point)
     """
     n = short_name(name)
-    m = re.match(r"cps::(k_cheb4|k_first4|k_apply4|k_update4|k_resid4|k_mg_restrict|k_mg_prolong_add)<(.*)>$", n)
+    m = re.match(r"cps::(k_cheb4|k_first4|k_apply4|k_update4|k_resid4|k_mg_restrict|k_mg_resid_restrict"
+                 r"|k_mg_prolong_add)<(.*)>$", n)
     if not m:
         return None
     kern, args = m.group(1), [a.strip() for a in m.group(2).split(",")]
@@ -140,7 +143,9 @@ def algorithmic_bytes(name):
     if kern == "k_resid4":
         return 3 * t
     if kern == "k_mg_restrict":
-        return t + t / 8
+        return t + 3 * t / 8
+    if kern == "k_mg_resid_restrict":
+        return 2 * t + 3 * t / 8
     if kern == "k_mg_prolong_add":
         return 2 * t + t / 8
     if kern == "k_first4":

@@ -91,6 +91,10 @@ def test_algorithmic_bytes_per_kernel():
     assert ab("void cps::k_finalize<0>(double const*, int, cps::DevState*)") is None
     assert ab("void cps::k_resid4<float>(cps::Geom)") == 12
     assert ab("void cps::(anonymous namespace)::k_mg_prolong_add<double>(int, int)") == 17
+    # fused residual + restriction: x and rho per fine point, three coarse values per 8 points
+    assert ab("void cps::(anonymous namespace)::k_mg_resid_restrict<float, false>(cps::Geom)") == 9.5
+    assert ab("void cps::(anonymous namespace)::k_mg_resid_restrict<double, true>(cps::Geom)") == 19
+    assert ab("void cps::(anonymous namespace)::k_mg_restrict<float>(int)") == 5.5
 
 
 def test_kernels_report(tmp_path):
@@ -111,8 +115,8 @@ def test_kernels_report(tmp_path):
     rep = profiling.kernels_report(str(db), 1000000, "T", "cmd")
     # 16 B x 1e6 points in 40 us = 400 GB/s = 0.05 of 8 TB/s
     assert "| `cps::k_cheb4<float, false>` | 10 | 40.00 | 16 | 400 | 0.05 |" in rep
-    # restriction: 4.5 B per fine point in 20 us = 225 GB/s
-    assert "| `cps::k_mg_restrict<float>` | 1 | 20.00 | 4.5 | 225 | 0.03 |" in rep
+    # restriction: 5.5 B per fine point in 20 us = 275 GB/s
+    assert "| `cps::k_mg_restrict<float>` | 1 | 20.00 | 5.5 | 275 | 0.03 |" in rep
     assert "k_fill" not in rep
 
 
