@@ -129,9 +129,10 @@ void launch_mg_smooth_tb(hipStream_t s, int nx, int ny, int nz, const Coef<T> &c
                          const MgSteps<T> &S, const DevState *st);
 // map[nodes[r]] = r for the nirr irregular rows
 void launch_mg_irr_map(hipStream_t s, int nirr, const int *nodes, int *map);
-// x += P e at the unknown fine nodes (type_f)
+// x += P e at the regular unknown fine nodes (interior nodes without a skip bit in skip_f,
+// W words per x-line)
 template <typename T>
-void launch_mg_prolong_add(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_f, const T *e, T *x);
+void launch_mg_prolong_add(hipStream_t s, const MgTransfer<T> &t, const uint32_t *skip_f, int W, const T *e, T *x);
 
 // sip.hip: the strongly implicit procedure for K (factors per node: b, c, d, e, f, g, h, 0)
 void launch_sip_factor(hipStream_t st, int nx, int ny, int nz, const Coef<double> &cf, const int8_t *type,

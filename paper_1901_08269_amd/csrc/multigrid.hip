@@ -183,7 +183,7 @@ __device__ __forceinline__ uint32_t bload_u32(__amdgpu_buffer_rsrc_t r, uint32_t
     return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
 }
 
-template <typename T, bool FIFTH>
+template <typename T, bool FIFTH, int CR>
 __global__ void __launch_bounds__(256) k_mg_resid_restrict(Geom g, Tiling tl, Coef<T> cf,
                                                            const uint32_t *__restrict__ skip,
                                                            const T *__restrict__ x, const T *__restrict__ rho,
@@ -191,12 +191,13 @@ __global__ void __launch_bounds__(256) k_mg_resid_restrict(Geom g, Tiling tl, Co
                                                            MgAxis<T> ax, MgAxis<T> ay, MgAxis<T> az,
                                                            T *__restrict__ rc, MgFirst<T> F, const DevState *st)
 {
+    constexpr int NR = 2 * CR + 1;                            // fine residual rows of a wavefront
     using V = typename MgVec4<T>::type;
     if (st && st->done) return;
     int bs, by, bz;
     if (!tile_of_block(tl, (int)blockIdx.x, bs, by, bz)) return;
-    const int J = 1 + by * 4 + (int)threadIdx.y;
-    if (J > ncy - 2) return;                                   // whole wavefront
+    const int J0 = 1 + (by * 4 + (int)threadIdx.y) * CR;     // the wavefront's first coarse row
+    if (J0 > ncy - 2) return;                                  // whole wavefront
     const int lane = (int)threadIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const size_t plane = (size_t)nx * ny, wplane = (size_t)ny * g.W;
@@ -230,36 +231,45 @@ __global__ void __launch_bounds__(256) k_mg_resid_restrict(Geom g, Tiling tl, Co
         kbx[u] = cx[6];
         kcx[u] = cx[7];
     }
-    // in-plane byte offsets of node ic on x rows 2J - 2 .. 2J + 2 (the last clamped to the
-    // wall row, where x is 0); the residual rows 2J - 1 .. 2J + 1 are x rows 1 .. 3, the last
-    // of them possibly the wall row; ow: byte offsets of their skip words
-    uint32_t ox[5], ow[3];
+    // in-plane byte offsets of node ic on x rows 2 J0 - 2 .. 2 J0 + 2 CR (clamped to the wall
+    // row, where x is 0); the residual rows 2 J0 - 1 .. 2 J0 + 2 CR - 1 are x rows 1 .. NR,
+    // those past the last interior row zeroed; ow: byte offsets of their skip words
+    uint32_t ox[NR + 2], ow[NR];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) ox[c] = (uint32_t)((ic + nx * min(2 * J - 2 + c, ny - 1)) * sizeof(T));
-    bool rok[3];
-    T kay[3], kby[3], kcy[3], wy[3];
+    for (int c = 0; c < NR + 2; ++c) ox[c] = (uint32_t)((ic + nx * min(2 * J0 - 2 + c, ny - 1)) * sizeof(T));
+    bool rok[NR];
+    T kay[NR], kby[NR], kcy[NR];
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        const int j = 2 * J - 1 + b;
+    for (int b = 0; b < NR; ++b) {
+        const int j = 2 * J0 - 1 + b;
         rok[b] = j <= ny - 2;
         const int jc = min(j, ny - 1);
         ow[b] = (uint32_t)((jc * g.W + (ic >> 5)) * sizeof(uint32_t));
         kay[b] = wave_uniform(cf.c[1][8 * jc + 5]);
         kby[b] = wave_uniform(cf.c[1][8 * jc + 6]);
         kcy[b] = wave_uniform(cf.c[1][8 * jc + 7]);
-        wy[b] = wave_uniform(ay.rw[3 * J + b]);
+    }
+    // the coarse rows J0 .. J0 + CR - 1 (those past the last interior one are not stored)
+    // and their y weights on fine rows 2J - 1 .. 2J + 1
+    bool jok[CR];
+    T wy[CR][3];
+#pragma unroll
+    for (int c = 0; c < CR; ++c) {
+        jok[c] = J0 + c <= ncy - 2;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) wy[c][q] = jok[c] ? wave_uniform(ay.rw[3 * (J0 + c) + q]) : T(0);
     }
 
     const int K0 = 1 + bz * tl.TZ, K1 = min(K0 + tl.TZ, ncz - 1);
     const int p0 = 2 * K0 - 1, p1 = 2 * K1 - 1;
     // x of the residual rows at the plane below (m) and at the current one (c); the fifth
     // node's in m5, c5
-    V xm[3], xc[3];
-    T m5[3], c5[3];
+    V xm[NR], xc[NR];
+    T m5[NR], c5[NR];
     {
         const __amdgpu_buffer_rsrc_t xb = plane_rsrc(x + (size_t)(p0 - 1) * plane), x0 = plane_rsrc(x + (size_t)p0 * plane);
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
+        for (int b = 0; b < NR; ++b) {
             xm[b] = bload4<T>(xb, ox[b + 1]);
             xc[b] = bload4<T>(x0, ox[b + 1]);
             m5[b] = need5 ? bload1<T>(xb, ox[b + 1] + 4 * sizeof(T)) : T(0);
@@ -268,22 +278,46 @@ __global__ void __launch_bounds__(256) k_mg_resid_restrict(Geom g, Tiling tl, Co
     }
     // the coarse plane being summed: the diagonals of its nodes (0 where not an unknown),
     // loaded when the plane opens and used when it is stored two fine planes later
-    T acc0 = T(0), acc1 = T(0), dg0 = T(0), dg1 = T(0);
+    T acc0[CR], acc1[CR], dg0[CR], dg1[CR];
+#pragma unroll
+    for (int c = 0; c < CR; ++c) acc0[c] = acc1[c] = dg0[c] = dg1[c] = T(0);
+    auto coarse_at = [&](int c, int K) -> size_t {
+        return (size_t)(own0 ? I0 : 1) + (size_t)ncx * (min(J0 + c, ncy - 2) + (size_t)ncy * K);
+    };
     auto open = [&](int K) {
-        acc0 = T(0);
-        acc1 = T(0);
-        const size_t ec = (size_t)(own0 ? I0 : 1) + (size_t)ncx * (J + (size_t)ncy * K);
-        dg0 = own0 ? F.diag[ec] : T(0);
-        dg1 = own1 ? F.diag[ec + 1] : T(0);
+#pragma unroll
+        for (int c = 0; c < CR; ++c) {
+            acc0[c] = T(0);
+            acc1[c] = T(0);
+            const size_t ec = coarse_at(c, K);
+            dg0[c] = (own0 && jok[c]) ? F.diag[ec] : T(0);
+            dg1[c] = (own1 && jok[c]) ? F.diag[ec + 1] : T(0);
+        }
     };
     auto emit = [&](int K) {
-        const size_t ec = (size_t)(own0 ? I0 : 1) + (size_t)ncx * (J + (size_t)ncy * K);
-        if (own0) rc[ec] = dg0 != T(0) ? acc0 : T(0);
-        if (own1) rc[ec + 1] = dg1 != T(0) ? acc1 : T(0);
-        if (F.x1) {
-            if (dg0 != T(0)) F.x1[ec] = F.c2 * acc0 / dg0;
-            if (dg1 != T(0)) F.x1[ec + 1] = F.c2 * acc1 / dg1;
+#pragma unroll
+        for (int c = 0; c < CR; ++c) {
+            if (!jok[c]) continue;
+            const size_t ec = coarse_at(c, K);
+            if (own0) rc[ec] = dg0[c] != T(0) ? acc0[c] : T(0);
+            if (own1) rc[ec + 1] = dg1[c] != T(0) ? acc1[c] : T(0);
+            if (F.x1) {
+                if (dg0[c] != T(0)) F.x1[ec] = F.c2 * acc0[c] / dg0[c];
+                if (dg1[c] != T(0)) F.x1[ec + 1] = F.c2 * acc1[c] / dg1[c];
+            }
         }
+    };
+    // coarse plane K += its z weight q times the fine plane's rows, restricted in y
+    auto add_plane = [&](int K, int q, const T *xr0, const T *xr1) {
+        const T wz = wave_uniform(az.rw[3 * K + q]);
+#pragma unroll
+        for (int c = 0; c < CR; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const T wyz = wz * wy[c][b];
+                acc0[c] += wyz * xr0[2 * c + b];
+                acc1[c] += wyz * xr1[2 * c + b];
+            }
     };
     // skip bits of nodes ic .. ic + 4 on the residual rows of plane q (words read in pairs;
     // the array carries two words of padding), loaded one plane ahead
@@ -292,19 +326,19 @@ __global__ void __launch_bounds__(256) k_mg_resid_restrict(Geom g, Tiling tl, Co
         const uint64_t pair = (uint64_t)bload_u32(sq, ow[b]) | ((uint64_t)bload_u32(sq, ow[b] + 4) << 32);
         return (uint32_t)(pair >> (ic & 31)) & smask;
     };
-    uint32_t skn[3];
+    uint32_t skn[NR];
 #pragma unroll
-    for (int b = 0; b < 3; ++b) skn[b] = skip_bits(p0, b);
+    for (int b = 0; b < NR; ++b) skn[b] = skip_bits(p0, b);
     for (int p = p0; p <= p1; ++p) {
         const bool pv = p <= nz - 2;                          // fine plane p is interior
         const size_t kp = (size_t)p * plane;
         const __amdgpu_buffer_rsrc_t xk = plane_rsrc(x + kp), xn = plane_rsrc(x + (size_t)min(p + 1, nz - 1) * plane);
         const __amdgpu_buffer_rsrc_t rk = plane_rsrc(rho + kp), rik = plane_rsrc(ri + kp);
-        V xp[3], rh[3], ri4[3];
-        uint32_t sk[3];
-        T lf[3], p5[3], q5[3], h5[3], ri5[3];
+        V xp[NR], rh[NR], ri4[NR];
+        uint32_t sk[NR];
+        T lf[NR], p5[NR], q5[NR], h5[NR], ri5[NR];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
+        for (int b = 0; b < NR; ++b) {
             const uint32_t o = ox[b + 1];
             sk[b] = skn[b];
             skn[b] = skip_bits(min(p + 1, nz - 1), b);
@@ -319,19 +353,20 @@ __global__ void __launch_bounds__(256) k_mg_resid_restrict(Geom g, Tiling tl, Co
             q5[b] = need5 ? bload1<T>(xk, o + 5 * sizeof(T)) : T(0);
             h5[b] = need5 ? bload1<T>(rk, o + 4 * sizeof(T)) : T(0);
         }
-        const V y0 = bload4<T>(xk, ox[0]), y4 = bload4<T>(xk, ox[4]);
-        const T y05 = need5 ? bload1<T>(xk, ox[0] + 4 * sizeof(T)) : T(0);
-        const T y45 = need5 ? bload1<T>(xk, ox[4] + 4 * sizeof(T)) : T(0);
+        // the outer y neighbours: x rows 0 and NR + 1
+        const V ylo = bload4<T>(xk, ox[0]), yhi = bload4<T>(xk, ox[NR + 1]);
+        const T ylo5 = need5 ? bload1<T>(xk, ox[0] + 4 * sizeof(T)) : T(0);
+        const T yhi5 = need5 ? bload1<T>(xk, ox[NR + 1] + 4 * sizeof(T)) : T(0);
         const T *cz = cf.c[2] + 8 * p;
         const T za = wave_uniform(cz[5]), zb = wave_uniform(cz[6]), zc = wave_uniform(cz[7]);
-        T xr0[3], xr1[3];
+        T xr0[NR], xr1[NR];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const V &s4 = b == 0 ? y0 : xc[b - 1];
-            const V &n4 = b == 2 ? y4 : xc[b + 1];
+        for (int b = 0; b < NR; ++b) {
+            const V &s4 = b == 0 ? ylo : xc[b - 1];
+            const V &n4 = b == NR - 1 ? yhi : xc[b + 1];
             const T cv[5] = {xc[b].x, xc[b].y, xc[b].z, xc[b].w, c5[b]};
-            const T sv[5] = {s4.x, s4.y, s4.z, s4.w, b == 0 ? y05 : c5[b - 1]};
-            const T nw[5] = {n4.x, n4.y, n4.z, n4.w, b == 2 ? y45 : c5[b + 1]};
+            const T sv[5] = {s4.x, s4.y, s4.z, s4.w, b == 0 ? ylo5 : c5[b - 1]};
+            const T nw[5] = {n4.x, n4.y, n4.z, n4.w, b == NR - 1 ? yhi5 : c5[b + 1]};
             const T mv[5] = {xm[b].x, xm[b].y, xm[b].z, xm[b].w, m5[b]};
             const T uv[5] = {xp[b].x, xp[b].y, xp[b].z, xp[b].w, p5[b]};
             const T rv[5] = {rh[b].x, rh[b].y, rh[b].z, rh[b].w, h5[b]};
@@ -362,36 +397,18 @@ __global__ void __launch_bounds__(256) k_mg_resid_restrict(Geom g, Tiling tl, Co
             // fine plane 2K + 1: the last of coarse plane K, the first of K + 1
             const int K = (p - 1) >> 1;
             if (K >= K0) {
-                const T wz = wave_uniform(az.rw[3 * K + 2]);
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const T wyz = wz * wy[b];
-                    acc0 += wyz * xr0[b];
-                    acc1 += wyz * xr1[b];
-                }
+                add_plane(K, 2, xr0, xr1);
                 emit(K);
             }
             if (K + 1 < K1) {
                 open(K + 1);
-                const T wz = wave_uniform(az.rw[3 * (K + 1)]);
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const T wyz = wz * wy[b];
-                    acc0 += wyz * xr0[b];
-                    acc1 += wyz * xr1[b];
-                }
+                add_plane(K + 1, 0, xr0, xr1);
             }
         } else {
-            const T wz = wave_uniform(az.rw[3 * (p >> 1) + 1]);
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const T wyz = wz * wy[b];
-                acc0 += wyz * xr0[b];
-                acc1 += wyz * xr1[b];
-            }
+            add_plane(p >> 1, 1, xr0, xr1);
         }
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
+        for (int b = 0; b < NR; ++b) {
             xm[b] = xc[b];
             xc[b] = xp[b];
             m5[b] = c5[b];
@@ -418,8 +435,8 @@ __global__ void __launch_bounds__(256) k_mg_resid_restrict(Geom g, Tiling tl, Co
 template <typename T>
 __global__ void __launch_bounds__(256) k_mg_prolong_add(int nfx, int nfy, int nfz, int ncx, int ncy, int ncz,
                                                         MgAxis<T> ax, MgAxis<T> ay, MgAxis<T> az,
-                                                        const int8_t *__restrict__ type_f, const T *__restrict__ e,
-                                                        T *__restrict__ x)
+                                                        const uint32_t *__restrict__ skip, int W,
+                                                        const T *__restrict__ e, T *__restrict__ x)
 {
     using V = typename MgVec4<T>::type;
     const int j = 1 + (int)(blockIdx.y * 4 + threadIdx.y), kp = 2 * (int)blockIdx.z;
@@ -432,15 +449,18 @@ __global__ void __launch_bounds__(256) k_mg_prolong_add(int nfx, int nfy, int nf
     bool ok[2];
     size_t ef[2];
     V xv[2];
-    int8_t ty[2][4];
+    uint32_t sk[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int k = kp + h;
         ok[h] = k >= 1 && k <= nfz - 2;
-        ef[h] = (size_t)i0 + (size_t)nfx * j + (size_t)(ok[h] ? k : 1) * fplane;
+        const int kc = ok[h] ? k : 1;
+        ef[h] = (size_t)i0 + (size_t)nfx * j + (size_t)kc * fplane;
         xv[h] = *reinterpret_cast<const V *>(x + ef[h]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) ty[h][u] = type_f[ef[h] + min(u, nv - 1)];
+        // skip bits (solid and irregular nodes) of nodes i0 .. i0 + 3: words read in pairs,
+        // the array carries two words of padding
+        const uint32_t *w = skip + ((size_t)kc * nfy + j) * W + (i0 >> 5);
+        sk[h] = (uint32_t)((((uint64_t)w[0]) | ((uint64_t)w[1] << 32)) >> (i0 & 31)) & 0xFu;
     }
     const V q00 = *reinterpret_cast<const V *>(e00);
     const V q10 = *reinterpret_cast<const V *>(e00 + ncx);
@@ -465,7 +485,7 @@ __global__ void __launch_bounds__(256) k_mg_prolong_add(int nfx, int nfy, int nf
             const T l = d == 0 ? ryz[0] : (d == 1 ? ryz[1] : ryz[2]);
             const T r = d == 0 ? ryz[1] : (d == 1 ? ryz[2] : ryz[3]);
             add[u] = (T(1) - wx[u]) * l + wx[u] * r;
-            m[u] = u < nv && ty[h][u] == 1;   // regular unknowns only
+            m[u] = u < nv && !((sk[h] >> u) & 1u);   // regular unknowns only (interior, no skip bit)
             all = all && m[u];
         }
         V xo = xv[h];
@@ -731,6 +751,9 @@ void launch_mg_restrict(hipStream_t s, const MgTransfer<T> &t, const T *r, T *rc
                                                   rc, first);
 }
 
+// coarse rows per wavefront of the fused residual and restriction
+constexpr int RR_ROWS = 1;
+
 template <typename T>
 void launch_mg_resid_restrict(hipStream_t s, const Geom &g, const Coef<T> &cf, const uint32_t *skip, const T *x,
                               const T *rho, const T *ri, const MgTransfer<T> &t, T *rc, const MgFirst<T> &first,
@@ -739,8 +762,8 @@ void launch_mg_resid_restrict(hipStream_t s, const Geom &g, const Coef<T> &cf, c
     // the fifth-node path (more registers) only where a further segment exists
     const int ncx = t.nc[0], ncy = t.nc[1], ncz = t.nc[2];
     const bool fifth = (ncx - 2 + 127) / 128 > 1;
-    const void *fn = fifth ? reinterpret_cast<const void *>(&k_mg_resid_restrict<T, true>)
-                           : reinterpret_cast<const void *>(&k_mg_resid_restrict<T, false>);
+    const void *fn = fifth ? reinterpret_cast<const void *>(&k_mg_resid_restrict<T, true, RR_ROWS>)
+                           : reinterpret_cast<const void *>(&k_mg_resid_restrict<T, false, RR_ROWS>);
     // The march is bound by the latency of its plane steps: all blocks run in one round,
     // as many as fit on the device at once (z-chunks of at least two coarse planes).
     static int per_cu[2] = {0, 0};
@@ -755,9 +778,9 @@ void launch_mg_resid_restrict(hipStream_t s, const Geom &g, const Coef<T> &cf, c
         ncu = 256;
     Tiling tl{};
     tl.tw = 128;
-    tl.ty = 4;
+    tl.ty = 4 * RR_ROWS;
     tl.tiles_x = (ncx - 2 + 127) / 128;
-    tl.tiles_y = (ncy - 2 + 3) / 4;
+    tl.tiles_y = (ncy - 2 + tl.ty - 1) / tl.ty;
     const int nzi = ncz - 2, per_plane = tl.tiles_x * tl.tiles_y;
     const int want = std::max(1, per_cu[fifth] * ncu / per_plane);
     tl.TZ = std::max(std::min(2, nzi), (nzi + want - 1) / want);
@@ -765,20 +788,20 @@ void launch_mg_resid_restrict(hipStream_t s, const Geom &g, const Coef<T> &cf, c
     tl.ntiles = per_plane * tl.zchunks;
     tl.nblk = (tl.ntiles + NXCD - 1) / NXCD * NXCD;
     if (fifth)
-        k_mg_resid_restrict<T, true><<<tl.nblk, dim3(64, 4), 0, s>>>(g, tl, cf, skip, x, rho, ri, ncx, ncy, ncz,
-                                                                     t.ax[0], t.ax[1], t.ax[2], rc, first, st);
+        k_mg_resid_restrict<T, true, RR_ROWS><<<tl.nblk, dim3(64, 4), 0, s>>>(
+            g, tl, cf, skip, x, rho, ri, ncx, ncy, ncz, t.ax[0], t.ax[1], t.ax[2], rc, first, st);
     else
-        k_mg_resid_restrict<T, false><<<tl.nblk, dim3(64, 4), 0, s>>>(g, tl, cf, skip, x, rho, ri, ncx, ncy, ncz,
-                                                                      t.ax[0], t.ax[1], t.ax[2], rc, first, st);
+        k_mg_resid_restrict<T, false, RR_ROWS><<<tl.nblk, dim3(64, 4), 0, s>>>(
+            g, tl, cf, skip, x, rho, ri, ncx, ncy, ncz, t.ax[0], t.ax[1], t.ax[2], rc, first, st);
 }
 
 template <typename T>
-void launch_mg_prolong_add(hipStream_t s, const MgTransfer<T> &t, const int8_t *type_f, const T *e, T *x)
+void launch_mg_prolong_add(hipStream_t s, const MgTransfer<T> &t, const uint32_t *skip_f, int W, const T *e, T *x)
 {
     // blockIdx.z = p covers fine planes 2p and 2p + 1 (interior planes 1 .. nf[2] - 2)
     dim3 grid((unsigned)((t.nf[0] - 2 + 255) / 256), (unsigned)((t.nf[1] - 2 + 3) / 4), (unsigned)((t.nf[2] - 2) / 2 + 1));
     k_mg_prolong_add<T><<<grid, dim3(64, 4), 0, s>>>(t.nf[0], t.nf[1], t.nf[2], t.nc[0], t.nc[1], t.nc[2], t.ax[0],
-                                                     t.ax[1], t.ax[2], type_f, e, x);
+                                                     t.ax[1], t.ax[2], skip_f, W, e, x);
 }
 
 template <typename T>
@@ -835,9 +858,9 @@ template void launch_mg_resid_restrict<double>(hipStream_t, const Geom &, const 
 template void launch_mg_resid_restrict<float>(hipStream_t, const Geom &, const Coef<float> &, const uint32_t *, const float *, const float *,
                                                const float *, const MgTransfer<float> &, float *,
                                                const MgFirst<float> &, const DevState *);
-template void launch_mg_prolong_add<double>(hipStream_t, const MgTransfer<double> &, const int8_t *, const double *,
-                                            double *);
-template void launch_mg_prolong_add<float>(hipStream_t, const MgTransfer<float> &, const int8_t *, const float *,
+template void launch_mg_prolong_add<double>(hipStream_t, const MgTransfer<double> &, const uint32_t *, int,
+                                            const double *, double *);
+template void launch_mg_prolong_add<float>(hipStream_t, const MgTransfer<float> &, const uint32_t *, int, const float *,
                                            float *);
 
 }  // namespace cps

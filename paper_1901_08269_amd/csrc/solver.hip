@@ -603,7 +603,7 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
                                mg_steps<T>(s, 1, nu), st);
         launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), Rr, mg_vecs<T>(s->mg[l + 1])[0], mg_first<T>(s, l + 1));
         T *e = mg_level<T>(s, l + 1, st);
-        launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.type, e, B);
+        launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.skip, Lv.g.W, e, B);
         launch_mg_smooth_tb<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, B, A, nullptr,
                                mg_steps<T>(s, 0, nu), st);
         return A;
@@ -613,7 +613,7 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
     launch_resid<T>(L, cf, ir, x, R, r, st, next_rev(s, l));
     launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), r, mg_vecs<T>(s->mg[l + 1])[0], mg_first<T>(s, l + 1));
     T *e = mg_level<T>(s, l + 1, st);
-    launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.type, e, x);
+    launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.skip, Lv.g.W, e, x);
     return mg_smooth<T>(s, l, L, cf, ir, R, x, Z, x, r, nullptr, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
 }
 
@@ -660,7 +660,7 @@ void mg_precond(cps_solver *s, Vecs<T> &V, int kind, const T *r, T *ps, const T 
     launch_mg_resid_restrict<T>(s->stream, s->g, cf, L.skip, x, ps, res, mg_transfer<T>(s->mg[0]),
                                 mg_vecs<T>(s->mg[1])[0], mg_first<T>(s, 1), st);
     T *e = mg_level<T>(s, 1, st);
-    launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(s->mg[0]), s->type, e, x);
+    launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(s->mg[0]), s->skip, s->g.W, e, x);
     mg_smooth<T>(s, 0, L, cf, ir, ps, x, nullptr, x, res, dst, 0, nu, s->mg_c1.data(), s->mg_c2.data(), st, samp);
 }
 
