@@ -708,7 +708,6 @@ __global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, 
     }
 }
 
-// map[node] = irregular row of the node (the rows list nodes in increasing order)
 // diag[e] = the diagonal of K at node e if it is an unknown (the 1D tables of a regular node,
 // summed as cx + (cy + cz), or the stored row of an irregular one), 0 otherwise
 template <typename T>
@@ -726,6 +725,7 @@ __global__ void k_mg_diag(int nx, int ny, int nz, Coef<T> cf, const int8_t *__re
     }
 }
 
+// map[node] = irregular row of the node (the rows list nodes in increasing order)
 __global__ void k_mg_irr_map(int nirr, const int *__restrict__ nodes, int *__restrict__ map)
 {
     const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
