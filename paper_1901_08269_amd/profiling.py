@@ -175,17 +175,23 @@ def fine_grid_launches(db):
     return sorted(rows, key=lambda r: -r[1] * r[2])
 
 
-def kernels_report(db, points, title, cmd):
+def kernels_report(db, points, title, cmd, exclude=()):
+    """exclude: short kernel names that have no launch over the problem's grid in the run (a
+    kernel that only runs on coarser grids, or only over the irregular rows there), whose
+    longest launches would otherwise be taken for it."""
     out = [f"# {title}", "", "Command (run from the repository root on an MI355X):", "", "```", cmd, "```", "",
            f"Solve kernels from `rocprofv3 --kernel-trace --stats`, launches on the problem's grid only "
            f"({points} interior points per launch; a multigrid kernel's launches on coarser grids are left "
            "out); algorithmic bytes count each operand once per point (tables, halos, bits and the "
            f"irregular rows as overhead); GB/s = bytes per launch / average duration; peak "
-           f"{HBM_PEAK_GBS:.0f} GB/s.", "",
-           "| kernel | calls | avg us | B / point | GB/s | of peak |", "|---|---:|---:|---:|---:|---:|"]
+           f"{HBM_PEAK_GBS:.0f} GB/s."]
+    if exclude:
+        out.append("Left out, as they make no launch over the problem's grid: "
+                   + ", ".join(f"`{n}`" for n in exclude) + ".")
+    out += ["", "| kernel | calls | avg us | B / point | GB/s | of peak |", "|---|---:|---:|---:|---:|---:|"]
     for n, c, a in fine_grid_launches(db):
         b = algorithmic_bytes(n)
-        if b is None:
+        if b is None or short_name(n) in exclude:
             continue
         gbs = b * points / (a * 1e-6) / 1e9
         out.append(f"| `{short_name(n)}` | {c} | {a:.2f} | {b:g} | {gbs:.0f} | {gbs / HBM_PEAK_GBS:.2f} |")
@@ -311,6 +317,8 @@ def main(argv=None):
     k.add_argument("--points", type=int, required=True)
     k.add_argument("--title", required=True)
     k.add_argument("--cmd", required=True)
+    k.add_argument("--exclude", action="append", default=[],
+                   help="short kernel name without a launch over the problem's grid (repeatable)")
     mf = sub.add_parser("mfma")
     mf.add_argument("db")
     mf.add_argument("--title", required=True)
@@ -326,7 +334,7 @@ def main(argv=None):
     if a.mode == "stats":
         print(stats_report(a.db, a.title, a.cmd, a.top), end="")
     elif a.mode == "kernels":
-        print(kernels_report(a.db, a.points, a.title, a.cmd), end="")
+        print(kernels_report(a.db, a.points, a.title, a.cmd, tuple(a.exclude)), end="")
     elif a.mode == "mfma":
         print(mfma_report(a.db, a.title, a.cmd), end="")
     else:

@@ -118,6 +118,10 @@ def test_kernels_report(tmp_path):
     # restriction: 5.5 B per fine point in 20 us = 275 GB/s
     assert "| `cps::k_mg_restrict<float>` | 1 | 20.00 | 5.5 | 275 | 0.03 |" in rep
     assert "k_fill" not in rep
+    # a kernel without launches over the problem's grid is left out by name
+    rep = profiling.kernels_report(str(db), 1000000, "T", "cmd", exclude=("cps::k_mg_restrict<float>",))
+    assert "| `cps::k_mg_restrict<float>`" not in rep and "Left out" in rep
+    assert "| `cps::k_cheb4<float, false>` | 10 | 40.00 | 16 | 400 | 0.05 |" in rep
 
 
 def test_kernels_report_separates_levels_sharing_a_launch_grid(tmp_path):
