@@ -53,6 +53,8 @@ struct Geom {
     Tiling tr;                 // 256 x 4 tiles: one x-row segment of 256 nodes per wavefront,
                                // four nodes per lane (vectorised Chebyshev sweeps)
     Tiling tr2;                // 256 x (4 RPW2) tiles: RPW2 rows per wavefront (two-vector sweeps)
+    Tiling tr2s;               // the same tiles in more z-chunks, for the FP32 two-vector sweeps
+                               // (fewer registers: more of their wavefronts fit at once)
     int lg;                    // coarse multigrid levels whose rows are at most 128 nodes
                                // long: 2^lg lanes per row, 64 / 2^lg rows per wavefront
                                // (tr then has (4 * 2^lg) x (4 * 64 / 2^lg) tiles); 6 otherwise
@@ -96,6 +98,13 @@ struct DevState {
     int done;                  // 0 running, 1 converged, 2 breakdown, 3 NaN
     int iters;                 // completed iterations
 };
+
+// the tiling of the two-vector sweeps in precision T
+template <typename T>
+__host__ __device__ __forceinline__ const Tiling &tr2_of(const Geom &g)
+{
+    return sizeof(T) == 4 ? g.tr2s : g.tr2;
+}
 
 __device__ __forceinline__ bool tile_of_block(const Tiling &t, int b, int &bx, int &by, int &bz)
 {

@@ -346,6 +346,9 @@ Tiling make_tiling(int nx, int ny, int nz, int tw, int ty, int target_blocks, in
 // 47.5 us) and at 512^3.  Fewer chunks leave wavefronts idle; more chunks re-read more halo
 // planes and put the blocks in more than one round.
 constexpr int ROW_ZCHUNKS = 16;
+// The FP32 two-vector sweeps (113 VGPRs, four wavefronts per SIMD, against 180 and two in
+// FP64) fill the GPU with more z-chunks: 24 instead of 16 (768 instead of 512 blocks at 256^3).
+constexpr int ROW_ZCHUNKS_F32 = 24;
 // z-chunks of the vectorised B apply and vector updates (each at least 4 planes; 8 and 32
 // measured the same at 256^3)
 constexpr int APPLY_ZCHUNKS = 16;
@@ -376,6 +379,7 @@ Geom make_geom(int nx, int ny, int nz, bool coarse = false)
                       : make_tiling(nx, ny, nz, 4 * TX, TY * RPW, per_plane * ROW_ZCHUNKS, 4);
         const int per_plane2 = ((nx - 2 + 4 * TX - 1) / (4 * TX)) * ((ny - 2 + TY * RPW2 - 1) / (TY * RPW2));
         g.tr2 = make_tiling(nx, ny, nz, 4 * TX, TY * RPW2, per_plane2 * ROW_ZCHUNKS, 4);
+        g.tr2s = make_tiling(nx, ny, nz, 4 * TX, TY * RPW2, per_plane2 * ROW_ZCHUNKS_F32, 4);
     }
     size_t nn = (size_t)nx * ny * nz;
     g.nflat = (int)std::min<size_t>((nn / 4 + 255) / 256 + 1, FLAT_BLOCKS);
@@ -1438,7 +1442,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->irr_wstart = dalloc<int>(s, (size_t)s->g.W * ny * nz);
         launch_irr_words(s->stream, s->g, s->type, s->irr_node, s->nirr, s->irr_bits, s->irr_wstart);
         // reduction scratch: enough for the largest launch
-        size_t maxblk = (size_t)std::max({s->g.ta.nblk, s->g.tr.nblk, s->g.tr2.nblk, s->g.nflat}) +
+        size_t maxblk = (size_t)std::max({s->g.ta.nblk, s->g.tr.nblk, s->g.tr2.nblk, s->g.tr2s.nblk, s->g.nflat}) +
                         (size_t)(s->nirr + (NT / IRR_LANES) - 1) / (NT / IRR_LANES) + 8;
         s->partials = dalloc<double>(s, 2 * maxblk);
         s->st = dalloc<DevState>(s, 1);

@@ -240,7 +240,7 @@ __device__ __forceinline__ void cheb4_rows(const Geom &g, const Coef<T> &cf, con
         xn[e] = RES ? rho[e] - kx : z0 + c1 * (z0 - prev) + c2 * (rho[e] - kx) / k7[0];
         return;
     }
-    const Tiling &tl = (R == RPW) ? g.tr : g.tr2;
+    const Tiling &tl = (R == RPW) ? g.tr : tr2_of<T>(g);
     int bs, by, bz;
     if (!tile_of_block(tl, b, bs, by, bz)) return;
     const int jw = 1 + (by * TY + wv) * (MR ? TX / lw : R);    // the wavefront's first row
@@ -935,7 +935,7 @@ void launch_cheb(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T *
     const bool mr = L.g.lg < 6;
     if (xm1 == nullptr) {
         // the sweep without an x_{k-1} moves less per plane step: RPW2 rows per wavefront
-        dim3 grid2(L.g.tr2.nblk + irr_blocks(ir.n, NT));
+        dim3 grid2(tr2_of<T>(L.g).nblk + irr_blocks(ir.n, NT));
         if (mr) k_cheb4m<T, true><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, xc, xm1, rho, xn, (T)c1, (T)c2, st, rev);
         else if (ev0)
             hipExtLaunchKernelGGL((k_cheb4<T, true, RPW2>), grid2, blk, 0, L.stream, ev0, ev1, 0, L.g, cf, ir, L.skip, xc,
@@ -956,7 +956,7 @@ void launch_resid(const Launch &L, const Coef<T> &cf, const Irr<T> &ir, const T 
                   const DevState *st, int rev)
 {
     dim3 grid(L.g.tr.nblk + irr_blocks(ir.n, NT)), blk = tile_block();
-    dim3 grid2(L.g.tr2.nblk + irr_blocks(ir.n, NT));
+    dim3 grid2(tr2_of<T>(L.g).nblk + irr_blocks(ir.n, NT));
     if (L.g.lg < 6) k_resid4m<T><<<grid, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st, rev);
     else k_resid4<T, RPW2><<<grid2, blk, 0, L.stream>>>(L.g, cf, ir, L.skip, x, rho, r, st, rev);
 }
