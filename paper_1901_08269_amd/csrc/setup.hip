@@ -809,6 +809,7 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
     __shared__ signed char pt_off[BR_ROWS * 27][PT_CAP];
     __shared__ bool pt_ibi[BR_ROWS * 27][PT_CAP];
     __shared__ double qbar[BR_ROWS];
+    __shared__ double slot_sum[BR_ROWS][NSLOT];
     __shared__ int wfb[BR_ROWS][27];
     __shared__ double wminhb[BR_ROWS][27];
     const int grp = threadIdx.x / BR_LANES, lane = threadIdx.x % BR_LANES;
@@ -890,13 +891,15 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
     __syncthreads();
     if (!live) return;
     // Sum the windows' lists in window order: lane l owns the slots l, l + 32, ... and adds
-    // the entries for them in list order (the same order for every run), lane 0 the
-    // right-hand side, which starts from Q-bar.
+    // the entries for them in list order (the same order for every run) into its slots of
+    // the row's LDS sums (a lane reads every entry's slot and only its own entries' values),
+    // lane 0 the right-hand side, which starts from Q-bar.
     constexpr int SPL = (NSLOT + BR_LANES - 1) / BR_LANES;   // slots per lane
-    double mine[SPL];
+    double *sums = slot_sum[grp];
     uint32_t mused = 0u;
 #pragma unroll
-    for (int q = 0; q < SPL; ++q) mine[q] = 0.0;
+    for (int q = 0; q < SPL; ++q)
+        if (lane + BR_LANES * q < NSLOT) sums[lane + BR_LANES * q] = 0.0;
     double rhs = qbar[grp];
     for (int w = 0; w < 27; ++w) {
         const WinList &R = wl[grp][w];
@@ -905,15 +908,15 @@ __global__ void __launch_bounds__(BR_ROWS * BR_LANES) k_build_rows(
             const int sl = R.slot[e];
             if (sl < 0) {
                 if (lane == 0) rhs += R.v[e];
-            } else if (sl % BR_LANES == lane) {
-                const int qs = sl / BR_LANES;
-#pragma unroll
-                for (int q = 0; q < SPL; ++q)       // static indices keep mine[] in registers
-                    if (q == qs) mine[q] += R.v[e];
-                mused |= 1u << qs;
+            } else if ((sl & (BR_LANES - 1)) == lane) {
+                sums[sl] += R.v[e];
+                mused |= 1u << (sl / BR_LANES);
             }
         }
     }
+    double mine[SPL];
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) mine[q] = lane + BR_LANES * q < NSLOT ? sums[lane + BR_LANES * q] : 0.0;
     // emit in slot order: slot sl = lane + 32 q; its output position is the number of used
     // slots before it (prefix over q, then over lanes)
     int cnt_total = 0, base_q = 0;
