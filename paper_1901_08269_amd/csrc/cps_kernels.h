@@ -153,9 +153,10 @@ struct SetupOut {
 // the 1D tables of all three axes (8 values per index; FP64 and FP32, 3 * 8 * nmax each)
 void launch_coef(hipStream_t s, int nx, int ny, int nz, int nmax, const double *xyz, double *coef, float *coef32);
 // classify nodes; flags: bit0 invalid input (NaN/Inf), bit1 a wall node inside a body has a
-// fluid neighbour
+// fluid neighbour; with phi_out, g_out and f_out non-null the fields are also copied there
 void launch_classify(hipStream_t s, int nx, int ny, int nz, const double *phi, const double *g, const double *f,
-                     int8_t *type, int *flags);
+                     int8_t *type, int *flags, double *phi_out = nullptr, double *g_out = nullptr,
+                     double *f_out = nullptr);
 void launch_mark_irregular(hipStream_t s, int nx, int ny, int nz, int8_t *type);
 // ordered compaction of the irregular nodes; returns the count through *count (device int)
 void launch_compact(hipStream_t s, size_t n, const int8_t *type, int8_t want, int *blockcnt, int *list, int *count,

@@ -73,18 +73,25 @@ void launch_coef(hipStream_t s, int nx, int ny, int nz, int nmax, const double *
 // ---------------------------------------------------------------------------------------
 // classification
 // ---------------------------------------------------------------------------------------
-// one thread per node: x from the thread index, y and z from the grid (no 64-bit divisions)
+// one thread per node: x from the thread index, y and z from the grid (no 64-bit divisions);
+// with phi_out (then also g_out, f_out) the three fields are copied on the way
 __global__ void __launch_bounds__(256) k_classify(int nx, int ny, int nz, const double *__restrict__ phi,
                                                   const double *__restrict__ g, const double *__restrict__ f,
-                                                  int8_t *__restrict__ type, int *flags)
+                                                  int8_t *__restrict__ type, int *flags, double *__restrict__ phi_out,
+                                                  double *__restrict__ g_out, double *__restrict__ f_out)
 {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     const int j = (int)(blockIdx.y * blockDim.y + threadIdx.y);
     const int k = (int)blockIdx.z;
     if (i >= nx || j >= ny) return;
     const size_t e = (size_t)i + (size_t)nx * j + (size_t)nx * ny * k;
-    const double p = phi[e];
-    if (!isfinite(p) || !isfinite(g[e]) || !isfinite(f[e])) atomicOr(flags, 1);
+    const double p = phi[e], gv = g[e], fv = f[e];
+    if (!isfinite(p) || !isfinite(gv) || !isfinite(fv)) atomicOr(flags, 1);
+    if (phi_out) {
+        phi_out[e] = p;
+        g_out[e] = gv;
+        f_out[e] = fv;
+    }
     const bool wall = i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1;
     if (wall) {
         // A wall node may lie in a body (an interior problem) as long as no fluid node is
@@ -107,10 +114,10 @@ __global__ void __launch_bounds__(256) k_classify(int nx, int ny, int nz, const 
 }
 
 void launch_classify(hipStream_t s, int nx, int ny, int nz, const double *phi, const double *g, const double *f,
-                     int8_t *type, int *flags)
+                     int8_t *type, int *flags, double *phi_out, double *g_out, double *f_out)
 {
     dim3 blk(64, 4), grid((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4), (unsigned)nz);
-    k_classify<<<grid, blk, 0, s>>>(nx, ny, nz, phi, g, f, type, flags);
+    k_classify<<<grid, blk, 0, s>>>(nx, ny, nz, phi, g, f, type, flags, phi_out, g_out, f_out);
 }
 
 // a fluid node with a solid node among its 26 neighbours is irregular (one thread per

@@ -1390,9 +1390,13 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->phi = dalloc<double>(s, s->nn);
         s->gf = dalloc<double>(s, s->nn);
         s->f = dalloc<double>(s, s->nn);
-        to_device(s, s->phi, phi, s->nn * sizeof(double));
-        to_device(s, s->gf, g, s->nn * sizeof(double));
-        to_device(s, s->f, f, s->nn * sizeof(double));
+        // host fields are uploaded first; device fields are copied by the classification
+        // pass itself, which reads them anyway
+        if (!o.device_ptrs) {
+            to_device(s, s->phi, phi, s->nn * sizeof(double));
+            to_device(s, s->gf, g, s->nn * sizeof(double));
+            to_device(s, s->f, f, s->nn * sizeof(double));
+        }
         // 1D tables
         s->coef64 = dalloc<double>(s, (size_t)3 * 8 * s->nmax);
         s->coef32 = dalloc<float>(s, (size_t)3 * 8 * s->nmax);
@@ -1401,7 +1405,10 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->type = dalloc<int8_t>(s, s->nn);
         s->dflag = dalloc<int>(s, 1);
         ck(hipMemsetAsync(s->dflag, 0, sizeof(int), s->stream));
-        launch_classify(s->stream, nx, ny, nz, s->phi, s->gf, s->f, s->type, s->dflag);
+        if (o.device_ptrs)
+            launch_classify(s->stream, nx, ny, nz, phi, g, f, s->type, s->dflag, s->phi, s->gf, s->f);
+        else
+            launch_classify(s->stream, nx, ny, nz, s->phi, s->gf, s->f, s->type, s->dflag);
         ck(hipMemcpyAsync(s->hscalar, s->dflag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
         sync(s);
         int flags;

@@ -112,3 +112,34 @@ def test_sweep_timing_counts_and_leaves_the_solution_unchanged(precision, precon
     assert 0.0 < st1["sweep_full_ms"] < st1["sweep_ms"] and 0.0 < st1["sweep_ms"] / n < 5.0
     assert st0["sweep_launches"] == 0 and st0["sweep_ms"] == 0.0
     assert st1["iters"] == st0["iters"] and bool((u0 == u1).all())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_host_pointer_setup_and_solve_match_device_pointers(precision):
+    """The C-ABI with host arrays (device_ptrs = 0: the library uploads phi, g and f before
+    classifying them, and copies the solution back) gives the solution of the device-array
+    path (where the classification pass copies the fields on the way), bit for bit."""
+    import ctypes as C
+    print(f"[case] host pointers sphere 40^3 {precision}", flush=True)
+    w = _sphere()
+    u_dev, st_dev = cps.Solver.from_workload(w, precision=precision).solve(1e-10)
+    L = cps.load_library()
+    o = cps.CpsOptions()
+    L.cps_default_options(C.byref(o))
+    o.precision = cps.CPS_MIXED if precision == "mixed" else cps.CPS_FP64
+    o.device_ptrs = 0
+    arr = {k: np.ascontiguousarray(getattr(w, k), dtype=np.float64) for k in ("x", "y", "z", "phi", "g", "f")}
+    h = C.c_void_p()
+    p = lambda a: C.c_void_p(a.ctypes.data)
+    rc = L.cps_setup(C.byref(h), len(arr["x"]), len(arr["y"]), len(arr["z"]), p(arr["x"]), p(arr["y"]),
+                     p(arr["z"]), p(arr["phi"]), p(arr["g"]), p(arr["f"]), C.byref(o))
+    assert rc == 0
+    try:
+        u = np.empty(tuple(u_dev.shape))
+        st = cps.CpsStats()
+        st.struct_size = C.sizeof(cps.CpsStats)
+        assert L.cps_solve(h, 1e-10, p(u), 0, C.byref(st)) == 0
+    finally:
+        L.cps_destroy(h)
+    assert st.iters == st_dev["iters"]
+    assert np.array_equal(u, u_dev.cpu().numpy())
