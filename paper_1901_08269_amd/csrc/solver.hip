@@ -975,7 +975,7 @@ int rhs_build(cps_solver *s)
     }
     launch_to_float(st, (size_t)7 * n, s->irr_k64, s->irr_k32);
     launch_to_float(st, (size_t)n, s->irr_bd64, s->irr_bd32);
-    launch_fill<double>(st, s->nn, s->rhs, 0.0);
+    launch_fill<double>(st, s->nn + VEC_PAD, s->rhs, 0.0);
     launch_rhs_regular(st, s->nx, s->ny, s->nz, s->coef64, s->f, s->gf, s->type, s->rhs);
     launch_scatter_rows(st, n, s->irr_node, rhs_row, s->rhs);
     long long *dsum = dalloc<long long>(s, 1);
@@ -1454,7 +1454,7 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->partials = dalloc<double>(s, 2 * maxblk);
         s->st = dalloc<DevState>(s, 1);
         ck(hipMemsetAsync(s->st, 0, sizeof(DevState), s->stream));
-        s->rhs = dalloc<double>(s, s->nn);
+        s->rhs = dalloc<double>(s, s->nn + VEC_PAD);   // read as 4-vectors by the residual
         rc = rhs_build(s);
         if (rc == CPS_OK && o.precond == CPS_PRECOND_MULTIGRID) mg_build(s, hx);
         if (rc == CPS_OK && o.precond == CPS_PRECOND_SIP) sip_build(s);

@@ -493,8 +493,9 @@ __global__ void __launch_bounds__(NT) k_apply4(Geom g, Coef<T> cf, Irr<T> ir, co
                 if (out) {
                     sk = skip4(skip + (size_t)kc * wplane + wr, ic);
                     if (MODE == MODE_RES) {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) aux[u] = u < q.nv ? (AuxT<T, MODE>)bvec[e0 + (size_t)kc * plane + u] : 0;
+                        // b carries zero padding past its last node (one 4-vector load)
+                        const typename Vec4Of<double>::type b4 = load4(bvec, e0 + (size_t)kc * plane, q);
+                        aux[0] = b4.x; aux[1] = b4.y; aux[2] = b4.z; aux[3] = b4.w;
                     } else if (MODE == MODE_V || MODE == MODE_T) {
                         const V a4 = load4(w, e0 + (size_t)kc * plane, q);
                         aux[0] = a4.x; aux[1] = a4.y; aux[2] = a4.z; aux[3] = a4.w;
