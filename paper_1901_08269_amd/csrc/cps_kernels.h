@@ -123,10 +123,15 @@ struct MgSteps {
     int n;
     T c1[MG_TB_H], c2[MG_TB_H];
 };
+// tr, e_add: start from x + P e at the regular unknowns (e: the next coarser level's
+// correction, tr: the transfers to it) instead of x.  tr, rc, first: instead of the residual
+// (rout null), its restriction into that level (rho in rc, its first step as in
+// launch_mg_restrict); needs S.n <= MG_TB_H - 2.
 template <typename T>
 void launch_mg_smooth_tb(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf, const int8_t *type,
                          const int *irr_map, const T *k7, const T *rho, const T *xin, T *xout, T *rout,
-                         const MgSteps<T> &S, const DevState *st);
+                         const MgSteps<T> &S, const DevState *st, const MgTransfer<T> *tr = nullptr,
+                         const T *e_add = nullptr, T *rc = nullptr, const MgFirst<T> *first = nullptr);
 // map[nodes[r]] = r for the nirr irregular rows
 void launch_mg_irr_map(hipStream_t s, int nirr, const int *nodes, int *map);
 // x += P e at the regular unknown fine nodes (interior nodes without a skip bit in skip_f,

@@ -621,16 +621,29 @@ constexpr int MG_TB_E = MG_TB_TS + 2 * MG_TB_H;
 constexpr int MG_TB_E3 = MG_TB_E * MG_TB_E * MG_TB_E;
 constexpr int MG_TB_NPT = (MG_TB_E3 + MG_TB_THREADS - 1) / MG_TB_THREADS;
 
-template <typename T, bool RES>
+// What a temporally blocked pass writes besides x on its tile: nothing (TB_X), the residual
+// on the tile (TB_RES), or the residual restricted into the next coarser level (TB_RESTRICT:
+// that level's rho and first step, as k_mg_restrict forms them, for the coarse nodes whose
+// centre lies in the tile; the residual is formed on the tile and one layer around it, which
+// needs the pass to leave two layers exact, S.n <= MG_TB_H - 2).  With PRO the pass starts
+// from x + P e at the regular unknowns (the coarse correction added on load, as
+// k_mg_prolong_add forms it) instead of x.
+enum { TB_X = 0, TB_RES = 1, TB_RESTRICT = 2 };
+
+template <typename T, int OUT, bool PRO>
 __global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, int nz, Coef<T> cf,
                                                                 const int8_t *__restrict__ type,
                                                                 const int *__restrict__ irr_map,
                                                                 const T *__restrict__ k7, const T *__restrict__ rho,
                                                                 const T *__restrict__ xin, T *__restrict__ xout,
-                                                                T *__restrict__ rout, MgSteps<T> S, const DevState *st)
+                                                                T *__restrict__ rout, MgSteps<T> S, const DevState *st,
+                                                                MgTransfer<T> tr, const T *__restrict__ ec,
+                                                                T *__restrict__ rc, MgFirst<T> F)
 {
     constexpr int E = MG_TB_E, E2 = E * E, NPT = MG_TB_NPT;
+    static_assert(MG_TB_TS % 2 == 0, "a tile holds whole coarse cells");
     __shared__ T xs[MG_TB_E3];
+    __shared__ T rs[OUT == TB_RESTRICT ? MG_TB_E3 : 1];
     if (st && st->done) return;
     const int t = (int)threadIdx.x;
     const int o[3] = {1 + MG_TB_TS * (int)blockIdx.x - MG_TB_H, 1 + MG_TB_TS * (int)blockIdx.y - MG_TB_H,
@@ -646,7 +659,26 @@ __global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, 
         const size_t e = in ? (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k) : 0;
         const int8_t ty = in ? type[e] : (int8_t)0;
         act[u] = ty == 1 || ty == 2;
-        if (q < MG_TB_E3) xs[q] = act[u] ? xin[e] : T(0);
+        T x0 = act[u] ? xin[e] : T(0);
+        if (PRO) {
+            // (P e)(i, j, k): the coarse interval of each index, combined in y, then z, then x
+            const int ic = min(max(i, 1), nx - 2), jc = min(max(j, 1), ny - 2), kc = min(max(k, 1), nz - 2);
+            const int ncx = tr.nc[0], ncy = tr.nc[1], ncz = tr.nc[2];
+            const int a0 = min(ic >> 1, ncx - 2), b0 = min(jc >> 1, ncy - 2), c0 = min(kc >> 1, ncz - 2);
+            const size_t cpl = (size_t)ncx * ncy;
+            const T *e00 = ec + (size_t)c0 * cpl + (size_t)b0 * ncx + a0;
+            const T wx = tr.ax[0].pw[ic], wy = tr.ax[1].pw[jc], wz = tr.ax[2].pw[kc];
+            T ryz[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const T lo = (T(1) - wy) * e00[h] + wy * e00[ncx + h];
+                const T hi = (T(1) - wy) * e00[cpl + h] + wy * e00[cpl + ncx + h];
+                ryz[h] = (T(1) - wz) * lo + wz * hi;
+            }
+            const T add = (T(1) - wx) * ryz[0] + wx * ryz[1];
+            if (ty == 1) x0 = x0 + add;
+        }
+        if (q < MG_TB_E3) xs[q] = x0;
         rh[u] = act[u] ? rho[e] : T(0);
         xp[u] = T(0);
         kd[u] = T(1);
@@ -698,13 +730,50 @@ __global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, 
     for (int u = 0; u < NPT; ++u) {
         const int q = t + MG_TB_THREADS * u;
         const int ii = q % E, jj = (q / E) % E, kk = q / E2;
+        if (OUT == TB_RESTRICT && q < MG_TB_E3) {
+            // the residual on the tile and the layer around it, 0 elsewhere and off the unknowns
+            const bool near = ii >= MG_TB_H - 1 && ii <= MG_TB_H + MG_TB_TS && jj >= MG_TB_H - 1 &&
+                              jj <= MG_TB_H + MG_TB_TS && kk >= MG_TB_H - 1 && kk <= MG_TB_H + MG_TB_TS;
+            rs[q] = (act[u] && near) ? rh[u] - kx_of(u, q, xs[q]) : T(0);
+        }
         if (!act[u] || ii < MG_TB_H || ii >= MG_TB_H + MG_TB_TS || jj < MG_TB_H || jj >= MG_TB_H + MG_TB_TS ||
             kk < MG_TB_H || kk >= MG_TB_H + MG_TB_TS)
             continue;
         const size_t e = (size_t)(o[0] + ii) + (size_t)nx * ((size_t)(o[1] + jj) + (size_t)ny * (o[2] + kk));
         const T x0 = xs[q];
         xout[e] = x0;
-        if (RES) rout[e] = rh[u] - kx_of(u, q, x0);
+        if (OUT == TB_RES) rout[e] = rh[u] - kx_of(u, q, x0);
+    }
+    if (OUT == TB_RESTRICT) {
+        // coarse node (I, J, K) = (1 + TS/2 b + c): its fine points 2I - 1 .. 2I + 1 are the
+        // extended-tile points H + 2c .. H + 2c + 2 of each direction
+        constexpr int CT = MG_TB_TS / 2;
+        __syncthreads();
+        if (t < CT * CT * CT) {
+            const int ci = t % CT, cj = (t / CT) % CT, ck = t / (CT * CT);
+            const int I = 1 + CT * (int)blockIdx.x + ci, J = 1 + CT * (int)blockIdx.y + cj,
+                      K = 1 + CT * (int)blockIdx.z + ck;
+            const int ncx = tr.nc[0], ncy = tr.nc[1];
+            if (I <= ncx - 2 && J <= ncy - 2 && K <= tr.nc[2] - 2) {
+                const int i0 = MG_TB_H + 2 * ci, j0 = MG_TB_H + 2 * cj, k0 = MG_TB_H + 2 * ck;
+                const T wx0 = tr.ax[0].rw[3 * I], wx1 = tr.ax[0].rw[3 * I + 1], wx2 = tr.ax[0].rw[3 * I + 2];
+                T acc = T(0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T wz = tr.ax[2].rw[3 * K + c];
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const T wyz = wz * tr.ax[1].rw[3 * J + b];
+                        const T *row = rs + (k0 + c) * E2 + (j0 + b) * E + i0;
+                        acc += wyz * (wx0 * row[0] + wx1 * row[1] + wx2 * row[2]);
+                    }
+                }
+                const size_t e = (size_t)I + (size_t)ncx * (J + (size_t)ncy * K);
+                const T dg = F.diag[e];
+                rc[e] = dg != T(0) ? acc : T(0);
+                if (F.x1 && dg != T(0)) F.x1[e] = F.c2 * acc / dg;
+            }
+        }
     }
 }
 
@@ -815,16 +884,21 @@ void launch_mg_coarsest(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf
 template <typename T>
 void launch_mg_smooth_tb(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf, const int8_t *type,
                          const int *irr_map, const T *k7, const T *rho, const T *xin, T *xout, T *rout,
-                         const MgSteps<T> &S, const DevState *st)
+                         const MgSteps<T> &S, const DevState *st, const MgTransfer<T> *tr, const T *e_add, T *rc,
+                         const MgFirst<T> *first)
 {
     const dim3 grid((unsigned)((nx - 2 + MG_TB_TS - 1) / MG_TB_TS), (unsigned)((ny - 2 + MG_TB_TS - 1) / MG_TB_TS),
                     (unsigned)((nz - 2 + MG_TB_TS - 1) / MG_TB_TS));
-    if (rout)
-        k_mg_smooth_tb<T, true><<<grid, MG_TB_THREADS, 0, s>>>(nx, ny, nz, cf, type, irr_map, k7, rho, xin, xout, rout,
-                                                               S, st);
-    else
-        k_mg_smooth_tb<T, false><<<grid, MG_TB_THREADS, 0, s>>>(nx, ny, nz, cf, type, irr_map, k7, rho, xin, xout,
-                                                                nullptr, S, st);
+    const MgTransfer<T> t = tr ? *tr : MgTransfer<T>{};
+    const MgFirst<T> F = first ? *first : MgFirst<T>{};
+#define CPS_TB_LAUNCH(OUT, PRO)                                                                                        \
+    k_mg_smooth_tb<T, OUT, PRO><<<grid, MG_TB_THREADS, 0, s>>>(nx, ny, nz, cf, type, irr_map, k7, rho, xin, xout, rout, \
+                                                               S, st, t, e_add, rc, F)
+    if (rc) CPS_TB_LAUNCH(TB_RESTRICT, false);
+    else if (rout) CPS_TB_LAUNCH(TB_RES, false);
+    else if (e_add) CPS_TB_LAUNCH(TB_X, true);
+    else CPS_TB_LAUNCH(TB_X, false);
+#undef CPS_TB_LAUNCH
 }
 
 void launch_mg_irr_map(hipStream_t s, int nirr, const int *nodes, int *map)
@@ -840,10 +914,13 @@ template void launch_mg_coarsest<float>(hipStream_t, int, int, int, const Coef<f
                                         const DevState *);
 template void launch_mg_smooth_tb<double>(hipStream_t, int, int, int, const Coef<double> &, const int8_t *,
                                           const int *, const double *, const double *, const double *, double *,
-                                          double *, const MgSteps<double> &, const DevState *);
+                                          double *, const MgSteps<double> &, const DevState *,
+                                          const MgTransfer<double> *, const double *, double *,
+                                          const MgFirst<double> *);
 template void launch_mg_smooth_tb<float>(hipStream_t, int, int, int, const Coef<float> &, const int8_t *, const int *,
                                          const float *, const float *, const float *, float *, float *,
-                                         const MgSteps<float> &, const DevState *);
+                                         const MgSteps<float> &, const DevState *, const MgTransfer<float> *,
+                                         const float *, float *, const MgFirst<float> *);
 template void launch_mg_restrict<double>(hipStream_t, const MgTransfer<double> &, const double *, double *,
                                          const MgFirst<double> &);
 template void launch_mg_restrict<float>(hipStream_t, const MgTransfer<float> &, const float *, float *,

@@ -600,16 +600,25 @@ T *mg_level(cps_solver *s, int l, const DevState *st)
     const int nu = s->opt.mg_nu;
     if (nu <= MG_TB_H && (long long)(Lv.n[0] - 2) * (Lv.n[1] - 2) * (Lv.n[2] - 2) <= MG_TB_MAX_POINTS) {
         // each smoothing pass in one temporally blocked launch: steps 1 .. nu - 1 from the
-        // restriction's first step x_1 (in A) and the residual; after the coarse correction,
-        // steps 0 .. nu - 1 from the corrected iterate
-        T *Rr = V[3];
-        launch_mg_smooth_tb<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, A, B, Rr,
-                               mg_steps<T>(s, 1, nu), st);
-        launch_mg_restrict<T>(s->stream, mg_transfer<T>(Lv), Rr, mg_vecs<T>(s->mg[l + 1])[0], mg_first<T>(s, l + 1));
+        // restriction's first step x_1 (in A), then the residual restricted into the next
+        // level in the same launch (or, for more steps than that leaves room for, stored
+        // and restricted apart); after the coarse correction, steps 0 .. nu - 1 from the
+        // iterate with the prolonged correction added on load
+        const MgTransfer<T> &tr = mg_transfer<T>(Lv);
+        const MgFirst<T> first = mg_first<T>(s, l + 1);
+        T *rc = mg_vecs<T>(s->mg[l + 1])[0];
+        if (nu - 1 <= MG_TB_H - 2) {
+            launch_mg_smooth_tb<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, A, B,
+                                   nullptr, mg_steps<T>(s, 1, nu), st, &tr, nullptr, rc, &first);
+        } else {
+            T *Rr = V[3];
+            launch_mg_smooth_tb<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, A, B, Rr,
+                                   mg_steps<T>(s, 1, nu), st);
+            launch_mg_restrict<T>(s->stream, tr, Rr, rc, first);
+        }
         T *e = mg_level<T>(s, l + 1, st);
-        launch_mg_prolong_add<T>(s->stream, mg_transfer<T>(Lv), Lv.skip, Lv.g.W, e, B);
         launch_mg_smooth_tb<T>(s->stream, Lv.n[0], Lv.n[1], Lv.n[2], cf, Lv.type, Lv.irr_map, ir.k7, R, B, A, nullptr,
-                               mg_steps<T>(s, 0, nu), st);
+                               mg_steps<T>(s, 0, nu), st, &tr, e);
         return A;
     }
     T *x = mg_smooth<T>(s, l, L, cf, ir, R, nullptr, Z, A, B, nullptr, 1, nu, s->mg_c1.data(), s->mg_c2.data(), st, false);
