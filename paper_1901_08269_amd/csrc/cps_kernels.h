@@ -97,10 +97,12 @@ void launch_mg_resid_restrict(hipStream_t s, const Geom &g, const Coef<T> &cf, c
                               const T *rho, const T *ri, const MgTransfer<T> &t, T *rc, const MgFirst<T> &first,
                               const DevState *st);
 // The coarsest level's `steps` Chebyshev steps (coefficients c1, c2) from 0 in one workgroup
-// of MG_LDS_THREADS threads; the level has at most MG_LDS_NODES interior nodes.  irr_map:
-// irregular row of each irregular node.  Writes out at the unknown nodes.
+// of MG_LDS_THREADS threads; the level has at most MG_LDS_NODES interior nodes and steps is at
+// most MG_MAX_COARSE_STEPS.  irr_map: irregular row of each irregular node.  Writes out at
+// the unknown nodes.
 constexpr int MG_LDS_NODES = 4096;
 constexpr int MG_LDS_THREADS = 1024;
+constexpr int MG_MAX_COARSE_STEPS = 64;
 template <typename T>
 void launch_mg_coarsest(hipStream_t s, int nx, int ny, int nz, const Coef<T> &cf, const int8_t *type,
                         const int *irr_map, const T *k7, const T *rho, T *out, int steps, const T *c1, const T *c2,

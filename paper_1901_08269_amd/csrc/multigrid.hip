@@ -522,9 +522,14 @@ __global__ void __launch_bounds__(MG_LDS_THREADS) k_mg_coarsest(int nx, int ny, 
 {
     constexpr int NPT = MG_LDS_NODES / MG_LDS_THREADS;
     __shared__ T xs[MG_LDS_NODES];
+    __shared__ T cs[2 * MG_MAX_COARSE_STEPS];
     if (st && st->done) return;
     const int ni = nx - 2, nj = ny - 2, nk = nz - 2, nij = ni * nj, nint = nij * nk;
     const int t = (int)threadIdx.x;
+    if (t < steps) {
+        cs[t] = c1[t];
+        cs[MG_MAX_COARSE_STEPS + t] = c2[t];
+    }
     T kd[NPT], ko[NPT][6], rh[NPT], xp[NPT];
     unsigned inm[NPT];                 // bit v: neighbour v (-x, +x, -y, +y, -z, +z) is interior
     bool act[NPT];
@@ -543,24 +548,33 @@ __global__ void __launch_bounds__(MG_LDS_THREADS) k_mg_coarsest(int nx, int ny, 
         inm[u] = 0u;
 #pragma unroll
         for (int v = 0; v < 6; ++v) ko[u][v] = T(0);
-        if (q >= nint) continue;
-        const int i = 1 + q % ni, j = 1 + (q / ni) % nj, k = 1 + q / nij;
-        const size_t e = node_of(q);
-        const int8_t ty = type[e];
+        // the loads that do not depend on the node's type are issued at once (a point past
+        // the level's interior reads node 0), so only an irregular row's stored K row waits
+        // for a first round trip
+        const bool in = q < nint;
+        const int qq = in ? q : 0;
+        const int i = 1 + qq % ni, j = 1 + (qq / ni) % nj, k = 1 + qq / nij;
+        const size_t e = in ? node_of(q) : 0;
+        const int8_t ty_l = type[e];
+        const T r_l = rho[e];
+        const int ir_l = irr_map[e];
+        const T *cx = cf.c[0] + 8 * i, *cy = cf.c[1] + 8 * j, *cz = cf.c[2] + 8 * k;
+        const T cx5 = cx[5], cx6 = cx[6], cx7 = cx[7], cy5 = cy[5], cy6 = cy[6], cy7 = cy[7];
+        const T cz5 = cz[5], cz6 = cz[6], cz7 = cz[7];
+        const int8_t ty = in ? ty_l : (int8_t)0;
         act[u] = ty == 1 || ty == 2;
         if (!act[u]) continue;
-        rh[u] = rho[e];
+        rh[u] = r_l;
         if (ty == 2) {
-            const T *row = k7 + 7 * (size_t)irr_map[e];
+            const T *row = k7 + 7 * (size_t)ir_l;
             kd[u] = row[0];
 #pragma unroll
             for (int v = 0; v < 6; ++v) ko[u][v] = row[1 + v];
         } else {
-            const T *cx = cf.c[0] + 8 * i, *cy = cf.c[1] + 8 * j, *cz = cf.c[2] + 8 * k;
-            kd[u] = cx[6] + cy[6] + cz[6];
-            ko[u][0] = cx[5]; ko[u][1] = cx[7];
-            ko[u][2] = cy[5]; ko[u][3] = cy[7];
-            ko[u][4] = cz[5]; ko[u][5] = cz[7];
+            kd[u] = cx6 + cy6 + cz6;
+            ko[u][0] = cx5; ko[u][1] = cx7;
+            ko[u][2] = cy5; ko[u][3] = cy7;
+            ko[u][4] = cz5; ko[u][5] = cz7;
         }
         // a wall neighbour is read as the node itself with coefficient 0
         inm[u] = (i > 1 ? 1u : 0u) | (i < nx - 2 ? 2u : 0u) | (j > 1 ? 4u : 0u) | (j < ny - 2 ? 8u : 0u) |
@@ -580,7 +594,7 @@ __global__ void __launch_bounds__(MG_LDS_THREADS) k_mg_coarsest(int nx, int ny, 
     __syncthreads();
     const int d[6] = {-1, 1, -ni, ni, -nij, nij};
     for (int s = 0; s < steps; ++s) {
-        const T a1 = c1[s], a2 = c2[s];
+        const T a1 = cs[s], a2 = cs[MG_MAX_COARSE_STEPS + s];
         T xn[NPT];
 #pragma unroll
         for (int u = 0; u < NPT; ++u) {
@@ -657,12 +671,21 @@ __global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, 
         const int i = o[0] + ii, j = o[1] + jj, k = o[2] + kk;
         const bool in = q < MG_TB_E3 && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2;
         const size_t e = in ? (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k) : 0;
-        const int8_t ty = in ? type[e] : (int8_t)0;
+        // every load that does not depend on the node's type is issued at once (e and the
+        // clamped indices address valid entries for any point), so only an irregular row's
+        // stored K row waits for a first round trip
+        const int ic = min(max(i, 1), nx - 2), jc = min(max(j, 1), ny - 2), kc = min(max(k, 1), nz - 2);
+        const int8_t ty_l = type[e];
+        const T x_l = xin[e], r_l = rho[e];
+        const int ir_l = irr_map[e];
+        const T *cx = cf.c[0] + 8 * ic, *cy = cf.c[1] + 8 * jc, *cz = cf.c[2] + 8 * kc;
+        const T cx5 = cx[5], cx6 = cx[6], cx7 = cx[7], cy5 = cy[5], cy6 = cy[6], cy7 = cy[7];
+        const T cz5 = cz[5], cz6 = cz[6], cz7 = cz[7];
+        const int8_t ty = in ? ty_l : (int8_t)0;
         act[u] = ty == 1 || ty == 2;
-        T x0 = act[u] ? xin[e] : T(0);
+        T x0 = act[u] ? x_l : T(0);
         if (PRO) {
             // (P e)(i, j, k): the coarse interval of each index, combined in y, then z, then x
-            const int ic = min(max(i, 1), nx - 2), jc = min(max(j, 1), ny - 2), kc = min(max(k, 1), nz - 2);
             const int ncx = tr.nc[0], ncy = tr.nc[1], ncz = tr.nc[2];
             const int a0 = min(ic >> 1, ncx - 2), b0 = min(jc >> 1, ncy - 2), c0 = min(kc >> 1, ncz - 2);
             const size_t cpl = (size_t)ncx * ncy;
@@ -679,22 +702,21 @@ __global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, 
             if (ty == 1) x0 = x0 + add;
         }
         if (q < MG_TB_E3) xs[q] = x0;
-        rh[u] = act[u] ? rho[e] : T(0);
+        rh[u] = act[u] ? r_l : T(0);
         xp[u] = T(0);
         kd[u] = T(1);
 #pragma unroll
         for (int v = 0; v < 6; ++v) ko[u][v] = T(0);
         if (ty == 2) {
-            const T *r = k7 + 7 * (size_t)irr_map[e];
+            const T *r = k7 + 7 * (size_t)ir_l;
             kd[u] = r[0];
 #pragma unroll
             for (int v = 0; v < 6; ++v) ko[u][v] = r[1 + v];
         } else if (ty == 1) {
-            const T *cx = cf.c[0] + 8 * i, *cy = cf.c[1] + 8 * j, *cz = cf.c[2] + 8 * k;
-            kd[u] = (cx[6] + cy[6]) + cz[6];
-            ko[u][0] = cx[5]; ko[u][1] = cx[7];
-            ko[u][2] = cy[5]; ko[u][3] = cy[7];
-            ko[u][4] = cz[5]; ko[u][5] = cz[7];
+            kd[u] = (cx6 + cy6) + cz6;
+            ko[u][0] = cx5; ko[u][1] = cx7;
+            ko[u][2] = cy5; ko[u][3] = cy7;
+            ko[u][4] = cz5; ko[u][5] = cz7;
         }
     }
     __syncthreads();

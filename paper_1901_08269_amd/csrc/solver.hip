@@ -36,6 +36,7 @@ constexpr int DEFAULT_INNER = 24;
 constexpr double DEFAULT_LAM_HI = 2.0;
 constexpr int ELL_CAP = 243;               // 27 box nodes + 216 extra-point positions
 constexpr int MAX_INNER = 64;
+static_assert(MAX_INNER <= MG_MAX_COARSE_STEPS, "the coarsest level's steps fit its kernel's coefficient array");
 
 template <typename T>
 struct Vecs {
