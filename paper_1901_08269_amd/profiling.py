@@ -1,12 +1,14 @@
 """Summaries of rocprofv3 result databases as short markdown.
 
-Three reports:
+Five reports:
 
 ``stats``    per-kernel call counts and durations from a ``--kernel-trace --stats`` run.
 ``kernels``  the solve kernels of such a run against the HBM roofline: algorithmic bytes
              per interior point (each operand read or written once), GB/s from the average
              launch duration, fraction of the 8 TB/s peak.
 ``mfma``     MFMA busy share and BF16 matrix FLOP rate of the network's kernels from one ``--pmc`` run.
+``counters`` counters of chosen kernels from one or more ``--pmc`` passes, with derived
+             figures (resident waves, wait shares, cache latencies, address-unit load).
 ``traffic``  HBM bytes per launch of one kernel (or several counted together, as the
              instantiations of one kernel template) on the problem's grid from two ``--pmc`` runs
              (``FETCH_SIZE`` and ``WRITE_SIZE``, each in its own pass), each counter scaled by
@@ -20,6 +22,7 @@ Usage::
     python -m paper_1901_08269_amd.profiling stats DB --title T --cmd C [--top 20]
     python -m paper_1901_08269_amd.profiling kernels DB --points P --title T --cmd C
     python -m paper_1901_08269_amd.profiling mfma DB --title T --cmd C
+    python -m paper_1901_08269_amd.profiling counters DB [DB ...] --kernel NAME [--kernel ...] --title T --cmd C
     python -m paper_1901_08269_amd.profiling traffic --fetch DB --write DB \\
         --copy-fetch DB --copy-write DB --copy-bytes B --kernel NAME=BYTES_PER_UNIT [--kernel ...] --units U \\
         --title T --cmd C
@@ -292,6 +295,101 @@ def mfma_report(db, title, cmd):
     return "\n".join(out) + "\n"
 
 
+def counters_report(dbs, kernels, title, cmd):
+    """Per kernel (matched by its short name), the mean over dispatches of each counter summed
+    over its hardware instances, from one or more ``--pmc`` passes of the same program, and the
+    figures derived from them where their counters are present:
+
+    * waves resident per SIMD: 4 SQ_WAVE_CYCLES (quad-cycles, summed over the shader engines)
+      over the busy cycles of one engine (SQ_BUSY_CYCLES summed over the engines, divided by
+      their count) and the SIMD count;
+    * the share of wave time spent waiting (SQ_WAIT_ANY), waiting for issue
+      (SQ_WAIT_INST_ANY) and executing (SQ_ACTIVE_INST_ANY), each over SQ_WAVE_CYCLES;
+    * instructions per wave (SQ_INSTS_* over SQ_WAVES);
+    * mean L1-to-L2 read latency in cycles (TCP_TCC_READ_REQ_LATENCY_sum over
+      TCP_TCC_READ_REQ_sum) and mean L2-to-memory read latency (TCC_EA0_RDREQ_LEVEL_sum over
+      TCC_EA0_RDREQ_sum), the L2 hit share (TCC_HIT_sum over TCC_HIT_sum + TCC_MISS_sum);
+    * the share of active GPU cycles (GRBM_GUI_ACTIVE) in which the address unit is busy
+      (TA_BUSY_avr) or its address path is stalled by the cache (TA_ADDR_STALLED_BY_TC_CYCLES
+      per TA instance)."""
+    acc = {}
+    for db in dbs:
+        con = sqlite3.connect(db)
+        for name, disp, dur, cname, val in con.execute(
+                "select name, dispatch_id, duration, counter_name, counter_value from pmc_events"):
+            n = short_name(name)
+            if n not in kernels:
+                continue
+            d = acc.setdefault(n, {}).setdefault(cname, {}).setdefault((db, disp), [0.0, 0, dur])
+            d[0] += val
+            d[1] += 1
+        con.close()
+    names = []
+    for n in kernels:
+        for c in acc.get(n, {}):
+            if c not in names:
+                names.append(c)
+
+    def mean(n, c):
+        ds = acc.get(n, {}).get(c)
+        return None if not ds else sum(v[0] for v in ds.values()) / len(ds)
+
+    def inst(n, c):
+        ds = acc.get(n, {}).get(c)
+        return None if not ds else sum(v[1] for v in ds.values()) / len(ds)
+
+    out = [f"# {title}", "", "Commands (run from the repository root on an MI355X, one counter set per pass):", "",
+           "```", cmd, "```", "", "Each counter summed over its hardware instances, mean over dispatches:", "",
+           "| counter | " + " | ".join(f"`{n}`" for n in kernels) + " |",
+           "|---|" + "---:|" * len(kernels)]
+    rows = [("dispatches", lambda n: max((len(v) for v in acc.get(n, {}).values()), default=0)),
+            ("mean us under counters", lambda n: next(
+                (sum(v[2] for v in ds.values()) / len(ds) / 1e3 for ds in acc.get(n, {}).values()), None))]
+    for c in names:
+        rows.append((c, lambda n, c=c: mean(n, c)))
+
+    def fmt(v):
+        if v is None:
+            return "-"
+        return f"{v:.4g}" if abs(v) < 1e6 else f"{v:.4e}"
+    for label, f in rows:
+        out.append(f"| {label} | " + " | ".join(fmt(f(n)) for n in kernels) + " |")
+
+    def ratio(a, b, scale=1.0):
+        return None if a is None or not b else scale * a / b
+
+    def derived(n):
+        W, B, S = mean(n, "SQ_WAVE_CYCLES"), mean(n, "SQ_BUSY_CYCLES"), inst(n, "SQ_BUSY_CYCLES")
+        waves = mean(n, "SQ_WAVES")
+        res = None if W is None or not B or not S else 4.0 * W / (B / S) / SIMDS
+        hit, miss = mean(n, "TCC_HIT_sum"), mean(n, "TCC_MISS_sum")
+        gui = mean(n, "GRBM_GUI_ACTIVE")
+        stall, ta_n = mean(n, "TA_ADDR_STALLED_BY_TC_CYCLES"), inst(n, "TA_ADDR_STALLED_BY_TC_CYCLES")
+        return [("waves resident per SIMD", res),
+                ("wave time waiting, %", ratio(mean(n, "SQ_WAIT_ANY"), W, 100.0)),
+                ("wave time waiting for issue, %", ratio(mean(n, "SQ_WAIT_INST_ANY"), W, 100.0)),
+                ("wave time executing, %", ratio(mean(n, "SQ_ACTIVE_INST_ANY"), W, 100.0)),
+                ("VALU instructions per wave", ratio(mean(n, "SQ_INSTS_VALU"), waves)),
+                ("vector loads per wave", ratio(mean(n, "SQ_INSTS_VMEM_RD"), waves)),
+                ("L1-to-L2 read latency, cycles",
+                 ratio(mean(n, "TCP_TCC_READ_REQ_LATENCY_sum"), mean(n, "TCP_TCC_READ_REQ_sum"))),
+                ("L2-to-memory read latency, cycles",
+                 ratio(mean(n, "TCC_EA0_RDREQ_LEVEL_sum"), mean(n, "TCC_EA0_RDREQ_sum"))),
+                ("L2 hit share, %", None if hit is None or miss is None or not hit + miss else 100.0 * hit / (hit + miss)),
+                ("address unit busy, % of active cycles", ratio(mean(n, "TA_BUSY_avr"), gui, 100.0)),
+                ("address path stalled by the cache, % of active cycles",
+                 None if stall is None or not ta_n or not gui else 100.0 * stall / ta_n / gui)]
+    table = [derived(n) for n in kernels]
+    if table and any(v is not None for row in table for _, v in row):
+        out += ["", "Derived:", "", "| figure | " + " | ".join(f"`{n}`" for n in kernels) + " |",
+                "|---|" + "---:|" * len(kernels)]
+        for q in range(len(table[0])):
+            if all(t[q][1] is None for t in table):
+                continue
+            out.append(f"| {table[0][q][0]} | " + " | ".join(fmt(t[q][1]) for t in table) + " |")
+    return "\n".join(out) + "\n"
+
+
 def read_traffic(path):
     """The machine-readable lines of a traffic report, or None if absent."""
     if not os.path.exists(path):
@@ -323,6 +421,11 @@ def main(argv=None):
     mf.add_argument("db")
     mf.add_argument("--title", required=True)
     mf.add_argument("--cmd", required=True)
+    cn = sub.add_parser("counters")
+    cn.add_argument("db", nargs="+")
+    cn.add_argument("--kernel", action="append", required=True, help="short kernel name (repeatable)")
+    cn.add_argument("--title", required=True)
+    cn.add_argument("--cmd", required=True)
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write", "title", "cmd"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
@@ -337,6 +440,8 @@ def main(argv=None):
         print(kernels_report(a.db, a.points, a.title, a.cmd, tuple(a.exclude)), end="")
     elif a.mode == "mfma":
         print(mfma_report(a.db, a.title, a.cmd), end="")
+    elif a.mode == "counters":
+        print(counters_report(a.db, a.kernel, a.title, a.cmd), end="")
     else:
         print(traffic_report(a), end="")
 

@@ -138,3 +138,42 @@ def test_kernels_report_separates_levels_sharing_a_launch_grid(tmp_path):
     con.close()
     rep = profiling.kernels_report(str(db), 1000000, "T", "cmd")
     assert "| `cps::k_cheb4<float, false>` | 10 | 40.00 | 16 | 400 | 0.05 |" in rep
+
+
+def test_counters_report_sums_instances_and_derives_figures(tmp_path):
+    """Counters summed over their instances per dispatch, averaged over dispatches, from two
+    passes; resident waves = 4 wave quad-cycles / (busy cycles of one engine) / SIMDs."""
+    k = "cps::k_x<float>"
+    dbs = []
+    for q, rows in enumerate([
+        # pass A: two engines report each SQ counter; two dispatches
+        [(7, "SQ_WAVES", 10.0), (7, "SQ_WAVES", 14.0), (7, "SQ_WAVE_CYCLES", 512.0), (7, "SQ_WAVE_CYCLES", 512.0),
+         (7, "SQ_BUSY_CYCLES", 100.0), (7, "SQ_BUSY_CYCLES", 100.0), (7, "SQ_WAIT_ANY", 256.0),
+         (7, "SQ_WAIT_ANY", 256.0),
+         (9, "SQ_WAVES", 12.0), (9, "SQ_WAVES", 12.0), (9, "SQ_WAVE_CYCLES", 512.0), (9, "SQ_WAVE_CYCLES", 512.0),
+         (9, "SQ_BUSY_CYCLES", 100.0), (9, "SQ_BUSY_CYCLES", 100.0), (9, "SQ_WAIT_ANY", 256.0),
+         (9, "SQ_WAIT_ANY", 256.0)],
+        # pass B: cache counters, one dispatch
+        [(3, "TCC_HIT_sum", 30.0), (3, "TCC_MISS_sum", 70.0), (3, "TCP_TCC_READ_REQ_LATENCY_sum", 5000.0),
+         (3, "TCP_TCC_READ_REQ_sum", 10.0)]]):
+        db = str(tmp_path / f"p{q}.db")
+        con = sqlite3.connect(db)
+        con.execute("create table pmc_events (name text, dispatch_id int, duration real, counter_name text, "
+                    "counter_value real)")
+        for disp, c, v in rows:
+            con.execute("insert into pmc_events values (?,?,?,?,?)", (f"void {k}(cps::Geom, int)", disp, 2000.0, c, v))
+        con.execute("insert into pmc_events values (?,?,?,?,?)", ("void cps::k_other(int)", 1, 5.0, "SQ_WAVES", 1e9))
+        con.commit()
+        con.close()
+        dbs.append(db)
+    rep = profiling.counters_report(dbs, [k], "t", "c")
+    lines = {l.split("|")[1].strip(): l.split("|")[2].strip() for l in rep.splitlines() if l.startswith("| ")}
+    assert lines["SQ_WAVES"] == "24"                     # 10 + 14 and 12 + 12
+    assert lines["dispatches"] == "2"
+    assert lines["mean us under counters"] == "2"
+    # 4 x 1024 quad-cycles / (200 cycles / 2 engines) / 1024 SIMDs
+    assert abs(float(lines["waves resident per SIMD"]) - 4.0 * 1024 / 100.0 / profiling.SIMDS) < 1e-12
+    assert float(lines["wave time waiting, %"]) == 50.0
+    assert float(lines["L2 hit share, %"]) == 30.0
+    assert float(lines["L1-to-L2 read latency, cycles"]) == 500.0
+    assert "k_other" not in rep
