@@ -935,28 +935,53 @@ int fill_stats(cps_solver *s, cps_stats *st, const DevState &ds, int iters, int 
     return status;
 }
 
-int rhs_build(cps_solver *s)
+// The irregular rows' construction in flight: its scratch buffers, between the launches
+// (rows_launch) and the host's reading of their results (rows_finish).
+struct RowsPending {
+    int *ell_col, *len, *fb;
+    double *ell_val, *rhs_row, *minhb, *ibi_tab;
+};
+
+// Queues the irregular rows (FP64) into ELL scratch and their row pointers; touches no host
+// staging, so other work may use it until rows_finish.
+RowsPending rows_launch(cps_solver *s)
 {
-    // irregular rows (FP64): ELL scratch -> CSR; K rows; diagonal; RHS; then regular RHS
     const hipStream_t st = s->stream;
-    int n = s->nirr;
-    int *ell_col = dalloc<int>(s, (size_t)n * ELL_CAP);
-    double *ell_val = dalloc<double>(s, (size_t)n * ELL_CAP);
-    int *len = dalloc<int>(s, n + 1);
-    double *rhs_row = dalloc<double>(s, n);
-    double *minhb = dalloc<double>(s, n);
-    int *fb = dalloc<int>(s, n);
+    const int n = s->nirr;
+    RowsPending p;
+    p.ell_col = dalloc<int>(s, (size_t)n * ELL_CAP);
+    p.ell_val = dalloc<double>(s, (size_t)n * ELL_CAP);
+    p.len = dalloc<int>(s, n + 1);
+    p.rhs_row = dalloc<double>(s, n);
+    p.minhb = dalloc<double>(s, n);
+    p.fb = dalloc<int>(s, n);
     if (!s->irr_k64) {
         s->irr_k64 = dalloc<double>(s, (size_t)7 * n);
         s->irr_bd64 = dalloc<double>(s, n);
         s->irr_ptr = dalloc<int>(s, n + 1);
     }
-    double *ibi_tab = dalloc<double>(s, 12 * (size_t)n + 1);
+    if (!s->irr_k32) {
+        s->irr_k32 = dalloc<float>(s, (size_t)7 * n);
+        s->irr_bd32 = dalloc<float>(s, n);
+    }
+    p.ibi_tab = dalloc<double>(s, 12 * (size_t)n + 1);
     ck(hipMemsetAsync(s->dflag, 0, sizeof(int), st));
     launch_build_rows(st, s->nx, s->ny, s->nz, s->xyz, s->xyz + s->nx, s->xyz + s->nx + s->ny, s->coef64, s->phi, s->gf,
-                      s->f, s->type, n, s->irr_node, s->irr_bits, s->irr_wstart, ibi_tab, ELL_CAP, ell_col, ell_val,
-                      len, rhs_row, s->irr_k64, s->irr_bd64, minhb, fb, s->dflag);
-    launch_scan(st, len, s->irr_ptr, n);
+                      s->f, s->type, n, s->irr_node, s->irr_bits, s->irr_wstart, p.ibi_tab, ELL_CAP, p.ell_col,
+                      p.ell_val, p.len, p.rhs_row, s->irr_k64, s->irr_bd64, p.minhb, p.fb, s->dflag);
+    launch_scan(st, p.len, s->irr_ptr, n);
+    return p;
+}
+
+// The rest of the right-hand side once the rows are queued: CSR packing, K rows in FP32,
+// the regular and irregular right-hand side, the wall-distance and fallback summaries, the
+// norms of b.
+int rows_finish(cps_solver *s, const RowsPending &p)
+{
+    const hipStream_t st = s->stream;
+    const int n = s->nirr;
+    int *ell_col = p.ell_col, *len = p.len, *fb = p.fb;
+    double *ell_val = p.ell_val, *rhs_row = p.rhs_row, *minhb = p.minhb, *ibi_tab = p.ibi_tab;
     int total = 0, bad = 0;
     ck(hipMemcpyAsync(s->hscalar, s->irr_ptr + n, sizeof(int), hipMemcpyDeviceToHost, st));
     ck(hipMemcpyAsync(s->hscalar + 1, s->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -964,9 +989,9 @@ int rhs_build(cps_solver *s)
     std::memcpy(&total, s->hscalar, sizeof(int));
     std::memcpy(&bad, s->hscalar + 1, sizeof(int));
     if (bad) {
-        for (void *p : {(void *)ell_col, (void *)ell_val, (void *)len, (void *)rhs_row, (void *)minhb, (void *)fb,
+        for (void *q : {(void *)ell_col, (void *)ell_val, (void *)len, (void *)rhs_row, (void *)minhb, (void *)fb,
                         (void *)ibi_tab})
-            dfree(s, p);
+            dfree(s, q);
         return CPS_EGEOM;   // a singular one-sided system
     }
     if (!s->irr_col || s->nnz != total) {
@@ -979,10 +1004,6 @@ int rhs_build(cps_solver *s)
     }
     s->nnz = total;
     launch_pack_rows(st, n, ELL_CAP, ell_col, ell_val, len, s->irr_ptr, s->irr_col, s->irr_val64, s->irr_val32);
-    if (!s->irr_k32) {
-        s->irr_k32 = dalloc<float>(s, (size_t)7 * n);
-        s->irr_bd32 = dalloc<float>(s, n);
-    }
     launch_to_float(st, (size_t)7 * n, s->irr_k64, s->irr_k32);
     launch_to_float(st, (size_t)n, s->irr_bd64, s->irr_bd32);
     launch_fill<double>(st, s->nn + VEC_PAD, s->rhs, 0.0);
@@ -1014,10 +1035,16 @@ int rhs_build(cps_solver *s)
         s->bn2 += hp[2 * q];
         s->bs2 += hp[2 * q + 1];
     }
-    for (void *p : {(void *)ell_col, (void *)ell_val, (void *)len, (void *)rhs_row, (void *)minhb, (void *)fb,
+    for (void *q : {(void *)ell_col, (void *)ell_val, (void *)len, (void *)rhs_row, (void *)minhb, (void *)fb,
                     (void *)dsum, (void *)dmin, (void *)mpart, (void *)ibi_tab})
-        dfree(s, p);
+        dfree(s, q);
     return CPS_OK;
+}
+
+// irregular rows (FP64): ELL scratch -> CSR; K rows; diagonal; RHS; then regular RHS
+int rhs_build(cps_solver *s)
+{
+    return rows_finish(s, rows_launch(s));
 }
 
 int count_nodes(cps_solver *s, size_t nn, const int8_t *type, int8_t want, int *list, long long *count)
@@ -1041,6 +1068,22 @@ int count_nodes(cps_solver *s, size_t nn, const int8_t *type, int8_t want, int *
 int count_type(cps_solver *s, int8_t want, int *list, long long *count)
 {
     return count_nodes(s, s->nn, s->type, want, list, count);
+}
+
+// A second stream per device on which the setup builds the multigrid hierarchy while the
+// problem grid's irregular rows are built on the solver's stream.  Created on first use and
+// kept for the process's lifetime; default priority, and non-blocking so that it also runs
+// beside the null stream.
+hipStream_t setup_aux_stream()
+{
+    static std::mutex mu;
+    static std::vector<hipStream_t> per_dev;
+    int dev = 0;
+    ck(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)per_dev.size() <= dev) per_dev.resize(dev + 1, nullptr);
+    if (!per_dev[dev]) ck(hipStreamCreateWithFlags(&per_dev[dev], hipStreamNonBlocking));
+    return per_dev[dev];
 }
 
 // 1D multigrid tables of one axis: fine coordinates xf[nf], the coarse points' indices idx
@@ -1137,6 +1180,10 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
     std::vector<double> hx = hx0;
     const double *phi_f = s->phi;
     std::vector<void *> temps;
+    // the coarse classifications' flags (never read) go to a word of their own: the problem
+    // grid's rows may be under construction on another stream, reporting into s->dflag
+    int *cflag = dalloc<int>(s, 1);
+    temps.push_back(cflag);
     std::vector<std::vector<char>> keep;   // sources of the asynchronous table uploads
     struct SyncFirst {                     // destroyed before `keep`, also when a step throws
         hipStream_t st;
@@ -1198,7 +1245,7 @@ void mg_build(cps_solver *s, const std::vector<double> &hx0)
         // level set is a subset of the validated one, and a wall node in a body next to a
         // fluid node is no error on a coarse level (a zero Dirichlet node of the correction)
         C.type = dalloc<int8_t>(s, C.nn);
-        launch_classify(s->stream, cx, cy, cz, phic, phic, phic, C.type, s->dflag);
+        launch_classify(s->stream, cx, cy, cz, phic, phic, phic, C.type, cflag);
         launch_mark_irregular(s->stream, cx, cy, cz, C.type);
         int *lst = dalloc<int>(s, C.nn);
         temps.push_back(lst);
@@ -1465,8 +1512,28 @@ int cps_setup(cps_solver **out, int32_t nx, int32_t ny, int32_t nz, const double
         s->st = dalloc<DevState>(s, 1);
         ck(hipMemsetAsync(s->st, 0, sizeof(DevState), s->stream));
         s->rhs = dalloc<double>(s, s->nn + VEC_PAD);   // read as 4-vectors by the residual
-        rc = rhs_build(s);
-        if (rc == CPS_OK && o.precond == CPS_PRECOND_MULTIGRID) mg_build(s, hx);
+        if (o.precond == CPS_PRECOND_MULTIGRID) {
+            // The hierarchy needs the node types and coordinates, not the irregular rows: it
+            // is built on a second stream, after the work queued so far, while the rows are
+            // built on the solver's stream; its host waits (level sizes) wait for it alone.
+            // The rows' host staging is read only after the hierarchy is done.
+            ck(hipEventRecord(s->ev[0], s->stream));
+            const RowsPending rows = rows_launch(s);
+            {
+                struct Restore {
+                    cps_solver *s;
+                    hipStream_t st;
+                    ~Restore() { s->stream = st; }
+                } restore{s, s->stream};
+                const hipStream_t aux = setup_aux_stream();
+                ck(hipStreamWaitEvent(aux, s->ev[0], 0));
+                s->stream = aux;
+                mg_build(s, hx);
+            }
+            rc = rows_finish(s, rows);
+        } else {
+            rc = rhs_build(s);
+        }
         if (rc == CPS_OK && o.precond == CPS_PRECOND_SIP) sip_build(s);
         sync(s);
     } catch (int code) {
