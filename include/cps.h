@@ -271,6 +271,15 @@ int cps_model_restrict_noalloc(cps_model *m, cps_solver *s, const double *u, flo
 /* u0 (device, nx*ny*nz FP64) = sigma * trilinear prolongation of the network's prediction
  * for the solver's problem; pass it to cps_solve as the warm start. */
 int cps_model_predict(cps_model *m, cps_solver *s, double *u0);
+/* The same warm start from the fields themselves, without a solver, queued on `stream` (NULL:
+ * the model's stream) and returned from at once, so that it can run beside the solver's setup
+ * of the same problem.  phi, g, f: device FP64 arrays of the nx x ny x nz grid (x fastest; the
+ * grid must have 4 nc interior points per direction), ready on `stream` when it reaches the
+ * call (order their producer before it); u0: device, nx*ny*nz FP64, every node written,
+ * complete when `stream` passes the call.  The call uses the model's work buffers: calls on
+ * one model must not overlap.  CPS_EINVAL for a NULL pointer or a grid of another size. */
+int cps_model_predict_fields(cps_model *m, int32_t nx, int32_t ny, int32_t nz, const double *phi, const double *g,
+                             const double *f, double *u0, void *stream);
 /* Write the weights to `path` (raw binary: magic "CPSNET01", the spec, the parameter count,
  * the FP32 weights).  CPS_EINVAL if the file cannot be written. */
 int cps_model_save(cps_model *m, const char *path);

@@ -711,13 +711,11 @@ double *scratch_address(int dev)
 
 // The network input of the solver's problem (and the target's cell means of u), with the
 // sigma reduction's partial sums in part[SCALE_BLOCKS] and sigma in sig[0] (device).
-int restrict_into(cps_model *m, cps_solver *s, const double *u, float *inputs, float *target, double *sigma,
-                  double *part, double *sig)
+// The network's inputs for the fields phi, g, f of an nx x ny x nz grid, queued on the
+// model's stream; with `wait` the call returns once they are complete.
+int restrict_fields(cps_model *m, int nx, int ny, int nz, const double *phi, const double *g, const double *f,
+                    const double *u, float *inputs, float *target, double *sigma, double *part, double *sig, bool wait)
 {
-    const double *phi, *g, *f;
-    int nx, ny, nz;
-    void *sst;
-    cps_internal_fields(s, &phi, &g, &f, &nx, &ny, &nz, &sst);
     const int nc = m->spec.nc;
     if (nx - 2 != 4 * nc || ny - 2 != 4 * nc || nz - 2 != 4 * nc || m->spec.in_ch != 3) return CPS_EINVAL;
     const size_t nn = (size_t)nx * ny * nz;
@@ -728,8 +726,18 @@ int restrict_into(cps_model *m, cps_solver *s, const double *u, float *inputs, f
         k_restrict_u<<<nblk((size_t)nc * nc * nc), 256, 0, m->stream>>>(nx, ny, nc, u, phi, g, sig, target);
     nck(hipGetLastError());
     if (sigma) nck(hipMemcpyAsync(sigma, sig, sizeof(double), hipMemcpyDeviceToHost, m->stream));
-    nck(hipStreamSynchronize(m->stream));
+    if (wait) nck(hipStreamSynchronize(m->stream));
     return CPS_OK;
+}
+
+int restrict_into(cps_model *m, cps_solver *s, const double *u, float *inputs, float *target, double *sigma,
+                  double *part, double *sig)
+{
+    const double *phi, *g, *f;
+    int nx, ny, nz;
+    void *sst;
+    cps_internal_fields(s, &phi, &g, &f, &nx, &ny, &nz, &sst);
+    return restrict_fields(m, nx, ny, nz, phi, g, f, u, inputs, target, sigma, part, sig, true);
 }
 
 template <typename T>
@@ -1097,6 +1105,31 @@ int cps_model_predict(cps_model *m, cps_solver *s, double *u0)
         k_prolong<<<dim3(nblk((size_t)nx), (unsigned)ny, (unsigned)nz), 256, 0, m->stream>>>(nx, ny, nz, nc, m->pred,
                                                                                             m->sig, u0);
         nck(hipStreamSynchronize(m->stream));
+    } catch (NetFail &f_) {
+        return f_.code;
+    }
+    return CPS_OK;
+}
+
+int cps_model_predict_fields(cps_model *m, int32_t nx, int32_t ny, int32_t nz, const double *phi, const double *g,
+                             const double *f, double *u0, void *stream)
+{
+    if (!m || !phi || !g || !f || !u0) return CPS_EINVAL;
+    // the call's kernels go to `stream`; the model's own stream is restored on every return
+    struct Restore {
+        cps_model *m;
+        hipStream_t st;
+        ~Restore() { m->stream = st; }
+    } restore{m, m->stream};
+    if (stream) m->stream = (hipStream_t)stream;
+    const int nc = m->spec.nc;
+    try {
+        int rc = restrict_fields(m, nx, ny, nz, phi, g, f, nullptr, m->inp, nullptr, nullptr, m->lpart, m->sig, false);
+        if (rc) return rc;
+        forward(m, 1);
+        k_prolong<<<dim3(nblk((size_t)nx), (unsigned)ny, (unsigned)nz), 256, 0, m->stream>>>(nx, ny, nz, nc, m->pred,
+                                                                                            m->sig, u0);
+        nck(hipGetLastError());
     } catch (NetFail &f_) {
         return f_.code;
     }

@@ -51,6 +51,7 @@ def _bind(L):
     L.cps_model_restrict.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double)]
     L.cps_model_restrict_noalloc.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double)]
     L.cps_model_predict.argtypes = [vp, vp, vp]
+    L.cps_model_predict_fields.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp, vp]
     L.cps_model_save.argtypes = [vp, C.c_char_p]
     L.cps_model_save_checkpoint.argtypes = [vp, C.c_char_p]
     L.cps_model_load.argtypes = [vp, C.c_char_p]
@@ -58,7 +59,7 @@ def _bind(L):
     L.cps_model_destroy.restype = None
     for n in ("cps_model_create", "cps_model_set_params", "cps_model_get_params", "cps_model_forward",
               "cps_model_train_step", "cps_model_restrict", "cps_model_restrict_noalloc", "cps_model_predict",
-              "cps_model_save", "cps_model_save_checkpoint", "cps_model_load"):
+              "cps_model_predict_fields", "cps_model_save", "cps_model_save_checkpoint", "cps_model_load"):
         getattr(L, n).restype = C.c_int
     L._net_bound = True
     return L
@@ -153,6 +154,24 @@ class Model:
         torch = self.torch
         u0 = torch.empty(solver.shape, dtype=torch.float64, device="cuda")   # every node is written
         self._ck(self.L.cps_model_predict(self.h, solver.h, _p(u0)), "predict")
+        return u0
+
+    def predict_fields(self, phi, g, f, stream):
+        """The warm start from the problem's fields (contiguous FP64 CUDA tensors of shape
+        (nz, ny, nx)), queued on the torch stream `stream`, which first waits for the current
+        stream (where the fields and u0 are made); returns u0 at once.  It is complete when
+        `stream` passes this point: wait for `stream` before using it."""
+        torch = self.torch
+        for t in (phi, g, f):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.shape == phi.shape):
+                raise ValueError("phi, g, f: contiguous FP64 CUDA tensors of one shape")
+        u0 = torch.empty(phi.shape, dtype=torch.float64, device="cuda")   # every node is written
+        stream.wait_stream(torch.cuda.current_stream())
+        for t in (phi, g, f, u0):
+            t.record_stream(stream)
+        nz, ny, nx = phi.shape
+        self._ck(self.L.cps_model_predict_fields(self.h, nx, ny, nz, _p(phi), _p(g), _p(f), _p(u0),
+                                                 C.c_void_p(stream.cuda_stream)), "predict_fields")
         return u0
 
     def save(self, path):
@@ -339,6 +358,9 @@ class WarmStart:
 
     def predict(self, solver, w=None):
         return self.model.predict(solver)
+
+    def predict_fields(self, phi, g, f, stream):
+        return self.model.predict_fields(phi, g, f, stream)
 
 
 def load_default(N):

@@ -186,6 +186,32 @@ def test_prolong_vs_oracle():
     assert err <= 1e-12
 
 
+def test_predict_fields_matches_predict():
+    """cps_model_predict_fields (the fields themselves, queued on a stream of the caller's, no
+    solver) gives cps_model_predict's u0 bit for bit, on a side stream and on the current one;
+    a grid that is not 4 nc points a side is refused."""
+    import torch
+    N = 32
+    print(f"[case] predict_fields N={N}", flush=True)
+    w = W.sphere_sin(N, beta=1.2, r=0.2)
+    S = cps.Solver.from_workload(w)
+    m = learned.Model(N // 4, batch=1, seed=5)
+    ref = m.predict(S).cpu().numpy()
+    fields = [torch.as_tensor(getattr(w, k), dtype=torch.float64).cuda().contiguous() for k in ("phi", "g", "f")]
+    side = torch.cuda.Stream()
+    u_side = m.predict_fields(*fields, side)
+    side.synchronize()
+    u_cur = m.predict_fields(*fields, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert np.array_equal(u_side.cpu().numpy(), ref)
+    assert np.array_equal(u_cur.cpu().numpy(), ref)
+    small = [t[:-4, :-4, :-4].contiguous() for t in fields]
+    with pytest.raises(Exception):
+        m.predict_fields(*small, side)
+    side.synchronize()
+    S.close()
+
+
 def test_headline_mixed_learned_vs_oracle_samples():
     """The benchmark path: 256^3, 8 spheres, mixed precision from the shipped network's warm
     start.  At tol 1e-10 both residual norms meet the bound; at tol 1e-13 the solution matches
