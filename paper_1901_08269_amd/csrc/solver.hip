@@ -826,11 +826,13 @@ DevState run_iterations_enqueue(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget
     return read_state(s);
 }
 
+// it0: the device's iteration count when the run starts (the caller knows it from the
+// state it read last; a restart does not change it)
 template <typename T, typename TXS>
-DevState run_iterations(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget, const double *c1, const double *c2)
+DevState run_iterations(cps_solver *s, Vecs<T> &V, TXS *xsol, int budget, const double *c1, const double *c2,
+                        int it0)
 {
     const int64_t base = s->iter_enq;
-    const int it0 = read_state(s).iters;
     s->hist_it0 = it0;
     s->hist_run = 0;
     DevState out = run_iterations_enqueue<T, TXS>(s, V, xsol, budget, c1, c2);
@@ -1651,11 +1653,16 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
                     ++restarts;
                     if (++r64 > s->opt.max_restarts) return CPS_EBREAKDOWN;
                 }
-                set_stop2(s, jacobi_target(ds));
+                const double target2 = jacobi_target(ds);
+                set_stop2(s, target2);
                 launch_restart<double>(L, s->ir64(), V.r, V.r0, V.p, V.v, s->st);
-                DevState d0 = read_state(s);
-                DevState d1 = d0.done ? d0 : run_iterations<double, double>(s, V, x64, s->opt.max_iters - iters, c1, c2);
-                iters += d1.iters - d0.iters;
+                // the restart is done at once exactly when the residual already meets the
+                // target (it compares the same two values on the device); otherwise the first
+                // state read of the run reports a non-finite restart
+                DevState d1 = ds;
+                if (ds.res2s <= target2) d1.done = 1;
+                else d1 = run_iterations<double, double>(s, V, x64, s->opt.max_iters - iters, c1, c2, ds.iters);
+                iters += d1.iters - ds.iters;
                 if (d1.done == 3) return CPS_ENAN;
             }
         };
@@ -1692,10 +1699,12 @@ int cps_solve(cps_solver *s, double tol, double *u, int32_t warm_start, cps_stat
                 set_stop2(s, target2);
                 launch_fill<float>(s->stream, s->nn, V.x, 0.0f);
                 launch_restart<float>(L, s->ir32(), V.r, V.r0, V.p, V.v, s->st);
-                DevState d0 = read_state(s);
-                DevState d1 = d0.done ? d0 : run_iterations<float, float>(s, V, V.x, s->opt.max_iters - iters, c1, c2);
-                iters += d1.iters - d0.iters;
-                iters32 += d1.iters - d0.iters;
+                // done at once exactly when the residual already meets the target (see above)
+                DevState d1 = ds;
+                if (ds.res2s <= target2) d1.done = 1;
+                else d1 = run_iterations<float, float>(s, V, V.x, s->opt.max_iters - iters, c1, c2, ds.iters);
+                iters += d1.iters - ds.iters;
+                iters32 += d1.iters - ds.iters;
                 if (d1.done == 3) { ++restarts; continue; }   // discard a non-finite correction
                 if (d1.done == 2) ++restarts;
                 launch_add_correction(s->stream, s->nn, x64, V.x);
