@@ -143,6 +143,10 @@ def main():
     print(f"# inputs generated in {time.time() - t_gen:.1f}s", file=sys.stderr, flush=True)
 
     side = torch.cuda.Stream()        # the warm start's stream when it runs beside the setup
+    # the warm start's launches are made from a worker thread (the library calls release the
+    # interpreter lock), so that the setup's host work does not wait behind them
+    import concurrent.futures
+    launcher = concurrent.futures.ThreadPoolExecutor(max_workers=1)
 
     def step(precision, timing, precond=None, tol=None, warm=True, overlap=False):
         """setup + (warm start) + solve; returns (u, stats) with the warm start's time in
@@ -152,11 +156,13 @@ def main():
         use = warm and learned is not None and precision == "mixed"
         u0, pms = None, 0.0
         if use and overlap:
-            u0 = learned.predict_fields(dev["phi"], dev["g"], dev["f"], side)
+            side.wait_stream(torch.cuda.current_stream())    # the fields, before the setup's work
+            fut = launcher.submit(learned.predict_fields, dev["phi"], dev["g"], dev["f"], side, False)
         S = cps.Solver(dev["x"], dev["y"], dev["z"], dev["phi"], dev["g"], dev["f"], precision=precision,
                        kernel_timing=timing, precond=precond or args.precond)
         if use and overlap:
             ta = time.perf_counter()
+            u0 = fut.result()
             side.synchronize()
             pms = (time.perf_counter() - ta) * 1e3
         elif use:

@@ -156,17 +156,19 @@ class Model:
         self._ck(self.L.cps_model_predict(self.h, solver.h, _p(u0)), "predict")
         return u0
 
-    def predict_fields(self, phi, g, f, stream):
+    def predict_fields(self, phi, g, f, stream, wait=True):
         """The warm start from the problem's fields (contiguous FP64 CUDA tensors of shape
         (nz, ny, nx)), queued on the torch stream `stream`, which first waits for the current
-        stream (where the fields and u0 are made); returns u0 at once.  It is complete when
-        `stream` passes this point: wait for `stream` before using it."""
+        stream (where the fields and u0 are made; wait=False leaves that ordering to the
+        caller); returns u0 at once.  It is complete when `stream` passes this point: wait
+        for `stream` before using it."""
         torch = self.torch
         for t in (phi, g, f):
             if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.shape == phi.shape):
                 raise ValueError("phi, g, f: contiguous FP64 CUDA tensors of one shape")
         u0 = torch.empty(phi.shape, dtype=torch.float64, device="cuda")   # every node is written
-        stream.wait_stream(torch.cuda.current_stream())
+        if wait:
+            stream.wait_stream(torch.cuda.current_stream())
         for t in (phi, g, f, u0):
             t.record_stream(stream)
         nz, ny, nx = phi.shape
@@ -359,8 +361,8 @@ class WarmStart:
     def predict(self, solver, w=None):
         return self.model.predict(solver)
 
-    def predict_fields(self, phi, g, f, stream):
-        return self.model.predict_fields(phi, g, f, stream)
+    def predict_fields(self, phi, g, f, stream, wait=True):
+        return self.model.predict_fields(phi, g, f, stream, wait)
 
 
 def load_default(N):
