@@ -508,9 +508,10 @@ __global__ void __launch_bounds__(256) k_mg_prolong_add(int nfx, int nfy, int nf
 // in one workgroup (the level has at most MG_LDS_NODES interior nodes): x_k lives in LDS
 // (interior nodes, x fastest); each thread keeps, for its nodes q = t + MG_LDS_THREADS u,
 // x_{k-1} and the K row and rho divided by the row's diagonal (the tables' regular row, or
-// the stored Shortley-Weller row of an irregular node) in registers.  A barrier separates the reads of x_k from the writes of
-// x_{k+1}.  Wall neighbours hold 0 in every iterate and get coefficient 0; solid nodes are
-// never written.  x_steps goes to the unknown nodes of out.
+// the stored Shortley-Weller row of an irregular node) in registers.  x_k and x_{k+1} live
+// in two LDS arrays that swap roles every step, one barrier apart.  Wall neighbours hold 0
+// in every iterate and get coefficient 0; solid nodes are never written.  x_steps goes to
+// the unknown nodes of out.
 template <typename T>
 __global__ void __launch_bounds__(MG_LDS_THREADS) k_mg_coarsest(int nx, int ny, int nz, Coef<T> cf,
                                                                 const int8_t *__restrict__ type,
@@ -521,7 +522,7 @@ __global__ void __launch_bounds__(MG_LDS_THREADS) k_mg_coarsest(int nx, int ny, 
                                                                 const DevState *st)
 {
     constexpr int NPT = MG_LDS_NODES / MG_LDS_THREADS;
-    __shared__ T xs[MG_LDS_NODES];
+    __shared__ T xa[MG_LDS_NODES], xb[MG_LDS_NODES];   // x_k and x_{k+1}, swapped every step
     __shared__ T cs[2 * MG_MAX_COARSE_STEPS];
     if (st && st->done) return;
     const int ni = nx - 2, nj = ny - 2, nk = nz - 2, nij = ni * nj, nint = nij * nk;
@@ -540,7 +541,8 @@ __global__ void __launch_bounds__(MG_LDS_THREADS) k_mg_coarsest(int nx, int ny, 
 #pragma unroll
     for (int u = 0; u < NPT; ++u) {
         const int q = t + MG_LDS_THREADS * u;
-        xs[q] = T(0);
+        xa[q] = T(0);
+        xb[q] = T(0);
         xp[u] = T(0);
         act[u] = false;
         kd[u] = T(1);
@@ -593,28 +595,29 @@ __global__ void __launch_bounds__(MG_LDS_THREADS) k_mg_coarsest(int nx, int ny, 
     }
     __syncthreads();
     const int d[6] = {-1, 1, -ni, ni, -nij, nij};
+    // step s reads x_s from one array and writes x_{s+1} into the other (nodes that are not
+    // unknowns stay 0 in both), so one barrier per step separates them
+    T *cur = xa, *nxt = xb;
     for (int s = 0; s < steps; ++s) {
         const T a1 = cs[s], a2 = cs[MG_MAX_COARSE_STEPS + s];
-        T xn[NPT];
 #pragma unroll
         for (int u = 0; u < NPT; ++u) {
             const int q = t + MG_LDS_THREADS * u;
-            const T x0 = xs[q];
+            const T x0 = cur[q];
             T kx = x0;
 #pragma unroll
-            for (int v = 0; v < 6; ++v) kx += ko[u][v] * xs[((inm[u] >> v) & 1u) ? q + d[v] : q];
-            xn[u] = x0 + a1 * (x0 - xp[u]) + a2 * (rh[u] - kx);
+            for (int v = 0; v < 6; ++v) kx += ko[u][v] * cur[((inm[u] >> v) & 1u) ? q + d[v] : q];
+            if (act[u]) nxt[q] = x0 + a1 * (x0 - xp[u]) + a2 * (rh[u] - kx);
             xp[u] = x0;
         }
         __syncthreads();
-#pragma unroll
-        for (int u = 0; u < NPT; ++u)
-            if (act[u]) xs[t + MG_LDS_THREADS * u] = xn[u];
-        __syncthreads();
+        T *const tmp = cur;
+        cur = nxt;
+        nxt = tmp;
     }
 #pragma unroll
     for (int u = 0; u < NPT; ++u)
-        if (act[u]) out[node_of(t + MG_LDS_THREADS * u)] = xs[t + MG_LDS_THREADS * u];
+        if (act[u]) out[node_of(t + MG_LDS_THREADS * u)] = cur[t + MG_LDS_THREADS * u];
 }
 
 // Temporally blocked Chebyshev-Jacobi steps on a coarse level (launch_mg_smooth_tb).  The
@@ -645,7 +648,7 @@ constexpr int MG_TB_NPT = (MG_TB_E3 + MG_TB_THREADS - 1) / MG_TB_THREADS;
 enum { TB_X = 0, TB_RES = 1, TB_RESTRICT = 2 };
 
 template <typename T, int OUT, bool PRO>
-__global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, int nz, Coef<T> cf,
+__global__ void __launch_bounds__(MG_TB_THREADS, sizeof(T) == 4 ? 8 : 1) k_mg_smooth_tb(int nx, int ny, int nz, Coef<T> cf,
                                                                 const int8_t *__restrict__ type,
                                                                 const int *__restrict__ irr_map,
                                                                 const T *__restrict__ k7, const T *__restrict__ rho,
@@ -664,6 +667,15 @@ __global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, 
                       1 + MG_TB_TS * (int)blockIdx.z - MG_TB_H};
     T xp[NPT], rh[NPT], kd[NPT], ko[NPT][6];
     bool act[NPT];
+    // TB_RESTRICT: thread t < (TS/2)^3 restricts into coarse node (I, J, K) = (1 + TS/2 b + c)
+    // at the end; its nine weights and the node's diagonal are loaded with the tile and kept
+    // in LDS until then
+    constexpr int CT = MG_TB_TS / 2, CT3 = CT * CT * CT;
+    __shared__ T rsw[OUT == TB_RESTRICT ? CT3 : 1][10];
+    const int ci = t % CT, cj = (t / CT) % CT, ck = t / (CT * CT);
+    const int cI = 1 + CT * (int)blockIdx.x + ci, cJ = 1 + CT * (int)blockIdx.y + cj, cK = 1 + CT * (int)blockIdx.z + ck;
+    const bool cown = OUT == TB_RESTRICT && t < CT3 && cI <= tr.nc[0] - 2 && cJ <= tr.nc[1] - 2 && cK <= tr.nc[2] - 2;
+    const size_t ce = cown ? (size_t)cI + (size_t)tr.nc[0] * (cJ + (size_t)tr.nc[1] * cK) : 0;
 #pragma unroll
     for (int u = 0; u < NPT; ++u) {
         const int q = t + MG_TB_THREADS * u;
@@ -719,6 +731,15 @@ __global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, 
             ko[u][4] = cz5; ko[u][5] = cz7;
         }
     }
+    if (cown) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            rsw[t][c] = tr.ax[0].rw[3 * cI + c];
+            rsw[t][3 + c] = tr.ax[1].rw[3 * cJ + c];
+            rsw[t][6 + c] = tr.ax[2].rw[3 * cK + c];
+        }
+        rsw[t][9] = F.diag[ce];
+    }
     __syncthreads();
     // K x at point q of the LDS tile (neighbours outside the extended tile read 0)
     auto kx_of = [&](int u, int q, T x0) {
@@ -767,34 +788,25 @@ __global__ void __launch_bounds__(MG_TB_THREADS) k_mg_smooth_tb(int nx, int ny, 
         if (OUT == TB_RES) rout[e] = rh[u] - kx_of(u, q, x0);
     }
     if (OUT == TB_RESTRICT) {
-        // coarse node (I, J, K) = (1 + TS/2 b + c): its fine points 2I - 1 .. 2I + 1 are the
-        // extended-tile points H + 2c .. H + 2c + 2 of each direction
-        constexpr int CT = MG_TB_TS / 2;
+        // coarse node (I, J, K): its fine points 2I - 1 .. 2I + 1 are the extended-tile points
+        // H + 2c .. H + 2c + 2 of each direction
         __syncthreads();
-        if (t < CT * CT * CT) {
-            const int ci = t % CT, cj = (t / CT) % CT, ck = t / (CT * CT);
-            const int I = 1 + CT * (int)blockIdx.x + ci, J = 1 + CT * (int)blockIdx.y + cj,
-                      K = 1 + CT * (int)blockIdx.z + ck;
-            const int ncx = tr.nc[0], ncy = tr.nc[1];
-            if (I <= ncx - 2 && J <= ncy - 2 && K <= tr.nc[2] - 2) {
-                const int i0 = MG_TB_H + 2 * ci, j0 = MG_TB_H + 2 * cj, k0 = MG_TB_H + 2 * ck;
-                const T wx0 = tr.ax[0].rw[3 * I], wx1 = tr.ax[0].rw[3 * I + 1], wx2 = tr.ax[0].rw[3 * I + 2];
-                T acc = T(0);
+        if (cown) {
+            const int i0 = MG_TB_H + 2 * ci, j0 = MG_TB_H + 2 * cj, k0 = MG_TB_H + 2 * ck;
+            const T *w = rsw[t];
+            T acc = T(0);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const T wz = tr.ax[2].rw[3 * K + c];
+            for (int c = 0; c < 3; ++c) {
 #pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        const T wyz = wz * tr.ax[1].rw[3 * J + b];
-                        const T *row = rs + (k0 + c) * E2 + (j0 + b) * E + i0;
-                        acc += wyz * (wx0 * row[0] + wx1 * row[1] + wx2 * row[2]);
-                    }
+                for (int b = 0; b < 3; ++b) {
+                    const T wyz = w[6 + c] * w[3 + b];
+                    const T *row = rs + (k0 + c) * E2 + (j0 + b) * E + i0;
+                    acc += wyz * (w[0] * row[0] + w[1] * row[1] + w[2] * row[2]);
                 }
-                const size_t e = (size_t)I + (size_t)ncx * (J + (size_t)ncy * K);
-                const T dg = F.diag[e];
-                rc[e] = dg != T(0) ? acc : T(0);
-                if (F.x1 && dg != T(0)) F.x1[e] = F.c2 * acc / dg;
             }
+            const T cdg = w[9];
+            rc[ce] = cdg != T(0) ? acc : T(0);
+            if (F.x1 && cdg != T(0)) F.x1[ce] = F.c2 * acc / cdg;
         }
     }
 }
