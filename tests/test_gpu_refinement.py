@@ -143,3 +143,29 @@ def test_host_pointer_setup_and_solve_match_device_pointers(precision):
         L.cps_destroy(h)
     assert st.iters == st_dev["iters"]
     assert np.array_equal(u, u_dev.cpu().numpy())
+
+
+def test_setup_on_a_side_stream_matches_default_stream():
+    """The setup builds the multigrid hierarchy on a second stream of its own, ordered after
+    the work the solver's stream has queued: a solver on a non-default torch stream (which
+    does not synchronise with the null stream) gives the default-stream solver's irregular
+    rows and solution bit for bit."""
+    import torch
+    print("[case] setup on a side stream, sphere 40^3 mixed", flush=True)
+    w = _sphere()
+    S0 = cps.Solver.from_workload(w, precision="mixed")
+    rows0 = [np.asarray(a).copy() for a in S0.irregular()]
+    u0, st0 = S0.solve(1e-10)
+    u0 = u0.cpu().numpy()
+    S0.close()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        S1 = cps.Solver.from_workload(w, precision="mixed")
+        rows1 = [np.asarray(a).copy() for a in S1.irregular()]
+        u1, st1 = S1.solve(1e-10)
+        side.synchronize()
+        u1 = u1.cpu().numpy()
+        S1.close()
+    assert all(np.array_equal(a, b) for a, b in zip(rows0, rows1))
+    assert st1["iters"] == st0["iters"]
+    assert np.array_equal(u1, u0)
