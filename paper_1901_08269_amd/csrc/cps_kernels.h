@@ -47,6 +47,16 @@ void launch_restart(const Launch &L, const Irr<T> &ir, const T *r, T *r0, T *p, 
 void launch_add_correction(hipStream_t s, size_t n, double *u, const float *d);
 template <typename T>
 void launch_fill(hipStream_t s, size_t n, T *a, T val);
+// up to 12 vectors of one grid
+template <typename T>
+struct VecList {
+    T *p[12];
+    int n;
+};
+// v.p[q][e] = 0 at the nodes e < nn that are not unknowns (type 1 or 2) and at e = nn ..
+// nn + pad - 1, for every vector of the list; the unknowns' entries are not touched
+template <typename T>
+void launch_zero_off_unknowns(hipStream_t s, size_t nn, size_t pad, const int8_t *type, const VecList<T> &v);
 template <typename TI, typename TO>
 void launch_masked_copy(hipStream_t s, size_t n, const int8_t *type, const TI *src, TO *dst);
 void launch_output(hipStream_t s, size_t n, const int8_t *type, const double *x, const double *gv, double *u);

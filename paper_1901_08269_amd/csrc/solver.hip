@@ -406,11 +406,16 @@ template <typename T>
 void alloc_vecs(cps_solver *s, Vecs<T> &V)
 {
     if (V.ready) return;
+    // every kernel writes a vector's unknowns before it reads them (the Krylov vectors are set
+    // by the restart, the iterates by each pass's first step), and reads the other nodes and
+    // the padding as zeros: one launch zeroes those in all vectors
     T **all[] = {&V.r, &V.r0, &V.p, &V.ph, &V.v, &V.s, &V.sh, &V.t, &V.x, &V.c[0], &V.c[1]};
+    VecList<T> list{};
     for (T **p : all) {
         *p = dalloc<T>(s, s->nn + VEC_PAD);
-        launch_fill<T>(s->stream, s->nn + VEC_PAD, *p, T(0));
+        list.p[list.n++] = *p;
     }
+    launch_zero_off_unknowns<T>(s->stream, s->nn, VEC_PAD, s->type, list);
     V.ready = true;
 }
 
@@ -473,11 +478,14 @@ void mg_alloc(cps_solver *s)
         MgLevel &Lv = s->mg[l];
         T **v;
         if constexpr (sizeof(T) == 8) v = Lv.v64; else v = Lv.v32;
+        // as for the problem grid's vectors: the unknowns are written before they are read
+        VecList<T> list{};
         for (int q = 0; q < 4; ++q)
             if (!v[q]) {
                 v[q] = dalloc<T>(s, Lv.nn + VEC_PAD);
-                launch_fill<T>(s->stream, Lv.nn + VEC_PAD, v[q], T(0));
+                list.p[list.n++] = v[q];
             }
+        launch_zero_off_unknowns<T>(s->stream, Lv.nn, VEC_PAD, Lv.type, list);
     }
     if (s->mg.size() > 1) {
         T **z;

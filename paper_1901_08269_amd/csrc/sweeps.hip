@@ -824,6 +824,21 @@ __global__ void k_fill(size_t n, T *__restrict__ a, T val)
     for (; e < n; e += (size_t)gridDim.x * blockDim.x) a[e] = val;
 }
 
+// 0 in every vector of the list at the nodes that are not unknowns (types other than 1 and 2)
+// and in the padding past the last node; the unknowns' entries are left as they are
+template <typename T>
+__global__ void k_zero_off_unknowns(size_t nn, size_t pad, const int8_t *__restrict__ type, VecList<T> v)
+{
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; e < nn + pad; e += (size_t)gridDim.x * blockDim.x) {
+        if (e < nn) {
+            const int8_t t = type[e];
+            if (t == 1 || t == 2) continue;
+        }
+        for (int q = 0; q < v.n; ++q) v.p[q][e] = T(0);
+    }
+}
+
 // dst = src at unknown nodes (types 1, 2), 0 elsewhere; converts precision
 template <typename TI, typename TO>
 __global__ void k_masked_copy(size_t n, const int8_t *__restrict__ type, const TI *__restrict__ src, TO *__restrict__ dst)
@@ -1009,6 +1024,12 @@ void launch_add_correction(hipStream_t s, size_t n, double *u, const float *d)
 }
 
 template <typename T>
+void launch_zero_off_unknowns(hipStream_t s, size_t nn, size_t pad, const int8_t *type, const VecList<T> &v)
+{
+    if (v.n > 0) k_zero_off_unknowns<T><<<flat_grid(nn + pad), 256, 0, s>>>(nn, pad, type, v);
+}
+
+template <typename T>
 void launch_fill(hipStream_t s, size_t n, T *a, T val)
 {
     k_fill<T><<<flat_grid(n), 256, 0, s>>>(n, a, val);
@@ -1075,6 +1096,8 @@ template void launch_restart<double>(const Launch &, const Irr<double> &, const 
                                      DevState *);
 template void launch_restart<float>(const Launch &, const Irr<float> &, const float *, float *, float *, float *,
                                     DevState *);
+template void launch_zero_off_unknowns<double>(hipStream_t, size_t, size_t, const int8_t *, const VecList<double> &);
+template void launch_zero_off_unknowns<float>(hipStream_t, size_t, size_t, const int8_t *, const VecList<float> &);
 template void launch_fill<double>(hipStream_t, size_t, double *, double);
 template void launch_fill<float>(hipStream_t, size_t, float *, float);
 template void launch_fill<unsigned>(hipStream_t, size_t, unsigned *, unsigned);
